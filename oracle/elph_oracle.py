@@ -1,0 +1,585 @@
+"""Plain FP64 NumPy oracle of the e-ph transition-probability path.
+
+Test infrastructure only (tests, smoke check and the benchmark's CPU leg); the
+product library never imports it and shares no code with it.
+
+Every function cites the passage of the paper it follows (section and
+equation of "The elphbolt ab initio solver for the coupled electron-phonon
+Boltzmann transport equations").  Equation numbers count the displayed
+equations in order of appearance: Eq. 1 H(k), Eq. 2 electron velocity,
+Eq. 3 D(q), Eq. 4 non-analytic term, Eq. 5 phonon velocity, Eq. 6 e-ph
+vertex, Eq. 7 Froehlich term, Eq. 8 X^{+/-}, Eq. 12 Y^{ph-e}, Eqs. 17-18
+deviation functions, Eq. 19 coupled BTEs, Eqs. 20-27 RTA / self / drag
+terms, Eqs. 28-31 transport tensors and the Kelvin-Onsager relation.
+
+Readings of the paper used here (where it is silent, garbled or ambiguous):
+
+* Normalisations 1/N_e, 1/N_ph of Eqs. 1, 3, 6 are absorbed into the
+  Wannier-space inputs; optional per-vector weights w_R multiply each term.
+* Phases are exp(+2 pi i k_frac . n) with integer cell vectors n (Eqs. 1, 3,
+  6 show cell phases only, no atom-position phases).
+* Eq. 6 index order: U columns are eigenvectors; m is the initial band at k,
+  n the final band at k' = k + q:
+  g_x[n,m] = sum_{n',m'} conj(U_{k'}[n',n]) gW_x[n',m'] U_k[m',m], and the
+  phonon projection is g_s = sum_x l_{x,s} u_q[x,s] g_x with the mass of
+  the atom of x inside the sum.
+* Eq. 6 prefactor: l = sqrt(hbar^2 / (2 M hbar*omega)) =
+  sqrt(C / (2 M[amu] hbar*omega[eV])) Angstrom with C = hbar^2/(amu A^2).
+* Modes with hbar*omega < omega_min (the acoustic modes at Gamma) are
+  dropped: their g, X and rates are zero.
+* The energy-conserving delta of Eq. 8 is a Gaussian of standard deviation
+  sigma, never truncated.
+* Emission in Eq. 8 uses n and omega at -q; the force constants are real so
+  omega(-q) = omega(q).
+* Y = (N_k/N_q) X^+ on the same term (Eq. 12 vs Eq. 8), spin degeneracy 2.
+* Electron states enter through an energy window |eps - mu| <= w (per state);
+  k is kept if any band is active; initial and final states are active
+  states.  N_k is the full mesh count.
+* Transport tensors (Eqs. 28-30) carry 1/N_k (electrons) and 1/N_q
+  (phonons); V is the cell volume.
+* The e-ph collision operator conserves carrier number: the in-scattering
+  matrix of Eq. 22 has every group-constant vector as an eigenvector with
+  eigenvalue 1, one per group of states that the Gaussian-broadened
+  interaction couples.  Groups are the maximal runs of active states, sorted
+  by energy, with no gap wider than hw_max + 12 sigma (beyond which the
+  coupling is below 1e-31 of the peak).  Iterated electron responses are
+  constrained to sum_{i in group} f_i (1 - f_i) I_i = 0 for every group (no
+  change of carrier number), applied after every electron sweep; for
+  materials with inversion or time-reversal symmetry this holds by itself.
+* Phonon scattering other than ph-e (ph-ph, ph-isotope) is an external rate
+  per mode (default model gamma0 (hw/hw_max)^2 (T/300 K), gamma0 = 1e12/s);
+  the ph-ph in-scattering term Delta F^S is zero.
+"""
+import numpy as np
+
+# CODATA 2018
+HBAR_EVS = 6.582119569e-16        # eV s
+KB_EVK = 8.617333262e-5           # eV / K
+E_CHARGE = 1.602176634e-19        # C  (= J per eV)
+AMU_KG = 1.66053906660e-27        # kg
+ANG_M = 1.0e-10                   # m per Angstrom
+HBAR_JS = HBAR_EVS * E_CHARGE
+# (hbar omega)^2 [eV^2] = C_PHONON [eV] * lambda [eV / (A^2 amu)]
+C_PHONON = HBAR_JS ** 2 / (AMU_KG * ANG_M ** 2) / E_CHARGE
+SPIN_DEG = 2.0
+OMEGA_MIN_DEFAULT = 1.0e-4        # eV
+DEGEN_TOL = 1.0e-6                # eV, degenerate-group tolerance
+
+LEVEL_RTA, LEVEL_PARTIAL, LEVEL_DRAGLESS, LEVEL_COUPLED = 0, 1, 2, 3
+
+__all__ = [
+    "HBAR_EVS", "KB_EVK", "E_CHARGE", "AMU_KG", "ANG_M", "C_PHONON", "SPIN_DEG",
+    "OMEGA_MIN_DEFAULT", "LEVEL_RTA", "LEVEL_PARTIAL", "LEVEL_DRAGLESS", "LEVEL_COUPLED",
+    "mesh_points", "mesh_linear", "phases", "bloch_hamiltonian", "bloch_hamiltonian_grad",
+    "electron_bands", "electron_velocities", "dynamical_matrix", "dynamical_matrix_grad",
+    "phonon_modes", "phonon_velocities", "fermi_pair", "bose_pair", "gaussian_delta",
+    "g_wannier_brute", "g_wannier_factorised", "g_bloch", "Problem", "default_w_ext",
+    "iterate", "transport_tensors", "ko_residual", "energy_groups",
+]
+
+
+# ----------------------------------------------------------------------------
+# meshes and phases
+
+def mesh_points(n):
+    """Gamma-centred n^3 mesh in fractional coordinates, linear index
+    (a*n + b)*n + c for k = (a, b, c)/n."""
+    a = np.arange(n)
+    g = np.stack(np.meshgrid(a, a, a, indexing="ij"), -1).reshape(-1, 3)
+    return g.astype(np.float64) / n
+
+
+def mesh_linear(ijk, n):
+    ijk = np.mod(np.asarray(ijk, dtype=np.int64), n)
+    return (ijk[..., 0] * n + ijk[..., 1]) * n + ijk[..., 2]
+
+
+def phases(kfrac, R, w=None):
+    """w_R exp(2 pi i k . R) for fractional k and integer R -> [nk, nR]."""
+    arg = 2.0 * np.pi * (np.atleast_2d(kfrac) @ np.asarray(R, dtype=np.float64).T)
+    ph = np.exp(1j * arg)
+    if w is not None:
+        ph = ph * np.asarray(w)[None, :]
+    return ph
+
+
+# ----------------------------------------------------------------------------
+# electrons: Eq. 1 (H(k)), Eq. 2 (velocity)
+
+def bloch_hamiltonian(mat, kfrac):
+    """Eq. 1: H(k) = sum_Re w exp(i k.Re) H(Re)."""
+    return np.einsum("kr,rab->kab", phases(kfrac, mat["re"], mat["wre"]), mat["h_r"])
+
+
+def _cart(mat, R):
+    return np.asarray(R, dtype=np.float64) @ np.asarray(mat["lat"])  # Angstrom
+
+
+def bloch_hamiltonian_grad(mat, kfrac):
+    """Cartesian gradient of Eq. 1: sum_Re i Re_cart w exp(i k.Re) H(Re), eV*A."""
+    ph = phases(kfrac, mat["re"], mat["wre"])
+    rc = _cart(mat, mat["re"])
+    return np.einsum("kr,rc,rab->kcab", 1j * ph, rc, mat["h_r"])
+
+
+def electron_bands(mat, kfrac):
+    """Diagonalise H(k) (after Eq. 1): eigenvalues ascending, U columns."""
+    return np.linalg.eigh(bloch_hamiltonian(mat, kfrac))
+
+
+def _group_average(values, energies, tol=DEGEN_TOL):
+    """Average per-state values over groups of (sorted) degenerate states."""
+    out = values.copy()
+    nk, nb = energies.shape
+    for k in range(nk):
+        start = 0
+        for b in range(1, nb + 1):
+            if b == nb or energies[k, b] - energies[k, b - 1] >= tol:
+                if b - start > 1:
+                    out[k, start:b] = values[k, start:b].mean(0)
+                start = b
+    return out
+
+
+def electron_velocities(mat, kfrac, eps, U):
+    """Eq. 2: v = (1/hbar) <mk| grad_k H |mk>, m/s, degenerate groups averaged."""
+    dh = bloch_hamiltonian_grad(mat, kfrac)
+    diag = np.einsum("kam,kcab,kbm->kmc", np.conj(U), dh, U).real  # eV*A
+    v = diag * ANG_M / HBAR_EVS
+    return _group_average(v, eps)
+
+
+# ----------------------------------------------------------------------------
+# phonons: Eq. 3 (D(q), short-range part), Eq. 5 (velocity)
+
+def dynamical_matrix(mat, qfrac):
+    """Eq. 3 without the non-analytic term: D(q) = sum_Rp w exp(i q.Rp) D(Rp)."""
+    return np.einsum("kr,rab->kab", phases(qfrac, mat["rp"], mat["wrp"]), mat["d_r"])
+
+
+def dynamical_matrix_grad(mat, qfrac):
+    ph = phases(qfrac, mat["rp"], mat["wrp"])
+    rc = _cart(mat, mat["rp"])
+    return np.einsum("kr,rc,rab->kcab", 1j * ph, rc, mat["d_r"])
+
+
+def phonon_modes(mat, qfrac):
+    """Diagonalise D(q): hbar*omega = sqrt(C max(lambda, 0)) eV, u columns."""
+    lam, u = np.linalg.eigh(dynamical_matrix(mat, qfrac))
+    hw = np.sqrt(C_PHONON * np.maximum(lam, 0.0))
+    return hw, u
+
+
+def phonon_velocities(mat, qfrac, hw, u, omega_min=OMEGA_MIN_DEFAULT):
+    """Eq. 5: v = <sq| grad_q D |sq> / (2 omega), m/s; zero below omega_min."""
+    dd = dynamical_matrix_grad(mat, qfrac)
+    diag = np.einsum("kas,kcab,kbs->ksc", np.conj(u), dd, u).real  # eV/(A amu)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = C_PHONON * diag / (2.0 * hw[..., None]) * ANG_M / HBAR_EVS
+    v = np.where((hw >= omega_min)[..., None], v, 0.0)
+    return _group_average(v, hw)
+
+
+# ----------------------------------------------------------------------------
+# thermal factors and the delta function (Eq. 8)
+
+def fermi_pair(eps, mu, T):
+    """(f, 1 - f) of the Fermi-Dirac distribution, each from its own logistic."""
+    x = (np.asarray(eps) - mu) / (KB_EVK * T)
+    f = np.exp(-np.logaddexp(0.0, x))
+    omf = np.exp(-np.logaddexp(0.0, -x))
+    return f, omf
+
+
+def bose_pair(hw, T):
+    """(n, 1 + n) of the Bose-Einstein distribution."""
+    y = np.asarray(hw) / (KB_EVK * T)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        n = 1.0 / np.expm1(y)
+        onp = -1.0 / np.expm1(-y)
+    return n, onp
+
+
+def gaussian_delta(x, sigma):
+    """Normalised Gaussian of standard deviation sigma (eV^-1)."""
+    return np.exp(-0.5 * (np.asarray(x) / sigma) ** 2) / (np.sqrt(2.0 * np.pi) * sigma)
+
+
+# ----------------------------------------------------------------------------
+# Eq. 6: the e-ph vertex
+
+def g_wannier_brute(mat, k, q):
+    """Wannier part of Eq. 6 as the literal double sum over (Re, Rp):
+    gW_x = sum_{Re,Rp} w_e w_p exp(i(k.Re + q.Rp)) g(Re, Rp)_x  -> [nbr, nb, nb]."""
+    re, rp = np.asarray(mat["re"], float), np.asarray(mat["rp"], float)
+    k = np.asarray(k, float)
+    q = np.asarray(q, float)
+    nbr = 3 * mat["natom"]
+    nb = mat["nwann"]
+    out = np.zeros((nbr, nb, nb), dtype=np.complex128)
+    for ie in range(re.shape[0]):
+        for ip in range(rp.shape[0]):
+            ph = mat["wre"][ie] * mat["wrp"][ip] * np.exp(
+                2j * np.pi * (k @ re[ie] + q @ rp[ip]))
+            out += ph * mat["g_r"][ie, ip]
+    return out
+
+
+def g_wannier_factorised(mat, k, qs):
+    """Same sum as :func:`g_wannier_brute`, the exponential split into its
+    R_e and R_p factors: first sum over R_e at fixed k, then over R_p for
+    every q in ``qs`` -> [nq, nbr, nb, nb]."""
+    g = mat["g_r"]
+    ne, npr = g.shape[0], g.shape[1]
+    phk = phases(k, mat["re"], mat["wre"])[0]                          # [Re]
+    gk = (phk @ g.reshape(ne, -1)).reshape((npr,) + g.shape[2:])       # [Rp, x, n', m']
+    phq = phases(np.atleast_2d(qs), mat["rp"], mat["wrp"])             # [nq, Rp]
+    return (phq @ gk.reshape(npr, -1)).reshape((phq.shape[0],) + g.shape[2:])
+
+
+def phonon_lengths(mat, hw, omega_min=OMEGA_MIN_DEFAULT):
+    """Eq. 6 prefactor l_{x,s} = sqrt(C / (2 M_tau(x) hbar omega_s)) in A,
+    zero for modes below omega_min -> [..., nbr(x), nbr(s)]."""
+    mass_x = np.repeat(np.asarray(mat["mass"], float), 3)
+    hw = np.asarray(hw)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l = np.sqrt(C_PHONON / (2.0 * mass_x[:, None] * hw[..., None, :]))
+    return np.where((hw >= omega_min)[..., None, :], l, 0.0)
+
+
+def g_bloch(mat, gW, Uk, Ukq, u_q, hw_q, omega_min=OMEGA_MIN_DEFAULT):
+    """Eq. 6 Bloch vertex g[..., s, n, m] from the Wannier-gauge gW[..., x, n', m']:
+    rotate with the electron eigenvectors at k (initial) and k+q (final), then
+    project on the phonon eigenvectors with the length prefactor."""
+    gh = np.einsum("...ab,...xac,...cd->...xbd", np.conj(Ukq), gW, Uk)
+    lu = phonon_lengths(mat, hw_q, omega_min) * u_q                   # [..., x, s]
+    return np.einsum("...xs,...xnm->...snm", lu, gh)
+
+
+# ----------------------------------------------------------------------------
+# the whole problem on a mesh
+
+class Problem:
+    """Tables and transition probabilities of one material on an n^3 mesh
+    (equal k and q meshes, so q = k' - k mod 1 lies on the q mesh)."""
+
+    def __init__(self, mat, mesh, mu, window, sigma, omega_min=OMEGA_MIN_DEFAULT):
+        self.mat = mat
+        self.n = int(mesh)
+        self.mu = float(mu)
+        self.window = float(window)
+        self.sigma = float(sigma)
+        self.omega_min = float(omega_min)
+        self.nb = int(mat["nwann"])
+        self.nbr = 3 * int(mat["natom"])
+        self.kfrac = mesh_points(self.n)
+        self.nk = self.kfrac.shape[0]
+        self.nq = self.nk
+        self.ijk = np.rint(self.kfrac * self.n).astype(np.int64)
+
+        # electrons on the whole mesh: energies decide the window (Eq. 1)
+        eps_all = np.empty((self.nk, self.nb))
+        for s in range(0, self.nk, 65536):
+            eps_all[s:s + 65536] = np.linalg.eigvalsh(
+                bloch_hamiltonian(mat, self.kfrac[s:s + 65536]))
+        self.eps_all = eps_all
+        act = np.abs(eps_all - self.mu) <= self.window
+        self.active = act
+        self.kept = np.nonzero(act.any(1))[0]                 # mesh indices, ascending
+        self.kidx_of_mesh = np.full(self.nk, -1, dtype=np.int64)
+        self.kidx_of_mesh[self.kept] = np.arange(self.kept.size)
+        st_k, st_m = np.nonzero(act[self.kept])
+        self.state_k = self.kept[st_k]                        # mesh index of each state
+        self.state_kidx = st_k
+        self.state_m = st_m
+        self.nstates = st_k.size
+        self.nact = act[self.kept].sum(1)
+        self.state_off = np.concatenate([[0], np.cumsum(self.nact)])
+
+        kk = self.kfrac[self.kept]
+        self.eps_kept, self.U_kept = electron_bands(mat, kk)
+        self.v_kept = electron_velocities(mat, kk, self.eps_kept, self.U_kept)
+        self.eps = self.eps_kept[st_k, st_m]
+        self.v_state = self.v_kept[st_k, st_m]
+
+        # phonons on the whole q mesh (Eqs. 3, 5)
+        self.hw, self.u = phonon_modes(mat, self.kfrac)
+        self.v_ph = phonon_velocities(mat, self.kfrac, self.hw, self.u, self.omega_min)
+        self.mode_on = self.hw >= self.omega_min
+
+    # ---- index helpers
+    def q_index(self, kmesh_from, kmesh_to):
+        return mesh_linear(self.ijk[kmesh_to] - self.ijk[kmesh_from], self.n)
+
+    def neg_q(self, qmesh):
+        return mesh_linear(-self.ijk[qmesh], self.n)
+
+    # ---- Eq. 6 for one initial kept k and every kept k'
+    def g2_row(self, kidx, brute=False):
+        """|g^{s n m}_{k q}|^2 for the kept k number ``kidx`` (initial) and every
+        kept k' (final) -> [nK', nbr(s), nb(n), nb(m)]."""
+        kmesh = self.kept[kidx]
+        k = self.kfrac[kmesh]
+        qmesh = self.q_index(np.full(self.kept.size, kmesh), self.kept)
+        qs = self.kfrac[qmesh]
+        if brute:
+            gW = np.stack([g_wannier_brute(self.mat, k, q) for q in qs])
+        else:
+            gW = g_wannier_factorised(self.mat, k, qs)
+        g = g_bloch(self.mat, gW, self.U_kept[kidx][None], self.U_kept,
+                    self.u[qmesh], self.hw[qmesh], self.omega_min)
+        return np.abs(g) ** 2, qmesh
+
+    # ---- Eq. 8
+    def transition_probs(self, T, rows=None, brute=False):
+        """X^+ and X^- of Eq. 8 for initial states ``rows`` (all when None) and
+        every final active state -> (Xp, Xm) of shape [len(rows), nstates, nbr]."""
+        rows = np.arange(self.nstates) if rows is None else np.asarray(rows)
+        f, omf = fermi_pair(self.eps, self.mu, T)
+        pref = 2.0 * np.pi / (HBAR_EVS * self.nk)
+        Xp = np.zeros((rows.size, self.nstates, self.nbr))
+        Xm = np.zeros_like(Xp)
+        by_k = {}
+        for r, i in enumerate(rows):
+            by_k.setdefault(int(self.state_kidx[i]), []).append((r, i))
+        jk = self.state_kidx                      # kept-k number of each final state
+        jm = self.state_m
+        for kidx, lst in by_k.items():
+            g2, qmesh = self.g2_row(kidx, brute)  # [nK', s, n, m]
+            hw = self.hw[qmesh]                   # [nK', s]
+            on = self.mode_on[qmesh]
+            nq, onq = bose_pair(hw, T)
+            for r, i in lst:
+                m = self.state_m[i]
+                g2j = g2[jk, :, jm, m]             # [nstates, s]
+                de = (self.eps - self.eps[i])[:, None]          # eps_j - eps_i
+                dp = gaussian_delta(de - hw[jk], self.sigma)
+                dm = gaussian_delta(de + hw[jk], self.sigma)
+                occ = f[i] * omf                               # f_i (1 - f_j)
+                with np.errstate(invalid="ignore"):
+                    xp = pref * g2j * occ[:, None] * nq[jk] * dp
+                    xm = pref * g2j * occ[:, None] * onq[jk] * dm
+                Xp[r] = np.where(on[jk], xp, 0.0)
+                Xm[r] = np.where(on[jk], xm, 0.0)
+        return Xp, Xm
+
+    # ---- Eq. 21 (e-ph part)
+    def rates_e(self, T, Xp, Xm, rows=None):
+        rows = np.arange(self.nstates) if rows is None else np.asarray(rows)
+        f, omf = fermi_pair(self.eps, self.mu, T)
+        tot = (Xp + Xm).sum(axis=(1, 2))
+        return tot / (f[rows] * omf[rows])
+
+    # ---- Eqs. 12, 25 (ph-e part) from the full X^+ array
+    def rates_ph(self, T, Xp):
+        """W_sq = d_s/(n(1+n)) sum_{mnk} Y, Y = (N_k/N_q) X^+  -> [nq, nbr]."""
+        qij = self.q_index(self.state_k[:, None], self.state_k[None, :])   # [i, j]
+        acc = _scatter_q(qij, Xp, self.nq)
+        n, onp = bose_pair(self.hw, T)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            w = SPIN_DEG * (self.nk / self.nq) * acc / (n * onp)
+        return np.where(self.mode_on, w, 0.0)
+
+    def rates_ph_at(self, T, qmesh_list):
+        """W_sq of Eq. 25 (ph-e part) at selected q, each summed over its pairs
+        (k, k+q) directly from Eq. 12 -> [len(q), nbr]."""
+        f, omf = fermi_pair(self.eps, self.mu, T)
+        pref = 2.0 * np.pi / (HBAR_EVS * self.nq)
+        out = np.zeros((len(qmesh_list), self.nbr))
+        for t, qm in enumerate(qmesh_list):
+            hw = self.hw[qm]
+            if not self.mode_on[qm].any():
+                continue
+            n, onp = bose_pair(hw, T)
+            acc = np.zeros(self.nbr)
+            for kidx, kmesh in enumerate(self.kept):
+                kp = mesh_linear(self.ijk[kmesh] + self.ijk[qm], self.n)
+                kpidx = self.kidx_of_mesh[kp]
+                if kpidx < 0:
+                    continue
+                gW = g_wannier_factorised(self.mat, self.kfrac[kmesh], self.kfrac[qm][None])[0]
+                g = g_bloch(self.mat, gW, self.U_kept[kidx], self.U_kept[kpidx],
+                            self.u[qm], hw, self.omega_min)
+                g2 = np.abs(g) ** 2                                  # [s, n, m]
+                for i in range(self.state_off[kidx], self.state_off[kidx + 1]):
+                    for j in range(self.state_off[kpidx], self.state_off[kpidx + 1]):
+                        m, nn = self.state_m[i], self.state_m[j]
+                        d = gaussian_delta(self.eps[j] - self.eps[i] - hw, self.sigma)
+                        acc += pref * g2[:, nn, m] * f[i] * omf[j] * n * d
+            with np.errstate(divide="ignore", invalid="ignore"):
+                w = SPIN_DEG * acc / (n * onp)
+            out[t] = np.where(self.mode_on[qm], w, 0.0)
+        return out
+
+
+def _scatter_q(qij, vals, nq):
+    """sum of vals[i, j, s] into out[q_ij, s] (a plain bin count per branch)."""
+    nbr = vals.shape[-1]
+    key = qij.reshape(-1)
+    out = np.empty((nq, nbr))
+    for s in range(nbr):
+        out[:, s] = np.bincount(key, weights=vals[..., s].reshape(-1), minlength=nq)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Eqs. 19-27: the coupled BTEs, unified iteration
+
+def default_w_ext(prob, T, gamma0=1.0e12):
+    """External (non ph-e) phonon rate per mode, s^-1: gamma0 (hw/hw_max)^2 T/300."""
+    hwmax = prob.hw.max()
+    w = gamma0 * (prob.hw / hwmax) ** 2 * (T / 300.0)
+    return np.where(prob.mode_on, w, 0.0)
+
+
+def energy_groups(eps, hw_max, sigma):
+    """Group label of each state: runs of sorted energies split at gaps wider
+    than hw_max + 12 sigma."""
+    eps = np.asarray(eps)
+    order = np.argsort(eps, kind="stable")
+    brk = np.concatenate([[0], np.cumsum(np.diff(eps[order]) > hw_max + 12.0 * sigma)])
+    grp = np.empty(eps.size, dtype=np.int64)
+    grp[order] = brk
+    return grp
+
+
+def _rel_change(new, old):
+    nn = np.linalg.norm(new)
+    return np.linalg.norm(new - old) / max(nn, 1e-300)
+
+
+def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=None):
+    """Solve Eq. 19 with the unified scheme: each phonon (outer) iteration
+    brings the electrons (inner) to self-consistency with the current phonons.
+    ``Xp``/``Xm`` are the full [nstates, nstates, nbr] arrays of Eq. 8.
+    Returns dict(I, J, F, G, W_e, W_ph, iters, converged)."""
+    M, nbr = prob.nstates, prob.nbr
+    f, omf = fermi_pair(prob.eps, prob.mu, T)
+    ff = f * omf
+    W_e = (Xp + Xm).sum(axis=(1, 2)) / ff
+    if w_ext is None:
+        w_ext = default_w_ext(prob, T)
+    W_phe = prob.rates_ph(T, Xp)
+    W_p = W_phe + w_ext                                     # [nq, nbr]
+    n, onp = bose_pair(prob.hw, T)
+    on = prob.mode_on
+
+    v = prob.v_state
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv_we = np.where(W_e > 0, 1.0 / W_e, 0.0)
+        inv_wp = np.where(on & (W_p > 0), 1.0 / W_p, 0.0)
+    I0 = ((prob.eps - prob.mu) / T * inv_we)[:, None] * v      # eV m / K
+    J0 = inv_we[:, None] * v                                   # m (per unit charge)
+    F0 = (prob.hw / T * inv_wp)[..., None] * prob.v_ph         # eV m / K
+    G0 = np.zeros_like(F0)
+
+    qij = prob.q_index(prob.state_k[:, None], prob.state_k[None, :])
+    nqij = prob.neg_q(qij)
+    # normalised kernels
+    with np.errstate(divide="ignore", invalid="ignore"):
+        row = np.where(W_e > 0, 1.0 / (ff * W_e), 0.0)
+    Kp = Xp * row[:, None, None]
+    Km = Xm * row[:, None, None]
+    Kself = (Kp + Km).sum(2)                                   # [i, j]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ph_norm = np.where(on, SPIN_DEG * (prob.nk / prob.nq) * inv_wp / (n * onp), 0.0)
+    w = ff
+    grp = energy_groups(prob.eps, prob.hw.max(), prob.sigma)
+    ngrp = grp.max() + 1
+    wsum = np.bincount(grp, weights=w, minlength=ngrp)
+
+    def project(x):
+        out = x.copy()
+        for c in range(x.shape[1]):
+            mean = np.bincount(grp, weights=w * x[:, c], minlength=ngrp) / wsum
+            out[:, c] -= mean[grp]
+        return out
+
+    def drag_e(phon):
+        """Eq. 23 for fixed phonon responses: sum_{j,s} (-F_{s,q} X^+ + F_{s,-q} X^-)."""
+        acc = np.zeros((M, 3))
+        for c in range(3):
+            acc[:, c] = (-(Kp * phon[qij, :, c]).sum((1, 2))
+                         + (Km * phon[nqij, :, c]).sum((1, 2)))
+        return acc
+
+    def ph_drag(x, phon0):
+        """Eq. 27: phon0 + d_s/(n(1+n)W) sum Y (x_j - x_i), Y = (N_k/N_q) X^+."""
+        acc = np.zeros(phon0.shape)
+        for c in range(3):
+            diff = x[None, :, c] - x[:, None, c]               # x_j - x_i  [i, j]
+            acc[..., c] = _scatter_q(qij, Xp * diff[:, :, None], prob.nq)
+        return phon0 + ph_norm[..., None] * acc
+
+    def solve_e(x0, x):
+        """Electron BTE (Eqs. 19, 22) to self-consistency for a fixed drive x0."""
+        for it in range(1, maxit + 1):
+            xn = project(x0 + Kself @ x)
+            r = _rel_change(xn, x)
+            x = xn
+            if r < tol * 0.1:
+                return x, it, True
+        return x, maxit, False
+
+    out = dict(W_e=W_e, W_ph=W_phe, W_p=W_p, I0=I0, J0=J0, F0=F0)
+    if level == LEVEL_RTA:
+        out.update(I=I0.copy(), J=J0.copy(), F=F0.copy(), G=G0.copy(), iters=0, converged=True)
+        return out
+    if level == LEVEL_DRAGLESS:
+        I, itI, cI = solve_e(I0, I0.copy())
+        J, itJ, cJ = solve_e(J0, J0.copy())
+        out.update(I=I, J=J, F=F0.copy(), G=G0.copy(), iters=max(itI, itJ), converged=cI and cJ)
+        return out
+
+    I, J, F, G = I0.copy(), J0.copy(), F0.copy(), G0.copy()
+    converged = False
+    it = 0
+    for it in range(1, maxit + 1):
+        In, _, c1 = solve_e(I0 + drag_e(F), I)
+        Jn, _, c2 = solve_e(J0 + drag_e(G), J)
+        Fn = ph_drag(In, F0)
+        Gn = ph_drag(Jn, G0)
+        r = max(_rel_change(In, I), _rel_change(Jn, J), _rel_change(Fn, F), _rel_change(Gn, G))
+        I, J, F, G = In, Jn, Fn, Gn
+        if level == LEVEL_PARTIAL:
+            converged = c1 and c2
+            break
+        if r < tol and c1 and c2:
+            converged = True
+            break
+    out.update(I=I, J=J, F=F, G=G, iters=it, converged=converged)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Eqs. 28-31: transport tensors
+
+def transport_tensors(prob, T, I, J, F, G):
+    """sigma, sigma*S, alpha_el, kappa0_el, alpha_ph, kappa_ph (SI units) from
+    Eqs. 28-30 with 1/N_k and 1/N_q normalisations."""
+    V = abs(np.linalg.det(np.asarray(prob.mat["lat"]))) * ANG_M ** 3
+    kT = KB_EVK * T * E_CHARGE                              # J
+    f, omf = fermi_pair(prob.eps, prob.mu, T)
+    ff = f * omf
+    v = prob.v_state
+    I_si, J_si = I * E_CHARGE, J * E_CHARGE
+    F_si, G_si = F * E_CHARGE, G * E_CHARGE
+    de = (prob.eps - prob.mu) * E_CHARGE
+    ce = SPIN_DEG / (V * kT * prob.nk)
+    sigma = ce * E_CHARGE * np.einsum("i,ia,ib->ab", ff, v, J_si)
+    sigmaS = ce * E_CHARGE * np.einsum("i,ia,ib->ab", ff, v, -I_si)
+    alpha_el = -ce * np.einsum("i,i,ia,ib->ab", de, ff, v, J_si)
+    kappa0_el = -ce * np.einsum("i,i,ia,ib->ab", de, ff, v, -I_si)
+    n, onp = bose_pair(prob.hw, T)
+    wgt = np.where(prob.mode_on, prob.hw * E_CHARGE * n * onp, 0.0)
+    cp = 1.0 / (V * kT * prob.nq)
+    alpha_ph = cp * np.einsum("qs,qsa,qsb->ab", wgt, prob.v_ph, -G_si)
+    kappa_ph = cp * np.einsum("qs,qsa,qsb->ab", wgt, prob.v_ph, F_si)
+    return dict(sigma=sigma, sigmaS=sigmaS, alpha_el=alpha_el, kappa0_el=kappa0_el,
+                alpha_ph=alpha_ph, kappa_ph=kappa_ph)
+
+
+def ko_residual(tens, T):
+    """Eq. 31: |sigma S - (alpha_el + alpha_ph)/T| / |sigma S| (Frobenius)."""
+    d = tens["sigmaS"] - (tens["alpha_el"] + tens["alpha_ph"]) / T
+    return np.linalg.norm(d) / max(np.linalg.norm(tens["sigmaS"]), 1e-300)

@@ -1,0 +1,472 @@
+"""Pins of the CPU oracle to facts other than itself.
+
+Each test fixes a part of the oracle against mathematics the paper's method
+must obey: exact inverse transforms on a coarse mesh, closed-form band and
+phonon models, finite differences, a quadrature of the delta function,
+identities of the Fermi/Bose factors, analytic eigenvectors, detailed
+balance between absorption and emission, closed-form rates of a flat-band /
+Einstein-phonon model, brute force on tiny meshes and a dense direct solve of
+the coupled BTEs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import materials as sm
+
+
+# ---------------------------------------------------------------------------
+# helpers: hand-built materials
+
+def _material(nb, na, re, rp, h_r, d_r, g_r, masses, a=5.4):
+    re = np.asarray(re, dtype=np.int32).reshape(-1, 3)
+    rp = np.asarray(rp, dtype=np.int32).reshape(-1, 3)
+    return dict(nwann=nb, natom=na, re=re, rp=rp, wre=np.ones(len(re)),
+                wrp=np.ones(len(rp)), lat=a * np.eye(3), mass=np.asarray(masses, float),
+                h_r=np.asarray(h_r, complex), d_r=np.asarray(d_r, float),
+                g_r=np.asarray(g_r, complex))
+
+
+def _tiny(name):
+    cfg = synth.config(name)
+    return cfg, synth.material_for(cfg)
+
+
+# ---------------------------------------------------------------------------
+# Eqs. 1, 3, 6: Fourier sums
+
+def test_coarse_mesh_exactness_hamiltonian():
+    """R = {-1,0,1}^3 is dual to a 3^3 mesh: H(R) obtained from random Bloch
+    matrices on that mesh by an FFT must interpolate back to them exactly."""
+    rng = np.random.default_rng(7)
+    n, nb = 3, 3
+    kf = oracle.mesh_points(n)
+    hk = rng.standard_normal((n, n, n, nb, nb)) + 1j * rng.standard_normal((n, n, n, nb, nb))
+    hk = hk + np.conj(np.swapaxes(hk, -1, -2))
+    # H(R) = (1/N) sum_k exp(-2 pi i k.R) H(k): numpy's forward FFT, divided by N
+    hR_grid = np.fft.fftn(hk, axes=(0, 1, 2)) / n ** 3
+    rs = sm.rset_cube(-1, 1)
+    h_r = np.stack([hR_grid[tuple(np.mod(r, n))] for r in rs])
+    mat = _material(nb, 1, rs, rs, h_r, np.zeros((27, 3, 3)), np.zeros((27, 27, 3, nb, nb)), [1.0])
+    got = oracle.bloch_hamiltonian(mat, kf)
+    assert np.abs(got - hk.reshape(-1, nb, nb)).max() < 1e-13
+
+
+def test_coarse_mesh_exactness_dynamical_matrix():
+    rng = np.random.default_rng(8)
+    n, nbr = 3, 6
+    # real force constants with D(-R) = D(R)^T give Hermitian D(q)
+    rs = sm.rset_cube(-1, 1)
+    idx = {tuple(r): i for i, r in enumerate(rs)}
+    d = rng.standard_normal((27, nbr, nbr))
+    d = 0.5 * (d + np.transpose(d[[idx[tuple(-r)] for r in rs]], (0, 2, 1)))
+    mat = _material(1, 2, rs, rs, np.zeros((27, 1, 1)), d, np.zeros((27, 27, nbr, 1, 1)), [1.0, 2.0])
+    dq = oracle.dynamical_matrix(mat, oracle.mesh_points(n))
+    # back to real space with numpy's inverse FFT and compare
+    grid = dq.reshape(n, n, n, nbr, nbr)
+    back = np.fft.fftn(grid, axes=(0, 1, 2)) / n ** 3
+    for r in rs:
+        assert np.abs(back[tuple(np.mod(r, n))] - d[idx[tuple(r)]]).max() < 1e-13
+    assert np.abs(dq - np.conj(np.swapaxes(dq, -1, -2))).max() < 1e-13
+
+
+def test_coarse_mesh_exactness_vertex():
+    """g(Re, Rp) from random g(k, q) on a 3^3 x 3^3 grid by a 6-d FFT must
+    interpolate back to g(k, q) exactly (both the brute double sum and the
+    factorised sum)."""
+    rng = np.random.default_rng(9)
+    n, nb, nbr = 3, 2, 3
+    shape = (n, n, n, n, n, n, nbr, nb, nb)
+    gkq = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    gR = np.fft.fftn(gkq, axes=tuple(range(6))) / n ** 6
+    rs = sm.rset_cube(-1, 1)
+    g_r = np.empty((27, 27, nbr, nb, nb), complex)
+    for ie, re_ in enumerate(rs):
+        for ip, rp_ in enumerate(rs):
+            g_r[ie, ip] = gR[tuple(np.mod(re_, n)) + tuple(np.mod(rp_, n))]
+    mat = _material(nb, 1, rs, rs, np.zeros((27, nb, nb)), np.zeros((27, 3, 3)), g_r, [1.0])
+    kf = oracle.mesh_points(n)
+    for a in (0, 5, 13, 26):
+        ka = tuple(np.rint(kf[a] * n).astype(int))
+        qs = kf
+        fac = oracle.g_wannier_factorised(mat, kf[a], qs)
+        want = gkq[ka].reshape(n ** 3, nbr, nb, nb)
+        assert np.abs(fac - want).max() < 1e-12
+        for b in (0, 7, 20):
+            br = oracle.g_wannier_brute(mat, kf[a], kf[b])
+            assert np.abs(br - want[b]).max() < 1e-12
+
+
+@pytest.mark.parametrize("name", ["tiny3", "tiny4"])
+def test_brute_equals_factorised_rates(name):
+    """Transition probabilities from the literal double sum equal the
+    factorised sum on tiny meshes."""
+    cfg, mat = _tiny(name)
+    prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+    rows = np.arange(0, prob.nstates, max(1, prob.nstates // 5))
+    xb = prob.transition_probs(300.0, rows, brute=True)
+    xf = prob.transition_probs(300.0, rows, brute=False)
+    for a, b in zip(xb, xf):
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max()
+
+
+# ---------------------------------------------------------------------------
+# eigensolves and velocities (Eqs. 1-2, 3, 5)
+
+def test_cosine_band_and_velocity():
+    """One band with nearest-neighbour hopping t: eps = e0 + 2t sum cos(2 pi k_i),
+    v_i = -(2 t a / hbar) sin(2 pi k_i)."""
+    e0, t, a = 0.3, -0.7, 5.4
+    rs = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]])
+    h = np.array([e0, t, t, t, t, t, t], complex).reshape(-1, 1, 1)
+    mat = _material(1, 1, rs, rs[:1], h, np.zeros((1, 3, 3)), np.zeros((7, 1, 3, 1, 1)), [1.0], a)
+    rng = np.random.default_rng(1)
+    k = rng.random((50, 3))
+    eps, U = oracle.electron_bands(mat, k)
+    want = e0 + 2 * t * np.cos(2 * np.pi * k).sum(1)
+    assert np.abs(eps[:, 0] - want).max() < 1e-13
+    v = oracle.electron_velocities(mat, k, eps, U)
+    vw = -(2 * t * a / oracle.HBAR_EVS) * np.sin(2 * np.pi * k) * oracle.ANG_M
+    assert np.abs(v[:, 0, :] - vw).max() < 1e-10 * np.abs(vw).max()
+
+
+def test_scalar_springs_phonons():
+    """D(0) = 6K/M, D(+-e_i) = -K/M (times I3): (hw)^2 = C (4K/M) sum sin^2(pi q_i),
+    triply degenerate; v = a C K sin(2 pi q)/(M hw) /hbar."""
+    K, M, a = 2.5, 28.0855, 5.4
+    rs = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]])
+    d = np.stack([6 * K / M * np.eye(3)] + [-K / M * np.eye(3)] * 6)
+    mat = _material(1, 1, rs[:1], rs, np.zeros((1, 1, 1)), d, np.zeros((1, 7, 3, 1, 1)), [M], a)
+    rng = np.random.default_rng(2)
+    q = rng.random((40, 3))
+    hw, u = oracle.phonon_modes(mat, q)
+    want = np.sqrt(oracle.C_PHONON * 4 * K / M * (np.sin(np.pi * q) ** 2).sum(1))
+    assert np.abs(hw - want[:, None]).max() < 1e-13
+    v = oracle.phonon_velocities(mat, q, hw, u)
+    vw = a * oracle.C_PHONON * K * np.sin(2 * np.pi * q) / (M * want[:, None]) \
+        * oracle.ANG_M / oracle.HBAR_EVS
+    for s in range(3):
+        assert np.abs(v[:, s, :] - vw).max() < 1e-9 * np.abs(vw).max()
+    # acoustic sum rule: zero modes at Gamma
+    hw0, _ = oracle.phonon_modes(mat, np.zeros((1, 3)))
+    assert hw0.max() < 1e-6
+
+
+@pytest.mark.parametrize("name", ["plain8", "tiny4"])
+def test_eigensolves_hermitian_residuals(name):
+    cfg, mat = _tiny(name)
+    k = np.random.default_rng(3).random((30, 3))
+    H = oracle.bloch_hamiltonian(mat, k)
+    assert np.abs(H - np.conj(np.swapaxes(H, -1, -2))).max() < 1e-13
+    eps, U = oracle.electron_bands(mat, k)
+    nrm = np.abs(H).max()
+    assert np.abs(H @ U - U * eps[:, None, :]).max() < 1e-12 * nrm
+    assert np.abs(np.conj(np.swapaxes(U, -1, -2)) @ U - np.eye(U.shape[-1])).max() < 1e-13
+    D = oracle.dynamical_matrix(mat, k)
+    lam, u = np.linalg.eigh(D)
+    assert np.abs(D @ u - u * lam[:, None, :]).max() < 1e-12 * np.abs(D).max()
+    assert lam.min() > -1e-12 * np.abs(D).max()          # Gram form: PSD
+    hw0, _ = oracle.phonon_modes(mat, np.zeros((1, 3)))
+    assert np.sort(hw0[0])[:3].max() < 1e-6               # ASR: 3 zero modes at Gamma
+
+
+@pytest.mark.parametrize("name", ["plain8", "tiny4"])
+def test_velocities_match_finite_differences(name):
+    """Eq. 2 and Eq. 5 against central differences of the eigenvalues."""
+    cfg, mat = _tiny(name)
+    rng = np.random.default_rng(4)
+    k = rng.random((6, 3))
+    a = mat["lat"][0, 0]
+    h = 1e-5
+    eps, U = oracle.electron_bands(mat, k)
+    v = oracle.electron_velocities(mat, k, eps, U)
+    hw, u = oracle.phonon_modes(mat, k)
+    vp = oracle.phonon_velocities(mat, k, hw, u)
+    for c in range(3):
+        dk = np.zeros(3)
+        dk[c] = h
+        ep, _ = oracle.electron_bands(mat, k + dk)
+        em, _ = oracle.electron_bands(mat, k - dk)
+        # d eps / d k_cart = (a / 2 pi) d eps / d k_frac
+        fd = (ep - em) / (2 * h) * a / (2 * np.pi) * oracle.ANG_M / oracle.HBAR_EVS
+        assert np.abs(fd - v[..., c]).max() < 1e-6 * np.abs(v).max()
+        hp, _ = oracle.phonon_modes(mat, k + dk)
+        hm, _ = oracle.phonon_modes(mat, k - dk)
+        fdp = (hp - hm) / (2 * h) * a / (2 * np.pi) * oracle.ANG_M / oracle.HBAR_EVS
+        assert np.abs(fdp - vp[..., c]).max() < 1e-5 * np.abs(vp).max()
+
+
+# ---------------------------------------------------------------------------
+# delta and thermal factors (Eq. 8)
+
+def test_gaussian_delta_normalised_and_symmetric():
+    s = 0.01
+    x = np.linspace(-12 * s, 12 * s, 200001)
+    d = oracle.gaussian_delta(x, s)
+    integral = np.trapezoid(d, x)
+    assert abs(integral - 1.0) < 1e-12
+    assert np.abs(d - oracle.gaussian_delta(-x, s)).max() == 0.0
+
+
+def test_thermal_identities():
+    x = np.linspace(-3, 3, 101)
+    T = 250.0
+    f, omf = oracle.fermi_pair(x, 0.0, T)
+    f2, omf2 = oracle.fermi_pair(-x, 0.0, T)
+    assert np.abs(f + f2 - 1).max() < 1e-15
+    assert np.abs(omf - f2).max() < 1e-15
+    y = np.linspace(1e-3, 0.2, 50)
+    n, onp = oracle.bose_pair(y, T)
+    nm, _ = oracle.bose_pair(-y, T)
+    assert np.abs(onp + nm).max() < 1e-12 * np.abs(nm).max()
+    # at exact energy conservation eps_n = eps_m + hw:
+    # (1 - f_n) n / (1 - f_m) = n + f_n
+    em = np.linspace(-0.2, 0.2, 21)
+    for hw in (0.005, 0.03, 0.06):
+        _, omf_m = oracle.fermi_pair(em, 0.0, T)
+        f_n, omf_n = oracle.fermi_pair(em + hw, 0.0, T)
+        nn, _ = oracle.bose_pair(hw, T)
+        lhs = omf_n * nn / omf_m
+        assert np.abs(lhs - (nn + f_n)).max() < 1e-13 * lhs.max()
+
+
+# ---------------------------------------------------------------------------
+# Eq. 6: Bloch rotation
+
+def test_gauge_invariance_of_g2():
+    cfg, mat = _tiny("tiny4")
+    rng = np.random.default_rng(5)
+    k, q = rng.random(3), rng.random(3)
+    gW = oracle.g_wannier_factorised(mat, k, q[None])[0]
+    _, Uk = oracle.electron_bands(mat, k[None])
+    _, Ukq = oracle.electron_bands(mat, (k + q)[None])
+    hw, u = oracle.phonon_modes(mat, q[None])
+    g1 = oracle.g_bloch(mat, gW, Uk[0], Ukq[0], u[0], hw[0])
+    ph = lambda n: np.exp(2j * np.pi * rng.random(n))  # noqa: E731
+    g2 = oracle.g_bloch(mat, gW, Uk[0] * ph(mat["nwann"]), Ukq[0] * ph(mat["nwann"]),
+                        u[0] * ph(3 * mat["natom"]), hw[0])
+    assert np.abs(np.abs(g1) ** 2 - np.abs(g2) ** 2).max() < 1e-13 * (np.abs(g1) ** 2).max()
+
+
+def test_rotation_index_order_analytic_eigenvectors():
+    """Two bands, H(k) = [[D, t(k)], [t(k)*, -D]] with t(k) = t0 exp(2 pi i k_x),
+    one atom with an Einstein spring, g^W = c_x * identity.  Summed over the
+    degenerate branches, |g^{nm}|^2 = l^2 |c|^2 |<n,k+q|m,k>|^2 with the
+    closed-form eigenvectors; the final band n sits at k+q."""
+    Dl, t0, K, M = 0.4, 0.3 + 0.2j, 1.7, 12.011
+    rs_e = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0]])
+    h = np.zeros((3, 2, 2), complex)
+    h[0] = np.diag([Dl, -Dl])
+    h[1, 0, 1] = t0
+    h[2, 1, 0] = np.conj(t0)
+    d = (K / M * np.eye(3))[None]
+    c = np.array([0.7 - 0.1j, -0.2 + 0.5j, 0.3j])
+    g = np.zeros((3, 1, 3, 2, 2), complex)
+    for x in range(3):
+        g[0, 0, x] = c[x] * np.eye(2)
+    mat = _material(2, 1, rs_e, [[0, 0, 0]], h, d, g, [M])
+    hw0 = np.sqrt(oracle.C_PHONON * K / M)
+    l2 = oracle.C_PHONON / (2 * M * hw0)
+
+    def vecs(k):
+        tk = t0 * np.exp(2j * np.pi * k[0])
+        E = np.sqrt(Dl ** 2 + abs(tk) ** 2)
+        lo = np.array([-tk, Dl + E])
+        hi = np.array([Dl + E, np.conj(tk)])
+        return np.stack([lo / np.linalg.norm(lo), hi / np.linalg.norm(hi)], 1)
+
+    rng = np.random.default_rng(6)
+    for _ in range(5):
+        k, q = rng.random(3), rng.random(3)
+        Vk, Vkq = vecs(k), vecs(k + q)
+        gW = oracle.g_wannier_factorised(mat, k, q[None])[0]
+        _, Uk = oracle.electron_bands(mat, k[None])
+        _, Ukq = oracle.electron_bands(mat, (k + q)[None])
+        hw, u = oracle.phonon_modes(mat, q[None])
+        gb = oracle.g_bloch(mat, gW, Uk[0], Ukq[0], u[0], hw[0])
+        got = (np.abs(gb) ** 2).sum(0)                       # [n, m]
+        ov = np.abs(np.conj(Vkq).T @ Vk) ** 2                 # [n, m] = |<n,k+q|m,k>|^2
+        want = l2 * np.vdot(c, c).real * ov
+        assert np.abs(got - want).max() < 1e-12 * want.max()
+
+
+def test_hermitian_pair_identity():
+    """|g^s_{nm}(k,q)|^2 = |g^s_{mn}(k+q,-q)|^2 for the generated materials."""
+    cfg, mat = _tiny("plain8")
+    rng = np.random.default_rng(10)
+    for _ in range(4):
+        k, q = rng.random(3), rng.random(3)
+        gW = oracle.g_wannier_factorised(mat, k, q[None])[0]
+        gR = oracle.g_wannier_factorised(mat, k + q, -q[None])[0]
+        _, Uk = oracle.electron_bands(mat, k[None])
+        _, Ukq = oracle.electron_bands(mat, (k + q)[None])
+        hw, u = oracle.phonon_modes(mat, q[None])
+        hwm, um = oracle.phonon_modes(mat, -q[None])
+        a = np.abs(oracle.g_bloch(mat, gW, Uk[0], Ukq[0], u[0], hw[0])) ** 2
+        b = np.abs(oracle.g_bloch(mat, gR, Ukq[0], Uk[0], um[0], hwm[0])) ** 2
+        assert np.abs(a - np.swapaxes(b, -1, -2)).max() < 1e-12 * a.max()
+
+
+# ---------------------------------------------------------------------------
+# Eq. 8: transition probabilities
+
+@pytest.fixture(scope="module")
+def plain8():
+    cfg, mat = _tiny("plain8")
+    prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+    rows = np.arange(0, prob.nstates, 37)
+    Xp, Xm = prob.transition_probs(cfg["T"], rows)
+    return cfg, prob, rows, Xp, Xm
+
+
+def test_detailed_balance_per_term(plain8):
+    """X^+_{i->j|s,q} exp(-beta(eps_j - eps_i - hw)) = X^-_{j->i|s,-q}."""
+    cfg, prob, rows, Xp, Xm = plain8
+    T = cfg["T"]
+    cols = np.arange(0, prob.nstates, 53)
+    _, XmT = prob.transition_probs(T, cols)
+    beta = 1.0 / (oracle.KB_EVK * T)
+    worst = 0.0
+    for r, i in enumerate(rows):
+        for c, j in enumerate(cols):
+            q = prob.q_index(prob.state_k[i], prob.state_k[j])
+            hw = prob.hw[q]
+            lhs = Xp[r, j] * np.exp(-beta * (prob.eps[j] - prob.eps[i] - hw))
+            rhs = XmT[c, i]
+            scale = max(lhs.max(), rhs.max(), 1e-300)
+            worst = max(worst, np.abs(lhs - rhs).max() / scale)
+    assert worst < 1e-10
+
+
+def _flat_einstein(nk_mesh, eps0, K, M, g0, sigma):
+    rs = np.array([[0, 0, 0]])
+    g = np.zeros((1, 1, 3, 1, 1), complex)
+    g[0, 0, :, 0, 0] = g0
+    mat = _material(1, 1, rs, rs, np.full((1, 1, 1), eps0), (K / M * np.eye(3))[None], g, [M])
+    return mat
+
+
+def test_flat_band_einstein_closed_forms():
+    """Flat band, Einstein phonon, local vertex g0: W_e = (2pi/hbar) l^2 |g0|^2
+    (2n+1) delta(hw0) and sum_s W_ph = d_s (2pi/hbar)(N_k/N_q) l^2 |g0|^2
+    f(1-f) delta(hw0) / (1+n)."""
+    eps0, K, M, sigma, T, mu = 0.05, 0.9, 28.0855, 0.02, 300.0, 0.0
+    g0 = np.array([0.4 + 0.1j, -0.3j, 0.25])
+    mat = _flat_einstein(3, eps0, K, M, g0, sigma)
+    prob = oracle.Problem(mat, 3, mu, np.inf, sigma)
+    Xp, Xm = prob.transition_probs(T)
+    W = prob.rates_e(T, Xp, Xm)
+    hw0 = np.sqrt(oracle.C_PHONON * K / M)
+    l2 = oracle.C_PHONON / (2 * M * hw0)
+    n, onp = oracle.bose_pair(hw0, T)
+    d = oracle.gaussian_delta(hw0, sigma)
+    g2 = np.vdot(g0, g0).real
+    want = 2 * np.pi / oracle.HBAR_EVS * l2 * g2 * (2 * n + 1) * d
+    assert np.abs(W - want).max() < 1e-12 * want
+    Wph = prob.rates_ph(T, Xp)
+    f, omf = oracle.fermi_pair(eps0, mu, T)
+    want_ph = oracle.SPIN_DEG * 2 * np.pi / oracle.HBAR_EVS * l2 * g2 * f * omf * d / onp
+    assert np.abs(Wph.sum(1) - want_ph).max() < 1e-12 * want_ph
+
+
+def test_e_side_equals_ph_side(plain8):
+    """sum of all X^+ (electron side) = (N_q/N_k) sum of all Y (phonon side)."""
+    cfg, prob, rows, Xp, Xm = plain8
+    T = cfg["T"]
+    Xp_all, _ = prob.transition_probs(T)
+    Wph = prob.rates_ph(T, Xp_all)
+    n, onp = oracle.bose_pair(prob.hw, T)
+    ysum = np.where(prob.mode_on, Wph * n * onp, 0.0).sum() / oracle.SPIN_DEG
+    assert abs(ysum * prob.nq / prob.nk - Xp_all.sum()) < 1e-12 * Xp_all.sum()
+
+
+# ---------------------------------------------------------------------------
+# Eqs. 19-31: the coupled BTEs
+
+def _bordered_solve(prob, T, Xp, Xm, w_ext):
+    """Dense direct solve of the coupled linear system with the carrier-number
+    constraint: (1 - Aee - Aep Ape) I + alpha 1 = I0 + Aep F0, w.I = 0."""
+    M, nbr, nq = prob.nstates, prob.nbr, prob.nq
+    f, omf = oracle.fermi_pair(prob.eps, prob.mu, T)
+    ff = f * omf
+    We = (Xp + Xm).sum((1, 2)) / ff
+    Wphe = prob.rates_ph(T, Xp)
+    Wp = Wphe + w_ext
+    n, onp = oracle.bose_pair(prob.hw, T)
+    on = prob.mode_on
+    qij = prob.q_index(prob.state_k[:, None], prob.state_k[None, :])
+    nqij = prob.neg_q(qij)
+    row = 1.0 / (ff * We)
+    Aee = (Xp + Xm).sum(2) * row[:, None]
+    P = nq * nbr
+    Aep = np.zeros((M, P))
+    for i in range(M):
+        for j in range(M):
+            for s in range(nbr):
+                Aep[i, qij[i, j] * nbr + s] -= Xp[i, j, s] * row[i]
+                Aep[i, nqij[i, j] * nbr + s] += Xm[i, j, s] * row[i]
+    Ape = np.zeros((P, M))
+    pn = np.where(on, oracle.SPIN_DEG * (prob.nk / prob.nq) / (Wp * n * onp), 0.0).reshape(-1)
+    for i in range(M):
+        for j in range(M):
+            for s in range(nbr):
+                p = qij[i, j] * nbr + s
+                Ape[p, j] += pn[p] * Xp[i, j, s]
+                Ape[p, i] -= pn[p] * Xp[i, j, s]
+    v = prob.v_state
+    I0 = ((prob.eps - prob.mu) / T / We)[:, None] * v
+    J0 = (1.0 / We)[:, None] * v
+    inv_wp = np.where(on, 1.0 / Wp, 0.0)
+    F0 = ((prob.hw / T * inv_wp)[..., None] * prob.v_ph).reshape(P, 3)
+    grp = oracle.energy_groups(prob.eps, prob.hw.max(), prob.sigma)
+    C = grp.max() + 1
+    A = np.zeros((M + C, M + C))
+    A[:M, :M] = np.eye(M) - Aee - Aep @ Ape
+    for c in range(C):
+        A[:M, M + c] = (grp == c)
+        A[M + c, :M] = ff * (grp == c)
+    rhsI = np.zeros((M + C, 3))
+    rhsI[:M] = I0 + Aep @ F0
+    rhsJ = np.zeros((M + C, 3))
+    rhsJ[:M] = J0
+    I = np.linalg.solve(A, rhsI)[:M]
+    J = np.linalg.solve(A, rhsJ)[:M]
+    F = F0 + Ape @ I
+    G = Ape @ J
+    return I, J, F.reshape(nq, nbr, 3), G.reshape(nq, nbr, 3)
+
+
+def test_iteration_matches_dense_direct_solve():
+    cfg = synth.config("metal6")
+    mat = synth.material_for(cfg)
+    T = 300.0
+    prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+    Xp, Xm = prob.transition_probs(T)
+    w_ext = oracle.default_w_ext(prob, T, gamma0=1e13)
+    res = oracle.iterate(prob, T, Xp, Xm, oracle.LEVEL_COUPLED, tol=1e-12, maxit=500, w_ext=w_ext)
+    assert res["converged"]
+    I, J, F, G = _bordered_solve(prob, T, Xp, Xm, w_ext)
+    for got, want in ((res["I"], I), (res["J"], J), (res["F"], F), (res["G"], G)):
+        assert np.abs(got - want).max() < 1e-8 * np.abs(want).max()
+    # drag actually couples the systems here
+    assert np.abs(res["G"]).max() > 1e-6 * np.abs(res["F"]).max()
+
+
+def test_rta_level_reproduces_eqs_20_24_and_kelvin_onsager():
+    cfg = synth.config("metal6")
+    mat = synth.material_for(cfg)
+    T = 300.0
+    prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+    Xp, Xm = prob.transition_probs(T)
+    res = oracle.iterate(prob, T, Xp, Xm, oracle.LEVEL_RTA)
+    f, omf = oracle.fermi_pair(prob.eps, prob.mu, T)
+    We = (Xp + Xm).sum((1, 2)) / (f * omf)
+    I0 = ((prob.eps - prob.mu) / T / We)[:, None] * prob.v_state
+    J0 = (1 / We)[:, None] * prob.v_state
+    assert np.abs(res["I"] - I0).max() <= 1e-14 * np.abs(I0).max()
+    assert np.abs(res["J"] - J0).max() <= 1e-14 * np.abs(J0).max()
+    tens = oracle.transport_tensors(prob, T, res["I"], res["J"], res["F"], res["G"])
+    # at RTA the phonon Peltier term vanishes and sigma S = alpha_el / T exactly
+    assert oracle.ko_residual(tens, T) < 1e-12
+    assert np.all(np.linalg.eigvalsh(0.5 * (tens["sigma"] + tens["sigma"].T)) > 0)
