@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the e-ph transition-probability path on one MI355X.
+
+One step = the whole path over the workload: electron and phonon tables
+(Fourier sums, FP64 eigensolves, window), the two vertex contractions with
+the fused |g|^2 / delta / thermal epilogue writing the temperature-independent
+term store, the electron and phonon RTA rates, and the coupled drag iteration
+(unified scheme) with the transport tensors.  Inputs are resident on the
+device before the timed region.
+
+Prints one JSON line (rank 0).  ``value`` is transition probabilities X^{+/-}
+per second of the best precision form whose rates stay within relative 1e-5
+of the FP64 path in the same run.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "e-ph transition probabilities/s at rel err 1e-5 vs FP64; MFMA util"
+PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, dense MFMA
+WORKLOADS = {
+    "mixed48": "8 Wannier bands, 2 atoms, 203 R_e + 203 R_p vectors, 48^3 k and q meshes, "
+               "window +-0.4 eV around mu = CBM - 0.1 eV keeping 3% of k, Gaussian sigma 10 meV, 300 K",
+    "plain8": "4 Wannier bands, 2 atoms, 27 + 27 R vectors, 8^3 meshes, all k, mu = midgap + 0.1 eV, 300 K",
+}
+
+
+def rate_err(w, ref):
+    w, ref = np.asarray(w).ravel(), np.asarray(ref).ravel()
+    mx = np.abs(ref).max()
+    big = np.abs(ref) >= 1e-12 * mx
+    e = (np.abs(w[big] - ref[big]) / np.abs(ref[big])).max() if big.any() else 0.0
+    if (~big).any():
+        e = max(e, (np.abs(w[~big] - ref[~big]) / mx).max())
+    return float(e)
+
+
+def contraction_flops(sz, nre, nrp):
+    """Algorithmic flops of the two complex contractions (8 flops per complex
+    multiply-add, unpadded lengths) and of the phonon projection."""
+    M, nb, nbr = sz["nstates"], sz["nwann"], sz["nbr"]
+    step1 = 8.0 * M * (nre * nb) * (nbr * nrp * nb)
+    step2 = 8.0 * M * M * nbr * (nrp * nb) + 8.0 * M * M * nbr * nbr
+    return step1, step2
+
+
+def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit):
+    dev = torch.device("cuda:0")
+    T = cfg["T"]
+    ctx = E.elph_create(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], precision=form)
+    sz = E.elph_sizes(ctx)
+    M, nbr, nk = sz["nstates"], sz["nbr"], sz["nk"]
+    we = torch.empty(M, dtype=torch.float64, device=dev)
+    wph = torch.empty(nk * nbr, dtype=torch.float64, device=dev)
+    I = torch.empty(3 * M, dtype=torch.float64, device=dev)
+    J = torch.empty_like(I)
+    F = torch.empty(3 * nk * nbr, dtype=torch.float64, device=dev)
+    G = torch.empty_like(F)
+    E.elph_timing(ctx, True)
+    info = {}
+
+    def step():
+        E.elph_reset(ctx)
+        E.elph_sizes(ctx)                       # tables (A1-A3)
+        E.elph_scatt_rates(ctx, T, we, wph)     # vertices, store, rates (A4-A8)
+        if with_iterate:                        # coupled drag iteration (A9)
+            r = E.elph_iterate(ctx, T, I, J, F, G, level=E.elph.ELPH_LEVEL_COUPLED, tol=tol, maxit=maxit,
+                               raise_on_noconv=False)
+            info["iters"] = r["iters"]
+            info["ko_residual"] = r["ko_residual"]
+            info["iter_status"] = r["status"]
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    kt = {"tables": [], "step1": [], "step2": [], "iterate": []}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        ms = E.elph_timing(ctx, True, read=True)
+        for key in kt:
+            if ms[key] >= 0:
+                kt[key].append(ms[key])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    out = dict(sizes=sz, ms_per_step=wall * 1e3, kernel_ms={k: float(np.mean(v)) for k, v in kt.items() if v},
+               we=we.cpu().numpy(), wph=wph.cpu().numpy(), **info)
+    ctx.close()
+    return out
+
+
+def cpu_baseline(mat, cfg, gpu_we, budget_s=20.0):
+    """The oracle on a bounded sample: its tables plus the transition
+    probabilities of a seeded subset of initial states (all final states)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = len(os.sched_getaffinity(0))
+    T = cfg["T"]
+    t0 = time.perf_counter()
+    prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+    t_tab = time.perf_counter() - t0
+    rng = np.random.default_rng(2024)
+    order = rng.permutation(prob.nstates)
+    done, t_rows, errs = 0, 0.0, []
+    while done < order.size and t_rows < budget_s:
+        rows = order[done:done + 4]
+        t1 = time.perf_counter()
+        Xp, Xm = prob.transition_probs(T, rows)
+        w = prob.rates_e(T, Xp, Xm, rows)
+        t_rows += time.perf_counter() - t1
+        errs.append(rate_err(gpu_we[rows], w))
+        done += rows.size
+    x_sample = 2.0 * done * prob.nstates * prob.nbr
+    t_eff = t_rows + t_tab * done / prob.nstates
+    return {
+        "value": x_sample / t_eff, "unit": "transition probabilities/s", "cores": int(cores), "kind": "oracle",
+        "sample": "oracle tables (%.1f s, amortised by rows) + X^{+/-} of %d seeded initial states x all %d "
+                  "final states x %d branches (%.1f s)" % (t_tab, done, prob.nstates, prob.nbr, t_rows),
+        "max_rel_err_W_e_gpu_fp64_vs_oracle_sample": float(max(errs)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mixed48", choices=sorted(WORKLOADS))
+    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--no-iterate", action="store_true")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (the path would shard by kept-k rows across GPUs; "
+              "see the design notes); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2109_08547_amd as E
+
+    cfg = synth.config(args.workload)
+    mat = synth.material_for(cfg)
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    if "fp64" not in forms:
+        forms = ["fp64"] + forms
+    res = {}
+    for form in forms:
+        print("bench: form %s on %s" % (form, args.workload), file=sys.stderr, flush=True)
+        res[form] = run_form(E, torch, mat, cfg, form, args.steps, args.warmup, not args.no_iterate, args.tol,
+                             args.maxit)
+    sz = res["fp64"]["sizes"]
+    nterms = 2.0 * sz["nterms"]
+    s1, s2 = contraction_flops(sz, mat["re"].shape[0], mat["rp"].shape[0])
+    ref_we, ref_wph = res["fp64"]["we"], res["fp64"]["wph"]
+    forms_out = {}
+    best = "fp64"
+    for form, r in res.items():
+        e_we = rate_err(r["we"], ref_we)
+        e_wph = rate_err(r["wph"], ref_wph)
+        forms_out[form] = {
+            "value": nterms / (r["ms_per_step"] * 1e-3), "ms_per_step": r["ms_per_step"],
+            "kernel_ms": r["kernel_ms"], "rel_err_vs_fp64": {"W_e": e_we, "W_ph": e_wph},
+            "step2_tflops": s2 / (r["kernel_ms"]["step2"] * 1e-3) / 1e12,
+            "step1_tflops": s1 / (r["kernel_ms"]["step1"] * 1e-3) / 1e12,
+            "iters": r.get("iters"), "iter_status": r.get("iter_status"), "ko_residual": r.get("ko_residual"),
+        }
+        if form != "fp64" and e_we <= 1e-5 and e_wph <= 1e-5 and \
+                forms_out[form]["value"] > forms_out[best]["value"]:
+            best = form
+    b = forms_out[best]
+    achieved = b["step2_tflops"]
+    line = {
+        "metric": METRIC, "value": b["value"], "unit": "transition probabilities/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32"}[best],
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
+                   "nstates": sz["nstates"], "nkept": sz["nkept"], "terms_per_step": nterms,
+                   "form": best, "iterate": not args.no_iterate},
+        "roofline": {"bound": "mfma", "kernel": "k_step2 (fused step-2 contraction + epilogue)",
+                     "achieved": achieved, "peak": PEAK[best], "unit": "TFLOP/s", "frac": achieved / PEAK[best],
+                     "traffic": None},
+        "forms": forms_out,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(mat, cfg, ref_we, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

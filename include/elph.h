@@ -1,0 +1,212 @@
+/*
+ * elph.h -- C ABI of libelph: the electron-phonon transition-probability path
+ * (Wannier-interpolated e-ph vertices, transition probabilities, RTA
+ * scattering rates and the coupled e-ph drag iteration) on AMD MI355X.
+ *
+ * Physics follows "The elphbolt ab initio solver for the coupled
+ * electron-phonon Boltzmann transport equations": section "Electrons,
+ * phonons, and interactions" (Eqs. 1-3, 5, 6, 8, 12), section "Coupled and
+ * decoupled BTEs" (Eqs. 17-27) and section "Transport coefficients"
+ * (Eqs. 28-31).  Equation numbers count displayed equations in order.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units: energies eV, lengths Angstrom, masses amu, temperatures K, rates
+ * 1/s, velocities m/s.  Complex numbers are interleaved (re, im) doubles.
+ * All arrays are row-major.
+ *
+ * Meshes: the k mesh and the q mesh are the same Gamma-centred
+ * N0 x N1 x N2 mesh, k = (a/N0, b/N1, c/N2), linear index (a*N1 + b)*N2 + c.
+ * q = k' - k is reduced modulo the mesh.
+ *
+ * Active states (the transport window): state (k, m) is active when
+ * |eps_mk - mu| <= window; k is "kept" when any band is active.  Active
+ * states are numbered 0..nstates-1 in increasing mesh index of k, then
+ * increasing band index m (bands ascending in energy).
+ *
+ * Term store: transition probabilities are returned as dense arrays
+ * X[i][j][s] over initial active state i, final active state j and phonon
+ * branch s (0..3*natom-1, ascending in energy at q = k_j - k_i).  Branches
+ * with hbar*omega < omega_min (the acoustic modes at Gamma) carry zeros.
+ *
+ * Pointers: unless stated otherwise, output arrays are DEVICE pointers
+ * allocated by the caller (for example the data pointer of a GPU tensor),
+ * written asynchronously on the context's stream.  Input descriptions
+ * (elph_wannier, elph_params) are host memory, copied at elph_create; the
+ * caller keeps ownership of everything it passes.
+ *
+ * Errors: every call returns an elph_status.  On error, outputs are
+ * unspecified and the context stays usable, except after ELPH_EHIP (a HIP
+ * runtime failure), after which only elph_destroy is allowed.
+ * elph_last_error() returns a message for the last failing call, valid
+ * until the next call on that context.  A context is not thread-safe;
+ * separate contexts are independent.
+ */
+#ifndef ELPH_H
+#define ELPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct elph_ctx_s* elph_ctx;
+typedef int32_t elph_status;
+
+enum {
+  ELPH_OK = 0,
+  ELPH_EINVAL = 1,   /* malformed input or argument */
+  ELPH_ENOMEM = 2,   /* device or host allocation failed */
+  ELPH_EHIP = 3,     /* HIP runtime error; the context is unusable */
+  ELPH_ENOCONV = 4,  /* iteration did not reach the tolerance; results are the last iterate */
+  ELPH_ESTATE = 5    /* call not valid in the context's current state */
+};
+
+/* Arithmetic of the two Wannier contractions (Eq. 6).  Eigensolves and the
+ * thermal/delta factors and all rate accumulations stay FP64 in every form. */
+enum {
+  ELPH_FP64 = 0,     /* FP64 MFMA contractions (plain path) */
+  ELPH_FP32 = 1,     /* FP32 MFMA contractions, FP32 accumulation */
+  ELPH_BF16X3 = 2,   /* BF16 split a = hi + lo, 3 products, FP32 accumulation */
+  ELPH_BF16X6 = 3    /* BF16 split a = hi + mid + lo, 6 products, FP32 accumulation */
+};
+
+/* Solution levels of the coupled BTEs (section "Coupled and decoupled BTEs"). */
+enum {
+  ELPH_LEVEL_RTA = 0,       /* Eqs. 20, 24 only */
+  ELPH_LEVEL_PARTIAL = 1,   /* first phonon iteration of the unified scheme */
+  ELPH_LEVEL_DRAGLESS = 2,  /* self terms only (Eq. 22), no drag */
+  ELPH_LEVEL_COUPLED = 3    /* full dragged solution (Eq. 19) */
+};
+
+/* Wannier-space inputs (section "Electrons, phonons, and interactions" and
+ * the workflow section: Hamiltonian, dynamical matrix and e-ph vertex in the
+ * Wannier basis with their real-space cell lists and weights). */
+typedef struct {
+  int32_t nwann;          /* Wannier bands nb, 1..16 */
+  int32_t natom;          /* atoms per cell; branches nbr = 3*natom, 1..16 */
+  int32_t nre, nrp;       /* number of electron / phonon cell vectors */
+  const int32_t* re;      /* [nre][3] integer cell vectors R_e (lattice units) */
+  const int32_t* rp;      /* [nrp][3] integer cell vectors R_p */
+  const double* wre;      /* [nre] weights of R_e, or NULL for all 1 */
+  const double* wrp;      /* [nrp] weights of R_p, or NULL for all 1 */
+  const double* lat;      /* [3][3] lattice vectors as rows, Angstrom */
+  const double* mass;     /* [natom] amu */
+  const double* h_r;      /* [nre][nb][nb] complex, eV (Eq. 1); H(-R) = H(R)^dagger */
+  const double* d_r;      /* [nrp][nbr][nbr] real, mass-weighted eV/(A^2 amu) (Eq. 3) */
+  const double* g_r;      /* [nre][nrp][nbr][nb][nb] complex, eV/A (Eq. 6);
+                             index order [..][x = 3*atom + cart][final n'][initial m'] */
+} elph_wannier;
+
+typedef struct {
+  int32_t mesh[3];        /* N0, N1, N2 of the common k and q mesh */
+  int32_t precision;      /* ELPH_FP64 / ELPH_FP32 / ELPH_BF16X3 / ELPH_BF16X6 */
+  double mu_eV;           /* chemical potential */
+  double window_eV;       /* half-width of the transport window; INFINITY keeps all */
+  double sigma_eV;        /* standard deviation of the Gaussian delta (Eq. 8) */
+  double omega_min_eV;    /* modes below this are dropped; 0 selects 1e-4 eV */
+} elph_params;
+
+typedef struct {
+  int64_t nk;             /* mesh points (= nq) */
+  int64_t nkept;          /* kept k */
+  int64_t nstates;        /* active states */
+  int32_t nwann, nbr;
+  int64_t nterms;         /* nstates * nstates * nbr: length of one term array */
+  double hw_max_eV;       /* largest phonon energy on the mesh */
+  int32_t ngroups;        /* energy groups of active states (see elph_iterate); 0 until it ran */
+  int32_t reserved;
+} elph_sizes_t;
+
+/* Create a context on a HIP stream (hipStream_t passed as void*, NULL = the
+ * default stream).  Validates the inputs: finite values, nb and nbr in 1..16,
+ * lattice Hermiticity H(-R) = H(R)^dagger, real D(-R) = D(R)^T, and the
+ * acoustic sum rule sum_R D(R) t = 0 on mass-weighted translations t
+ * (relative tolerance 1e-8); violations return ELPH_EINVAL.  Copies all
+ * inputs to the device.  Tables are built lazily by the first call needing
+ * them. */
+elph_status elph_create(const elph_wannier* w, const elph_params* p, void* hip_stream,
+                        elph_ctx* out);
+
+/* Free every device and host resource of the context; NULL is a no-op. */
+void elph_destroy(elph_ctx ctx);
+
+/* Message of the last failing call on ctx ("" if none); ctx may be NULL for
+ * errors of elph_create. */
+const char* elph_last_error(elph_ctx ctx);
+
+/* Drop every derived table, contraction operand and the vertex store; the
+ * next call rebuilds what it needs (inputs stay on the device).  Used to
+ * time the whole path and to release memory. */
+elph_status elph_reset(elph_ctx ctx);
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * the table build, the step-1 contraction, the step-2 contraction (fused with
+ * the rate epilogue) and the whole iteration.  enable = 1 turns recording on
+ * for later calls, 0 turns it off.  ms (host, may be NULL) receives the
+ * durations of the most recent recorded launches in milliseconds:
+ * [tables, step1, step2, iterate] (-1 where nothing was recorded);
+ * synchronises the stream when ms is given. */
+elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms);
+
+/* Build the electron and phonon tables if needed (Eqs. 1-3, 5 and the
+ * window) and report sizes; synchronises the stream. */
+elph_status elph_sizes(elph_ctx ctx, elph_sizes_t* out);
+
+/* Copy tables to caller device buffers (any pointer may be NULL to skip):
+ * state_k [nstates] mesh index, state_m [nstates] band, eps [nstates] eV,
+ * vel [nstates][3] m/s (Eq. 2, averaged over degenerate groups),
+ * hw [nk][nbr] eV and vph [nk][nbr][3] m/s (Eq. 5, zero below omega_min). */
+elph_status elph_tables(elph_ctx ctx, int32_t* state_k, int32_t* state_m, double* eps,
+                        double* vel, double* hw, double* vph);
+
+/* Eq. 6 for arbitrary mesh pairs (k, q), all bands and branches:
+ * kidx, qidx [npairs] device int32 mesh indices; g_out [npairs][nbr][nb][nb]
+ * complex = g^{s n m}_{k q} with n the final band at k+q and m the initial
+ * band at k, eV.  The result depends on the eigenvector gauge; |g|^2 and
+ * sums over degenerate groups do not.  Branches below omega_min give 0. */
+elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
+                          const int32_t* qidx, double* g_out);
+
+/* Eq. 8 over the window at temperature T: Xp, Xm [nterms] FP64 (term-store
+ * layout, absorption + and emission -).  Either may be NULL.  When store_B
+ * is nonzero the temperature-independent terms are also retained in the
+ * context (the "vertex store" reused by elph_scatt_rates and elph_iterate
+ * at any temperature). */
+elph_status elph_transition_probs(elph_ctx ctx, double T_K, double* Xp, double* Xm,
+                                  int32_t store_B);
+
+/* RTA scattering rates at T: W_e [nstates] (Eq. 21, e-ph part) and
+ * W_ph [nk][nbr] (Eq. 25, ph-e part with Y of Eq. 12, spin degeneracy 2),
+ * s^-1.  Either may be NULL.  Reuses the vertex store if present,
+ * otherwise recomputes the vertices (and keeps them). */
+elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, double* W_ph);
+
+/* Coupled e-ph BTEs with the unified single-iterator scheme (Eq. 19,
+ * Eqs. 20-27): each phonon iteration brings the electron equations to
+ * self-consistency (relative tolerance tol/10) with the current phonons.
+ * W_ph_ext [nk][nbr] device: phonon rates from other channels (ph-ph,
+ * isotopes), s^-1, added to the ph-e rate (Eq. 25); NULL selects the model
+ * 1e12 (hw/hw_max)^2 (T/300).  The ph-ph in-scattering term is zero.
+ * Electron responses are constrained to carry no change of carrier number
+ * in each energy group (sorted active energies split at gaps wider than
+ * hw_max + 12 sigma), which removes the conserved modes of the e-ph
+ * collision operator.
+ * Outputs (device): I, J [nstates][3] (I in eV m/K, J in m per unit charge),
+ * F, G [nk][nbr][3].  tensors (host, may be NULL): 6 row-major 3x3 tensors
+ * sigma (S/m), sigma*S (A/(m K)), alpha_el (A/m), kappa0_el (W/(m K)),
+ * alpha_ph (A/m), kappa_ph (W/(m K)) of Eqs. 28-30 with 1/N_k, 1/N_q.
+ * iters (host, may be NULL): phonon iterations used.  ko_residual (host,
+ * may be NULL): |sigma S - (alpha_el + alpha_ph)/T| / |sigma S| (Eq. 31).
+ * Residual = max over I, J, F, G of |x_new - x_old| / |x_new| (2-norms).
+ * Returns ELPH_ENOCONV (with the last iterate) if maxit is reached. */
+elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph_ext, int32_t level,
+                         double tol, int32_t maxit, double* I, double* J, double* F,
+                         double* G, double* tensors, int32_t* iters, double* ko_residual);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELPH_H */

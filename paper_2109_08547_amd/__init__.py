@@ -1,0 +1,10 @@
+"""MI355X-native e-ph transition-probability path (HIP library + binding).
+
+The compute lives in libelph.so (csrc/, C ABI in include/elph.h); the
+``elph`` module is its ctypes binding.
+"""
+from . import elph  # noqa: F401
+from .elph import (  # noqa: F401
+    elph_create, elph_destroy, elph_reset, elph_timing, elph_sizes, elph_tables, elph_interp_g,
+    elph_transition_probs, elph_scatt_rates, elph_iterate, ElphError,
+)

@@ -1,0 +1,469 @@
+// C ABI of libelph (declared in include/elph.h): context lifecycle, input
+// validation and orchestration of the table, vertex, rate and iteration
+// kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "common.h"
+#include "tables.h"
+#include "vertex.h"
+
+using namespace elph;
+
+namespace elph {
+
+hipError_t dev_alloc(elph_ctx ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 1);
+  if (e == hipSuccess) ctx->allocs.push_back(*p);
+  return e;
+}
+
+void dev_free(elph_ctx ctx, void* p) {
+  if (!p) return;
+  auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
+  if (it != ctx->allocs.end()) {
+    ctx->allocs.erase(it);
+    (void)hipFree(p);
+  }
+}
+
+}  // namespace elph
+
+static thread_local std::string g_create_err;
+
+#define CHECK_CTX(ctx)                                          \
+  do {                                                          \
+    if (!(ctx)) return ELPH_EINVAL;                             \
+    if ((ctx)->hip_dead) {                                      \
+      (ctx)->err = "context unusable after a HIP error";        \
+      return ELPH_ESTATE;                                       \
+    }                                                           \
+    (ctx)->err.clear();                                         \
+  } while (0)
+
+#define HIPCHK(x)                                                       \
+  do {                                                                  \
+    hipError_t e_ = (x);                                                \
+    if (e_ != hipSuccess) {                                             \
+      ctx->err = std::string("HIP error ") + hipGetErrorString(e_) +    \
+                 " at " + __FILE__ + ":" + std::to_string(__LINE__);    \
+      ctx->hip_dead = true;                                             \
+      return ELPH_EHIP;                                                 \
+    }                                                                   \
+  } while (0)
+
+static bool all_finite(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static elph_status fail_create(const std::string& msg) {
+  g_create_err = msg;
+  return ELPH_EINVAL;
+}
+
+// Checks of the Wannier inputs: Hermiticity in the lattice sense, real
+// symmetric force constants and the acoustic sum rule.
+static elph_status validate(const elph_wannier* w, const elph_params* p) {
+  if (!w || !p) return fail_create("null input");
+  if (w->nwann < 1 || w->nwann > kMaxBands) return fail_create("nwann must be in 1..16");
+  if (w->natom < 1 || 3 * w->natom > 15) return fail_create("natom must be in 1..5");
+  if (w->nre < 1 || w->nrp < 1) return fail_create("empty cell-vector list");
+  if (!w->re || !w->rp || !w->lat || !w->mass || !w->h_r || !w->d_r || !w->g_r)
+    return fail_create("null array in elph_wannier");
+  for (int d = 0; d < 3; ++d)
+    if (p->mesh[d] < 1 || p->mesh[d] > 4096) return fail_create("mesh sizes must be in 1..4096");
+  if ((int64_t)p->mesh[0] * p->mesh[1] * p->mesh[2] > (int64_t)1 << 31) return fail_create("mesh too large");
+  if (!(p->sigma_eV > 0) || !std::isfinite(p->sigma_eV)) return fail_create("sigma must be positive");
+  if (!(p->window_eV > 0)) return fail_create("window must be positive (INFINITY keeps all)");
+  if (!std::isfinite(p->mu_eV)) return fail_create("mu must be finite");
+  if (p->omega_min_eV < 0 || !std::isfinite(p->omega_min_eV)) return fail_create("omega_min must be >= 0");
+  if (p->precision != ELPH_FP64 && p->precision != ELPH_FP32) return fail_create("precision form not available");
+  const int nb = w->nwann, nbr = 3 * w->natom;
+  const size_t nn = (size_t)nb * nb, mm = (size_t)nbr * nbr;
+  if (!all_finite(w->lat, 9) || !all_finite(w->mass, w->natom)) return fail_create("non-finite lattice or mass");
+  for (int a = 0; a < w->natom; ++a)
+    if (!(w->mass[a] > 0)) return fail_create("masses must be positive");
+  if (!all_finite(w->h_r, 2 * nn * w->nre)) return fail_create("non-finite H(R)");
+  if (!all_finite(w->d_r, mm * w->nrp)) return fail_create("non-finite D(R)");
+  if (!all_finite(w->g_r, 2 * (size_t)w->nre * w->nrp * nbr * nn)) return fail_create("non-finite g(Re, Rp)");
+  if ((w->wre && !all_finite(w->wre, w->nre)) || (w->wrp && !all_finite(w->wrp, w->nrp)))
+    return fail_create("non-finite weights");
+
+  // H(-R) = H(R)^dagger
+  std::map<std::tuple<int, int, int>, int> re, rp;
+  for (int r = 0; r < w->nre; ++r) re[{w->re[3 * r], w->re[3 * r + 1], w->re[3 * r + 2]}] = r;
+  for (int r = 0; r < w->nrp; ++r) rp[{w->rp[3 * r], w->rp[3 * r + 1], w->rp[3 * r + 2]}] = r;
+  double hmax = 0;
+  for (size_t t = 0; t < 2 * nn * w->nre; ++t) hmax = std::max(hmax, std::fabs(w->h_r[t]));
+  for (int r = 0; r < w->nre; ++r) {
+    auto it = re.find({-w->re[3 * r], -w->re[3 * r + 1], -w->re[3 * r + 2]});
+    if (it == re.end()) return fail_create("R_e list is not closed under R -> -R");
+    const int m = it->second;
+    const double wr = w->wre ? w->wre[r] : 1.0, wm = w->wre ? w->wre[m] : 1.0;
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) {
+        const double* x = w->h_r + 2 * ((size_t)r * nn + a * nb + b);
+        const double* y = w->h_r + 2 * ((size_t)m * nn + b * nb + a);
+        if (std::fabs(wr * x[0] - wm * y[0]) > 1e-8 * hmax || std::fabs(wr * x[1] + wm * y[1]) > 1e-8 * hmax)
+          return fail_create("H(R) is not Hermitian: H(-R) != H(R)^dagger");
+      }
+  }
+  // D(-R) = D(R)^T and the acoustic sum rule on mass-weighted translations
+  double dmax = 0;
+  for (size_t t = 0; t < mm * w->nrp; ++t) dmax = std::max(dmax, std::fabs(w->d_r[t]));
+  std::vector<double> dsum(mm, 0.0);
+  for (int r = 0; r < w->nrp; ++r) {
+    auto it = rp.find({-w->rp[3 * r], -w->rp[3 * r + 1], -w->rp[3 * r + 2]});
+    if (it == rp.end()) return fail_create("R_p list is not closed under R -> -R");
+    const int m = it->second;
+    const double wr = w->wrp ? w->wrp[r] : 1.0, wm = w->wrp ? w->wrp[m] : 1.0;
+    for (int a = 0; a < nbr; ++a)
+      for (int b = 0; b < nbr; ++b) {
+        if (std::fabs(wr * w->d_r[(size_t)r * mm + a * nbr + b] - wm * w->d_r[(size_t)m * mm + b * nbr + a]) >
+            1e-8 * dmax)
+          return fail_create("D(R) is not symmetric: D(-R) != D(R)^T");
+        dsum[a * nbr + b] += wr * w->d_r[(size_t)r * mm + a * nbr + b];
+      }
+  }
+  double msum = 0;
+  for (int t = 0; t < w->natom; ++t) msum += w->mass[t];
+  for (int al = 0; al < 3; ++al)
+    for (int a = 0; a < nbr; ++a) {
+      double acc = 0;
+      for (int t = 0; t < w->natom; ++t) acc += dsum[a * nbr + 3 * t + al] * std::sqrt(w->mass[t] / msum);
+      if (std::fabs(acc) > 1e-8 * dmax * std::sqrt((double)w->nrp)) return fail_create("acoustic sum rule violated");
+    }
+  return ELPH_OK;
+}
+
+extern "C" elph_status elph_create(const elph_wannier* w, const elph_params* p, void* hip_stream,
+                                   elph_ctx* out) {
+  if (!out) return fail_create("null output handle");
+  *out = nullptr;
+  elph_status st = validate(w, p);
+  if (st != ELPH_OK) return st;
+  elph_ctx ctx = new (std::nothrow) elph_ctx_s();
+  if (!ctx) {
+    g_create_err = "host allocation failed";
+    return ELPH_ENOMEM;
+  }
+  ctx->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    g_create_err = "no HIP device";
+    return ELPH_EHIP;
+  }
+  ctx->nb = w->nwann;
+  ctx->na = w->natom;
+  ctx->nbr = 3 * w->natom;
+  ctx->nre = w->nre;
+  ctx->nrp = w->nrp;
+  for (int d = 0; d < 3; ++d) ctx->mesh[d] = p->mesh[d];
+  ctx->nk = (int64_t)p->mesh[0] * p->mesh[1] * p->mesh[2];
+  ctx->precision = p->precision;
+  ctx->mu = p->mu_eV;
+  ctx->window = p->window_eV;
+  ctx->sigma = p->sigma_eV;
+  ctx->omega_min = p->omega_min_eV > 0 ? p->omega_min_eV : 1.0e-4;
+  std::memcpy(ctx->lat, w->lat, sizeof(ctx->lat));
+  const double* L = w->lat;
+  ctx->volume_A3 = std::fabs(L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
+                             L[2] * (L[3] * L[7] - L[4] * L[6]));
+  ctx->mass.assign(w->mass, w->mass + w->natom);
+
+  const int nb = ctx->nb, nbr = ctx->nbr;
+  const size_t nn = (size_t)nb * nb, mm = (size_t)nbr * nbr;
+  struct Up {
+    void** dst;
+    const void* src;
+    size_t bytes;
+  };
+  std::vector<double> mass_x(nbr);
+  for (int x = 0; x < nbr; ++x) mass_x[x] = w->mass[x / 3];
+  std::vector<Up> ups = {
+      {(void**)&ctx->d_re, w->re, (size_t)w->nre * 3 * sizeof(int32_t)},
+      {(void**)&ctx->d_rp, w->rp, (size_t)w->nrp * 3 * sizeof(int32_t)},
+      {(void**)&ctx->d_hr, w->h_r, (size_t)w->nre * nn * 2 * sizeof(double)},
+      {(void**)&ctx->d_dr, w->d_r, (size_t)w->nrp * mm * sizeof(double)},
+      {(void**)&ctx->d_gr, w->g_r, (size_t)w->nre * w->nrp * nbr * nn * 2 * sizeof(double)},
+      {(void**)&ctx->d_mass_x, mass_x.data(), nbr * sizeof(double)},
+      {(void**)&ctx->d_lat, w->lat, 9 * sizeof(double)},
+  };
+  if (w->wre) ups.push_back({(void**)&ctx->d_wre, w->wre, (size_t)w->nre * sizeof(double)});
+  if (w->wrp) ups.push_back({(void**)&ctx->d_wrp, w->wrp, (size_t)w->nrp * sizeof(double)});
+  for (auto& u : ups) {
+    if (dev_alloc(ctx, u.dst, u.bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      g_create_err = "device allocation of the inputs failed";
+      elph_destroy(ctx);
+      return ELPH_ENOMEM;
+    }
+    if (hipMemcpy(*u.dst, u.src, u.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      g_create_err = "copy of the inputs to the device failed";
+      elph_destroy(ctx);
+      return ELPH_EHIP;
+    }
+  }
+  st = make_axis_tables(ctx);
+  if (st != ELPH_OK) {
+    g_create_err = ctx->err;
+    elph_destroy(ctx);
+    return st;
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    g_create_err = "stream synchronisation failed";
+    elph_destroy(ctx);
+    return ELPH_EHIP;
+  }
+  g_create_err.clear();
+  *out = ctx;
+  return ELPH_OK;
+}
+
+extern "C" elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms) {
+  CHECK_CTX(ctx);
+  if (enable && !ctx->ev[0]) {
+    for (int e = 0; e < 8; ++e) HIPCHK(hipEventCreate(&ctx->ev[e]));
+  }
+  if (ms) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int t = 0; t < 4; ++t) {
+      ms[t] = -1.0;
+      if (ctx->ev_recorded[t]) {
+        float v = 0.f;
+        HIPCHK(hipEventElapsedTime(&v, ctx->ev[2 * t], ctx->ev[2 * t + 1]));
+        ms[t] = v;
+      }
+    }
+  }
+  ctx->timing = enable != 0;
+  return ELPH_OK;
+}
+
+extern "C" void elph_destroy(elph_ctx ctx) {
+  if (!ctx) return;
+  if (!ctx->hip_dead) (void)hipStreamSynchronize(ctx->stream);
+  for (int e = 0; e < 8; ++e)
+    if (ctx->ev[e]) (void)hipEventDestroy(ctx->ev[e]);
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  ctx->allocs.clear();
+  delete ctx;
+}
+
+extern "C" const char* elph_last_error(elph_ctx ctx) {
+  if (!ctx) return g_create_err.c_str();
+  return ctx->err.c_str();
+}
+
+// Drop every derived table, operand and the vertex store (inputs stay).
+static void drop_derived(elph_ctx ctx) {
+  void** ptrs[] = {(void**)&ctx->d_eps_all, (void**)&ctx->d_kidx,      (void**)&ctx->d_kept,
+                   (void**)&ctx->d_soff,    (void**)&ctx->d_state_k,   (void**)&ctx->d_state_kidx,
+                   (void**)&ctx->d_state_m, (void**)&ctx->d_eps,       (void**)&ctx->d_vel,
+                   (void**)&ctx->d_group,   (void**)&ctx->d_U,         (void**)&ctx->d_hw,
+                   (void**)&ctx->d_Lq,      (void**)&ctx->d_vph,       (void**)&ctx->d_Ee,
+                   (void**)&ctx->d_Ep,      (void**)&ctx->d_Ae,        (void**)&ctx->d_Ap,
+                   (void**)&ctx->d_gR,      (void**)&ctx->d_B2,        (void**)&ctx->d_Bp,
+                   (void**)&ctx->d_Bm,      (void**)&ctx->d_we_part};
+  for (void** p : ptrs) {
+    dev_free(ctx, *p);
+    *p = nullptr;
+  }
+  ctx->we_part_len = 0;
+  ctx->tables_ready = ctx->operands_ready = ctx->store_ready = false;
+  ctx->nkept = ctx->nstates = 0;
+  ctx->ngroups = 0;
+}
+
+extern "C" elph_status elph_reset(elph_ctx ctx) {
+  CHECK_CTX(ctx);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  drop_derived(ctx);
+  return ELPH_OK;
+}
+
+extern "C" elph_status elph_sizes(elph_ctx ctx, elph_sizes_t* out) {
+  CHECK_CTX(ctx);
+  if (!out) {
+    ctx->err = "null output";
+    return ELPH_EINVAL;
+  }
+  elph_status st = build_tables(ctx);
+  if (st != ELPH_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  out->nk = ctx->nk;
+  out->nkept = ctx->nkept;
+  out->nstates = ctx->nstates;
+  out->nwann = ctx->nb;
+  out->nbr = ctx->nbr;
+  out->nterms = ctx->nstates * ctx->nstates * ctx->nbr;
+  out->hw_max_eV = ctx->hw_max;
+  out->ngroups = ctx->ngroups;
+  out->reserved = 0;
+  return ELPH_OK;
+}
+
+extern "C" elph_status elph_tables(elph_ctx ctx, int32_t* state_k, int32_t* state_m, double* eps, double* vel,
+                                   double* hw, double* vph) {
+  CHECK_CTX(ctx);
+  elph_status st = build_tables(ctx);
+  if (st != ELPH_OK) return st;
+  hipStream_t s = ctx->stream;
+  const int64_t M = ctx->nstates, nm = ctx->nk * ctx->nbr;
+  if (state_k) HIPCHK(hipMemcpyAsync(state_k, ctx->d_state_k, M * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  if (state_m) HIPCHK(hipMemcpyAsync(state_m, ctx->d_state_m, M * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  if (eps) HIPCHK(hipMemcpyAsync(eps, ctx->d_eps, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (vel) HIPCHK(hipMemcpyAsync(vel, ctx->d_vel, M * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (hw) HIPCHK(hipMemcpyAsync(hw, ctx->d_hw, nm * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (vph) HIPCHK(hipMemcpyAsync(vph, ctx->d_vph, nm * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return ELPH_OK;
+}
+
+extern "C" elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx,
+                                     double* g_out) {
+  CHECK_CTX(ctx);
+  if (npairs < 0 || (npairs > 0 && (!kidx || !qidx || !g_out))) {
+    ctx->err = "invalid pair list or output";
+    return ELPH_EINVAL;
+  }
+  return interp_g(ctx, npairs, kidx, qidx, g_out);
+}
+
+static elph_status check_T(elph_ctx ctx, double T) {
+  if (!(T > 0) || !std::isfinite(T)) {
+    ctx->err = "temperature must be positive";
+    return ELPH_EINVAL;
+  }
+  return ELPH_OK;
+}
+
+template <typename ST>
+__global__ void k_x_inplace(int64_t M, int nbr, int n0, int n1, int n2, const int32_t* __restrict__ st_k,
+                            const double* __restrict__ f, const double* __restrict__ omf,
+                            const double* __restrict__ nocc, double* __restrict__ Xp, double* __restrict__ Xm) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * M * nbr) return;
+  const int s = (int)(t % nbr);
+  const int64_t ij = t / nbr;
+  const int64_t i = ij / M, j = ij % M;
+  const int64_t kj = st_k[j], ki = st_k[i];
+  int cj = (int)(kj % n2), ci = (int)(ki % n2);
+  int64_t tj = kj / n2, ti = ki / n2;
+  int bj = (int)(tj % n1), bi = (int)(ti % n1);
+  int aj = (int)(tj / n1), ai = (int)(ti / n1);
+  int a = aj - ai; if (a < 0) a += n0;
+  int b = bj - bi; if (b < 0) b += n1;
+  int c = cj - ci; if (c < 0) c += n2;
+  const int64_t q = ((int64_t)a * n1 + b) * n2 + c;
+  const double n = nocc[q * nbr + s];
+  const double occ = f[i] * omf[j];
+  Xp[t] *= occ * n;
+  Xm[t] *= occ * (1.0 + n);
+}
+
+extern "C" elph_status elph_transition_probs(elph_ctx ctx, double T_K, double* Xp, double* Xm, int32_t store_B) {
+  CHECK_CTX(ctx);
+  elph_status st = check_T(ctx, T_K);
+  if (st != ELPH_OK) return st;
+  st = build_tables(ctx);
+  if (st != ELPH_OK) return st;
+  Thermal th;
+  st = make_thermal(ctx, T_K, &th);
+  if (st != ELPH_OK) return st;
+  if (store_B) {
+    st = ensure_store(ctx);
+    if (st == ELPH_OK && (Xp || Xm)) st = x_from_store(ctx, th, Xp, Xm);
+  } else if (Xp || Xm) {
+    const int64_t n = ctx->nstates * ctx->nstates * ctx->nbr;
+    double* a = Xp;
+    double* b = Xm;
+    void* tmp = nullptr;
+    if (!a || !b) {
+      if (dev_alloc(ctx, &tmp, (size_t)n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        free_thermal(ctx, &th);
+        ctx->err = "device allocation failed";
+        return ELPH_ENOMEM;
+      }
+      if (!a) a = (double*)tmp;
+      if (!b) b = (double*)tmp;
+    }
+    st = run_vertex(ctx, a, b, true, nullptr, nullptr, nullptr);
+    if (st == ELPH_OK) {
+      hipLaunchKernelGGL(k_x_inplace<double>, dim3(blocks_for(n, 256)), dim3(256), 0, ctx->stream, ctx->nstates,
+                         ctx->nbr, ctx->mesh[0], ctx->mesh[1], ctx->mesh[2], ctx->d_state_k, th.f, th.omf, th.nocc,
+                         a, b);
+      HIPCHK(hipGetLastError());
+    }
+    if (tmp) {
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      dev_free(ctx, tmp);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  free_thermal(ctx, &th);
+  return st;
+}
+
+extern "C" elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, double* W_ph) {
+  CHECK_CTX(ctx);
+  elph_status st = check_T(ctx, T_K);
+  if (st != ELPH_OK) return st;
+  st = build_tables(ctx);
+  if (st != ELPH_OK) return st;
+  Thermal th;
+  st = make_thermal(ctx, T_K, &th);
+  if (st != ELPH_OK) return st;
+  if (ctx->store_ready) {
+    st = rates_from_store(ctx, th, W_e, W_ph);
+  } else {
+    // vertices, store and the electron rates in one pass; phonon rates by a
+    // q-gather over the fresh store
+    const bool f64 = ctx->precision == ELPH_FP64;
+    const size_t n = (size_t)ctx->nstates * ctx->nstates * ctx->nbr;
+    void* we = nullptr;
+    if ((!ctx->d_Bp && (dev_alloc(ctx, &ctx->d_Bp, n * (f64 ? 8 : 4)) != hipSuccess ||
+                        dev_alloc(ctx, &ctx->d_Bm, n * (f64 ? 8 : 4)) != hipSuccess)) ||
+        dev_alloc(ctx, &we, ctx->nstates * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      free_thermal(ctx, &th);
+      ctx->err = "device allocation of the vertex store failed";
+      return ELPH_ENOMEM;
+    }
+    ctx->store_f32 = !f64;
+    st = run_vertex(ctx, ctx->d_Bp, ctx->d_Bm, f64, &th, W_e ? W_e : (double*)we, nullptr);
+    if (st == ELPH_OK) ctx->store_ready = true;
+    if (st == ELPH_OK && W_ph) st = rates_from_store(ctx, th, nullptr, W_ph);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, we);
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  free_thermal(ctx, &th);
+  return st;
+}
+
+extern "C" elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph_ext, int32_t level, double tol,
+                                    int32_t maxit, double* I, double* J, double* F, double* G, double* tensors,
+                                    int32_t* iters, double* ko_residual) {
+  CHECK_CTX(ctx);
+  elph_status st = check_T(ctx, T_K);
+  if (st != ELPH_OK) return st;
+  if (level < ELPH_LEVEL_RTA || level > ELPH_LEVEL_COUPLED || !(tol > 0) || maxit < 1) {
+    ctx->err = "invalid level, tolerance or maxit";
+    return ELPH_EINVAL;
+  }
+  st = build_tables(ctx);
+  if (st != ELPH_OK) return st;
+  int it = 0;
+  mark(ctx, 6);
+  st = iterate(ctx, T_K, W_ph_ext, level, tol, maxit, I, J, F, G, tensors, &it, ko_residual);
+  mark(ctx, 7);
+  if (iters) *iters = it;
+  return st;
+}

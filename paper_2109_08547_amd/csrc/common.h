@@ -1,0 +1,143 @@
+// Internal declarations of libelph (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/elph.h"
+
+namespace elph {
+
+// CODATA 2018.
+constexpr double kHbarEVs = 6.582119569e-16;     // eV s
+constexpr double kBoltzEVK = 8.617333262e-5;     // eV / K
+constexpr double kCharge = 1.602176634e-19;      // C = J/eV
+constexpr double kAmuKg = 1.66053906660e-27;     // kg
+constexpr double kAngM = 1.0e-10;                // m / Angstrom
+constexpr double kSpinDeg = 2.0;
+constexpr double kPi = 3.14159265358979323846;
+// (hbar omega)^2 [eV^2] = kPhononC [eV] * lambda [eV/(A^2 amu)]
+constexpr double kHbarJs = kHbarEVs * kCharge;
+constexpr double kPhononC = kHbarJs * kHbarJs / (kAmuKg * kAngM * kAngM) / kCharge;
+
+constexpr int kMaxBands = 16;
+
+// ---------------------------------------------------------------- complex
+struct cd {
+  double x, y;
+};
+__host__ __device__ inline cd cmake(double a, double b) { return cd{a, b}; }
+__host__ __device__ inline cd cadd(cd a, cd b) { return cd{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cd csub(cd a, cd b) { return cd{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline cd cmul(cd a, cd b) {
+  return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ inline cd cmulc(cd a, cd b) {  // a * conj(b)
+  return cd{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+__host__ __device__ inline cd cconj(cd a) { return cd{a.x, -a.y}; }
+__host__ __device__ inline cd cscale(cd a, double s) { return cd{a.x * s, a.y * s}; }
+__host__ __device__ inline double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
+
+// ---------------------------------------------------------------- launch helpers
+inline unsigned blocks_for(int64_t n, int threads) {
+  return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace elph
+
+// ---------------------------------------------------------------- context
+struct elph_ctx_s {
+  // status
+  std::string err;
+  bool hip_dead = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // inputs (host copies of scalars)
+  int nb = 0, na = 0, nbr = 0, nre = 0, nrp = 0;
+  int mesh[3] = {0, 0, 0};
+  int64_t nk = 0;
+  int precision = ELPH_FP64;
+  double mu = 0, window = 0, sigma = 0, omega_min = 1e-4;
+  double lat[9];
+  double volume_A3 = 0;
+  std::vector<double> mass;
+
+  // device inputs
+  int32_t* d_re = nullptr;   // [nre][3]
+  int32_t* d_rp = nullptr;   // [nrp][3]
+  double* d_wre = nullptr;   // [nre]
+  double* d_wrp = nullptr;   // [nrp]
+  double* d_hr = nullptr;    // [nre][nb][nb] complex
+  double* d_dr = nullptr;    // [nrp][nbr][nbr]
+  double* d_gr = nullptr;    // [nre][nrp][nbr][nb][nb] complex (as given)
+  double* d_mass_x = nullptr;  // [nbr] mass of the atom of each x
+  double* d_lat = nullptr;   // [9]
+  double2* d_tab[3] = {nullptr, nullptr, nullptr};  // per-axis exp(2 pi i j / N)
+
+  // tables
+  bool tables_ready = false;
+  int64_t nkept = 0, nstates = 0;
+  int ngroups = 0;
+  double hw_max = 0;
+  double* d_eps_all = nullptr;    // [nk][nb]
+  int32_t* d_kidx = nullptr;      // [nk] kept index or -1
+  int32_t* d_kept = nullptr;      // [nkept] mesh index
+  int32_t* d_soff = nullptr;      // [nkept+1] first state of each kept k
+  int32_t* d_state_k = nullptr;   // [nstates] mesh index
+  int32_t* d_state_kidx = nullptr;  // [nstates] kept index
+  int32_t* d_state_m = nullptr;   // [nstates] band
+  double* d_eps = nullptr;        // [nstates]
+  double* d_vel = nullptr;        // [nstates][3]
+  int32_t* d_group = nullptr;     // [nstates] energy group
+  double* d_U = nullptr;          // [nkept][nb][nb] complex, columns = eigenvectors
+  double* d_hw = nullptr;         // [nk][nbr]
+  double* d_Lq = nullptr;         // [nk][nbr(x)][nbr(s)] complex, l_{x,s} u[x][s]
+  double* d_vph = nullptr;        // [nk][nbr][3]
+  double* d_Ee = nullptr;         // [nkept][nre] complex  w_e exp(2 pi i k.Re)
+  double* d_Ep = nullptr;         // [nkept][nrp] complex  exp(2 pi i k.Rp)
+
+  // contraction operands (precision dependent)
+  int64_t m_pad = 0;              // nstates padded
+  int64_t ke = 0, kp = 0;         // padded contraction lengths
+  void* d_Ae = nullptr;           // [m_pad][ke]
+  void* d_Ap = nullptr;           // [m_pad][kp]
+  void* d_gR = nullptr;           // [nbr*nrp*nb][ke]
+  void* d_B2 = nullptr;           // [m_pad*nbr][kp]
+  bool operands_ready = false;
+
+  // vertex store (temperature independent), FP64 or FP32 by precision
+  void* d_Bp = nullptr;
+  void* d_Bm = nullptr;
+  bool store_ready = false;
+  bool store_f32 = false;
+
+  // scratch
+  double* d_we_part = nullptr;    // [n_jtiles][m_pad]
+  int64_t we_part_len = 0;
+
+  // event timing: [0,1] tables, [2,3] step 1, [4,5] step 2, [6,7] iterate
+  bool timing = false;
+  hipEvent_t ev[8] = {};
+  bool ev_recorded[4] = {false, false, false, false};
+
+  std::vector<void*> allocs;      // everything to free
+};
+
+namespace elph {
+
+// Record timing event e (0..7) on the context stream when timing is on.
+inline void mark(elph_ctx ctx, int e) {
+  if (!ctx->timing) return;
+  (void)hipEventRecord(ctx->ev[e], ctx->stream);
+  if (e & 1) ctx->ev_recorded[e >> 1] = true;
+}
+
+// Allocation helper: records the pointer in ctx->allocs.
+hipError_t dev_alloc(elph_ctx ctx, void** p, size_t bytes);
+void dev_free(elph_ctx ctx, void* p);
+
+}  // namespace elph

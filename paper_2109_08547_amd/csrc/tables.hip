@@ -1,0 +1,724 @@
+// Electron and phonon tables on the device:
+//  * per-axis phase tables and Fourier sums H(k), grad H(k), D(q), grad D(q)
+//    (Eqs. 1 and 3 of "The elphbolt ab initio solver ...", short-range part),
+//  * a batched FP64 cyclic Jacobi eigensolver for Hermitian matrices up to
+//    16 x 16 (eigenvalues ascending, eigenvectors as columns),
+//  * the transport window and its compaction into kept k and active states,
+//  * band and branch velocities (Eqs. 2 and 5) and the phonon factors of
+//    Eq. 6 (l_{x,s} u_q[x,s], with l = sqrt(C / (2 M hbar omega))).
+#include "tables.h"
+
+#include <utility>
+
+namespace elph {
+
+// ---------------------------------------------------------------------------
+// phases
+
+__global__ void k_axis_table(int n, double2* tab) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s, c;
+  sincospi(2.0 * (double)j / (double)n, &s, &c);
+  tab[j] = make_double2(c, s);
+}
+
+struct MeshPhase {
+  const double2* t0;
+  const double2* t1;
+  const double2* t2;
+  int n0, n1, n2;
+  // exp(2 pi i k . R) for k = (a/n0, b/n1, c/n2) and integer R
+  __device__ inline cd operator()(int a, int b, int c, int r0, int r1, int r2) const {
+    int i0 = (int)(((int64_t)a * r0) % n0); if (i0 < 0) i0 += n0;
+    int i1 = (int)(((int64_t)b * r1) % n1); if (i1 < 0) i1 += n1;
+    int i2 = (int)(((int64_t)c * r2) % n2); if (i2 < 0) i2 += n2;
+    double2 p0 = t0[i0], p1 = t1[i1], p2 = t2[i2];
+    cd z = cmul(cmake(p0.x, p0.y), cmake(p1.x, p1.y));
+    return cmul(z, cmake(p2.x, p2.y));
+  }
+};
+
+static MeshPhase mesh_phase(elph_ctx c) {
+  return MeshPhase{c->d_tab[0], c->d_tab[1], c->d_tab[2], c->mesh[0], c->mesh[1], c->mesh[2]};
+}
+
+__device__ inline void mesh_coords(int64_t lin, int n1, int n2, int& a, int& b, int& c) {
+  c = (int)(lin % n2);
+  int64_t t = lin / n2;
+  b = (int)(t % n1);
+  a = (int)(t / n1);
+}
+
+// Fourier sum over R for a list of mesh points: out[p][a][b] = sum_R w_R e^{ik.R} M(R)[a][b]
+// and optionally grad[p][c][a][b] = sum_R i R_cart[c] w_R e^{ik.R} M(R)[a][b].
+// One block handles KPB points; the phases of its points are staged in LDS.
+template <bool REAL_IN, bool GRAD>
+__global__ void k_fourier(MeshPhase ph, const int32_t* __restrict__ pts, int64_t base, int64_t npts,
+                          const int32_t* __restrict__ R, const double* __restrict__ w, int nR,
+                          const double* __restrict__ lat, const double* __restrict__ Min, int n,
+                          int kpb, cd* __restrict__ out, cd* __restrict__ grad) {
+  extern __shared__ cd sph[];  // [kpb][nR]
+  const int nn = n * n;
+  const int64_t p0 = (int64_t)blockIdx.x * kpb;
+  for (int t = threadIdx.x; t < kpb * nR; t += blockDim.x) {
+    int lp = t / nR, r = t % nR;
+    int64_t p = p0 + lp;
+    cd z = cmake(0, 0);
+    if (p < npts) {
+      int a, b, c;
+      mesh_coords(pts ? (int64_t)pts[p] : base + p, ph.n1, ph.n2, a, b, c);
+      z = cscale(ph(a, b, c, R[3 * r], R[3 * r + 1], R[3 * r + 2]), w ? w[r] : 1.0);
+    }
+    sph[t] = z;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kpb * nn; e += blockDim.x) {
+    int lp = e / nn, ab = e % nn;
+    int64_t p = p0 + lp;
+    if (p >= npts) continue;
+    cd acc = cmake(0, 0);
+    cd g0 = cmake(0, 0), g1 = cmake(0, 0), g2 = cmake(0, 0);
+    for (int r = 0; r < nR; ++r) {
+      cd z = sph[lp * nR + r];
+      cd m;
+      if (REAL_IN) m = cmake(Min[(int64_t)r * nn + ab], 0.0);
+      else m = cmake(Min[2 * ((int64_t)r * nn + ab)], Min[2 * ((int64_t)r * nn + ab) + 1]);
+      cd zm = cmul(z, m);
+      acc = cadd(acc, zm);
+      if (GRAD) {
+        double r0 = R[3 * r], r1 = R[3 * r + 1], r2 = R[3 * r + 2];
+        cd izm = cmake(-zm.y, zm.x);
+        g0 = cadd(g0, cscale(izm, r0 * lat[0] + r1 * lat[3] + r2 * lat[6]));
+        g1 = cadd(g1, cscale(izm, r0 * lat[1] + r1 * lat[4] + r2 * lat[7]));
+        g2 = cadd(g2, cscale(izm, r0 * lat[2] + r1 * lat[5] + r2 * lat[8]));
+      }
+    }
+    out[p * nn + ab] = acc;
+    if (GRAD) {
+      grad[(p * 3 + 0) * nn + ab] = g0;
+      grad[(p * 3 + 1) * nn + ab] = g1;
+      grad[(p * 3 + 2) * nn + ab] = g2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched cyclic Jacobi for Hermitian n x n (n <= P <= 16).
+//
+// A group of P lanes owns one matrix: lane j holds column j of A and of the
+// accumulated rotation V in registers.  Each sweep runs the P-1 rounds of a
+// round-robin tournament; in a round the P/2 disjoint pairs (p, q) rotate in
+// parallel with the unitary J = [[c, s e^{i phi}], [-s e^{-i phi}, c]] that
+// zeroes A[p][q] (phi = arg A[p][q], t = tan(theta) from the classical
+// symmetric Jacobi formula): columns with the partner lane's column, rows
+// with the pair parameters broadcast from the owning lanes.  Padded
+// rows/columns carry a large diagonal and zero coupling, so they never
+// rotate and sort last.
+
+__host__ __device__ constexpr int rr_partner(int i, int rho, int P) {
+  // round-robin (circle method) schedule over P players, rounds 0..P-2
+  return (i == P - 1) ? ((rho * (P / 2)) % (P - 1))
+                      : ((((rho - i) % (P - 1) + (P - 1)) % (P - 1)) == i
+                             ? P - 1
+                             : (((rho - i) % (P - 1) + (P - 1)) % (P - 1)));
+}
+
+__device__ inline double shfl_d(double v, int src) { return __shfl(v, src, 64); }
+__device__ inline cd shfl_c(cd v, int src) { return cmake(__shfl(v.x, src, 64), __shfl(v.y, src, 64)); }
+
+// Wave-private LDS: column storage col[lane][r] (row stride P+1 against bank
+// conflicts) and the rotation parameters of each lane.
+template <int P>
+struct JacobiLds {
+  cd col[64][P + 1];
+  double c[64];
+  cd se[64];
+};
+
+template <int P, int RHO, int p>
+__device__ __forceinline__ void jacobi_row_pair(cd (&a)[P], const JacobiLds<P>& L, int base) {
+  constexpr int q = rr_partner(p, RHO, P);
+  if constexpr (p < q) {
+    const double cp = L.c[base + p];
+    const cd sp = L.se[base + p];
+    const cd ap = a[p], aq = a[q];
+    a[p] = csub(cscale(ap, cp), cmul(sp, aq));
+    a[q] = cadd(cmul(cconj(sp), ap), cscale(aq, cp));
+  }
+}
+
+template <int P, int RHO, int... PS>
+__device__ __forceinline__ void jacobi_rows(cd (&a)[P], const JacobiLds<P>& L, int base,
+                                            std::integer_sequence<int, PS...>) {
+  (jacobi_row_pair<P, RHO, PS>(a, L, base), ...);
+}
+
+// One round RHO of the tournament.  Register arrays are indexed statically;
+// the lane-dependent reads (own diagonal, partner column) go through LDS.
+template <int P, bool VECS, int RHO>
+__device__ __forceinline__ void jacobi_round(cd (&a)[P], cd (&v)[P], int j, int lane, int base,
+                                             JacobiLds<P>& L) {
+  const int pj = rr_partner(j, RHO, P);
+  const bool isp = j < pj;
+#pragma unroll
+  for (int r = 0; r < P; ++r) L.col[lane][r] = a[r];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const cd ajj = L.col[lane][j];
+  const cd ajp = L.col[lane][pj];
+  const double dpart = L.col[base + pj][pj].x;
+  const cd opart = L.col[base + pj][j];
+  const double app = isp ? ajj.x : dpart;
+  const double aqq = isp ? dpart : ajj.x;
+  const cd apq = isp ? opart : ajp;  // A[p][q] lives in column q
+  double c = 1.0;
+  cd se = cmake(0, 0);
+  const double habs = sqrt(cabs2(apq));
+  if (habs > 1.0e-300) {
+    const double tau = (aqq - app) / (2.0 * habs);
+    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    c = 1.0 / sqrt(1.0 + t * t);
+    const double s = t * c;
+    se = cscale(apq, s / habs);  // s e^{i phi}
+  }
+  // columns: A <- A J, V <- V J
+  const cd wgt = isp ? cmake(-se.x, se.y) /* -conj(se) */ : se;
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    const cd pa = L.col[base + pj][r];
+    a[r] = cadd(cscale(a[r], c), cmul(wgt, pa));
+    if (VECS) {
+      const cd pv = shfl_c(v[r], base + pj);
+      v[r] = cadd(cscale(v[r], c), cmul(wgt, pv));
+    }
+  }
+  L.c[lane] = c;
+  L.se[lane] = se;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  // rows: A <- J^H A, pair parameters from the lane owning row p
+  jacobi_rows<P, RHO>(a, L, base, std::make_integer_sequence<int, P>{});
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+template <int P, bool VECS, int... RHO>
+__device__ __forceinline__ void jacobi_sweep(cd (&a)[P], cd (&v)[P], int j, int lane, int base,
+                                             JacobiLds<P>& L, std::integer_sequence<int, RHO...>) {
+  (jacobi_round<P, VECS, RHO>(a, v, j, lane, base, L), ...);
+}
+
+template <int P, bool VECS, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_jacobi(const cd* __restrict__ Ain, int64_t nmat, int n,
+                                                       double* __restrict__ evals, cd* __restrict__ evecs,
+                                                       int max_sweeps) {
+  __shared__ JacobiLds<P> lds[WAVES];
+  JacobiLds<P>& L = lds[threadIdx.x / 64];
+  const int lane = threadIdx.x & 63;
+  const int j = lane % P;
+  const int base = lane - j;
+  const int64_t mat = ((int64_t)blockIdx.x * WAVES + threadIdx.x / 64) * (64 / P) + lane / P;
+  const bool valid = mat < nmat;
+  const int64_t nn = (int64_t)n * n;
+
+  cd a[P], v[P];
+  double frob = 0.0;
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    cd x = cmake(0, 0);
+    if (valid && r < n && j < n) x = Ain[mat * nn + (int64_t)r * n + j];
+    frob += cabs2(x);
+    a[r] = x;
+    v[r] = cmake(r == j ? 1.0 : 0.0, 0.0);
+  }
+  // padded (or absent) columns: distinct large diagonal, no coupling
+  if (!(valid && j < n)) {
+#pragma unroll
+    for (int r = 0; r < P; ++r)
+      if (r == j) a[r] = cmake(1.0e200 * (1.0 + j), 0.0);
+  }
+  // Frobenius norm^2 of the group's matrix
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) frob += __shfl_xor(frob, o, 64);
+  const double tol2 = 1.0e-30 * frob;
+
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    jacobi_sweep<P, VECS>(a, v, j, lane, base, L, std::make_integer_sequence<int, P - 1>{});
+    // convergence: off-diagonal norm of the whole group
+    double off = 0.0;
+#pragma unroll
+    for (int r = 0; r < P; ++r)
+      if (r != j) off += cabs2(a[r]);
+#pragma unroll
+    for (int o = 1; o < P; o <<= 1) off += __shfl_xor(off, o, 64);
+    const bool done = !(off > tol2);
+    if (__all(done)) break;
+  }
+
+  // sort ascending
+#pragma unroll
+  for (int r = 0; r < P; ++r) L.col[lane][r] = a[r];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const double dj = L.col[lane][j].x;
+  int rank = 0;
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    const double dr = shfl_d(dj, base + r);
+    rank += (dr < dj || (dr == dj && r < j)) ? 1 : 0;
+  }
+  if (valid && j < n && rank < n) {
+    if (evals) evals[mat * n + rank] = dj;
+    if (VECS) {
+#pragma unroll
+      for (int r = 0; r < P; ++r)
+        if (r < n) evecs[mat * nn + (int64_t)r * n + rank] = v[r];
+    }
+  }
+}
+
+template <bool VECS>
+static void launch_jacobi_t(const cd* A, int64_t nmat, int n, double* ev, cd* U, hipStream_t s) {
+  if (n <= 4) {
+    constexpr int W = 4;
+    hipLaunchKernelGGL((k_jacobi<4, VECS, W>), dim3(blocks_for(nmat, W * 16)), dim3(64 * W), 0, s, A, nmat, n, ev,
+                       U, 12);
+  } else if (n <= 8) {
+    constexpr int W = 4;
+    hipLaunchKernelGGL((k_jacobi<8, VECS, W>), dim3(blocks_for(nmat, W * 8)), dim3(64 * W), 0, s, A, nmat, n, ev,
+                       U, 12);
+  } else {
+    constexpr int W = 2;
+    hipLaunchKernelGGL((k_jacobi<16, VECS, W>), dim3(blocks_for(nmat, W * 4)), dim3(64 * W), 0, s, A, nmat, n,
+                       ev, U, 14);
+  }
+}
+
+void launch_jacobi(const cd* A, int64_t nmat, int n, double* evals, cd* evecs, hipStream_t s) {
+  if (nmat <= 0) return;
+  if (evecs) launch_jacobi_t<true>(A, nmat, n, evals, evecs, s);
+  else launch_jacobi_t<false>(A, nmat, n, evals, nullptr, s);
+}
+
+// ---------------------------------------------------------------------------
+// window and compaction
+
+__global__ void k_window(const double* __restrict__ eps, int64_t nk, int nb, double mu, double window,
+                         int32_t* __restrict__ nact, int32_t* __restrict__ kept_flag) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nk) return;
+  int c = 0;
+  for (int m = 0; m < nb; ++m) c += (fabs(eps[k * nb + m] - mu) <= window) ? 1 : 0;
+  nact[k] = c;
+  kept_flag[k] = c > 0 ? 1 : 0;
+}
+
+// exclusive scan, three phases; block size 1024
+__global__ void k_scan_block(const int32_t* __restrict__ in, int64_t n, int32_t* __restrict__ out,
+                             int32_t* __restrict__ block_sums) {
+  __shared__ int32_t s[1024];
+  int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  int32_t x = i < n ? in[i] : 0;
+  s[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int32_t t = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) out[i] = s[threadIdx.x] - x;
+  if (threadIdx.x == 1023) block_sums[blockIdx.x] = s[1023];
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ block_pref) {
+  int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  if (i < n) out[i] += block_pref[blockIdx.x];
+}
+
+// exclusive scan of in[0..n) into out[0..n); total written to out_total (device, 1 int)
+void scan_exclusive(elph_ctx ctx, const int32_t* in, int64_t n, int32_t* out, int32_t* out_total,
+                    int32_t* scratch, hipStream_t s) {
+  int64_t nblk = (n + 1023) / 1024;
+  if (nblk == 0) {
+    hipMemsetAsync(out_total, 0, sizeof(int32_t), s);
+    return;
+  }
+  int32_t* bsum = scratch;          // [nblk]
+  int32_t* bpref = scratch + nblk;  // [nblk]
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nblk), dim3(1024), 0, s, in, n, out, bsum);
+  if (nblk == 1) {
+    hipMemsetAsync(bpref, 0, sizeof(int32_t), s);
+    hipMemcpyAsync(out_total, bsum, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    return;
+  }
+  int32_t* tot2 = scratch + 2 * nblk;
+  scan_exclusive(ctx, bsum, nblk, bpref, tot2, scratch + 2 * nblk + 1, s);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nblk), dim3(1024), 0, s, out, n, bpref);
+  hipMemcpyAsync(out_total, tot2, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+}
+
+__global__ void k_compact_kept(const int32_t* __restrict__ flag, const int32_t* __restrict__ pos, int64_t nk,
+                               int32_t* __restrict__ kidx, int32_t* __restrict__ kept,
+                               const int32_t* __restrict__ nact_mesh, int32_t* __restrict__ nact_kept) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nk) return;
+  if (flag[k]) {
+    kidx[k] = pos[k];
+    kept[pos[k]] = (int32_t)k;
+    nact_kept[pos[k]] = nact_mesh[k];
+  } else {
+    kidx[k] = -1;
+  }
+}
+
+__global__ void k_fill_states(const int32_t* __restrict__ kept, int64_t nkept, const int32_t* __restrict__ soff,
+                              const double* __restrict__ eps_all, int nb, double mu, double window,
+                              int32_t* __restrict__ st_k, int32_t* __restrict__ st_kidx,
+                              int32_t* __restrict__ st_m, double* __restrict__ st_eps) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nkept) return;
+  int32_t km = kept[t];
+  int32_t o = soff[t];
+  for (int m = 0; m < nb; ++m) {
+    double e = eps_all[(int64_t)km * nb + m];
+    if (fabs(e - mu) <= window) {
+      st_k[o] = km;
+      st_kidx[o] = (int32_t)t;
+      st_m[o] = m;
+      st_eps[o] = e;
+      ++o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// velocities
+
+// Electron: v[m] = Re(U[:,m]^H dH_c U[:,m]) (A eV -> m/s), averaged over
+// degenerate groups of eps, written for active states of each kept k.
+__global__ void k_electron_vel(int64_t nkept, int nb, const cd* __restrict__ U, const cd* __restrict__ dH,
+                               const double* __restrict__ eps_all, const int32_t* __restrict__ kept,
+                               const int32_t* __restrict__ soff, double mu, double window, double degen,
+                               double* __restrict__ vel) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nkept) return;
+  const int64_t nn = (int64_t)nb * nb;
+  const cd* u = U + t * nn;
+  double vd[kMaxBands][3];
+  const double conv = kAngM / kHbarEVs;
+  for (int m = 0; m < nb; ++m) {
+    for (int c = 0; c < 3; ++c) {
+      const cd* h = dH + (t * 3 + c) * nn;
+      double acc = 0.0;
+      for (int a = 0; a < nb; ++a) {
+        cd row = cmake(0, 0);
+        for (int b = 0; b < nb; ++b) row = cadd(row, cmul(h[a * nb + b], u[b * nb + m]));
+        acc += cmul(cconj(u[a * nb + m]), row).x;
+      }
+      vd[m][c] = acc * conv;
+    }
+  }
+  const double* e = eps_all + (int64_t)kept[t] * nb;
+  int start = 0;
+  for (int b = 1; b <= nb; ++b) {
+    if (b == nb || e[b] - e[b - 1] >= degen) {
+      if (b - start > 1) {
+        for (int c = 0; c < 3; ++c) {
+          double s = 0;
+          for (int m = start; m < b; ++m) s += vd[m][c];
+          s /= (double)(b - start);
+          for (int m = start; m < b; ++m) vd[m][c] = s;
+        }
+      }
+      start = b;
+    }
+  }
+  int o = soff[t];
+  for (int m = 0; m < nb; ++m) {
+    if (fabs(e[m] - mu) <= window) {
+      for (int c = 0; c < 3; ++c) vel[(int64_t)o * 3 + c] = vd[m][c];
+      ++o;
+    }
+  }
+}
+
+// Phonons: hbar omega, l*u table, velocities (Eq. 5) for a chunk of q.
+__global__ void k_phonon_derived(int64_t nq, int nbr, const double* __restrict__ lam, const cd* __restrict__ u,
+                                 const cd* __restrict__ dD, const double* __restrict__ mass_x, double omega_min,
+                                 double degen, double* __restrict__ hw, cd* __restrict__ Lq,
+                                 double* __restrict__ vph) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t nn = (int64_t)nbr * nbr;
+  double w[kMaxBands];
+  double vd[kMaxBands][3];
+  const double conv = kAngM / kHbarEVs;
+  for (int s = 0; s < nbr; ++s) {
+    double l = lam[q * nbr + s];
+    w[s] = sqrt(kPhononC * (l > 0.0 ? l : 0.0));
+    hw[q * nbr + s] = w[s];
+  }
+  for (int s = 0; s < nbr; ++s) {
+    const bool on = w[s] >= omega_min;
+    for (int x = 0; x < nbr; ++x) {
+      cd val = cmake(0, 0);
+      if (on) val = cscale(u[q * nn + x * nbr + s], sqrt(kPhononC / (2.0 * mass_x[x] * w[s])));
+      Lq[q * nn + x * nbr + s] = val;
+    }
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+      if (on) {
+        const cd* d = dD + (q * 3 + c) * nn;
+        for (int a = 0; a < nbr; ++a) {
+          cd row = cmake(0, 0);
+          for (int b = 0; b < nbr; ++b) row = cadd(row, cmul(d[a * nbr + b], u[q * nn + b * nbr + s]));
+          acc += cmul(cconj(u[q * nn + a * nbr + s]), row).x;
+        }
+        acc = kPhononC * acc / (2.0 * w[s]) * conv;
+      }
+      vd[s][c] = acc;
+    }
+  }
+  int start = 0;
+  for (int b = 1; b <= nbr; ++b) {
+    if (b == nbr || w[b] - w[b - 1] >= degen) {
+      if (b - start > 1) {
+        for (int c = 0; c < 3; ++c) {
+          double s = 0;
+          for (int m = start; m < b; ++m) s += vd[m][c];
+          s /= (double)(b - start);
+          for (int m = start; m < b; ++m) vd[m][c] = s;
+        }
+      }
+      start = b;
+    }
+  }
+  for (int s = 0; s < nbr; ++s)
+    for (int c = 0; c < 3; ++c) vph[(q * nbr + s) * 3 + c] = vd[s][c];
+}
+
+// phase tables of kept k: Ee[t][r] = w_r e^{2 pi i k.Re_r}, Ep[t][r] = e^{2 pi i k.Rp_r}
+__global__ void k_kept_phases(MeshPhase ph, const int32_t* __restrict__ kept, int64_t nkept,
+                              const int32_t* __restrict__ R, const double* __restrict__ w, int nR,
+                              cd* __restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nkept * nR) return;
+  int64_t t = e / nR;
+  int r = (int)(e % nR);
+  int a, b, c;
+  mesh_coords(kept[t], ph.n1, ph.n2, a, b, c);
+  cd z = ph(a, b, c, R[3 * r], R[3 * r + 1], R[3 * r + 2]);
+  out[e] = cscale(z, w ? w[r] : 1.0);
+}
+
+__global__ void k_max_reduce(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
+  __shared__ double s[256];
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, x[i]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// host drivers
+
+#define HIPCHK(x)                                                       \
+  do {                                                                  \
+    hipError_t e_ = (x);                                                \
+    if (e_ != hipSuccess) {                                             \
+      ctx->err = std::string("HIP error ") + hipGetErrorString(e_) +    \
+                 " at " + __FILE__ + ":" + std::to_string(__LINE__);    \
+      ctx->hip_dead = true;                                             \
+      return ELPH_EHIP;                                                 \
+    }                                                                   \
+  } while (0)
+
+#define ALLOC(ptr, bytes)                                                          \
+  do {                                                                             \
+    void* p_ = nullptr;                                                            \
+    hipError_t e_ = dev_alloc(ctx, &p_, (size_t)(bytes));                          \
+    if (e_ != hipSuccess) {                                                        \
+      ctx->err = "device allocation of " + std::to_string((size_t)(bytes)) + " bytes failed"; \
+      (void)hipGetLastError();                                                     \
+      return ELPH_ENOMEM;                                                          \
+    }                                                                              \
+    ptr = (decltype(ptr))p_;                                                       \
+  } while (0)
+
+static int fourier_kpb(int n, int nR) {
+  int kpb = 256 / (n * n);
+  if (kpb < 1) kpb = 1;
+  int lds_cap = (48 * 1024) / (nR * (int)sizeof(cd));
+  if (lds_cap < 1) lds_cap = 1;
+  return kpb < lds_cap ? kpb : lds_cap;
+}
+
+template <bool REAL_IN, bool GRAD>
+static void launch_fourier(elph_ctx ctx, const int32_t* pts, int64_t base, int64_t npts, const int32_t* R,
+                           const double* w, int nR, const double* Min, int n, cd* out, cd* grad) {
+  int kpb = fourier_kpb(n, nR);
+  size_t lds = (size_t)kpb * nR * sizeof(cd);
+  hipLaunchKernelGGL((k_fourier<REAL_IN, GRAD>), dim3(blocks_for(npts, kpb)), dim3(256), lds, ctx->stream,
+                     mesh_phase(ctx), pts, base, npts, R, w, nR, ctx->d_lat, Min, n, kpb, out, grad);
+}
+
+elph_status build_tables(elph_ctx ctx) {
+  if (ctx->tables_ready) return ELPH_OK;
+  mark(ctx, 0);
+  hipStream_t s = ctx->stream;
+  const int nb = ctx->nb, nbr = ctx->nbr;
+  const int64_t nk = ctx->nk;
+  const int64_t chunk = 1 << 16;
+
+  // ---- electrons on the whole mesh: eigenvalues decide the window (Eq. 1)
+  ALLOC(ctx->d_eps_all, nk * nb * sizeof(double));
+  cd* hbuf = nullptr;
+  const int nmaxb = nb > nbr ? nb : nbr;
+  ALLOC(hbuf, chunk * (int64_t)nmaxb * nmaxb * sizeof(cd));
+  cd* gbuf = nullptr;
+  ALLOC(gbuf, chunk * 3 * (int64_t)nmaxb * nmaxb * sizeof(cd));
+  for (int64_t k0 = 0; k0 < nk; k0 += chunk) {
+    int64_t cnt = (nk - k0 < chunk) ? nk - k0 : chunk;
+    launch_fourier<false, false>(ctx, nullptr, k0, cnt, ctx->d_re, ctx->d_wre, ctx->nre, ctx->d_hr, nb, hbuf,
+                                 nullptr);
+    launch_jacobi(hbuf, cnt, nb, ctx->d_eps_all + k0 * nb, nullptr, s);
+  }
+  HIPCHK(hipGetLastError());
+
+  // ---- window and compaction
+  int32_t *nact_mesh = nullptr, *flag = nullptr, *pos = nullptr, *scr = nullptr, *tot = nullptr;
+  ALLOC(nact_mesh, nk * sizeof(int32_t));
+  ALLOC(flag, nk * sizeof(int32_t));
+  ALLOC(pos, nk * sizeof(int32_t));
+  ALLOC(scr, (4 * ((nk + 1023) / 1024) + 64) * sizeof(int32_t));
+  ALLOC(tot, 2 * sizeof(int32_t));
+  hipLaunchKernelGGL(k_window, dim3(blocks_for(nk, 256)), dim3(256), 0, s, ctx->d_eps_all, nk, nb, ctx->mu,
+                     ctx->window, nact_mesh, flag);
+  scan_exclusive(ctx, flag, nk, pos, tot, scr, s);
+  int32_t h_nkept = 0;
+  HIPCHK(hipMemcpyAsync(&h_nkept, tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->nkept = h_nkept;
+  if (ctx->nkept == 0) {
+    ctx->err = "no electron state inside the transport window";
+    return ELPH_EINVAL;
+  }
+  ALLOC(ctx->d_kidx, nk * sizeof(int32_t));
+  ALLOC(ctx->d_kept, ctx->nkept * sizeof(int32_t));
+  int32_t* nact_kept = nullptr;
+  ALLOC(nact_kept, (ctx->nkept + 1) * sizeof(int32_t));
+  ALLOC(ctx->d_soff, (ctx->nkept + 1) * sizeof(int32_t));
+  hipLaunchKernelGGL(k_compact_kept, dim3(blocks_for(nk, 256)), dim3(256), 0, s, flag, pos, nk, ctx->d_kidx,
+                     ctx->d_kept, nact_mesh, nact_kept);
+  scan_exclusive(ctx, nact_kept, ctx->nkept, ctx->d_soff, tot + 1, scr, s);
+  HIPCHK(hipMemcpyAsync(ctx->d_soff + ctx->nkept, tot + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  int32_t h_ns = 0;
+  HIPCHK(hipMemcpyAsync(&h_ns, tot + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->nstates = h_ns;
+  const int64_t M = ctx->nstates;
+  ALLOC(ctx->d_state_k, M * sizeof(int32_t));
+  ALLOC(ctx->d_state_kidx, M * sizeof(int32_t));
+  ALLOC(ctx->d_state_m, M * sizeof(int32_t));
+  ALLOC(ctx->d_eps, M * sizeof(double));
+  ALLOC(ctx->d_vel, M * 3 * sizeof(double));
+  hipLaunchKernelGGL(k_fill_states, dim3(blocks_for(ctx->nkept, 256)), dim3(256), 0, s, ctx->d_kept, ctx->nkept,
+                     ctx->d_soff, ctx->d_eps_all, nb, ctx->mu, ctx->window, ctx->d_state_k, ctx->d_state_kidx,
+                     ctx->d_state_m, ctx->d_eps);
+
+  // ---- eigenvectors and velocities of kept k (Eqs. 1, 2)
+  ALLOC(ctx->d_U, ctx->nkept * (int64_t)nb * nb * sizeof(cd));
+  for (int64_t k0 = 0; k0 < ctx->nkept; k0 += chunk) {
+    int64_t cnt = (ctx->nkept - k0 < chunk) ? ctx->nkept - k0 : chunk;
+    launch_fourier<false, true>(ctx, ctx->d_kept + k0, 0, cnt, ctx->d_re, ctx->d_wre, ctx->nre, ctx->d_hr, nb, hbuf,
+                                gbuf);
+    launch_jacobi(hbuf, cnt, nb, nullptr, (cd*)ctx->d_U + k0 * nb * nb, s);
+    hipLaunchKernelGGL(k_electron_vel, dim3(blocks_for(cnt, 64)), dim3(64), 0, s, cnt, nb,
+                       (const cd*)ctx->d_U + k0 * nb * nb, gbuf, ctx->d_eps_all, ctx->d_kept + k0,
+                       ctx->d_soff + k0, ctx->mu, ctx->window, 1.0e-6, ctx->d_vel);
+  }
+  HIPCHK(hipGetLastError());
+
+  // ---- phonons on the whole q mesh (Eqs. 3, 5, 6 prefactor)
+  ALLOC(ctx->d_hw, nk * nbr * sizeof(double));
+  ALLOC(ctx->d_Lq, nk * (int64_t)nbr * nbr * sizeof(cd));
+  ALLOC(ctx->d_vph, nk * nbr * 3 * sizeof(double));
+  double* lam = nullptr;
+  cd* ubuf = nullptr;
+  ALLOC(lam, chunk * nbr * sizeof(double));
+  ALLOC(ubuf, chunk * (int64_t)nbr * nbr * sizeof(cd));
+  for (int64_t q0 = 0; q0 < nk; q0 += chunk) {
+    int64_t cnt = (nk - q0 < chunk) ? nk - q0 : chunk;
+    launch_fourier<true, true>(ctx, nullptr, q0, cnt, ctx->d_rp, ctx->d_wrp, ctx->nrp, ctx->d_dr, nbr, hbuf, gbuf);
+    launch_jacobi(hbuf, cnt, nbr, lam, ubuf, s);
+    hipLaunchKernelGGL(k_phonon_derived, dim3(blocks_for(cnt, 64)), dim3(64), 0, s, cnt, nbr, lam, ubuf, gbuf,
+                       ctx->d_mass_x, ctx->omega_min, 1.0e-6, ctx->d_hw + q0 * nbr,
+                       (cd*)ctx->d_Lq + q0 * nbr * nbr, ctx->d_vph + q0 * nbr * 3);
+  }
+  HIPCHK(hipGetLastError());
+
+  // ---- hw_max
+  double* red = nullptr;
+  ALLOC(red, 256 * sizeof(double));
+  hipLaunchKernelGGL(k_max_reduce, dim3(256), dim3(256), 0, s, ctx->d_hw, nk * nbr, red);
+  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, red, 256, red);
+  HIPCHK(hipMemcpyAsync(&ctx->hw_max, red, sizeof(double), hipMemcpyDeviceToHost, s));
+
+  // ---- phases of kept k
+  ALLOC(ctx->d_Ee, ctx->nkept * ctx->nre * sizeof(cd));
+  ALLOC(ctx->d_Ep, ctx->nkept * ctx->nrp * sizeof(cd));
+  hipLaunchKernelGGL(k_kept_phases, dim3(blocks_for(ctx->nkept * ctx->nre, 256)), dim3(256), 0, s,
+                     mesh_phase(ctx), ctx->d_kept, ctx->nkept, ctx->d_re, ctx->d_wre, ctx->nre, (cd*)ctx->d_Ee);
+  hipLaunchKernelGGL(k_kept_phases, dim3(blocks_for(ctx->nkept * ctx->nrp, 256)), dim3(256), 0, s,
+                     mesh_phase(ctx), ctx->d_kept, ctx->nkept, ctx->d_rp, nullptr, ctx->nrp, (cd*)ctx->d_Ep);
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+
+  // scratch no longer needed
+  dev_free(ctx, hbuf);
+  dev_free(ctx, gbuf);
+  dev_free(ctx, nact_mesh);
+  dev_free(ctx, flag);
+  dev_free(ctx, pos);
+  dev_free(ctx, scr);
+  dev_free(ctx, tot);
+  dev_free(ctx, nact_kept);
+  dev_free(ctx, lam);
+  dev_free(ctx, ubuf);
+  dev_free(ctx, red);
+  mark(ctx, 1);
+  ctx->tables_ready = true;
+  return ELPH_OK;
+}
+
+elph_status make_axis_tables(elph_ctx ctx) {
+  for (int d = 0; d < 3; ++d) {
+    ALLOC(ctx->d_tab[d], ctx->mesh[d] * sizeof(double2));
+    hipLaunchKernelGGL(k_axis_table, dim3(blocks_for(ctx->mesh[d], 256)), dim3(256), 0, ctx->stream,
+                       ctx->mesh[d], ctx->d_tab[d]);
+  }
+  HIPCHK(hipGetLastError());
+  return ELPH_OK;
+}
+
+// H(k) (and optionally eigen-decomposition) for an arbitrary list of mesh points
+elph_status fourier_points(elph_ctx ctx, bool phonon, const int32_t* pts, int64_t npts, cd* out) {
+  if (phonon)
+    launch_fourier<true, false>(ctx, pts, 0, npts, ctx->d_rp, ctx->d_wrp, ctx->nrp, ctx->d_dr, ctx->nbr, out,
+                                nullptr);
+  else
+    launch_fourier<false, false>(ctx, pts, 0, npts, ctx->d_re, ctx->d_wre, ctx->nre, ctx->d_hr, ctx->nb, out,
+                                 nullptr);
+  HIPCHK(hipGetLastError());
+  return ELPH_OK;
+}
+
+}  // namespace elph

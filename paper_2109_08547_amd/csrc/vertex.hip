@@ -1,0 +1,506 @@
+// The e-ph vertex of Eq. 6 ("The elphbolt ab initio solver ...") over all
+// pairs of active states, as two complex contractions on MFMA:
+//
+//   step 1 (per initial state i = (k, m)):
+//     Z[i][(x, Rp, n')] = sum_{(Re, m')} Ae[i][(Re, m')] g[Re][Rp][x][n'][m'],
+//     Ae[i][(Re, m')]   = w_e e^{2 pi i k.Re} U_k[m'][m]
+//     B2[(i, x)][(Rp, n')] = e^{-2 pi i k.Rp} Z[i][(x, Rp, n')]
+//   step 2 (all final states j = (k', n) against all initial states i):
+//     gh[j][(i, x)] = sum_{(Rp, n')} Ap[j][(Rp, n')] B2[(i, x)][(Rp, n')],
+//     Ap[j][(Rp, n')] = w_p e^{2 pi i k'.Rp} conj(U_k'[n'][n])
+//
+// so that gh is the Bloch-rotated vertex conj(U_k')^T gW(k, q) U_k of the
+// paper's Eq. 6 with q = k' - k (e^{2 pi i q.Rp} = e^{2 pi i k'.Rp}
+// e^{-2 pi i k.Rp}).  The epilogue of step 2 projects on the phonon
+// eigenvectors with the length prefactor (g_s = sum_x l_{x,s} u_q[x][s] gh_x),
+// forms |g_s|^2 and the Gaussian energy-conserving delta of Eq. 8, stores the
+// temperature-independent terms B^{+/-} = (2 pi / hbar N_k) |g|^2 delta(...)
+// and accumulates the electron rate of Eq. 21 and the phonon rate of Eq. 25.
+//
+// Complex products use four real MFMAs (re*re - im*im, re*im + im*re).
+// MFMA 16x16x4 operand layout (f64 and f32): lane l supplies A[row l%16][k l/16]
+// and B[k l/16][col l%16]; accumulator r of lane l holds column l%16 and row
+// l/16 + 4r (f64) or 4(l/16) + r (f32).
+#include "vertex.h"
+#include "tables.h"
+
+namespace elph {
+
+// ---------------------------------------------------------------------------
+// precision policies
+
+template <typename T>
+struct Mfma;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <>
+struct Mfma<double> {
+  typedef d4 acc_t;
+  __device__ static inline acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lk, int r) { return lk + 4 * r; }
+};
+
+template <>
+struct Mfma<float> {
+  typedef f4 acc_t;
+  __device__ static inline acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lk, int r) { return 4 * lk + r; }
+};
+
+template <typename T>
+struct Cplx {
+  T x, y;
+};
+
+template <typename T>
+__device__ inline Cplx<T> ldc(const T* p) {
+  if constexpr (sizeof(T) == 8) {
+    double2 v = *reinterpret_cast<const double2*>(p);
+    return Cplx<T>{(T)v.x, (T)v.y};
+  } else {
+    float2 v = *reinterpret_cast<const float2*>(p);
+    return Cplx<T>{(T)v.x, (T)v.y};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// operand builders (write the precision T of the contraction)
+
+template <typename T>
+__global__ void k_build_Ae(int64_t nstates, int nb, int nre, int64_t ke, const int32_t* __restrict__ st_kidx,
+                           const int32_t* __restrict__ st_m, const cd* __restrict__ Ee, const cd* __restrict__ U,
+                           T* __restrict__ Ae) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cols = (int64_t)nre * nb;
+  if (e >= nstates * cols) return;
+  int64_t i = e / cols;
+  int64_t col = e % cols;
+  int r = (int)(col / nb), mp = (int)(col % nb);
+  int t = st_kidx[i], m = st_m[i];
+  cd z = cmul(Ee[(int64_t)t * nre + r], U[((int64_t)t * nb + mp) * nb + m]);
+  Ae[2 * (i * ke + col)] = (T)z.x;
+  Ae[2 * (i * ke + col) + 1] = (T)z.y;
+}
+
+template <typename T>
+__global__ void k_build_Ap(int64_t nstates, int nb, int nrp, int64_t kp, const int32_t* __restrict__ st_kidx,
+                           const int32_t* __restrict__ st_m, const cd* __restrict__ Ep,
+                           const double* __restrict__ wrp, const cd* __restrict__ U, T* __restrict__ Ap) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cols = (int64_t)nrp * nb;
+  if (e >= nstates * cols) return;
+  int64_t j = e / cols;
+  int64_t col = e % cols;
+  int r = (int)(col / nb), np = (int)(col % nb);
+  int t = st_kidx[j], n = st_m[j];
+  cd z = cmul(Ep[(int64_t)t * nrp + r], cconj(U[((int64_t)t * nb + np) * nb + n]));
+  if (wrp) z = cscale(z, wrp[r]);
+  Ap[2 * (j * kp + col)] = (T)z.x;
+  Ap[2 * (j * kp + col) + 1] = (T)z.y;
+}
+
+// gR[(x, Rp, n')][(Re, m')] = g[Re][Rp][x][n'][m']
+template <typename T>
+__global__ void k_permute_g(int nre, int nrp, int nbr, int nb, int64_t ke, const double* __restrict__ g,
+                            T* __restrict__ gR) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nre * nrp * nbr * nb * nb;
+  if (e >= total) return;
+  int mp = (int)(e % nb);
+  int64_t t = e / nb;
+  int np = (int)(t % nb);
+  t /= nb;
+  int x = (int)(t % nbr);
+  t /= nbr;
+  int rp = (int)(t % nrp);
+  int re = (int)(t / nrp);
+  int64_t row = ((int64_t)x * nrp + rp) * nb + np;
+  int64_t col = (int64_t)re * nb + mp;
+  gR[2 * (row * ke + col)] = (T)g[2 * e];
+  gR[2 * (row * ke + col) + 1] = (T)g[2 * e + 1];
+}
+
+// ---------------------------------------------------------------------------
+// step 1: C[i][col] = sum_k Ae[i][k] gR[col][k]; epilogue writes B2 with the
+// e^{-2 pi i k_i . Rp} factor.  Block 2x2 waves, wave tile 32 x 32.
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_step1(int64_t m_pad, int64_t ncol, int64_t ke, const T* __restrict__ Ae,
+                                               const T* __restrict__ gR, int nrp, int nb, int nbr, int64_t kp,
+                                               int64_t nstates, const int32_t* __restrict__ st_kidx,
+                                               const cd* __restrict__ Ep, T* __restrict__ B2) {
+  typedef Mfma<T> MM;
+  typedef typename MM::acc_t acc_t;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t m0 = (int64_t)blockIdx.y * 64 + (wave >> 1) * 32;
+  const int64_t n0 = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  const T* pa[2];
+  const T* pb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    pa[t] = Ae + 2 * ((m0 + 16 * t + lr) * ke + lk);
+    int64_t nrow = n0 + 16 * t + lr;
+    if (nrow >= ncol) nrow = ncol - 1;
+    pb[t] = gR + 2 * (nrow * ke + lk);
+  }
+  acc_t cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = MM::zero();
+      ci[a][b] = MM::zero();
+    }
+  for (int64_t k = 0; k < ke; k += 4) {
+    Cplx<T> fa[2], fb[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      fa[t] = ldc(pa[t] + 2 * k);
+      fb[t] = ldc(pb[t] + 2 * k);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = MM::mma(fa[a].x, fb[b].x, cr[a][b]);
+        cr[a][b] = MM::mma(-fa[a].y, fb[b].y, cr[a][b]);
+        ci[a][b] = MM::mma(fa[a].x, fb[b].y, ci[a][b]);
+        ci[a][b] = MM::mma(fa[a].y, fb[b].x, ci[a][b]);
+      }
+  }
+  // epilogue
+  const int64_t per_x = (int64_t)nrp * nb;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = m0 + 16 * a + MM::row(lk, r);
+        const int64_t col = n0 + 16 * b + lr;
+        if (i >= nstates || col >= ncol) continue;
+        const int x = (int)(col / per_x);
+        const int64_t rem = col % per_x;
+        const int rp = (int)(rem / nb);
+        const cd ph = Ep[(int64_t)st_kidx[i] * nrp + rp];
+        const cd z = cmulc(cmake((double)cr[a][b][r], (double)ci[a][b][r]), ph);  // * conj(ph)
+        T* dst = B2 + 2 * ((i * nbr + x) * kp + rem);
+        dst[0] = (T)z.x;
+        dst[1] = (T)z.y;
+      }
+}
+
+// ---------------------------------------------------------------------------
+// step 2 fused with the epilogue.  Block 2x2 waves: 32 final states j x 32
+// initial states i; a wave owns 16 j x 16 i x NX branches-of-x tiles.
+
+struct EpiParams {
+  int64_t nstates;
+  int nbr;
+  int n0, n1, n2;            // mesh
+  double pref;               // 2 pi / (hbar N_k) / (sqrt(2 pi) sigma)
+  double inv2s2;             // 1 / (2 sigma^2)
+  double omega_min;
+  const int32_t* st_k;       // mesh index of each state
+  const double* eps;         // [nstates]
+  const double* hw;          // [nk][nbr]
+  const cd* Lq;              // [nk][nbr][nbr]
+  // temperature dependent (may be null when rates are not wanted)
+  const double* lomf;        // [nstates] log(1 - f)
+  const double* fstate;      // [nstates] f
+  const double* omf;         // [nstates] 1 - f
+  const double* nocc;        // [nk][nbr] Bose occupation
+  double* we_part;           // [gridDim.x][m_pad]
+  double* wph_acc;           // [nk][nbr]
+  int64_t m_pad;
+};
+
+__device__ inline int64_t q_of(int64_t kj, int64_t ki, int n0, int n1, int n2) {
+  int cj = (int)(kj % n2), ci = (int)(ki % n2);
+  int64_t tj = kj / n2, ti = ki / n2;
+  int bj = (int)(tj % n1), bi = (int)(ti % n1);
+  int aj = (int)(tj / n1), ai = (int)(ti / n1);
+  int a = aj - ai; if (a < 0) a += n0;
+  int b = bj - bi; if (b < 0) b += n1;
+  int c = cj - ci; if (c < 0) c += n2;
+  return ((int64_t)a * n1 + b) * n2 + c;
+}
+
+template <typename T, typename ST, int NX>
+__global__ void __launch_bounds__(256) k_step2(int64_t kp, const T* __restrict__ Ap, const T* __restrict__ B2,
+                                               EpiParams ep, ST* __restrict__ Bp, ST* __restrict__ Bm) {
+  typedef Mfma<T> MM;
+  typedef typename MM::acc_t acc_t;
+  __shared__ double red[4][16];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t j0 = (int64_t)blockIdx.x * 32 + (wave >> 1) * 16;
+  const int64_t i0 = (int64_t)blockIdx.y * 32 + (wave & 1) * 16;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  const T* pa = Ap + 2 * ((j0 + lr) * kp + lk);
+  const T* pb = B2 + 2 * (((i0 + lr) * NX) * kp + lk);
+  acc_t cr[NX], ci[NX];
+#pragma unroll
+  for (int x = 0; x < NX; ++x) {
+    cr[x] = MM::zero();
+    ci[x] = MM::zero();
+  }
+  for (int64_t k = 0; k < kp; k += 4) {
+    const Cplx<T> fa = ldc(pa + 2 * k);
+    const T nai = -fa.y;
+#pragma unroll
+    for (int x = 0; x < NX; ++x) {
+      const Cplx<T> fb = ldc(pb + 2 * (x * kp + k));
+      cr[x] = MM::mma(fa.x, fb.x, cr[x]);
+      cr[x] = MM::mma(nai, fb.y, cr[x]);
+      ci[x] = MM::mma(fa.x, fb.y, ci[x]);
+      ci[x] = MM::mma(fa.y, fb.x, ci[x]);
+    }
+  }
+
+  // epilogue: lane owns rows j = j0 + MM::row(lk, r), column i = i0 + lr
+  const int64_t i = i0 + lr;
+  const bool want_rates = ep.we_part != nullptr;
+  double we = 0.0;
+  if (i < ep.nstates) {
+    const int64_t ki = ep.st_k[i];
+    const double ei = ep.eps[i];
+    const double lomf_i = want_rates ? ep.lomf[i] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = j0 + MM::row(lk, r);
+      if (j >= ep.nstates) continue;
+      const int64_t q = q_of(ep.st_k[j], ki, ep.n0, ep.n1, ep.n2);
+      const double de = ep.eps[j] - ei;
+      const cd* L = ep.Lq + q * NX * NX;
+      const double* hwq = ep.hw + q * NX;
+      const double rij = want_rates ? exp(ep.lomf[j] - lomf_i) : 0.0;
+      const int64_t tb = (i * ep.nstates + j) * NX;
+#pragma unroll
+      for (int s = 0; s < NX; ++s) {
+        double gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+          const cd l = L[x * NX + s];
+          const double ar = (double)cr[x][r], ai = (double)ci[x][r];
+          gr += l.x * ar - l.y * ai;
+          gi += l.x * ai + l.y * ar;
+        }
+        const double g2 = gr * gr + gi * gi;
+        const double w = hwq[s];
+        double bp = 0.0, bm = 0.0;
+        if (w >= ep.omega_min) {
+          const double dp = de - w, dm = de + w;
+          bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
+          bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
+        }
+        Bp[tb + s] = (ST)bp;
+        Bm[tb + s] = (ST)bm;
+        if (want_rates && w >= ep.omega_min) {
+          const double n = ep.nocc[q * NX + s];
+          we += (bp * n + bm * (1.0 + n)) * rij;
+        }
+      }
+    }
+  }
+  if (want_rates) {
+    // sum over the 4 lanes sharing column i, then the two waves of this block
+    we += __shfl_xor(we, 16, 64);
+    we += __shfl_xor(we, 32, 64);
+    if (lk == 0) red[wave][lr] = we;
+    __syncthreads();
+    if (wave < 2 && lk == 0) {
+      const double tot = red[wave][lr] + red[wave + 2][lr];
+      if (i < ep.nstates) ep.we_part[(int64_t)blockIdx.x * ep.m_pad + i] = tot;
+    }
+  }
+}
+
+// W_e[i] = sum over j-tiles of the partials, in tile order
+__global__ void k_reduce_we(const double* __restrict__ part, int64_t ntiles, int64_t m_pad, int64_t nstates,
+                            double* __restrict__ we) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nstates) return;
+  double s = 0.0;
+  for (int64_t t = 0; t < ntiles; ++t) s += part[t * m_pad + i];
+  we[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+template <typename T>
+static elph_status build_operands_t(elph_ctx ctx) {
+  hipStream_t s = ctx->stream;
+  const int64_t M = ctx->nstates;
+  const int nb = ctx->nb, nbr = ctx->nbr;
+  ctx->m_pad = (M + 63) / 64 * 64;
+  ctx->ke = ((int64_t)ctx->nre * nb + 15) / 16 * 16;
+  ctx->kp = ((int64_t)ctx->nrp * nb + 15) / 16 * 16;
+  const int64_t ncol = (int64_t)nbr * ctx->nrp * nb;
+  const size_t esz = 2 * sizeof(T);
+  size_t bytes_ae = (size_t)ctx->m_pad * ctx->ke * esz;
+  size_t bytes_ap = (size_t)ctx->m_pad * ctx->kp * esz;
+  size_t bytes_gr = (size_t)ncol * ctx->ke * esz;
+  size_t bytes_b2 = (size_t)ctx->m_pad * nbr * ctx->kp * esz;
+  void *ae, *ap, *gr, *b2;
+  if (dev_alloc(ctx, &ae, bytes_ae) != hipSuccess || dev_alloc(ctx, &ap, bytes_ap) != hipSuccess ||
+      dev_alloc(ctx, &gr, bytes_gr) != hipSuccess || dev_alloc(ctx, &b2, bytes_b2) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "device allocation of the contraction operands failed";
+    return ELPH_ENOMEM;
+  }
+  ctx->d_Ae = ae;
+  ctx->d_Ap = ap;
+  ctx->d_gR = gr;
+  ctx->d_B2 = b2;
+  if (hipMemsetAsync(ae, 0, bytes_ae, s) != hipSuccess || hipMemsetAsync(ap, 0, bytes_ap, s) != hipSuccess ||
+      hipMemsetAsync(gr, 0, bytes_gr, s) != hipSuccess || hipMemsetAsync(b2, 0, bytes_b2, s) != hipSuccess) {
+    ctx->err = "hipMemsetAsync failed";
+    ctx->hip_dead = true;
+    return ELPH_EHIP;
+  }
+  hipLaunchKernelGGL(k_build_Ae<T>, dim3(blocks_for(M * ctx->nre * nb, 256)), dim3(256), 0, s, M, nb, ctx->nre,
+                     ctx->ke, ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_Ee, (const cd*)ctx->d_U,
+                     (T*)ae);
+  hipLaunchKernelGGL(k_build_Ap<T>, dim3(blocks_for(M * ctx->nrp * nb, 256)), dim3(256), 0, s, M, nb, ctx->nrp,
+                     ctx->kp, ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_Ep, ctx->d_wrp,
+                     (const cd*)ctx->d_U, (T*)ap);
+  const int64_t gtotal = (int64_t)ctx->nre * ctx->nrp * nbr * nb * nb;
+  hipLaunchKernelGGL(k_permute_g<T>, dim3(blocks_for(gtotal, 256)), dim3(256), 0, s, ctx->nre, ctx->nrp, nbr, nb,
+                     ctx->ke, ctx->d_gr, (T*)gr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    ctx->err = std::string("kernel launch failed: ") + hipGetErrorString(e);
+    ctx->hip_dead = true;
+    return ELPH_EHIP;
+  }
+  ctx->operands_ready = true;
+  return ELPH_OK;
+}
+
+elph_status build_operands(elph_ctx ctx) {
+  if (ctx->operands_ready) return ELPH_OK;
+  if (ctx->precision == ELPH_FP64) return build_operands_t<double>(ctx);
+  if (ctx->precision == ELPH_FP32) return build_operands_t<float>(ctx);
+  ctx->err = "precision form not available";
+  return ELPH_EINVAL;
+}
+
+template <typename T>
+static void launch_step1_t(elph_ctx ctx) {
+  const int64_t ncol = (int64_t)ctx->nbr * ctx->nrp * ctx->nb;
+  dim3 grid((unsigned)((ncol + 63) / 64), (unsigned)(ctx->m_pad / 64));
+  hipLaunchKernelGGL(k_step1<T>, grid, dim3(256), 0, ctx->stream, ctx->m_pad, ncol, ctx->ke, (const T*)ctx->d_Ae,
+                     (const T*)ctx->d_gR, ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, ctx->nstates, ctx->d_state_kidx,
+                     (const cd*)ctx->d_Ep, (T*)ctx->d_B2);
+}
+
+template <typename T, typename ST, int NX>
+static void launch_step2_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm) {
+  dim3 grid((unsigned)(ctx->m_pad / 32), (unsigned)(ctx->m_pad / 32));
+  hipLaunchKernelGGL((k_step2<T, ST, NX>), grid, dim3(256), 0, ctx->stream, ctx->kp, (const T*)ctx->d_Ap,
+                     (const T*)ctx->d_B2, ep, (ST*)Bp, (ST*)Bm);
+}
+
+template <typename T, typename ST>
+static elph_status launch_step2_t(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm) {
+  switch (ctx->nbr) {
+    case 3: launch_step2_nx<T, ST, 3>(ctx, ep, Bp, Bm); break;
+    case 6: launch_step2_nx<T, ST, 6>(ctx, ep, Bp, Bm); break;
+    case 9: launch_step2_nx<T, ST, 9>(ctx, ep, Bp, Bm); break;
+    case 12: launch_step2_nx<T, ST, 12>(ctx, ep, Bp, Bm); break;
+    case 15: launch_step2_nx<T, ST, 15>(ctx, ep, Bp, Bm); break;
+    default: ctx->err = "unsupported branch count"; return ELPH_EINVAL;
+  }
+  return ELPH_OK;
+}
+
+// Run both contractions and the epilogue.  Bp/Bm receive the term store
+// (double when store_f64, else float).  If th != nullptr the rates at that
+// temperature are accumulated into we_out [nstates] and wph_acc [nk][nbr]
+// (wph_acc must be zeroed by the caller).
+elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const Thermal* th, double* we_out,
+                       double* wph_acc) {
+  elph_status st = build_operands(ctx);
+  if (st != ELPH_OK) return st;
+  EpiParams ep;
+  ep.nstates = ctx->nstates;
+  ep.nbr = ctx->nbr;
+  ep.n0 = ctx->mesh[0];
+  ep.n1 = ctx->mesh[1];
+  ep.n2 = ctx->mesh[2];
+  ep.pref = 2.0 * kPi / (kHbarEVs * (double)ctx->nk) / (sqrt(2.0 * kPi) * ctx->sigma);
+  ep.inv2s2 = 1.0 / (2.0 * ctx->sigma * ctx->sigma);
+  ep.omega_min = ctx->omega_min;
+  ep.st_k = ctx->d_state_k;
+  ep.eps = ctx->d_eps;
+  ep.hw = ctx->d_hw;
+  ep.Lq = (const cd*)ctx->d_Lq;
+  ep.m_pad = ctx->m_pad;
+  const int64_t ntiles = ctx->m_pad / 32;
+  if (th) {
+    if (ctx->we_part_len < ntiles * ctx->m_pad) {
+      void* p;
+      if (dev_alloc(ctx, &p, (size_t)ntiles * ctx->m_pad * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->err = "device allocation of rate partials failed";
+        return ELPH_ENOMEM;
+      }
+      if (ctx->d_we_part) dev_free(ctx, ctx->d_we_part);
+      ctx->d_we_part = (double*)p;
+      ctx->we_part_len = ntiles * ctx->m_pad;
+    }
+    ep.lomf = th->lomf;
+    ep.fstate = th->f;
+    ep.omf = th->omf;
+    ep.nocc = th->nocc;
+    ep.we_part = ctx->d_we_part;
+    ep.wph_acc = wph_acc;
+  } else {
+    ep.lomf = ep.fstate = ep.omf = ep.nocc = nullptr;
+    ep.we_part = nullptr;
+    ep.wph_acc = nullptr;
+  }
+  if (ctx->precision == ELPH_FP64) {
+    mark(ctx, 2);
+    launch_step1_t<double>(ctx);
+    mark(ctx, 3);
+    mark(ctx, 4);
+    st = store_f64 ? launch_step2_t<double, double>(ctx, ep, Bp, Bm) : launch_step2_t<double, float>(ctx, ep, Bp, Bm);
+    mark(ctx, 5);
+  } else {
+    mark(ctx, 2);
+    launch_step1_t<float>(ctx);
+    mark(ctx, 3);
+    mark(ctx, 4);
+    st = store_f64 ? launch_step2_t<float, double>(ctx, ep, Bp, Bm) : launch_step2_t<float, float>(ctx, ep, Bp, Bm);
+    mark(ctx, 5);
+  }
+  if (st != ELPH_OK) return st;
+  if (th && we_out) {
+    hipLaunchKernelGGL(k_reduce_we, dim3(blocks_for(ctx->nstates, 256)), dim3(256), 0, ctx->stream,
+                       ctx->d_we_part, ntiles, ctx->m_pad, ctx->nstates, we_out);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    ctx->err = std::string("kernel launch failed: ") + hipGetErrorString(e);
+    ctx->hip_dead = true;
+    return ELPH_EHIP;
+  }
+  return ELPH_OK;
+}
+
+}  // namespace elph

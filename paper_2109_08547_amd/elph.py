@@ -1,0 +1,205 @@
+"""ctypes binding of libelph (include/elph.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts NumPy host
+inputs and GPU tensors (device outputs, via their data pointers) into the C
+ABI's plain pointers and turns nonzero status codes into ElphError.  It fails
+loudly when the compiled library is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libelph.so")
+
+ELPH_OK, ELPH_EINVAL, ELPH_ENOMEM, ELPH_EHIP, ELPH_ENOCONV, ELPH_ESTATE = range(6)
+ELPH_FP64, ELPH_FP32, ELPH_BF16X3, ELPH_BF16X6 = range(4)
+ELPH_LEVEL_RTA, ELPH_LEVEL_PARTIAL, ELPH_LEVEL_DRAGLESS, ELPH_LEVEL_COUPLED = range(4)
+PRECISIONS = {"fp64": ELPH_FP64, "fp32": ELPH_FP32, "bf16x3": ELPH_BF16X3, "bf16x6": ELPH_BF16X6}
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+_c_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class ElphWannier(ctypes.Structure):
+    _fields_ = [("nwann", ctypes.c_int32), ("natom", ctypes.c_int32), ("nre", ctypes.c_int32),
+                ("nrp", ctypes.c_int32), ("re", _c_i32p), ("rp", _c_i32p), ("wre", _c_f64p),
+                ("wrp", _c_f64p), ("lat", _c_f64p), ("mass", _c_f64p), ("h_r", _c_f64p),
+                ("d_r", _c_f64p), ("g_r", _c_f64p)]
+
+
+class ElphParams(ctypes.Structure):
+    _fields_ = [("mesh", ctypes.c_int32 * 3), ("precision", ctypes.c_int32), ("mu_eV", ctypes.c_double),
+                ("window_eV", ctypes.c_double), ("sigma_eV", ctypes.c_double),
+                ("omega_min_eV", ctypes.c_double)]
+
+
+class ElphSizes(ctypes.Structure):
+    _fields_ = [("nk", ctypes.c_int64), ("nkept", ctypes.c_int64), ("nstates", ctypes.c_int64),
+                ("nwann", ctypes.c_int32), ("nbr", ctypes.c_int32), ("nterms", ctypes.c_int64),
+                ("hw_max_eV", ctypes.c_double), ("ngroups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
+           "elph_tables",
+           "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate")
+
+_lib = None
+
+
+def load():
+    """Load libelph.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libelph.so is not built; run __graft_entry__.build() or "
+                           "python -m paper_2109_08547_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.elph_create.argtypes = [ctypes.POINTER(ElphWannier), ctypes.POINTER(ElphParams), vp,
+                                ctypes.POINTER(vp)]
+    lib.elph_destroy.argtypes = [vp]
+    lib.elph_destroy.restype = None
+    lib.elph_last_error.argtypes = [vp]
+    lib.elph_last_error.restype = ctypes.c_char_p
+    lib.elph_reset.argtypes = [vp]
+    lib.elph_timing.argtypes = [vp, ctypes.c_int32, vp]
+    lib.elph_sizes.argtypes = [vp, ctypes.POINTER(ElphSizes)]
+    lib.elph_tables.argtypes = [vp] * 7
+    lib.elph_interp_g.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
+    lib.elph_transition_probs.argtypes = [vp, ctypes.c_double, vp, vp, ctypes.c_int32]
+    lib.elph_scatt_rates.argtypes = [vp, ctypes.c_double, vp, vp]
+    lib.elph_iterate.argtypes = [vp, ctypes.c_double, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                 vp, vp, vp, vp, vp, vp, vp]
+    for name in EXPORTS:
+        if name not in ("elph_destroy", "elph_last_error"):
+            getattr(lib, name).restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+class ElphError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("elph status %d: %s" % (status, message))
+        self.status = status
+        self.message = message
+
+
+def _ptr(t):
+    """Device pointer of a GPU tensor (or None)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns an elph_ctx handle; keeps the host input arrays alive while needed."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().elph_destroy(self.handle)
+            self.handle = None
+
+
+def _check(ctx, status):
+    if status != ELPH_OK:
+        msg = load().elph_last_error(ctx.handle if ctx is not None else None)
+        raise ElphError(status, msg.decode() if msg else "")
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def elph_create(mat, mesh, mu, window, sigma, omega_min=0.0, precision=ELPH_FP64, stream=None):
+    """Create a context from a material dict (nwann, natom, re, rp, wre, wrp,
+    lat, mass, h_r, d_r, g_r as NumPy arrays).  ``stream`` is a HIP stream
+    handle (int) or None for the default stream."""
+    lib = load()
+    keep = {k: _arr(mat[k], np.int32) for k in ("re", "rp")}
+    for k in ("wre", "wrp", "lat", "mass", "d_r"):
+        keep[k] = _arr(mat[k], np.float64)
+    for k in ("h_r", "g_r"):
+        keep[k] = _arr(mat[k], np.complex128).view(np.float64)
+    w = ElphWannier()
+    w.nwann, w.natom = int(mat["nwann"]), int(mat["natom"])
+    w.nre, w.nrp = keep["re"].shape[0], keep["rp"].shape[0]
+    for k in ("re", "rp"):
+        setattr(w, k, keep[k].ctypes.data_as(_c_i32p))
+    for k in ("wre", "wrp", "lat", "mass", "h_r", "d_r", "g_r"):
+        setattr(w, k, keep[k].ctypes.data_as(_c_f64p))
+    p = ElphParams()
+    m = [int(mesh)] * 3 if np.isscalar(mesh) else [int(x) for x in mesh]
+    p.mesh[:] = m
+    p.precision = PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
+    p.mu_eV, p.window_eV, p.sigma_eV, p.omega_min_eV = float(mu), float(window), float(sigma), float(omega_min)
+    h = ctypes.c_void_p()
+    st = lib.elph_create(ctypes.byref(w), ctypes.byref(p), ctypes.c_void_p(stream) if stream else None,
+                         ctypes.byref(h))
+    _check(None, st)
+    return Context(h)
+
+
+def elph_destroy(ctx):
+    ctx.close()
+
+
+def elph_reset(ctx):
+    _check(ctx, load().elph_reset(ctx.handle))
+
+
+def elph_timing(ctx, enable=True, read=False):
+    """Turn event timing on/off; with read=True return the last durations (ms)
+    of [tables, step1, step2, iterate] (-1 where none was recorded)."""
+    ms = np.full(4, -1.0)
+    _check(ctx, load().elph_timing(ctx.handle, int(bool(enable)),
+                                   ms.ctypes.data_as(ctypes.c_void_p) if read else None))
+    return dict(zip(("tables", "step1", "step2", "iterate"), ms)) if read else None
+
+
+def elph_sizes(ctx):
+    s = ElphSizes()
+    _check(ctx, load().elph_sizes(ctx.handle, ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in ElphSizes._fields_ if f != "reserved"}
+
+
+def elph_tables(ctx, state_k=None, state_m=None, eps=None, vel=None, hw=None, vph=None):
+    _check(ctx, load().elph_tables(ctx.handle, _ptr(state_k), _ptr(state_m), _ptr(eps), _ptr(vel), _ptr(hw),
+                                   _ptr(vph)))
+
+
+def elph_interp_g(ctx, kidx, qidx, g_out):
+    n = int(kidx.numel())
+    _check(ctx, load().elph_interp_g(ctx.handle, n, _ptr(kidx), _ptr(qidx), _ptr(g_out)))
+
+
+def elph_transition_probs(ctx, T, Xp=None, Xm=None, store_B=False):
+    _check(ctx, load().elph_transition_probs(ctx.handle, float(T), _ptr(Xp), _ptr(Xm), int(bool(store_B))))
+
+
+def elph_scatt_rates(ctx, T, W_e=None, W_ph=None):
+    _check(ctx, load().elph_scatt_rates(ctx.handle, float(T), _ptr(W_e), _ptr(W_ph)))
+
+
+def elph_iterate(ctx, T, I, J, F, G, W_ph_ext=None, level=ELPH_LEVEL_COUPLED, tol=1e-8, maxit=200,
+                 raise_on_noconv=True):
+    """Returns dict(tensors [6,3,3] numpy, iters, ko_residual, status)."""
+    tens = np.zeros(54)
+    iters = ctypes.c_int32(0)
+    ko = ctypes.c_double(0.0)
+    st = load().elph_iterate(ctx.handle, float(T), _ptr(W_ph_ext), int(level), float(tol), int(maxit),
+                             _ptr(I), _ptr(J), _ptr(F), _ptr(G), tens.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(iters), ctypes.byref(ko))
+    if st != ELPH_OK and not (st == ELPH_ENOCONV and not raise_on_noconv):
+        _check(ctx, st)
+    names = ("sigma", "sigmaS", "alpha_el", "kappa0_el", "alpha_ph", "kappa_ph")
+    return {"tensors": {n: tens[9 * a:9 * a + 9].reshape(3, 3).copy() for a, n in enumerate(names)},
+            "iters": iters.value, "ko_residual": ko.value, "status": st}

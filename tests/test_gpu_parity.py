@@ -1,0 +1,265 @@
+"""HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerances: the plain FP64 path must match to relative 1e-10; elementwise
+terms use |d| <= 1e-10 |x| + 1e-12 max|x| because tiny vertices carry the
+absolute rounding of the phase sums.  Rates use the max-per-state relative
+error over states with W_ref >= 1e-12 max W_ref (smaller ones absolutely).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import materials as sm
+
+torch = pytest.importorskip("torch")
+E = pytest.importorskip("paper_2109_08547_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rate_err(w, ref, floor=1e-12):
+    w, ref = np.asarray(w).ravel(), np.asarray(ref).ravel()
+    mx = np.abs(ref).max()
+    big = np.abs(ref) >= floor * mx
+    e_rel = (np.abs(w[big] - ref[big]) / np.abs(ref[big])).max() if big.any() else 0.0
+    e_abs = (np.abs(w[~big] - ref[~big]) / mx).max() if (~big).any() else 0.0
+    return max(e_rel, e_abs)
+
+
+def term_ok(x, ref, rtol=1e-10, atol_rel=1e-12):
+    x, ref = np.asarray(x), np.asarray(ref)
+    bound = rtol * np.abs(ref) + atol_rel * np.abs(ref).max()
+    return np.all(np.abs(x - ref) <= bound), (np.abs(x - ref) / (np.abs(ref) + 1e-300)).max()
+
+
+def make_ctx(cfg, mat, precision="fp64", window=None, mu=None):
+    return E.elph_create(mat, cfg["mesh"], cfg["mu"] if mu is None else mu,
+                         cfg["window"] if window is None else window, cfg["sigma"], precision=precision)
+
+
+def dtensor(n, dtype=torch.float64):
+    return torch.empty(int(n), dtype=dtype, device=DEV)
+
+
+class Case:
+    """A workload with its oracle results on all rows (small meshes)."""
+
+    def __init__(self, name, T=300.0, mat=None, cfg=None):
+        self.cfg = cfg or synth.config(name)
+        self.mat = mat or synth.material_for(self.cfg)
+        self.T = T
+        c = self.cfg
+        self.prob = oracle.Problem(self.mat, c["mesh"], c["mu"], c["window"], c["sigma"])
+        self.Xp, self.Xm = self.prob.transition_probs(T)
+        self.we = self.prob.rates_e(T, self.Xp, self.Xm)
+        self.wph = self.prob.rates_ph(T, self.Xp)
+
+
+_cases = {}
+
+
+def case(name):
+    if name not in _cases:
+        _cases[name] = Case(name)
+    return _cases[name]
+
+
+def _maxsize_case():
+    """Largest band and branch counts the library supports: 16 bands, 5 atoms."""
+    if "max16" not in _cases:
+        mat = sm.make_material(16, 5, 41, sm.rset_cube(-1, 1), sm.rset_cube(0, 1), 2.0, 0.15, 0.6, 0.004)
+        cfg = dict(mesh=3, mu=0.0, window=0.9, sigma=0.02, T=300.0)
+        _cases["max16"] = Case("max16", mat=mat, cfg=cfg)
+    return _cases["max16"]
+
+
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["tiny4", "plain8", "metal6"])
+def test_tables(name):
+    c = case(name)
+    ctx = make_ctx(c.cfg, c.mat)
+    sz = E.elph_sizes(ctx)
+    p = c.prob
+    assert sz["nstates"] == p.nstates and sz["nkept"] == p.kept.size and sz["nk"] == p.nk
+    M, nm = sz["nstates"], sz["nk"] * sz["nbr"]
+    sk, smm = dtensor(M, torch.int32), dtensor(M, torch.int32)
+    eps, vel = dtensor(M), dtensor(3 * M)
+    hw, vph = dtensor(nm), dtensor(3 * nm)
+    E.elph_tables(ctx, sk, smm, eps, vel, hw, vph)
+    torch.cuda.synchronize()
+    assert np.array_equal(sk.cpu().numpy(), p.state_k)
+    assert np.array_equal(smm.cpu().numpy(), p.state_m)
+    assert np.abs(eps.cpu().numpy() - p.eps).max() < 1e-12 * max(1.0, np.abs(p.eps).max())
+    v = vel.cpu().numpy().reshape(M, 3)
+    assert np.abs(v - p.v_state).max() < 1e-9 * np.abs(p.v_state).max()
+    # compare (hbar omega)^2: the zero modes at Gamma are square roots of rounding noise
+    assert np.abs(hw.cpu().numpy().reshape(-1, sz["nbr"]) ** 2 - p.hw ** 2).max() < 1e-12 * p.hw.max() ** 2
+    vp = vph.cpu().numpy().reshape(-1, sz["nbr"], 3)
+    assert np.abs(vp - p.v_ph).max() < 1e-8 * np.abs(p.v_ph).max()
+    assert abs(sz["hw_max_eV"] - p.hw.max()) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["tiny3", "tiny4", "plain8", "metal6"])
+def test_transition_probs_full(name):
+    c = case(name)
+    ctx = make_ctx(c.cfg, c.mat)
+    sz = E.elph_sizes(ctx)
+    xp, xm = dtensor(sz["nterms"]), dtensor(sz["nterms"])
+    E.elph_transition_probs(ctx, c.T, xp, xm)
+    torch.cuda.synchronize()
+    shape = c.Xp.shape
+    ok_p, ep = term_ok(xp.cpu().numpy().reshape(shape), c.Xp)
+    ok_m, em = term_ok(xm.cpu().numpy().reshape(shape), c.Xm)
+    assert ok_p and ok_m, (ep, em)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["tiny3", "tiny4", "plain8", "metal6"])
+def test_scatt_rates_full(name):
+    c = case(name)
+    ctx = make_ctx(c.cfg, c.mat)
+    sz = E.elph_sizes(ctx)
+    we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
+    E.elph_scatt_rates(ctx, c.T, we, wph)
+    torch.cuda.synchronize()
+    assert rate_err(we.cpu().numpy(), c.we) < 1e-10
+    assert rate_err(wph.cpu().numpy(), c.wph) < 1e-10
+    # the vertex store is reused at another temperature
+    T2 = 200.0
+    E.elph_scatt_rates(ctx, T2, we, wph)
+    torch.cuda.synchronize()
+    Xp2, Xm2 = c.prob.transition_probs(T2)
+    assert rate_err(we.cpu().numpy(), c.prob.rates_e(T2, Xp2, Xm2)) < 1e-10
+    assert rate_err(wph.cpu().numpy(), c.prob.rates_ph(T2, Xp2)) < 1e-10
+    # transition probabilities from the retained store
+    xp, xm = dtensor(sz["nterms"]), dtensor(sz["nterms"])
+    E.elph_transition_probs(ctx, T2, xp, xm, store_B=True)
+    torch.cuda.synchronize()
+    assert term_ok(xp.cpu().numpy().reshape(Xp2.shape), Xp2)[0]
+    assert term_ok(xm.cpu().numpy().reshape(Xm2.shape), Xm2)[0]
+    ctx.close()
+
+
+def test_maximum_sizes_16_bands_5_atoms():
+    c = _maxsize_case()
+    ctx = make_ctx(c.cfg, c.mat)
+    sz = E.elph_sizes(ctx)
+    assert sz["nwann"] == 16 and sz["nbr"] == 15 and sz["nstates"] == c.prob.nstates
+    we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
+    E.elph_scatt_rates(ctx, c.T, we, wph)
+    torch.cuda.synchronize()
+    assert rate_err(we.cpu().numpy(), c.we) < 1e-10
+    assert rate_err(wph.cpu().numpy(), c.wph) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["tiny4", "plain8"])
+def test_interp_g_pairs(name):
+    c = case(name)
+    p = c.prob
+    ctx = make_ctx(c.cfg, c.mat)
+    rng = np.random.default_rng(17)
+    npairs = 40
+    kk = rng.integers(0, p.nk, npairs).astype(np.int32)
+    qq = rng.integers(1, p.nk, npairs).astype(np.int32)  # q != Gamma (degenerate acoustic)
+    g = torch.empty((npairs, p.nbr, p.nb, p.nb, 2), dtype=torch.float64, device=DEV)
+    E.elph_interp_g(ctx, torch.from_numpy(kk).to(DEV), torch.from_numpy(qq).to(DEV), g)
+    torch.cuda.synchronize()
+    g2 = (g.cpu().numpy() ** 2).sum(-1)
+    for t in range(npairs):
+        k, q = p.kfrac[kk[t]], p.kfrac[qq[t]]
+        gW = oracle.g_wannier_brute(c.mat, k, q) if name == "tiny4" else \
+            oracle.g_wannier_factorised(c.mat, k, q[None])[0]
+        _, Uk = oracle.electron_bands(c.mat, k[None])
+        _, Ukq = oracle.electron_bands(c.mat, (k + q)[None])
+        hw, u = oracle.phonon_modes(c.mat, q[None])
+        ref = np.abs(oracle.g_bloch(c.mat, gW, Uk[0], Ukq[0], u[0], hw[0])) ** 2
+        assert np.abs(g2[t] - ref).max() <= 1e-10 * ref.max(), t
+    # an empty list is a no-op
+    E.elph_interp_g(ctx, torch.empty(0, dtype=torch.int32, device=DEV),
+                    torch.empty(0, dtype=torch.int32, device=DEV), g)
+    ctx.close()
+
+
+def test_determinism_plain8():
+    c = case("plain8")
+    ctx = make_ctx(c.cfg, c.mat)
+    sz = E.elph_sizes(ctx)
+    out = []
+    for _ in range(2):
+        E.elph_reset(ctx)
+        we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
+        xp = dtensor(sz["nterms"])
+        E.elph_scatt_rates(ctx, c.T, we, wph)
+        E.elph_transition_probs(ctx, c.T, xp, None, store_B=True)
+        torch.cuda.synchronize()
+        out.append((we.cpu().numpy(), wph.cpu().numpy(), xp.cpu().numpy()))
+    # fixed-order reductions everywhere: bitwise equal
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["plain8", "metal6"])
+def test_fp32_form(name):
+    c = case(name)
+    ctx = make_ctx(c.cfg, c.mat, precision="fp32")
+    sz = E.elph_sizes(ctx)
+    we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
+    E.elph_scatt_rates(ctx, c.T, we, wph)
+    torch.cuda.synchronize()
+    # FP32 accumulation gives each vertex ~2^-24 sqrt(K) absolute error relative to its
+    # terms, so rates built only from strongly cancelled vertices (below 1e-6 of the
+    # largest rate) are judged by the norm-wise error
+    w1, w2 = we.cpu().numpy(), wph.cpu().numpy()
+    strict = rate_err(w1, c.we), rate_err(w2, c.wph)
+    e1, e2 = rate_err(w1, c.we, 1e-6), rate_err(w2, c.wph, 1e-6)
+    n1 = np.linalg.norm(w1 - c.we) / np.linalg.norm(c.we)
+    n2 = np.linalg.norm(w2 - c.wph.ravel()) / np.linalg.norm(c.wph)
+    print("fp32 form %s: strict %.2e %.2e, above 1e-6 max %.2e %.2e, norm-wise %.2e %.2e"
+          % (name, strict[0], strict[1], e1, e2, n1, n2))
+    assert e1 < 1e-5 and e2 < 1e-5 and n1 < 1e-6 and n2 < 1e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_iterate_metal6(level):
+    c = case("metal6")
+    T = c.T
+    ctx = make_ctx(c.cfg, c.mat)
+    sz = E.elph_sizes(ctx)
+    M, nm = sz["nstates"], sz["nk"] * sz["nbr"]
+    I, J, F, G = dtensor(3 * M), dtensor(3 * M), dtensor(3 * nm), dtensor(3 * nm)
+    wext = oracle.default_w_ext(c.prob, T, gamma0=1e13)
+    wext_d = torch.from_numpy(np.ascontiguousarray(wext.reshape(-1))).to(DEV)
+    tol = 1e-12
+    res = E.elph_iterate(ctx, T, I, J, F, G, W_ph_ext=wext_d, level=level, tol=tol, maxit=400)
+    torch.cuda.synchronize()
+    ref = oracle.iterate(c.prob, T, c.Xp, c.Xm, level, tol=tol, maxit=400, w_ext=wext)
+    assert ref["converged"]
+    got = dict(I=I.cpu().numpy().reshape(M, 3), J=J.cpu().numpy().reshape(M, 3),
+               F=F.cpu().numpy().reshape(-1, sz["nbr"], 3), G=G.cpu().numpy().reshape(-1, sz["nbr"], 3))
+    for key in ("I", "J", "F", "G"):
+        scale = np.abs(ref[key]).max()
+        if scale == 0:
+            assert np.abs(got[key]).max() == 0
+            continue
+        assert np.abs(got[key] - ref[key]).max() <= 1e-8 * scale, key
+    tens = oracle.transport_tensors(c.prob, T, ref["I"], ref["J"], ref["F"], ref["G"])
+    for key, val in tens.items():
+        assert np.abs(res["tensors"][key] - val).max() <= 1e-8 * max(np.abs(val).max(), 1e-300), key
+    assert abs(res["ko_residual"] - oracle.ko_residual(tens, T)) < 1e-6
+    ctx.close()
+
+
+def test_window_excluding_everything_is_einval():
+    c = case("plain8")
+    ctx = make_ctx(c.cfg, c.mat, window=1e-9, mu=50.0)
+    with pytest.raises(E.ElphError) as ei:
+        E.elph_sizes(ctx)
+    assert ei.value.status == E.elph.ELPH_EINVAL
+    ctx.close()
