@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace elph {
 
@@ -197,7 +199,7 @@ __global__ void __launch_bounds__(256) k_we_rows(int64_t M, int nbr, MeshDims md
 //   acc[q][s][c] = sum_{i in k, j in k'} B+[i][j][s] f_i (1 - f_j) w_c(i, j),
 // with w = 1 (NV = 1, the phonon rate of Eq. 25) or w = x_j - x_i (NV = 6,
 // the drag term of Eq. 27).  Lane partials are combined in a fixed order.
-template <typename ST, int NV>
+template <typename ST, int NV, int NX>
 __global__ void __launch_bounds__(256) k_q_gather(int64_t nq, int64_t M, int nbr, MeshDims md,
                                                   const ST* __restrict__ Bp, const int32_t* __restrict__ kept,
                                                   int64_t nkept, const int32_t* __restrict__ kidx,
@@ -210,9 +212,9 @@ __global__ void __launch_bounds__(256) k_q_gather(int64_t nq, int64_t M, int nbr
   const int qc = (int)(q % md.n2);
   const int64_t qt = q / md.n2;
   const int qb = (int)(qt % md.n1), qa = (int)(qt / md.n1);
-  double a[kMaxBands][NV];
+  double a[NX][NV];
 #pragma unroll
-  for (int s = 0; s < kMaxBands; ++s)
+  for (int s = 0; s < NX; ++s)
 #pragma unroll
     for (int c = 0; c < NV; ++c) a[s][c] = 0.0;
   for (int64_t t = lane; t < nkept; t += 64) {
@@ -233,30 +235,45 @@ __global__ void __launch_bounds__(256) k_q_gather(int64_t nq, int64_t M, int nbr
         else
 #pragma unroll
           for (int c = 0; c < NV; ++c) w[c] = x[(int64_t)j * NV + c] - x[(int64_t)i * NV + c];
-        const ST* b = Bp + ((int64_t)i * M + j) * nbr;
+        const ST* b = Bp + ((int64_t)i * M + j) * NX;
 #pragma unroll
-        for (int s = 0; s < kMaxBands; ++s) {
-          if (s < nbr) {
-            const double v = (double)b[s] * occ;
+        for (int s = 0; s < NX; ++s) {
+          const double v = (double)b[s] * occ;
 #pragma unroll
-            for (int c = 0; c < NV; ++c) a[s][c] += v * w[c];
-          }
+          for (int c = 0; c < NV; ++c) a[s][c] += v * w[c];
         }
       }
     }
   }
   // fixed-order butterfly over the wavefront
 #pragma unroll
-  for (int s = 0; s < kMaxBands; ++s) {
-    if (s >= nbr) break;
+  for (int s = 0; s < NX; ++s) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
       double v = a[s][c];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if (lane == 0) acc[(q * nbr + s) * NV + c] = v;
+      if (lane == 0) acc[(q * NX + s) * NV + c] = v;
     }
   }
+}
+
+template <typename ST, int NV>
+static void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x,
+                            double* acc) {
+  const dim3 grid(blocks_for(ctx->nk, 4)), blk(256);
+  const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
+#define QG(NXV)                                                                                           \
+  hipLaunchKernelGGL((k_q_gather<ST, NV, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, NXV, md, Bp, \
+                     ctx->d_kept, ctx->nkept, ctx->d_kidx, ctx->d_soff, f, omf, x, acc)
+  switch (ctx->nbr) {
+    case 3: QG(3); break;
+    case 6: QG(6); break;
+    case 9: QG(9); break;
+    case 12: QG(12); break;
+    default: QG(15); break;
+  }
+#undef QG
 }
 
 // W_ph = d_s (N_k/N_q) acc / (1 + n)
@@ -307,9 +324,7 @@ static elph_status rates_from_store_t(elph_ctx ctx, const Thermal& th, double* w
     const int64_t nm = ctx->nk * nbr;
     double* acc = nullptr;
     ALLOC(acc, nm * sizeof(double));
-    hipLaunchKernelGGL((k_q_gather<ST, 1>), dim3(blocks_for(ctx->nk, 4)), dim3(256), 0, s, ctx->nk, M, nbr,
-                       mdims(ctx), (const ST*)ctx->d_Bp, ctx->d_kept, ctx->nkept, ctx->d_kidx, ctx->d_soff, th.f,
-                       th.omf, (const double*)nullptr, acc);
+    launch_q_gather<ST, 1>(ctx, (const ST*)ctx->d_Bp, th.f, th.omf, nullptr, acc);
     elph_status st = finalize_wph(ctx, th, acc, wph);
     HIPCHK(hipStreamSynchronize(s));
     dev_free(ctx, acc);
@@ -604,24 +619,86 @@ __global__ void __launch_bounds__(256) k_drag_e(int64_t M, int nbr, MeshDims md,
   }
 }
 
-// xn[i][c] = x0[i][c] + De[i][c] + sum_j K[i][j] x[j][c]
+// xn[i][c] = x0[i][c] + De[i][c] + sgn * sum_j K[i][j] x[j][c].  A block owns
+// 4 rows (one wavefront each); chunks of 256 rows of x are staged in LDS and
+// shared by the 4 rows; each wavefront reduces with butterflies (fixed order).
 __global__ void __launch_bounds__(256) k_self_sweep(int64_t M, const double* __restrict__ K,
                                                     const double* __restrict__ x, const double* __restrict__ x0,
-                                                    const double* __restrict__ De, double* __restrict__ xn) {
-  __shared__ double sh[6 * 4];
-  const int64_t i = blockIdx.x;
+                                                    const double* __restrict__ De, double sgn,
+                                                    double* __restrict__ xn) {
+  __shared__ double xs[256 * 6];
+  const int r = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + r;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t j = threadIdx.x; j < M; j += 256) {
-    const double k = K[i * M + j];
-    if (k == 0.0) continue;
+  for (int64_t j0 = 0; j0 < M; j0 += 256) {
+    const int64_t nj = (M - j0 < 256) ? M - j0 : 256;
+    for (int t = threadIdx.x; t < nj * 6; t += 256) xs[t] = x[j0 * 6 + t];
+    __syncthreads();
+    if (i < M) {
+      const double* Ki = K + i * M + j0;
+      for (int jj = l; jj < nj; jj += 64) {
+        const double k = Ki[jj];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += k * x[j * 6 + c];
+        for (int c = 0; c < 6; ++c) acc[c] += k * xs[jj * 6 + c];
+      }
+    }
+    __syncthreads();
   }
-  block_sum<6>(acc, sh);
-  if (threadIdx.x < 6) {
-    const int c = threadIdx.x;
-    xn[i * 6 + c] = x0[i * 6 + c] + (De ? De[i * 6 + c] : 0.0) + acc[c];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
+  if (i < M && l < 6) {
+    double v = acc[0];
+#pragma unroll
+    for (int c = 1; c < 6; ++c)
+      if (c == l) v = acc[c];
+    xn[i * 6 + l] = x0[i * 6 + l] + (De ? De[i * 6 + l] : 0.0) + sgn * v;
   }
+}
+
+// ---- BiCGSTAB on the projected electron operator: six independent columns
+// (I and J, three Cartesian components each) share every sweep.
+struct Col6 {
+  double v[6];
+};
+
+// per-column dot products of up to three pairs of [n][6] arrays; part[block][18]
+__global__ void __launch_bounds__(256) k_dots6(int64_t n, const double* __restrict__ a0,
+                                               const double* __restrict__ b0, const double* __restrict__ a1,
+                                               const double* __restrict__ b1, const double* __restrict__ a2,
+                                               const double* __restrict__ b2, double* __restrict__ part) {
+  __shared__ double sh[18 * 4];
+  double acc[18];
+#pragma unroll
+  for (int c = 0; c < 18; ++c) acc[c] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n * 6; t += (int64_t)gridDim.x * 256) {
+    const int c = (int)(t % 6);
+    const double p0 = a0[t] * b0[t];
+    const double p1 = a1 ? a1[t] * b1[t] : 0.0;
+    const double p2 = a2 ? a2[t] * b2[t] : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 6; ++cc)
+      if (cc == c) {
+        acc[cc] += p0;
+        acc[6 + cc] += p1;
+        acc[12 + cc] += p2;
+      }
+  }
+  block_sum<18>(acc, sh);
+  if (threadIdx.x < 18) part[blockIdx.x * 18 + threadIdx.x] = acc[threadIdx.x];
+}
+
+// y = a + sa * b + sc * c   (column-wise scalars; b or c may be null)
+__global__ void k_lin6(int64_t n, const double* __restrict__ a, Col6 sa, const double* __restrict__ b, Col6 sc,
+                       const double* __restrict__ c, double* __restrict__ y) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * 6) return;
+  const int col = (int)(t % 6);
+  double v = a ? a[t] : 0.0;
+  if (b) v += sa.v[col] * b[t];
+  if (c) v += sc.v[col] * c[t];
+  y[t] = v;
 }
 
 // remove the weighted mean of every energy group (no change of carrier number)
@@ -896,25 +973,124 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
                        ctx->d_state_k, th.lomf, th.nocc, we, K);
     HIPCHK(hipGetLastError());
 
+    int last_inner = 0;
+    const bool verbose = std::getenv("ELPH_VERBOSE") != nullptr;
+    Col6 one6, zero6, mone6;
+    for (int c = 0; c < 6; ++c) {
+      one6.v[c] = 1.0;
+      zero6.v[c] = 0.0;
+      mone6.v[c] = -1.0;
+    }
+    double *kr = nullptr, *krh = nullptr, *kp = nullptr, *kv = nullptr, *ks = nullptr, *kt = nullptr;
+    ALLOC(kr, M * 6 * sizeof(double));
+    ALLOC(krh, M * 6 * sizeof(double));
+    ALLOC(kp, M * 6 * sizeof(double));
+    ALLOC(kv, M * 6 * sizeof(double));
+    ALLOC(ks, M * 6 * sizeof(double));
+    ALLOC(kt, M * 6 * sizeof(double));
     auto solve_e = [&](bool drag, bool* ok) -> elph_status {
       // drive: x0 (+ electron drag from the current phonons)
       if (drag) {
         hipLaunchKernelGGL(k_drag_e<ST>, dim3((unsigned)M), dim3(256), 0, s, M, nbr, md, Bp, Bm, ctx->d_state_k,
                            th.lomf, th.nocc, we, phon, De);
       }
+      // Self-consistency of the electrons for this drive: the fixed point of
+      // x = P(b + K x) (P removes the group means), reached with BiCGSTAB on
+      // L x = P(x - K x) = P b for the six columns at once.
       *ok = false;
-      for (int it = 0; it < maxit; ++it) {
-        hipLaunchKernelGGL(k_self_sweep, dim3((unsigned)M), dim3(256), 0, s, M, K, x, x0, drag ? De : nullptr, xn);
-        hipLaunchKernelGGL(k_project, dim3((unsigned)ctx->ngroups), dim3(256), 0, s, order, goff, wff, xn);
-        Norms nr;
-        elph_status e2 = diff_norms(ctx, M, xn, x, part, hpart, &nr);
-        if (e2 != ELPH_OK) return e2;
-        std::swap(x, xn);
-        if (rel(nr.dI, nr.nI) < 0.1 * tol && rel(nr.dJ, nr.nJ) < 0.1 * tol) {
-          *ok = true;
-          break;
-        }
+      double* b = xn;  // drive b = x0 (+ drag), projected
+      hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, x0, one6,
+                         drag ? De : nullptr, zero6, (const double*)nullptr, b);
+      if (!drag) hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, x0, zero6,
+                                    (const double*)nullptr, zero6, (const double*)nullptr, b);
+      hipLaunchKernelGGL(k_project, dim3((unsigned)ctx->ngroups), dim3(256), 0, s, order, goff, wff, b);
+      auto applyL = [&](const double* in, double* out) {
+        hipLaunchKernelGGL(k_self_sweep, dim3(blocks_for(M, 4)), dim3(256), 0, s, M, K, in, in,
+                           (const double*)nullptr, -1.0, out);
+        hipLaunchKernelGGL(k_project, dim3((unsigned)ctx->ngroups), dim3(256), 0, s, order, goff, wff, out);
+      };
+      auto dots = [&](const double* a0, const double* b0, const double* a1, const double* b1, const double* a2,
+                      const double* b2, double (&out)[18]) -> elph_status {
+        const int blocks = 128;
+        hipLaunchKernelGGL(k_dots6, dim3(blocks), dim3(256), 0, s, M, a0, b0, a1, b1, a2, b2, part);
+        HIPCHK(hipMemcpyAsync(hpart.data(), part, blocks * 18 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int c = 0; c < 18; ++c) out[c] = 0.0;
+        for (int bl = 0; bl < blocks; ++bl)
+          for (int c = 0; c < 18; ++c) out[c] += hpart[bl * 18 + c];
+        return ELPH_OK;
+      };
+      // x starts from the previous solution, projected
+      hipLaunchKernelGGL(k_project, dim3((unsigned)ctx->ngroups), dim3(256), 0, s, order, goff, wff, x);
+      applyL(x, kv);
+      hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, b, mone6, kv, zero6,
+                         (const double*)nullptr, kr);  // r = b - L x
+      HIPCHK(hipMemcpyAsync(krh, kr, M * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemsetAsync(kp, 0, M * 6 * sizeof(double), s));
+      HIPCHK(hipMemsetAsync(kv, 0, M * 6 * sizeof(double), s));
+      double rho_old[6], alpha[6], omega[6], d[18];
+      bool done[6];
+      for (int c = 0; c < 6; ++c) {
+        rho_old[c] = alpha[c] = omega[c] = 1.0;
+        done[c] = false;
       }
+      elph_status e2 = dots(b, b, x, x, kr, kr, d);
+      if (e2 != ELPH_OK) return e2;
+      double bnorm[6];
+      for (int c = 0; c < 6; ++c) {
+        bnorm[c] = std::sqrt(d[c]);
+        done[c] = std::sqrt(d[12 + c]) <= 0.1 * tol * std::max(bnorm[c], 1e-300);
+      }
+      for (int it = 0; it < maxit && !std::all_of(done, done + 6, [](bool v) { return v; }); ++it) {
+        last_inner = it + 1;
+        e2 = dots(krh, kr, nullptr, nullptr, nullptr, nullptr, d);
+        if (e2 != ELPH_OK) return e2;
+        Col6 beta, mbo;
+        for (int c = 0; c < 6; ++c) {
+          const double rho = d[c];
+          if (done[c] || rho == 0.0 || omega[c] == 0.0) {
+            beta.v[c] = 0.0;
+            mbo.v[c] = 0.0;
+            rho_old[c] = rho;
+            continue;
+          }
+          beta.v[c] = (rho / rho_old[c]) * (alpha[c] / omega[c]);
+          mbo.v[c] = -beta.v[c] * omega[c];
+          rho_old[c] = rho;
+        }
+        // p = r + beta p - beta omega v
+        hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, kr, beta, kp, mbo, kv, kp);
+        applyL(kp, kv);
+        e2 = dots(krh, kv, nullptr, nullptr, nullptr, nullptr, d);
+        if (e2 != ELPH_OK) return e2;
+        Col6 ma;
+        for (int c = 0; c < 6; ++c) {
+          alpha[c] = (!done[c] && d[c] != 0.0) ? rho_old[c] / d[c] : 0.0;
+          ma.v[c] = -alpha[c];
+        }
+        // s = r - alpha v  (into ks)
+        hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, kr, ma, kv, zero6,
+                           (const double*)nullptr, ks);
+        applyL(ks, kt);
+        e2 = dots(kt, ks, kt, kt, nullptr, nullptr, d);
+        if (e2 != ELPH_OK) return e2;
+        Col6 al, om, mom;
+        for (int c = 0; c < 6; ++c) {
+          omega[c] = (!done[c] && d[6 + c] > 0.0) ? d[c] / d[6 + c] : 0.0;
+          al.v[c] = done[c] ? 0.0 : alpha[c];
+          om.v[c] = done[c] ? 0.0 : omega[c];
+          mom.v[c] = -om.v[c];
+        }
+        // x = x + alpha p + omega s ; r = s - omega t
+        hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, x, al, kp, om, ks, x);
+        hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, ks, mom, kt, zero6,
+                           (const double*)nullptr, kr);
+        e2 = dots(kr, kr, nullptr, nullptr, nullptr, nullptr, d);
+        if (e2 != ELPH_OK) return e2;
+        for (int c = 0; c < 6; ++c)
+          if (!done[c] && std::sqrt(d[c]) <= 0.1 * tol * std::max(bnorm[c], 1e-300)) done[c] = true;
+      }
+      *ok = std::all_of(done, done + 6, [](bool v) { return v; });
       return ELPH_OK;
     };
 
@@ -935,8 +1111,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
         st = diff_norms(ctx, M, x, xprev, part, hpart, &ne);
         if (st != ELPH_OK) return st;
         // phonon drag from the new electrons
-        hipLaunchKernelGGL((k_q_gather<ST, 6>), dim3(blocks_for(ctx->nk, 4)), dim3(256), 0, s, ctx->nk, M, nbr,
-                           md, Bp, ctx->d_kept, ctx->nkept, ctx->d_kidx, ctx->d_soff, th.f, th.omf, x, acc);
+        launch_q_gather<ST, 6>(ctx, Bp, th.f, th.omf, x, acc);
         hipLaunchKernelGGL(k_ph_drag_finalize, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, acc, phon0,
                            ctx->d_hw, th.nocc, wp, ctx->omega_min, phonn);
         Norms np_;
@@ -946,6 +1121,9 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
         used = it;
         const double r = std::max(std::max(rel(ne.dI, ne.nI), rel(ne.dJ, ne.nJ)),
                                   std::max(rel(np_.dI, np_.nI), rel(np_.dJ, np_.nJ)));
+        if (verbose)
+          std::fprintf(stderr, "elph_iterate: outer %d inner %d res I %.3e J %.3e F %.3e G %.3e\n", it, last_inner,
+                       rel(ne.dI, ne.nI), rel(ne.dJ, ne.nJ), rel(np_.dI, np_.nI), rel(np_.dJ, np_.nJ));
         if (level == ELPH_LEVEL_PARTIAL) {
           converged = ok;
           break;
@@ -958,6 +1136,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
     }
     dev_free(ctx, order);
     dev_free(ctx, goff);
+    for (double* pbuf : {kr, krh, kp, kv, ks, kt}) dev_free(ctx, pbuf);
   }
 
   // outputs

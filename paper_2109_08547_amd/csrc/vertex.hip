@@ -43,6 +43,7 @@ struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int lk, int r) { return lk + 4 * r; }
+  static constexpr bool kFold = false;
 };
 
 template <>
@@ -53,6 +54,7 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int lk, int r) { return 4 * lk + r; }
+  static constexpr bool kFold = true;
 };
 
 template <typename T>
@@ -132,17 +134,34 @@ __global__ void k_permute_g(int nre, int nrp, int nbr, int nb, int64_t ke, const
 // step 1: C[i][col] = sum_k Ae[i][k] gR[col][k]; epilogue writes B2 with the
 // e^{-2 pi i k_i . Rp} factor.  Block 2x2 waves, wave tile 32 x 32.
 
+// Step-1 contraction of one material (operands and sizes).
 template <typename T>
-__global__ void __launch_bounds__(256) k_step1(int64_t m_pad, int64_t ncol, int64_t ke, const T* __restrict__ Ae,
-                                               const T* __restrict__ gR, int nrp, int nb, int nbr, int64_t kp,
-                                               int64_t nstates, const int32_t* __restrict__ st_kidx,
-                                               const cd* __restrict__ Ep, T* __restrict__ B2) {
+struct S1Desc {
+  int64_t m_pad, ncol, ke, kp, nstates;
+  const T* Ae;
+  const T* gR;
+  T* B2;
+  int nrp, nb, nbr;
+  const int32_t* st_kidx;
+  const cd* Ep;
+};
+
+// One 64 x 64 output tile (block column bx, block row by) of step 1.
+template <typename T>
+__device__ __forceinline__ void step1_tile(const S1Desc<T>& d, int64_t bx, int64_t by) {
   typedef Mfma<T> MM;
   typedef typename MM::acc_t acc_t;
+  const int64_t ncol = d.ncol, ke = d.ke, kp = d.kp, nstates = d.nstates;
+  const T* __restrict__ Ae = d.Ae;
+  const T* __restrict__ gR = d.gR;
+  T* __restrict__ B2 = d.B2;
+  const int nrp = d.nrp, nb = d.nb, nbr = d.nbr;
+  const int32_t* __restrict__ st_kidx = d.st_kidx;
+  const cd* __restrict__ Ep = d.Ep;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t m0 = (int64_t)blockIdx.y * 64 + (wave >> 1) * 32;
-  const int64_t n0 = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
+  const int64_t m0 = by * 64 + (wave >> 1) * 32;
+  const int64_t n0 = bx * 64 + (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
 
   const T* pa[2];
@@ -155,29 +174,63 @@ __global__ void __launch_bounds__(256) k_step1(int64_t m_pad, int64_t ncol, int6
     pb[t] = gR + 2 * (nrow * ke + lk);
   }
   acc_t cr[2][2], ci[2][2];
+  // FP64 running sums: the FP32 form folds its MFMA accumulators in every 16 k
+  // so that rounding is relative to a 16-term partial, not the whole sum
+  double fr[2][2][4], fi[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       cr[a][b] = MM::zero();
       ci[a][b] = MM::zero();
-    }
-  for (int64_t k = 0; k < ke; k += 4) {
-    Cplx<T> fa[2], fb[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      fa[t] = ldc(pa[t] + 2 * k);
-      fb[t] = ldc(pb[t] + 2 * k);
+      for (int r = 0; r < 4; ++r) fr[a][b][r] = fi[a][b][r] = 0.0;
     }
+  for (int64_t k0 = 0; k0 < ke; k0 += 16) {
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int64_t k = k0 + kk;
+      Cplx<T> fa[2], fb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        fa[t] = ldc(pa[t] + 2 * k);
+        fb[t] = ldc(pb[t] + 2 * k);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = MM::mma(fa[a].x, fb[b].x, cr[a][b]);
+          cr[a][b] = MM::mma(-fa[a].y, fb[b].y, cr[a][b]);
+          ci[a][b] = MM::mma(fa[a].x, fb[b].y, ci[a][b]);
+          ci[a][b] = MM::mma(fa[a].y, fb[b].x, ci[a][b]);
+        }
+    }
+    if constexpr (MM::kFold) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            fr[a][b][r] += (double)cr[a][b][r];
+            fi[a][b][r] += (double)ci[a][b][r];
+          }
+          cr[a][b] = MM::zero();
+          ci[a][b] = MM::zero();
+        }
+    }
+  }
+  if constexpr (!MM::kFold) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cr[a][b] = MM::mma(fa[a].x, fb[b].x, cr[a][b]);
-        cr[a][b] = MM::mma(-fa[a].y, fb[b].y, cr[a][b]);
-        ci[a][b] = MM::mma(fa[a].x, fb[b].y, ci[a][b]);
-        ci[a][b] = MM::mma(fa[a].y, fb[b].x, ci[a][b]);
-      }
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          fr[a][b][r] = (double)cr[a][b][r];
+          fi[a][b][r] = (double)ci[a][b][r];
+        }
   }
   // epilogue
   const int64_t per_x = (int64_t)nrp * nb;
@@ -194,11 +247,16 @@ __global__ void __launch_bounds__(256) k_step1(int64_t m_pad, int64_t ncol, int6
         const int64_t rem = col % per_x;
         const int rp = (int)(rem / nb);
         const cd ph = Ep[(int64_t)st_kidx[i] * nrp + rp];
-        const cd z = cmulc(cmake((double)cr[a][b][r], (double)ci[a][b][r]), ph);  // * conj(ph)
+        const cd z = cmulc(cmake(fr[a][b][r], fi[a][b][r]), ph);  // * conj(ph)
         T* dst = B2 + 2 * ((i * nbr + x) * kp + rem);
         dst[0] = (T)z.x;
         dst[1] = (T)z.y;
       }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_step1(S1Desc<T> d) {
+  step1_tile<T>(d, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -237,27 +295,50 @@ __device__ inline int64_t q_of(int64_t kj, int64_t ki, int n0, int n1, int n2) {
   return ((int64_t)a * n1 + b) * n2 + c;
 }
 
+// Step-2 contraction of one material with its epilogue parameters.
+template <typename T>
+struct S2Desc {
+  int64_t kp;
+  const T* Ap;
+  const T* B2;
+  void* Bp;
+  void* Bm;
+  EpiParams ep;
+};
+
+// One 32 x 32 (j, i) tile (block row bx over j, block column by over i).
 template <typename T, typename ST, int NX>
-__global__ void __launch_bounds__(256) k_step2(int64_t kp, const T* __restrict__ Ap, const T* __restrict__ B2,
-                                               EpiParams ep, ST* __restrict__ Bp, ST* __restrict__ Bm) {
+__device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64_t by, double (*red)[16]) {
   typedef Mfma<T> MM;
   typedef typename MM::acc_t acc_t;
-  __shared__ double red[4][16];
+  const int64_t kp = d.kp;
+  const T* __restrict__ Ap = d.Ap;
+  const T* __restrict__ B2 = d.B2;
+  ST* __restrict__ Bp = (ST*)d.Bp;
+  ST* __restrict__ Bm = (ST*)d.Bm;
+  const EpiParams& ep = d.ep;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t j0 = (int64_t)blockIdx.x * 32 + (wave >> 1) * 16;
-  const int64_t i0 = (int64_t)blockIdx.y * 32 + (wave & 1) * 16;
+  const int64_t j0 = bx * 32 + (wave >> 1) * 16;
+  const int64_t i0 = by * 32 + (wave & 1) * 16;
   const int lr = lane & 15, lk = lane >> 4;
 
   const T* pa = Ap + 2 * ((j0 + lr) * kp + lk);
   const T* pb = B2 + 2 * (((i0 + lr) * NX) * kp + lk);
   acc_t cr[NX], ci[NX];
+  double fr[MM::kFold ? NX : 1][4], fi[MM::kFold ? NX : 1][4];
 #pragma unroll
   for (int x = 0; x < NX; ++x) {
     cr[x] = MM::zero();
     ci[x] = MM::zero();
   }
-  for (int64_t k = 0; k < kp; k += 4) {
+  if constexpr (MM::kFold) {
+#pragma unroll
+    for (int x = 0; x < NX; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fr[x][r] = fi[x][r] = 0.0;
+  }
+  auto kstep = [&](int64_t k) {
     const Cplx<T> fa = ldc(pa + 2 * k);
     const T nai = -fa.y;
 #pragma unroll
@@ -268,8 +349,26 @@ __global__ void __launch_bounds__(256) k_step2(int64_t kp, const T* __restrict__
       ci[x] = MM::mma(fa.x, fb.y, ci[x]);
       ci[x] = MM::mma(fa.y, fb.x, ci[x]);
     }
+  };
+  if constexpr (!MM::kFold) {
+    for (int64_t k = 0; k < kp; k += 4) kstep(k);
   }
-
+  for (int64_t k0 = 0; MM::kFold && k0 < kp; k0 += 16) {
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) kstep(k0 + kk);
+    if constexpr (MM::kFold) {
+#pragma unroll
+      for (int x = 0; x < NX; ++x) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          fr[x][r] += (double)cr[x][r];
+          fi[x][r] += (double)ci[x][r];
+        }
+        cr[x] = MM::zero();
+        ci[x] = MM::zero();
+      }
+    }
+  }
   // epilogue: lane owns rows j = j0 + MM::row(lk, r), column i = i0 + lr
   const int64_t i = i0 + lr;
   const bool want_rates = ep.we_part != nullptr;
@@ -294,7 +393,14 @@ __global__ void __launch_bounds__(256) k_step2(int64_t kp, const T* __restrict__
 #pragma unroll
         for (int x = 0; x < NX; ++x) {
           const cd l = L[x * NX + s];
-          const double ar = (double)cr[x][r], ai = (double)ci[x][r];
+          double ar, ai;
+          if constexpr (MM::kFold) {
+            ar = fr[x][r];
+            ai = fi[x][r];
+          } else {
+            ar = (double)cr[x][r];
+            ai = (double)ci[x][r];
+          }
           gr += l.x * ar - l.y * ai;
           gi += l.x * ai + l.y * ar;
         }
@@ -323,9 +429,15 @@ __global__ void __launch_bounds__(256) k_step2(int64_t kp, const T* __restrict__
     __syncthreads();
     if (wave < 2 && lk == 0) {
       const double tot = red[wave][lr] + red[wave + 2][lr];
-      if (i < ep.nstates) ep.we_part[(int64_t)blockIdx.x * ep.m_pad + i] = tot;
+      if (i < ep.nstates) ep.we_part[bx * ep.m_pad + i] = tot;
     }
   }
+}
+
+template <typename T, typename ST, int NX>
+__global__ void __launch_bounds__(256) k_step2(S2Desc<T> d) {
+  __shared__ double red[4][16];
+  step2_tile<T, ST, NX>(d, blockIdx.x, blockIdx.y, red);
 }
 
 // W_e[i] = sum over j-tiles of the partials, in tile order
@@ -400,19 +512,42 @@ elph_status build_operands(elph_ctx ctx) {
 }
 
 template <typename T>
+S1Desc<T> step1_desc(elph_ctx ctx) {
+  S1Desc<T> d;
+  d.m_pad = ctx->m_pad;
+  d.ncol = (int64_t)ctx->nbr * ctx->nrp * ctx->nb;
+  d.ke = ctx->ke;
+  d.kp = ctx->kp;
+  d.nstates = ctx->nstates;
+  d.Ae = (const T*)ctx->d_Ae;
+  d.gR = (const T*)ctx->d_gR;
+  d.B2 = (T*)ctx->d_B2;
+  d.nrp = ctx->nrp;
+  d.nb = ctx->nb;
+  d.nbr = ctx->nbr;
+  d.st_kidx = ctx->d_state_kidx;
+  d.Ep = (const cd*)ctx->d_Ep;
+  return d;
+}
+
+template <typename T>
 static void launch_step1_t(elph_ctx ctx) {
-  const int64_t ncol = (int64_t)ctx->nbr * ctx->nrp * ctx->nb;
-  dim3 grid((unsigned)((ncol + 63) / 64), (unsigned)(ctx->m_pad / 64));
-  hipLaunchKernelGGL(k_step1<T>, grid, dim3(256), 0, ctx->stream, ctx->m_pad, ncol, ctx->ke, (const T*)ctx->d_Ae,
-                     (const T*)ctx->d_gR, ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, ctx->nstates, ctx->d_state_kidx,
-                     (const cd*)ctx->d_Ep, (T*)ctx->d_B2);
+  const S1Desc<T> d = step1_desc<T>(ctx);
+  dim3 grid((unsigned)((d.ncol + 63) / 64), (unsigned)(ctx->m_pad / 64));
+  hipLaunchKernelGGL(k_step1<T>, grid, dim3(256), 0, ctx->stream, d);
 }
 
 template <typename T, typename ST, int NX>
 static void launch_step2_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm) {
+  S2Desc<T> d;
+  d.kp = ctx->kp;
+  d.Ap = (const T*)ctx->d_Ap;
+  d.B2 = (const T*)ctx->d_B2;
+  d.Bp = Bp;
+  d.Bm = Bm;
+  d.ep = ep;
   dim3 grid((unsigned)(ctx->m_pad / 32), (unsigned)(ctx->m_pad / 32));
-  hipLaunchKernelGGL((k_step2<T, ST, NX>), grid, dim3(256), 0, ctx->stream, ctx->kp, (const T*)ctx->d_Ap,
-                     (const T*)ctx->d_B2, ep, (ST*)Bp, (ST*)Bm);
+  hipLaunchKernelGGL((k_step2<T, ST, NX>), grid, dim3(256), 0, ctx->stream, d);
 }
 
 template <typename T, typename ST>

@@ -65,13 +65,19 @@ def _gap_delta(hk, onsite, s_H, nb):
     return x1
 
 
-def calibrate(name):
+def calibrate(name, sub=1):
+    """``sub`` > 1 bisects s_H on every sub-th mesh point per axis (the final
+    gap, mu and kept fraction are taken on the full mesh)."""
     t0 = time.time()
     cfg = synth.config(name, calibrated=False)
     nb = cfg["nb"]
     kfrac = oracle.mesh_points(cfg["mesh"])
     mat, hk = _raw_hk(cfg, kfrac)
     onsite = np.array([-1.0 if b < nb // 2 else 1.0 for b in range(nb)])
+    n = cfg["mesh"]
+    ijk = np.rint(kfrac * n).astype(int)
+    coarse = np.all(ijk % sub == 0, axis=1)
+    hk_full = hk
 
     # force-constant scale from the raw Gram matrices
     lam_max = 0.0
@@ -80,7 +86,7 @@ def calibrate(name):
         lam_max = max(lam_max, float(np.linalg.eigvalsh(d).max()))
     c_D = HW_MAX ** 2 / (oracle.C_PHONON * lam_max)
 
-    def solve(s_H):
+    def solve(s_H, hk=hk_full):
         if "delta_fixed" in cfg:
             delta = float(cfg["delta_fixed"])
         else:
@@ -103,9 +109,10 @@ def calibrate(name):
         target = cfg["kept_target"]
         lo, hi = np.log(0.005), np.log(2.0)
         # kept fraction falls as s_H grows (more dispersive bands)
+        hk_c = hk_full[coarse]
         for _ in range(40):
             mid = 0.5 * (lo + hi)
-            _, _, kept, _, _ = solve(np.exp(mid))
+            _, _, kept, _, _ = solve(np.exp(mid), hk_c)
             if kept > target:
                 lo = mid
             else:
@@ -123,16 +130,22 @@ def calibrate(name):
     return rec
 
 
-def main(names):
+def main(names, sub=1):
     data = {}
     if os.path.exists(OUT):
         with open(OUT) as fh:
             data = json.load(fh)
     for name in names:
-        data[name] = calibrate(name)
+        data[name] = calibrate(name, sub)
         with open(OUT, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["tiny3", "tiny4", "metal6", "plain8", "mixed48"])
+    args = sys.argv[1:]
+    sub = 1
+    if args and args[0].startswith("--sub="):
+        sub = int(args.pop(0).split("=")[1])
+    if args == ["batch"]:
+        args = ["batch%02d" % j for j in range(32)]
+    main(args or ["tiny3", "tiny4", "metal6", "plain8", "mixed48"], sub)
