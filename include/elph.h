@@ -136,10 +136,14 @@ void elph_destroy(elph_ctx ctx);
  * errors of elph_create. */
 const char* elph_last_error(elph_ctx ctx);
 
-/* Drop every derived table, contraction operand and the vertex store; the
- * next call rebuilds what it needs (inputs stay on the device).  Used to
- * time the whole path and to release memory. */
-elph_status elph_reset(elph_ctx ctx);
+/* what = ELPH_RESET_ALL: drop every derived table, contraction operand and
+ * the vertex store (releases their memory); ELPH_RESET_STORE: only mark the
+ * vertex store stale so that the next rate call recomputes the vertices.
+ * The next call rebuilds what it needs (inputs stay on the device).  Used to
+ * time the path and to release memory.  Do not reset a context that belongs
+ * to a live batch. */
+enum { ELPH_RESET_ALL = 0, ELPH_RESET_STORE = 1 };
+elph_status elph_reset(elph_ctx ctx, int32_t what);
 
 /* Kernel timing with HIP events recorded on the context's stream around
  * the table build, the step-1 contraction, the step-2 contraction (fused with
@@ -204,6 +208,39 @@ elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, double* W_ph
 elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph_ext, int32_t level,
                          double tol, int32_t maxit, double* I, double* J, double* F,
                          double* G, double* tensors, int32_t* iters, double* ko_residual);
+
+/* ---- Batches: many independent materials evaluated together ------------
+ * The vertex contractions of all materials run in persistent launches that
+ * pull (material, tile) work items from a queue, longest contraction first
+ * (one step-1 launch, one step-2 launch per branch count), and the whole
+ * per-temperature sequence can be captured in a HIP graph and replayed.
+ * Results are identical to elph_scatt_rates on each context.  Contexts must
+ * share one precision form; while a batch call runs, their work goes to the
+ * batch's own stream.  The batch does not own the contexts (destroy the
+ * batch first). */
+typedef struct elph_batch_s* elph_batch;
+
+/* n >= 1 contexts (host array of handles). */
+elph_status elph_batch_create(int32_t n, const elph_ctx* ctxs, elph_batch* out);
+void elph_batch_destroy(elph_batch b);
+/* Message of the last failing batch call; b may be NULL for create errors. */
+const char* elph_batch_last_error(elph_batch b);
+
+/* Eqs. 21 and 25 for every material: W_e[m] [nstates_m], W_ph[m] [nk_m][nbr_m]
+ * are device pointers in host arrays of length n (either array, or any entry,
+ * may be NULL).  use_graph != 0 captures the sequence in a HIP graph on the
+ * first call for a given temperature and set of output pointers and replays
+ * it afterwards.  Synchronises the batch stream.  The vertex stores of all
+ * contexts are left valid. */
+elph_status elph_batch_scatt_rates(elph_batch b, double T_K, double* const* W_e, double* const* W_ph,
+                                   int32_t use_graph);
+
+/* Autotuner: times each persistent-launch variant (blocks per compute unit
+ * 1, 2, 4, 8 x work items in cost order or in natural order) on this batch,
+ * keeps the fastest, and caches it for batches of the same shape.
+ * choice (host, may be NULL) receives [blocks_per_cu, cost_ordered];
+ * best_ms (host, may be NULL) the per-evaluation time of the winner. */
+elph_status elph_batch_tune(elph_batch b, double T_K, int32_t* choice, double* best_ms);
 
 #ifdef __cplusplus
 }

@@ -7,4 +7,5 @@ from . import elph  # noqa: F401
 from .elph import (  # noqa: F401
     elph_create, elph_destroy, elph_reset, elph_timing, elph_sizes, elph_tables, elph_interp_g,
     elph_transition_probs, elph_scatt_rates, elph_iterate, ElphError,
+    elph_batch_create, elph_batch_destroy, elph_batch_scatt_rates, elph_batch_tune,
 )

@@ -281,10 +281,15 @@ static void drop_derived(elph_ctx ctx) {
   ctx->ngroups = 0;
 }
 
-extern "C" elph_status elph_reset(elph_ctx ctx) {
+extern "C" elph_status elph_reset(elph_ctx ctx, int32_t what) {
   CHECK_CTX(ctx);
+  if (what != ELPH_RESET_ALL && what != ELPH_RESET_STORE) {
+    ctx->err = "unknown reset mode";
+    return ELPH_EINVAL;
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  drop_derived(ctx);
+  if (what == ELPH_RESET_ALL) drop_derived(ctx);
+  else ctx->store_ready = false;
   return ELPH_OK;
 }
 
@@ -465,5 +470,85 @@ extern "C" elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph
   st = iterate(ctx, T_K, W_ph_ext, level, tol, maxit, I, J, F, G, tensors, &it, ko_residual);
   mark(ctx, 7);
   if (iters) *iters = it;
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+
+struct elph_batch_s {
+  BatchImpl* impl = nullptr;
+  std::string err;
+};
+
+static thread_local std::string g_batch_err;
+
+extern "C" elph_status elph_batch_create(int32_t n, const elph_ctx* ctxs, elph_batch* out) {
+  if (!out || n < 1 || !ctxs) {
+    g_batch_err = "invalid arguments";
+    return ELPH_EINVAL;
+  }
+  *out = nullptr;
+  std::vector<elph_ctx> v(ctxs, ctxs + n);
+  for (elph_ctx c : v)
+    if (!c) {
+      g_batch_err = "null context";
+      return ELPH_EINVAL;
+    }
+  std::string err;
+  BatchImpl* impl = batch_new(v, &err);
+  if (!impl) {
+    g_batch_err = err;
+    return ELPH_EINVAL;
+  }
+  elph_batch b = new (std::nothrow) elph_batch_s();
+  if (!b) {
+    batch_free(impl);
+    g_batch_err = "host allocation failed";
+    return ELPH_ENOMEM;
+  }
+  b->impl = impl;
+  *out = b;
+  return ELPH_OK;
+}
+
+extern "C" void elph_batch_destroy(elph_batch b) {
+  if (!b) return;
+  batch_free(b->impl);
+  delete b;
+}
+
+extern "C" const char* elph_batch_last_error(elph_batch b) {
+  if (!b) return g_batch_err.c_str();
+  return b->err.c_str();
+}
+
+extern "C" elph_status elph_batch_scatt_rates(elph_batch b, double T_K, double* const* W_e, double* const* W_ph,
+                                              int32_t use_graph) {
+  if (!b) return ELPH_EINVAL;
+  b->err.clear();
+  if (!(T_K > 0) || !std::isfinite(T_K)) {
+    b->err = "temperature must be positive";
+    return ELPH_EINVAL;
+  }
+  elph_status st = batch_rates(b->impl, T_K, W_e, W_ph, use_graph != 0);
+  if (st != ELPH_OK) b->err = batch_error(b->impl);
+  return st;
+}
+
+extern "C" elph_status elph_batch_tune(elph_batch b, double T_K, int32_t* choice, double* best_ms) {
+  if (!b) return ELPH_EINVAL;
+  b->err.clear();
+  if (!(T_K > 0) || !std::isfinite(T_K)) {
+    b->err = "temperature must be positive";
+    return ELPH_EINVAL;
+  }
+  int ch[2] = {0, 0};
+  elph_status st = batch_tune(b->impl, T_K, ch, best_ms);
+  if (st != ELPH_OK) b->err = batch_error(b->impl);
+  if (choice) {
+    choice[0] = ch[0];
+    choice[1] = ch[1];
+  }
   return st;
 }

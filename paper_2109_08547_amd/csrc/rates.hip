@@ -75,18 +75,30 @@ __global__ void k_bose(int64_t n, const double* __restrict__ hw, double kT, doub
   nocc[t] = (w >= omega_min) ? 1.0 / expm1(w / kT) : 0.0;
 }
 
-elph_status make_thermal(elph_ctx ctx, double T, Thermal* th) {
+elph_status alloc_thermal(elph_ctx ctx, Thermal* th) {
   const int64_t M = ctx->nstates;
   const int64_t nm = ctx->nk * ctx->nbr;
   ALLOC(th->f, M * sizeof(double));
   ALLOC(th->omf, M * sizeof(double));
   ALLOC(th->lomf, M * sizeof(double));
   ALLOC(th->nocc, nm * sizeof(double));
+  return ELPH_OK;
+}
+
+void fill_thermal(elph_ctx ctx, double T, const Thermal& th, hipStream_t s) {
+  const int64_t M = ctx->nstates;
+  const int64_t nm = ctx->nk * ctx->nbr;
   const double kT = kBoltzEVK * T;
-  hipLaunchKernelGGL(k_thermal_states, dim3(blocks_for(M, 256)), dim3(256), 0, ctx->stream, M, ctx->d_eps, ctx->mu,
-                     kT, th->f, th->omf, th->lomf);
-  hipLaunchKernelGGL(k_bose, dim3(blocks_for(nm, 256)), dim3(256), 0, ctx->stream, nm, ctx->d_hw, kT,
-                     ctx->omega_min, th->nocc);
+  hipLaunchKernelGGL(k_thermal_states, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, ctx->d_eps, ctx->mu, kT, th.f,
+                     th.omf, th.lomf);
+  hipLaunchKernelGGL(k_bose, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, ctx->d_hw, kT, ctx->omega_min,
+                     th.nocc);
+}
+
+elph_status make_thermal(elph_ctx ctx, double T, Thermal* th) {
+  elph_status st = alloc_thermal(ctx, th);
+  if (st != ELPH_OK) return st;
+  fill_thermal(ctx, T, *th, ctx->stream);
   HIPCHK(hipGetLastError());
   return ELPH_OK;
 }
@@ -259,8 +271,8 @@ __global__ void __launch_bounds__(256) k_q_gather(int64_t nq, int64_t M, int nbr
 }
 
 template <typename ST, int NV>
-static void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x,
-                            double* acc) {
+void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x,
+                     double* acc) {
   const dim3 grid(blocks_for(ctx->nk, 4)), blk(256);
   const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
 #define QG(NXV)                                                                                           \
@@ -286,6 +298,11 @@ __global__ void k_wph_finalize(int64_t n, const double* __restrict__ acc, const 
 }
 
 static MeshDims mdims(elph_ctx ctx) { return MeshDims{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]}; }
+
+template void launch_q_gather<float, 1>(elph_ctx, const float*, const double*, const double*, const double*,
+                                       double*);
+template void launch_q_gather<double, 1>(elph_ctx, const double*, const double*, const double*, const double*,
+                                        double*);
 
 elph_status ensure_store(elph_ctx ctx) {
   if (ctx->store_ready) return ELPH_OK;

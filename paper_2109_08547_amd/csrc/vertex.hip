@@ -24,6 +24,11 @@
 #include "vertex.h"
 #include "tables.h"
 
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
 namespace elph {
 
 // ---------------------------------------------------------------------------
@@ -451,6 +456,45 @@ __global__ void k_reduce_we(const double* __restrict__ part, int64_t ntiles, int
 }
 
 // ---------------------------------------------------------------------------
+// persistent launches over a work queue of (material, tile) items
+
+__global__ void k_zero_ints(int* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_step1_persist(const S1Desc<T>* __restrict__ descs,
+                                                       const int4* __restrict__ items, int nitems, int* counter) {
+  __shared__ int item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = item_sh;
+    __syncthreads();
+    if (it >= nitems) break;  // uniform over the block; every block reaches it
+    const int4 w = items[it];
+    step1_tile<T>(descs[w.x], w.y, w.z);
+  }
+}
+
+template <typename T, typename ST, int NX>
+__global__ void __launch_bounds__(256) k_step2_persist(const S2Desc<T>* __restrict__ descs,
+                                                       const int4* __restrict__ items, int nitems, int* counter) {
+  __shared__ double red[4][16];
+  __shared__ int item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = item_sh;
+    __syncthreads();
+    if (it >= nitems) break;
+    const int4 w = items[it];
+    step2_tile<T, ST, NX>(descs[w.x], w.y, w.z, red);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 
 template <typename T>
@@ -563,14 +607,7 @@ static elph_status launch_step2_t(elph_ctx ctx, const EpiParams& ep, void* Bp, v
   return ELPH_OK;
 }
 
-// Run both contractions and the epilogue.  Bp/Bm receive the term store
-// (double when store_f64, else float).  If th != nullptr the rates at that
-// temperature are accumulated into we_out [nstates] and wph_acc [nk][nbr]
-// (wph_acc must be zeroed by the caller).
-elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const Thermal* th, double* we_out,
-                       double* wph_acc) {
-  elph_status st = build_operands(ctx);
-  if (st != ELPH_OK) return st;
+static EpiParams epi_params(elph_ctx ctx) {
   EpiParams ep;
   ep.nstates = ctx->nstates;
   ep.nbr = ctx->nbr;
@@ -585,29 +622,46 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
   ep.hw = ctx->d_hw;
   ep.Lq = (const cd*)ctx->d_Lq;
   ep.m_pad = ctx->m_pad;
+  ep.lomf = ep.fstate = ep.omf = ep.nocc = nullptr;
+  ep.we_part = nullptr;
+  ep.wph_acc = nullptr;
+  return ep;
+}
+
+static elph_status ensure_we_part(elph_ctx ctx) {
+  const int64_t ntiles = ctx->m_pad / 32;
+  if (ctx->we_part_len >= ntiles * ctx->m_pad) return ELPH_OK;
+  void* p;
+  if (dev_alloc(ctx, &p, (size_t)ntiles * ctx->m_pad * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "device allocation of rate partials failed";
+    return ELPH_ENOMEM;
+  }
+  if (ctx->d_we_part) dev_free(ctx, ctx->d_we_part);
+  ctx->d_we_part = (double*)p;
+  ctx->we_part_len = ntiles * ctx->m_pad;
+  return ELPH_OK;
+}
+
+// Run both contractions and the epilogue.  Bp/Bm receive the term store
+// (double when store_f64, else float).  If th != nullptr the rates at that
+// temperature are accumulated into we_out [nstates] and wph_acc [nk][nbr]
+// (wph_acc must be zeroed by the caller).
+elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const Thermal* th, double* we_out,
+                       double* wph_acc) {
+  elph_status st = build_operands(ctx);
+  if (st != ELPH_OK) return st;
+  EpiParams ep = epi_params(ctx);
   const int64_t ntiles = ctx->m_pad / 32;
   if (th) {
-    if (ctx->we_part_len < ntiles * ctx->m_pad) {
-      void* p;
-      if (dev_alloc(ctx, &p, (size_t)ntiles * ctx->m_pad * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        ctx->err = "device allocation of rate partials failed";
-        return ELPH_ENOMEM;
-      }
-      if (ctx->d_we_part) dev_free(ctx, ctx->d_we_part);
-      ctx->d_we_part = (double*)p;
-      ctx->we_part_len = ntiles * ctx->m_pad;
-    }
+    st = ensure_we_part(ctx);
+    if (st != ELPH_OK) return st;
     ep.lomf = th->lomf;
     ep.fstate = th->f;
     ep.omf = th->omf;
     ep.nocc = th->nocc;
     ep.we_part = ctx->d_we_part;
     ep.wph_acc = wph_acc;
-  } else {
-    ep.lomf = ep.fstate = ep.omf = ep.nocc = nullptr;
-    ep.we_part = nullptr;
-    ep.wph_acc = nullptr;
   }
   if (ctx->precision == ELPH_FP64) {
     mark(ctx, 2);
@@ -637,5 +691,390 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
   }
   return ELPH_OK;
 }
+
+
+// ---------------------------------------------------------------------------
+// Batches of materials: one persistent step-1 launch over every material's
+// tiles and one persistent step-2 launch per branch count, items ordered
+// longest contraction first; the whole per-temperature sequence can be
+// captured in a HIP graph and replayed.
+
+struct BatchImpl {
+  struct Cls {
+    int nx = 0;
+    std::vector<int> mats;          // material of each descriptor slot
+    void* d_desc = nullptr;         // S2Desc<T>[mats.size()]
+    int4* d_items = nullptr;
+    std::vector<int4> sorted, natural;
+  };
+  std::vector<elph_ctx> ctx;
+  std::vector<hipStream_t> saved_streams;
+  hipStream_t stream = nullptr;
+  int precision = ELPH_FP32;
+  bool prepared = false;
+  std::vector<Thermal> th;
+  std::vector<double*> acc, we_tmp;
+  void* d_s1desc = nullptr;
+  int4* d_s1items = nullptr;
+  std::vector<int4> s1_sorted, s1_natural;
+  std::vector<Cls> cls;
+  int* d_counters = nullptr;
+  int bpc = 2;
+  bool sorted = true;
+  bool tuned = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double gT = -1.0;
+  std::vector<double*> gptrs;
+  std::vector<void*> allocs;
+  std::string err;
+  int ncu = 256;
+};
+
+static std::map<std::string, std::pair<int, bool>>& tune_cache() {
+  static std::map<std::string, std::pair<int, bool>> c;
+  return c;
+}
+
+#define BCHK(x)                                                          \
+  do {                                                                   \
+    hipError_t e_ = (x);                                                 \
+    if (e_ != hipSuccess) {                                              \
+      b->err = std::string("HIP error ") + hipGetErrorString(e_) + " at " + __FILE__ + ":" + std::to_string(__LINE__); \
+      return ELPH_EHIP;                                                  \
+    }                                                                    \
+  } while (0)
+
+static hipError_t balloc(BatchImpl* b, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 1);
+  if (e == hipSuccess) b->allocs.push_back(*p);
+  return e;
+}
+
+struct StreamSwap {  // run the contexts' launches on the batch stream
+  BatchImpl* b;
+  explicit StreamSwap(BatchImpl* bb) : b(bb) {
+    for (size_t m = 0; m < b->ctx.size(); ++m) b->ctx[m]->stream = b->stream;
+  }
+  ~StreamSwap() {
+    for (size_t m = 0; m < b->ctx.size(); ++m) b->ctx[m]->stream = b->saved_streams[m];
+  }
+};
+
+static std::string batch_signature(BatchImpl* b) {
+  std::string sig = std::to_string(b->precision);
+  for (elph_ctx c : b->ctx)
+    sig += ":" + std::to_string(c->nstates) + "," + std::to_string(c->nbr) + "," + std::to_string(c->ke) + "," +
+           std::to_string(c->kp);
+  return sig;
+}
+
+template <typename T>
+static elph_status batch_prepare_t(BatchImpl* b) {
+  const int n = (int)b->ctx.size();
+  StreamSwap sw(b);
+  std::vector<S1Desc<T>> s1(n);
+  std::map<int, int> cls_of_nx;
+  for (int m = 0; m < n; ++m) {
+    elph_ctx c = b->ctx[m];
+    elph_status st = build_tables(c);
+    if (st == ELPH_OK) st = build_operands(c);
+    if (st == ELPH_OK) st = ensure_we_part(c);
+    if (st != ELPH_OK) {
+      b->err = "material " + std::to_string(m) + ": " + c->err;
+      return st;
+    }
+    const size_t nt = (size_t)c->nstates * c->nstates * c->nbr;
+    const size_t esz = sizeof(T);
+    if (!c->d_Bp) {
+      if (dev_alloc(c, &c->d_Bp, nt * esz) != hipSuccess || dev_alloc(c, &c->d_Bm, nt * esz) != hipSuccess) {
+        (void)hipGetLastError();
+        b->err = "material " + std::to_string(m) + ": vertex store allocation failed";
+        return ELPH_ENOMEM;
+      }
+    }
+    c->store_f32 = sizeof(T) == 4;
+    Thermal t;
+    st = alloc_thermal(c, &t);
+    if (st != ELPH_OK) {
+      b->err = c->err;
+      return st;
+    }
+    b->th.push_back(t);
+    void *a = nullptr, *w = nullptr;
+    if (dev_alloc(c, &a, (size_t)c->nk * c->nbr * sizeof(double)) != hipSuccess ||
+        dev_alloc(c, &w, (size_t)c->nstates * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      b->err = "scratch allocation failed";
+      return ELPH_ENOMEM;
+    }
+    b->acc.push_back((double*)a);
+    b->we_tmp.push_back((double*)w);
+    s1[m] = step1_desc<T>(c);
+    if (!cls_of_nx.count(c->nbr)) {
+      cls_of_nx[c->nbr] = (int)b->cls.size();
+      b->cls.push_back(BatchImpl::Cls());
+      b->cls.back().nx = c->nbr;
+    }
+    b->cls[cls_of_nx[c->nbr]].mats.push_back(m);
+    for (int64_t by = 0; by < c->m_pad / 64; ++by)
+      for (int64_t bx = 0; bx < (s1[m].ncol + 63) / 64; ++bx) b->s1_natural.push_back(make_int4(m, (int)bx, (int)by, 0));
+  }
+  auto cost1 = [&](const int4& w) { return b->ctx[w.x]->ke; };
+  b->s1_sorted = b->s1_natural;
+  std::stable_sort(b->s1_sorted.begin(), b->s1_sorted.end(),
+                   [&](const int4& a, const int4& c) { return cost1(a) > cost1(c); });
+  if (balloc(b, &b->d_s1desc, n * sizeof(S1Desc<T>)) != hipSuccess ||
+      balloc(b, (void**)&b->d_s1items, b->s1_natural.size() * sizeof(int4)) != hipSuccess ||
+      balloc(b, (void**)&b->d_counters, 64 * sizeof(int)) != hipSuccess) {
+    b->err = "batch allocation failed";
+    return ELPH_ENOMEM;
+  }
+  BCHK(hipMemcpy(b->d_s1desc, s1.data(), n * sizeof(S1Desc<T>), hipMemcpyHostToDevice));
+  for (auto& cl : b->cls) {
+    std::vector<S2Desc<T>> d(cl.mats.size());
+    for (size_t slot = 0; slot < cl.mats.size(); ++slot) {
+      const int m = cl.mats[slot];
+      elph_ctx c = b->ctx[m];
+      S2Desc<T>& e = d[slot];
+      e.kp = c->kp;
+      e.Ap = (const T*)c->d_Ap;
+      e.B2 = (const T*)c->d_B2;
+      e.Bp = c->d_Bp;
+      e.Bm = c->d_Bm;
+      e.ep = epi_params(c);
+      e.ep.lomf = b->th[m].lomf;
+      e.ep.fstate = b->th[m].f;
+      e.ep.omf = b->th[m].omf;
+      e.ep.nocc = b->th[m].nocc;
+      e.ep.we_part = c->d_we_part;
+      for (int64_t by = 0; by < c->m_pad / 32; ++by)
+        for (int64_t bx = 0; bx < c->m_pad / 32; ++bx) cl.natural.push_back(make_int4((int)slot, (int)bx, (int)by, 0));
+    }
+    cl.sorted = cl.natural;
+    std::stable_sort(cl.sorted.begin(), cl.sorted.end(), [&](const int4& a, const int4& c2) {
+      return b->ctx[cl.mats[a.x]]->kp > b->ctx[cl.mats[c2.x]]->kp;
+    });
+    if (balloc(b, &cl.d_desc, d.size() * sizeof(S2Desc<T>)) != hipSuccess ||
+        balloc(b, (void**)&cl.d_items, cl.natural.size() * sizeof(int4)) != hipSuccess) {
+      b->err = "batch allocation failed";
+      return ELPH_ENOMEM;
+    }
+    BCHK(hipMemcpy(cl.d_desc, d.data(), d.size() * sizeof(S2Desc<T>), hipMemcpyHostToDevice));
+  }
+  b->prepared = true;
+  return ELPH_OK;
+}
+
+static elph_status batch_upload_order(BatchImpl* b) {
+  const std::vector<int4>& s1 = b->sorted ? b->s1_sorted : b->s1_natural;
+  BCHK(hipMemcpy(b->d_s1items, s1.data(), s1.size() * sizeof(int4), hipMemcpyHostToDevice));
+  for (auto& cl : b->cls) {
+    const std::vector<int4>& it = b->sorted ? cl.sorted : cl.natural;
+    BCHK(hipMemcpy(cl.d_items, it.data(), it.size() * sizeof(int4), hipMemcpyHostToDevice));
+  }
+  return ELPH_OK;
+}
+
+template <typename T, typename ST>
+static elph_status batch_launch_step2(BatchImpl* b, BatchImpl::Cls& cl, int* counter) {
+  const int nitems = (int)cl.natural.size();
+  const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)b->bpc * b->ncu);
+  const S2Desc<T>* d = (const S2Desc<T>*)cl.d_desc;
+#define S2P(NXV)                                                                                              \
+  hipLaunchKernelGGL((k_step2_persist<T, ST, NXV>), dim3(grid), dim3(256), 0, b->stream, d, cl.d_items, nitems, \
+                     counter)
+  switch (cl.nx) {
+    case 3: S2P(3); break;
+    case 6: S2P(6); break;
+    case 9: S2P(9); break;
+    case 12: S2P(12); break;
+    case 15: S2P(15); break;
+    default: b->err = "unsupported branch count"; return ELPH_EINVAL;
+  }
+#undef S2P
+  return ELPH_OK;
+}
+
+// The per-temperature sequence (no synchronisation, no allocation: safe to capture).
+template <typename T>
+static elph_status batch_sequence(BatchImpl* b, double T_K, double* const* we, double* const* wph) {
+  typedef T ST;  // the store keeps the precision of the contraction
+  const int n = (int)b->ctx.size();
+  StreamSwap sw(b);
+  for (int m = 0; m < n; ++m) fill_thermal(b->ctx[m], T_K, b->th[m], b->stream);
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, b->stream, b->d_counters, 64);
+  const int n1 = (int)b->s1_natural.size();
+  hipLaunchKernelGGL(k_step1_persist<T>, dim3((unsigned)std::min<int64_t>(n1, (int64_t)b->bpc * b->ncu)),
+                     dim3(256), 0, b->stream, (const S1Desc<T>*)b->d_s1desc, b->d_s1items, n1, b->d_counters);
+  for (size_t c = 0; c < b->cls.size(); ++c) {
+    elph_status st = batch_launch_step2<T, ST>(b, b->cls[c], b->d_counters + 1 + c);
+    if (st != ELPH_OK) return st;
+  }
+  for (int m = 0; m < n; ++m) {
+    elph_ctx c = b->ctx[m];
+    double* wout = (we && we[m]) ? we[m] : b->we_tmp[m];
+    hipLaunchKernelGGL(k_reduce_we, dim3(blocks_for(c->nstates, 256)), dim3(256), 0, b->stream, c->d_we_part,
+                       c->m_pad / 32, c->m_pad, c->nstates, wout);
+    if (wph && wph[m]) {
+      launch_q_gather<ST, 1>(c, (const ST*)c->d_Bp, b->th[m].f, b->th[m].omf, nullptr, b->acc[m]);
+      elph_status st = finalize_wph(c, b->th[m], b->acc[m], wph[m]);
+      if (st != ELPH_OK) return st;
+    }
+  }
+  BCHK(hipGetLastError());
+  return ELPH_OK;
+}
+
+BatchImpl* batch_new(const std::vector<elph_ctx>& ctxs, std::string* err) {
+  BatchImpl* b = new (std::nothrow) BatchImpl();
+  if (!b) {
+    *err = "host allocation failed";
+    return nullptr;
+  }
+  b->ctx = ctxs;
+  for (elph_ctx c : ctxs) b->saved_streams.push_back(c->stream);
+  b->precision = ctxs[0]->precision;
+  for (elph_ctx c : ctxs)
+    if (c->precision != b->precision || c->hip_dead) {
+      *err = "batch contexts must share one precision form and be usable";
+      delete b;
+      return nullptr;
+    }
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    *err = "stream creation failed";
+    delete b;
+    return nullptr;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    b->ncu = prop.multiProcessorCount;
+  return b;
+}
+
+void batch_free(BatchImpl* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (void* p : b->allocs) (void)hipFree(p);
+  for (size_t m = 0; m < b->ctx.size(); ++m) {
+    free_thermal(b->ctx[m], &b->th[m]);
+    dev_free(b->ctx[m], b->acc[m]);
+    dev_free(b->ctx[m], b->we_tmp[m]);
+  }
+  (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+static elph_status batch_prepare(BatchImpl* b) {
+  if (b->prepared) return ELPH_OK;
+  elph_status st = b->precision == ELPH_FP64 ? batch_prepare_t<double>(b) : batch_prepare_t<float>(b);
+  if (st != ELPH_OK) return st;
+  auto it = tune_cache().find(batch_signature(b));
+  if (it != tune_cache().end()) {
+    b->bpc = it->second.first;
+    b->sorted = it->second.second;
+    b->tuned = true;
+  }
+  return batch_upload_order(b);
+}
+
+static elph_status batch_run(BatchImpl* b, double T_K, double* const* we, double* const* wph) {
+  return b->precision == ELPH_FP64 ? batch_sequence<double>(b, T_K, we, wph)
+                                   : batch_sequence<float>(b, T_K, we, wph);
+}
+
+elph_status batch_rates(BatchImpl* b, double T_K, double* const* we, double* const* wph, bool use_graph) {
+  elph_status st = batch_prepare(b);
+  if (st != ELPH_OK) return st;
+  const int n = (int)b->ctx.size();
+  if (!use_graph) {
+    st = batch_run(b, T_K, we, wph);
+    if (st != ELPH_OK) return st;
+  } else {
+    std::vector<double*> key;
+    for (int m = 0; m < n; ++m) {
+      key.push_back(we ? we[m] : nullptr);
+      key.push_back(wph ? wph[m] : nullptr);
+    }
+    if (!b->gexec || b->gT != T_K || key != b->gptrs) {
+      if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
+      b->gexec = nullptr;
+      b->graph = nullptr;
+      BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      st = batch_run(b, T_K, we, wph);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(b->stream, &g);
+      if (st != ELPH_OK) return st;
+      BCHK(e);
+      b->graph = g;
+      BCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+      b->gT = T_K;
+      b->gptrs = key;
+    }
+    BCHK(hipGraphLaunch(b->gexec, b->stream));
+  }
+  BCHK(hipStreamSynchronize(b->stream));
+  for (elph_ctx c : b->ctx) c->store_ready = true;
+  return ELPH_OK;
+}
+
+// Autotuner: time every (blocks per CU, item order) variant of the two
+// persistent contraction launches and keep the fastest for this signature.
+elph_status batch_tune(BatchImpl* b, double T_K, int* choice, double* best_ms) {
+  elph_status st = batch_prepare(b);
+  if (st != ELPH_OK) return st;
+  hipEvent_t e0, e1;
+  BCHK(hipEventCreate(&e0));
+  BCHK(hipEventCreate(&e1));
+  double best = 1e300;
+  int best_bpc = b->bpc;
+  bool best_sorted = b->sorted;
+  for (int bpc : {1, 2, 4, 8}) {
+    for (int so = 0; so < 2; ++so) {
+      b->bpc = bpc;
+      b->sorted = so == 1;
+      st = batch_upload_order(b);
+      if (st != ELPH_OK) return st;
+      st = batch_run(b, T_K, nullptr, nullptr);  // warm
+      if (st != ELPH_OK) return st;
+      BCHK(hipEventRecord(e0, b->stream));
+      for (int rep = 0; rep < 2; ++rep) {
+        st = batch_run(b, T_K, nullptr, nullptr);
+        if (st != ELPH_OK) return st;
+      }
+      BCHK(hipEventRecord(e1, b->stream));
+      BCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      BCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms / 2.0 < best) {
+        best = ms / 2.0;
+        best_bpc = bpc;
+        best_sorted = so == 1;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->bpc = best_bpc;
+  b->sorted = best_sorted;
+  b->tuned = true;
+  tune_cache()[batch_signature(b)] = {best_bpc, best_sorted};
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  if (choice) {
+    choice[0] = best_bpc;
+    choice[1] = best_sorted ? 1 : 0;
+  }
+  if (best_ms) *best_ms = best;
+  return batch_upload_order(b);
+}
+
+const std::string& batch_error(BatchImpl* b) { return b->err; }
 
 }  // namespace elph

@@ -42,7 +42,8 @@ class ElphSizes(ctypes.Structure):
 
 
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
-           "elph_tables",
+           "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
+           "elph_batch_tune", "elph_tables",
            "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate")
 
 _lib = None
@@ -64,7 +65,7 @@ def load():
     lib.elph_destroy.restype = None
     lib.elph_last_error.argtypes = [vp]
     lib.elph_last_error.restype = ctypes.c_char_p
-    lib.elph_reset.argtypes = [vp]
+    lib.elph_reset.argtypes = [vp, ctypes.c_int32]
     lib.elph_timing.argtypes = [vp, ctypes.c_int32, vp]
     lib.elph_sizes.argtypes = [vp, ctypes.POINTER(ElphSizes)]
     lib.elph_tables.argtypes = [vp] * 7
@@ -73,8 +74,16 @@ def load():
     lib.elph_scatt_rates.argtypes = [vp, ctypes.c_double, vp, vp]
     lib.elph_iterate.argtypes = [vp, ctypes.c_double, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                  vp, vp, vp, vp, vp, vp, vp]
+    lib.elph_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.elph_batch_destroy.argtypes = [vp]
+    lib.elph_batch_destroy.restype = None
+    lib.elph_batch_last_error.argtypes = [vp]
+    lib.elph_batch_last_error.restype = ctypes.c_char_p
+    lib.elph_batch_scatt_rates.argtypes = [vp, ctypes.c_double, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.c_int32]
+    lib.elph_batch_tune.argtypes = [vp, ctypes.c_double, vp, vp]
     for name in EXPORTS:
-        if name not in ("elph_destroy", "elph_last_error"):
+        if name not in ("elph_destroy", "elph_last_error", "elph_batch_destroy", "elph_batch_last_error"):
             getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -152,8 +161,11 @@ def elph_destroy(ctx):
     ctx.close()
 
 
-def elph_reset(ctx):
-    _check(ctx, load().elph_reset(ctx.handle))
+ELPH_RESET_ALL, ELPH_RESET_STORE = 0, 1
+
+
+def elph_reset(ctx, what=ELPH_RESET_ALL):
+    _check(ctx, load().elph_reset(ctx.handle, int(what)))
 
 
 def elph_timing(ctx, enable=True, read=False):
@@ -203,3 +215,55 @@ def elph_iterate(ctx, T, I, J, F, G, W_ph_ext=None, level=ELPH_LEVEL_COUPLED, to
     names = ("sigma", "sigmaS", "alpha_el", "kappa0_el", "alpha_ph", "kappa_ph")
     return {"tensors": {n: tens[9 * a:9 * a + 9].reshape(3, 3).copy() for a, n in enumerate(names)},
             "iters": iters.value, "ko_residual": ko.value, "status": st}
+
+
+class Batch:
+    """Owns an elph_batch handle (the contexts must outlive it)."""
+
+    def __init__(self, ctxs):
+        lib = load()
+        self.ctxs = list(ctxs)
+        arr = (ctypes.c_void_p * len(self.ctxs))(*[c.handle.value if hasattr(c.handle, "value") else c.handle
+                                                 for c in self.ctxs])
+        h = ctypes.c_void_p()
+        st = lib.elph_batch_create(len(self.ctxs), arr, ctypes.byref(h))
+        if st != ELPH_OK:
+            raise ElphError(st, lib.elph_batch_last_error(None).decode())
+        self.handle = h
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().elph_batch_destroy(self.handle)
+            self.handle = None
+
+    def _check(self, st):
+        if st != ELPH_OK:
+            raise ElphError(st, load().elph_batch_last_error(self.handle).decode())
+
+
+def elph_batch_create(ctxs):
+    return Batch(ctxs)
+
+
+def elph_batch_destroy(batch):
+    batch.close()
+
+
+def elph_batch_scatt_rates(batch, T, W_e=None, W_ph=None, use_graph=True):
+    n = len(batch.ctxs)
+    def arr(ts):
+        if ts is None:
+            return None
+        return (ctypes.c_void_p * n)(*[t.data_ptr() if t is not None else None for t in ts])
+    batch._check(load().elph_batch_scatt_rates(batch.handle, float(T), arr(W_e), arr(W_ph), int(bool(use_graph))))
+
+
+def elph_batch_tune(batch, T):
+    ch = np.zeros(2, dtype=np.int32)
+    best = ctypes.c_double(0.0)
+    batch._check(load().elph_batch_tune(batch.handle, float(T), ch.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.byref(best)))
+    return {"blocks_per_cu": int(ch[0]), "cost_ordered": bool(ch[1]), "best_ms": best.value}

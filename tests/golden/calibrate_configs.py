@@ -48,21 +48,35 @@ def _raw_hk(cfg, kfrac):
 
 
 def _gap_delta(hk, onsite, s_H, nb):
-    """Secant iteration on gap(delta) = GAP (gap is close to linear in delta)."""
+    """Bracketed Illinois (regula falsi) iteration on gap(delta) = GAP; the
+    gap grows with delta."""
     def gap(delta):
         e = _bands(hk, onsite, s_H, delta)
-        return e[:, nb // 2].min() - e[:, nb // 2 - 1].max()
-    x0, x1 = 0.5, 1.5
-    f0, f1 = gap(x0) - GAP, gap(x1) - GAP
-    for _ in range(50):
-        if abs(f1) < 1e-11 or f1 == f0:
-            break
-        x2 = x1 - f1 * (x1 - x0) / (f1 - f0)
-        x0, f0 = x1, f1
-        x1, f1 = x2, gap(x2) - GAP
-    if abs(f1) > 1e-9:
-        raise RuntimeError("gap calibration did not converge")
-    return x1
+        return e[:, nb // 2].min() - e[:, nb // 2 - 1].max() - GAP
+    lo, hi = 0.0, 1.0
+    flo, fhi = gap(lo), gap(hi)
+    while fhi < 0:
+        lo, flo = hi, fhi
+        hi *= 2.0
+        fhi = gap(hi)
+    side = 0
+    x = hi
+    for _ in range(100):
+        x = (lo * fhi - hi * flo) / (fhi - flo)
+        fx = gap(x)
+        if abs(fx) < 1e-11 or hi - lo < 1e-13:
+            return x
+        if fx > 0:
+            hi, fhi = x, fx
+            if side == 1:
+                flo *= 0.5
+            side = 1
+        else:
+            lo, flo = x, fx
+            if side == -1:
+                fhi *= 0.5
+            side = -1
+    raise RuntimeError("gap calibration did not converge")
 
 
 def calibrate(name, sub=1):
