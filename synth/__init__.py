@@ -7,6 +7,7 @@ transition probabilities).  Calibrated scale parameters (band gap offset,
 Hamiltonian scale, force-constant scale, chemical potential) are stored in
 ``configs.json``, written by ``tests/golden/calibrate_configs.py``.
 """
+from . import mlp  # noqa: F401
 from .materials import (  # noqa: F401
     rset_cube, rset_sphere, make_material, config, config_names, material_for,
     MASS_CYCLE, LATTICE_A,
