@@ -136,13 +136,16 @@ void elph_destroy(elph_ctx ctx);
  * errors of elph_create. */
 const char* elph_last_error(elph_ctx ctx);
 
-/* what = ELPH_RESET_ALL: drop every derived table, contraction operand and
- * the vertex store (releases their memory); ELPH_RESET_STORE: only mark the
- * vertex store stale so that the next rate call recomputes the vertices.
- * The next call rebuilds what it needs (inputs stay on the device).  Used to
- * time the path and to release memory.  Do not reset a context that belongs
- * to a live batch. */
-enum { ELPH_RESET_ALL = 0, ELPH_RESET_STORE = 1 };
+/* what = ELPH_RESET_ALL: drop every derived table, contraction operand, the
+ * vertex store and the cached rates; their device blocks stay in the
+ * context's pool and are reused by later allocations of the same size.
+ * ELPH_RESET_STORE: only mark the vertex store (and the cached rates) stale
+ * so that the next rate call recomputes the vertices.  ELPH_RESET_TRIM: as
+ * ELPH_RESET_ALL, then return the pool's memory to the device.  The next
+ * call rebuilds what it needs (inputs stay on the device).  Used to time the
+ * path and to release memory.  Do not reset a context that belongs to a live
+ * batch. */
+enum { ELPH_RESET_ALL = 0, ELPH_RESET_STORE = 1, ELPH_RESET_TRIM = 2 };
 elph_status elph_reset(elph_ctx ctx, int32_t what);
 
 /* Kernel timing with HIP events recorded on the context's stream around

@@ -17,18 +17,40 @@ namespace elph {
 
 hipError_t dev_alloc(elph_ctx ctx, void** p, size_t bytes) {
   *p = nullptr;
-  hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 1);
-  if (e == hipSuccess) ctx->allocs.push_back(*p);
+  const size_t n = bytes > 0 ? bytes : 1;
+  for (size_t k = 0; k < ctx->pool.size(); ++k)
+    if (ctx->pool[k].second == n) {
+      *p = ctx->pool[k].first;
+      ctx->pool.erase(ctx->pool.begin() + k);
+      ctx->allocs.push_back({*p, n});
+      return hipSuccess;
+    }
+  hipError_t e = hipMalloc(p, n);
+  if (e != hipSuccess) {
+    // give the pool back to the device and try once more
+    (void)hipGetLastError();
+    pool_trim(ctx);
+    e = hipMalloc(p, n);
+  }
+  if (e == hipSuccess) ctx->allocs.push_back({*p, n});
   return e;
 }
 
 void dev_free(elph_ctx ctx, void* p) {
   if (!p) return;
-  auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
-  if (it != ctx->allocs.end()) {
-    ctx->allocs.erase(it);
-    (void)hipFree(p);
-  }
+  for (size_t k = 0; k < ctx->allocs.size(); ++k)
+    if (ctx->allocs[k].first == p) {
+      ctx->pool.push_back(ctx->allocs[k]);
+      ctx->allocs.erase(ctx->allocs.begin() + k);
+      return;
+    }
+}
+
+void pool_trim(elph_ctx ctx) {
+  if (ctx->pool.empty()) return;
+  if (!ctx->hip_dead) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& b : ctx->pool) (void)hipFree(b.first);
+  ctx->pool.clear();
 }
 
 }  // namespace elph
@@ -45,16 +67,6 @@ static thread_local std::string g_create_err;
     (ctx)->err.clear();                                         \
   } while (0)
 
-#define HIPCHK(x)                                                       \
-  do {                                                                  \
-    hipError_t e_ = (x);                                                \
-    if (e_ != hipSuccess) {                                             \
-      ctx->err = std::string("HIP error ") + hipGetErrorString(e_) +    \
-                 " at " + __FILE__ + ":" + std::to_string(__LINE__);    \
-      ctx->hip_dead = true;                                             \
-      return ELPH_EHIP;                                                 \
-    }                                                                   \
-  } while (0)
 
 static bool all_finite(const double* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
@@ -251,8 +263,11 @@ extern "C" void elph_destroy(elph_ctx ctx) {
   if (!ctx->hip_dead) (void)hipStreamSynchronize(ctx->stream);
   for (int e = 0; e < 8; ++e)
     if (ctx->ev[e]) (void)hipEventDestroy(ctx->ev[e]);
-  for (void* p : ctx->allocs) (void)hipFree(p);
+  for (auto& b : ctx->allocs) (void)hipFree(b.first);
+  for (auto& b : ctx->pool) (void)hipFree(b.first);
   ctx->allocs.clear();
+  ctx->pool.clear();
+  if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
   delete ctx;
 }
 
@@ -270,26 +285,36 @@ static void drop_derived(elph_ctx ctx) {
                    (void**)&ctx->d_Lq,      (void**)&ctx->d_vph,       (void**)&ctx->d_Ee,
                    (void**)&ctx->d_Ep,      (void**)&ctx->d_Ae,        (void**)&ctx->d_Ap,
                    (void**)&ctx->d_gR,      (void**)&ctx->d_B2,        (void**)&ctx->d_Bp,
-                   (void**)&ctx->d_Bm,      (void**)&ctx->d_we_part};
+                   (void**)&ctx->d_Bm,      (void**)&ctx->d_we_part,   (void**)&ctx->d_order,
+                   (void**)&ctx->d_goff,    (void**)&ctx->d_we_cache,  (void**)&ctx->d_wph_cache,
+                   (void**)&ctx->d_poff,    (void**)&ctx->d_plist};
   for (void** p : ptrs) {
     dev_free(ctx, *p);
     *p = nullptr;
   }
   ctx->we_part_len = 0;
   ctx->tables_ready = ctx->operands_ready = ctx->store_ready = false;
+  ctx->groups_ready = ctx->rates_valid = ctx->pairs_ready = ctx->pairs_failed = false;
   ctx->nkept = ctx->nstates = 0;
   ctx->ngroups = 0;
 }
 
 extern "C" elph_status elph_reset(elph_ctx ctx, int32_t what) {
   CHECK_CTX(ctx);
-  if (what != ELPH_RESET_ALL && what != ELPH_RESET_STORE) {
+  if (what != ELPH_RESET_ALL && what != ELPH_RESET_STORE && what != ELPH_RESET_TRIM) {
     ctx->err = "unknown reset mode";
     return ELPH_EINVAL;
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  if (what == ELPH_RESET_ALL) drop_derived(ctx);
-  else ctx->store_ready = false;
+  if (what == ELPH_RESET_ALL) {
+    drop_derived(ctx);
+  } else if (what == ELPH_RESET_STORE) {
+    ctx->store_ready = false;
+    ctx->rates_valid = false;
+  } else {
+    drop_derived(ctx);
+    pool_trim(ctx);
+  }
   return ELPH_OK;
 }
 
@@ -447,6 +472,18 @@ extern "C" elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, d
     if (st == ELPH_OK && W_ph) st = rates_from_store(ctx, th, nullptr, W_ph);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     dev_free(ctx, we);
+  }
+  if (st == ELPH_OK && W_e && W_ph) {
+    // keep the rates for an iteration at the same temperature
+    const int64_t M = ctx->nstates, nm = ctx->nk * ctx->nbr;
+    if (!ctx->d_we_cache) ALLOC(ctx->d_we_cache, M * sizeof(double));
+    if (!ctx->d_wph_cache) ALLOC(ctx->d_wph_cache, nm * sizeof(double));
+    HIPCHK(hipMemcpyAsync(ctx->d_we_cache, W_e, M * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->d_wph_cache, W_ph, nm * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->rates_T = T_K;
+    ctx->rates_valid = true;
+  } else {
+    ctx->rates_valid = false;
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   free_thermal(ctx, &th);

@@ -23,6 +23,7 @@ constexpr double kHbarJs = kHbarEVs * kCharge;
 constexpr double kPhononC = kHbarJs * kHbarJs / (kAmuKg * kAngM * kAngM) / kCharge;
 
 constexpr int kMaxBands = 16;
+constexpr int64_t kMaxPairKept = 46340;  // nkept^2 below 2^31
 
 // ---------------------------------------------------------------- complex
 struct cd {
@@ -124,7 +125,25 @@ struct elph_ctx_s {
   hipEvent_t ev[8] = {};
   bool ev_recorded[4] = {false, false, false, false};
 
-  std::vector<void*> allocs;      // everything to free
+  // caches reused across calls (dropped with the tables)
+  int32_t* d_order = nullptr;     // [nstates] states sorted by energy
+  int32_t* d_goff = nullptr;      // [ngroups+1] offsets of the energy groups in d_order
+  bool groups_ready = false;
+  int32_t* d_poff = nullptr;      // [nk+1] offsets of the pair lists by q
+  int32_t* d_plist = nullptr;     // [nkept^2] kept index t of each pair (k_t, k_t + q)
+  bool pairs_ready = false;
+  bool pairs_failed = false;      // lists not allocatable: q-gathers walk the kept set
+  double* d_we_cache = nullptr;   // [nstates] W_e of the last full elph_scatt_rates
+  double* d_wph_cache = nullptr;  // [nk][nbr] W_ph of the same call
+  double rates_T = -1.0;
+  bool rates_valid = false;
+  double* h_pin = nullptr;        // pinned host words for solver status reads
+
+  // device memory: live blocks (pointer, bytes) and released blocks kept for
+  // reuse by later allocations of the same size (freed by elph_destroy or
+  // ELPH_RESET_TRIM)
+  std::vector<std::pair<void*, size_t>> allocs;
+  std::vector<std::pair<void*, size_t>> pool;
 };
 
 namespace elph {
@@ -136,8 +155,36 @@ inline void mark(elph_ctx ctx, int e) {
   if (e & 1) ctx->ev_recorded[e >> 1] = true;
 }
 
-// Allocation helper: records the pointer in ctx->allocs.
+// Device allocation through the context pool: a released block of exactly
+// the requested size is reused, otherwise hipMalloc.  dev_free returns the
+// block to the pool; pool_trim releases the pool.
 hipError_t dev_alloc(elph_ctx ctx, void** p, size_t bytes);
 void dev_free(elph_ctx ctx, void* p);
+void pool_trim(elph_ctx ctx);
+
+// Host-side error plumbing of functions that take `elph_ctx ctx` and return
+// elph_status.
+#define HIPCHK(x)                                                       \
+  do {                                                                  \
+    hipError_t e_ = (x);                                                \
+    if (e_ != hipSuccess) {                                             \
+      ctx->err = std::string("HIP error ") + hipGetErrorString(e_) +    \
+                 " at " + __FILE__ + ":" + std::to_string(__LINE__);    \
+      ctx->hip_dead = true;                                             \
+      return ELPH_EHIP;                                                 \
+    }                                                                   \
+  } while (0)
+
+#define ALLOC(ptr, bytes)                                                          \
+  do {                                                                             \
+    void* p_ = nullptr;                                                            \
+    hipError_t e_ = dev_alloc(ctx, &p_, (size_t)(bytes));                          \
+    if (e_ != hipSuccess) {                                                        \
+      ctx->err = "device allocation of " + std::to_string((size_t)(bytes)) + " bytes failed"; \
+      (void)hipGetLastError();                                                     \
+      return ELPH_ENOMEM;                                                          \
+    }                                                                              \
+    ptr = (decltype(ptr))p_;                                                       \
+  } while (0)
 
 }  // namespace elph

@@ -11,6 +11,7 @@
 //  * the vertex of Eq. 6 at arbitrary mesh pairs (elph_interp_g).
 #include "tables.h"
 #include "vertex.h"
+#include "devutil.h"
 
 #include <algorithm>
 #include <cmath>
@@ -19,28 +20,6 @@
 
 namespace elph {
 
-#define HIPCHK(x)                                                       \
-  do {                                                                  \
-    hipError_t e_ = (x);                                                \
-    if (e_ != hipSuccess) {                                             \
-      ctx->err = std::string("HIP error ") + hipGetErrorString(e_) +    \
-                 " at " + __FILE__ + ":" + std::to_string(__LINE__);    \
-      ctx->hip_dead = true;                                             \
-      return ELPH_EHIP;                                                 \
-    }                                                                   \
-  } while (0)
-
-#define ALLOC(ptr, bytes)                                                          \
-  do {                                                                             \
-    void* p_ = nullptr;                                                            \
-    hipError_t e_ = dev_alloc(ctx, &p_, (size_t)(bytes));                          \
-    if (e_ != hipSuccess) {                                                        \
-      ctx->err = "device allocation of " + std::to_string((size_t)(bytes)) + " bytes failed"; \
-      (void)hipGetLastError();                                                     \
-      return ELPH_ENOMEM;                                                          \
-    }                                                                              \
-    ptr = (decltype(ptr))p_;                                                       \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // thermal tables
@@ -111,55 +90,6 @@ void free_thermal(elph_ctx ctx, Thermal* th) {
   *th = Thermal();
 }
 
-// ---------------------------------------------------------------------------
-// helpers
-
-__device__ inline int64_t q_between(int64_t kj, int64_t ki, int n0, int n1, int n2) {
-  int cj = (int)(kj % n2), ci = (int)(ki % n2);
-  int64_t tj = kj / n2, ti = ki / n2;
-  int bj = (int)(tj % n1), bi = (int)(ti % n1);
-  int aj = (int)(tj / n1), ai = (int)(ti / n1);
-  int a = aj - ai; if (a < 0) a += n0;
-  int b = bj - bi; if (b < 0) b += n1;
-  int c = cj - ci; if (c < 0) c += n2;
-  return ((int64_t)a * n1 + b) * n2 + c;
-}
-
-__device__ inline int64_t q_neg(int64_t q, int n0, int n1, int n2) {
-  int c = (int)(q % n2);
-  int64_t t = q / n2;
-  int b = (int)(t % n1);
-  int a = (int)(t / n1);
-  a = a ? n0 - a : 0;
-  b = b ? n1 - b : 0;
-  c = c ? n2 - c : 0;
-  return ((int64_t)a * n1 + b) * n2 + c;
-}
-
-// Sum of NV values over a 256-thread block (fixed order): wave butterflies,
-// then the four wave results in LDS.  sh holds at least NV * 4 doubles.
-template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double* sh) {
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    double x = v[c];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    v[c] = x;
-  }
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int c = 0; c < NV; ++c) sh[c * 4 + wave] = v[c];
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < NV; ++c) v[c] = (sh[c * 4 + 0] + sh[c * 4 + 1]) + (sh[c * 4 + 2] + sh[c * 4 + 3]);
-  __syncthreads();
-}
-
-struct MeshDims {
-  int n0, n1, n2;
-};
 
 // ---------------------------------------------------------------------------
 // X from the store:  X+ = B+ f_i (1 - f_j) n,  X- = B- f_i (1 - f_j) (1 + n)
@@ -182,23 +112,27 @@ __global__ void k_x_from_store(int64_t M, int nbr, MeshDims md, const ST* __rest
 }
 
 // W_e[i] = sum_{j,s} (B+ n + B- (1+n)) (1 - f_j)/(1 - f_i): Eq. 21 with X/(f(1-f))
-template <typename ST>
-__global__ void __launch_bounds__(256) k_we_rows(int64_t M, int nbr, MeshDims md, const ST* __restrict__ Bp,
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_we_rows(int64_t M, MeshDims md, const ST* __restrict__ Bp,
                                                  const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
                                                  const double* __restrict__ lomf, const double* __restrict__ nocc,
                                                  double* __restrict__ we) {
   __shared__ double sh[4];
   const int64_t i = blockIdx.x;
-  const int64_t ki = st_k[i];
+  const int ki = st_k[i];
   const double li = lomf[i];
   double acc[1] = {0.0};
-  const int64_t row = M * nbr;
-  for (int64_t t = threadIdx.x; t < row; t += 256) {
-    const int64_t j = t / nbr;
-    const int s = (int)(t % nbr);
-    const int64_t q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
-    const double n = nocc[q * nbr + s];
-    const double b = (double)Bp[i * row + t] * n + (double)Bm[i * row + t] * (1.0 + n);
+  const ST* __restrict__ bp = Bp + i * M * NX;
+  const ST* __restrict__ bm = Bm + i * M * NX;
+  for (int64_t j = threadIdx.x; j < M; j += 256) {
+    const int q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
+    const double* nq = nocc + (int64_t)q * NX;
+    double b = 0.0;
+#pragma unroll
+    for (int s = 0; s < NX; ++s) {
+      const double n = nq[s];
+      b += (double)bp[j * NX + s] * n + (double)bm[j * NX + s] * (1.0 + n);
+    }
     if (b != 0.0) acc[0] += b * exp(lomf[j] - li);
   }
   block_sum<1>(acc, sh);
@@ -270,11 +204,180 @@ __global__ void __launch_bounds__(256) k_q_gather(int64_t nq, int64_t M, int nbr
   }
 }
 
+// ---- pairs by q: for every q the kept k, by ascending kept index t, whose
+// k + q is also kept.  Counted and placed with integer atomics, then each q's
+// list is sorted, so the lists (and every sum over them) are deterministic.
+
+__global__ void k_pair_count(int64_t nkept, const int32_t* __restrict__ kept, MeshDims md,
+                             int32_t* __restrict__ cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nkept * nkept) return;
+  const int64_t t = p / nkept, u = p - t * nkept;
+  atomicAdd(&cnt[q_between(kept[u], kept[t], md.n0, md.n1, md.n2)], 1);
+}
+
+__global__ void k_pair_fill(int64_t nkept, const int32_t* __restrict__ kept, MeshDims md,
+                            const int32_t* __restrict__ off, int32_t* __restrict__ cur, int32_t* __restrict__ tmp) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nkept * nkept) return;
+  const int64_t t = p / nkept, u = p - t * nkept;
+  const int q = q_between(kept[u], kept[t], md.n0, md.n1, md.n2);
+  tmp[off[q] + atomicAdd(&cur[q], 1)] = (int32_t)t;
+}
+
+// one block per q: bitonic sort in LDS up to 4096 entries, rank placement
+// (entries of one q are distinct) beyond
+__global__ void __launch_bounds__(256) k_pair_sort(const int32_t* __restrict__ off, const int32_t* __restrict__ tmp,
+                                                   int32_t* __restrict__ list) {
+  __shared__ int32_t sh[4096];
+  const int32_t b = off[blockIdx.x], len = off[blockIdx.x + 1] - b;
+  if (len <= 4096) {
+    int np = 1;
+    while (np < len) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += 256) sh[i] = i < len ? tmp[b + i] : 0x7fffffff;
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < np; i += 256) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const int32_t x = sh[i], y = sh[ixj];
+            if ((x > y) == ((i & k) == 0)) {
+              sh[i] = y;
+              sh[ixj] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (int i = threadIdx.x; i < len; i += 256) list[b + i] = sh[i];
+  } else {
+    for (int i = threadIdx.x; i < len; i += 256) {
+      const int32_t v = tmp[b + i];
+      int32_t rank = 0;
+      for (int k = 0; k < len; ++k) rank += tmp[b + k] < v ? 1 : 0;
+      list[b + rank] = v;
+    }
+  }
+}
+
+elph_status ensure_pairs(elph_ctx ctx) {
+  if (ctx->pairs_ready) return ELPH_OK;
+  hipStream_t s = ctx->stream;
+  const int64_t nk = ctx->nk, nkept = ctx->nkept, npairs = nkept * nkept;
+  const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
+  int32_t *cnt = nullptr, *tmp = nullptr, *scr = nullptr, *tot = nullptr;
+  if (!ctx->d_poff) ALLOC(ctx->d_poff, (nk + 1) * sizeof(int32_t));
+  if (!ctx->d_plist) ALLOC(ctx->d_plist, npairs * sizeof(int32_t));
+  ALLOC(cnt, nk * sizeof(int32_t));
+  ALLOC(tmp, npairs * sizeof(int32_t));
+  ALLOC(scr, (4 * ((nk + 1023) / 1024) + 64) * sizeof(int32_t));
+  HIPCHK(hipMemsetAsync(cnt, 0, nk * sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_pair_count, dim3(blocks_for(npairs, 256)), dim3(256), 0, s, nkept, ctx->d_kept, md, cnt);
+  tot = ctx->d_poff + nk;  // total lands in the last offset
+  scan_exclusive(ctx, cnt, nk, ctx->d_poff, tot, scr, s);
+  HIPCHK(hipMemsetAsync(cnt, 0, nk * sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_pair_fill, dim3(blocks_for(npairs, 256)), dim3(256), 0, s, nkept, ctx->d_kept, md,
+                     ctx->d_poff, cnt, tmp);
+  hipLaunchKernelGGL(k_pair_sort, dim3((unsigned)nk), dim3(256), 0, s, ctx->d_poff, tmp, ctx->d_plist);
+  HIPCHK(hipGetLastError());
+  dev_free(ctx, cnt);
+  dev_free(ctx, tmp);
+  dev_free(ctx, scr);
+  ctx->pairs_ready = true;
+  return ELPH_OK;
+}
+
+// acc[q][s][c] over the pair list of q: lanes take every 64th pair, then a
+// fixed-order butterfly over the wavefront
+template <typename ST, int NV, int NX>
+__global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, MeshDims md,
+                                                      const ST* __restrict__ Bp, const int32_t* __restrict__ kept,
+                                                      const int32_t* __restrict__ kidx,
+                                                      const int32_t* __restrict__ soff,
+                                                      const int32_t* __restrict__ poff,
+                                                      const int32_t* __restrict__ plist, const double* __restrict__ f,
+                                                      const double* __restrict__ omf, const double* __restrict__ x,
+                                                      double* __restrict__ acc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= nq) return;  // whole wavefront exits together
+  const int qc = (int)(q % md.n2);
+  const int qt = (int)(q / md.n2);
+  const int qb = qt % md.n1, qa = qt / md.n1;
+  double a[NX][NV];
+#pragma unroll
+  for (int s = 0; s < NX; ++s)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) a[s][c] = 0.0;
+  const int32_t pe = poff[q + 1];
+  for (int32_t p = poff[q] + lane; p < pe; p += 64) {
+    const int32_t t = plist[p];
+    const int k = kept[t];
+    const int kc = k % md.n2, kt = k / md.n2;
+    const int kb = kt % md.n1, ka = kt / md.n1;
+    int c2 = kc + qc; if (c2 >= md.n2) c2 -= md.n2;
+    int b2 = kb + qb; if (b2 >= md.n1) b2 -= md.n1;
+    int a2 = ka + qa; if (a2 >= md.n0) a2 -= md.n0;
+    const int32_t u = kidx[(a2 * md.n1 + b2) * md.n2 + c2];
+    for (int32_t i = soff[t]; i < soff[t + 1]; ++i) {
+      const double fi = f[i];
+      for (int32_t j = soff[u]; j < soff[u + 1]; ++j) {
+        const double occ = fi * omf[j];
+        double w[NV];
+        if (NV == 1) w[0] = 1.0;
+        else
+#pragma unroll
+          for (int c = 0; c < NV; ++c) w[c] = x[(int64_t)j * NV + c] - x[(int64_t)i * NV + c];
+        const ST* b = Bp + ((int64_t)i * M + j) * NX;
+#pragma unroll
+        for (int s = 0; s < NX; ++s) {
+          const double v = (double)b[s] * occ;
+#pragma unroll
+          for (int c = 0; c < NV; ++c) a[s][c] += v * w[c];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NX; ++s) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double v = a[s][c];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) acc[(q * NX + s) * NV + c] = v;
+    }
+  }
+}
+
 template <typename ST, int NV>
 void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x,
                      double* acc) {
   const dim3 grid(blocks_for(ctx->nk, 4)), blk(256);
   const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
+  bool csr = ctx->pairs_ready;
+  if (!csr && !ctx->pairs_failed && ctx->nkept <= kMaxPairKept) {
+    const elph_status st = ensure_pairs(ctx);
+    csr = st == ELPH_OK;
+    if (!csr) ctx->pairs_failed = true;
+    if (st == ELPH_ENOMEM) ctx->err.clear();  // the walk below needs no extra memory
+  }
+  if (csr) {
+#define QG(NXV)                                                                                                \
+  hipLaunchKernelGGL((k_q_gather_csr<ST, NV, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, md, Bp,   \
+                     ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist, f, omf, x, acc)
+    switch (ctx->nbr) {
+      case 3: QG(3); break;
+      case 6: QG(6); break;
+      case 9: QG(9); break;
+      case 12: QG(12); break;
+      default: QG(15); break;
+    }
+#undef QG
+    return;
+  }
+  // pair lists beyond 2^31 entries (or not allocatable): walk every kept k per q
 #define QG(NXV)                                                                                           \
   hipLaunchKernelGGL((k_q_gather<ST, NV, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, NXV, md, Bp, \
                      ctx->d_kept, ctx->nkept, ctx->d_kidx, ctx->d_soff, f, omf, x, acc)
@@ -334,8 +437,17 @@ static elph_status rates_from_store_t(elph_ctx ctx, const Thermal& th, double* w
   const int nbr = ctx->nbr;
   hipStream_t s = ctx->stream;
   if (we) {
-    hipLaunchKernelGGL(k_we_rows<ST>, dim3((unsigned)M), dim3(256), 0, s, M, nbr, mdims(ctx), (const ST*)ctx->d_Bp,
-                       (const ST*)ctx->d_Bm, ctx->d_state_k, th.lomf, th.nocc, we);
+#define WR(NXV)                                                                                            \
+  hipLaunchKernelGGL((k_we_rows<ST, NXV>), dim3((unsigned)M), dim3(256), 0, s, M, mdims(ctx), (const ST*)ctx->d_Bp, \
+                     (const ST*)ctx->d_Bm, ctx->d_state_k, th.lomf, th.nocc, we)
+    switch (nbr) {
+      case 3: WR(3); break;
+      case 6: WR(6); break;
+      case 9: WR(9); break;
+      case 12: WR(12); break;
+      default: WR(15); break;
+    }
+#undef WR
   }
   if (wph) {
     const int64_t nm = ctx->nk * nbr;
@@ -582,129 +694,50 @@ __global__ void k_group_bounds(int64_t n, const int32_t* __restrict__ flag, cons
   group[order[t]] = g;
 }
 
-template <typename ST>
-__global__ void __launch_bounds__(256) k_build_kself(int64_t M, int nbr, MeshDims md, const ST* __restrict__ Bp,
-                                                     const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
-                                                     const double* __restrict__ lomf,
-                                                     const double* __restrict__ nocc, const double* __restrict__ we,
-                                                     double* __restrict__ K) {
-  int64_t ij = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ij >= M * M) return;
-  const int64_t i = ij / M, j = ij % M;
-  const int64_t q = q_between(st_k[j], st_k[i], md.n0, md.n1, md.n2);
-  double acc = 0.0;
-  for (int s = 0; s < nbr; ++s) {
-    const double n = nocc[q * nbr + s];
-    acc += (double)Bp[ij * nbr + s] * n + (double)Bm[ij * nbr + s] * (1.0 + n);
-  }
-  const double w = we[i];
-  K[ij] = (w > 0.0 && acc != 0.0) ? acc * exp(lomf[j] - lomf[i]) / w : 0.0;
-}
-
 // De[i][c] = sum_{j,s} r_ij / W_i (-P[q][s][c] B+ n + P[-q][s][c] B- (1+n)), c = 0..5
-template <typename ST>
-__global__ void __launch_bounds__(256) k_drag_e(int64_t M, int nbr, MeshDims md, const ST* __restrict__ Bp,
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_drag_e(int64_t M, MeshDims md, const ST* __restrict__ Bp,
                                                 const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
                                                 const double* __restrict__ lomf, const double* __restrict__ nocc,
                                                 const double* __restrict__ we, const double* __restrict__ phon,
                                                 double* __restrict__ De) {
   __shared__ double sh[6 * 4];
   const int64_t i = blockIdx.x;
-  const int64_t ki = st_k[i];
+  const int ki = st_k[i];
   const double li = lomf[i];
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  const int64_t row = M * nbr;
-  for (int64_t t = threadIdx.x; t < row; t += 256) {
-    const int64_t j = t / nbr;
-    const int s = (int)(t % nbr);
-    const double bp = (double)Bp[i * row + t], bm = (double)Bm[i * row + t];
-    if (bp == 0.0 && bm == 0.0) continue;
-    const int64_t q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
-    const int64_t mq = q_neg(q, md.n0, md.n1, md.n2);
-    const double n = nocc[q * nbr + s];
+  const ST* __restrict__ bp = Bp + i * M * NX;
+  const ST* __restrict__ bm = Bm + i * M * NX;
+  const int row = (int)(M * NX);
+  for (int t = threadIdx.x; t < row; t += 256) {
+    const double vp = (double)bp[t], vm = (double)bm[t];
+    if (vp == 0.0 && vm == 0.0) continue;
+    const int j = t / NX, s = t - j * NX;
+    const int q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
+    const int mq = q_neg(q, md.n0, md.n1, md.n2);
+    const double n = nocc[(int64_t)q * NX + s];
     const double r = exp(lomf[j] - li);
-    const double a = -bp * n * r, b = bm * (1.0 + n) * r;
-    const double* pq = phon + (q * nbr + s) * 6;
-    const double* pm = phon + (mq * nbr + s) * 6;
+    const double a = -vp * n * r, b = vm * (1.0 + n) * r;
+    const double* pq = phon + ((int64_t)q * NX + s) * 6;
+    const double* pm = phon + ((int64_t)mq * NX + s) * 6;
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[c] += a * pq[c] + b * pm[c];
   }
   block_sum<6>(acc, sh);
+  double v = acc[0];
+#pragma unroll
+  for (int c = 1; c < 6; ++c)
+    if ((int)threadIdx.x == c) v = acc[c];
   if (threadIdx.x < 6) {
     const double w = we[i];
-    De[i * 6 + threadIdx.x] = (w > 0.0) ? acc[threadIdx.x] / w : 0.0;
+    De[i * 6 + threadIdx.x] = (w > 0.0) ? v / w : 0.0;
   }
 }
 
-// xn[i][c] = x0[i][c] + De[i][c] + sgn * sum_j K[i][j] x[j][c].  A block owns
-// 4 rows (one wavefront each); chunks of 256 rows of x are staged in LDS and
-// shared by the 4 rows; each wavefront reduces with butterflies (fixed order).
-__global__ void __launch_bounds__(256) k_self_sweep(int64_t M, const double* __restrict__ K,
-                                                    const double* __restrict__ x, const double* __restrict__ x0,
-                                                    const double* __restrict__ De, double sgn,
-                                                    double* __restrict__ xn) {
-  __shared__ double xs[256 * 6];
-  const int r = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + r;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t j0 = 0; j0 < M; j0 += 256) {
-    const int64_t nj = (M - j0 < 256) ? M - j0 : 256;
-    for (int t = threadIdx.x; t < nj * 6; t += 256) xs[t] = x[j0 * 6 + t];
-    __syncthreads();
-    if (i < M) {
-      const double* Ki = K + i * M + j0;
-      for (int jj = l; jj < nj; jj += 64) {
-        const double k = Ki[jj];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += k * xs[jj * 6 + c];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int c = 0; c < 6; ++c)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
-  if (i < M && l < 6) {
-    double v = acc[0];
-#pragma unroll
-    for (int c = 1; c < 6; ++c)
-      if (c == l) v = acc[c];
-    xn[i * 6 + l] = x0[i * 6 + l] + (De ? De[i * 6 + l] : 0.0) + sgn * v;
-  }
-}
-
-// ---- BiCGSTAB on the projected electron operator: six independent columns
-// (I and J, three Cartesian components each) share every sweep.
+// six-column scalars for the vector kernels
 struct Col6 {
   double v[6];
 };
-
-// per-column dot products of up to three pairs of [n][6] arrays; part[block][18]
-__global__ void __launch_bounds__(256) k_dots6(int64_t n, const double* __restrict__ a0,
-                                               const double* __restrict__ b0, const double* __restrict__ a1,
-                                               const double* __restrict__ b1, const double* __restrict__ a2,
-                                               const double* __restrict__ b2, double* __restrict__ part) {
-  __shared__ double sh[18 * 4];
-  double acc[18];
-#pragma unroll
-  for (int c = 0; c < 18; ++c) acc[c] = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n * 6; t += (int64_t)gridDim.x * 256) {
-    const int c = (int)(t % 6);
-    const double p0 = a0[t] * b0[t];
-    const double p1 = a1 ? a1[t] * b1[t] : 0.0;
-    const double p2 = a2 ? a2[t] * b2[t] : 0.0;
-#pragma unroll
-    for (int cc = 0; cc < 6; ++cc)
-      if (cc == c) {
-        acc[cc] += p0;
-        acc[6 + cc] += p1;
-        acc[12 + cc] += p2;
-      }
-  }
-  block_sum<18>(acc, sh);
-  if (threadIdx.x < 18) part[blockIdx.x * 18 + threadIdx.x] = acc[threadIdx.x];
-}
 
 // y = a + sa * b + sc * c   (column-wise scalars; b or c may be null)
 __global__ void k_lin6(int64_t n, const double* __restrict__ a, Col6 sa, const double* __restrict__ b, Col6 sc,
@@ -945,29 +978,32 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   elph_status st = make_thermal(ctx, T, &th);
   if (st != ELPH_OK) return st;
 
-  double *we = nullptr, *wphe = nullptr, *wp = nullptr, *x0 = nullptr, *x = nullptr, *xn = nullptr, *De = nullptr;
-  double *phon0 = nullptr, *phon = nullptr, *phonn = nullptr, *acc = nullptr, *K = nullptr, *part = nullptr,
-         *wff = nullptr;
+  double *we = nullptr, *wphe = nullptr, *wp = nullptr, *x0 = nullptr, *x = nullptr, *De = nullptr;
+  double *phon0 = nullptr, *phon = nullptr, *phonn = nullptr, *acc = nullptr, *part = nullptr, *wff = nullptr;
+  double *xprev = nullptr, *sbase = nullptr;
   ALLOC(we, M * sizeof(double));
   ALLOC(wphe, nm * sizeof(double));
   ALLOC(wp, nm * sizeof(double));
   ALLOC(x0, M * 6 * sizeof(double));
   ALLOC(x, M * 6 * sizeof(double));
-  ALLOC(xn, M * 6 * sizeof(double));
   ALLOC(De, M * 6 * sizeof(double));
   ALLOC(phon0, nm * 6 * sizeof(double));
   ALLOC(phon, nm * 6 * sizeof(double));
   ALLOC(phonn, nm * 6 * sizeof(double));
   ALLOC(acc, nm * 6 * sizeof(double));
-  ALLOC(K, M * M * sizeof(double));
   ALLOC(part, 256 * 64 * sizeof(double));
   ALLOC(wff, M * sizeof(double));
-  double* xprev = nullptr;
   ALLOC(xprev, M * 6 * sizeof(double));
   std::vector<double> hpart(256 * 64);
 
-  st = rates_from_store(ctx, th, we, wphe);
-  if (st != ELPH_OK) return st;
+  if (ctx->rates_valid && ctx->rates_T == T) {
+    // rates of the preceding elph_scatt_rates at this temperature
+    HIPCHK(hipMemcpyAsync(we, ctx->d_we_cache, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(wphe, ctx->d_wph_cache, nm * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    st = rates_from_store(ctx, th, we, wphe);
+    if (st != ELPH_OK) return st;
+  }
   hipLaunchKernelGGL(k_wp_total, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, wphe, wext, ctx->d_hw, ctx->hw_max,
                      T, ctx->omega_min, wp);
   hipLaunchKernelGGL(k_rta_e, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, ctx->d_eps, ctx->d_vel, ctx->mu, T, we,
@@ -981,133 +1017,55 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   int used = 0;
   bool converged = true;
   if (level != ELPH_LEVEL_RTA) {
-    int32_t *order = nullptr, *goff = nullptr;
-    st = build_groups(ctx, &order, &goff);
-    if (st != ELPH_OK) return st;
+    if (!ctx->groups_ready) {
+      st = build_groups(ctx, &ctx->d_order, &ctx->d_goff);
+      if (st != ELPH_OK) return st;
+      ctx->groups_ready = true;
+    }
+    const int32_t* order = ctx->d_order;
+    const int32_t* goff = ctx->d_goff;
+    const unsigned ng = (unsigned)ctx->ngroups;
     // f(1-f) weights of the projection
     hipLaunchKernelGGL(k_mul, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, th.f, th.omf, wff);
-    hipLaunchKernelGGL(k_build_kself<ST>, dim3(blocks_for(M * M, 256)), dim3(256), 0, s, M, nbr, md, Bp, Bm,
-                       ctx->d_state_k, th.lomf, th.nocc, we, K);
-    HIPCHK(hipGetLastError());
+    SelfSolver sv;
+    ALLOC(sbase, self_solver_doubles(M) * sizeof(double));
+    self_solver_carve(M, sbase, &sv);
+    st = build_self_operator<ST>(ctx, Bp, Bm, th.lomf, th.nocc, we, order, goff, wff, sv.KT);
+    if (st != ELPH_OK) return st;
 
     int last_inner = 0;
     const bool verbose = std::getenv("ELPH_VERBOSE") != nullptr;
-    Col6 one6, zero6, mone6;
+    Col6 one6, zero6;
     for (int c = 0; c < 6; ++c) {
       one6.v[c] = 1.0;
       zero6.v[c] = 0.0;
-      mone6.v[c] = -1.0;
     }
-    double *kr = nullptr, *krh = nullptr, *kp = nullptr, *kv = nullptr, *ks = nullptr, *kt = nullptr;
-    ALLOC(kr, M * 6 * sizeof(double));
-    ALLOC(krh, M * 6 * sizeof(double));
-    ALLOC(kp, M * 6 * sizeof(double));
-    ALLOC(kv, M * 6 * sizeof(double));
-    ALLOC(ks, M * 6 * sizeof(double));
-    ALLOC(kt, M * 6 * sizeof(double));
     auto solve_e = [&](bool drag, bool* ok) -> elph_status {
-      // drive: x0 (+ electron drag from the current phonons)
+      // drive b = P(x0 (+ electron drag from the current phonons)); the
+      // fixed point x = P(b + K x) solves L x = b with L = 1 - P K on the
+      // range of P, started from the previous solution
       if (drag) {
-        hipLaunchKernelGGL(k_drag_e<ST>, dim3((unsigned)M), dim3(256), 0, s, M, nbr, md, Bp, Bm, ctx->d_state_k,
-                           th.lomf, th.nocc, we, phon, De);
+#define DE(NXV)                                                                                           \
+  hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)M), dim3(256), 0, s, M, md, Bp, Bm, ctx->d_state_k, \
+                     th.lomf, th.nocc, we, phon, De)
+        switch (nbr) {
+          case 3: DE(3); break;
+          case 6: DE(6); break;
+          case 9: DE(9); break;
+          case 12: DE(12); break;
+          default: DE(15); break;
+        }
+#undef DE
       }
-      // Self-consistency of the electrons for this drive: the fixed point of
-      // x = P(b + K x) (P removes the group means), reached with BiCGSTAB on
-      // L x = P(x - K x) = P b for the six columns at once.
-      *ok = false;
-      double* b = xn;  // drive b = x0 (+ drag), projected
       hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, x0, one6,
-                         drag ? De : nullptr, zero6, (const double*)nullptr, b);
-      if (!drag) hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, x0, zero6,
-                                    (const double*)nullptr, zero6, (const double*)nullptr, b);
-      hipLaunchKernelGGL(k_project, dim3((unsigned)ctx->ngroups), dim3(256), 0, s, order, goff, wff, b);
-      auto applyL = [&](const double* in, double* out) {
-        hipLaunchKernelGGL(k_self_sweep, dim3(blocks_for(M, 4)), dim3(256), 0, s, M, K, in, in,
-                           (const double*)nullptr, -1.0, out);
-        hipLaunchKernelGGL(k_project, dim3((unsigned)ctx->ngroups), dim3(256), 0, s, order, goff, wff, out);
-      };
-      auto dots = [&](const double* a0, const double* b0, const double* a1, const double* b1, const double* a2,
-                      const double* b2, double (&out)[18]) -> elph_status {
-        const int blocks = 128;
-        hipLaunchKernelGGL(k_dots6, dim3(blocks), dim3(256), 0, s, M, a0, b0, a1, b1, a2, b2, part);
-        HIPCHK(hipMemcpyAsync(hpart.data(), part, blocks * 18 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int c = 0; c < 18; ++c) out[c] = 0.0;
-        for (int bl = 0; bl < blocks; ++bl)
-          for (int c = 0; c < 18; ++c) out[c] += hpart[bl * 18 + c];
-        return ELPH_OK;
-      };
-      // x starts from the previous solution, projected
-      hipLaunchKernelGGL(k_project, dim3((unsigned)ctx->ngroups), dim3(256), 0, s, order, goff, wff, x);
-      applyL(x, kv);
-      hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, b, mone6, kv, zero6,
-                         (const double*)nullptr, kr);  // r = b - L x
-      HIPCHK(hipMemcpyAsync(krh, kr, M * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemsetAsync(kp, 0, M * 6 * sizeof(double), s));
-      HIPCHK(hipMemsetAsync(kv, 0, M * 6 * sizeof(double), s));
-      double rho_old[6], alpha[6], omega[6], d[18];
-      bool done[6];
-      for (int c = 0; c < 6; ++c) {
-        rho_old[c] = alpha[c] = omega[c] = 1.0;
-        done[c] = false;
-      }
-      elph_status e2 = dots(b, b, x, x, kr, kr, d);
+                         drag ? De : nullptr, zero6, (const double*)nullptr, sv.b);
+      hipLaunchKernelGGL(k_project, dim3(ng), dim3(256), 0, s, order, goff, wff, sv.b);
+      hipLaunchKernelGGL(k_project, dim3(ng), dim3(256), 0, s, order, goff, wff, x);
+      elph_status e2 = self_solve(ctx, sv, x, tol, maxit, ok, &last_inner);
       if (e2 != ELPH_OK) return e2;
-      double bnorm[6];
-      for (int c = 0; c < 6; ++c) {
-        bnorm[c] = std::sqrt(d[c]);
-        done[c] = std::sqrt(d[12 + c]) <= 0.1 * tol * std::max(bnorm[c], 1e-300);
-      }
-      for (int it = 0; it < maxit && !std::all_of(done, done + 6, [](bool v) { return v; }); ++it) {
-        last_inner = it + 1;
-        e2 = dots(krh, kr, nullptr, nullptr, nullptr, nullptr, d);
-        if (e2 != ELPH_OK) return e2;
-        Col6 beta, mbo;
-        for (int c = 0; c < 6; ++c) {
-          const double rho = d[c];
-          if (done[c] || rho == 0.0 || omega[c] == 0.0) {
-            beta.v[c] = 0.0;
-            mbo.v[c] = 0.0;
-            rho_old[c] = rho;
-            continue;
-          }
-          beta.v[c] = (rho / rho_old[c]) * (alpha[c] / omega[c]);
-          mbo.v[c] = -beta.v[c] * omega[c];
-          rho_old[c] = rho;
-        }
-        // p = r + beta p - beta omega v
-        hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, kr, beta, kp, mbo, kv, kp);
-        applyL(kp, kv);
-        e2 = dots(krh, kv, nullptr, nullptr, nullptr, nullptr, d);
-        if (e2 != ELPH_OK) return e2;
-        Col6 ma;
-        for (int c = 0; c < 6; ++c) {
-          alpha[c] = (!done[c] && d[c] != 0.0) ? rho_old[c] / d[c] : 0.0;
-          ma.v[c] = -alpha[c];
-        }
-        // s = r - alpha v  (into ks)
-        hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, kr, ma, kv, zero6,
-                           (const double*)nullptr, ks);
-        applyL(ks, kt);
-        e2 = dots(kt, ks, kt, kt, nullptr, nullptr, d);
-        if (e2 != ELPH_OK) return e2;
-        Col6 al, om, mom;
-        for (int c = 0; c < 6; ++c) {
-          omega[c] = (!done[c] && d[6 + c] > 0.0) ? d[c] / d[6 + c] : 0.0;
-          al.v[c] = done[c] ? 0.0 : alpha[c];
-          om.v[c] = done[c] ? 0.0 : omega[c];
-          mom.v[c] = -om.v[c];
-        }
-        // x = x + alpha p + omega s ; r = s - omega t
-        hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, x, al, kp, om, ks, x);
-        hipLaunchKernelGGL(k_lin6, dim3(blocks_for(M * 6, 256)), dim3(256), 0, s, M, ks, mom, kt, zero6,
-                           (const double*)nullptr, kr);
-        e2 = dots(kr, kr, nullptr, nullptr, nullptr, nullptr, d);
-        if (e2 != ELPH_OK) return e2;
-        for (int c = 0; c < 6; ++c)
-          if (!done[c] && std::sqrt(d[c]) <= 0.1 * tol * std::max(bnorm[c], 1e-300)) done[c] = true;
-      }
-      *ok = std::all_of(done, done + 6, [](bool v) { return v; });
+      // remove what rounding left along the group directions
+      hipLaunchKernelGGL(k_project, dim3(ng), dim3(256), 0, s, order, goff, wff, x);
+      HIPCHK(hipGetLastError());
       return ELPH_OK;
     };
 
@@ -1151,9 +1109,6 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
         }
       }
     }
-    dev_free(ctx, order);
-    dev_free(ctx, goff);
-    for (double* pbuf : {kr, krh, kp, kv, ks, kt}) dev_free(ctx, pbuf);
   }
 
   // outputs
@@ -1201,8 +1156,8 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   }
   HIPCHK(hipStreamSynchronize(s));
   if (iters) *iters = used;
-  for (void* p : {(void*)we, (void*)wphe, (void*)wp, (void*)x0, (void*)x, (void*)xn, (void*)De, (void*)phon0,
-                  (void*)phon, (void*)phonn, (void*)acc, (void*)K, (void*)part, (void*)wff, (void*)xprev})
+  for (void* p : {(void*)we, (void*)wphe, (void*)wp, (void*)x0, (void*)x, (void*)De, (void*)phon0, (void*)phon,
+                  (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase})
     dev_free(ctx, p);
   free_thermal(ctx, &th);
   if (!converged) {

@@ -530,28 +530,6 @@ __global__ void k_max_reduce(const double* __restrict__ x, int64_t n, double* __
 // ---------------------------------------------------------------------------
 // host drivers
 
-#define HIPCHK(x)                                                       \
-  do {                                                                  \
-    hipError_t e_ = (x);                                                \
-    if (e_ != hipSuccess) {                                             \
-      ctx->err = std::string("HIP error ") + hipGetErrorString(e_) +    \
-                 " at " + __FILE__ + ":" + std::to_string(__LINE__);    \
-      ctx->hip_dead = true;                                             \
-      return ELPH_EHIP;                                                 \
-    }                                                                   \
-  } while (0)
-
-#define ALLOC(ptr, bytes)                                                          \
-  do {                                                                             \
-    void* p_ = nullptr;                                                            \
-    hipError_t e_ = dev_alloc(ctx, &p_, (size_t)(bytes));                          \
-    if (e_ != hipSuccess) {                                                        \
-      ctx->err = "device allocation of " + std::to_string((size_t)(bytes)) + " bytes failed"; \
-      (void)hipGetLastError();                                                     \
-      return ELPH_ENOMEM;                                                          \
-    }                                                                              \
-    ptr = (decltype(ptr))p_;                                                       \
-  } while (0)
 
 static int fourier_kpb(int n, int nR) {
   int kpb = 256 / (n * n);

@@ -23,12 +23,34 @@ template <typename ST, int NV>
 void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x, double* acc);
 void free_thermal(elph_ctx ctx, Thermal* th);
 elph_status ensure_store(elph_ctx ctx);
+// pair lists by q used by the q-gathers (built once per table build)
+elph_status ensure_pairs(elph_ctx ctx);
 elph_status rates_from_store(elph_ctx ctx, const Thermal& th, double* we, double* wph);
 elph_status x_from_store(elph_ctx ctx, const Thermal& th, double* Xp, double* Xm);
 elph_status finalize_wph(elph_ctx ctx, const Thermal& th, double* acc, double* wph);
 elph_status interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx, double* g_out);
 elph_status iterate(elph_ctx ctx, double T, const double* wext, int level, double tol, int maxit, double* I,
                     double* J, double* F, double* G, double* tensors, int* iters, double* ko);
+
+// electron self-consistency solver (solve.hip)
+struct SelfSolver {
+  double* KT = nullptr;                 // [M][M] transposed, group-projected self operator
+  double *b = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
+  double* part = nullptr;               // [S][M][6] split partials of the matrix-vector product
+  double* dpart = nullptr;              // [nblk][12] dot partials
+  double* sc = nullptr;                 // device scalars
+  int S = 1, nblk = 1;
+  int64_t jlen = 1;
+};
+size_t self_solver_doubles(int64_t M);
+void self_solver_carve(int64_t M, double* base, SelfSolver* sv);
+template <typename ST>
+elph_status build_self_operator(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc,
+                                const double* we, const int32_t* order, const int32_t* goff, const double* wff,
+                                double* KT);
+// Solves L x = b (b in sv.b, projected; x projected on entry) to relative
+// residual 0.1 tol per column; *ok when all six columns reached it.
+elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double tol, int maxit, bool* ok, int* iters);
 
 // batches of materials in persistent launches (vertex.hip)
 struct BatchImpl;

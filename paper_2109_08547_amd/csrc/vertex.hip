@@ -289,15 +289,18 @@ struct EpiParams {
   int64_t m_pad;
 };
 
-__device__ inline int64_t q_of(int64_t kj, int64_t ki, int n0, int n1, int n2) {
-  int cj = (int)(kj % n2), ci = (int)(ki % n2);
-  int64_t tj = kj / n2, ti = ki / n2;
-  int bj = (int)(tj % n1), bi = (int)(ti % n1);
-  int aj = (int)(tj / n1), ai = (int)(ti / n1);
-  int a = aj - ai; if (a < 0) a += n0;
-  int b = bj - bi; if (b < 0) b += n1;
-  int c = cj - ci; if (c < 0) c += n2;
-  return ((int64_t)a * n1 + b) * n2 + c;
+__device__ inline int q_of(int kj, int ki, int n0, int n1, int n2) {
+  const unsigned uj = (unsigned)kj, ui = (unsigned)ki;
+  const unsigned u2 = (unsigned)n2, u1 = (unsigned)n1;
+  const unsigned tj = uj / u2, ti = ui / u2;
+  int c = (int)(uj - tj * u2) - (int)(ui - ti * u2);
+  const unsigned aj = tj / u1, ai = ti / u1;
+  int b = (int)(tj - aj * u1) - (int)(ti - ai * u1);
+  int a = (int)aj - (int)ai;
+  if (a < 0) a += n0;
+  if (b < 0) b += n1;
+  if (c < 0) c += n2;
+  return (a * n1 + b) * n2 + c;
 }
 
 // Step-2 contraction of one material with its epilogue parameters.
@@ -780,6 +783,13 @@ static elph_status batch_prepare_t(BatchImpl* b) {
     elph_status st = build_tables(c);
     if (st == ELPH_OK) st = build_operands(c);
     if (st == ELPH_OK) st = ensure_we_part(c);
+    // pair lists now, so that no allocation happens under graph capture
+    if (st == ELPH_OK && !c->pairs_ready && !c->pairs_failed && c->nkept <= kMaxPairKept) {
+      if (ensure_pairs(c) != ELPH_OK) {
+        c->pairs_failed = true;
+        c->err.clear();
+      }
+    }
     if (st != ELPH_OK) {
       b->err = "material " + std::to_string(m) + ": " + c->err;
       return st;

@@ -161,7 +161,7 @@ def elph_destroy(ctx):
     ctx.close()
 
 
-ELPH_RESET_ALL, ELPH_RESET_STORE = 0, 1
+ELPH_RESET_ALL, ELPH_RESET_STORE, ELPH_RESET_TRIM = 0, 1, 2
 
 
 def elph_reset(ctx, what=ELPH_RESET_ALL):
