@@ -245,6 +245,69 @@ elph_status elph_batch_scatt_rates(elph_batch b, double T_K, double* const* W_e,
  * best_ms (host, may be NULL) the per-evaluation time of the winner. */
 elph_status elph_batch_tune(elph_batch b, double T_K, int32_t* choice, double* best_ms);
 
+/* ---------------------------------------------------------------------------
+ * Learned screen of negligible terms.  A small MLP predicts log10 |g|^2
+ * (|g^{s n m}_{k q}|^2 of Eq. 6 in eV^2) of a term from its features; with
+ * the exact Gaussian delta and occupations of Eq. 8 this gives a predicted
+ * X of every term, and the step-2 tiles whose predicted terms all lie below
+ * tau times the largest predicted term of their initial state are skipped.
+ * The exact path stays the judge: callers compare the screened rates with
+ * elph_scatt_rates.
+ *
+ * Network: depth hidden layers of `width` units, z = a W + b, a = GELU(z)
+ * (z Phi(z), Phi the normal CDF), output y = a w + b; loss = mean squared
+ * error.  Products run on BF16 copies of the weights with FP32 accumulation;
+ * FP32 master weights are updated by Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * params (host, FP32): for each layer in order W [fan_in][fan_out] row-major
+ * then b [fan_out]; elph_mlp_nparams gives the length. */
+typedef struct elph_mlp_s* elph_mlp;
+
+/* 1 <= nin <= 1024; width a multiple of 64 in [64, 1024]; 1 <= depth <= 8.
+ * hip_stream: NULL = default stream.  Errors: EINVAL (sizes, non-finite
+ * params), ENOMEM. */
+elph_status elph_mlp_create(int32_t nin, int32_t width, int32_t depth, const float* params,
+                            void* hip_stream, elph_mlp* out);
+void elph_mlp_destroy(elph_mlp m);
+const char* elph_mlp_last_error(elph_mlp m);
+int64_t elph_mlp_nparams(elph_mlp m);
+/* FP32 master parameters to / from the host; setting resets Adam. */
+elph_status elph_mlp_get_params(elph_mlp m, float* params);
+elph_status elph_mlp_set_params(elph_mlp m, const float* params);
+/* y [n] = network(x [n][nin]); x, y device FP32. */
+elph_status elph_mlp_forward(elph_mlp m, int64_t n, const float* x, float* y);
+/* Gradient of the loss over a batch (n a positive multiple of 64) into grad
+ * [nparams] (device FP32, may be NULL); loss (host, may be NULL). */
+elph_status elph_mlp_gradients(elph_mlp m, int64_t n, const float* x, const float* t, float* grad,
+                               double* loss);
+/* One Adam step of learning rate lr on the batch; loss before the step. */
+elph_status elph_mlp_train_step(elph_mlp m, int64_t n, const float* x, const float* t, float lr,
+                                double* loss);
+
+/* Number of screen features of a context: 9 + 2 nwann + nbr, in the order
+ * k (3 fractional coordinates), q (3), eps_{m k}, eps_{n k+q} (eV, relative
+ * to mu), hbar omega_{q s} / hbar omega_max, one-hot m (nwann), one-hot n
+ * (nwann), one-hot s (nbr). */
+int32_t elph_screen_nin(elph_ctx ctx);
+
+/* Training samples from the exact vertex (Eq. 6): for every mesh pair
+ * (kidx[p], qidx[p]) (device int32) and every (s, n, m), a feature row of
+ * x [npairs * nbr * nwann^2][nin] and the target t = log10(max(|g|^2, 1e-12))
+ * (device FP32), ordered like elph_interp_g. */
+elph_status elph_screen_samples(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
+                                const int32_t* qidx, float* x, float* t);
+
+enum { ELPH_SCREEN_NONE = 0, ELPH_SCREEN_ENERGY = 1, ELPH_SCREEN_MLP = 2 };
+/* Screened RTA rates at T (outputs as elph_scatt_rates).  mode ENERGY keeps
+ * a term when one of its Gaussian factors exceeds exp(-18) (|dE -/+ hw| <
+ * 6 sigma; m may be NULL); mode MLP keeps it when its predicted X is at
+ * least tau times the largest predicted X of its initial state.  A step-2
+ * tile (32 final x 32 initial states) is computed when any of its terms is
+ * kept, otherwise its vertex-store entries are zero.  The vertex store is
+ * replaced by the screened one.  stats (host, may be NULL) [4]: tiles,
+ * tiles computed, terms evaluated by the screen, screen time (ms). */
+elph_status elph_scatt_rates_screened(elph_ctx ctx, elph_mlp m, int32_t mode, double tau, double T_K,
+                                      double* W_e, double* W_ph, double* stats);
+
 #ifdef __cplusplus
 }
 #endif

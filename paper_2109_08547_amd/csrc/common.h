@@ -138,6 +138,7 @@ struct elph_ctx_s {
   double rates_T = -1.0;
   bool rates_valid = false;
   double* h_pin = nullptr;        // pinned host words for solver status reads
+  const uint8_t* d_tile_keep = nullptr;  // step-2 tile mask of a screened evaluation (else null)
 
   // device memory: live blocks (pointer, bytes) and released blocks kept for
   // reuse by later allocations of the same size (freed by elph_destroy or

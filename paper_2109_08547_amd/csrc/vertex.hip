@@ -287,6 +287,7 @@ struct EpiParams {
   double* we_part;           // [gridDim.x][m_pad]
   double* wph_acc;           // [nk][nbr]
   int64_t m_pad;
+  const uint8_t* tile_keep;  // [m_pad/32][m_pad/32] computed tiles (null = all)
 };
 
 __device__ inline int q_of(int kj, int ki, int n0, int n1, int n2) {
@@ -325,6 +326,21 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
   ST* __restrict__ Bp = (ST*)d.Bp;
   ST* __restrict__ Bm = (ST*)d.Bm;
   const EpiParams& ep = d.ep;
+  if (ep.tile_keep && !ep.tile_keep[bx * (ep.m_pad / 32) + by]) {
+    // screened out: zero vertex-store entries and W_e partials of the tile
+    for (int e = threadIdx.x; e < 32 * 32 * NX; e += 256) {
+      const int s = e % NX, jj = (e / NX) % 32, ii = e / (NX * 32);
+      const int64_t i = by * 32 + ii, j = bx * 32 + jj;
+      if (i < ep.nstates && j < ep.nstates) {
+        const int64_t tb = (i * ep.nstates + j) * NX + s;
+        Bp[tb] = (ST)0;
+        Bm[tb] = (ST)0;
+      }
+    }
+    if (ep.we_part && threadIdx.x < 32 && by * 32 + threadIdx.x < ep.nstates)
+      ep.we_part[bx * ep.m_pad + by * 32 + threadIdx.x] = 0.0;
+    return;
+  }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t j0 = bx * 32 + (wave >> 1) * 16;
@@ -628,6 +644,7 @@ static EpiParams epi_params(elph_ctx ctx) {
   ep.lomf = ep.fstate = ep.omf = ep.nocc = nullptr;
   ep.we_part = nullptr;
   ep.wph_acc = nullptr;
+  ep.tile_keep = ctx->d_tile_keep;
   return ep;
 }
 

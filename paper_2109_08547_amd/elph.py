@@ -44,7 +44,13 @@ class ElphSizes(ctypes.Structure):
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
            "elph_batch_tune", "elph_tables",
-           "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate")
+           "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate",
+           "elph_mlp_create", "elph_mlp_destroy", "elph_mlp_last_error", "elph_mlp_nparams",
+           "elph_mlp_get_params", "elph_mlp_set_params", "elph_mlp_forward", "elph_mlp_gradients",
+           "elph_mlp_train_step", "elph_screen_nin", "elph_screen_samples", "elph_scatt_rates_screened")
+_NO_STATUS = ("elph_destroy", "elph_last_error", "elph_batch_destroy", "elph_batch_last_error", "elph_mlp_destroy",
+              "elph_mlp_last_error", "elph_mlp_nparams", "elph_screen_nin")
+ELPH_SCREEN_NONE, ELPH_SCREEN_ENERGY, ELPH_SCREEN_MLP = range(3)
 
 _lib = None
 
@@ -82,8 +88,24 @@ def load():
     lib.elph_batch_scatt_rates.argtypes = [vp, ctypes.c_double, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                            ctypes.c_int32]
     lib.elph_batch_tune.argtypes = [vp, ctypes.c_double, vp, vp]
+    lib.elph_mlp_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.POINTER(vp)]
+    lib.elph_mlp_destroy.argtypes = [vp]
+    lib.elph_mlp_destroy.restype = None
+    lib.elph_mlp_last_error.argtypes = [vp]
+    lib.elph_mlp_last_error.restype = ctypes.c_char_p
+    lib.elph_mlp_nparams.argtypes = [vp]
+    lib.elph_mlp_nparams.restype = ctypes.c_int64
+    lib.elph_mlp_get_params.argtypes = [vp, vp]
+    lib.elph_mlp_set_params.argtypes = [vp, vp]
+    lib.elph_mlp_forward.argtypes = [vp, ctypes.c_int64, vp, vp]
+    lib.elph_mlp_gradients.argtypes = [vp, ctypes.c_int64, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.elph_mlp_train_step.argtypes = [vp, ctypes.c_int64, vp, vp, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]
+    lib.elph_screen_nin.argtypes = [vp]
+    lib.elph_screen_nin.restype = ctypes.c_int32
+    lib.elph_screen_samples.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+    lib.elph_scatt_rates_screened.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, vp, vp, vp]
     for name in EXPORTS:
-        if name not in ("elph_destroy", "elph_last_error", "elph_batch_destroy", "elph_batch_last_error"):
+        if name not in _NO_STATUS:
             getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -267,3 +289,92 @@ def elph_batch_tune(batch, T):
     batch._check(load().elph_batch_tune(batch.handle, float(T), ch.ctypes.data_as(ctypes.c_void_p),
                                         ctypes.byref(best)))
     return {"blocks_per_cu": int(ch[0]), "cost_ordered": bool(ch[1]), "best_ms": best.value}
+
+
+# ---------------------------------------------------------------------------
+# learned screen
+
+
+class MLP:
+    """Owns an elph_mlp handle (the screening network)."""
+
+    def __init__(self, nin, width, depth, params, stream=None):
+        lib = load()
+        self.nin, self.width, self.depth = int(nin), int(width), int(depth)
+        prm = _arr(params, np.float32)
+        h = ctypes.c_void_p()
+        st = lib.elph_mlp_create(self.nin, self.width, self.depth, prm.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if st != ELPH_OK:
+            raise ElphError(st, lib.elph_mlp_last_error(None).decode())
+        self.handle = h
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().elph_mlp_destroy(self.handle)
+            self.handle = None
+
+    def _check(self, st):
+        if st != ELPH_OK:
+            raise ElphError(st, load().elph_mlp_last_error(self.handle).decode())
+
+
+def elph_mlp_create(nin, width, depth, params, stream=None):
+    return MLP(nin, width, depth, params, stream)
+
+
+def elph_mlp_nparams(mlp):
+    return int(load().elph_mlp_nparams(mlp.handle))
+
+
+def elph_mlp_get_params(mlp):
+    out = np.empty(elph_mlp_nparams(mlp), dtype=np.float32)
+    mlp._check(load().elph_mlp_get_params(mlp.handle, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def elph_mlp_set_params(mlp, params):
+    prm = _arr(params, np.float32)
+    mlp._check(load().elph_mlp_set_params(mlp.handle, prm.ctypes.data_as(ctypes.c_void_p)))
+
+
+def elph_mlp_forward(mlp, x, y):
+    """x [n][nin], y [n]: FP32 GPU tensors."""
+    mlp._check(load().elph_mlp_forward(mlp.handle, int(y.numel()), _ptr(x), _ptr(y)))
+
+
+def elph_mlp_gradients(mlp, x, t, grad=None):
+    loss = ctypes.c_double(0.0)
+    mlp._check(load().elph_mlp_gradients(mlp.handle, int(t.numel()), _ptr(x), _ptr(t), _ptr(grad),
+                                         ctypes.byref(loss)))
+    return loss.value
+
+
+def elph_mlp_train_step(mlp, x, t, lr):
+    loss = ctypes.c_double(0.0)
+    mlp._check(load().elph_mlp_train_step(mlp.handle, int(t.numel()), _ptr(x), _ptr(t), ctypes.c_float(lr),
+                                          ctypes.byref(loss)))
+    return loss.value
+
+
+def elph_screen_nin(ctx):
+    return int(load().elph_screen_nin(ctx.handle))
+
+
+def elph_screen_samples(ctx, kidx, qidx, x, t):
+    """kidx, qidx: int32 GPU tensors [npairs]; x [npairs*nbr*nb*nb][nin],
+    t [npairs*nbr*nb*nb]: FP32 GPU tensors."""
+    _check(ctx, load().elph_screen_samples(ctx.handle, int(kidx.numel()), _ptr(kidx), _ptr(qidx), _ptr(x),
+                                           _ptr(t)))
+
+
+def elph_scatt_rates_screened(ctx, mlp, mode, tau, T, W_e=None, W_ph=None):
+    stats = np.zeros(4, dtype=np.float64)
+    _check(ctx, load().elph_scatt_rates_screened(ctx.handle, mlp.handle if mlp is not None else None, int(mode),
+                                                 float(tau), float(T), _ptr(W_e), _ptr(W_ph),
+                                                 stats.ctypes.data_as(ctypes.c_void_p)))
+    return {"tiles": int(stats[0]), "tiles_computed": int(stats[1]), "terms_screened": int(stats[2]),
+            "screen_ms": float(stats[3])}

@@ -32,3 +32,12 @@ def unflatten(flat, nin, width=256, depth=3):
         o += b
         out.append((W, bias))
     return out
+
+
+def bf16_round(a):
+    """Round float32 values to the nearest bfloat16 (ties to even), returned
+    as float32: the effective values of BF16 weights and inputs."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).reshape(a.shape)

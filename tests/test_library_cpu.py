@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "elph.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:elph_status|void|const char\*)\s+(elph_\w+)\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:elph_status|void|const char\*|int64_t|int32_t)\s+(elph_\w+)\(", src, re.M)))
 
 
 def test_exports_match_header():
@@ -78,3 +78,15 @@ def test_rejects_unsupported_sizes():
     big = dict(mat)
     big["natom"] = 6
     assert _create_status(big)[0] == E.elph.ELPH_EINVAL
+
+
+def test_mlp_create_rejects_bad_shapes_before_device_work():
+    prm = np.zeros(10, dtype=np.float32)
+    for nin, width, depth in ((0, 64, 1), (8, 100, 1), (8, 64, 0), (8, 64, 9), (2000, 64, 1)):
+        with pytest.raises(E.ElphError) as ei:
+            E.elph_mlp_create(nin, width, depth, prm)
+        assert ei.value.status == E.elph.ELPH_EINVAL
+
+
+def test_screen_nin_of_null_context_is_zero():
+    assert E.elph.load().elph_screen_nin(None) == 0

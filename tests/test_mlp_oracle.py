@@ -47,3 +47,15 @@ def test_adam_first_step_is_lr_times_sign():
     p, _, _ = mo.adam_step(params, grads, m, v, 1, 0.01, eps=1e-12)
     assert np.allclose(p[0][0], 1.0 - 0.01)
     assert np.allclose(p[0][1], [0.01, 0.0, -0.01])
+
+
+def test_bf16_round_grid_and_ties():
+    grid = np.array([1.0, 1.0078125, -2.5, 3.0e-3, 0.0], np.float32)
+    grid = synth.mlp.bf16_round(grid)
+    assert np.array_equal(synth.mlp.bf16_round(grid), grid)
+    # halfway between 1 and 1 + 2^-7 goes to the even mantissa (1.0);
+    # halfway between 1 + 2^-7 and 1 + 2^-6 goes to 1 + 2^-6
+    assert synth.mlp.bf16_round(np.float32(1.0 + 2.0 ** -8)) == 1.0
+    assert synth.mlp.bf16_round(np.float32(1.0 + 3 * 2.0 ** -8)) == np.float32(1.0 + 2.0 ** -6)
+    x = np.random.default_rng(0).standard_normal(1000).astype(np.float32)
+    assert np.max(np.abs(synth.mlp.bf16_round(x) - x) / np.abs(x)) <= 2.0 ** -8
