@@ -95,7 +95,7 @@ static elph_status validate(const elph_wannier* w, const elph_params* p) {
   if (!(p->window_eV > 0)) return fail_create("window must be positive (INFINITY keeps all)");
   if (!std::isfinite(p->mu_eV)) return fail_create("mu must be finite");
   if (p->omega_min_eV < 0 || !std::isfinite(p->omega_min_eV)) return fail_create("omega_min must be >= 0");
-  if (p->precision != ELPH_FP64 && p->precision != ELPH_FP32) return fail_create("precision form not available");
+  if (p->precision < ELPH_FP64 || p->precision > ELPH_BF16X6) return fail_create("unknown precision form");
   const int nb = w->nwann, nbr = 3 * w->natom;
   const size_t nn = (size_t)nb * nb, mm = (size_t)nbr * nbr;
   if (!all_finite(w->lat, 9) || !all_finite(w->mass, w->natom)) return fail_create("non-finite lattice or mass");

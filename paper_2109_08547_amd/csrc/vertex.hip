@@ -62,6 +62,124 @@ struct Mfma<float> {
   static constexpr bool kFold = true;
 };
 
+// BF16 split forms: every operand value a = a_1 + a_2 (+ a_3), each a_s a
+// BF16 number (a_1 = bf16(a), a_2 = bf16(a - a_1), ...).  Storage per row:
+// groups of 8 consecutive k, each group holding the planes re_1, im_1, re_2,
+// im_2 (, re_3, im_3) of 8 BF16 values (16 bytes), so that a lane reads its
+// 8-k MFMA fragment of every plane with 16-byte loads.
+template <int NS>
+struct Bf16S {};
+
+template <typename T>
+struct Store {
+  typedef T type;
+  static constexpr int per_c = 2;      // storage elements per complex value
+  static constexpr int kalign = 16;    // padding of the contraction length
+};
+template <int NS>
+struct Store<Bf16S<NS>> {
+  typedef unsigned short type;
+  static constexpr int per_c = 2 * NS;
+  static constexpr int kalign = 32;
+};
+
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned short us8v __attribute__((ext_vector_type(8)));
+
+template <int NS>
+struct Mfma<Bf16S<NS>> {
+  typedef f4 acc_t;
+  __device__ static inline acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static inline acc_t mma(us8v a, us8v b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0,
+                                                  0, 0);
+  }
+  __device__ static inline int row(int lk, int r) { return 4 * lk + r; }
+  static constexpr bool kFold = true;
+};
+
+// BF16 nearest (ties to even) of a double, through its float value
+__device__ inline unsigned short bf16_of(double v) {
+  unsigned u = __float_as_uint((float)v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline double bf16_val(unsigned short h) { return (double)__uint_as_float(((unsigned)h) << 16); }
+
+// write the complex value (re, im) at (row, k) of an operand of padded length K
+template <typename T>
+__device__ inline void put_c(typename Store<T>::type* base, int64_t row, int64_t K, int64_t k, double re, double im) {
+  base[2 * (row * K + k)] = (T)re;
+  base[2 * (row * K + k) + 1] = (T)im;
+}
+
+template <int NS>
+__device__ inline void put_split(unsigned short* base, int64_t row, int64_t K, int64_t k, double re, double im) {
+  unsigned short* g = base + row * K * 2 * NS + (k >> 3) * (16 * NS) + (k & 7);
+  double r = re, i = im;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const unsigned short hr = bf16_of(r), hi = bf16_of(i);
+    g[(2 * s) * 8] = hr;
+    g[(2 * s + 1) * 8] = hi;
+    r -= bf16_val(hr);
+    i -= bf16_val(hi);
+  }
+}
+
+template <typename T>
+struct PutC {
+  __device__ static inline void put(typename Store<T>::type* base, int64_t row, int64_t K, int64_t k, double re,
+                                    double im) {
+    put_c<T>(base, row, K, k, re, im);
+  }
+};
+template <int NS>
+struct PutC<Bf16S<NS>> {
+  __device__ static inline void put(unsigned short* base, int64_t row, int64_t K, int64_t k, double re, double im) {
+    put_split<NS>(base, row, K, k, re, im);
+  }
+};
+
+// Products of a split complex fragment pair, smallest terms first:
+// cr += Re(a) Re(b) - Im(a) Im(b), ci += Re(a) Im(b) + Im(a) Re(b), keeping
+// the split pairs (s_a, s_b) with s_a + s_b <= 1 (NS = 2: three products)
+// or <= 2 (NS = 3: six products).
+template <int NS>
+__device__ inline void split_cmma(const us8v (&a)[2 * NS], const us8v (&na_im)[NS], const us8v (&b)[2 * NS], f4& cr,
+                                  f4& ci) {
+  typedef Mfma<Bf16S<NS>> MM;
+  constexpr int np = NS == 2 ? 3 : 6;
+#pragma unroll
+  for (int t = 0; t < np; ++t) {
+    int sa, sb;
+    if (NS == 2) {  // (0,1), (1,0), (0,0)
+      sa = t == 1 ? 1 : 0;
+      sb = t == 0 ? 1 : 0;
+    } else {        // (1,1), (0,2), (2,0), (0,1), (1,0), (0,0)
+      sa = t == 0 ? 1 : t == 2 ? 2 : t == 4 ? 1 : 0;
+      sb = t == 0 ? 1 : t == 1 ? 2 : t == 3 ? 1 : 0;
+    }
+    cr = MM::mma(a[2 * sa], b[2 * sb], cr);
+    cr = MM::mma(na_im[sa], b[2 * sb + 1], cr);
+    ci = MM::mma(a[2 * sa], b[2 * sb + 1], ci);
+    ci = MM::mma(a[2 * sa + 1], b[2 * sb], ci);
+  }
+}
+
+template <int NS>
+__device__ inline void load_split(const unsigned short* p, us8v (&v)[2 * NS]) {
+#pragma unroll
+  for (int s = 0; s < 2 * NS; ++s) v[s] = *reinterpret_cast<const us8v*>(p + 8 * s);
+}
+
+template <int NS>
+__device__ inline void neg_im(const us8v (&a)[2 * NS], us8v (&na)[NS]) {
+  const us8v sign = {0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) na[s] = a[2 * s + 1] ^ sign;
+}
+
 template <typename T>
 struct Cplx {
   T x, y;
@@ -84,7 +202,7 @@ __device__ inline Cplx<T> ldc(const T* p) {
 template <typename T>
 __global__ void k_build_Ae(int64_t nstates, int nb, int nre, int64_t ke, const int32_t* __restrict__ st_kidx,
                            const int32_t* __restrict__ st_m, const cd* __restrict__ Ee, const cd* __restrict__ U,
-                           T* __restrict__ Ae) {
+                           typename Store<T>::type* __restrict__ Ae) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t cols = (int64_t)nre * nb;
   if (e >= nstates * cols) return;
@@ -93,14 +211,14 @@ __global__ void k_build_Ae(int64_t nstates, int nb, int nre, int64_t ke, const i
   int r = (int)(col / nb), mp = (int)(col % nb);
   int t = st_kidx[i], m = st_m[i];
   cd z = cmul(Ee[(int64_t)t * nre + r], U[((int64_t)t * nb + mp) * nb + m]);
-  Ae[2 * (i * ke + col)] = (T)z.x;
-  Ae[2 * (i * ke + col) + 1] = (T)z.y;
+  PutC<T>::put(Ae, i, ke, col, z.x, z.y);
 }
 
 template <typename T>
 __global__ void k_build_Ap(int64_t nstates, int nb, int nrp, int64_t kp, const int32_t* __restrict__ st_kidx,
                            const int32_t* __restrict__ st_m, const cd* __restrict__ Ep,
-                           const double* __restrict__ wrp, const cd* __restrict__ U, T* __restrict__ Ap) {
+                           const double* __restrict__ wrp, const cd* __restrict__ U,
+                           typename Store<T>::type* __restrict__ Ap) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t cols = (int64_t)nrp * nb;
   if (e >= nstates * cols) return;
@@ -110,14 +228,13 @@ __global__ void k_build_Ap(int64_t nstates, int nb, int nrp, int64_t kp, const i
   int t = st_kidx[j], n = st_m[j];
   cd z = cmul(Ep[(int64_t)t * nrp + r], cconj(U[((int64_t)t * nb + np) * nb + n]));
   if (wrp) z = cscale(z, wrp[r]);
-  Ap[2 * (j * kp + col)] = (T)z.x;
-  Ap[2 * (j * kp + col) + 1] = (T)z.y;
+  PutC<T>::put(Ap, j, kp, col, z.x, z.y);
 }
 
 // gR[(x, Rp, n')][(Re, m')] = g[Re][Rp][x][n'][m']
 template <typename T>
 __global__ void k_permute_g(int nre, int nrp, int nbr, int nb, int64_t ke, const double* __restrict__ g,
-                            T* __restrict__ gR) {
+                            typename Store<T>::type* __restrict__ gR) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)nre * nrp * nbr * nb * nb;
   if (e >= total) return;
@@ -131,8 +248,7 @@ __global__ void k_permute_g(int nre, int nrp, int nbr, int nb, int64_t ke, const
   int re = (int)(t / nrp);
   int64_t row = ((int64_t)x * nrp + rp) * nb + np;
   int64_t col = (int64_t)re * nb + mp;
-  gR[2 * (row * ke + col)] = (T)g[2 * e];
-  gR[2 * (row * ke + col) + 1] = (T)g[2 * e + 1];
+  PutC<T>::put(gR, row, ke, col, g[2 * e], g[2 * e + 1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -143,12 +259,23 @@ __global__ void k_permute_g(int nre, int nrp, int nbr, int nb, int64_t ke, const
 template <typename T>
 struct S1Desc {
   int64_t m_pad, ncol, ke, kp, nstates;
-  const T* Ae;
-  const T* gR;
-  T* B2;
+  const typename Store<T>::type* Ae;
+  const typename Store<T>::type* gR;
+  typename Store<T>::type* B2;
   int nrp, nb, nbr;
   const int32_t* st_kidx;
   const cd* Ep;
+};
+
+template <typename T>
+struct IsSplit {
+  static constexpr bool value = false;
+  static constexpr int ns = 0;
+};
+template <int NS>
+struct IsSplit<Bf16S<NS>> {
+  static constexpr bool value = true;
+  static constexpr int ns = NS;
 };
 
 // One 64 x 64 output tile (block column bx, block row by) of step 1.
@@ -156,10 +283,11 @@ template <typename T>
 __device__ __forceinline__ void step1_tile(const S1Desc<T>& d, int64_t bx, int64_t by) {
   typedef Mfma<T> MM;
   typedef typename MM::acc_t acc_t;
+  typedef typename Store<T>::type SE;
   const int64_t ncol = d.ncol, ke = d.ke, kp = d.kp, nstates = d.nstates;
-  const T* __restrict__ Ae = d.Ae;
-  const T* __restrict__ gR = d.gR;
-  T* __restrict__ B2 = d.B2;
+  const SE* __restrict__ Ae = d.Ae;
+  const SE* __restrict__ gR = d.gR;
+  SE* __restrict__ B2 = d.B2;
   const int nrp = d.nrp, nb = d.nb, nbr = d.nbr;
   const int32_t* __restrict__ st_kidx = d.st_kidx;
   const cd* __restrict__ Ep = d.Ep;
@@ -169,18 +297,9 @@ __device__ __forceinline__ void step1_tile(const S1Desc<T>& d, int64_t bx, int64
   const int64_t n0 = bx * 64 + (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
 
-  const T* pa[2];
-  const T* pb[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    pa[t] = Ae + 2 * ((m0 + 16 * t + lr) * ke + lk);
-    int64_t nrow = n0 + 16 * t + lr;
-    if (nrow >= ncol) nrow = ncol - 1;
-    pb[t] = gR + 2 * (nrow * ke + lk);
-  }
   acc_t cr[2][2], ci[2][2];
-  // FP64 running sums: the FP32 form folds its MFMA accumulators in every 16 k
-  // so that rounding is relative to a 16-term partial, not the whole sum
+  // FP64 running sums: the FP32 and BF16 forms fold their MFMA accumulators
+  // in every 16 (32) k so that rounding is relative to a short partial sum
   double fr[2][2][4], fi[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -191,27 +310,30 @@ __device__ __forceinline__ void step1_tile(const S1Desc<T>& d, int64_t bx, int64
 #pragma unroll
       for (int r = 0; r < 4; ++r) fr[a][b][r] = fi[a][b][r] = 0.0;
     }
-  for (int64_t k0 = 0; k0 < ke; k0 += 16) {
+  if constexpr (IsSplit<T>::value) {
+    constexpr int NS = IsSplit<T>::ns;
+    const SE* pa[2];
+    const SE* pb[2];
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-      const int64_t k = k0 + kk;
-      Cplx<T> fa[2], fb[2];
+    for (int t = 0; t < 2; ++t) {
+      pa[t] = Ae + (m0 + 16 * t + lr) * ke * 2 * NS + lk * 16 * NS;
+      int64_t nrow = n0 + 16 * t + lr;
+      if (nrow >= ncol) nrow = ncol - 1;
+      pb[t] = gR + nrow * ke * 2 * NS + lk * 16 * NS;
+    }
+    for (int64_t k0 = 0; k0 < ke; k0 += 32) {
+      const int64_t go = (k0 >> 3) * 16 * NS;
+      us8v fa[2][2 * NS], fb[2][2 * NS], na[2][NS];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        fa[t] = ldc(pa[t] + 2 * k);
-        fb[t] = ldc(pb[t] + 2 * k);
+        load_split<NS>(pa[t] + go, fa[t]);
+        load_split<NS>(pb[t] + go, fb[t]);
+        neg_im<NS>(fa[t], na[t]);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cr[a][b] = MM::mma(fa[a].x, fb[b].x, cr[a][b]);
-          cr[a][b] = MM::mma(-fa[a].y, fb[b].y, cr[a][b]);
-          ci[a][b] = MM::mma(fa[a].x, fb[b].y, ci[a][b]);
-          ci[a][b] = MM::mma(fa[a].y, fb[b].x, ci[a][b]);
-        }
-    }
-    if constexpr (MM::kFold) {
+        for (int b = 0; b < 2; ++b) split_cmma<NS>(fa[a], na[a], fb[b], cr[a][b], ci[a][b]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -225,17 +347,62 @@ __device__ __forceinline__ void step1_tile(const S1Desc<T>& d, int64_t bx, int64
           ci[a][b] = MM::zero();
         }
     }
-  }
-  if constexpr (!MM::kFold) {
+  } else {
+    const T* pa[2];
+    const T* pb[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int t = 0; t < 2; ++t) {
+      pa[t] = Ae + 2 * ((m0 + 16 * t + lr) * ke + lk);
+      int64_t nrow = n0 + 16 * t + lr;
+      if (nrow >= ncol) nrow = ncol - 1;
+      pb[t] = gR + 2 * (nrow * ke + lk);
+    }
+    for (int64_t k0 = 0; k0 < ke; k0 += 16) {
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int64_t k = k0 + kk;
+        Cplx<T> fa[2], fb[2];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          fr[a][b][r] = (double)cr[a][b][r];
-          fi[a][b][r] = (double)ci[a][b][r];
+        for (int t = 0; t < 2; ++t) {
+          fa[t] = ldc(pa[t] + 2 * k);
+          fb[t] = ldc(pb[t] + 2 * k);
         }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = MM::mma(fa[a].x, fb[b].x, cr[a][b]);
+            cr[a][b] = MM::mma(-fa[a].y, fb[b].y, cr[a][b]);
+            ci[a][b] = MM::mma(fa[a].x, fb[b].y, ci[a][b]);
+            ci[a][b] = MM::mma(fa[a].y, fb[b].x, ci[a][b]);
+          }
+      }
+      if constexpr (MM::kFold) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              fr[a][b][r] += (double)cr[a][b][r];
+              fi[a][b][r] += (double)ci[a][b][r];
+            }
+            cr[a][b] = MM::zero();
+            ci[a][b] = MM::zero();
+          }
+      }
+    }
+    if constexpr (!MM::kFold) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            fr[a][b][r] = (double)cr[a][b][r];
+            fi[a][b][r] = (double)ci[a][b][r];
+          }
+    }
   }
   // epilogue
   const int64_t per_x = (int64_t)nrp * nb;
@@ -253,9 +420,7 @@ __device__ __forceinline__ void step1_tile(const S1Desc<T>& d, int64_t bx, int64
         const int rp = (int)(rem / nb);
         const cd ph = Ep[(int64_t)st_kidx[i] * nrp + rp];
         const cd z = cmulc(cmake(fr[a][b][r], fi[a][b][r]), ph);  // * conj(ph)
-        T* dst = B2 + 2 * ((i * nbr + x) * kp + rem);
-        dst[0] = (T)z.x;
-        dst[1] = (T)z.y;
+        PutC<T>::put(B2, i * nbr + x, kp, rem, z.x, z.y);
       }
 }
 
@@ -308,8 +473,8 @@ __device__ inline int q_of(int kj, int ki, int n0, int n1, int n2) {
 template <typename T>
 struct S2Desc {
   int64_t kp;
-  const T* Ap;
-  const T* B2;
+  const typename Store<T>::type* Ap;
+  const typename Store<T>::type* B2;
   void* Bp;
   void* Bm;
   EpiParams ep;
@@ -321,8 +486,9 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
   typedef Mfma<T> MM;
   typedef typename MM::acc_t acc_t;
   const int64_t kp = d.kp;
-  const T* __restrict__ Ap = d.Ap;
-  const T* __restrict__ B2 = d.B2;
+  typedef typename Store<T>::type SE;
+  const SE* __restrict__ Ap = d.Ap;
+  const SE* __restrict__ B2 = d.B2;
   ST* __restrict__ Bp = (ST*)d.Bp;
   ST* __restrict__ Bm = (ST*)d.Bm;
   const EpiParams& ep = d.ep;
@@ -347,8 +513,6 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
   const int64_t i0 = by * 32 + (wave & 1) * 16;
   const int lr = lane & 15, lk = lane >> 4;
 
-  const T* pa = Ap + 2 * ((j0 + lr) * kp + lk);
-  const T* pb = B2 + 2 * (((i0 + lr) * NX) * kp + lk);
   acc_t cr[NX], ci[NX];
   double fr[MM::kFold ? NX : 1][4], fi[MM::kFold ? NX : 1][4];
 #pragma unroll
@@ -362,25 +526,21 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
 #pragma unroll
       for (int r = 0; r < 4; ++r) fr[x][r] = fi[x][r] = 0.0;
   }
-  auto kstep = [&](int64_t k) {
-    const Cplx<T> fa = ldc(pa + 2 * k);
-    const T nai = -fa.y;
+  if constexpr (IsSplit<T>::value) {
+    constexpr int NS = IsSplit<T>::ns;
+    const SE* pa = Ap + (j0 + lr) * kp * 2 * NS + lk * 16 * NS;
+    const SE* pb = B2 + ((i0 + lr) * NX) * kp * 2 * NS + lk * 16 * NS;
+    for (int64_t k0 = 0; k0 < kp; k0 += 32) {
+      const int64_t go = (k0 >> 3) * 16 * NS;
+      us8v fa[2 * NS], na[NS];
+      load_split<NS>(pa + go, fa);
+      neg_im<NS>(fa, na);
 #pragma unroll
-    for (int x = 0; x < NX; ++x) {
-      const Cplx<T> fb = ldc(pb + 2 * (x * kp + k));
-      cr[x] = MM::mma(fa.x, fb.x, cr[x]);
-      cr[x] = MM::mma(nai, fb.y, cr[x]);
-      ci[x] = MM::mma(fa.x, fb.y, ci[x]);
-      ci[x] = MM::mma(fa.y, fb.x, ci[x]);
-    }
-  };
-  if constexpr (!MM::kFold) {
-    for (int64_t k = 0; k < kp; k += 4) kstep(k);
-  }
-  for (int64_t k0 = 0; MM::kFold && k0 < kp; k0 += 16) {
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) kstep(k0 + kk);
-    if constexpr (MM::kFold) {
+      for (int x = 0; x < NX; ++x) {
+        us8v fb[2 * NS];
+        load_split<NS>(pb + x * kp * 2 * NS + go, fb);
+        split_cmma<NS>(fa, na, fb, cr[x], ci[x]);
+      }
 #pragma unroll
       for (int x = 0; x < NX; ++x) {
 #pragma unroll
@@ -390,6 +550,40 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
         }
         cr[x] = MM::zero();
         ci[x] = MM::zero();
+      }
+    }
+  } else {
+    const T* pa = Ap + 2 * ((j0 + lr) * kp + lk);
+    const T* pb = B2 + 2 * (((i0 + lr) * NX) * kp + lk);
+    auto kstep = [&](int64_t k) {
+      const Cplx<T> fa = ldc(pa + 2 * k);
+      const T nai = -fa.y;
+#pragma unroll
+      for (int x = 0; x < NX; ++x) {
+        const Cplx<T> fb = ldc(pb + 2 * (x * kp + k));
+        cr[x] = MM::mma(fa.x, fb.x, cr[x]);
+        cr[x] = MM::mma(nai, fb.y, cr[x]);
+        ci[x] = MM::mma(fa.x, fb.y, ci[x]);
+        ci[x] = MM::mma(fa.y, fb.x, ci[x]);
+      }
+    };
+    if constexpr (!MM::kFold) {
+      for (int64_t k = 0; k < kp; k += 4) kstep(k);
+    }
+    for (int64_t k0 = 0; MM::kFold && k0 < kp; k0 += 16) {
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) kstep(k0 + kk);
+      if constexpr (MM::kFold) {
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            fr[x][r] += (double)cr[x][r];
+            fi[x][r] += (double)ci[x][r];
+          }
+          cr[x] = MM::zero();
+          ci[x] = MM::zero();
+        }
       }
     }
   }
@@ -521,11 +715,13 @@ static elph_status build_operands_t(elph_ctx ctx) {
   hipStream_t s = ctx->stream;
   const int64_t M = ctx->nstates;
   const int nb = ctx->nb, nbr = ctx->nbr;
+  typedef typename Store<T>::type SE;
+  constexpr int64_t al = Store<T>::kalign;
   ctx->m_pad = (M + 63) / 64 * 64;
-  ctx->ke = ((int64_t)ctx->nre * nb + 15) / 16 * 16;
-  ctx->kp = ((int64_t)ctx->nrp * nb + 15) / 16 * 16;
+  ctx->ke = ((int64_t)ctx->nre * nb + al - 1) / al * al;
+  ctx->kp = ((int64_t)ctx->nrp * nb + al - 1) / al * al;
   const int64_t ncol = (int64_t)nbr * ctx->nrp * nb;
-  const size_t esz = 2 * sizeof(T);
+  const size_t esz = Store<T>::per_c * sizeof(SE);
   size_t bytes_ae = (size_t)ctx->m_pad * ctx->ke * esz;
   size_t bytes_ap = (size_t)ctx->m_pad * ctx->kp * esz;
   size_t bytes_gr = (size_t)ncol * ctx->ke * esz;
@@ -549,13 +745,13 @@ static elph_status build_operands_t(elph_ctx ctx) {
   }
   hipLaunchKernelGGL(k_build_Ae<T>, dim3(blocks_for(M * ctx->nre * nb, 256)), dim3(256), 0, s, M, nb, ctx->nre,
                      ctx->ke, ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_Ee, (const cd*)ctx->d_U,
-                     (T*)ae);
+                     (SE*)ae);
   hipLaunchKernelGGL(k_build_Ap<T>, dim3(blocks_for(M * ctx->nrp * nb, 256)), dim3(256), 0, s, M, nb, ctx->nrp,
                      ctx->kp, ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_Ep, ctx->d_wrp,
-                     (const cd*)ctx->d_U, (T*)ap);
+                     (const cd*)ctx->d_U, (SE*)ap);
   const int64_t gtotal = (int64_t)ctx->nre * ctx->nrp * nbr * nb * nb;
   hipLaunchKernelGGL(k_permute_g<T>, dim3(blocks_for(gtotal, 256)), dim3(256), 0, s, ctx->nre, ctx->nrp, nbr, nb,
-                     ctx->ke, ctx->d_gr, (T*)gr);
+                     ctx->ke, ctx->d_gr, (SE*)gr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     ctx->err = std::string("kernel launch failed: ") + hipGetErrorString(e);
@@ -570,6 +766,8 @@ elph_status build_operands(elph_ctx ctx) {
   if (ctx->operands_ready) return ELPH_OK;
   if (ctx->precision == ELPH_FP64) return build_operands_t<double>(ctx);
   if (ctx->precision == ELPH_FP32) return build_operands_t<float>(ctx);
+  if (ctx->precision == ELPH_BF16X3) return build_operands_t<Bf16S<2>>(ctx);
+  if (ctx->precision == ELPH_BF16X6) return build_operands_t<Bf16S<3>>(ctx);
   ctx->err = "precision form not available";
   return ELPH_EINVAL;
 }
@@ -582,9 +780,9 @@ S1Desc<T> step1_desc(elph_ctx ctx) {
   d.ke = ctx->ke;
   d.kp = ctx->kp;
   d.nstates = ctx->nstates;
-  d.Ae = (const T*)ctx->d_Ae;
-  d.gR = (const T*)ctx->d_gR;
-  d.B2 = (T*)ctx->d_B2;
+  d.Ae = (const typename Store<T>::type*)ctx->d_Ae;
+  d.gR = (const typename Store<T>::type*)ctx->d_gR;
+  d.B2 = (typename Store<T>::type*)ctx->d_B2;
   d.nrp = ctx->nrp;
   d.nb = ctx->nb;
   d.nbr = ctx->nbr;
@@ -604,8 +802,8 @@ template <typename T, typename ST, int NX>
 static void launch_step2_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm) {
   S2Desc<T> d;
   d.kp = ctx->kp;
-  d.Ap = (const T*)ctx->d_Ap;
-  d.B2 = (const T*)ctx->d_B2;
+  d.Ap = (const typename Store<T>::type*)ctx->d_Ap;
+  d.B2 = (const typename Store<T>::type*)ctx->d_B2;
   d.Bp = Bp;
   d.Bm = Bm;
   d.ep = ep;
@@ -690,12 +888,28 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     mark(ctx, 4);
     st = store_f64 ? launch_step2_t<double, double>(ctx, ep, Bp, Bm) : launch_step2_t<double, float>(ctx, ep, Bp, Bm);
     mark(ctx, 5);
-  } else {
+  } else if (ctx->precision == ELPH_FP32) {
     mark(ctx, 2);
     launch_step1_t<float>(ctx);
     mark(ctx, 3);
     mark(ctx, 4);
     st = store_f64 ? launch_step2_t<float, double>(ctx, ep, Bp, Bm) : launch_step2_t<float, float>(ctx, ep, Bp, Bm);
+    mark(ctx, 5);
+  } else if (ctx->precision == ELPH_BF16X3) {
+    mark(ctx, 2);
+    launch_step1_t<Bf16S<2>>(ctx);
+    mark(ctx, 3);
+    mark(ctx, 4);
+    st = store_f64 ? launch_step2_t<Bf16S<2>, double>(ctx, ep, Bp, Bm)
+                   : launch_step2_t<Bf16S<2>, float>(ctx, ep, Bp, Bm);
+    mark(ctx, 5);
+  } else {
+    mark(ctx, 2);
+    launch_step1_t<Bf16S<3>>(ctx);
+    mark(ctx, 3);
+    mark(ctx, 4);
+    st = store_f64 ? launch_step2_t<Bf16S<3>, double>(ctx, ep, Bp, Bm)
+                   : launch_step2_t<Bf16S<3>, float>(ctx, ep, Bp, Bm);
     mark(ctx, 5);
   }
   if (st != ELPH_OK) return st;
@@ -963,8 +1177,9 @@ BatchImpl* batch_new(const std::vector<elph_ctx>& ctxs, std::string* err) {
   for (elph_ctx c : ctxs) b->saved_streams.push_back(c->stream);
   b->precision = ctxs[0]->precision;
   for (elph_ctx c : ctxs)
-    if (c->precision != b->precision || c->hip_dead) {
-      *err = "batch contexts must share one precision form and be usable";
+    if (c->precision != b->precision || c->hip_dead ||
+        (b->precision != ELPH_FP64 && b->precision != ELPH_FP32)) {
+      *err = "batch contexts must share the FP64 or the FP32 form and be usable";
       delete b;
       return nullptr;
     }

@@ -226,6 +226,33 @@ def test_fp32_form(name):
     ctx.close()
 
 
+# BF16 split forms: every operand is a sum of BF16 parts; the x3 form keeps
+# the products of total order <= 2^-8 (each product then has relative error
+# about 2 * 2^-16 plus FP32 accumulation), the x6 form those of order <=
+# 2^-16 (error about 3 * 2^-24, as the FP32 form).  |g|^2 doubles the
+# relative error and rates are sums of positive terms, so the x3 bound is
+# 3 x 2 x 2 x 2^-16 ~ 2e-4 per rate; the x6 form meets the FP32 bounds.
+@pytest.mark.parametrize("name", ["plain8", "metal6"])
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6"])
+def test_bf16_split_forms(name, form):
+    c = case(name)
+    ctx = make_ctx(c.cfg, c.mat, precision=form)
+    sz = E.elph_sizes(ctx)
+    we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
+    E.elph_scatt_rates(ctx, c.T, we, wph)
+    torch.cuda.synchronize()
+    w1, w2 = we.cpu().numpy(), wph.cpu().numpy()
+    e1, e2 = rate_err(w1, c.we, 1e-6), rate_err(w2, c.wph, 1e-6)
+    n1 = np.linalg.norm(w1 - c.we) / np.linalg.norm(c.we)
+    n2 = np.linalg.norm(w2 - c.wph.ravel()) / np.linalg.norm(c.wph)
+    print("%s form %s: above 1e-6 max %.2e %.2e, norm-wise %.2e %.2e" % (form, name, e1, e2, n1, n2))
+    if form == "bf16x6":
+        assert e1 < 1e-5 and e2 < 1e-5 and n1 < 1e-6 and n2 < 1e-6
+    else:
+        assert e1 < 2e-4 and e2 < 2e-4 and n1 < 2e-5 and n2 < 2e-5
+    ctx.close()
+
+
 @pytest.mark.parametrize("level", [0, 1, 2, 3])
 def test_iterate_metal6(level):
     c = case("metal6")
