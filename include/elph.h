@@ -206,7 +206,11 @@ elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, double* W_ph
  * alpha_ph (A/m), kappa_ph (W/(m K)) of Eqs. 28-30 with 1/N_k, 1/N_q.
  * iters (host, may be NULL): phonon iterations used.  ko_residual (host,
  * may be NULL): |sigma S - (alpha_el + alpha_ph)/T| / |sigma S| (Eq. 31).
- * Residual = max over I, J, F, G of |x_new - x_old| / |x_new| (2-norms).
+ * Residual = max over I, J, F, G of |x_new - x_old| / |x_new| (2-norms),
+ * where for F, G x_new is the phonon map applied to x_old.  At level
+ * COUPLED the phonon iterates are Anderson-accelerated (history 6, per
+ * Cartesian column): the converged pair is the fixed point of the scheme,
+ * reached in fewer phonon iterations than by plain substitution.
  * Returns ELPH_ENOCONV (with the last iterate) if maxit is reached. */
 elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph_ext, int32_t level,
                          double tol, int32_t maxit, double* I, double* J, double* F,

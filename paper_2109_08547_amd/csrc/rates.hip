@@ -840,6 +840,52 @@ __global__ void __launch_bounds__(256) k_diff_norms(int64_t n, const double* __r
   if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = acc[threadIdx.x];
 }
 
+// ---- Anderson acceleration of the outer (phonon) fixed point
+constexpr int kAA = 6;  // history length
+struct Ptr8 {
+  const double* p[8];
+};
+struct Gam8 {
+  double g[8][6];
+};
+
+// part[block][v][c] = sum over the block's elements of column c of vs[v] . a
+__global__ void __launch_bounds__(192) k_dots_multi(int64_t n6, int nv, Ptr8 vs, const double* __restrict__ a,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[192];
+  // 192 threads and a stride that is a multiple of 6: each thread keeps one column
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 192 + threadIdx.x; t < n6; t += (int64_t)gridDim.x * 192)
+      s += vs.p[v][t] * a[t];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      double c = 0.0;
+      for (int k = threadIdx.x; k < 192; k += 6) c += sh[k];
+      part[((int64_t)blockIdx.x * 8 + v) * 6 + threadIdx.x] = c;
+    }
+    __syncthreads();
+  }
+}
+
+// y = a - b
+__global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = a[t] - b[t];
+}
+
+// x += f - sum_l gamma_l (dX_l + dF_l)   (column-wise gamma)
+__global__ void k_aa_update(int64_t n6, int nh, Ptr8 dX, Ptr8 dF, Gam8 gm, const double* __restrict__ f,
+                            double* __restrict__ x) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n6) return;
+  const int c = (int)(t % 6);
+  double v = x[t] + f[t];
+  for (int l = 0; l < nh; ++l) v -= gm.g[l][c] * (dX.p[l][t] + dF.p[l][t]);
+  x[t] = v;
+}
+
 // transport tensors: 6 tensors of 9 = 54 partial sums per block
 __global__ void __launch_bounds__(256) k_tensor_e(int64_t M, const double* __restrict__ eps, double mu,
                                                   const double* __restrict__ f, const double* __restrict__ omf,
@@ -964,6 +1010,55 @@ static elph_status diff_norms(elph_ctx ctx, int64_t n, const double* a, const do
 
 static double rel(double d2, double n2) { return std::sqrt(d2) / std::max(std::sqrt(n2), 1e-300); }
 
+// out[v][c] = column-c dot of vs[v] and a, v < nv (block partials summed in order)
+static elph_status dots_multi(elph_ctx ctx, int64_t n6, int nv, const Ptr8& vs, const double* a, double* part,
+                              std::vector<double>& hpart, double (*out)[6]) {
+  const int blocks = 128;
+  hipLaunchKernelGGL(k_dots_multi, dim3(blocks), dim3(192), 0, ctx->stream, n6, nv, vs, a, part);
+  HIPCHK(hipMemcpyAsync(hpart.data(), part, blocks * 8 * 6 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int v = 0; v < nv; ++v)
+    for (int c = 0; c < 6; ++c) {
+      double s = 0.0;
+      for (int b = 0; b < blocks; ++b) s += hpart[((size_t)b * 8 + v) * 6 + c];
+      out[v][c] = s;
+    }
+  return ELPH_OK;
+}
+
+// Solve (G + lambda I) g = r for an n x n symmetric system (n <= 8) by
+// Gaussian elimination with partial pivoting; false when singular.
+static bool small_solve(int n, double (*G)[8], const double* r, double* g) {
+  double A[8][9];
+  double dmax = 0.0;
+  for (int i = 0; i < n; ++i) dmax = std::max(dmax, std::fabs(G[i][i]));
+  if (!(dmax > 0.0)) return false;
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) A[i][j] = G[i][j] + (i == j ? 1e-12 * dmax : 0.0);
+    A[i][n] = r[i];
+  }
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[i][k]) > std::fabs(A[p][k])) p = i;
+    if (!(std::fabs(A[p][k]) > 1e-300)) return false;
+    if (p != k)
+      for (int j = 0; j <= n; ++j) std::swap(A[k][j], A[p][j]);
+    for (int i = k + 1; i < n; ++i) {
+      const double m = A[i][k] / A[k][k];
+      for (int j = k; j <= n; ++j) A[i][j] -= m * A[k][j];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = A[i][n];
+    for (int j = i + 1; j < n; ++j) s -= A[i][j] * g[j];
+    g[i] = s / A[i][i];
+  }
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(g[i])) return false;
+  return true;
+}
+
 template <typename ST>
 static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int level, double tol, int maxit,
                              double* I, double* J, double* F, double* G, double* tensors, int* iters, double* ko) {
@@ -1077,6 +1172,27 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
       used = 1;
     } else {
       converged = false;
+      // Anderson acceleration of the phonon fixed point phon -> Phi(phon)
+      // (the unified scheme's outer map); the electrons are always solved
+      // for the current phonon iterate, so a converged pair is the scheme's
+      // fixed point.  PARTIAL stops after the first map evaluation.
+      const int64_t n6 = nm * 6;
+      double *fcur = nullptr, *fprev = nullptr, *pprev = nullptr, *aabuf = nullptr;
+      const bool accel = level == ELPH_LEVEL_COUPLED;
+      if (accel) {
+        ALLOC(fcur, n6 * sizeof(double));
+        ALLOC(fprev, n6 * sizeof(double));
+        ALLOC(pprev, n6 * sizeof(double));
+        ALLOC(aabuf, 2 * kAA * n6 * sizeof(double));
+      }
+      Ptr8 dX{}, dF{};
+      for (int l = 0; l < kAA; ++l) {
+        dX.p[l] = accel ? aabuf + (size_t)l * n6 : nullptr;
+        dF.p[l] = accel ? aabuf + (size_t)(kAA + l) * n6 : nullptr;
+      }
+      double Gm[6][8][8];
+      int nh = 0, head = 0;
+      std::vector<double> hp2(128 * 8 * 6);
       for (int it = 1; it <= maxit; ++it) {
         bool ok = false;
         HIPCHK(hipMemcpyAsync(xprev, x, M * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1085,14 +1201,13 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
         Norms ne;
         st = diff_norms(ctx, M, x, xprev, part, hpart, &ne);
         if (st != ELPH_OK) return st;
-        // phonon drag from the new electrons
+        // phonon drag from the new electrons: phonn = Phi(phon)
         launch_q_gather<ST, 6>(ctx, Bp, th.f, th.omf, x, acc);
         hipLaunchKernelGGL(k_ph_drag_finalize, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, acc, phon0,
                            ctx->d_hw, th.nocc, wp, ctx->omega_min, phonn);
         Norms np_;
         st = diff_norms(ctx, nm, phonn, phon, part, hpart, &np_);
         if (st != ELPH_OK) return st;
-        std::swap(phon, phonn);
         used = it;
         const double r = std::max(std::max(rel(ne.dI, ne.nI), rel(ne.dJ, ne.nJ)),
                                   std::max(rel(np_.dI, np_.nI), rel(np_.dJ, np_.nJ)));
@@ -1100,14 +1215,56 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
           std::fprintf(stderr, "elph_iterate: outer %d inner %d res I %.3e J %.3e F %.3e G %.3e\n", it, last_inner,
                        rel(ne.dI, ne.nI), rel(ne.dJ, ne.nJ), rel(np_.dI, np_.nI), rel(np_.dJ, np_.nJ));
         if (level == ELPH_LEVEL_PARTIAL) {
+          std::swap(phon, phonn);
           converged = ok;
           break;
         }
         if (ok && r < tol) {
+          std::swap(phon, phonn);
           converged = true;
           break;
         }
+        // f = Phi(phon) - phon; history of differences of f and of phon
+        hipLaunchKernelGGL(k_sub, dim3(blocks_for(n6, 256)), dim3(256), 0, s, n6, phonn, phon, fcur);
+        if (it > 1) {
+          double* dXh = const_cast<double*>(dX.p[head]);
+          double* dFh = const_cast<double*>(dF.p[head]);
+          hipLaunchKernelGGL(k_sub, dim3(blocks_for(n6, 256)), dim3(256), 0, s, n6, fcur, fprev, dFh);
+          hipLaunchKernelGGL(k_sub, dim3(blocks_for(n6, 256)), dim3(256), 0, s, n6, phon, pprev, dXh);
+          nh = std::min(nh + 1, kAA);
+          double row[8][6];
+          st = dots_multi(ctx, n6, nh, dF, dFh, part, hp2, row);
+          if (st != ELPH_OK) return st;
+          for (int c = 0; c < 6; ++c)
+            for (int l = 0; l < nh; ++l) Gm[c][head][l] = Gm[c][l][head] = row[l][c];
+          head = (head + 1) % kAA;
+        }
+        HIPCHK(hipMemcpyAsync(fprev, fcur, n6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(pprev, phon, n6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        Gam8 gm{};
+        if (nh > 0) {
+          double rhs[8][6];
+          st = dots_multi(ctx, n6, nh, dF, fcur, part, hp2, rhs);
+          if (st != ELPH_OK) return st;
+          for (int c = 0; c < 6; ++c) {
+            double Gc[8][8], rc[8], gc[8];
+            for (int a = 0; a < nh; ++a) {
+              rc[a] = rhs[a][c];
+              for (int b = 0; b < nh; ++b) Gc[a][b] = Gm[c][a][b];
+            }
+            if (small_solve(nh, Gc, rc, gc))
+              for (int a = 0; a < nh; ++a) gm.g[a][c] = gc[a];
+          }
+        }
+        // phon <- phon + f - sum_l gamma_l (dX_l + dF_l)
+        hipLaunchKernelGGL(k_aa_update, dim3(blocks_for(n6, 256)), dim3(256), 0, s, n6, nh, dX, dF, gm, fcur, phon);
+        HIPCHK(hipGetLastError());
       }
+      if (!converged && level == ELPH_LEVEL_COUPLED) {
+        // return the last map value with the electrons it came from
+        std::swap(phon, phonn);
+      }
+      for (double* pbuf : {fcur, fprev, pprev, aabuf}) dev_free(ctx, pbuf);
     }
   }
 
