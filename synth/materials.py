@@ -69,7 +69,7 @@ def _cnormal(rng, shape):
 
 
 def make_material(nb, na, seed, rset_e, rset_b, L, s_H, delta, c_D, s_g=1.0,
-                  masses=None, lattice_a=LATTICE_A, dtype_g=np.complex128):
+                  masses=None, lattice_a=LATTICE_A, dtype_g=np.complex128, with_g=True):
     """Assemble one synthetic material; returns a dict of numpy arrays.
 
     ``rset_e`` is used for both R_e and R_p; ``rset_b`` is the half-radius
@@ -119,6 +119,11 @@ def make_material(nb, na, seed, rset_e, rset_b, L, s_H, delta, c_D, s_g=1.0,
             d[rmap[dr]] += B[ia].T @ B[ib]
     d *= c_D
     del bmap
+
+    lat = lattice_a * np.eye(3)
+    if not with_g:  # band and phonon calibration only (g is drawn last)
+        return {"nwann": nb, "natom": na, "re": rs.copy(), "rp": rs.copy(), "wre": np.ones(nr),
+                "wrp": np.ones(nr), "lat": lat, "mass": masses, "h_r": h, "d_r": d, "g_r": None}
 
     # --- g(R_e, R_p)
     decay = np.exp(-(rnorm[:, None] + rnorm[None, :]) / L)  # [Re, Rp]
@@ -231,4 +236,4 @@ def material_for(cfg, **overrides):
     c.update(overrides)
     return make_material(nb=c["nb"], na=c["na"], seed=c["seed"], rset_e=_rset(c["rset"]),
                          rset_b=_rset(c["rset_b"]), L=c["L"], s_H=c["s_H"],
-                         delta=c["delta"], c_D=c["c_D"])
+                         delta=c["delta"], c_D=c["c_D"], with_g=c.get("with_g", True))

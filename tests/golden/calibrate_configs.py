@@ -40,7 +40,7 @@ def _bands(h_raw_k, onsite, s_H, delta):
 
 
 def _raw_hk(cfg, kfrac):
-    mat = sm.material_for(cfg, s_H=1.0, delta=0.0, c_D=1.0)
+    mat = sm.material_for(cfg, s_H=1.0, delta=0.0, c_D=1.0, with_g=False)
     out = np.empty((kfrac.shape[0], cfg["nb"], cfg["nb"]), dtype=np.complex128)
     for s in range(0, kfrac.shape[0], 32768):
         out[s:s + 32768] = oracle.bloch_hamiltonian(mat, kfrac[s:s + 32768])
