@@ -432,23 +432,29 @@ elph_status finalize_wph(elph_ctx ctx, const Thermal& th, double* acc, double* w
 }
 
 template <typename ST>
-static elph_status rates_from_store_t(elph_ctx ctx, const Thermal& th, double* we, double* wph) {
+void launch_we_rows(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc, double* we) {
   const int64_t M = ctx->nstates;
+  hipStream_t s = ctx->stream;
+#define WR(NXV)                                                                                            \
+  hipLaunchKernelGGL((k_we_rows<ST, NXV>), dim3((unsigned)M), dim3(256), 0, s, M, mdims(ctx), Bp, Bm,      \
+                     ctx->d_state_k, lomf, nocc, we)
+  switch (ctx->nbr) {
+    case 3: WR(3); break;
+    case 6: WR(6); break;
+    case 9: WR(9); break;
+    case 12: WR(12); break;
+    default: WR(15); break;
+  }
+#undef WR
+}
+template void launch_we_rows<float>(elph_ctx, const float*, const float*, const double*, const double*, double*);
+template void launch_we_rows<double>(elph_ctx, const double*, const double*, const double*, const double*, double*);
+
+template <typename ST>
+static elph_status rates_from_store_t(elph_ctx ctx, const Thermal& th, double* we, double* wph) {
   const int nbr = ctx->nbr;
   hipStream_t s = ctx->stream;
-  if (we) {
-#define WR(NXV)                                                                                            \
-  hipLaunchKernelGGL((k_we_rows<ST, NXV>), dim3((unsigned)M), dim3(256), 0, s, M, mdims(ctx), (const ST*)ctx->d_Bp, \
-                     (const ST*)ctx->d_Bm, ctx->d_state_k, th.lomf, th.nocc, we)
-    switch (nbr) {
-      case 3: WR(3); break;
-      case 6: WR(6); break;
-      case 9: WR(9); break;
-      case 12: WR(12); break;
-      default: WR(15); break;
-    }
-#undef WR
-  }
+  if (we) launch_we_rows<ST>(ctx, (const ST*)ctx->d_Bp, (const ST*)ctx->d_Bm, th.lomf, th.nocc, we);
   if (wph) {
     const int64_t nm = ctx->nk * nbr;
     double* acc = nullptr;
@@ -850,22 +856,26 @@ struct Gam8 {
 };
 
 // part[block][v][c] = sum over the block's elements of column c of vs[v] . a
+// (one pass over a; 192 threads and a stride that is a multiple of 6, so each
+// thread keeps one column; the 32 threads of a column are summed in order)
 __global__ void __launch_bounds__(192) k_dots_multi(int64_t n6, int nv, Ptr8 vs, const double* __restrict__ a,
                                                     double* __restrict__ part) {
-  __shared__ double sh[192];
-  // 192 threads and a stride that is a multiple of 6: each thread keeps one column
-  for (int v = 0; v < nv; ++v) {
-    double s = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * 192 + threadIdx.x; t < n6; t += (int64_t)gridDim.x * 192)
-      s += vs.p[v][t] * a[t];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < 6) {
-      double c = 0.0;
-      for (int k = threadIdx.x; k < 192; k += 6) c += sh[k];
-      part[((int64_t)blockIdx.x * 8 + v) * 6 + threadIdx.x] = c;
-    }
-    __syncthreads();
+  __shared__ double sh[8][192];
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t t = (int64_t)blockIdx.x * 192 + threadIdx.x; t < n6; t += (int64_t)gridDim.x * 192) {
+    const double at = a[t];
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+      if (v < nv) s[v] += vs.p[v][t] * at;
+  }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) sh[v][threadIdx.x] = s[v];
+  __syncthreads();
+  if (threadIdx.x < 48) {
+    const int v = threadIdx.x / 6, c = threadIdx.x % 6;
+    double sum = 0.0;
+    for (int k = c; k < 192; k += 6) sum += sh[v][k];
+    part[((int64_t)blockIdx.x * 8 + v) * 6 + c] = sum;
   }
 }
 
@@ -1013,7 +1023,7 @@ static double rel(double d2, double n2) { return std::sqrt(d2) / std::max(std::s
 // out[v][c] = column-c dot of vs[v] and a, v < nv (block partials summed in order)
 static elph_status dots_multi(elph_ctx ctx, int64_t n6, int nv, const Ptr8& vs, const double* a, double* part,
                               std::vector<double>& hpart, double (*out)[6]) {
-  const int blocks = 128;
+  const int blocks = 256;
   hipLaunchKernelGGL(k_dots_multi, dim3(blocks), dim3(192), 0, ctx->stream, n6, nv, vs, a, part);
   HIPCHK(hipMemcpyAsync(hpart.data(), part, blocks * 8 * 6 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1123,9 +1133,11 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
     // f(1-f) weights of the projection
     hipLaunchKernelGGL(k_mul, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, th.f, th.omf, wff);
     SelfSolver sv;
-    ALLOC(sbase, self_solver_doubles(M) * sizeof(double));
-    self_solver_carve(M, sbase, &sv);
-    st = build_self_operator<ST>(ctx, Bp, Bm, th.lomf, th.nocc, we, order, goff, wff, sv.KT);
+    // the self operator is kept in the store's precision (FP32 in the forms)
+    const bool kt_f32 = sizeof(ST) == 4;
+    ALLOC(sbase, self_solver_doubles(M, kt_f32) * sizeof(double));
+    self_solver_carve(M, kt_f32, sbase, &sv);
+    st = build_self_operator<ST>(ctx, Bp, Bm, th.lomf, th.nocc, we, order, goff, wff, sv);
     if (st != ELPH_OK) return st;
 
     int last_inner = 0;
@@ -1192,7 +1204,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
       }
       double Gm[6][8][8];
       int nh = 0, head = 0;
-      std::vector<double> hp2(128 * 8 * 6);
+      std::vector<double> hp2(256 * 8 * 6);
       for (int it = 1; it <= maxit; ++it) {
         bool ok = false;
         HIPCHK(hipMemcpyAsync(xprev, x, M * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -24,11 +24,11 @@ namespace elph {
 // K^T[j][i] = K[i][j] = sum_s (B+_ijs n_qs + B-_ijs (1 + n_qs)) e^{lomf_j - lomf_i} / W_i,
 // q = k_j - k_i.  64 x 64 tiles through LDS: the store is read along j and
 // K^T written along i.
-template <typename ST>
+template <typename ST, typename KS>
 __global__ void __launch_bounds__(256) k_build_kT(int64_t M, int nbr, MeshDims md, const ST* __restrict__ Bp,
                                                   const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
                                                   const double* __restrict__ lomf, const double* __restrict__ nocc,
-                                                  const double* __restrict__ we, double* __restrict__ KT) {
+                                                  const double* __restrict__ we, KS* __restrict__ KT) {
   __shared__ double tile[64][65];
   const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
   {
@@ -56,37 +56,42 @@ __global__ void __launch_bounds__(256) k_build_kT(int64_t M, int nbr, MeshDims m
   const int64_t i = i0 + il;
   for (int jl = threadIdx.x >> 6; jl < 64; jl += 4) {
     const int64_t j = j0 + jl;
-    if (i < M && j < M) KT[j * M + i] = tile[il][jl];
+    if (i < M && j < M) KT[j * M + i] = (KS)tile[il][jl];
   }
 }
 
 // K' = P K on the transposed storage: in row j of K^T, subtract from every
 // member i of group g the weighted mean sum_{i' in g} w_i' K^T[j][i'] / sum w.
 // One block per row; groups in order, each reduced in a fixed order.
+template <typename KS>
 __global__ void __launch_bounds__(256) k_kT_project(int64_t M, int ngroups, const int32_t* __restrict__ order,
                                                     const int32_t* __restrict__ goff, const double* __restrict__ w,
-                                                    double* __restrict__ KT) {
+                                                    KS* __restrict__ KT) {
   __shared__ double sh[2 * 4];
-  double* row = KT + (int64_t)blockIdx.x * M;
+  KS* row = KT + (int64_t)blockIdx.x * M;
   for (int g = 0; g < ngroups; ++g) {
     const int32_t b = goff[g], e = goff[g + 1];
     double acc[2] = {0.0, 0.0};
     for (int32_t t = b + (int32_t)threadIdx.x; t < e; t += 256) {
       const int32_t i = order[t];
-      acc[0] += w[i] * row[i];
+      acc[0] += w[i] * (double)row[i];
       acc[1] += w[i];
     }
     block_sum<2>(acc, sh);
     if (!(acc[1] > 0.0)) continue;
     const double mean = acc[0] / acc[1];
-    for (int32_t t = b + (int32_t)threadIdx.x; t < e; t += 256) row[order[t]] -= mean;
+    for (int32_t t = b + (int32_t)threadIdx.x; t < e; t += 256) {
+      const int32_t i = order[t];
+      row[i] = (KS)((double)row[i] - mean);
+    }
   }
 }
 
 // part[split][i][c] = sum_{j in split} K^T[j][i] in[j][c].  Block = 64
 // states (one per lane) x one j split; the four wavefronts take every fourth
 // j and are summed in wave order.
-__global__ void __launch_bounds__(256) k_kmv(int64_t M, int64_t jlen, const double* __restrict__ KT,
+template <typename KS>
+__global__ void __launch_bounds__(256) k_kmv(int64_t M, int64_t jlen, const KS* __restrict__ KT,
                                              const double* __restrict__ in, double* __restrict__ part) {
   __shared__ double red[3][6][64];
   const int lane = threadIdx.x & 63;
@@ -98,7 +103,7 @@ __global__ void __launch_bounds__(256) k_kmv(int64_t M, int64_t jlen, const doub
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int64_t j = jb + wave; j < je; j += 4) {
-    const double k = KT[j * M + ic];
+    const double k = (double)KT[j * M + ic];
     const double* xj = in + j * 6;
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[c] += k * xj[c];
@@ -279,23 +284,30 @@ __global__ void __launch_bounds__(192) k_bi_scal(int mode, int nblk, const doubl
 template <typename ST>
 elph_status build_self_operator(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc,
                                 const double* we, const int32_t* order, const int32_t* goff, const double* wff,
-                                double* KT) {
+                                const SelfSolver& sv) {
   const int64_t M = ctx->nstates;
   const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
   const unsigned nt = blocks_for(M, 64);
-  hipLaunchKernelGGL(k_build_kT<ST>, dim3(nt, nt), dim3(256), 0, ctx->stream, M, ctx->nbr, md, Bp, Bm,
-                     ctx->d_state_k, lomf, nocc, we, KT);
-  hipLaunchKernelGGL(k_kT_project, dim3((unsigned)M), dim3(256), 0, ctx->stream, M, ctx->ngroups, order, goff, wff,
-                     KT);
+  if (sv.kt_f32) {
+    hipLaunchKernelGGL((k_build_kT<ST, float>), dim3(nt, nt), dim3(256), 0, ctx->stream, M, ctx->nbr, md, Bp, Bm,
+                       ctx->d_state_k, lomf, nocc, we, (float*)sv.KT);
+    hipLaunchKernelGGL(k_kT_project<float>, dim3((unsigned)M), dim3(256), 0, ctx->stream, M, ctx->ngroups, order,
+                       goff, wff, (float*)sv.KT);
+  } else {
+    hipLaunchKernelGGL((k_build_kT<ST, double>), dim3(nt, nt), dim3(256), 0, ctx->stream, M, ctx->nbr, md, Bp, Bm,
+                       ctx->d_state_k, lomf, nocc, we, (double*)sv.KT);
+    hipLaunchKernelGGL(k_kT_project<double>, dim3((unsigned)M), dim3(256), 0, ctx->stream, M, ctx->ngroups, order,
+                       goff, wff, (double*)sv.KT);
+  }
   HIPCHK(hipGetLastError());
   return ELPH_OK;
 }
 template elph_status build_self_operator<double>(elph_ctx, const double*, const double*, const double*,
                                                  const double*, const double*, const int32_t*, const int32_t*,
-                                                 const double*, double*);
+                                                 const double*, const SelfSolver&);
 template elph_status build_self_operator<float>(elph_ctx, const float*, const float*, const double*, const double*,
                                                 const double*, const int32_t*, const int32_t*, const double*,
-                                                double*);
+                                                const SelfSolver&);
 
 void self_solver_layout(int64_t M, SelfSolver* sv) {
   const int64_t rows = M > 0 ? (M + 63) / 64 : 1;
@@ -309,17 +321,20 @@ void self_solver_layout(int64_t M, SelfSolver* sv) {
   sv->nblk = (int)(need < 1 ? 1 : need < 256 ? need : 256);
 }
 
-size_t self_solver_doubles(int64_t M) {
+static size_t kt_doubles(int64_t M, bool f32) { return f32 ? ((size_t)M * M + 1) / 2 : (size_t)M * M; }
+
+size_t self_solver_doubles(int64_t M, bool kt_f32) {
   SelfSolver sv;
   self_solver_layout(M, &sv);
-  return (size_t)M * M + 7 * (size_t)M * 6 + (size_t)sv.S * M * 6 + (size_t)sv.nblk * 12 + SC_N;
+  return kt_doubles(M, kt_f32) + 7 * (size_t)M * 6 + (size_t)sv.S * M * 6 + (size_t)sv.nblk * 12 + SC_N;
 }
 
-void self_solver_carve(int64_t M, double* base, SelfSolver* sv) {
+void self_solver_carve(int64_t M, bool kt_f32, double* base, SelfSolver* sv) {
   self_solver_layout(M, sv);
   double* p = base;
   sv->KT = p;
-  p += (size_t)M * M;
+  sv->kt_f32 = kt_f32;
+  p += kt_doubles(M, kt_f32);
   double** vecs[] = {&sv->b, &sv->r, &sv->rh, &sv->p, &sv->v, &sv->s, &sv->t};
   for (double** v : vecs) {
     *v = p;
@@ -336,8 +351,12 @@ void self_solver_carve(int64_t M, double* base, SelfSolver* sv) {
 static void apply_L(elph_ctx ctx, const SelfSolver& sv, const double* in, double* out, const double* a0, int sq,
                     double* dpart) {
   const int64_t M = ctx->nstates;
-  hipLaunchKernelGGL(k_kmv, dim3(blocks_for(M, 64), (unsigned)sv.S), dim3(256), 0, ctx->stream, M, sv.jlen, sv.KT,
-                     in, sv.part);
+  if (sv.kt_f32)
+    hipLaunchKernelGGL(k_kmv<float>, dim3(blocks_for(M, 64), (unsigned)sv.S), dim3(256), 0, ctx->stream, M, sv.jlen,
+                       (const float*)sv.KT, in, sv.part);
+  else
+    hipLaunchKernelGGL(k_kmv<double>, dim3(blocks_for(M, 64), (unsigned)sv.S), dim3(256), 0, ctx->stream, M,
+                       sv.jlen, (const double*)sv.KT, in, sv.part);
   hipLaunchKernelGGL(k_kmv_fin, dim3((unsigned)sv.nblk), dim3(kVB), 0, ctx->stream, 6 * M, sv.S, in, sv.part, out,
                      a0, sq, dpart);
 }

@@ -26,6 +26,9 @@ elph_status ensure_store(elph_ctx ctx);
 // pair lists by q used by the q-gathers (built once per table build)
 elph_status ensure_pairs(elph_ctx ctx);
 elph_status rates_from_store(elph_ctx ctx, const Thermal& th, double* we, double* wph);
+// W_e[i] = sum_{j,s} (B+ n + B- (1 + n)) (1 - f_j) / (1 - f_i) from a finished store
+template <typename ST>
+void launch_we_rows(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc, double* we);
 elph_status x_from_store(elph_ctx ctx, const Thermal& th, double* Xp, double* Xm);
 elph_status finalize_wph(elph_ctx ctx, const Thermal& th, double* acc, double* wph);
 elph_status interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx, double* g_out);
@@ -34,7 +37,8 @@ elph_status iterate(elph_ctx ctx, double T, const double* wext, int level, doubl
 
 // electron self-consistency solver (solve.hip)
 struct SelfSolver {
-  double* KT = nullptr;                 // [M][M] transposed, group-projected self operator
+  void* KT = nullptr;                   // [M][M] transposed, group-projected self operator (FP64 or FP32)
+  bool kt_f32 = false;
   double *b = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
   double* part = nullptr;               // [S][M][6] split partials of the matrix-vector product
   double* dpart = nullptr;              // [nblk][12] dot partials
@@ -42,12 +46,12 @@ struct SelfSolver {
   int S = 1, nblk = 1;
   int64_t jlen = 1;
 };
-size_t self_solver_doubles(int64_t M);
-void self_solver_carve(int64_t M, double* base, SelfSolver* sv);
+size_t self_solver_doubles(int64_t M, bool kt_f32);
+void self_solver_carve(int64_t M, bool kt_f32, double* base, SelfSolver* sv);
 template <typename ST>
 elph_status build_self_operator(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc,
                                 const double* we, const int32_t* order, const int32_t* goff, const double* wff,
-                                double* KT);
+                                const SelfSolver& sv);
 // Solves L x = b (b in sv.b, projected; x projected on entry) to relative
 // residual 0.1 tol per column; *ok when all six columns reached it.
 elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double tol, int maxit, bool* ok, int* iters);

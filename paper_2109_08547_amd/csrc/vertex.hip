@@ -669,6 +669,229 @@ __global__ void k_reduce_we(const double* __restrict__ part, int64_t ntiles, int
 }
 
 // ---------------------------------------------------------------------------
+// Split-BF16 step 2 as a plain complex GEMM plus a separate epilogue:
+//   C[c][j] = sum_k B2[c][k] Ap[j][k],  c = i*NX + x,
+// with the 32x32x16 BF16 MFMA (lane l supplies A[l%32][8(l/32)+t] and
+// B[8(l/32)+t][l%32]; accumulator r holds row 8(r/4) + 4(l/32) + r%4,
+// column l%32).  A block computes 64 c x 64 j (2 x 2 wavefronts of 32 x 32);
+// each 32-k stage of both operands is staged in LDS (rows padded by 16 bytes
+// so the fragment reads do not collide in banks), the next stage is fetched
+// into registers while the current one is multiplied, and the FP32
+// accumulators fold into FP64 after every stage.  C is FP32 complex.
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+template <int NS>
+struct SplitGemm {
+  static constexpr int kRowU = 64 * NS;      // ushorts of one row's 32-k stage (4 groups x 2NS planes x 8)
+  static constexpr int kLdsRow = kRowU + 8;  // padded LDS row
+  static constexpr int kChunks = 8 * NS;     // 16-byte chunks per row and stage
+};
+
+template <int NS>
+__device__ inline f16v mma32(us8v a, us8v b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0, 0,
+                                                 0);
+}
+
+template <int NS>
+__device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&na_im)[NS], const us8v (&b)[2 * NS],
+                                    f16v& cr, f16v& ci) {
+  constexpr int np = NS == 2 ? 3 : 6;
+#pragma unroll
+  for (int t = 0; t < np; ++t) {
+    int sa, sb;
+    if (NS == 2) {
+      sa = t == 1 ? 1 : 0;
+      sb = t == 0 ? 1 : 0;
+    } else {
+      sa = t == 0 ? 1 : t == 2 ? 2 : t == 4 ? 1 : 0;
+      sb = t == 0 ? 1 : t == 1 ? 2 : t == 3 ? 1 : 0;
+    }
+    cr = mma32<NS>(a[2 * sa], b[2 * sb], cr);
+    cr = mma32<NS>(na_im[sa], b[2 * sb + 1], cr);
+    ci = mma32<NS>(a[2 * sa], b[2 * sb + 1], ci);
+    ci = mma32<NS>(a[2 * sa + 1], b[2 * sb], ci);
+  }
+}
+
+// rows c in [c0, c0 + nc) (c0 a multiple of nx), all j < nj; C is stored as
+// [(c - c0) / nx][j][(c - c0) % nx] with j stride nx (ldc >= nj)
+template <int NS>
+__global__ void __launch_bounds__(256) k_cgemm_split(int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx,
+                                                     const unsigned short* __restrict__ Bm2,
+                                                     const unsigned short* __restrict__ Apm, float* __restrict__ C,
+                                                     int64_t ldc) {
+  typedef SplitGemm<NS> G;
+  __shared__ __attribute__((aligned(16))) unsigned short As[64 * G::kLdsRow];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[64 * G::kLdsRow];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t cb = c0 + (int64_t)blockIdx.y * 64;   // first row c of the block
+  const int64_t jb = (int64_t)blockIdx.x * 64;        // first column j
+  const int64_t rowlen = K * 2 * NS;                  // ushorts per operand row
+  const int nst = (int)(K / 32);
+  constexpr int per_thread = (64 * G::kChunks) / 256;  // chunks per thread and operand (2NS)
+  uint4 ra[per_thread], rb[per_thread];
+  auto fetch = [&](int s) {
+#pragma unroll
+    for (int u = 0; u < per_thread; ++u) {
+      const int e = tid + 256 * u;
+      const int row = e / G::kChunks, w = e - row * G::kChunks;
+      const int64_t ca = cb + row, jr = jb + row;
+      const int64_t off = (int64_t)s * G::kRowU + (int64_t)w * 8;
+      ra[u] = (ca < c0 + nc) ? *reinterpret_cast<const uint4*>(Bm2 + ca * rowlen + off) : make_uint4(0, 0, 0, 0);
+      rb[u] = (jr < nj) ? *reinterpret_cast<const uint4*>(Apm + jr * rowlen + off) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int u = 0; u < per_thread; ++u) {
+      const int e = tid + 256 * u;
+      const int row = e / G::kChunks, w = e - row * G::kChunks;
+      *reinterpret_cast<uint4*>(As + row * G::kLdsRow + w * 8) = ra[u];
+      *reinterpret_cast<uint4*>(Bs + row * G::kLdsRow + w * 8) = rb[u];
+    }
+  };
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 31, lh = lane >> 5;
+  f16v cr, ci;
+  double fr[16], fi[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    cr[r] = 0.f;
+    ci[r] = 0.f;
+    fr[r] = fi[r] = 0.0;
+  }
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    if (s + 1 < nst) fetch(s + 1);
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+      // 16-k half kh: groups 2kh + lh of the stage
+      const int gofs = (2 * kh + lh) * 16 * NS;
+      us8v a[2 * NS], b[2 * NS], na[NS];
+#pragma unroll
+      for (int p = 0; p < 2 * NS; ++p) {
+        a[p] = *reinterpret_cast<const us8v*>(As + (wm + lr) * G::kLdsRow + gofs + 8 * p);
+        b[p] = *reinterpret_cast<const us8v*>(Bs + (wn + lr) * G::kLdsRow + gofs + 8 * p);
+      }
+      neg_im<NS>(a, na);
+      split_cmma32<NS>(a, na, b, cr, ci);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      fr[r] += (double)cr[r];
+      fi[r] += (double)ci[r];
+      cr[r] = 0.f;
+      ci[r] = 0.f;
+    }
+    __syncthreads();
+    if (s + 1 < nst) {
+      stash();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t c = cb + wm + 8 * (r >> 2) + 4 * lh + (r & 3);
+    const int64_t j = jb + wn + lr;
+    if (c < c0 + nc && j < nj) {
+      const int64_t il = (c - c0) / nx, x = (c - c0) - il * nx;
+      *reinterpret_cast<float2*>(C + 2 * ((il * ldc + j) * nx + x)) = make_float2((float)fr[r], (float)fi[r]);
+    }
+  }
+}
+
+// Epilogue of the split path, one wavefront per q: the phonon factors of q
+// (l u, hbar omega) are wavefront-uniform; lanes take the kept pairs
+// (k_t, k_t + q) of q's list with t in [t0, t1) (the chunk's initial
+// states) and write g_s = sum_x l u gh_x, |g|^2 and the Gaussians into the
+// store B+/-.
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t0, int32_t t1, EpiParams ep,
+                                               const int32_t* __restrict__ kept, const int32_t* __restrict__ kidx,
+                                               const int32_t* __restrict__ soff, const int32_t* __restrict__ poff,
+                                               const int32_t* __restrict__ plist, const float* __restrict__ C,
+                                               int64_t ldc, ST* __restrict__ Bp, ST* __restrict__ Bm) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (q >= nq) return;  // whole wavefront exits together
+  const int qc = (int)(q % ep.n2);
+  const int qt = (int)(q / ep.n2);
+  const int qb = qt % ep.n1, qa = qt / ep.n1;
+  const cd* __restrict__ L = ep.Lq + q * NX * NX;
+  const double* __restrict__ hwq = ep.hw + q * NX;
+  const int32_t pe = poff[q + 1];
+  for (int32_t p = poff[q] + lane; p < pe; p += 64) {
+    const int32_t t = plist[p];
+    if (t < t0 || t >= t1) continue;
+    const int k = kept[t];
+    const int kc = k % ep.n2, kt = k / ep.n2;
+    const int kb = kt % ep.n1, ka = kt / ep.n1;
+    int c2 = kc + qc; if (c2 >= ep.n2) c2 -= ep.n2;
+    int b2 = kb + qb; if (b2 >= ep.n1) b2 -= ep.n1;
+    int a2 = ka + qa; if (a2 >= ep.n0) a2 -= ep.n0;
+    const int32_t u = kidx[(a2 * ep.n1 + b2) * ep.n2 + c2];
+    for (int32_t i = soff[t]; i < soff[t + 1]; ++i) {
+      const double ei = ep.eps[i];
+      for (int32_t j = soff[u]; j < soff[u + 1]; ++j) {
+        const float* cg = C + 2 * (((int64_t)(i - i0) * ldc + j) * NX);
+        double ar[NX], ai[NX];
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+          const float2 v = *reinterpret_cast<const float2*>(cg + 2 * x);
+          ar[x] = v.x;
+          ai[x] = v.y;
+        }
+        const double de = ep.eps[j] - ei;
+        const int64_t tb = ((int64_t)i * ep.nstates + j) * NX;
+#pragma unroll
+        for (int s = 0; s < NX; ++s) {
+          double gr = 0.0, gi = 0.0;
+#pragma unroll
+          for (int x = 0; x < NX; ++x) {
+            const cd l = L[x * NX + s];
+            gr += l.x * ar[x] - l.y * ai[x];
+            gi += l.x * ai[x] + l.y * ar[x];
+          }
+          const double g2 = gr * gr + gi * gi;
+          const double w = hwq[s];
+          double bp = 0.0, bm = 0.0;
+          if (w >= ep.omega_min) {
+            const double dp = de - w, dm = de + w;
+            bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
+            bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
+          }
+          Bp[tb + s] = (ST)bp;
+          Bm[tb + s] = (ST)bm;
+        }
+      }
+    }
+  }
+}
+
+// Step-1 epilogue of the split path: B2[(i, x)][(Rp, n')] = C1[i][col] e^{-2 pi i k_i.Rp}
+// written as BF16 parts; col = (x, Rp, n'), rows [i0, i0 + ni).
+template <int NS>
+__global__ void k_step1_epi_split(int64_t i0, int64_t ni, int64_t ncol, int nrp, int nb, int nbr, int64_t kp,
+                                  const float* __restrict__ C1, const int32_t* __restrict__ st_kidx,
+                                  const cd* __restrict__ Ep, unsigned short* __restrict__ B2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ni * ncol) return;
+  const int64_t il = e / ncol, col = e - il * ncol;
+  const int64_t i = i0 + il;
+  const int64_t per_x = (int64_t)nrp * nb;
+  const int x = (int)(col / per_x);
+  const int64_t rem = col - x * per_x;
+  const int rp = (int)(rem / nb);
+  const float2 v = *reinterpret_cast<const float2*>(C1 + 2 * e);
+  const cd z = cmulc(cmake(v.x, v.y), Ep[(int64_t)st_kidx[i] * nrp + rp]);  // * conj(phase)
+  put_split<NS>(B2, i * nbr + x, kp, rem, z.x, z.y);
+}
+
+// ---------------------------------------------------------------------------
 // persistent launches over a work queue of (material, tile) items
 
 __global__ void k_zero_ints(int* p, int n) {
@@ -792,10 +1015,37 @@ S1Desc<T> step1_desc(elph_ctx ctx) {
 }
 
 template <typename T>
-static void launch_step1_t(elph_ctx ctx) {
+static elph_status launch_step1_t(elph_ctx ctx) {
   const S1Desc<T> d = step1_desc<T>(ctx);
+  if constexpr (IsSplit<T>::value) {
+    // split forms: GEMM into FP32 rows (chunks <= 2 GiB), then the phase
+    // epilogue that writes the BF16 parts of B2
+    constexpr int NS = IsSplit<T>::ns;
+    const int64_t M = ctx->nstates, ncol = d.ncol;
+    int64_t ci = ((int64_t)1 << 31) / (ncol * 8);
+    if (ci < 1) ci = 1;
+    if (ci > M) ci = M;
+    void* p = nullptr;
+    if (dev_alloc(ctx, &p, (size_t)ci * ncol * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->err = "device allocation of the step-1 buffer failed";
+      return ELPH_ENOMEM;
+    }
+    for (int64_t i0 = 0; i0 < M; i0 += ci) {
+      const int64_t ni = (M - i0 < ci) ? M - i0 : ci;
+      hipLaunchKernelGGL(k_cgemm_split<NS>, dim3((unsigned)((ncol + 63) / 64), (unsigned)((ni + 63) / 64)),
+                         dim3(256), 0, ctx->stream, i0, ni, ncol, ctx->ke, 1, (const unsigned short*)ctx->d_Ae,
+                         (const unsigned short*)ctx->d_gR, (float*)p, ncol);
+      hipLaunchKernelGGL(k_step1_epi_split<NS>, dim3(blocks_for(ni * ncol, 256)), dim3(256), 0, ctx->stream, i0, ni,
+                         ncol, ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, (const float*)p, ctx->d_state_kidx,
+                         (const cd*)ctx->d_Ep, (unsigned short*)ctx->d_B2);
+    }
+    dev_free(ctx, p);
+    return ELPH_OK;
+  }
   dim3 grid((unsigned)((d.ncol + 63) / 64), (unsigned)(ctx->m_pad / 64));
   hipLaunchKernelGGL(k_step1<T>, grid, dim3(256), 0, ctx->stream, d);
+  return ELPH_OK;
 }
 
 template <typename T, typename ST, int NX>
@@ -811,8 +1061,70 @@ static void launch_step2_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* B
   hipLaunchKernelGGL((k_step2<T, ST, NX>), grid, dim3(256), 0, ctx->stream, d);
 }
 
+// Split forms without a tile mask: GEMM into an FP32 buffer [i][j][x], then
+// the per-q epilogue over the kept pairs, in chunks of initial states (whole
+// kept k) so that the buffer stays <= 2 GiB; W_e from the finished store.
+template <int NS, typename ST, int NX>
+static elph_status launch_split_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm, int64_t* we_tiles) {
+  const int64_t M = ctx->nstates, ldc = ctx->m_pad;
+  elph_status st = ensure_pairs(ctx);
+  if (st != ELPH_OK) return st;
+  int64_t cap = ((int64_t)1 << 31) / ((int64_t)NX * ldc * 8);
+  if (cap < kMaxBands) cap = kMaxBands;
+  std::vector<int32_t> soff(ctx->nkept + 1);
+  if (hipMemcpyAsync(soff.data(), ctx->d_soff, (ctx->nkept + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                     ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    ctx->err = "copy of the state offsets failed";
+    ctx->hip_dead = true;
+    return ELPH_EHIP;
+  }
+  void* p = nullptr;
+  if (dev_alloc(ctx, &p, (size_t)std::min<int64_t>(cap, M) * NX * ldc * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "device allocation of the step-2 buffer failed";
+    return ELPH_ENOMEM;
+  }
+  float* C = (float*)p;
+  const unsigned jblk = (unsigned)((M + 63) / 64);
+  for (int32_t t0 = 0; t0 < ctx->nkept;) {
+    // whole kept k per chunk
+    int32_t t1 = t0 + 1;
+    while (t1 < ctx->nkept && soff[t1 + 1] - soff[t0] <= cap) ++t1;
+    const int64_t i0 = soff[t0], ni = soff[t1] - soff[t0];
+    const int64_t c0 = i0 * NX, nc = ni * NX;
+    hipLaunchKernelGGL(k_cgemm_split<NS>, dim3(jblk, (unsigned)((nc + 63) / 64)), dim3(256), 0, ctx->stream, c0, nc,
+                       M, ctx->kp, NX, (const unsigned short*)ctx->d_B2, (const unsigned short*)ctx->d_Ap, C, ldc);
+    hipLaunchKernelGGL((k_epi_q<ST, NX>), dim3((unsigned)((ctx->nk + 3) / 4)), dim3(256), 0, ctx->stream, ctx->nk,
+                       i0, t0, t1, ep, ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist,
+                       (const float*)C, ldc, (ST*)Bp, (ST*)Bm);
+    t0 = t1;
+  }
+  dev_free(ctx, C);
+  if (ep.we_part) {
+    // W_e into the first partial row; the caller's reduction copies it out
+    launch_we_rows<ST>(ctx, (const ST*)Bp, (const ST*)Bm, ep.lomf, ep.nocc, ep.we_part);
+    *we_tiles = 1;
+  }
+  return ELPH_OK;
+}
+
 template <typename T, typename ST>
-static elph_status launch_step2_t(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm) {
+static elph_status launch_step2_t(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm, int64_t* we_tiles) {
+  *we_tiles = ctx->m_pad / 32;
+  if constexpr (IsSplit<T>::value) {
+    constexpr int NS = IsSplit<T>::ns;
+    if (!ep.tile_keep) {
+      switch (ctx->nbr) {
+        case 3: return launch_split_nx<NS, ST, 3>(ctx, ep, Bp, Bm, we_tiles);
+        case 6: return launch_split_nx<NS, ST, 6>(ctx, ep, Bp, Bm, we_tiles);
+        case 9: return launch_split_nx<NS, ST, 9>(ctx, ep, Bp, Bm, we_tiles);
+        case 12: return launch_split_nx<NS, ST, 12>(ctx, ep, Bp, Bm, we_tiles);
+        case 15: return launch_split_nx<NS, ST, 15>(ctx, ep, Bp, Bm, we_tiles);
+        default: ctx->err = "unsupported branch count"; return ELPH_EINVAL;
+      }
+    }
+  }
   switch (ctx->nbr) {
     case 3: launch_step2_nx<T, ST, 3>(ctx, ep, Bp, Bm); break;
     case 6: launch_step2_nx<T, ST, 6>(ctx, ep, Bp, Bm); break;
@@ -870,7 +1182,7 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
   elph_status st = build_operands(ctx);
   if (st != ELPH_OK) return st;
   EpiParams ep = epi_params(ctx);
-  const int64_t ntiles = ctx->m_pad / 32;
+  int64_t we_tiles = ctx->m_pad / 32;
   if (th) {
     st = ensure_we_part(ctx);
     if (st != ELPH_OK) return st;
@@ -883,39 +1195,43 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
   }
   if (ctx->precision == ELPH_FP64) {
     mark(ctx, 2);
-    launch_step1_t<double>(ctx);
+    st = launch_step1_t<double>(ctx);
+    if (st != ELPH_OK) return st;
     mark(ctx, 3);
     mark(ctx, 4);
-    st = store_f64 ? launch_step2_t<double, double>(ctx, ep, Bp, Bm) : launch_step2_t<double, float>(ctx, ep, Bp, Bm);
+    st = store_f64 ? launch_step2_t<double, double>(ctx, ep, Bp, Bm, &we_tiles) : launch_step2_t<double, float>(ctx, ep, Bp, Bm, &we_tiles);
     mark(ctx, 5);
   } else if (ctx->precision == ELPH_FP32) {
     mark(ctx, 2);
-    launch_step1_t<float>(ctx);
+    st = launch_step1_t<float>(ctx);
+    if (st != ELPH_OK) return st;
     mark(ctx, 3);
     mark(ctx, 4);
-    st = store_f64 ? launch_step2_t<float, double>(ctx, ep, Bp, Bm) : launch_step2_t<float, float>(ctx, ep, Bp, Bm);
+    st = store_f64 ? launch_step2_t<float, double>(ctx, ep, Bp, Bm, &we_tiles) : launch_step2_t<float, float>(ctx, ep, Bp, Bm, &we_tiles);
     mark(ctx, 5);
   } else if (ctx->precision == ELPH_BF16X3) {
     mark(ctx, 2);
-    launch_step1_t<Bf16S<2>>(ctx);
+    st = launch_step1_t<Bf16S<2>>(ctx);
+    if (st != ELPH_OK) return st;
     mark(ctx, 3);
     mark(ctx, 4);
-    st = store_f64 ? launch_step2_t<Bf16S<2>, double>(ctx, ep, Bp, Bm)
-                   : launch_step2_t<Bf16S<2>, float>(ctx, ep, Bp, Bm);
+    st = store_f64 ? launch_step2_t<Bf16S<2>, double>(ctx, ep, Bp, Bm, &we_tiles)
+                   : launch_step2_t<Bf16S<2>, float>(ctx, ep, Bp, Bm, &we_tiles);
     mark(ctx, 5);
   } else {
     mark(ctx, 2);
-    launch_step1_t<Bf16S<3>>(ctx);
+    st = launch_step1_t<Bf16S<3>>(ctx);
+    if (st != ELPH_OK) return st;
     mark(ctx, 3);
     mark(ctx, 4);
-    st = store_f64 ? launch_step2_t<Bf16S<3>, double>(ctx, ep, Bp, Bm)
-                   : launch_step2_t<Bf16S<3>, float>(ctx, ep, Bp, Bm);
+    st = store_f64 ? launch_step2_t<Bf16S<3>, double>(ctx, ep, Bp, Bm, &we_tiles)
+                   : launch_step2_t<Bf16S<3>, float>(ctx, ep, Bp, Bm, &we_tiles);
     mark(ctx, 5);
   }
   if (st != ELPH_OK) return st;
   if (th && we_out) {
     hipLaunchKernelGGL(k_reduce_we, dim3(blocks_for(ctx->nstates, 256)), dim3(256), 0, ctx->stream,
-                       ctx->d_we_part, ntiles, ctx->m_pad, ctx->nstates, we_out);
+                       ctx->d_we_part, we_tiles, ctx->m_pad, ctx->nstates, we_out);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
