@@ -149,8 +149,10 @@ enum { ELPH_RESET_ALL = 0, ELPH_RESET_STORE = 1, ELPH_RESET_TRIM = 2 };
 elph_status elph_reset(elph_ctx ctx, int32_t what);
 
 /* Kernel timing with HIP events recorded on the context's stream around
- * the table build, the step-1 contraction, the step-2 contraction (fused with
- * the rate epilogue) and the whole iteration.  enable = 1 turns recording on
+ * the table build, the step-1 contraction (with its epilogue), the step-2
+ * contraction (FP64/FP32 forms: the kernel fused with the rate epilogue;
+ * BF16 split forms: the GEMM kernel alone, its per-q epilogue follows) and
+ * the whole iteration.  enable = 1 turns recording on
  * for later calls, 0 turns it off.  ms (host, may be NULL) receives the
  * durations of the most recent recorded launches in milliseconds:
  * [tables, step1, step2, iterate] (-1 where nothing was recorded);

@@ -717,7 +717,8 @@ __device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&na_im)
 
 // rows c in [c0, c0 + nc) (c0 a multiple of nx), all j < nj; C is stored as
 // [(c - c0) / nx][j][(c - c0) % nx] with j stride nx (ldc >= nj)
-template <int NS>
+// STEP (1 or 2) only names the instance, so profiles tell the two steps apart
+template <int NS, int STEP>
 __global__ void __launch_bounds__(256) k_cgemm_split(int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx,
                                                      const unsigned short* __restrict__ Bm2,
                                                      const unsigned short* __restrict__ Apm, float* __restrict__ C,
@@ -1033,7 +1034,7 @@ static elph_status launch_step1_t(elph_ctx ctx) {
     }
     for (int64_t i0 = 0; i0 < M; i0 += ci) {
       const int64_t ni = (M - i0 < ci) ? M - i0 : ci;
-      hipLaunchKernelGGL(k_cgemm_split<NS>, dim3((unsigned)((ncol + 63) / 64), (unsigned)((ni + 63) / 64)),
+      hipLaunchKernelGGL((k_cgemm_split<NS, 1>), dim3((unsigned)((ncol + 63) / 64), (unsigned)((ni + 63) / 64)),
                          dim3(256), 0, ctx->stream, i0, ni, ncol, ctx->ke, 1, (const unsigned short*)ctx->d_Ae,
                          (const unsigned short*)ctx->d_gR, (float*)p, ncol);
       hipLaunchKernelGGL(k_step1_epi_split<NS>, dim3(blocks_for(ni * ncol, 256)), dim3(256), 0, ctx->stream, i0, ni,
@@ -1087,14 +1088,17 @@ static elph_status launch_split_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, 
   }
   float* C = (float*)p;
   const unsigned jblk = (unsigned)((M + 63) / 64);
+  mark(ctx, 4);  // the step-2 window starts at the contraction (pair lists are built above)
   for (int32_t t0 = 0; t0 < ctx->nkept;) {
     // whole kept k per chunk
     int32_t t1 = t0 + 1;
     while (t1 < ctx->nkept && soff[t1 + 1] - soff[t0] <= cap) ++t1;
     const int64_t i0 = soff[t0], ni = soff[t1] - soff[t0];
     const int64_t c0 = i0 * NX, nc = ni * NX;
-    hipLaunchKernelGGL(k_cgemm_split<NS>, dim3(jblk, (unsigned)((nc + 63) / 64)), dim3(256), 0, ctx->stream, c0, nc,
-                       M, ctx->kp, NX, (const unsigned short*)ctx->d_B2, (const unsigned short*)ctx->d_Ap, C, ldc);
+    hipLaunchKernelGGL((k_cgemm_split<NS, 2>), dim3(jblk, (unsigned)((nc + 63) / 64)), dim3(256), 0, ctx->stream,
+                       c0, nc, M, ctx->kp, NX, (const unsigned short*)ctx->d_B2, (const unsigned short*)ctx->d_Ap, C,
+                       ldc);
+    if (t1 == ctx->nkept) mark(ctx, 5);  // step-2 window: the contraction (and earlier chunks' epilogues)
     hipLaunchKernelGGL((k_epi_q<ST, NX>), dim3((unsigned)((ctx->nk + 3) / 4)), dim3(256), 0, ctx->stream, ctx->nk,
                        i0, t0, t1, ep, ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist,
                        (const float*)C, ldc, (ST*)Bp, (ST*)Bm);
@@ -1217,7 +1221,7 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     mark(ctx, 4);
     st = store_f64 ? launch_step2_t<Bf16S<2>, double>(ctx, ep, Bp, Bm, &we_tiles)
                    : launch_step2_t<Bf16S<2>, float>(ctx, ep, Bp, Bm, &we_tiles);
-    mark(ctx, 5);
+    if (ep.tile_keep) mark(ctx, 5);
   } else {
     mark(ctx, 2);
     st = launch_step1_t<Bf16S<3>>(ctx);
@@ -1226,7 +1230,7 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     mark(ctx, 4);
     st = store_f64 ? launch_step2_t<Bf16S<3>, double>(ctx, ep, Bp, Bm, &we_tiles)
                    : launch_step2_t<Bf16S<3>, float>(ctx, ep, Bp, Bm, &we_tiles);
-    mark(ctx, 5);
+    if (ep.tile_keep) mark(ctx, 5);
   }
   if (st != ELPH_OK) return st;
   if (th && we_out) {
