@@ -717,39 +717,56 @@ __device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&na_im)
 
 // rows c in [c0, c0 + nc) (c0 a multiple of nx), all j < nj; C is stored as
 // [(c - c0) / nx][j][(c - c0) % nx] with j stride nx (ldc >= nj)
-// STEP (1 or 2) only names the instance, so profiles tell the two steps apart
-template <int NS, int STEP>
-__global__ void __launch_bounds__(256) k_cgemm_split(int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx,
-                                                     const unsigned short* __restrict__ Bm2,
-                                                     const unsigned short* __restrict__ Apm, float* __restrict__ C,
-                                                     int64_t ldc) {
+// STEP (1 or 2) only names the instance, so profiles tell the two steps
+// apart.  WR wavefronts along rows: the block computes 32*WR rows c x 64
+// columns j with 128*WR threads.
+template <int NS, int STEP, int WR>
+__global__ void __launch_bounds__(128 * WR) k_cgemm_split(int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx,
+                                                          const unsigned short* __restrict__ Bm2,
+                                                          const unsigned short* __restrict__ Apm,
+                                                          float* __restrict__ C, int64_t ldc) {
   typedef SplitGemm<NS> G;
-  __shared__ __attribute__((aligned(16))) unsigned short As[64 * G::kLdsRow];
+  constexpr int NT = 128 * WR, RA = 32 * WR;
+  __shared__ __attribute__((aligned(16))) unsigned short As[RA * G::kLdsRow];
   __shared__ __attribute__((aligned(16))) unsigned short Bs[64 * G::kLdsRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t cb = c0 + (int64_t)blockIdx.y * 64;   // first row c of the block
+  const int64_t cb = c0 + (int64_t)blockIdx.y * RA;   // first row c of the block
   const int64_t jb = (int64_t)blockIdx.x * 64;        // first column j
   const int64_t rowlen = K * 2 * NS;                  // ushorts per operand row
   const int nst = (int)(K / 32);
-  constexpr int per_thread = (64 * G::kChunks) / 256;  // chunks per thread and operand (2NS)
-  uint4 ra[per_thread], rb[per_thread];
+  constexpr int PA = RA * G::kChunks / NT;            // 16-byte chunks per thread, A tile
+  constexpr int PB = 64 * G::kChunks / NT;            // and B tile
+  static_assert(PA * NT == RA * G::kChunks && PB * NT == 64 * G::kChunks, "tile split");
+  uint4 ra[PA], rb[PB];
   auto fetch = [&](int s) {
+    const int64_t so = (int64_t)s * G::kRowU;
 #pragma unroll
-    for (int u = 0; u < per_thread; ++u) {
-      const int e = tid + 256 * u;
+    for (int u = 0; u < PA; ++u) {
+      const int e = tid + NT * u;
       const int row = e / G::kChunks, w = e - row * G::kChunks;
-      const int64_t ca = cb + row, jr = jb + row;
-      const int64_t off = (int64_t)s * G::kRowU + (int64_t)w * 8;
-      ra[u] = (ca < c0 + nc) ? *reinterpret_cast<const uint4*>(Bm2 + ca * rowlen + off) : make_uint4(0, 0, 0, 0);
-      rb[u] = (jr < nj) ? *reinterpret_cast<const uint4*>(Apm + jr * rowlen + off) : make_uint4(0, 0, 0, 0);
+      const int64_t ca = cb + row;
+      ra[u] = (ca < c0 + nc) ? *reinterpret_cast<const uint4*>(Bm2 + ca * rowlen + so + w * 8)
+                             : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int e = tid + NT * u;
+      const int row = e / G::kChunks, w = e - row * G::kChunks;
+      const int64_t jr = jb + row;
+      rb[u] = (jr < nj) ? *reinterpret_cast<const uint4*>(Apm + jr * rowlen + so + w * 8) : make_uint4(0, 0, 0, 0);
     }
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int u = 0; u < per_thread; ++u) {
-      const int e = tid + 256 * u;
+    for (int u = 0; u < PA; ++u) {
+      const int e = tid + NT * u;
       const int row = e / G::kChunks, w = e - row * G::kChunks;
       *reinterpret_cast<uint4*>(As + row * G::kLdsRow + w * 8) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int e = tid + NT * u;
+      const int row = e / G::kChunks, w = e - row * G::kChunks;
       *reinterpret_cast<uint4*>(Bs + row * G::kLdsRow + w * 8) = rb[u];
     }
   };
@@ -804,6 +821,9 @@ __global__ void __launch_bounds__(256) k_cgemm_split(int64_t c0, int64_t nc, int
     }
   }
 }
+
+// rows per block of the split GEMM (WR = 4: 128 rows)
+constexpr int kSplitWR = 4;
 
 // Epilogue of the split path, one wavefront per q: the phonon factors of q
 // (l u, hbar omega) are wavefront-uniform; lanes take the kept pairs
@@ -1034,8 +1054,9 @@ static elph_status launch_step1_t(elph_ctx ctx) {
     }
     for (int64_t i0 = 0; i0 < M; i0 += ci) {
       const int64_t ni = (M - i0 < ci) ? M - i0 : ci;
-      hipLaunchKernelGGL((k_cgemm_split<NS, 1>), dim3((unsigned)((ncol + 63) / 64), (unsigned)((ni + 63) / 64)),
-                         dim3(256), 0, ctx->stream, i0, ni, ncol, ctx->ke, 1, (const unsigned short*)ctx->d_Ae,
+      hipLaunchKernelGGL((k_cgemm_split<NS, 1, kSplitWR>),
+                         dim3((unsigned)((ncol + 63) / 64), (unsigned)((ni + 32 * kSplitWR - 1) / (32 * kSplitWR))),
+                         dim3(128 * kSplitWR), 0, ctx->stream, i0, ni, ncol, ctx->ke, 1, (const unsigned short*)ctx->d_Ae,
                          (const unsigned short*)ctx->d_gR, (float*)p, ncol);
       hipLaunchKernelGGL(k_step1_epi_split<NS>, dim3(blocks_for(ni * ncol, 256)), dim3(256), 0, ctx->stream, i0, ni,
                          ncol, ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, (const float*)p, ctx->d_state_kidx,
@@ -1095,7 +1116,9 @@ static elph_status launch_split_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, 
     while (t1 < ctx->nkept && soff[t1 + 1] - soff[t0] <= cap) ++t1;
     const int64_t i0 = soff[t0], ni = soff[t1] - soff[t0];
     const int64_t c0 = i0 * NX, nc = ni * NX;
-    hipLaunchKernelGGL((k_cgemm_split<NS, 2>), dim3(jblk, (unsigned)((nc + 63) / 64)), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL((k_cgemm_split<NS, 2, kSplitWR>),
+                       dim3(jblk, (unsigned)((nc + 32 * kSplitWR - 1) / (32 * kSplitWR))), dim3(128 * kSplitWR), 0,
+                       ctx->stream,
                        c0, nc, M, ctx->kp, NX, (const unsigned short*)ctx->d_B2, (const unsigned short*)ctx->d_Ap, C,
                        ldc);
     if (t1 == ctx->nkept) mark(ctx, 5);  // step-2 window: the contraction (and earlier chunks' epilogues)
