@@ -8,6 +8,7 @@
 //    Eq. 6 (l_{x,s} u_q[x,s], with l = sqrt(C / (2 M hbar omega))).
 #include "tables.h"
 
+#include <algorithm>
 #include <utility>
 
 namespace elph {
@@ -52,53 +53,111 @@ __device__ inline void mesh_coords(int64_t lin, int n1, int n2, int& a, int& b, 
 
 // Fourier sum over R for a list of mesh points: out[p][a][b] = sum_R w_R e^{ik.R} M(R)[a][b]
 // and optionally grad[p][c][a][b] = sum_R i R_cart[c] w_R e^{ik.R} M(R)[a][b].
-// One block handles KPB points; the phases of its points are staged in LDS.
-template <bool REAL_IN, bool GRAD>
-__global__ void k_fourier(MeshPhase ph, const int32_t* __restrict__ pts, int64_t base, int64_t npts,
-                          const int32_t* __restrict__ R, const double* __restrict__ w, int nR,
-                          const double* __restrict__ lat, const double* __restrict__ Min, int n,
-                          int kpb, cd* __restrict__ out, cd* __restrict__ grad) {
-  extern __shared__ cd sph[];  // [kpb][nR]
-  const int nn = n * n;
-  const int64_t p0 = (int64_t)blockIdx.x * kpb;
-  for (int t = threadIdx.x; t < kpb * nR; t += blockDim.x) {
-    int lp = t / nR, r = t % nR;
-    int64_t p = p0 + lp;
-    cd z = cmake(0, 0);
-    if (p < npts) {
-      int a, b, c;
-      mesh_coords(pts ? (int64_t)pts[p] : base + p, ph.n1, ph.n2, a, b, c);
-      z = cscale(ph(a, b, c, R[3 * r], R[3 * r + 1], R[3 * r + 2]), w ? w[r] : 1.0);
-    }
-    sph[t] = z;
+// The same sums as a complex GEMM on the 16x16x4 FP64 MFMA:
+// out[p][col] = sum_r A[p][r] M[r][col] with A[p][r] = w_r e^{2 pi i k_p.R_r}.
+// A wavefront owns 16 points x 16 columns; lane l supplies A[l%16][r0 + l/16]
+// (its phase computed from the per-axis tables) and M[r0 + l/16][col0 + l%16];
+// the gradient is three more products with A scaled by i R_cart.  The
+// accumulator of lane l holds rows l/16 + 4r, column l%16.
+typedef double d4f __attribute__((ext_vector_type(4)));
+
+__device__ inline d4f mma64(double a, double b, d4f c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// exp(2 pi i k.R) from the per-axis tables with 32-bit index arithmetic
+// (|a R| < 2^31 for the meshes and R sets here)
+__device__ inline cd phase32(const MeshPhase& ph, int a, int b, int c, int r0, int r1, int r2) {
+  int i0 = (a * r0) % ph.n0; if (i0 < 0) i0 += ph.n0;
+  int i1 = (b * r1) % ph.n1; if (i1 < 0) i1 += ph.n1;
+  int i2 = (c * r2) % ph.n2; if (i2 < 0) i2 += ph.n2;
+  const double2 p0 = ph.t0[i0], p1 = ph.t1[i1], p2 = ph.t2[i2];
+  return cmul(cmul(cmake(p0.x, p0.y), cmake(p1.x, p1.y)), cmake(p2.x, p2.y));
+}
+
+// CT column tiles of 16 per wavefront share each computed phase.
+template <bool REAL_IN, bool GRAD, int CT>
+__global__ void __launch_bounds__(256) k_fourier_mfma(MeshPhase ph, const int32_t* __restrict__ pts, int64_t base,
+                                                      int64_t npts, const int32_t* __restrict__ R,
+                                                      const double* __restrict__ w, int nR,
+                                                      const double* __restrict__ lat, const double* __restrict__ Min,
+                                                      int nn, cd* __restrict__ out, cd* __restrict__ grad) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (p0 >= npts) return;  // whole wavefront
+  const int colb = blockIdx.y * 16 * CT;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t p = p0 + lr;
+  const bool pv = p < npts;
+  int a = 0, b = 0, c = 0;
+  if (pv) mesh_coords(pts ? (int64_t)pts[p] : base + p, ph.n1, ph.n2, a, b, c);
+  constexpr int NG = GRAD ? 3 : 0;
+  const d4f zero = {0.0, 0.0, 0.0, 0.0};
+  d4f vr[CT], vi[CT], gr[CT][NG > 0 ? NG : 1], gi[CT][NG > 0 ? NG : 1];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    vr[t] = zero;
+    vi[t] = zero;
+#pragma unroll
+    for (int d = 0; d < (NG > 0 ? NG : 1); ++d) gr[t][d] = gi[t][d] = zero;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kpb * nn; e += blockDim.x) {
-    int lp = e / nn, ab = e % nn;
-    int64_t p = p0 + lp;
-    if (p >= npts) continue;
-    cd acc = cmake(0, 0);
-    cd g0 = cmake(0, 0), g1 = cmake(0, 0), g2 = cmake(0, 0);
-    for (int r = 0; r < nR; ++r) {
-      cd z = sph[lp * nR + r];
-      cd m;
-      if (REAL_IN) m = cmake(Min[(int64_t)r * nn + ab], 0.0);
-      else m = cmake(Min[2 * ((int64_t)r * nn + ab)], Min[2 * ((int64_t)r * nn + ab) + 1]);
-      cd zm = cmul(z, m);
-      acc = cadd(acc, zm);
+  for (int r0 = 0; r0 < nR; r0 += 4) {
+    const int r = r0 + lk;
+    cd z = cmake(0.0, 0.0);
+    double rc[3] = {0.0, 0.0, 0.0};
+    const bool rv = r < nR;
+    if (rv) {
+      const int R0 = R[3 * r], R1 = R[3 * r + 1], R2 = R[3 * r + 2];
+      if (pv) {
+        z = phase32(ph, a, b, c, R0, R1, R2);
+        if (w) z = cscale(z, w[r]);
+      }
+      if (GRAD)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rc[d] = R0 * lat[d] + R1 * lat[3 + d] + R2 * lat[6 + d];
+    }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int col = colb + 16 * t + lr;
+      double mr = 0.0, mi = 0.0;
+      if (rv && col < nn) {
+        if (REAL_IN) {
+          mr = Min[(int64_t)r * nn + col];
+        } else {
+          mr = Min[2 * ((int64_t)r * nn + col)];
+          mi = Min[2 * ((int64_t)r * nn + col) + 1];
+        }
+      }
+      vr[t] = mma64(z.x, mr, vr[t]);
+      vi[t] = mma64(z.y, mr, vi[t]);
+      if (!REAL_IN) {
+        vr[t] = mma64(-z.y, mi, vr[t]);
+        vi[t] = mma64(z.x, mi, vi[t]);
+      }
       if (GRAD) {
-        double r0 = R[3 * r], r1 = R[3 * r + 1], r2 = R[3 * r + 2];
-        cd izm = cmake(-zm.y, zm.x);
-        g0 = cadd(g0, cscale(izm, r0 * lat[0] + r1 * lat[3] + r2 * lat[6]));
-        g1 = cadd(g1, cscale(izm, r0 * lat[1] + r1 * lat[4] + r2 * lat[7]));
-        g2 = cadd(g2, cscale(izm, r0 * lat[2] + r1 * lat[5] + r2 * lat[8]));
+#pragma unroll
+        for (int d = 0; d < NG; ++d) {
+          const double zr = -rc[d] * z.y, zi = rc[d] * z.x;  // i R_cart z
+          gr[t][d] = mma64(zr, mr, gr[t][d]);
+          gi[t][d] = mma64(zi, mr, gi[t][d]);
+          if (!REAL_IN) {
+            gr[t][d] = mma64(-zi, mi, gr[t][d]);
+            gi[t][d] = mma64(zr, mi, gi[t][d]);
+          }
+        }
       }
     }
-    out[p * nn + ab] = acc;
-    if (GRAD) {
-      grad[(p * 3 + 0) * nn + ab] = g0;
-      grad[(p * 3 + 1) * nn + ab] = g1;
-      grad[(p * 3 + 2) * nn + ab] = g2;
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int col = colb + 16 * t + lr;
+    if (col >= nn) continue;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t pp = p0 + lk + 4 * rr;
+      if (pp >= npts) continue;
+      out[pp * nn + col] = cmake(vr[t][rr], vi[t][rr]);
+      if (GRAD)
+#pragma unroll
+        for (int d = 0; d < NG; ++d) grad[(pp * 3 + d) * nn + col] = cmake(gr[t][d][rr], gi[t][d][rr]);
     }
   }
 }
@@ -398,28 +457,35 @@ __global__ void k_fill_states(const int32_t* __restrict__ kept, int64_t nkept, c
 
 // Electron: v[m] = Re(U[:,m]^H dH_c U[:,m]) (A eV -> m/s), averaged over
 // degenerate groups of eps, written for active states of each kept k.
-__global__ void k_electron_vel(int64_t nkept, int nb, const cd* __restrict__ U, const cd* __restrict__ dH,
+__global__ void k_electron_vd(int64_t nkept, int nb, const cd* __restrict__ U, const cd* __restrict__ dH,
+                              double* __restrict__ vd) {
+  // thread per (kept k t, direction c, band m): u_m^+ (dH/dk_c) u_m / hbar
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nkept * 3 * nb) return;
+  const int64_t t = e / (3 * nb);
+  const int cm = (int)(e - t * 3 * nb), c = cm / nb, m = cm - c * nb;
+  const int64_t nn = (int64_t)nb * nb;
+  const cd* u = U + t * nn;
+  const cd* h = dH + (t * 3 + c) * nn;
+  double acc = 0.0;
+  for (int a = 0; a < nb; ++a) {
+    cd row = cmake(0, 0);
+    for (int b = 0; b < nb; ++b) row = cadd(row, cmul(h[a * nb + b], u[b * nb + m]));
+    acc += cmul(cconj(u[a * nb + m]), row).x;
+  }
+  vd[(t * nb + m) * 3 + c] = acc * (kAngM / kHbarEVs);
+}
+
+// average over degenerate bands, then keep the active states' velocities
+__global__ void k_electron_vel(int64_t nkept, int nb, const double* __restrict__ vdin,
                                const double* __restrict__ eps_all, const int32_t* __restrict__ kept,
                                const int32_t* __restrict__ soff, double mu, double window, double degen,
                                double* __restrict__ vel) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nkept) return;
-  const int64_t nn = (int64_t)nb * nb;
-  const cd* u = U + t * nn;
   double vd[kMaxBands][3];
-  const double conv = kAngM / kHbarEVs;
-  for (int m = 0; m < nb; ++m) {
-    for (int c = 0; c < 3; ++c) {
-      const cd* h = dH + (t * 3 + c) * nn;
-      double acc = 0.0;
-      for (int a = 0; a < nb; ++a) {
-        cd row = cmake(0, 0);
-        for (int b = 0; b < nb; ++b) row = cadd(row, cmul(h[a * nb + b], u[b * nb + m]));
-        acc += cmul(cconj(u[a * nb + m]), row).x;
-      }
-      vd[m][c] = acc * conv;
-    }
-  }
+  for (int m = 0; m < nb; ++m)
+    for (int c = 0; c < 3; ++c) vd[m][c] = vdin[(t * nb + m) * 3 + c];
   const double* e = eps_all + (int64_t)kept[t] * nb;
   int start = 0;
   for (int b = 1; b <= nb; ++b) {
@@ -444,59 +510,68 @@ __global__ void k_electron_vel(int64_t nkept, int nb, const cd* __restrict__ U, 
   }
 }
 
-// Phonons: hbar omega, l*u table, velocities (Eq. 5) for a chunk of q.
-__global__ void k_phonon_derived(int64_t nq, int nbr, const double* __restrict__ lam, const cd* __restrict__ u,
-                                 const cd* __restrict__ dD, const double* __restrict__ mass_x, double omega_min,
-                                 double degen, double* __restrict__ hw, cd* __restrict__ Lq,
-                                 double* __restrict__ vph) {
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+// Phonon factors per element: hbar omega_s = sqrt(C max(lambda_s, 0)) and
+// Lq[q][x][s] = l_{x,s} u_q[x][s] with l = sqrt(C / (2 M_x hbar omega_s))
+// (zero for modes below omega_min); thread per (q, x, s).
+__global__ void k_phonon_hw_L(int64_t nq, int nbr, const double* __restrict__ lam, const cd* __restrict__ u,
+                              const double* __restrict__ mass_x, double omega_min, double* __restrict__ hw,
+                              cd* __restrict__ Lq) {
   const int64_t nn = (int64_t)nbr * nbr;
-  double w[kMaxBands];
-  double vd[kMaxBands][3];
-  const double conv = kAngM / kHbarEVs;
-  for (int s = 0; s < nbr; ++s) {
-    double l = lam[q * nbr + s];
-    w[s] = sqrt(kPhononC * (l > 0.0 ? l : 0.0));
-    hw[q * nbr + s] = w[s];
-  }
-  for (int s = 0; s < nbr; ++s) {
-    const bool on = w[s] >= omega_min;
-    for (int x = 0; x < nbr; ++x) {
-      cd val = cmake(0, 0);
-      if (on) val = cscale(u[q * nn + x * nbr + s], sqrt(kPhononC / (2.0 * mass_x[x] * w[s])));
-      Lq[q * nn + x * nbr + s] = val;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nq * nn) return;
+  const int64_t q = e / nn;
+  const int xs = (int)(e - q * nn), x = xs / nbr, s = xs - x * nbr;
+  const double l = lam[q * nbr + s];
+  const double w = sqrt(kPhononC * (l > 0.0 ? l : 0.0));
+  if (x == 0) hw[q * nbr + s] = w;
+  Lq[e] = (w >= omega_min) ? cscale(u[e], sqrt(kPhononC / (2.0 * mass_x[x] * w))) : cmake(0.0, 0.0);
+}
+
+// Branch velocities (Eq. 5) v_c = (C / (2 hbar omega)) u_s^+ (dD/dq_c) u_s / hbar
+// before degenerate averaging; thread per (q, c, s), result in vph.
+__global__ void k_phonon_vel(int64_t nq, int nbr, const double* __restrict__ hw, const cd* __restrict__ u,
+                             const cd* __restrict__ dD, double omega_min, double* __restrict__ vph) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nq * 3 * nbr) return;
+  const int64_t q = e / (3 * nbr);
+  const int cs = (int)(e - q * 3 * nbr), c = cs / nbr, s = cs - c * nbr;
+  const int64_t nn = (int64_t)nbr * nbr;
+  const double w = hw[q * nbr + s];
+  double acc = 0.0;
+  if (w >= omega_min) {
+    const cd* d = dD + (q * 3 + c) * nn;
+    const cd* uq = u + q * nn;
+    for (int a = 0; a < nbr; ++a) {
+      cd row = cmake(0, 0);
+      for (int b = 0; b < nbr; ++b) row = cadd(row, cmul(d[a * nbr + b], uq[b * nbr + s]));
+      acc += cmul(cconj(uq[a * nbr + s]), row).x;
     }
-    for (int c = 0; c < 3; ++c) {
-      double acc = 0.0;
-      if (on) {
-        const cd* d = dD + (q * 3 + c) * nn;
-        for (int a = 0; a < nbr; ++a) {
-          cd row = cmake(0, 0);
-          for (int b = 0; b < nbr; ++b) row = cadd(row, cmul(d[a * nbr + b], u[q * nn + b * nbr + s]));
-          acc += cmul(cconj(u[q * nn + a * nbr + s]), row).x;
-        }
-        acc = kPhononC * acc / (2.0 * w[s]) * conv;
-      }
-      vd[s][c] = acc;
-    }
+    acc = kPhononC * acc / (2.0 * w) * (kAngM / kHbarEVs);
   }
+  vph[(q * nbr + s) * 3 + c] = acc;
+}
+
+// Average the branch velocities over groups of (near-)degenerate branches.
+__global__ void k_phonon_degen(int64_t nq, int nbr, const double* __restrict__ hw, double degen,
+                               double* __restrict__ vph) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const double* w = hw + q * nbr;
+  double* v = vph + q * nbr * 3;
   int start = 0;
   for (int b = 1; b <= nbr; ++b) {
     if (b == nbr || w[b] - w[b - 1] >= degen) {
       if (b - start > 1) {
         for (int c = 0; c < 3; ++c) {
           double s = 0;
-          for (int m = start; m < b; ++m) s += vd[m][c];
+          for (int m = start; m < b; ++m) s += v[m * 3 + c];
           s /= (double)(b - start);
-          for (int m = start; m < b; ++m) vd[m][c] = s;
+          for (int m = start; m < b; ++m) v[m * 3 + c] = s;
         }
       }
       start = b;
     }
   }
-  for (int s = 0; s < nbr; ++s)
-    for (int c = 0; c < 3; ++c) vph[(q * nbr + s) * 3 + c] = vd[s][c];
 }
 
 // phase tables of kept k: Ee[t][r] = w_r e^{2 pi i k.Re_r}, Ep[t][r] = e^{2 pi i k.Rp_r}
@@ -531,21 +606,14 @@ __global__ void k_max_reduce(const double* __restrict__ x, int64_t n, double* __
 // host drivers
 
 
-static int fourier_kpb(int n, int nR) {
-  int kpb = 256 / (n * n);
-  if (kpb < 1) kpb = 1;
-  int lds_cap = (48 * 1024) / (nR * (int)sizeof(cd));
-  if (lds_cap < 1) lds_cap = 1;
-  return kpb < lds_cap ? kpb : lds_cap;
-}
-
 template <bool REAL_IN, bool GRAD>
 static void launch_fourier(elph_ctx ctx, const int32_t* pts, int64_t base, int64_t npts, const int32_t* R,
                            const double* w, int nR, const double* Min, int n, cd* out, cd* grad) {
-  int kpb = fourier_kpb(n, nR);
-  size_t lds = (size_t)kpb * nR * sizeof(cd);
-  hipLaunchKernelGGL((k_fourier<REAL_IN, GRAD>), dim3(blocks_for(npts, kpb)), dim3(256), lds, ctx->stream,
-                     mesh_phase(ctx), pts, base, npts, R, w, nR, ctx->d_lat, Min, n, kpb, out, grad);
+  const int nn = n * n;
+  constexpr int CT = GRAD ? 1 : 4;  // column tiles per wavefront
+  hipLaunchKernelGGL((k_fourier_mfma<REAL_IN, GRAD, CT>),
+                     dim3(blocks_for(npts, 64), (unsigned)((nn + 16 * CT - 1) / (16 * CT))), dim3(256), 0,
+                     ctx->stream, mesh_phase(ctx), pts, base, npts, R, w, nR, ctx->d_lat, Min, nn, out, grad);
 }
 
 elph_status build_tables(elph_ctx ctx) {
@@ -614,14 +682,17 @@ elph_status build_tables(elph_ctx ctx) {
 
   // ---- eigenvectors and velocities of kept k (Eqs. 1, 2)
   ALLOC(ctx->d_U, ctx->nkept * (int64_t)nb * nb * sizeof(cd));
+  double* vdbuf = nullptr;
+  ALLOC(vdbuf, std::min<int64_t>(chunk, ctx->nkept) * nb * 3 * sizeof(double));
   for (int64_t k0 = 0; k0 < ctx->nkept; k0 += chunk) {
     int64_t cnt = (ctx->nkept - k0 < chunk) ? ctx->nkept - k0 : chunk;
     launch_fourier<false, true>(ctx, ctx->d_kept + k0, 0, cnt, ctx->d_re, ctx->d_wre, ctx->nre, ctx->d_hr, nb, hbuf,
                                 gbuf);
     launch_jacobi(hbuf, cnt, nb, nullptr, (cd*)ctx->d_U + k0 * nb * nb, s);
-    hipLaunchKernelGGL(k_electron_vel, dim3(blocks_for(cnt, 64)), dim3(64), 0, s, cnt, nb,
-                       (const cd*)ctx->d_U + k0 * nb * nb, gbuf, ctx->d_eps_all, ctx->d_kept + k0,
-                       ctx->d_soff + k0, ctx->mu, ctx->window, 1.0e-6, ctx->d_vel);
+    hipLaunchKernelGGL(k_electron_vd, dim3(blocks_for(cnt * 3 * nb, 256)), dim3(256), 0, s, cnt, nb,
+                       (const cd*)ctx->d_U + k0 * nb * nb, gbuf, vdbuf);
+    hipLaunchKernelGGL(k_electron_vel, dim3(blocks_for(cnt, 64)), dim3(64), 0, s, cnt, nb, vdbuf, ctx->d_eps_all,
+                       ctx->d_kept + k0, ctx->d_soff + k0, ctx->mu, ctx->window, 1.0e-6, ctx->d_vel);
   }
   HIPCHK(hipGetLastError());
 
@@ -637,9 +708,12 @@ elph_status build_tables(elph_ctx ctx) {
     int64_t cnt = (nk - q0 < chunk) ? nk - q0 : chunk;
     launch_fourier<true, true>(ctx, nullptr, q0, cnt, ctx->d_rp, ctx->d_wrp, ctx->nrp, ctx->d_dr, nbr, hbuf, gbuf);
     launch_jacobi(hbuf, cnt, nbr, lam, ubuf, s);
-    hipLaunchKernelGGL(k_phonon_derived, dim3(blocks_for(cnt, 64)), dim3(64), 0, s, cnt, nbr, lam, ubuf, gbuf,
-                       ctx->d_mass_x, ctx->omega_min, 1.0e-6, ctx->d_hw + q0 * nbr,
-                       (cd*)ctx->d_Lq + q0 * nbr * nbr, ctx->d_vph + q0 * nbr * 3);
+    hipLaunchKernelGGL(k_phonon_hw_L, dim3(blocks_for(cnt * nbr * nbr, 256)), dim3(256), 0, s, cnt, nbr, lam, ubuf,
+                       ctx->d_mass_x, ctx->omega_min, ctx->d_hw + q0 * nbr, (cd*)ctx->d_Lq + q0 * nbr * nbr);
+    hipLaunchKernelGGL(k_phonon_vel, dim3(blocks_for(cnt * 3 * nbr, 256)), dim3(256), 0, s, cnt, nbr,
+                       ctx->d_hw + q0 * nbr, ubuf, gbuf, ctx->omega_min, ctx->d_vph + q0 * nbr * 3);
+    hipLaunchKernelGGL(k_phonon_degen, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, cnt, nbr, ctx->d_hw + q0 * nbr,
+                       1.0e-6, ctx->d_vph + q0 * nbr * 3);
   }
   HIPCHK(hipGetLastError());
 
@@ -669,6 +743,7 @@ elph_status build_tables(elph_ctx ctx) {
   dev_free(ctx, scr);
   dev_free(ctx, tot);
   dev_free(ctx, nact_kept);
+  dev_free(ctx, vdbuf);
   dev_free(ctx, lam);
   dev_free(ctx, ubuf);
   dev_free(ctx, red);
