@@ -66,7 +66,7 @@ def contraction_flops(sz, nre, nrp):
     return step1, step2
 
 
-def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit):
+def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit, coupled=True):
     dev = torch.device("cuda:0")
     T = cfg["T"]
     ctx = E.elph_create(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], precision=form)
@@ -105,7 +105,7 @@ def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit):
     wall = (time.perf_counter() - t0) / steps
     out = dict(sizes=sz, ms_per_step=wall * 1e3, kernel_ms={k: float(np.mean(v)) for k, v in kt.items() if v},
                we=we.cpu().numpy(), wph=wph.cpu().numpy(), **info)
-    if with_iterate:
+    if with_iterate and coupled:
         # full coupled solve to relative residual 1e-8, untimed in the step
         t1 = time.perf_counter()
         r = E.elph_iterate(ctx, T, I, J, F, G, level=E.elph.ELPH_LEVEL_COUPLED, tol=1e-8, maxit=400,
@@ -293,6 +293,11 @@ def main():
     ap.add_argument("--maxit", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-coupled", action="store_true",
+                    help="skip the untimed full coupled solve after the timed steps (shorter profiled runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise copy (neg) of 1 GiB float32 three times, whose HBM "
+                         "bytes are known, to scale the byte counters of a profiled run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (the path would shard by kept-k rows across GPUs; "
@@ -309,6 +314,15 @@ def main():
         form = args.forms.split(",")[-1] if args.forms != "fp64,fp32,bf16x3,bf16x6" else "fp32"
         print(json.dumps(run_large(E, torch, form=form)), flush=True)
         return
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        print("bench: copy calibration, 3 x neg over 2^28 float32 (1 GiB read + 1 GiB written each)",
+              file=sys.stderr, flush=True)
+        del a, b
     cfg = synth.config(args.workload)
     mat = synth.material_for(cfg)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
@@ -318,7 +332,7 @@ def main():
     for form in forms:
         print("bench: form %s on %s" % (form, args.workload), file=sys.stderr, flush=True)
         res[form] = run_form(E, torch, mat, cfg, form, args.steps, args.warmup, not args.no_iterate, args.tol,
-                             args.maxit)
+                             args.maxit, coupled=not args.no_coupled)
     sz = res["fp64"]["sizes"]
     nterms = 2.0 * sz["nterms"]
     s1, s2 = contraction_flops(sz, mat["re"].shape[0], mat["rp"].shape[0])

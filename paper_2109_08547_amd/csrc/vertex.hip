@@ -673,13 +673,15 @@ __global__ void k_reduce_we(const double* __restrict__ part, int64_t ntiles, int
 //   C[c][j] = sum_k B2[c][k] Ap[j][k],  c = i*NX + x,
 // with the 32x32x16 BF16 MFMA (lane l supplies A[l%32][8(l/32)+t] and
 // B[8(l/32)+t][l%32]; accumulator r holds row 8(r/4) + 4(l/32) + r%4,
-// column l%32).  A block computes 64 c x 64 j (2 x 2 wavefronts of 32 x 32);
-// each 32-k stage of both operands is staged in LDS (rows padded by 16 bytes
-// so the fragment reads do not collide in banks), the next stage is fetched
-// into registers while the current one is multiplied, and the FP32
-// accumulators fold into FP64 after every stage.  C is FP32 complex.
+// column l%32).  A block computes 32*WR c x 64 j (WR x 2 wavefronts of
+// 32 x 32); each 32-k stage of both operands is staged in LDS (rows padded by
+// 16 bytes so the fragment reads do not collide in banks).  C is FP32
+// complex.
 
 typedef float f16v __attribute__((ext_vector_type(16)));
+// plain vector type for the staged 16-byte chunks (not the HIP struct), so
+// the copies stay in registers
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int NS>
 struct SplitGemm {
@@ -694,9 +696,12 @@ __device__ inline f16v mma32(us8v a, us8v b, f16v c) {
                                                  0);
 }
 
+// One 16-k slice of the complex product on a 32 x 32 tile: the real part's
+// two terms go to separate accumulators (cr += a_re b_re, cn += a_im b_im,
+// subtracted when folded), so no operand needs negating.
 template <int NS>
-__device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&na_im)[NS], const us8v (&b)[2 * NS],
-                                    f16v& cr, f16v& ci) {
+__device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&b)[2 * NS], f16v& cr, f16v& cn,
+                                    f16v& ci) {
   constexpr int np = NS == 2 ? 3 : 6;
 #pragma unroll
   for (int t = 0; t < np; ++t) {
@@ -709,107 +714,156 @@ __device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&na_im)
       sb = t == 0 ? 1 : t == 1 ? 2 : t == 3 ? 1 : 0;
     }
     cr = mma32<NS>(a[2 * sa], b[2 * sb], cr);
-    cr = mma32<NS>(na_im[sa], b[2 * sb + 1], cr);
+    cn = mma32<NS>(a[2 * sa + 1], b[2 * sb + 1], cn);
     ci = mma32<NS>(a[2 * sa], b[2 * sb + 1], ci);
     ci = mma32<NS>(a[2 * sa + 1], b[2 * sb], ci);
   }
+}
+
+// Block order: the 8 XCDs take workgroups round-robin (id % 8) and each runs
+// 32 blocks at a time (one per CU), so blocks 8s + x with s in [32u, 32u+32)
+// run together on XCD x.  Each such set of 32 is one group of kGY x kGX
+// neighbouring blocks (4 row tiles x 8 column tiles, 512 x 512 outputs), so a
+// staged slice of a row or column tile is fetched into that XCD's L2 once and
+// read by 8 or 4 blocks.  Groups are numbered column-fastest over the block
+// grid and dealt to the XCDs in turn.
+constexpr int kGY = 4, kGX = 8;
+
+struct GemmGrid {
+  int32_t ny, nx;    // row and column tiles
+  int32_t ngx, ng;   // groups per group row, groups
+  int64_t blocks;    // workgroups launched (whole groups on every XCD)
+};
+
+inline GemmGrid gemm_grid(int64_t rows, int64_t cols, int rows_per_block) {
+  GemmGrid g;
+  g.ny = (int32_t)((rows + rows_per_block - 1) / rows_per_block);
+  g.nx = (int32_t)((cols + 63) / 64);
+  g.ngx = (g.nx + kGX - 1) / kGX;
+  g.ng = ((g.ny + kGY - 1) / kGY) * g.ngx;
+  g.blocks = (int64_t)((g.ng + 7) / 8) * 8 * (kGY * kGX);
+  return g;
 }
 
 // rows c in [c0, c0 + nc) (c0 a multiple of nx), all j < nj; C is stored as
 // [(c - c0) / nx][j][(c - c0) % nx] with j stride nx (ldc >= nj)
 // STEP (1 or 2) only names the instance, so profiles tell the two steps
 // apart.  WR wavefronts along rows: the block computes 32*WR rows c x 64
-// columns j with 128*WR threads.
+// columns j with 128*WR threads.  Two LDS buffers: stage s + 1 is loaded into
+// registers while stage s is multiplied from one buffer, then stored into the
+// other, with one barrier per stage.
 template <int NS, int STEP, int WR>
 __global__ void __launch_bounds__(128 * WR) k_cgemm_split(int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx,
-                                                          const unsigned short* __restrict__ Bm2,
+                                                          GemmGrid gg, const unsigned short* __restrict__ Bm2,
                                                           const unsigned short* __restrict__ Apm,
                                                           float* __restrict__ C, int64_t ldc) {
   typedef SplitGemm<NS> G;
   constexpr int NT = 128 * WR, RA = 32 * WR;
-  __shared__ __attribute__((aligned(16))) unsigned short As[RA * G::kLdsRow];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[64 * G::kLdsRow];
+  constexpr int LA = RA * G::kLdsRow, LB = 64 * G::kLdsRow;
+  __shared__ __attribute__((aligned(16))) unsigned short As[2 * LA];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2 * LB];
+  // block -> (row tile, column tile), uniform over the block
+  const int32_t bid = (int32_t)blockIdx.x, slot = bid >> 3;
+  const int32_t grp = (slot / (kGY * kGX)) * 8 + (bid & 7), pos = slot % (kGY * kGX);
+  if (grp >= gg.ng) return;
+  const int32_t ty = (grp / gg.ngx) * kGY + pos / kGX, tx = (grp % gg.ngx) * kGX + pos % kGX;
+  if (ty >= gg.ny || tx >= gg.nx) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t cb = c0 + (int64_t)blockIdx.y * RA;   // first row c of the block
-  const int64_t jb = (int64_t)blockIdx.x * 64;        // first column j
+  const int64_t cb = c0 + (int64_t)ty * RA;           // first row c of the block
+  const int64_t jb = (int64_t)tx * 64;                // first column j
   const int64_t rowlen = K * 2 * NS;                  // ushorts per operand row
   const int nst = (int)(K / 32);
   constexpr int PA = RA * G::kChunks / NT;            // 16-byte chunks per thread, A tile
   constexpr int PB = 64 * G::kChunks / NT;            // and B tile
   static_assert(PA * NT == RA * G::kChunks && PB * NT == 64 * G::kChunks, "tile split");
-  uint4 ra[PA], rb[PB];
-  auto fetch = [&](int s) {
-    const int64_t so = (int64_t)s * G::kRowU;
+  u32x4 ra[PA], rb[PB];
+  // Loads are unconditional: rows past the end and stages past the last are
+  // clamped to valid ones.  A clamped row only feeds outputs (c, j) outside
+  // the result, which are never stored, and a clamped stage is never used.
+  const int64_t clast = c0 + nc - 1, jlast = nj - 1;
+  auto fetch = [&](int s, u32x4(&xa)[PA], u32x4(&xb)[PB]) {
+    const int64_t so = (int64_t)(s < nst ? s : nst - 1) * G::kRowU;
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
       const int e = tid + NT * u;
       const int row = e / G::kChunks, w = e - row * G::kChunks;
-      const int64_t ca = cb + row;
-      ra[u] = (ca < c0 + nc) ? *reinterpret_cast<const uint4*>(Bm2 + ca * rowlen + so + w * 8)
-                             : make_uint4(0, 0, 0, 0);
+      const int64_t ca = cb + row < clast ? cb + row : clast;
+      xa[u] = *reinterpret_cast<const u32x4*>(Bm2 + ca * rowlen + so + w * 8);
     }
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
       const int e = tid + NT * u;
       const int row = e / G::kChunks, w = e - row * G::kChunks;
-      const int64_t jr = jb + row;
-      rb[u] = (jr < nj) ? *reinterpret_cast<const uint4*>(Apm + jr * rowlen + so + w * 8) : make_uint4(0, 0, 0, 0);
+      const int64_t jr = jb + row < jlast ? jb + row : jlast;
+      xb[u] = *reinterpret_cast<const u32x4*>(Apm + jr * rowlen + so + w * 8);
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](const u32x4(&xa)[PA], const u32x4(&xb)[PB], unsigned short* as, unsigned short* bs) {
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
       const int e = tid + NT * u;
       const int row = e / G::kChunks, w = e - row * G::kChunks;
-      *reinterpret_cast<uint4*>(As + row * G::kLdsRow + w * 8) = ra[u];
+      *reinterpret_cast<u32x4*>(as + row * G::kLdsRow + w * 8) = xa[u];
     }
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
       const int e = tid + NT * u;
       const int row = e / G::kChunks, w = e - row * G::kChunks;
-      *reinterpret_cast<uint4*>(Bs + row * G::kLdsRow + w * 8) = rb[u];
+      *reinterpret_cast<u32x4*>(bs + row * G::kLdsRow + w * 8) = xb[u];
     }
   };
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 31, lh = lane >> 5;
-  f16v cr, ci;
+  f16v cr, cn, ci;
   double fr[16], fi[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    cr[r] = 0.f;
-    ci[r] = 0.f;
+    cr[r] = cn[r] = ci[r] = 0.f;
     fr[r] = fi[r] = 0.0;
   }
-  fetch(0);
-  stash();
-  __syncthreads();
-  for (int s = 0; s < nst; ++s) {
-    if (s + 1 < nst) fetch(s + 1);
+  auto compute = [&](const unsigned short* as, const unsigned short* bs) {
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
       // 16-k half kh: groups 2kh + lh of the stage
       const int gofs = (2 * kh + lh) * 16 * NS;
-      us8v a[2 * NS], b[2 * NS], na[NS];
+      us8v a[2 * NS], b[2 * NS];
 #pragma unroll
       for (int p = 0; p < 2 * NS; ++p) {
-        a[p] = *reinterpret_cast<const us8v*>(As + (wm + lr) * G::kLdsRow + gofs + 8 * p);
-        b[p] = *reinterpret_cast<const us8v*>(Bs + (wn + lr) * G::kLdsRow + gofs + 8 * p);
+        a[p] = *reinterpret_cast<const us8v*>(as + (wm + lr) * G::kLdsRow + gofs + 8 * p);
+        b[p] = *reinterpret_cast<const us8v*>(bs + (wn + lr) * G::kLdsRow + gofs + 8 * p);
       }
-      neg_im<NS>(a, na);
-      split_cmma32<NS>(a, na, b, cr, ci);
+      split_cmma32<NS>(a, b, cr, cn, ci);
     }
+  };
+  // FP32 partial sums of one stage (32 k) into FP64
+  auto fold = [&]() {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      fr[r] += (double)cr[r];
+      fr[r] += (double)(cr[r] - cn[r]);
       fi[r] += (double)ci[r];
-      cr[r] = 0.f;
-      ci[r] = 0.f;
+      cr[r] = cn[r] = ci[r] = 0.f;
     }
+  };
+  fetch(0, ra, rb);
+  stash(ra, rb, As, Bs);
+  __syncthreads();
+  for (int s = 0; s < nst; s += 2) {
+    // even stage s from buffer 0; stage s + 1 into buffer 1 (the scheduling
+    // barriers keep the loads issued ahead of the multiplies they overlap)
+    fetch(s + 1, ra, rb);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(As, Bs);
+    fold();
+    stash(ra, rb, As + LA, Bs + LB);   // past the last stage: unused
     __syncthreads();
-    if (s + 1 < nst) {
-      stash();
-      __syncthreads();
-    }
+    if (s + 1 >= nst) break;
+    // odd stage s + 1 from buffer 1; stage s + 2 into buffer 0
+    fetch(s + 2, ra, rb);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(As + LA, Bs + LB);
+    fold();
+    stash(ra, rb, As, Bs);
+    __syncthreads();
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -824,6 +878,15 @@ __global__ void __launch_bounds__(128 * WR) k_cgemm_split(int64_t c0, int64_t nc
 
 // rows per block of the split GEMM (WR = 4: 128 rows)
 constexpr int kSplitWR = 4;
+
+template <int NS, int STEP>
+static void launch_cgemm_split(hipStream_t s, int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx,
+                               const unsigned short* A, const unsigned short* B, float* C, int64_t ldc) {
+  if (nc <= 0 || nj <= 0) return;
+  const GemmGrid gg = gemm_grid(nc, nj, 32 * kSplitWR);
+  hipLaunchKernelGGL((k_cgemm_split<NS, STEP, kSplitWR>), dim3((unsigned)gg.blocks), dim3(128 * kSplitWR), 0, s, c0,
+                     nc, nj, K, nx, gg, A, B, C, ldc);
+}
 
 // Epilogue of the split path, one wavefront per q: the phonon factors of q
 // (l u, hbar omega) are wavefront-uniform; lanes take the kept pairs
@@ -1054,10 +1117,8 @@ static elph_status launch_step1_t(elph_ctx ctx) {
     }
     for (int64_t i0 = 0; i0 < M; i0 += ci) {
       const int64_t ni = (M - i0 < ci) ? M - i0 : ci;
-      hipLaunchKernelGGL((k_cgemm_split<NS, 1, kSplitWR>),
-                         dim3((unsigned)((ncol + 63) / 64), (unsigned)((ni + 32 * kSplitWR - 1) / (32 * kSplitWR))),
-                         dim3(128 * kSplitWR), 0, ctx->stream, i0, ni, ncol, ctx->ke, 1, (const unsigned short*)ctx->d_Ae,
-                         (const unsigned short*)ctx->d_gR, (float*)p, ncol);
+      launch_cgemm_split<NS, 1>(ctx->stream, i0, ni, ncol, ctx->ke, 1, (const unsigned short*)ctx->d_Ae,
+                                (const unsigned short*)ctx->d_gR, (float*)p, ncol);
       hipLaunchKernelGGL(k_step1_epi_split<NS>, dim3(blocks_for(ni * ncol, 256)), dim3(256), 0, ctx->stream, i0, ni,
                          ncol, ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, (const float*)p, ctx->d_state_kidx,
                          (const cd*)ctx->d_Ep, (unsigned short*)ctx->d_B2);
@@ -1108,7 +1169,6 @@ static elph_status launch_split_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, 
     return ELPH_ENOMEM;
   }
   float* C = (float*)p;
-  const unsigned jblk = (unsigned)((M + 63) / 64);
   mark(ctx, 4);  // the step-2 window starts at the contraction (pair lists are built above)
   for (int32_t t0 = 0; t0 < ctx->nkept;) {
     // whole kept k per chunk
@@ -1116,11 +1176,8 @@ static elph_status launch_split_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, 
     while (t1 < ctx->nkept && soff[t1 + 1] - soff[t0] <= cap) ++t1;
     const int64_t i0 = soff[t0], ni = soff[t1] - soff[t0];
     const int64_t c0 = i0 * NX, nc = ni * NX;
-    hipLaunchKernelGGL((k_cgemm_split<NS, 2, kSplitWR>),
-                       dim3(jblk, (unsigned)((nc + 32 * kSplitWR - 1) / (32 * kSplitWR))), dim3(128 * kSplitWR), 0,
-                       ctx->stream,
-                       c0, nc, M, ctx->kp, NX, (const unsigned short*)ctx->d_B2, (const unsigned short*)ctx->d_Ap, C,
-                       ldc);
+    launch_cgemm_split<NS, 2>(ctx->stream, c0, nc, M, ctx->kp, NX, (const unsigned short*)ctx->d_B2,
+                              (const unsigned short*)ctx->d_Ap, C, ldc);
     if (t1 == ctx->nkept) mark(ctx, 5);  // step-2 window: the contraction (and earlier chunks' epilogues)
     hipLaunchKernelGGL((k_epi_q<ST, NX>), dim3((unsigned)((ctx->nk + 3) / 4)), dim3(256), 0, ctx->stream, ctx->nk,
                        i0, t0, t1, ep, ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist,
