@@ -45,6 +45,27 @@ WORKLOADS = {
 }
 
 
+def stored_traffic(form, workload):
+    """HBM bytes per launch of the step-2 split GEMM from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None
+    when the kernel source has changed since the counters were taken or the
+    summary covers another form or workload."""
+    if form != "bf16x6" or workload != "mixed48":
+        return None
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_cgemm_split_mixed48_counters.md")
+    src = os.path.join(ROOT, "paper_2109_08547_amd", "csrc", "vertex.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    if vals.get("source_sha256", "").strip() != sha:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def rate_err(w, ref, floor=1e-12):
     """Max-per-state relative error over rates >= floor * max (smaller ones
     judged absolutely against the max)."""
@@ -373,7 +394,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": ("k_cgemm_split<%d, 2> (step-2 contraction)" % (2 if best == "bf16x3" else 3)
                                                   if best.startswith("bf16") else "k_step2 (fused step-2 contraction + epilogue)"),
                      "achieved": achieved, "peak": PEAK[best], "unit": "TFLOP/s", "frac": achieved / PEAK[best],
-                     "traffic": None},
+                     "traffic": stored_traffic(best, args.workload)},
         "forms": forms_out,
     }
     if not args.no_cpu:
