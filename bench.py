@@ -33,6 +33,10 @@ METRIC = "e-ph transition probabilities/s at rel err 1e-5 vs FP64; MFMA util"
 # real product, so its ceiling is the 2.5 PFLOP/s BF16 peak divided by that
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}
+GEMM_KERNEL = {"fp64": "k_step2<double, double, NX> (fused step-2 contraction + epilogue)",
+               "fp32": "k_cgemm<OpF32, 2, 4> (step-2 contraction)",
+               "bf16x3": "k_cgemm<OpSplit<2>, 2, 4> (step-2 contraction)",
+               "bf16x6": "k_cgemm<OpSplit<3>, 2, 4> (step-2 contraction)"}
 WORKLOADS = {
     "mixed48": "8 Wannier bands, 2 atoms, 203 R_e + 203 R_p vectors, 48^3 k and q meshes, "
                "window +-0.4 eV around mu = CBM - 0.1 eV keeping 3% of k, Gaussian sigma 10 meV, 300 K",
@@ -53,7 +57,7 @@ def stored_traffic(form, workload):
     if form != "bf16x6" or workload != "mixed48":
         return None
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_cgemm_split_mixed48_counters.md")
+    path = os.path.join(ROOT, "profiles", "k_cgemm_mixed48_counters.md")
     src = os.path.join(ROOT, "paper_2109_08547_amd", "csrc", "vertex.hip")
     try:
         text = open(path).read()
@@ -391,8 +395,7 @@ def main():
         "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]),
                    "nstates": sz["nstates"], "nkept": sz["nkept"], "terms_per_step": nterms,
                    "form": best, "iterate": not args.no_iterate},
-        "roofline": {"bound": "mfma", "kernel": ("k_cgemm_split<%d, 2> (step-2 contraction)" % (2 if best == "bf16x3" else 3)
-                                                  if best.startswith("bf16") else "k_step2 (fused step-2 contraction + epilogue)"),
+        "roofline": {"bound": "mfma", "kernel": GEMM_KERNEL[best],
                      "achieved": achieved, "peak": PEAK[best], "unit": "TFLOP/s", "frac": achieved / PEAK[best],
                      "traffic": stored_traffic(best, args.workload)},
         "forms": forms_out,

@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace elph {
@@ -74,7 +75,7 @@ template <typename T>
 struct Store {
   typedef T type;
   static constexpr int per_c = 2;      // storage elements per complex value
-  static constexpr int kalign = 16;    // padding of the contraction length
+  static constexpr int kalign = sizeof(T) == 4 ? 32 : 16;  // padding of the contraction length (GEMM stages: 32)
 };
 template <int NS>
 struct Store<Bf16S<NS>> {
@@ -669,26 +670,20 @@ __global__ void k_reduce_we(const double* __restrict__ part, int64_t ntiles, int
 }
 
 // ---------------------------------------------------------------------------
-// Split-BF16 step 2 as a plain complex GEMM plus a separate epilogue:
-//   C[c][j] = sum_k B2[c][k] Ap[j][k],  c = i*NX + x,
-// with the 32x32x16 BF16 MFMA (lane l supplies A[l%32][8(l/32)+t] and
-// B[8(l/32)+t][l%32]; accumulator r holds row 8(r/4) + 4(l/32) + r%4,
-// column l%32).  A block computes 32*WR c x 64 j (WR x 2 wavefronts of
-// 32 x 32); each 32-k stage of both operands is staged in LDS (rows padded by
-// 16 bytes so the fragment reads do not collide in banks).  C is FP32
-// complex.
+// The contractions of the BF16 and FP32 forms as plain complex GEMMs plus
+// separate epilogues:
+//   C[c][j] = sum_k A[c][k] B[j][k]
+// (step 2: A = B2 with c = i*NX + x, B = A_p; step 1: A = A_e, B = gR).  All
+// 32 x 32 MFMAs used here share one accumulator layout: register r of lane l
+// holds row 8(r/4) + 4(l/32) + r%4, column l%32.  A block computes 32*WR
+// rows c x 64 columns j (WR x 2 wavefronts of 32 x 32); each 32-k stage of
+// both operands is staged in LDS (rows padded by 16 bytes so the fragment
+// reads do not collide in banks).  C is FP32 complex.
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 // plain vector type for the staged 16-byte chunks (not the HIP struct), so
 // the copies stay in registers
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-template <int NS>
-struct SplitGemm {
-  static constexpr int kRowU = 64 * NS;      // ushorts of one row's 32-k stage (4 groups x 2NS planes x 8)
-  static constexpr int kLdsRow = kRowU + 8;  // padded LDS row
-  static constexpr int kChunks = 8 * NS;     // 16-byte chunks per row and stage
-};
 
 template <int NS>
 __device__ inline f16v mma32(us8v a, us8v b, f16v c) {
@@ -720,6 +715,54 @@ __device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&b)[2 *
   }
 }
 
+// Operand formats, in 16-bit words per 32-k stage of a row (kRowU).
+// OpSplit<NS>: BF16 planes (groups of 8 k, each holding re/im of the NS
+// parts), 32x32x16 BF16 MFMA; lanes 0-31 take the first 8 k of each 16,
+// lanes 32-63 the next 8.
+template <int NS>
+struct OpSplit {
+  static constexpr int kRowU = 64 * NS;
+  __device__ static inline void mac(const unsigned short* arow, const unsigned short* brow, int lh, f16v& cr,
+                                    f16v& cn, f16v& ci) {
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+      const int gofs = (2 * kh + lh) * 16 * NS;  // group 2kh + lh of the stage
+      us8v a[2 * NS], b[2 * NS];
+#pragma unroll
+      for (int p = 0; p < 2 * NS; ++p) {
+        a[p] = *reinterpret_cast<const us8v*>(arow + gofs + 8 * p);
+        b[p] = *reinterpret_cast<const us8v*>(brow + gofs + 8 * p);
+      }
+      split_cmma32<NS>(a, b, cr, cn, ci);
+    }
+  }
+};
+
+// OpF32: complex FP32 interleaved (re, im per k), 32x32x2 FP32 MFMA.  The
+// stage's 32 k are split as k = 16 (l/32) + s over the MFMA's two k slots
+// and its 16 steps s, so each lane reads 16 consecutive complex values of
+// its row with 16-byte loads.
+struct OpF32 {
+  static constexpr int kRowU = 128;
+  __device__ static inline void mac(const unsigned short* arow, const unsigned short* brow, int lh, f16v& cr,
+                                    f16v& cn, f16v& ci) {
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const int off = lh * 64 + s2 * 8;  // two k of the lane's 16
+      const float4 a = *reinterpret_cast<const float4*>(arow + off);
+      const float4 b = *reinterpret_cast<const float4*>(brow + off);
+      cr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, cr, 0, 0, 0);
+      cn = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, cn, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, cr, 0, 0, 0);
+      cn = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, cn, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.w, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.z, ci, 0, 0, 0);
+    }
+  }
+};
+
 // Block order: the 8 XCDs take workgroups round-robin (id % 8) and each runs
 // 32 blocks at a time (one per CU), so blocks 8s + x with s in [32u, 32u+32)
 // run together on XCD x.  Each such set of 32 is one group of kGY x kGX
@@ -745,71 +788,81 @@ inline GemmGrid gemm_grid(int64_t rows, int64_t cols, int rows_per_block) {
   return g;
 }
 
-// rows c in [c0, c0 + nc) (c0 a multiple of nx), all j < nj; C is stored as
-// [(c - c0) / nx][j][(c - c0) % nx] with j stride nx (ldc >= nj)
-// STEP (1 or 2) only names the instance, so profiles tell the two steps
-// apart.  WR wavefronts along rows: the block computes 32*WR rows c x 64
-// columns j with 128*WR threads.  Two LDS buffers: stage s + 1 is loaded into
-// registers while stage s is multiplied from one buffer, then stored into the
-// other, with one barrier per stage.
-template <int NS, int STEP, int WR>
-__global__ void __launch_bounds__(128 * WR) k_cgemm_split(int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx,
-                                                          GemmGrid gg, const unsigned short* __restrict__ Bm2,
-                                                          const unsigned short* __restrict__ Apm,
-                                                          float* __restrict__ C, int64_t ldc) {
-  typedef SplitGemm<NS> G;
+// One GEMM: rows c in [c0, c0 + nc) (c0 a multiple of nx) of A, all j < nj;
+// C is stored as [(c - c0) / nx][j][(c - c0) % nx] with j stride nx
+// (ldc >= nj).  K is a multiple of 32.
+struct GemmArgs {
+  int64_t c0, nc, nj, K;
+  int nx;
+  const unsigned short* A;
+  const unsigned short* B;
+  float* C;
+  int64_t ldc;
+};
+
+template <class OP, int WR>
+struct GemmLds {
+  static constexpr int kLdsRow = OP::kRowU + 8;  // padded LDS row
+  static constexpr int LA = 32 * WR * kLdsRow, LB = 64 * kLdsRow;
+  unsigned short As[2 * LA];
+  unsigned short Bs[2 * LB];
+};
+
+// Block (ty, tx) of one GEMM with 128*WR threads.  Two LDS buffers: stage
+// s + 1 is loaded into registers while stage s is multiplied from one
+// buffer, then stored into the other, with one barrier per stage; the FP32
+// accumulators fold into FP64 after every stage.
+template <class OP, int WR>
+__device__ __forceinline__ void cgemm_block(const GemmArgs& g, int64_t ty, int64_t tx, GemmLds<OP, WR>& L) {
   constexpr int NT = 128 * WR, RA = 32 * WR;
-  constexpr int LA = RA * G::kLdsRow, LB = 64 * G::kLdsRow;
-  __shared__ __attribute__((aligned(16))) unsigned short As[2 * LA];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[2 * LB];
-  // block -> (row tile, column tile), uniform over the block
-  const int32_t bid = (int32_t)blockIdx.x, slot = bid >> 3;
-  const int32_t grp = (slot / (kGY * kGX)) * 8 + (bid & 7), pos = slot % (kGY * kGX);
-  if (grp >= gg.ng) return;
-  const int32_t ty = (grp / gg.ngx) * kGY + pos / kGX, tx = (grp % gg.ngx) * kGX + pos % kGX;
-  if (ty >= gg.ny || tx >= gg.nx) return;
+  constexpr int kLdsRow = GemmLds<OP, WR>::kLdsRow, LA = GemmLds<OP, WR>::LA, LB = GemmLds<OP, WR>::LB;
+  constexpr int kChunks = OP::kRowU / 8;              // 16-byte chunks per row and stage
+  unsigned short* As = L.As;
+  unsigned short* Bs = L.Bs;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t cb = c0 + (int64_t)ty * RA;           // first row c of the block
-  const int64_t jb = (int64_t)tx * 64;                // first column j
-  const int64_t rowlen = K * 2 * NS;                  // ushorts per operand row
-  const int nst = (int)(K / 32);
-  constexpr int PA = RA * G::kChunks / NT;            // 16-byte chunks per thread, A tile
-  constexpr int PB = 64 * G::kChunks / NT;            // and B tile
-  static_assert(PA * NT == RA * G::kChunks && PB * NT == 64 * G::kChunks, "tile split");
+  const int64_t cb = g.c0 + ty * RA;                  // first row c of the block
+  const int64_t jb = tx * 64;                         // first column j
+  const int64_t rowlen = g.K / 32 * OP::kRowU;        // 16-bit words per operand row
+  const int nst = (int)(g.K / 32);
+  constexpr int PA = RA * kChunks / NT;               // 16-byte chunks per thread, A tile
+  constexpr int PB = 64 * kChunks / NT;               // and B tile
+  static_assert(PA * NT == RA * kChunks && PB * NT == 64 * kChunks, "tile split");
   u32x4 ra[PA], rb[PB];
   // Loads are unconditional: rows past the end and stages past the last are
   // clamped to valid ones.  A clamped row only feeds outputs (c, j) outside
   // the result, which are never stored, and a clamped stage is never used.
-  const int64_t clast = c0 + nc - 1, jlast = nj - 1;
-  auto fetch = [&](int s, u32x4(&xa)[PA], u32x4(&xb)[PB]) {
-    const int64_t so = (int64_t)(s < nst ? s : nst - 1) * G::kRowU;
+  const int64_t clast = g.c0 + g.nc - 1, jlast = g.nj - 1;
+  const unsigned short* __restrict__ Am = g.A;
+  const unsigned short* __restrict__ Bm = g.B;
+  auto fetch = [&](int s) {
+    const int64_t so = (int64_t)(s < nst ? s : nst - 1) * OP::kRowU;
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
       const int e = tid + NT * u;
-      const int row = e / G::kChunks, w = e - row * G::kChunks;
+      const int row = e / kChunks, w = e - row * kChunks;
       const int64_t ca = cb + row < clast ? cb + row : clast;
-      xa[u] = *reinterpret_cast<const u32x4*>(Bm2 + ca * rowlen + so + w * 8);
+      ra[u] = *reinterpret_cast<const u32x4*>(Am + ca * rowlen + so + w * 8);
     }
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
       const int e = tid + NT * u;
-      const int row = e / G::kChunks, w = e - row * G::kChunks;
+      const int row = e / kChunks, w = e - row * kChunks;
       const int64_t jr = jb + row < jlast ? jb + row : jlast;
-      xb[u] = *reinterpret_cast<const u32x4*>(Apm + jr * rowlen + so + w * 8);
+      rb[u] = *reinterpret_cast<const u32x4*>(Bm + jr * rowlen + so + w * 8);
     }
   };
-  auto stash = [&](const u32x4(&xa)[PA], const u32x4(&xb)[PB], unsigned short* as, unsigned short* bs) {
+  auto stash = [&](unsigned short* as, unsigned short* bs) {
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
       const int e = tid + NT * u;
-      const int row = e / G::kChunks, w = e - row * G::kChunks;
-      *reinterpret_cast<u32x4*>(as + row * G::kLdsRow + w * 8) = xa[u];
+      const int row = e / kChunks, w = e - row * kChunks;
+      *reinterpret_cast<u32x4*>(as + row * kLdsRow + w * 8) = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
       const int e = tid + NT * u;
-      const int row = e / G::kChunks, w = e - row * G::kChunks;
-      *reinterpret_cast<u32x4*>(bs + row * G::kLdsRow + w * 8) = xb[u];
+      const int row = e / kChunks, w = e - row * kChunks;
+      *reinterpret_cast<u32x4*>(bs + row * kLdsRow + w * 8) = rb[u];
     }
   };
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -822,18 +875,7 @@ __global__ void __launch_bounds__(128 * WR) k_cgemm_split(int64_t c0, int64_t nc
     fr[r] = fi[r] = 0.0;
   }
   auto compute = [&](const unsigned short* as, const unsigned short* bs) {
-#pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-      // 16-k half kh: groups 2kh + lh of the stage
-      const int gofs = (2 * kh + lh) * 16 * NS;
-      us8v a[2 * NS], b[2 * NS];
-#pragma unroll
-      for (int p = 0; p < 2 * NS; ++p) {
-        a[p] = *reinterpret_cast<const us8v*>(as + (wm + lr) * G::kLdsRow + gofs + 8 * p);
-        b[p] = *reinterpret_cast<const us8v*>(bs + (wn + lr) * G::kLdsRow + gofs + 8 * p);
-      }
-      split_cmma32<NS>(a, b, cr, cn, ci);
-    }
+    OP::mac(as + (wm + lr) * kLdsRow, bs + (wn + lr) * kLdsRow, lh, cr, cn, ci);
   };
   // FP32 partial sums of one stage (32 k) into FP64
   auto fold = [&]() {
@@ -844,49 +886,99 @@ __global__ void __launch_bounds__(128 * WR) k_cgemm_split(int64_t c0, int64_t nc
       cr[r] = cn[r] = ci[r] = 0.f;
     }
   };
-  fetch(0, ra, rb);
-  stash(ra, rb, As, Bs);
+  fetch(0);
+  stash(As, Bs);
   __syncthreads();
   for (int s = 0; s < nst; s += 2) {
     // even stage s from buffer 0; stage s + 1 into buffer 1 (the scheduling
     // barriers keep the loads issued ahead of the multiplies they overlap)
-    fetch(s + 1, ra, rb);
+    fetch(s + 1);
     __builtin_amdgcn_sched_barrier(0);
     compute(As, Bs);
     fold();
-    stash(ra, rb, As + LA, Bs + LB);   // past the last stage: unused
+    stash(As + LA, Bs + LB);   // past the last stage: unused
     __syncthreads();
     if (s + 1 >= nst) break;
     // odd stage s + 1 from buffer 1; stage s + 2 into buffer 0
-    fetch(s + 2, ra, rb);
+    fetch(s + 2);
     __builtin_amdgcn_sched_barrier(0);
     compute(As + LA, Bs + LB);
     fold();
-    stash(ra, rb, As, Bs);
+    stash(As, Bs);
     __syncthreads();
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int64_t c = cb + wm + 8 * (r >> 2) + 4 * lh + (r & 3);
     const int64_t j = jb + wn + lr;
-    if (c < c0 + nc && j < nj) {
-      const int64_t il = (c - c0) / nx, x = (c - c0) - il * nx;
-      *reinterpret_cast<float2*>(C + 2 * ((il * ldc + j) * nx + x)) = make_float2((float)fr[r], (float)fi[r]);
+    if (c <= clast && j <= jlast) {
+      const int64_t il = (c - g.c0) / g.nx, x = (c - g.c0) - il * g.nx;
+      *reinterpret_cast<float2*>(g.C + 2 * ((il * g.ldc + j) * g.nx + x)) =
+          make_float2((float)fr[r], (float)fi[r]);
     }
   }
 }
 
-// rows per block of the split GEMM (WR = 4: 128 rows)
-constexpr int kSplitWR = 4;
-
-template <int NS, int STEP>
-static void launch_cgemm_split(hipStream_t s, int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx,
-                               const unsigned short* A, const unsigned short* B, float* C, int64_t ldc) {
-  if (nc <= 0 || nj <= 0) return;
-  const GemmGrid gg = gemm_grid(nc, nj, 32 * kSplitWR);
-  hipLaunchKernelGGL((k_cgemm_split<NS, STEP, kSplitWR>), dim3((unsigned)gg.blocks), dim3(128 * kSplitWR), 0, s, c0,
-                     nc, nj, K, nx, gg, A, B, C, ldc);
+// One GEMM over the XCD-grouped block order.  STEP (1 or 2) only names the
+// instance, so profiles tell the two steps apart.
+template <class OP, int STEP, int WR>
+__global__ void __launch_bounds__(128 * WR) k_cgemm(GemmArgs g, GemmGrid gg) {
+  __shared__ __attribute__((aligned(16))) GemmLds<OP, WR> L;
+  // block -> (row tile, column tile), uniform over the block
+  const int32_t bid = (int32_t)blockIdx.x, slot = bid >> 3;
+  const int32_t grp = (slot / (kGY * kGX)) * 8 + (bid & 7), pos = slot % (kGY * kGX);
+  if (grp >= gg.ng) return;
+  const int32_t ty = (grp / gg.ngx) * kGY + pos / kGX, tx = (grp % gg.ngx) * kGX + pos % kGX;
+  if (ty >= gg.ny || tx >= gg.nx) return;
+  cgemm_block<OP, WR>(g, ty, tx, L);
 }
+
+// Many GEMMs (one per material) in one persistent launch over a queue of
+// (GEMM, row tile, column tile) items; every block ends when the queue is
+// empty.  Each output block is computed exactly as by k_cgemm.
+__device__ inline GemmArgs promoted(const GemmArgs& in);
+
+template <class OP, int STEP, int WR>
+__global__ void __launch_bounds__(128 * WR) k_cgemm_persist(const GemmArgs* __restrict__ args,
+                                                            const int4* __restrict__ items, int nitems,
+                                                            int* counter) {
+  __shared__ __attribute__((aligned(16))) GemmLds<OP, WR> L;
+  __shared__ int item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = item_sh;
+    __syncthreads();
+    if (it >= nitems) break;  // uniform over the block; every block reaches it
+    const int4 w = items[it];
+    cgemm_block<OP, WR>(promoted(args[w.x]), w.y, w.z, L);
+    __syncthreads();          // the LDS buffers are reused by the next item
+  }
+}
+
+// rows per block of the GEMMs (WR = 4: 128 rows)
+constexpr int kGemmWR = 4;
+
+template <class OP, int STEP>
+static void launch_cgemm(hipStream_t s, int64_t c0, int64_t nc, int64_t nj, int64_t K, int nx, const void* A,
+                         const void* B, float* C, int64_t ldc) {
+  if (nc <= 0 || nj <= 0) return;
+  const GemmGrid gg = gemm_grid(nc, nj, 32 * kGemmWR);
+  GemmArgs g{c0, nc, nj, K, nx, (const unsigned short*)A, (const unsigned short*)B, C, ldc};
+  hipLaunchKernelGGL((k_cgemm<OP, STEP, kGemmWR>), dim3((unsigned)gg.blocks), dim3(128 * kGemmWR), 0, s, g, gg);
+}
+
+// operand format of a form
+template <typename T>
+struct GemmOp;
+template <int NS>
+struct GemmOp<Bf16S<NS>> {
+  typedef OpSplit<NS> type;
+};
+template <>
+struct GemmOp<float> {
+  typedef OpF32 type;
+};
 
 // Epilogue of the split path, one wavefront per q: the phonon factors of q
 // (l u, hbar omega) are wavefront-uniform; lanes take the kept pairs
@@ -956,12 +1048,12 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
   }
 }
 
-// Step-1 epilogue of the split path: B2[(i, x)][(Rp, n')] = C1[i][col] e^{-2 pi i k_i.Rp}
-// written as BF16 parts; col = (x, Rp, n'), rows [i0, i0 + ni).
-template <int NS>
-__global__ void k_step1_epi_split(int64_t i0, int64_t ni, int64_t ncol, int nrp, int nb, int nbr, int64_t kp,
-                                  const float* __restrict__ C1, const int32_t* __restrict__ st_kidx,
-                                  const cd* __restrict__ Ep, unsigned short* __restrict__ B2) {
+// Step-1 epilogue of the GEMM path: B2[(i, x)][(Rp, n')] = C1[i][col] e^{-2 pi i k_i.Rp}
+// written in the form's operand format; col = (x, Rp, n'), rows [i0, i0 + ni).
+template <typename T>
+__global__ void k_step1_epi(int64_t i0, int64_t ni, int64_t ncol, int nrp, int nb, int nbr, int64_t kp,
+                            const float* __restrict__ C1, const int32_t* __restrict__ st_kidx,
+                            const cd* __restrict__ Ep, typename Store<T>::type* __restrict__ B2) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ni * ncol) return;
   const int64_t il = e / ncol, col = e - il * ncol;
@@ -972,7 +1064,7 @@ __global__ void k_step1_epi_split(int64_t i0, int64_t ni, int64_t ncol, int nrp,
   const int rp = (int)(rem / nb);
   const float2 v = *reinterpret_cast<const float2*>(C1 + 2 * e);
   const cd z = cmulc(cmake(v.x, v.y), Ep[(int64_t)st_kidx[i] * nrp + rp]);  // * conj(phase)
-  put_split<NS>(B2, i * nbr + x, kp, rem, z.x, z.y);
+  PutC<T>::put(B2, i * nbr + x, kp, rem, z.x, z.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -980,6 +1072,61 @@ __global__ void k_step1_epi_split(int64_t i0, int64_t ni, int64_t ncol, int nrp,
 
 __global__ void k_zero_ints(int* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// Descriptors are read from memory here, so the compiler cannot see that
+// their pointers address global memory and would access through them with
+// flat instructions; re-deriving each pointer from a global-address-space
+// pointer lets every access compile to global loads and stores, as in the
+// single-material kernels whose descriptors are kernel arguments.
+template <typename P>
+__device__ inline P* as_global(P* p) {
+  typedef __attribute__((address_space(1))) P GP;
+  return (P*)(GP*)(uintptr_t)p;
+}
+
+__device__ inline void promote(EpiParams& e) {
+  e.st_k = as_global(e.st_k);
+  e.eps = as_global(e.eps);
+  e.hw = as_global(e.hw);
+  e.Lq = as_global(e.Lq);
+  e.lomf = as_global(e.lomf);
+  e.fstate = as_global(e.fstate);
+  e.omf = as_global(e.omf);
+  e.nocc = as_global(e.nocc);
+  e.we_part = as_global(e.we_part);
+  e.wph_acc = as_global(e.wph_acc);
+  e.tile_keep = as_global(e.tile_keep);
+}
+
+template <typename T>
+__device__ inline S1Desc<T> promoted(const S1Desc<T>& in) {
+  S1Desc<T> d = in;
+  d.Ae = as_global(d.Ae);
+  d.gR = as_global(d.gR);
+  d.B2 = as_global(d.B2);
+  d.st_kidx = as_global(d.st_kidx);
+  d.Ep = as_global(d.Ep);
+  return d;
+}
+
+__device__ inline GemmArgs promoted(const GemmArgs& in) {
+  GemmArgs g = in;
+  g.A = as_global(g.A);
+  g.B = as_global(g.B);
+  g.C = as_global(g.C);
+  return g;
+}
+
+template <typename T>
+__device__ inline S2Desc<T> promoted(const S2Desc<T>& in) {
+  S2Desc<T> d = in;
+  d.Ap = as_global(d.Ap);
+  d.B2 = as_global(d.B2);
+  d.Bp = as_global(d.Bp);
+  d.Bm = as_global(d.Bm);
+  promote(d.ep);
+  return d;
 }
 
 template <typename T>
@@ -993,7 +1140,7 @@ __global__ void __launch_bounds__(256) k_step1_persist(const S1Desc<T>* __restri
     __syncthreads();
     if (it >= nitems) break;  // uniform over the block; every block reaches it
     const int4 w = items[it];
-    step1_tile<T>(descs[w.x], w.y, w.z);
+    step1_tile<T>(promoted(descs[w.x]), w.y, w.z);
   }
 }
 
@@ -1009,7 +1156,7 @@ __global__ void __launch_bounds__(256) k_step2_persist(const S2Desc<T>* __restri
     __syncthreads();
     if (it >= nitems) break;
     const int4 w = items[it];
-    step2_tile<T, ST, NX>(descs[w.x], w.y, w.z, red);
+    step2_tile<T, ST, NX>(promoted(descs[w.x]), w.y, w.z, red);
     __syncthreads();
   }
 }
@@ -1098,13 +1245,19 @@ S1Desc<T> step1_desc(elph_ctx ctx) {
   return d;
 }
 
+// forms whose contractions run as GEMMs plus separate epilogues
+template <typename T>
+struct UsesGemm {
+  static constexpr bool value = IsSplit<T>::value || std::is_same<T, float>::value;
+};
+
 template <typename T>
 static elph_status launch_step1_t(elph_ctx ctx) {
   const S1Desc<T> d = step1_desc<T>(ctx);
-  if constexpr (IsSplit<T>::value) {
-    // split forms: GEMM into FP32 rows (chunks <= 2 GiB), then the phase
-    // epilogue that writes the BF16 parts of B2
-    constexpr int NS = IsSplit<T>::ns;
+  if constexpr (UsesGemm<T>::value) {
+    // GEMM into FP32 rows (chunks <= 2 GiB), then the phase epilogue that
+    // writes B2 in the form's operand format
+    typedef typename GemmOp<T>::type OP;
     const int64_t M = ctx->nstates, ncol = d.ncol;
     int64_t ci = ((int64_t)1 << 31) / (ncol * 8);
     if (ci < 1) ci = 1;
@@ -1117,11 +1270,10 @@ static elph_status launch_step1_t(elph_ctx ctx) {
     }
     for (int64_t i0 = 0; i0 < M; i0 += ci) {
       const int64_t ni = (M - i0 < ci) ? M - i0 : ci;
-      launch_cgemm_split<NS, 1>(ctx->stream, i0, ni, ncol, ctx->ke, 1, (const unsigned short*)ctx->d_Ae,
-                                (const unsigned short*)ctx->d_gR, (float*)p, ncol);
-      hipLaunchKernelGGL(k_step1_epi_split<NS>, dim3(blocks_for(ni * ncol, 256)), dim3(256), 0, ctx->stream, i0, ni,
-                         ncol, ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, (const float*)p, ctx->d_state_kidx,
-                         (const cd*)ctx->d_Ep, (unsigned short*)ctx->d_B2);
+      launch_cgemm<OP, 1>(ctx->stream, i0, ni, ncol, ctx->ke, 1, ctx->d_Ae, ctx->d_gR, (float*)p, ncol);
+      hipLaunchKernelGGL(k_step1_epi<T>, dim3(blocks_for(ni * ncol, 256)), dim3(256), 0, ctx->stream, i0, ni, ncol,
+                         ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, (const float*)p, ctx->d_state_kidx,
+                         (const cd*)ctx->d_Ep, (typename Store<T>::type*)ctx->d_B2);
     }
     dev_free(ctx, p);
     return ELPH_OK;
@@ -1144,11 +1296,12 @@ static void launch_step2_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* B
   hipLaunchKernelGGL((k_step2<T, ST, NX>), grid, dim3(256), 0, ctx->stream, d);
 }
 
-// Split forms without a tile mask: GEMM into an FP32 buffer [i][j][x], then
+// GEMM forms without a tile mask: GEMM into an FP32 buffer [i][j][x], then
 // the per-q epilogue over the kept pairs, in chunks of initial states (whole
 // kept k) so that the buffer stays <= 2 GiB; W_e from the finished store.
-template <int NS, typename ST, int NX>
-static elph_status launch_split_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm, int64_t* we_tiles) {
+template <typename T, typename ST, int NX>
+static elph_status launch_gemm_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm, int64_t* we_tiles) {
+  typedef typename GemmOp<T>::type OP;
   const int64_t M = ctx->nstates, ldc = ctx->m_pad;
   elph_status st = ensure_pairs(ctx);
   if (st != ELPH_OK) return st;
@@ -1176,8 +1329,7 @@ static elph_status launch_split_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, 
     while (t1 < ctx->nkept && soff[t1 + 1] - soff[t0] <= cap) ++t1;
     const int64_t i0 = soff[t0], ni = soff[t1] - soff[t0];
     const int64_t c0 = i0 * NX, nc = ni * NX;
-    launch_cgemm_split<NS, 2>(ctx->stream, c0, nc, M, ctx->kp, NX, (const unsigned short*)ctx->d_B2,
-                              (const unsigned short*)ctx->d_Ap, C, ldc);
+    launch_cgemm<OP, 2>(ctx->stream, c0, nc, M, ctx->kp, NX, ctx->d_B2, ctx->d_Ap, C, ldc);
     if (t1 == ctx->nkept) mark(ctx, 5);  // step-2 window: the contraction (and earlier chunks' epilogues)
     hipLaunchKernelGGL((k_epi_q<ST, NX>), dim3((unsigned)((ctx->nk + 3) / 4)), dim3(256), 0, ctx->stream, ctx->nk,
                        i0, t0, t1, ep, ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist,
@@ -1196,15 +1348,14 @@ static elph_status launch_split_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, 
 template <typename T, typename ST>
 static elph_status launch_step2_t(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm, int64_t* we_tiles) {
   *we_tiles = ctx->m_pad / 32;
-  if constexpr (IsSplit<T>::value) {
-    constexpr int NS = IsSplit<T>::ns;
+  if constexpr (UsesGemm<T>::value) {
     if (!ep.tile_keep) {
       switch (ctx->nbr) {
-        case 3: return launch_split_nx<NS, ST, 3>(ctx, ep, Bp, Bm, we_tiles);
-        case 6: return launch_split_nx<NS, ST, 6>(ctx, ep, Bp, Bm, we_tiles);
-        case 9: return launch_split_nx<NS, ST, 9>(ctx, ep, Bp, Bm, we_tiles);
-        case 12: return launch_split_nx<NS, ST, 12>(ctx, ep, Bp, Bm, we_tiles);
-        case 15: return launch_split_nx<NS, ST, 15>(ctx, ep, Bp, Bm, we_tiles);
+        case 3: return launch_gemm_nx<T, ST, 3>(ctx, ep, Bp, Bm, we_tiles);
+        case 6: return launch_gemm_nx<T, ST, 6>(ctx, ep, Bp, Bm, we_tiles);
+        case 9: return launch_gemm_nx<T, ST, 9>(ctx, ep, Bp, Bm, we_tiles);
+        case 12: return launch_gemm_nx<T, ST, 12>(ctx, ep, Bp, Bm, we_tiles);
+        case 15: return launch_gemm_nx<T, ST, 15>(ctx, ep, Bp, Bm, we_tiles);
         default: ctx->err = "unsupported branch count"; return ELPH_EINVAL;
       }
     }
@@ -1363,6 +1514,15 @@ struct BatchImpl {
   std::vector<void*> allocs;
   std::string err;
   int ncu = 256;
+  // GEMM forms: persistent GEMMs over every material's block tiles, then
+  // each material's epilogues
+  bool gemm = false;
+  GemmArgs* d_g1 = nullptr;
+  GemmArgs* d_g2 = nullptr;
+  int4* d_g1items = nullptr;
+  int4* d_g2items = nullptr;
+  std::vector<int4> g1_natural, g1_sorted, g2_natural, g2_sorted;
+  std::vector<float*> c1, c2;
 };
 
 static std::map<std::string, std::pair<int, bool>>& tune_cache() {
@@ -1461,6 +1621,54 @@ static elph_status batch_prepare_t(BatchImpl* b) {
     for (int64_t by = 0; by < c->m_pad / 64; ++by)
       for (int64_t bx = 0; bx < (s1[m].ncol + 63) / 64; ++bx) b->s1_natural.push_back(make_int4(m, (int)bx, (int)by, 0));
   }
+  if constexpr (UsesGemm<T>::value) {
+    // GEMM path: full-size FP32 result buffers per material (no chunks)
+    b->gemm = true;
+    std::vector<GemmArgs> g1(n), g2(n);
+    for (int m = 0; m < n; ++m) {
+      elph_ctx c = b->ctx[m];
+      if (!c->pairs_ready) {
+        b->err = "material " + std::to_string(m) + ": per-q pair lists are unavailable";
+        return ELPH_EINVAL;
+      }
+      const int64_t M = c->nstates, ncol = s1[m].ncol;
+      void *p1 = nullptr, *p2 = nullptr;
+      if (balloc(b, &p1, (size_t)M * ncol * 8) != hipSuccess ||
+          balloc(b, &p2, (size_t)M * c->nbr * c->m_pad * 8) != hipSuccess) {
+        b->err = "batch allocation of the GEMM buffers failed";
+        return ELPH_ENOMEM;
+      }
+      b->c1.push_back((float*)p1);
+      b->c2.push_back((float*)p2);
+      g1[m] = GemmArgs{0, M, ncol, c->ke, 1, (const unsigned short*)c->d_Ae, (const unsigned short*)c->d_gR,
+                       (float*)p1, ncol};
+      g2[m] = GemmArgs{0, M * c->nbr, M, c->kp, c->nbr, (const unsigned short*)c->d_B2,
+                       (const unsigned short*)c->d_Ap, (float*)p2, c->m_pad};
+      for (const auto& pr : {std::make_pair(&g1[m], &b->g1_natural), std::make_pair(&g2[m], &b->g2_natural)}) {
+        const GemmGrid gg = gemm_grid(pr.first->nc, pr.first->nj, 32 * kGemmWR);
+        for (int ty = 0; ty < gg.ny; ++ty)
+          for (int tx = 0; tx < gg.nx; ++tx) pr.second->push_back(make_int4(m, ty, tx, 0));
+      }
+    }
+    b->g1_sorted = b->g1_natural;
+    std::stable_sort(b->g1_sorted.begin(), b->g1_sorted.end(),
+                     [&](const int4& a, const int4& c2) { return g1[a.x].K > g1[c2.x].K; });
+    b->g2_sorted = b->g2_natural;
+    std::stable_sort(b->g2_sorted.begin(), b->g2_sorted.end(),
+                     [&](const int4& a, const int4& c2) { return g2[a.x].K > g2[c2.x].K; });
+    if (balloc(b, (void**)&b->d_g1, n * sizeof(GemmArgs)) != hipSuccess ||
+        balloc(b, (void**)&b->d_g2, n * sizeof(GemmArgs)) != hipSuccess ||
+        balloc(b, (void**)&b->d_g1items, b->g1_natural.size() * sizeof(int4)) != hipSuccess ||
+        balloc(b, (void**)&b->d_g2items, b->g2_natural.size() * sizeof(int4)) != hipSuccess ||
+        balloc(b, (void**)&b->d_counters, 64 * sizeof(int)) != hipSuccess) {
+      b->err = "batch allocation failed";
+      return ELPH_ENOMEM;
+    }
+    BCHK(hipMemcpy(b->d_g1, g1.data(), n * sizeof(GemmArgs), hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(b->d_g2, g2.data(), n * sizeof(GemmArgs), hipMemcpyHostToDevice));
+    b->prepared = true;
+    return ELPH_OK;
+  }
   auto cost1 = [&](const int4& w) { return b->ctx[w.x]->ke; };
   b->s1_sorted = b->s1_natural;
   std::stable_sort(b->s1_sorted.begin(), b->s1_sorted.end(),
@@ -1508,6 +1716,13 @@ static elph_status batch_prepare_t(BatchImpl* b) {
 }
 
 static elph_status batch_upload_order(BatchImpl* b) {
+  if (b->gemm) {
+    const std::vector<int4>& a = b->sorted ? b->g1_sorted : b->g1_natural;
+    const std::vector<int4>& c = b->sorted ? b->g2_sorted : b->g2_natural;
+    BCHK(hipMemcpy(b->d_g1items, a.data(), a.size() * sizeof(int4), hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(b->d_g2items, c.data(), c.size() * sizeof(int4), hipMemcpyHostToDevice));
+    return ELPH_OK;
+  }
   const std::vector<int4>& s1 = b->sorted ? b->s1_sorted : b->s1_natural;
   BCHK(hipMemcpy(b->d_s1items, s1.data(), s1.size() * sizeof(int4), hipMemcpyHostToDevice));
   for (auto& cl : b->cls) {
@@ -1537,10 +1752,72 @@ static elph_status batch_launch_step2(BatchImpl* b, BatchImpl::Cls& cl, int* cou
   return ELPH_OK;
 }
 
+template <typename ST, int NX>
+static void batch_epi_q(elph_ctx c, const EpiParams& ep, const float* C, hipStream_t s) {
+  hipLaunchKernelGGL((k_epi_q<ST, NX>), dim3((unsigned)((c->nk + 3) / 4)), dim3(256), 0, s, c->nk, (int64_t)0, 0,
+                     (int32_t)c->nkept, ep, c->d_kept, c->d_kidx, c->d_soff, c->d_poff, c->d_plist, C, c->m_pad,
+                     (ST*)c->d_Bp, (ST*)c->d_Bm);
+}
+
+// GEMM forms: two persistent GEMM launches over all materials, each
+// material's step-1 and step-2 epilogues, W_e from the store rows and W_ph.
+template <typename T>
+static elph_status batch_sequence_gemm(BatchImpl* b, double T_K, double* const* we, double* const* wph) {
+  typedef T ST;
+  typedef typename GemmOp<T>::type OP;
+  const int n = (int)b->ctx.size();
+  StreamSwap sw(b);
+  for (int m = 0; m < n; ++m) fill_thermal(b->ctx[m], T_K, b->th[m], b->stream);
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, b->stream, b->d_counters, 64);
+  const int n1 = (int)b->g1_natural.size(), n2 = (int)b->g2_natural.size();
+  hipLaunchKernelGGL((k_cgemm_persist<OP, 1, kGemmWR>), dim3((unsigned)std::min<int64_t>(n1, (int64_t)b->bpc * b->ncu)),
+                     dim3(128 * kGemmWR), 0, b->stream, (const GemmArgs*)b->d_g1, b->d_g1items, n1, b->d_counters);
+  for (int m = 0; m < n; ++m) {
+    elph_ctx c = b->ctx[m];
+    const int64_t M = c->nstates, ncol = (int64_t)c->nbr * c->nrp * c->nb;
+    hipLaunchKernelGGL(k_step1_epi<T>, dim3(blocks_for(M * ncol, 256)), dim3(256), 0, b->stream, (int64_t)0, M, ncol,
+                       c->nrp, c->nb, c->nbr, c->kp, (const float*)b->c1[m], c->d_state_kidx, (const cd*)c->d_Ep,
+                       (typename Store<T>::type*)c->d_B2);
+  }
+  hipLaunchKernelGGL((k_cgemm_persist<OP, 2, kGemmWR>), dim3((unsigned)std::min<int64_t>(n2, (int64_t)b->bpc * b->ncu)),
+                     dim3(128 * kGemmWR), 0, b->stream, (const GemmArgs*)b->d_g2, b->d_g2items, n2,
+                     b->d_counters + 1);
+  for (int m = 0; m < n; ++m) {
+    elph_ctx c = b->ctx[m];
+    EpiParams ep = epi_params(c);
+    ep.lomf = b->th[m].lomf;
+    ep.fstate = b->th[m].f;
+    ep.omf = b->th[m].omf;
+    ep.nocc = b->th[m].nocc;
+    ep.we_part = c->d_we_part;
+    const float* C = b->c2[m];
+    switch (c->nbr) {
+      case 3: batch_epi_q<ST, 3>(c, ep, C, b->stream); break;
+      case 6: batch_epi_q<ST, 6>(c, ep, C, b->stream); break;
+      case 9: batch_epi_q<ST, 9>(c, ep, C, b->stream); break;
+      case 12: batch_epi_q<ST, 12>(c, ep, C, b->stream); break;
+      case 15: batch_epi_q<ST, 15>(c, ep, C, b->stream); break;
+      default: b->err = "unsupported branch count"; return ELPH_EINVAL;
+    }
+    launch_we_rows<ST>(c, (const ST*)c->d_Bp, (const ST*)c->d_Bm, ep.lomf, ep.nocc, c->d_we_part);
+    double* wout = (we && we[m]) ? we[m] : b->we_tmp[m];
+    hipLaunchKernelGGL(k_reduce_we, dim3(blocks_for(c->nstates, 256)), dim3(256), 0, b->stream, c->d_we_part,
+                       (int64_t)1, c->m_pad, c->nstates, wout);
+    if (wph && wph[m]) {
+      launch_q_gather<ST, 1>(c, (const ST*)c->d_Bp, b->th[m].f, b->th[m].omf, nullptr, b->acc[m]);
+      elph_status st = finalize_wph(c, b->th[m], b->acc[m], wph[m]);
+      if (st != ELPH_OK) return st;
+    }
+  }
+  BCHK(hipGetLastError());
+  return ELPH_OK;
+}
+
 // The per-temperature sequence (no synchronisation, no allocation: safe to capture).
 template <typename T>
 static elph_status batch_sequence(BatchImpl* b, double T_K, double* const* we, double* const* wph) {
   typedef T ST;  // the store keeps the precision of the contraction
+  if constexpr (UsesGemm<T>::value) return batch_sequence_gemm<T>(b, T_K, we, wph);
   const int n = (int)b->ctx.size();
   StreamSwap sw(b);
   for (int m = 0; m < n; ++m) fill_thermal(b->ctx[m], T_K, b->th[m], b->stream);
