@@ -700,13 +700,36 @@ __global__ void k_group_bounds(int64_t n, const int32_t* __restrict__ flag, cons
   group[order[t]] = g;
 }
 
-// De[i][c] = sum_{j,s} r_ij / W_i (-P[q][s][c] B+ n + P[-q][s][c] B- (1+n)), c = 0..5
+// Drag factors of the current phonons, one contiguous row per (q, s):
+// H[q][s][c] = -n_qs P[q][s][c], H[q][s][6 + c] = (1 + n_qs) P[-q][s][c].
+// In the store's precision (FP32 in the forms), so the gathers of the
+// electron drag read half the bytes there.
+template <typename HT>
+__global__ void k_drag_prep(int64_t nq, int nbr, MeshDims md, const double* __restrict__ nocc,
+                            const double* __restrict__ phon, HT* __restrict__ H) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nq * nbr * 12) return;
+  const int64_t qs = e / 12;
+  const int c = (int)(e - qs * 12);
+  const int64_t q = qs / nbr;
+  const int s = (int)(qs - q * nbr);
+  const double n = nocc[qs];
+  double v;
+  if (c < 6) {
+    v = -n * phon[qs * 6 + c];
+  } else {
+    const int64_t mq = q_neg((int)q, md.n0, md.n1, md.n2);
+    v = (1.0 + n) * phon[(mq * nbr + s) * 6 + (c - 6)];
+  }
+  H[e] = (HT)v;
+}
+
+// De[i][c] = sum_{j,s} r_ij / W_i (B+ H[q][s][c] + B- H[q][s][6 + c]), c = 0..5
 template <typename ST, int NX>
 __global__ void __launch_bounds__(256) k_drag_e(int64_t M, MeshDims md, const ST* __restrict__ Bp,
                                                 const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
-                                                const double* __restrict__ lomf, const double* __restrict__ nocc,
-                                                const double* __restrict__ we, const double* __restrict__ phon,
-                                                double* __restrict__ De) {
+                                                const double* __restrict__ lomf, const double* __restrict__ we,
+                                                const ST* __restrict__ H, double* __restrict__ De) {
   __shared__ double sh[6 * 4];
   const int64_t i = blockIdx.x;
   const int ki = st_k[i];
@@ -720,14 +743,11 @@ __global__ void __launch_bounds__(256) k_drag_e(int64_t M, MeshDims md, const ST
     if (vp == 0.0 && vm == 0.0) continue;
     const int j = t / NX, s = t - j * NX;
     const int q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
-    const int mq = q_neg(q, md.n0, md.n1, md.n2);
-    const double n = nocc[(int64_t)q * NX + s];
     const double r = exp(lomf[j] - li);
-    const double a = -vp * n * r, b = vm * (1.0 + n) * r;
-    const double* pq = phon + ((int64_t)q * NX + s) * 6;
-    const double* pm = phon + ((int64_t)mq * NX + s) * 6;
+    const ST* h = H + ((int64_t)q * NX + s) * 12;
+    const double a = vp * r, b = vm * r;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += a * pq[c] + b * pm[c];
+    for (int c = 0; c < 6; ++c) acc[c] += a * (double)h[c] + b * (double)h[6 + c];
   }
   block_sum<6>(acc, sh);
   double v = acc[0];
@@ -857,16 +877,27 @@ struct Gam8 {
 
 // part[block][v][c] = sum over the block's elements of column c of vs[v] . a
 // (one pass over a; 192 threads and a stride that is a multiple of 6, so each
-// thread keeps one column; the 32 threads of a column are summed in order)
+// thread keeps one column; two strides per iteration keep twice the loads in
+// flight; the 32 threads of a column are summed in order)
+constexpr int kDotsBlocks = 1024;
+
 __global__ void __launch_bounds__(192) k_dots_multi(int64_t n6, int nv, Ptr8 vs, const double* __restrict__ a,
                                                     double* __restrict__ part) {
   __shared__ double sh[8][192];
   double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t t = (int64_t)blockIdx.x * 192 + threadIdx.x; t < n6; t += (int64_t)gridDim.x * 192) {
-    const double at = a[t];
+  const int64_t stride = (int64_t)gridDim.x * 192;
+  int64_t t = (int64_t)blockIdx.x * 192 + threadIdx.x;
+  for (; t + stride < n6; t += 2 * stride) {
+    const double a0 = a[t], a1 = a[t + stride];
 #pragma unroll
     for (int v = 0; v < 8; ++v)
-      if (v < nv) s[v] += vs.p[v][t] * at;
+      if (v < nv) s[v] += vs.p[v][t] * a0 + vs.p[v][t + stride] * a1;
+  }
+  if (t < n6) {
+    const double a0 = a[t];
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+      if (v < nv) s[v] += vs.p[v][t] * a0;
   }
 #pragma unroll
   for (int v = 0; v < 8; ++v) sh[v][threadIdx.x] = s[v];
@@ -1023,7 +1054,7 @@ static double rel(double d2, double n2) { return std::sqrt(d2) / std::max(std::s
 // out[v][c] = column-c dot of vs[v] and a, v < nv (block partials summed in order)
 static elph_status dots_multi(elph_ctx ctx, int64_t n6, int nv, const Ptr8& vs, const double* a, double* part,
                               std::vector<double>& hpart, double (*out)[6]) {
-  const int blocks = 256;
+  const int blocks = kDotsBlocks;
   hipLaunchKernelGGL(k_dots_multi, dim3(blocks), dim3(192), 0, ctx->stream, n6, nv, vs, a, part);
   HIPCHK(hipMemcpyAsync(hpart.data(), part, blocks * 8 * 6 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1096,9 +1127,11 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   ALLOC(phon, nm * 6 * sizeof(double));
   ALLOC(phonn, nm * 6 * sizeof(double));
   ALLOC(acc, nm * 6 * sizeof(double));
-  ALLOC(part, 256 * 64 * sizeof(double));
+  ALLOC(part, std::max(256 * 64, kDotsBlocks * 8 * 6) * sizeof(double));
   ALLOC(wff, M * sizeof(double));
   ALLOC(xprev, M * 6 * sizeof(double));
+  ST* hdrag = nullptr;
+  if (level != ELPH_LEVEL_RTA && level != ELPH_LEVEL_DRAGLESS) ALLOC(hdrag, nm * 12 * sizeof(ST));
   std::vector<double> hpart(256 * 64);
 
   if (ctx->rates_valid && ctx->rates_T == T) {
@@ -1152,9 +1185,11 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
       // fixed point x = P(b + K x) solves L x = b with L = 1 - P K on the
       // range of P, started from the previous solution
       if (drag) {
+        hipLaunchKernelGGL(k_drag_prep<ST>, dim3(blocks_for(nm * 12, 256)), dim3(256), 0, s, ctx->nk, nbr, md,
+                           th.nocc, phon, hdrag);
 #define DE(NXV)                                                                                           \
   hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)M), dim3(256), 0, s, M, md, Bp, Bm, ctx->d_state_k, \
-                     th.lomf, th.nocc, we, phon, De)
+                     th.lomf, we, hdrag, De)
         switch (nbr) {
           case 3: DE(3); break;
           case 6: DE(6); break;
@@ -1204,7 +1239,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
       }
       double Gm[6][8][8];
       int nh = 0, head = 0;
-      std::vector<double> hp2(256 * 8 * 6);
+      std::vector<double> hp2(kDotsBlocks * 8 * 6);
       for (int it = 1; it <= maxit; ++it) {
         bool ok = false;
         HIPCHK(hipMemcpyAsync(xprev, x, M * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1326,7 +1361,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   HIPCHK(hipStreamSynchronize(s));
   if (iters) *iters = used;
   for (void* p : {(void*)we, (void*)wphe, (void*)wp, (void*)x0, (void*)x, (void*)De, (void*)phon0, (void*)phon,
-                  (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase})
+                  (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase, (void*)hdrag})
     dev_free(ctx, p);
   free_thermal(ctx, &th);
   if (!converged) {
