@@ -194,7 +194,8 @@ elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, double* W_ph
 
 /* Coupled e-ph BTEs with the unified single-iterator scheme (Eq. 19,
  * Eqs. 20-27): each phonon iteration brings the electron equations to
- * self-consistency (relative tolerance tol/10) with the current phonons.
+ * self-consistency with the current phonons (relative residual tol/10, or
+ * tol/100 at level COUPLED).
  * W_ph_ext [nk][nbr] device: phonon rates from other channels (ph-ph,
  * isotopes), s^-1, added to the ph-e rate (Eq. 25); NULL selects the model
  * 1e12 (hw/hw_max)^2 (T/300).  The ph-ph in-scattering term is zero.

@@ -700,36 +700,13 @@ __global__ void k_group_bounds(int64_t n, const int32_t* __restrict__ flag, cons
   group[order[t]] = g;
 }
 
-// Drag factors of the current phonons, one contiguous row per (q, s):
-// H[q][s][c] = -n_qs P[q][s][c], H[q][s][6 + c] = (1 + n_qs) P[-q][s][c].
-// In the store's precision (FP32 in the forms), so the gathers of the
-// electron drag read half the bytes there.
-template <typename HT>
-__global__ void k_drag_prep(int64_t nq, int nbr, MeshDims md, const double* __restrict__ nocc,
-                            const double* __restrict__ phon, HT* __restrict__ H) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nq * nbr * 12) return;
-  const int64_t qs = e / 12;
-  const int c = (int)(e - qs * 12);
-  const int64_t q = qs / nbr;
-  const int s = (int)(qs - q * nbr);
-  const double n = nocc[qs];
-  double v;
-  if (c < 6) {
-    v = -n * phon[qs * 6 + c];
-  } else {
-    const int64_t mq = q_neg((int)q, md.n0, md.n1, md.n2);
-    v = (1.0 + n) * phon[(mq * nbr + s) * 6 + (c - 6)];
-  }
-  H[e] = (HT)v;
-}
-
-// De[i][c] = sum_{j,s} r_ij / W_i (B+ H[q][s][c] + B- H[q][s][6 + c]), c = 0..5
+// De[i][c] = sum_{j,s} r_ij / W_i (-P[q][s][c] B+ n + P[-q][s][c] B- (1+n)), c = 0..5
 template <typename ST, int NX>
 __global__ void __launch_bounds__(256) k_drag_e(int64_t M, MeshDims md, const ST* __restrict__ Bp,
                                                 const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
-                                                const double* __restrict__ lomf, const double* __restrict__ we,
-                                                const ST* __restrict__ H, double* __restrict__ De) {
+                                                const double* __restrict__ lomf, const double* __restrict__ nocc,
+                                                const double* __restrict__ we, const double* __restrict__ phon,
+                                                double* __restrict__ De) {
   __shared__ double sh[6 * 4];
   const int64_t i = blockIdx.x;
   const int ki = st_k[i];
@@ -743,11 +720,14 @@ __global__ void __launch_bounds__(256) k_drag_e(int64_t M, MeshDims md, const ST
     if (vp == 0.0 && vm == 0.0) continue;
     const int j = t / NX, s = t - j * NX;
     const int q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
+    const int mq = q_neg(q, md.n0, md.n1, md.n2);
+    const double n = nocc[(int64_t)q * NX + s];
     const double r = exp(lomf[j] - li);
-    const ST* h = H + ((int64_t)q * NX + s) * 12;
-    const double a = vp * r, b = vm * r;
+    const double a = -vp * n * r, b = vm * (1.0 + n) * r;
+    const double* pq = phon + ((int64_t)q * NX + s) * 6;
+    const double* pm = phon + ((int64_t)mq * NX + s) * 6;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += a * (double)h[c] + b * (double)h[6 + c];
+    for (int c = 0; c < 6; ++c) acc[c] += a * pq[c] + b * pm[c];
   }
   block_sum<6>(acc, sh);
   double v = acc[0];
@@ -1130,8 +1110,6 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   ALLOC(part, std::max(256 * 64, kDotsBlocks * 8 * 6) * sizeof(double));
   ALLOC(wff, M * sizeof(double));
   ALLOC(xprev, M * 6 * sizeof(double));
-  ST* hdrag = nullptr;
-  if (level != ELPH_LEVEL_RTA && level != ELPH_LEVEL_DRAGLESS) ALLOC(hdrag, nm * 12 * sizeof(ST));
   std::vector<double> hpart(256 * 64);
 
   if (ctx->rates_valid && ctx->rates_T == T) {
@@ -1180,16 +1158,19 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
       one6.v[c] = 1.0;
       zero6.v[c] = 0.0;
     }
+    // Inner tolerance: tol/10 when one phonon step is taken; tol/100 when the
+    // phonon iterates are driven to tol, since the error an inner solve
+    // leaves, amplified by the operator's conditioning, becomes noise in the
+    // outer differences that stalls the accelerated iteration above tol.
+    const double inner_thr = (level == ELPH_LEVEL_COUPLED ? 0.01 : 0.1) * tol;
     auto solve_e = [&](bool drag, bool* ok) -> elph_status {
       // drive b = P(x0 (+ electron drag from the current phonons)); the
       // fixed point x = P(b + K x) solves L x = b with L = 1 - P K on the
       // range of P, started from the previous solution
       if (drag) {
-        hipLaunchKernelGGL(k_drag_prep<ST>, dim3(blocks_for(nm * 12, 256)), dim3(256), 0, s, ctx->nk, nbr, md,
-                           th.nocc, phon, hdrag);
 #define DE(NXV)                                                                                           \
   hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)M), dim3(256), 0, s, M, md, Bp, Bm, ctx->d_state_k, \
-                     th.lomf, we, hdrag, De)
+                     th.lomf, th.nocc, we, phon, De)
         switch (nbr) {
           case 3: DE(3); break;
           case 6: DE(6); break;
@@ -1203,7 +1184,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
                          drag ? De : nullptr, zero6, (const double*)nullptr, sv.b);
       hipLaunchKernelGGL(k_project, dim3(ng), dim3(256), 0, s, order, goff, wff, sv.b);
       hipLaunchKernelGGL(k_project, dim3(ng), dim3(256), 0, s, order, goff, wff, x);
-      elph_status e2 = self_solve(ctx, sv, x, tol, maxit, ok, &last_inner);
+      elph_status e2 = self_solve(ctx, sv, x, inner_thr, maxit, ok, &last_inner);
       if (e2 != ELPH_OK) return e2;
       // remove what rounding left along the group directions
       hipLaunchKernelGGL(k_project, dim3(ng), dim3(256), 0, s, order, goff, wff, x);
@@ -1361,7 +1342,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   HIPCHK(hipStreamSynchronize(s));
   if (iters) *iters = used;
   for (void* p : {(void*)we, (void*)wphe, (void*)wp, (void*)x0, (void*)x, (void*)De, (void*)phon0, (void*)phon,
-                  (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase, (void*)hdrag})
+                  (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase})
     dev_free(ctx, p);
   free_thermal(ctx, &th);
   if (!converged) {

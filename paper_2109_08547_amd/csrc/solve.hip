@@ -361,11 +361,10 @@ static void apply_L(elph_ctx ctx, const SelfSolver& sv, const double* in, double
                      a0, sq, dpart);
 }
 
-elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double tol, int maxit, bool* ok,
+elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double thr, int maxit, bool* ok,
                        int* iters) {
   hipStream_t s = ctx->stream;
   const int64_t M = ctx->nstates, n6 = 6 * M;
-  const double thr = 0.1 * tol;
   const unsigned ev = blocks_for(n6, 256);
   if (!ctx->h_pin) HIPCHK(hipHostMalloc((void**)&ctx->h_pin, SC_N * sizeof(double), hipHostMallocDefault));
   // r0 = b - L x0 (v holds L x0 until the init kernel clears it)

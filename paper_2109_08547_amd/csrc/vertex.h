@@ -53,8 +53,8 @@ elph_status build_self_operator(elph_ctx ctx, const ST* Bp, const ST* Bm, const 
                                 const double* we, const int32_t* order, const int32_t* goff, const double* wff,
                                 const SelfSolver& sv);
 // Solves L x = b (b in sv.b, projected; x projected on entry) to relative
-// residual 0.1 tol per column; *ok when all six columns reached it.
-elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double tol, int maxit, bool* ok, int* iters);
+// residual thr per column; *ok when all six columns reached it.
+elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double thr, int maxit, bool* ok, int* iters);
 
 // batches of materials in persistent launches (vertex.hip)
 struct BatchImpl;
