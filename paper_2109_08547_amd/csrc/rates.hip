@@ -225,44 +225,66 @@ __global__ void k_pair_fill(int64_t nkept, const int32_t* __restrict__ kept, Mes
   tmp[off[q] + atomicAdd(&cur[q], 1)] = (int32_t)t;
 }
 
-// one block per q: bitonic sort in LDS up to 4096 entries, rank placement
-// (entries of one q are distinct) beyond
-__global__ void __launch_bounds__(256) k_pair_sort(const int32_t* __restrict__ off, const int32_t* __restrict__ tmp,
-                                                   int32_t* __restrict__ list) {
-  __shared__ int32_t sh[4096];
-  const int32_t b = off[blockIdx.x], len = off[blockIdx.x + 1] - b;
-  if (len <= 4096) {
-    int np = 1;
-    while (np < len) np <<= 1;
-    for (int i = threadIdx.x; i < np; i += 256) sh[i] = i < len ? tmp[b + i] : 0x7fffffff;
-    __syncthreads();
-    for (int k = 2; k <= np; k <<= 1)
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < np; i += 256) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const int32_t x = sh[i], y = sh[ixj];
-            if ((x > y) == ((i & k) == 0)) {
-              sh[i] = y;
-              sh[ixj] = x;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    for (int i = threadIdx.x; i < len; i += 256) list[b + i] = sh[i];
-  } else {
-    for (int i = threadIdx.x; i < len; i += 256) {
-      const int32_t v = tmp[b + i];
-      int32_t rank = 0;
-      for (int k = 0; k < len; ++k) rank += tmp[b + k] < v ? 1 : 0;
-      list[b + rank] = v;
+// The entries of one q are distinct kept indices t < nkept, so each lands at
+// its rank among them: one wavefront per q sets bit t of a bitmap in LDS,
+// takes exclusive prefix sums of the words' popcounts, and places every
+// entry at prefix + popcount of the lower bits of its word.  The block's
+// four wavefronts pass the same barriers whatever their list lengths.
+__global__ void __launch_bounds__(256) k_pair_place(int64_t nq, int nkept, const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ tmp, int32_t* __restrict__ list) {
+  extern __shared__ uint32_t sm[];  // per wavefront: bitmap [W], prefix [W]
+  const int W = (nkept + 31) / 32;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+  uint32_t* bits = sm + (size_t)wave * 2 * W;
+  uint32_t* pre = bits + W;
+  int32_t b = 0, len = 0;
+  if (q < nq) {
+    b = off[q];
+    len = off[q + 1] - b;
+  }
+  for (int w = lane; w < W; w += 64) bits[w] = 0u;
+  __syncthreads();
+  for (int e = lane; e < len; e += 64) {
+    const int32_t v = tmp[b + e];
+    atomicOr(&bits[v >> 5], 1u << (v & 31));
+  }
+  __syncthreads();
+  // exclusive prefix of the popcounts: lane owns words [lane per, lane per + per)
+  const int per = (W + 63) / 64;
+  int own = 0;
+  for (int k = 0; k < per; ++k) {
+    const int w = lane * per + k;
+    if (w < W) own += __popc(bits[w]);
+  }
+  int incl = own;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  int run = incl - own;
+  for (int k = 0; k < per; ++k) {
+    const int w = lane * per + k;
+    if (w < W) {
+      pre[w] = (uint32_t)run;
+      run += __popc(bits[w]);
     }
+  }
+  __syncthreads();
+  for (int e = lane; e < len; e += 64) {
+    const int32_t v = tmp[b + e];
+    const uint32_t word = bits[v >> 5];
+    list[b + (int32_t)pre[v >> 5] + __popc(word & ((1u << (v & 31)) - 1u))] = v;
   }
 }
 
 elph_status ensure_pairs(elph_ctx ctx) {
   if (ctx->pairs_ready) return ELPH_OK;
+  if (ctx->nkept > kMaxPairKept) {
+    ctx->err = "too many kept k for per-q pair lists (nkept^2 must stay below 2^31)";
+    return ELPH_EINVAL;
+  }
   hipStream_t s = ctx->stream;
   const int64_t nk = ctx->nk, nkept = ctx->nkept, npairs = nkept * nkept;
   const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
@@ -279,7 +301,9 @@ elph_status ensure_pairs(elph_ctx ctx) {
   HIPCHK(hipMemsetAsync(cnt, 0, nk * sizeof(int32_t), s));
   hipLaunchKernelGGL(k_pair_fill, dim3(blocks_for(npairs, 256)), dim3(256), 0, s, nkept, ctx->d_kept, md,
                      ctx->d_poff, cnt, tmp);
-  hipLaunchKernelGGL(k_pair_sort, dim3((unsigned)nk), dim3(256), 0, s, ctx->d_poff, tmp, ctx->d_plist);
+  const size_t place_lds = (size_t)4 * 2 * ((nkept + 31) / 32) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_pair_place, dim3((unsigned)((nk + 3) / 4)), dim3(256), place_lds, s, nk, (int)nkept,
+                     ctx->d_poff, tmp, ctx->d_plist);
   HIPCHK(hipGetLastError());
   dev_free(ctx, cnt);
   dev_free(ctx, tmp);
