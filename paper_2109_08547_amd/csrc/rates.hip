@@ -708,6 +708,44 @@ __global__ void k_bitonic(int64_t npow, int64_t kk, int64_t jj, double* __restri
   }
 }
 
+// The same sort in one block through LDS when npow <= kSortLds (one launch
+// instead of one per stage); the order (key, then index) is total, so the
+// result is the same.
+constexpr int kSortLds = 4096;
+
+__global__ void __launch_bounds__(1024) k_bitonic_lds(int npow, double* __restrict__ key, int32_t* __restrict__ idx) {
+  __shared__ double sk[kSortLds];
+  __shared__ int32_t si[kSortLds];
+  for (int t = threadIdx.x; t < npow; t += 1024) {
+    sk[t] = key[t];
+    si[t] = idx[t];
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= npow; kk <<= 1)
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int t = threadIdx.x; t < npow; t += 1024) {
+        const int p = t ^ jj;
+        if (p > t) {
+          const bool up = (t & kk) == 0;
+          const double a = sk[t], b = sk[p];
+          const int32_t ia = si[t], ib = si[p];
+          const bool greater = (a > b) || (a == b && ia > ib);
+          if (greater == up) {
+            sk[t] = b;
+            sk[p] = a;
+            si[t] = ib;
+            si[p] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int t = threadIdx.x; t < npow; t += 1024) {
+    key[t] = sk[t];
+    idx[t] = si[t];
+  }
+}
+
 __global__ void k_group_flags(int64_t n, const double* __restrict__ key, double gap, int32_t* __restrict__ flag) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -1005,9 +1043,13 @@ static elph_status build_groups(elph_ctx ctx, int32_t** order_out, int32_t** off
   ALLOC(scr, (4 * ((M + 1023) / 1024) + 64) * sizeof(int32_t));
   ALLOC(tot, sizeof(int32_t));
   hipLaunchKernelGGL(k_sort_init, dim3(blocks_for(npow, 256)), dim3(256), 0, s, M, npow, ctx->d_eps, key, idx);
-  for (int64_t kk = 2; kk <= npow; kk <<= 1)
-    for (int64_t jj = kk >> 1; jj > 0; jj >>= 1)
-      hipLaunchKernelGGL(k_bitonic, dim3(blocks_for(npow, 256)), dim3(256), 0, s, npow, kk, jj, key, idx);
+  if (npow <= kSortLds) {
+    hipLaunchKernelGGL(k_bitonic_lds, dim3(1), dim3(1024), 0, s, (int)npow, key, idx);
+  } else {
+    for (int64_t kk = 2; kk <= npow; kk <<= 1)
+      for (int64_t jj = kk >> 1; jj > 0; jj >>= 1)
+        hipLaunchKernelGGL(k_bitonic, dim3(blocks_for(npow, 256)), dim3(256), 0, s, npow, kk, jj, key, idx);
+  }
   const double gap = ctx->hw_max + 12.0 * ctx->sigma;
   hipLaunchKernelGGL(k_group_flags, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, key, gap, flag);
   scan_exclusive(ctx, flag, M, lab, tot, scr, s);
