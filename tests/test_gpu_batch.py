@@ -59,9 +59,11 @@ def test_batch_equals_single_contexts(precision):
         c.close()
     ctxs = [_ctx(cfg, mat, precision) for cfg, mat in mats]
     batch = E.elph_batch_create(ctxs)
-    for use_graph in (False, True, True):            # plain, capture, replay
+    for use_graph in (False, True, True, "tuned"):   # plain, capture, replay, after the tuner
+        if use_graph == "tuned":
+            E.elph_batch_tune(batch, T)                  # other grids and item orders, same blocks
         we, wph = _outputs(ctxs)
-        E.elph_batch_scatt_rates(batch, T, we, wph, use_graph=use_graph)
+        E.elph_batch_scatt_rates(batch, T, we, wph, use_graph=bool(use_graph))
         torch.cuda.synchronize()
         for m in range(len(mats)):
             assert np.array_equal(we[m].cpu().numpy(), single[m][0]), (use_graph, m)

@@ -144,16 +144,31 @@ def test_scatt_rates_full(name):
     ctx.close()
 
 
-def test_maximum_sizes_16_bands_5_atoms():
+# every form at the largest band and branch counts (15 branches: the widest
+# epilogues; the GEMM forms' row tiles end inside a block)
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_maximum_sizes_16_bands_5_atoms(form):
     c = _maxsize_case()
-    ctx = make_ctx(c.cfg, c.mat)
+    ctx = make_ctx(c.cfg, c.mat, precision=form)
     sz = E.elph_sizes(ctx)
     assert sz["nwann"] == 16 and sz["nbr"] == 15 and sz["nstates"] == c.prob.nstates
     we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
     E.elph_scatt_rates(ctx, c.T, we, wph)
     torch.cuda.synchronize()
-    assert rate_err(we.cpu().numpy(), c.we) < 1e-10
-    assert rate_err(wph.cpu().numpy(), c.wph) < 1e-10
+    w1, w2 = we.cpu().numpy(), wph.cpu().numpy()
+    if form == "fp64":
+        assert rate_err(w1, c.we) < 1e-10
+        assert rate_err(w2, c.wph) < 1e-10
+    else:
+        # the forms' bars, as in test_fp32_form and test_bf16_split_forms
+        e1, e2 = rate_err(w1, c.we, 1e-6), rate_err(w2, c.wph, 1e-6)
+        n1 = np.linalg.norm(w1 - c.we) / np.linalg.norm(c.we)
+        n2 = np.linalg.norm(w2 - c.wph.ravel()) / np.linalg.norm(c.wph)
+        print("%s at 16 bands, 5 atoms: above 1e-6 max %.2e %.2e, norm-wise %.2e %.2e" % (form, e1, e2, n1, n2))
+        if form == "bf16x3":
+            assert e1 < 2e-4 and e2 < 2e-4 and n1 < 2e-5 and n2 < 2e-5
+        else:
+            assert e1 < 1e-5 and e2 < 1e-5 and n1 < 1e-6 and n2 < 1e-6
     ctx.close()
 
 
