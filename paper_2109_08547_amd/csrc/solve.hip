@@ -89,7 +89,8 @@ __global__ void __launch_bounds__(256) k_kT_project(int64_t M, int ngroups, cons
 
 // part[split][i][c] = sum_{j in split} K^T[j][i] in[j][c].  Block = 64
 // states (one per lane) x one j split; the four wavefronts take every fourth
-// j and are summed in wave order.
+// j (eight rows of K^T loaded before they are used, to keep enough bytes in
+// flight) and are summed in wave order.
 template <typename KS>
 __global__ void __launch_bounds__(256) k_kmv(int64_t M, int64_t jlen, const KS* __restrict__ KT,
                                              const double* __restrict__ in, double* __restrict__ part) {
@@ -101,8 +102,19 @@ __global__ void __launch_bounds__(256) k_kmv(int64_t M, int64_t jlen, const KS* 
   const int64_t jb = (int64_t)blockIdx.y * jlen;
   const int64_t je = jb + jlen < M ? jb + jlen : M;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int64_t j = jb + wave; j < je; j += 4) {
+  int64_t j = jb + wave;
+  for (; j + 28 < je; j += 32) {
+    double kk[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) kk[u] = (double)KT[(j + 4 * u) * M + ic];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double* xj = in + (j + 4 * u) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] += kk[u] * xj[c];
+    }
+  }
+  for (; j < je; j += 4) {
     const double k = (double)KT[j * M + ic];
     const double* xj = in + j * 6;
 #pragma unroll
