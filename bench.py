@@ -29,14 +29,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "e-ph transition probabilities/s at rel err 1e-5 vs FP64; MFMA util"
 # TFLOP/s of algorithmic (complex-contraction) flops at the dense MFMA peak of
-# each form's arithmetic: a BF16 split form spends 3 or 6 BF16 products per
-# real product, so its ceiling is the 2.5 PFLOP/s BF16 peak divided by that
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}
-DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}
+# each form's arithmetic: a BF16 (FP16) split form spends 3 or 6 BF16 (FP16)
+# products per real product, so its ceiling is the 2.5 PFLOP/s BF16/FP16 peak
+# divided by that
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6, "fp16x3": 2500.0 / 3}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "fp16x3": "f16"}
 GEMM_KERNEL = {"fp64": "k_step2<double, double, NX> (fused step-2 contraction + epilogue)",
                "fp32": "k_cgemm<OpF32, 2, 4> (step-2 contraction)",
                "bf16x3": "k_cgemm<OpSplit<2>, 2, 4> (step-2 contraction)",
-               "bf16x6": "k_cgemm<OpSplit<3>, 2, 4> (step-2 contraction)"}
+               "bf16x6": "k_cgemm<OpSplit<3>, 2, 4> (step-2 contraction)",
+               "fp16x3": "k_cgemm<OpSplit<2, true>, 2, 4> (step-2 contraction)"}
 WORKLOADS = {
     "mixed48": "8 Wannier bands, 2 atoms, 203 R_e + 203 R_p vectors, 48^3 k and q meshes, "
                "window +-0.4 eV around mu = CBM - 0.1 eV keeping 3% of k, Gaussian sigma 10 meV, 300 K",
@@ -312,7 +314,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="mixed48", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp64,fp32,bf16x3,bf16x6")
+    ap.add_argument("--forms", default="fp64,fp32,bf16x3,bf16x6,fp16x3")
     ap.add_argument("--no-iterate", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=200)
@@ -336,7 +338,7 @@ def main():
         print(json.dumps(run_batch(E, torch, args.steps, args.warmup)), flush=True)
         return
     if args.workload == "large100":
-        form = args.forms.split(",")[-1] if args.forms != "fp64,fp32,bf16x3,bf16x6" else "fp32"
+        form = args.forms.split(",")[-1] if args.forms != "fp64,fp32,bf16x3,bf16x6,fp16x3" else "fp32"
         print(json.dumps(run_large(E, torch, form=form)), flush=True)
         return
     if args.copy_calibration:

@@ -69,7 +69,11 @@ enum {
   ELPH_FP64 = 0,     /* FP64 MFMA contractions (plain path) */
   ELPH_FP32 = 1,     /* FP32 MFMA contractions, FP32 accumulation */
   ELPH_BF16X3 = 2,   /* BF16 split a = hi + lo, 3 products, FP32 accumulation */
-  ELPH_BF16X6 = 3    /* BF16 split a = hi + mid + lo, 6 products, FP32 accumulation */
+  ELPH_BF16X6 = 3,   /* BF16 split a = hi + mid + lo, 6 products, FP32 accumulation */
+  ELPH_FP16X3 = 4    /* FP16 split a = hi + lo (22 significant bits), 3 products, FP32
+                        accumulation; operands scaled by powers of two derived from the
+                        largest Wannier weight and |g| so that both parts stay normal
+                        FP16 numbers (exact inverse scaling in the epilogues) */
 };
 
 /* Solution levels of the coupled BTEs (section "Coupled and decoupled BTEs"). */
@@ -101,7 +105,7 @@ typedef struct {
 
 typedef struct {
   int32_t mesh[3];        /* N0, N1, N2 of the common k and q mesh */
-  int32_t precision;      /* ELPH_FP64 / ELPH_FP32 / ELPH_BF16X3 / ELPH_BF16X6 */
+  int32_t precision;      /* ELPH_FP64 / ELPH_FP32 / ELPH_BF16X3 / ELPH_BF16X6 / ELPH_FP16X3 */
   double mu_eV;           /* chemical potential */
   double window_eV;       /* half-width of the transport window; INFINITY keeps all */
   double sigma_eV;        /* standard deviation of the Gaussian delta (Eq. 8) */

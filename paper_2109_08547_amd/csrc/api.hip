@@ -95,7 +95,7 @@ static elph_status validate(const elph_wannier* w, const elph_params* p) {
   if (!(p->window_eV > 0)) return fail_create("window must be positive (INFINITY keeps all)");
   if (!std::isfinite(p->mu_eV)) return fail_create("mu must be finite");
   if (p->omega_min_eV < 0 || !std::isfinite(p->omega_min_eV)) return fail_create("omega_min must be >= 0");
-  if (p->precision < ELPH_FP64 || p->precision > ELPH_BF16X6) return fail_create("unknown precision form");
+  if (p->precision < ELPH_FP64 || p->precision > ELPH_FP16X3) return fail_create("unknown precision form");
   const int nb = w->nwann, nbr = 3 * w->natom;
   const size_t nn = (size_t)nb * nb, mm = (size_t)nbr * nbr;
   if (!all_finite(w->lat, 9) || !all_finite(w->mass, w->natom)) return fail_create("non-finite lattice or mass");
@@ -183,6 +183,26 @@ extern "C" elph_status elph_create(const elph_wannier* w, const elph_params* p, 
   ctx->window = p->window_eV;
   ctx->sigma = p->sigma_eV;
   ctx->omega_min = p->omega_min_eV > 0 ? p->omega_min_eV : 1.0e-4;
+  if (ctx->precision == ELPH_FP16X3) {
+    // powers of two that put each operand's largest possible magnitude at
+    // 2^13 (FP16 holds up to 65504): |A_e| <= max|w_e|, |A_p| <= max|w_p|
+    // (unit eigenvectors times phases), |gR| <= max|g|, and
+    // |B2| <= N_Re nb max|w_e| max|g|
+    auto maxabs = [](const double* v, size_t n, double dflt) {
+      if (!v) return dflt;
+      double m = 0.0;
+      for (size_t k = 0; k < n; ++k) m = std::max(m, std::fabs(v[k]));
+      return m;
+    };
+    const int nb_ = w->nwann, nbr_ = 3 * w->natom;
+    const double we = maxabs(w->wre, (size_t)w->nre, 1.0), wp = maxabs(w->wrp, (size_t)w->nrp, 1.0);
+    const double gm = maxabs(w->g_r, 2 * (size_t)w->nre * w->nrp * nbr_ * nb_ * nb_, 1.0);
+    auto scale_for = [](double bound) { return bound > 0.0 ? std::ldexp(1.0, 13 - std::ilogb(bound) - 1) : 1.0; };
+    ctx->sc_ae = scale_for(we);
+    ctx->sc_ap = scale_for(wp);
+    ctx->sc_g = scale_for(gm);
+    ctx->sc_b2 = scale_for((double)w->nre * nb_ * we * gm);
+  }
   std::memcpy(ctx->lat, w->lat, sizeof(ctx->lat));
   const double* L = w->lat;
   ctx->volume_A3 = std::fabs(L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +

@@ -63,6 +63,9 @@ struct elph_ctx_s {
   int64_t nk = 0;
   int precision = ELPH_FP64;
   double mu = 0, window = 0, sigma = 0, omega_min = 1e-4;
+  // operand scales of the FP16 split form (powers of two; 1 in the other
+  // forms): A_e, A_p, gR, B2
+  double sc_ae = 1, sc_ap = 1, sc_g = 1, sc_b2 = 1;
   double lat[9];
   double volume_A3 = 0;
   std::vector<double> mass;

@@ -71,6 +71,15 @@ struct Mfma<float> {
 template <int NS>
 struct Bf16S {};
 
+// FP16 split form: the same layout with FP16 parts (a_1 = f16(a),
+// a_2 = f16(a - a_1): 22 significant bits with NS = 2).  FP16's exponent
+// range is narrow, so every operand carries a power-of-two scale that puts
+// its largest possible magnitude at 2^12-2^13; the second part of any value
+// within 2^-16 of that bound is then a normal FP16 number.  The epilogues
+// undo the scales exactly.
+template <int NS>
+struct F16S {};
+
 template <typename T>
 struct Store {
   typedef T type;
@@ -83,8 +92,11 @@ struct Store<Bf16S<NS>> {
   static constexpr int per_c = 2 * NS;
   static constexpr int kalign = 32;
 };
+template <int NS>
+struct Store<F16S<NS>> : Store<Bf16S<NS>> {};
 
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef unsigned short us8v __attribute__((ext_vector_type(8)));
 
 template <int NS>
@@ -98,6 +110,19 @@ struct Mfma<Bf16S<NS>> {
   __device__ static inline int row(int lk, int r) { return 4 * lk + r; }
   static constexpr bool kFold = true;
 };
+
+template <int NS>
+struct Mfma<F16S<NS>> : Mfma<Bf16S<NS>> {
+  typedef f4 acc_t;
+  __device__ static inline acc_t mma(us8v a, us8v b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a), __builtin_bit_cast(h8v, b), c, 0, 0,
+                                                 0);
+  }
+};
+
+// FP16 nearest of a double (through its float value) and back
+__device__ inline unsigned short f16_of(double v) { return __builtin_bit_cast(unsigned short, (_Float16)(float)v); }
+__device__ inline double f16_val(unsigned short h) { return (double)(float)__builtin_bit_cast(_Float16, h); }
 
 // BF16 nearest (ties to even) of a double, through its float value
 __device__ inline unsigned short bf16_of(double v) {
@@ -114,17 +139,17 @@ __device__ inline void put_c(typename Store<T>::type* base, int64_t row, int64_t
   base[2 * (row * K + k) + 1] = (T)im;
 }
 
-template <int NS>
+template <int NS, bool F16 = false>
 __device__ inline void put_split(unsigned short* base, int64_t row, int64_t K, int64_t k, double re, double im) {
   unsigned short* g = base + row * K * 2 * NS + (k >> 3) * (16 * NS) + (k & 7);
   double r = re, i = im;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const unsigned short hr = bf16_of(r), hi = bf16_of(i);
+    const unsigned short hr = F16 ? f16_of(r) : bf16_of(r), hi = F16 ? f16_of(i) : bf16_of(i);
     g[(2 * s) * 8] = hr;
     g[(2 * s + 1) * 8] = hi;
-    r -= bf16_val(hr);
-    i -= bf16_val(hi);
+    r -= F16 ? f16_val(hr) : bf16_val(hr);
+    i -= F16 ? f16_val(hi) : bf16_val(hi);
   }
 }
 
@@ -141,15 +166,21 @@ struct PutC<Bf16S<NS>> {
     put_split<NS>(base, row, K, k, re, im);
   }
 };
+template <int NS>
+struct PutC<F16S<NS>> {
+  __device__ static inline void put(unsigned short* base, int64_t row, int64_t K, int64_t k, double re, double im) {
+    put_split<NS, true>(base, row, K, k, re, im);
+  }
+};
 
 // Products of a split complex fragment pair, smallest terms first:
 // cr += Re(a) Re(b) - Im(a) Im(b), ci += Re(a) Im(b) + Im(a) Re(b), keeping
 // the split pairs (s_a, s_b) with s_a + s_b <= 1 (NS = 2: three products)
 // or <= 2 (NS = 3: six products).
-template <int NS>
+template <class SP, int NS>
 __device__ inline void split_cmma(const us8v (&a)[2 * NS], const us8v (&na_im)[NS], const us8v (&b)[2 * NS], f4& cr,
                                   f4& ci) {
-  typedef Mfma<Bf16S<NS>> MM;
+  typedef Mfma<SP> MM;
   constexpr int np = NS == 2 ? 3 : 6;
 #pragma unroll
   for (int t = 0; t < np; ++t) {
@@ -203,7 +234,7 @@ __device__ inline Cplx<T> ldc(const T* p) {
 template <typename T>
 __global__ void k_build_Ae(int64_t nstates, int nb, int nre, int64_t ke, const int32_t* __restrict__ st_kidx,
                            const int32_t* __restrict__ st_m, const cd* __restrict__ Ee, const cd* __restrict__ U,
-                           typename Store<T>::type* __restrict__ Ae) {
+                           double scale, typename Store<T>::type* __restrict__ Ae) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t cols = (int64_t)nre * nb;
   if (e >= nstates * cols) return;
@@ -212,13 +243,13 @@ __global__ void k_build_Ae(int64_t nstates, int nb, int nre, int64_t ke, const i
   int r = (int)(col / nb), mp = (int)(col % nb);
   int t = st_kidx[i], m = st_m[i];
   cd z = cmul(Ee[(int64_t)t * nre + r], U[((int64_t)t * nb + mp) * nb + m]);
-  PutC<T>::put(Ae, i, ke, col, z.x, z.y);
+  PutC<T>::put(Ae, i, ke, col, z.x * scale, z.y * scale);
 }
 
 template <typename T>
 __global__ void k_build_Ap(int64_t nstates, int nb, int nrp, int64_t kp, const int32_t* __restrict__ st_kidx,
                            const int32_t* __restrict__ st_m, const cd* __restrict__ Ep,
-                           const double* __restrict__ wrp, const cd* __restrict__ U,
+                           const double* __restrict__ wrp, const cd* __restrict__ U, double scale,
                            typename Store<T>::type* __restrict__ Ap) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t cols = (int64_t)nrp * nb;
@@ -229,13 +260,13 @@ __global__ void k_build_Ap(int64_t nstates, int nb, int nrp, int64_t kp, const i
   int t = st_kidx[j], n = st_m[j];
   cd z = cmul(Ep[(int64_t)t * nrp + r], cconj(U[((int64_t)t * nb + np) * nb + n]));
   if (wrp) z = cscale(z, wrp[r]);
-  PutC<T>::put(Ap, j, kp, col, z.x, z.y);
+  PutC<T>::put(Ap, j, kp, col, z.x * scale, z.y * scale);
 }
 
 // gR[(x, Rp, n')][(Re, m')] = g[Re][Rp][x][n'][m']
 template <typename T>
 __global__ void k_permute_g(int nre, int nrp, int nbr, int nb, int64_t ke, const double* __restrict__ g,
-                            typename Store<T>::type* __restrict__ gR) {
+                            double scale, typename Store<T>::type* __restrict__ gR) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)nre * nrp * nbr * nb * nb;
   if (e >= total) return;
@@ -249,7 +280,7 @@ __global__ void k_permute_g(int nre, int nrp, int nbr, int nb, int64_t ke, const
   int re = (int)(t / nrp);
   int64_t row = ((int64_t)x * nrp + rp) * nb + np;
   int64_t col = (int64_t)re * nb + mp;
-  PutC<T>::put(gR, row, ke, col, g[2 * e], g[2 * e + 1]);
+  PutC<T>::put(gR, row, ke, col, g[2 * e] * scale, g[2 * e + 1] * scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -275,6 +306,11 @@ struct IsSplit {
 };
 template <int NS>
 struct IsSplit<Bf16S<NS>> {
+  static constexpr bool value = true;
+  static constexpr int ns = NS;
+};
+template <int NS>
+struct IsSplit<F16S<NS>> {
   static constexpr bool value = true;
   static constexpr int ns = NS;
 };
@@ -334,7 +370,7 @@ __device__ __forceinline__ void step1_tile(const S1Desc<T>& d, int64_t bx, int64
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) split_cmma<NS>(fa[a], na[a], fb[b], cr[a][b], ci[a][b]);
+        for (int b = 0; b < 2; ++b) split_cmma<T, NS>(fa[a], na[a], fb[b], cr[a][b], ci[a][b]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -454,6 +490,7 @@ struct EpiParams {
   double* wph_acc;           // [nk][nbr]
   int64_t m_pad;
   const uint8_t* tile_keep;  // [m_pad/32][m_pad/32] computed tiles (null = all)
+  double cscale;             // undoes the operand scales of the step-2 contraction (1 but in the FP16 form)
 };
 
 __device__ inline int q_of(int kj, int ki, int n0, int n1, int n2) {
@@ -540,7 +577,7 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
       for (int x = 0; x < NX; ++x) {
         us8v fb[2 * NS];
         load_split<NS>(pb + x * kp * 2 * NS + go, fb);
-        split_cmma<NS>(fa, na, fb, cr[x], ci[x]);
+        split_cmma<T, NS>(fa, na, fb, cr[x], ci[x]);
       }
 #pragma unroll
       for (int x = 0; x < NX; ++x) {
@@ -614,11 +651,11 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
           const cd l = L[x * NX + s];
           double ar, ai;
           if constexpr (MM::kFold) {
-            ar = fr[x][r];
-            ai = fi[x][r];
+            ar = fr[x][r] * ep.cscale;
+            ai = fi[x][r] * ep.cscale;
           } else {
-            ar = (double)cr[x][r];
-            ai = (double)ci[x][r];
+            ar = (double)cr[x][r] * ep.cscale;
+            ai = (double)ci[x][r] * ep.cscale;
           }
           gr += l.x * ar - l.y * ai;
           gi += l.x * ai + l.y * ar;
@@ -685,16 +722,20 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 // the copies stay in registers
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int NS>
+template <bool F16>
 __device__ inline f16v mma32(us8v a, us8v b, f16v c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0, 0,
-                                                 0);
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8v, a), __builtin_bit_cast(h8v, b), c, 0, 0,
+                                                  0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0, 0,
+                                                   0);
 }
 
 // One 16-k slice of the complex product on a 32 x 32 tile: the real part's
 // two terms go to separate accumulators (cr += a_re b_re, cn += a_im b_im,
 // subtracted when folded), so no operand needs negating.
-template <int NS>
+template <int NS, bool F16>
 __device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&b)[2 * NS], f16v& cr, f16v& cn,
                                     f16v& ci) {
   constexpr int np = NS == 2 ? 3 : 6;
@@ -708,18 +749,18 @@ __device__ inline void split_cmma32(const us8v (&a)[2 * NS], const us8v (&b)[2 *
       sa = t == 0 ? 1 : t == 2 ? 2 : t == 4 ? 1 : 0;
       sb = t == 0 ? 1 : t == 1 ? 2 : t == 3 ? 1 : 0;
     }
-    cr = mma32<NS>(a[2 * sa], b[2 * sb], cr);
-    cn = mma32<NS>(a[2 * sa + 1], b[2 * sb + 1], cn);
-    ci = mma32<NS>(a[2 * sa], b[2 * sb + 1], ci);
-    ci = mma32<NS>(a[2 * sa + 1], b[2 * sb], ci);
+    cr = mma32<F16>(a[2 * sa], b[2 * sb], cr);
+    cn = mma32<F16>(a[2 * sa + 1], b[2 * sb + 1], cn);
+    ci = mma32<F16>(a[2 * sa], b[2 * sb + 1], ci);
+    ci = mma32<F16>(a[2 * sa + 1], b[2 * sb], ci);
   }
 }
 
 // Operand formats, in 16-bit words per 32-k stage of a row (kRowU).
-// OpSplit<NS>: BF16 planes (groups of 8 k, each holding re/im of the NS
-// parts), 32x32x16 BF16 MFMA; lanes 0-31 take the first 8 k of each 16,
-// lanes 32-63 the next 8.
-template <int NS>
+// OpSplit<NS, F16>: BF16 (or FP16) planes (groups of 8 k, each holding re/im
+// of the NS parts), 32x32x16 BF16 (FP16) MFMA; lanes 0-31 take the first 8 k
+// of each 16, lanes 32-63 the next 8.
+template <int NS, bool F16 = false>
 struct OpSplit {
   static constexpr int kRowU = 64 * NS;
   __device__ static inline void mac(const unsigned short* arow, const unsigned short* brow, int lh, f16v& cr,
@@ -733,7 +774,7 @@ struct OpSplit {
         a[p] = *reinterpret_cast<const us8v*>(arow + gofs + 8 * p);
         b[p] = *reinterpret_cast<const us8v*>(brow + gofs + 8 * p);
       }
-      split_cmma32<NS>(a, b, cr, cn, ci);
+      split_cmma32<NS, F16>(a, b, cr, cn, ci);
     }
   }
 };
@@ -975,6 +1016,10 @@ template <int NS>
 struct GemmOp<Bf16S<NS>> {
   typedef OpSplit<NS> type;
 };
+template <int NS>
+struct GemmOp<F16S<NS>> {
+  typedef OpSplit<NS, true> type;
+};
 template <>
 struct GemmOp<float> {
   typedef OpF32 type;
@@ -1018,8 +1063,8 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
 #pragma unroll
         for (int x = 0; x < NX; ++x) {
           const float2 v = *reinterpret_cast<const float2*>(cg + 2 * x);
-          ar[x] = v.x;
-          ai[x] = v.y;
+          ar[x] = (double)v.x * ep.cscale;
+          ai[x] = (double)v.y * ep.cscale;
         }
         const double de = ep.eps[j] - ei;
         const int64_t tb = ((int64_t)i * ep.nstates + j) * NX;
@@ -1053,7 +1098,7 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
 template <typename T>
 __global__ void k_step1_epi(int64_t i0, int64_t ni, int64_t ncol, int nrp, int nb, int nbr, int64_t kp,
                             const float* __restrict__ C1, const int32_t* __restrict__ st_kidx,
-                            const cd* __restrict__ Ep, typename Store<T>::type* __restrict__ B2) {
+                            const cd* __restrict__ Ep, double scale, typename Store<T>::type* __restrict__ B2) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ni * ncol) return;
   const int64_t il = e / ncol, col = e - il * ncol;
@@ -1064,7 +1109,7 @@ __global__ void k_step1_epi(int64_t i0, int64_t ni, int64_t ncol, int nrp, int n
   const int rp = (int)(rem / nb);
   const float2 v = *reinterpret_cast<const float2*>(C1 + 2 * e);
   const cd z = cmulc(cmake(v.x, v.y), Ep[(int64_t)st_kidx[i] * nrp + rp]);  // * conj(phase)
-  PutC<T>::put(B2, i * nbr + x, kp, rem, z.x, z.y);
+  PutC<T>::put(B2, i * nbr + x, kp, rem, z.x * scale, z.y * scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -1199,13 +1244,13 @@ static elph_status build_operands_t(elph_ctx ctx) {
   }
   hipLaunchKernelGGL(k_build_Ae<T>, dim3(blocks_for(M * ctx->nre * nb, 256)), dim3(256), 0, s, M, nb, ctx->nre,
                      ctx->ke, ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_Ee, (const cd*)ctx->d_U,
-                     (SE*)ae);
+                     ctx->sc_ae, (SE*)ae);
   hipLaunchKernelGGL(k_build_Ap<T>, dim3(blocks_for(M * ctx->nrp * nb, 256)), dim3(256), 0, s, M, nb, ctx->nrp,
                      ctx->kp, ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_Ep, ctx->d_wrp,
-                     (const cd*)ctx->d_U, (SE*)ap);
+                     (const cd*)ctx->d_U, ctx->sc_ap, (SE*)ap);
   const int64_t gtotal = (int64_t)ctx->nre * ctx->nrp * nbr * nb * nb;
   hipLaunchKernelGGL(k_permute_g<T>, dim3(blocks_for(gtotal, 256)), dim3(256), 0, s, ctx->nre, ctx->nrp, nbr, nb,
-                     ctx->ke, ctx->d_gr, (SE*)gr);
+                     ctx->ke, ctx->d_gr, ctx->sc_g, (SE*)gr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     ctx->err = std::string("kernel launch failed: ") + hipGetErrorString(e);
@@ -1222,6 +1267,7 @@ elph_status build_operands(elph_ctx ctx) {
   if (ctx->precision == ELPH_FP32) return build_operands_t<float>(ctx);
   if (ctx->precision == ELPH_BF16X3) return build_operands_t<Bf16S<2>>(ctx);
   if (ctx->precision == ELPH_BF16X6) return build_operands_t<Bf16S<3>>(ctx);
+  if (ctx->precision == ELPH_FP16X3) return build_operands_t<F16S<2>>(ctx);
   ctx->err = "precision form not available";
   return ELPH_EINVAL;
 }
@@ -1273,7 +1319,8 @@ static elph_status launch_step1_t(elph_ctx ctx) {
       launch_cgemm<OP, 1>(ctx->stream, i0, ni, ncol, ctx->ke, 1, ctx->d_Ae, ctx->d_gR, (float*)p, ncol);
       hipLaunchKernelGGL(k_step1_epi<T>, dim3(blocks_for(ni * ncol, 256)), dim3(256), 0, ctx->stream, i0, ni, ncol,
                          ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, (const float*)p, ctx->d_state_kidx,
-                         (const cd*)ctx->d_Ep, (typename Store<T>::type*)ctx->d_B2);
+                         (const cd*)ctx->d_Ep, ctx->sc_b2 / (ctx->sc_ae * ctx->sc_g),
+                         (typename Store<T>::type*)ctx->d_B2);
     }
     dev_free(ctx, p);
     return ELPH_OK;
@@ -1390,6 +1437,7 @@ static EpiParams epi_params(elph_ctx ctx) {
   ep.we_part = nullptr;
   ep.wph_acc = nullptr;
   ep.tile_keep = ctx->d_tile_keep;
+  ep.cscale = 1.0 / (ctx->sc_b2 * ctx->sc_ap);
   return ep;
 }
 
@@ -1443,7 +1491,16 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     mark(ctx, 3);
     mark(ctx, 4);
     st = store_f64 ? launch_step2_t<float, double>(ctx, ep, Bp, Bm, &we_tiles) : launch_step2_t<float, float>(ctx, ep, Bp, Bm, &we_tiles);
-    mark(ctx, 5);
+    if (ep.tile_keep) mark(ctx, 5);  // the GEMM path marks its own window (the contraction)
+  } else if (ctx->precision == ELPH_FP16X3) {
+    mark(ctx, 2);
+    st = launch_step1_t<F16S<2>>(ctx);
+    if (st != ELPH_OK) return st;
+    mark(ctx, 3);
+    mark(ctx, 4);
+    st = store_f64 ? launch_step2_t<F16S<2>, double>(ctx, ep, Bp, Bm, &we_tiles)
+                   : launch_step2_t<F16S<2>, float>(ctx, ep, Bp, Bm, &we_tiles);
+    if (ep.tile_keep) mark(ctx, 5);
   } else if (ctx->precision == ELPH_BF16X3) {
     mark(ctx, 2);
     st = launch_step1_t<Bf16S<2>>(ctx);
@@ -1777,7 +1834,7 @@ static elph_status batch_sequence_gemm(BatchImpl* b, double T_K, double* const* 
     const int64_t M = c->nstates, ncol = (int64_t)c->nbr * c->nrp * c->nb;
     hipLaunchKernelGGL(k_step1_epi<T>, dim3(blocks_for(M * ncol, 256)), dim3(256), 0, b->stream, (int64_t)0, M, ncol,
                        c->nrp, c->nb, c->nbr, c->kp, (const float*)b->c1[m], c->d_state_kidx, (const cd*)c->d_Ep,
-                       (typename Store<T>::type*)c->d_B2);
+                       c->sc_b2 / (c->sc_ae * c->sc_g), (typename Store<T>::type*)c->d_B2);
   }
   hipLaunchKernelGGL((k_cgemm_persist<OP, 2, kGemmWR>), dim3((unsigned)std::min<int64_t>(n2, (int64_t)b->bpc * b->ncu)),
                      dim3(128 * kGemmWR), 0, b->stream, (const GemmArgs*)b->d_g2, b->d_g2items, n2,

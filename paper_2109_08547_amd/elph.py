@@ -14,9 +14,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libelph.so")
 
 ELPH_OK, ELPH_EINVAL, ELPH_ENOMEM, ELPH_EHIP, ELPH_ENOCONV, ELPH_ESTATE = range(6)
-ELPH_FP64, ELPH_FP32, ELPH_BF16X3, ELPH_BF16X6 = range(4)
+ELPH_FP64, ELPH_FP32, ELPH_BF16X3, ELPH_BF16X6, ELPH_FP16X3 = range(5)
 ELPH_LEVEL_RTA, ELPH_LEVEL_PARTIAL, ELPH_LEVEL_DRAGLESS, ELPH_LEVEL_COUPLED = range(4)
-PRECISIONS = {"fp64": ELPH_FP64, "fp32": ELPH_FP32, "bf16x3": ELPH_BF16X3, "bf16x6": ELPH_BF16X6}
+PRECISIONS = {"fp64": ELPH_FP64, "fp32": ELPH_FP32, "bf16x3": ELPH_BF16X3, "bf16x6": ELPH_BF16X6,
+              "fp16x3": ELPH_FP16X3}
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_f64p = ctypes.POINTER(ctypes.c_double)
