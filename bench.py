@@ -52,11 +52,11 @@ WORKLOADS = {
 
 
 def stored_traffic(form, workload):
-    """HBM bytes per launch of the step-2 split GEMM from the committed
+    """HBM bytes per launch of the form's step-2 GEMM from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None
     when the kernel source has changed since the counters were taken or the
-    summary covers another form or workload."""
-    if form != "bf16x6" or workload != "mixed48":
+    summary does not cover this form and workload."""
+    if workload != "mixed48":
         return None
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_cgemm_mixed48_counters.md")
@@ -66,10 +66,12 @@ def stored_traffic(form, workload):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
-    if vals.get("source_sha256", "").strip() != sha:
+    vals = dict(l.split(": ", 1) for l in text.splitlines()
+                if l.startswith(("traffic_bytes_per_launch[", "source_sha256:")))
+    key = "traffic_bytes_per_launch[%s]" % form
+    if vals.get("source_sha256", "").strip() != sha or key not in vals:
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return float(vals[key])
 
 
 def rate_err(w, ref, floor=1e-12):
