@@ -329,7 +329,7 @@ def main():
                          "bytes are known, to scale the byte counters of a profiled run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (the path would shard by kept-k rows across GPUs; "
+        print("bench.py: the library runs on one GPU (the path would shard by kept-k rows across GPUs; "
               "see the design notes); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

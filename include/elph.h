@@ -262,8 +262,8 @@ elph_status elph_batch_tune(elph_batch b, double T_K, int32_t* choice, double* b
  * the exact Gaussian delta and occupations of Eq. 8 this gives a predicted
  * X of every term, and the step-2 tiles whose predicted terms all lie below
  * tau times the largest predicted term of their initial state are skipped.
- * The exact path stays the judge: callers compare the screened rates with
- * elph_scatt_rates.
+ * The exact path remains the reference: callers compare the screened rates
+ * with elph_scatt_rates.
  *
  * Network: depth hidden layers of `width` units, z = a W + b, a = GELU(z)
  * (z Phi(z), Phi the normal CDF), output y = a w + b; loss = mean squared
