@@ -37,14 +37,16 @@ elph_status iterate(elph_ctx ctx, double T, const double* wext, int level, doubl
 
 // electron self-consistency solver (solve.hip)
 struct SelfSolver {
-  void* KT = nullptr;                   // [M][M] transposed, group-projected self operator (FP64 or FP32)
+  void* KT = nullptr;                   // [M][ldk] transposed, group-projected self operator (FP64 or FP32)
   bool kt_f32 = false;
-  double *b = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
+  double *b = nullptr, *r = nullptr, *rh = nullptr, *s = nullptr, *t = nullptr;
+  double *p = nullptr, *p2 = nullptr, *v = nullptr, *v2 = nullptr;  // p and v alternate between two buffers
   double* part = nullptr;               // [S][M][6] split partials of the matrix-vector product
   double* dpart = nullptr;              // [nblk][12] dot partials
+  double* dxr = nullptr;                // [nblk][12] dot partials of the x, r update
   double* sc = nullptr;                 // device scalars
-  int S = 1, nblk = 1;
-  int64_t jlen = 1;
+  int S = 1, nblk = 1, nt = 1;          // j splits, vector-kernel blocks, row tiles
+  int64_t jlen = 1, ldk = 1;            // rows per split; row stride of K^T
 };
 size_t self_solver_doubles(int64_t M, bool kt_f32);
 void self_solver_carve(int64_t M, bool kt_f32, double* base, SelfSolver* sv);
