@@ -1,4 +1,4 @@
-// Internal device helpers shared by the rate and solver kernels.
+// Internal device helpers shared by the vertex, rate and solver kernels.
 #pragma once
 #include "common.h"
 
@@ -58,5 +58,37 @@ __device__ inline void block_sum(double (&v)[NV], double* sh) {
 struct MeshDims {
   int n0, n1, n2;
 };
+
+// Two adjacent values of T as one 8- or 16-byte access
+template <typename T>
+struct Two;
+template <>
+struct Two<float> {
+  typedef float2 type;
+};
+template <>
+struct Two<double> {
+  typedef double2 type;
+};
+
+// v[0..N) converted to T and stored at p, in pairs when N is even (p is
+// then aligned to two elements, as every row of N elements of an array of T
+// is)
+template <typename T, int N>
+__device__ inline void store_row(T* p, const double (&v)[N]) {
+  if constexpr (N % 2 == 0) {
+    typedef typename Two<T>::type T2;
+#pragma unroll
+    for (int s = 0; s < N; s += 2) {
+      T2 w;
+      w.x = (T)v[s];
+      w.y = (T)v[s + 1];
+      *reinterpret_cast<T2*>(p + s) = w;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < N; ++s) p[s] = (T)v[s];
+  }
+}
 
 }  // namespace elph

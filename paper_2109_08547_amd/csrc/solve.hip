@@ -195,17 +195,6 @@ __global__ void __launch_bounds__(kVB) k_bi_scal(int mode, int nblk, const doubl
 // launch, reduced by every block alike and stored by the first.
 enum { KMV_PLAIN = 0, KMV_P = 1, KMV_S = 2 };
 
-template <typename KS>
-struct Two;
-template <>
-struct Two<float> {
-  typedef float2 type;
-};
-template <>
-struct Two<double> {
-  typedef double2 type;
-};
-
 // part[split][i][c] = sum_{j in split} K^T[j][i] in[j][c] for the in of MODE.
 // Grid = (row tiles of kKmvRows states) x (S splits of the j range).  A block
 // takes two adjacent states per lane; its four wavefronts take every fourth

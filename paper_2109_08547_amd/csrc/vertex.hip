@@ -21,6 +21,7 @@
 // MFMA 16x16x4 operand layout (f64 and f32): lane l supplies A[row l%16][k l/16]
 // and B[k l/16][col l%16]; accumulator r of lane l holds column l%16 and row
 // l/16 + 4r (f64) or 4(l/16) + r (f32).
+#include "devutil.h"
 #include "vertex.h"
 #include "tables.h"
 
@@ -1068,6 +1069,7 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
         }
         const double de = ep.eps[j] - ei;
         const int64_t tb = ((int64_t)i * ep.nstates + j) * NX;
+        double bpv[NX], bmv[NX];
 #pragma unroll
         for (int s = 0; s < NX; ++s) {
           double gr = 0.0, gi = 0.0;
@@ -1085,9 +1087,11 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
             bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
             bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
           }
-          Bp[tb + s] = (ST)bp;
-          Bm[tb + s] = (ST)bm;
+          bpv[s] = bp;
+          bmv[s] = bm;
         }
+        store_row<ST, NX>(Bp + tb, bpv);
+        store_row<ST, NX>(Bm + tb, bmv);
       }
     }
   }
