@@ -81,6 +81,8 @@ struct elph_ctx_s {
   double* d_mass_x = nullptr;  // [nbr] mass of the atom of each x
   double* d_lat = nullptr;   // [9]
   double2* d_tab[3] = {nullptr, nullptr, nullptr};  // per-axis exp(2 pi i j / N)
+  int32_t* d_qrep = nullptr;                          // mesh points q with q <= -q (one of each +-q pair)
+  int64_t nqrep = 0;
 
   // tables
   bool tables_ready = false;

@@ -5,11 +5,14 @@
 //    16 x 16 (eigenvalues ascending, eigenvectors as columns),
 //  * the transport window and its compaction into kept k and active states,
 //  * band and branch velocities (Eqs. 2 and 5) and the phonon factors of
-//    Eq. 6 (l_{x,s} u_q[x,s], with l = sqrt(C / (2 M hbar omega))).
+//    Eq. 6 (l_{x,s} u_q[x,s], with l = sqrt(C / (2 M hbar omega))), the
+//    phonons diagonalised at one q of each +-q pair (time reversal).
+#include "devutil.h"
 #include "tables.h"
 
 #include <algorithm>
 #include <utility>
+#include <vector>
 
 namespace elph {
 
@@ -401,21 +404,21 @@ void scan_exclusive(elph_ctx ctx, const int32_t* in, int64_t n, int32_t* out, in
                     int32_t* scratch, hipStream_t s) {
   int64_t nblk = (n + 1023) / 1024;
   if (nblk == 0) {
-    hipMemsetAsync(out_total, 0, sizeof(int32_t), s);
+    (void)hipMemsetAsync(out_total, 0, sizeof(int32_t), s);  // errors surface at the caller's next check
     return;
   }
   int32_t* bsum = scratch;          // [nblk]
   int32_t* bpref = scratch + nblk;  // [nblk]
   hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nblk), dim3(1024), 0, s, in, n, out, bsum);
   if (nblk == 1) {
-    hipMemsetAsync(bpref, 0, sizeof(int32_t), s);
-    hipMemcpyAsync(out_total, bsum, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    (void)hipMemsetAsync(bpref, 0, sizeof(int32_t), s);
+    (void)hipMemcpyAsync(out_total, bsum, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
     return;
   }
   int32_t* tot2 = scratch + 2 * nblk;
   scan_exclusive(ctx, bsum, nblk, bpref, tot2, scratch + 2 * nblk + 1, s);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nblk), dim3(1024), 0, s, out, n, bpref);
-  hipMemcpyAsync(out_total, tot2, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+  (void)hipMemcpyAsync(out_total, tot2, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
 }
 
 __global__ void k_compact_kept(const int32_t* __restrict__ flag, const int32_t* __restrict__ pos, int64_t nk,
@@ -513,34 +516,58 @@ __global__ void k_electron_vel(int64_t nkept, int nb, const double* __restrict__
 // Phonon factors per element: hbar omega_s = sqrt(C max(lambda_s, 0)) and
 // Lq[q][x][s] = l_{x,s} u_q[x][s] with l = sqrt(C / (2 M_x hbar omega_s))
 // (zero for modes below omega_min); thread per (q, x, s).
-__global__ void k_phonon_hw_L(int64_t nq, int nbr, const double* __restrict__ lam, const cd* __restrict__ u,
+// Mesh index of -q
+__device__ inline int64_t mesh_neg(int64_t q, int n0, int n1, int n2) {
+  const int64_t c = q % n2, t = q / n2;
+  const int64_t b = t % n1, a = t / n1;
+  return ((a ? n0 - a : 0) * n1 + (b ? n1 - b : 0)) * n2 + (c ? n2 - c : 0);
+}
+
+// The force constants are real, so D(-q) = D(q)^* (time reversal): the
+// modes at -q are those at q with conjugated eigenvectors, the same
+// frequencies and opposite velocities.  The phonon tables are therefore
+// diagonalised at one q of each +-q pair (pts) and written at both.
+
+// hbar omega = sqrt(C lambda) and L[q][x][s] = u_xs sqrt(C / (2 M_x omega))
+// (Eq. 6 prefactor); thread per (point, x, s) of the chunk, also written at -q
+__global__ void k_phonon_hw_L(int64_t nq, int nbr, MeshDims md, const int32_t* __restrict__ pts,
+                              const double* __restrict__ lam, const cd* __restrict__ u,
                               const double* __restrict__ mass_x, double omega_min, double* __restrict__ hw,
                               cd* __restrict__ Lq) {
   const int64_t nn = (int64_t)nbr * nbr;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nq * nn) return;
-  const int64_t q = e / nn;
-  const int xs = (int)(e - q * nn), x = xs / nbr, s = xs - x * nbr;
-  const double l = lam[q * nbr + s];
+  const int64_t p = e / nn;
+  const int xs = (int)(e - p * nn), x = xs / nbr, s = xs - x * nbr;
+  const int64_t q = pts[p], mq = mesh_neg(q, md.n0, md.n1, md.n2);
+  const double l = lam[p * nbr + s];
   const double w = sqrt(kPhononC * (l > 0.0 ? l : 0.0));
+  const cd L = (w >= omega_min) ? cscale(u[e], sqrt(kPhononC / (2.0 * mass_x[x] * w))) : cmake(0.0, 0.0);
   if (x == 0) hw[q * nbr + s] = w;
-  Lq[e] = (w >= omega_min) ? cscale(u[e], sqrt(kPhononC / (2.0 * mass_x[x] * w))) : cmake(0.0, 0.0);
+  Lq[q * nn + xs] = L;
+  if (mq != q) {
+    if (x == 0) hw[mq * nbr + s] = w;
+    Lq[mq * nn + xs] = cconj(L);
+  }
 }
 
 // Branch velocities (Eq. 5) v_c = (C / (2 hbar omega)) u_s^+ (dD/dq_c) u_s / hbar
-// before degenerate averaging; thread per (q, c, s), result in vph.
-__global__ void k_phonon_vel(int64_t nq, int nbr, const double* __restrict__ hw, const cd* __restrict__ u,
-                             const cd* __restrict__ dD, double omega_min, double* __restrict__ vph) {
+// before degenerate averaging; thread per (point, c, s) of the chunk, result
+// in vph at q = pts[point].
+__global__ void k_phonon_vel(int64_t nq, int nbr, const int32_t* __restrict__ pts, const double* __restrict__ hw,
+                             const cd* __restrict__ u, const cd* __restrict__ dD, double omega_min,
+                             double* __restrict__ vph) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nq * 3 * nbr) return;
-  const int64_t q = e / (3 * nbr);
-  const int cs = (int)(e - q * 3 * nbr), c = cs / nbr, s = cs - c * nbr;
+  const int64_t p = e / (3 * nbr);
+  const int cs = (int)(e - p * 3 * nbr), c = cs / nbr, s = cs - c * nbr;
   const int64_t nn = (int64_t)nbr * nbr;
+  const int64_t q = pts[p];
   const double w = hw[q * nbr + s];
   double acc = 0.0;
   if (w >= omega_min) {
-    const cd* d = dD + (q * 3 + c) * nn;
-    const cd* uq = u + q * nn;
+    const cd* d = dD + (p * 3 + c) * nn;
+    const cd* uq = u + p * nn;
     for (int a = 0; a < nbr; ++a) {
       cd row = cmake(0, 0);
       for (int b = 0; b < nbr; ++b) row = cadd(row, cmul(d[a * nbr + b], uq[b * nbr + s]));
@@ -551,11 +578,13 @@ __global__ void k_phonon_vel(int64_t nq, int nbr, const double* __restrict__ hw,
   vph[(q * nbr + s) * 3 + c] = acc;
 }
 
-// Average the branch velocities over groups of (near-)degenerate branches.
-__global__ void k_phonon_degen(int64_t nq, int nbr, const double* __restrict__ hw, double degen,
-                               double* __restrict__ vph) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+// Average the branch velocities at q = pts[point] over groups of
+// (near-)degenerate branches, then write their negatives at -q.
+__global__ void k_phonon_degen(int64_t nq, int nbr, MeshDims md, const int32_t* __restrict__ pts,
+                               const double* __restrict__ hw, double degen, double* __restrict__ vph) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nq) return;
+  const int64_t q = pts[p], mq = mesh_neg(q, md.n0, md.n1, md.n2);
   const double* w = hw + q * nbr;
   double* v = vph + q * nbr * 3;
   int start = 0;
@@ -571,6 +600,10 @@ __global__ void k_phonon_degen(int64_t nq, int nbr, const double* __restrict__ h
       }
       start = b;
     }
+  }
+  if (mq != q) {
+    double* vm = vph + mq * nbr * 3;
+    for (int e = 0; e < nbr * 3; ++e) vm[e] = -v[e];
   }
 }
 
@@ -704,16 +737,18 @@ elph_status build_tables(elph_ctx ctx) {
   cd* ubuf = nullptr;
   ALLOC(lam, chunk * nbr * sizeof(double));
   ALLOC(ubuf, chunk * (int64_t)nbr * nbr * sizeof(cd));
-  for (int64_t q0 = 0; q0 < nk; q0 += chunk) {
-    int64_t cnt = (nk - q0 < chunk) ? nk - q0 : chunk;
-    launch_fourier<true, true>(ctx, nullptr, q0, cnt, ctx->d_rp, ctx->d_wrp, ctx->nrp, ctx->d_dr, nbr, hbuf, gbuf);
+  const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
+  for (int64_t r0 = 0; r0 < ctx->nqrep; r0 += chunk) {
+    const int64_t cnt = (ctx->nqrep - r0 < chunk) ? ctx->nqrep - r0 : chunk;
+    const int32_t* pts = ctx->d_qrep + r0;  // one q of each +-q pair; -q follows by time reversal
+    launch_fourier<true, true>(ctx, pts, 0, cnt, ctx->d_rp, ctx->d_wrp, ctx->nrp, ctx->d_dr, nbr, hbuf, gbuf);
     launch_jacobi(hbuf, cnt, nbr, lam, ubuf, s);
-    hipLaunchKernelGGL(k_phonon_hw_L, dim3(blocks_for(cnt * nbr * nbr, 256)), dim3(256), 0, s, cnt, nbr, lam, ubuf,
-                       ctx->d_mass_x, ctx->omega_min, ctx->d_hw + q0 * nbr, (cd*)ctx->d_Lq + q0 * nbr * nbr);
-    hipLaunchKernelGGL(k_phonon_vel, dim3(blocks_for(cnt * 3 * nbr, 256)), dim3(256), 0, s, cnt, nbr,
-                       ctx->d_hw + q0 * nbr, ubuf, gbuf, ctx->omega_min, ctx->d_vph + q0 * nbr * 3);
-    hipLaunchKernelGGL(k_phonon_degen, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, cnt, nbr, ctx->d_hw + q0 * nbr,
-                       1.0e-6, ctx->d_vph + q0 * nbr * 3);
+    hipLaunchKernelGGL(k_phonon_hw_L, dim3(blocks_for(cnt * nbr * nbr, 256)), dim3(256), 0, s, cnt, nbr, md, pts,
+                       lam, ubuf, ctx->d_mass_x, ctx->omega_min, ctx->d_hw, (cd*)ctx->d_Lq);
+    hipLaunchKernelGGL(k_phonon_vel, dim3(blocks_for(cnt * 3 * nbr, 256)), dim3(256), 0, s, cnt, nbr, pts,
+                       ctx->d_hw, ubuf, gbuf, ctx->omega_min, ctx->d_vph);
+    hipLaunchKernelGGL(k_phonon_degen, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, cnt, nbr, md, pts, ctx->d_hw,
+                       1.0e-6, ctx->d_vph);
   }
   HIPCHK(hipGetLastError());
 
@@ -759,6 +794,20 @@ elph_status make_axis_tables(elph_ctx ctx) {
                        ctx->mesh[d], ctx->d_tab[d]);
   }
   HIPCHK(hipGetLastError());
+  // one q of each +-q pair of the mesh (the smaller mesh index)
+  const int64_t n0 = ctx->mesh[0], n1 = ctx->mesh[1], n2 = ctx->mesh[2], nk = n0 * n1 * n2;
+  std::vector<int32_t> rep;
+  rep.reserve((size_t)(nk / 2 + 8));
+  for (int64_t a = 0; a < n0; ++a)
+    for (int64_t b = 0; b < n1; ++b)
+      for (int64_t c = 0; c < n2; ++c) {
+        const int64_t q = (a * n1 + b) * n2 + c;
+        const int64_t mq = ((a ? n0 - a : 0) * n1 + (b ? n1 - b : 0)) * n2 + (c ? n2 - c : 0);
+        if (q <= mq) rep.push_back((int32_t)q);
+      }
+  ctx->nqrep = (int64_t)rep.size();
+  ALLOC(ctx->d_qrep, rep.size() * sizeof(int32_t));
+  HIPCHK(hipMemcpy(ctx->d_qrep, rep.data(), rep.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   return ELPH_OK;
 }
 
