@@ -270,6 +270,35 @@ def test_bf16_split_forms(name, form):
     ctx.close()
 
 
+# 15 branches: the drag gathers take the branches in several passes.  Level
+# COUPLED only: the oracle's plain inner substitution does not reach 1e-13
+# within its iteration limit when it is started cold (PARTIAL), but does
+# when each inner solve starts from the previous outer iterate.
+@pytest.mark.parametrize("level", [3])
+def test_iterate_16_bands_5_atoms(level):
+    c = _maxsize_case()
+    T = c.T
+    ctx = make_ctx(c.cfg, c.mat)
+    sz = E.elph_sizes(ctx)
+    assert sz["nbr"] == 15
+    M, nm = sz["nstates"], sz["nk"] * sz["nbr"]
+    I, J, F, G = dtensor(3 * M), dtensor(3 * M), dtensor(3 * nm), dtensor(3 * nm)
+    wext = oracle.default_w_ext(c.prob, T, gamma0=1e13)
+    wext_d = torch.from_numpy(np.ascontiguousarray(wext.reshape(-1))).to(DEV)
+    tol = 1e-12
+    E.elph_iterate(ctx, T, I, J, F, G, W_ph_ext=wext_d, level=level, tol=tol, maxit=400)
+    torch.cuda.synchronize()
+    ref = oracle.iterate(c.prob, T, c.Xp, c.Xm, level, tol=tol, maxit=400, w_ext=wext)
+    assert ref["converged"]
+    got = dict(I=I.cpu().numpy().reshape(M, 3), J=J.cpu().numpy().reshape(M, 3),
+               F=F.cpu().numpy().reshape(-1, sz["nbr"], 3), G=G.cpu().numpy().reshape(-1, sz["nbr"], 3))
+    for key in ("I", "J", "F", "G"):
+        scale = np.abs(ref[key]).max()
+        assert scale > 0, key
+        assert np.abs(got[key] - ref[key]).max() <= 1e-8 * scale, key
+    ctx.close()
+
+
 @pytest.mark.parametrize("level", [0, 1, 2, 3])
 def test_iterate_metal6(level):
     c = case("metal6")
