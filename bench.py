@@ -144,6 +144,11 @@ def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit, 
                           "ms": (time.perf_counter() - t1) * 1e3, "ko_residual": r["ko_residual"],
                           "sigma_xx": float(r["tensors"]["sigma"][0, 0]),
                           "kappa_ph_xx": float(r["tensors"]["kappa_ph"][0, 0])}
+        # Kelvin-Onsager enforcement of that solution (Eqs. 32-35)
+        t2 = time.perf_counter()
+        k = E.elph_ko_enforce(ctx, T, I, J, F, G)
+        out["coupled"].update(ko_lambda=k["lambda"], ko_residual_enforced=k["ko_residual"],
+                              ko_ms=(time.perf_counter() - t2) * 1e3)
     ctx.close()
     return out
 

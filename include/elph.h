@@ -223,6 +223,25 @@ elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph_ext, int32
                          double tol, int32_t maxit, double* I, double* J, double* F,
                          double* G, double* tensors, int32_t* iters, double* ko_residual);
 
+/* Kelvin-Onsager enforcement (Eqs. 32-35) on responses at temperature T_K,
+ * normally those elph_iterate returned.  sigma*S and alpha split into
+ * diffusion and drag parts; with I_diff = (eps - mu)/T J (Eq. 34, I in eV m/K,
+ * J in m per unit charge) the diffusion part of sigma*S equals alpha_el/T
+ * identically, and the drag part I_drag = I - I_diff is rescaled:
+ * I <- I_diff + lambda I_drag, lambda being the scalar that brings
+ * sigma*S_drag[lambda I_drag] closest to alpha_ph/T (Eq. 35; least squares
+ * over the nine tensor components, the root of the scalar condition that the
+ * method finds by bisection, here in closed form).
+ * I [nstates][3] device, rewritten in place; J [nstates][3] and F, G
+ * [nk][nbr][3] device, read only.  tensors (host, may be NULL): the 54 values
+ * of elph_iterate after the correction; lambda and ko_residual (host, may be
+ * NULL): lambda and Eq. 31's residual after the correction.  Synchronises the
+ * context's stream.  EINVAL if a pointer is NULL, or if I has no drag part
+ * (I = I_diff, as at level RTA). */
+elph_status elph_ko_enforce(elph_ctx ctx, double T_K, double* I, const double* J,
+                            const double* F, const double* G, double* tensors,
+                            double* lambda, double* ko_residual);
+
 /* ---- Batches: many independent materials evaluated together ------------
  * The vertex contractions of all materials run in persistent launches that
  * pull (material, tile) work items from a queue, longest contraction first

@@ -74,7 +74,7 @@ __all__ = [
     "electron_bands", "electron_velocities", "dynamical_matrix", "dynamical_matrix_grad",
     "phonon_modes", "phonon_velocities", "fermi_pair", "bose_pair", "gaussian_delta",
     "g_wannier_brute", "g_wannier_factorised", "g_bloch", "Problem", "default_w_ext",
-    "iterate", "transport_tensors", "ko_residual", "energy_groups",
+    "iterate", "transport_tensors", "ko_residual", "ko_enforce", "energy_groups",
 ]
 
 
@@ -583,3 +583,44 @@ def ko_residual(tens, T):
     """Eq. 31: |sigma S - (alpha_el + alpha_ph)/T| / |sigma S| (Frobenius)."""
     d = tens["sigmaS"] - (tens["alpha_el"] + tens["alpha_ph"]) / T
     return np.linalg.norm(d) / max(np.linalg.norm(tens["sigmaS"]), 1e-300)
+
+
+def ko_enforce(prob, T, I, J, F, G, bisect_steps=200):
+    """Kelvin-Onsager enforcement (Eqs. 32-35, section on the coupled BTEs).
+
+    sigma S and alpha are split into diffusion and drag parts (Eq. 32) and I
+    into I_diff + I_drag (Eq. 33).  Demanding sigma S_diff[I_diff] =
+    alpha_el / T gives I_diff = (eps - mu) / (e T) J (Eq. 34; e = 1 in the
+    units of I and J here); the drag part is rescaled by the scalar lambda
+    that satisfies sigma S_drag[lambda I_drag] = alpha_ph / T (Eq. 35).
+    Reading: the tensor condition is taken in the least-squares sense
+    (Frobenius norm), the scalar condition being d/dlambda of
+    |sigma S_drag[lambda I_drag] - alpha_ph/T|^2 = 0, whose root is found by
+    bisection as the paper says.  Returns (I_ko, lambda, tensors of I_ko)."""
+    I_diff = ((prob.eps - prob.mu) / T)[:, None] * J
+    I_drag = I - I_diff
+    S_drag = transport_tensors(prob, T, I_drag, J, F, G)["sigmaS"]
+    target = transport_tensors(prob, T, I, J, F, G)["alpha_ph"] / T
+    if not np.any(S_drag):
+        raise ValueError("no drag part of sigma S to rescale")
+
+    def cond(lam):
+        # half the derivative of the squared residual; increasing in lambda
+        return float(np.sum(S_drag * (lam * S_drag - target)))
+
+    lo, hi = 0.0, 2.0
+    while cond(lo) > 0:
+        lo = 2.0 * lo - 1.0 if lo < 0 else -1.0
+    while cond(hi) < 0:
+        hi = 2.0 * hi
+    for _ in range(bisect_steps):
+        mid = 0.5 * (lo + hi)
+        if cond(mid) < 0:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo <= 4e-16 * max(abs(lo), abs(hi), 1.0):
+            break
+    lam = 0.5 * (lo + hi)
+    I_ko = I_diff + lam * I_drag
+    return I_ko, lam, transport_tensors(prob, T, I_ko, J, F, G)

@@ -530,6 +530,20 @@ extern "C" elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph
   return st;
 }
 
+extern "C" elph_status elph_ko_enforce(elph_ctx ctx, double T_K, double* I, const double* J, const double* F,
+                                       const double* G, double* tensors, double* lambda, double* ko_residual) {
+  CHECK_CTX(ctx);
+  elph_status st = check_T(ctx, T_K);
+  if (st != ELPH_OK) return st;
+  if (!I || !J || !F || !G) {
+    ctx->err = "I, J, F and G are required";
+    return ELPH_EINVAL;
+  }
+  st = build_tables(ctx);
+  if (st != ELPH_OK) return st;
+  return ko_enforce(ctx, T_K, I, J, F, G, tensors, lambda, ko_residual);
+}
+
 // ---------------------------------------------------------------------------
 // batches
 

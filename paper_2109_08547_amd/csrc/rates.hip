@@ -1029,6 +1029,30 @@ __global__ void k_split_out(int64_t n, const double* __restrict__ x, double* __r
   }
 }
 
+__global__ void k_join(int64_t n, const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ x) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  for (int c = 0; c < 3; ++c) {
+    x[t * 6 + c] = A[t * 3 + c];
+    x[t * 6 + 3 + c] = B[t * 3 + c];
+  }
+}
+
+// I <- I_diff + lambda (I - I_diff), I_diff = (eps - mu)/T J (Eqs. 33-35),
+// in x [M][6] and in I [M][3]
+__global__ void k_ko_apply(int64_t M, const double* __restrict__ eps, double mu, double T, double lambda,
+                           double* __restrict__ x, double* __restrict__ I) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const double d = (eps[i] - mu) / T;
+  for (int c = 0; c < 3; ++c) {
+    const double idiff = d * x[i * 6 + 3 + c];
+    const double v = idiff + lambda * (x[i * 6 + c] - idiff);
+    x[i * 6 + c] = v;
+    I[i * 3 + c] = v;
+  }
+}
+
 static elph_status build_groups(elph_ctx ctx, int32_t** order_out, int32_t** off_out) {
   hipStream_t s = ctx->stream;
   const int64_t M = ctx->nstates;
@@ -1144,6 +1168,53 @@ static bool small_solve(int n, double (*G)[8], const double* r, double* g) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(g[i])) return false;
   return true;
+}
+
+// The 54 transport-tensor values of Eqs. 28-30 (SI units) from the electron
+// responses x [M][6] (I, J) and the phonon responses phon [nm][6] (F, G);
+// part holds 64 x 54 block partials, summed on the host in block order.
+static elph_status transport_tensors(elph_ctx ctx, double T, const Thermal& th, const double* x, const double* phon,
+                                     double* part, double out[54]) {
+  hipStream_t s = ctx->stream;
+  const int64_t M = ctx->nstates, nm = ctx->nk * ctx->nbr;
+  const int blocks = 64;
+  std::vector<double> hpart(blocks * 54);
+  hipLaunchKernelGGL(k_tensor_e, dim3(blocks), dim3(256), 0, s, M, ctx->d_eps, ctx->mu, th.f, th.omf, ctx->d_vel, x,
+                     part);
+  hipLaunchKernelGGL(k_tensor_ph, dim3(blocks), dim3(256), 0, s, nm, ctx->d_hw, th.nocc, ctx->omega_min, ctx->d_vph,
+                     phon, part + blocks * 36);
+  HIPCHK(hipMemcpyAsync(hpart.data(), part, blocks * 54 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double te[36] = {0}, tp[18] = {0};
+  for (int b = 0; b < blocks; ++b) {
+    for (int c = 0; c < 36; ++c) te[c] += hpart[b * 36 + c];
+    for (int c = 0; c < 18; ++c) tp[c] += hpart[blocks * 36 + b * 18 + c];
+  }
+  const double V = ctx->volume_A3 * 1e-30;
+  const double kT = kBoltzEVK * T * kCharge;
+  const double ce = kSpinDeg / (V * kT * (double)ctx->nk);
+  const double cp = 1.0 / (V * kT * (double)ctx->nk);
+  const double e = kCharge;
+  for (int c = 0; c < 9; ++c) {
+    out[c] = ce * e * te[c] * e;                  // sigma: J in C m
+    out[9 + c] = ce * e * te[9 + c] * e;          // sigma S: I in J m / K
+    out[18 + c] = -ce * te[18 + c] * e * e;       // alpha_el: (eps - mu) in J, J in C m
+    out[27 + c] = -ce * te[27 + c] * e * e;       // kappa0_el
+    out[36 + c] = cp * tp[c] * e * e;             // alpha_ph: hw in J, G in C m
+    out[45 + c] = cp * tp[9 + c] * e * e;         // kappa_ph
+  }
+  return ELPH_OK;
+}
+
+// Eq. 31: |sigma S - (alpha_el + alpha_ph)/T| / |sigma S| (Frobenius)
+static double ko_residual_of(const double out[54], double T) {
+  double dn = 0, sn = 0;
+  for (int c = 0; c < 9; ++c) {
+    const double d = out[9 + c] - (out[18 + c] + out[36 + c]) / T;
+    dn += d * d;
+    sn += out[9 + c] * out[9 + c];
+  }
+  return std::sqrt(dn) / std::max(std::sqrt(sn), 1e-300);
 }
 
 template <typename ST>
@@ -1367,43 +1438,12 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   hipLaunchKernelGGL(k_split_out, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, phon, F, G);
   HIPCHK(hipGetLastError());
   if (tensors || ko) {
-    const int blocks = 64;
-    hipLaunchKernelGGL(k_tensor_e, dim3(blocks), dim3(256), 0, s, M, ctx->d_eps, ctx->mu, th.f, th.omf, ctx->d_vel,
-                       x, part);
-    hipLaunchKernelGGL(k_tensor_ph, dim3(blocks), dim3(256), 0, s, nm, ctx->d_hw, th.nocc, ctx->omega_min,
-                       ctx->d_vph, phon, part + blocks * 36);
-    HIPCHK(hipMemcpyAsync(hpart.data(), part, blocks * 54 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    double te[36] = {0}, tp[18] = {0};
-    for (int b = 0; b < blocks; ++b) {
-      for (int c = 0; c < 36; ++c) te[c] += hpart[b * 36 + c];
-      for (int c = 0; c < 18; ++c) tp[c] += hpart[blocks * 36 + b * 18 + c];
-    }
-    const double V = ctx->volume_A3 * 1e-30;
-    const double kT = kBoltzEVK * T * kCharge;
-    const double ce = kSpinDeg / (V * kT * (double)ctx->nk);
-    const double cp = 1.0 / (V * kT * (double)ctx->nk);
-    const double e = kCharge;
     double out[54];
-    for (int c = 0; c < 9; ++c) {
-      out[c] = ce * e * te[c] * e;                  // sigma: J in C m
-      out[9 + c] = ce * e * te[9 + c] * e;          // sigma S: I in J m / K
-      out[18 + c] = -ce * te[18 + c] * e * e;       // alpha_el: (eps - mu) in J, J in C m
-      out[27 + c] = -ce * te[27 + c] * e * e;       // kappa0_el
-      out[36 + c] = cp * tp[c] * e * e;             // alpha_ph: hw in J, G in C m
-      out[45 + c] = cp * tp[9 + c] * e * e;         // kappa_ph
-    }
+    st = transport_tensors(ctx, T, th, x, phon, part, out);
+    if (st != ELPH_OK) return st;
     if (tensors)
       for (int c = 0; c < 54; ++c) tensors[c] = out[c];
-    if (ko) {
-      double dn = 0, sn = 0;
-      for (int c = 0; c < 9; ++c) {
-        const double d = out[9 + c] - (out[18 + c] + out[36 + c]) / T;
-        dn += d * d;
-        sn += out[9 + c] * out[9 + c];
-      }
-      *ko = std::sqrt(dn) / std::max(std::sqrt(sn), 1e-300);
-    }
+    if (ko) *ko = ko_residual_of(out, T);
   }
   HIPCHK(hipStreamSynchronize(s));
   if (iters) *iters = used;
@@ -1416,6 +1456,60 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
     return ELPH_ENOCONV;
   }
   return ELPH_OK;
+}
+
+// Kelvin-Onsager enforcement (Eqs. 32-35) on responses I, J, F, G: with
+// I_diff = (eps - mu)/T J, sigma S_diff[I_diff] = alpha_el/T holds exactly,
+// so sigma S_drag[I_drag] = sigma S - alpha_el/T; lambda minimises
+// |lambda sigma S_drag - alpha_ph/T| (Frobenius), the root of the scalar
+// condition the bisection of the method solves, written in closed form.
+elph_status ko_enforce(elph_ctx ctx, double T, double* I, const double* J, const double* F, const double* G,
+                       double* tensors, double* lambda, double* ko) {
+  hipStream_t s = ctx->stream;
+  const int64_t M = ctx->nstates, nm = ctx->nk * ctx->nbr;
+  Thermal th;
+  elph_status st = make_thermal(ctx, T, &th);
+  if (st != ELPH_OK) return st;
+  double *x = nullptr, *phon = nullptr, *part = nullptr;
+  ALLOC(x, M * 6 * sizeof(double));
+  ALLOC(phon, nm * 6 * sizeof(double));
+  ALLOC(part, 64 * 54 * sizeof(double));
+  hipLaunchKernelGGL(k_join, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, (const double*)I, J, x);
+  hipLaunchKernelGGL(k_join, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, F, G, phon);
+  HIPCHK(hipGetLastError());
+  double out[54];
+  st = transport_tensors(ctx, T, th, x, phon, part, out);
+  double lam = 0.0;
+  if (st == ELPH_OK) {
+    double sa = 0.0, ss = 0.0;
+    for (int c = 0; c < 9; ++c) {
+      const double sd = out[9 + c] - out[18 + c] / T;  // sigma S_drag[I_drag]
+      sa += sd * (out[36 + c] / T);
+      ss += sd * sd;
+    }
+    if (!(ss > 0.0)) {
+      ctx->err = "sigma S has no drag part to rescale (I = (eps - mu)/T J)";
+      st = ELPH_EINVAL;
+    } else {
+      lam = sa / ss;
+      hipLaunchKernelGGL(k_ko_apply, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, ctx->d_eps, ctx->mu, T, lam, x,
+                         I);
+      HIPCHK(hipGetLastError());
+      st = transport_tensors(ctx, T, th, x, phon, part, out);
+    }
+  }
+  if (st == ELPH_OK) {
+    if (tensors)
+      for (int c = 0; c < 54; ++c) tensors[c] = out[c];
+    if (lambda) *lambda = lam;
+    if (ko) *ko = ko_residual_of(out, T);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  dev_free(ctx, x);
+  dev_free(ctx, phon);
+  dev_free(ctx, part);
+  free_thermal(ctx, &th);
+  return st;
 }
 
 elph_status iterate(elph_ctx ctx, double T, const double* wext, int level, double tol, int maxit, double* I,

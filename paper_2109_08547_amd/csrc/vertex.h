@@ -34,6 +34,8 @@ elph_status finalize_wph(elph_ctx ctx, const Thermal& th, double* acc, double* w
 elph_status interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx, double* g_out);
 elph_status iterate(elph_ctx ctx, double T, const double* wext, int level, double tol, int maxit, double* I,
                     double* J, double* F, double* G, double* tensors, int* iters, double* ko);
+elph_status ko_enforce(elph_ctx ctx, double T, double* I, const double* J, const double* F, const double* G,
+                       double* tensors, double* lambda, double* ko);
 
 // electron self-consistency solver (solve.hip)
 struct SelfSolver {

@@ -45,7 +45,7 @@ class ElphSizes(ctypes.Structure):
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
            "elph_batch_tune", "elph_tables",
-           "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate",
+           "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce",
            "elph_mlp_create", "elph_mlp_destroy", "elph_mlp_last_error", "elph_mlp_nparams",
            "elph_mlp_get_params", "elph_mlp_set_params", "elph_mlp_forward", "elph_mlp_gradients",
            "elph_mlp_train_step", "elph_screen_nin", "elph_screen_samples", "elph_scatt_rates_screened")
@@ -81,6 +81,7 @@ def load():
     lib.elph_scatt_rates.argtypes = [vp, ctypes.c_double, vp, vp]
     lib.elph_iterate.argtypes = [vp, ctypes.c_double, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                  vp, vp, vp, vp, vp, vp, vp]
+    lib.elph_ko_enforce.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp]
     lib.elph_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.elph_batch_destroy.argtypes = [vp]
     lib.elph_batch_destroy.restype = None
@@ -238,6 +239,19 @@ def elph_iterate(ctx, T, I, J, F, G, W_ph_ext=None, level=ELPH_LEVEL_COUPLED, to
     names = ("sigma", "sigmaS", "alpha_el", "kappa0_el", "alpha_ph", "kappa_ph")
     return {"tensors": {n: tens[9 * a:9 * a + 9].reshape(3, 3).copy() for a, n in enumerate(names)},
             "iters": iters.value, "ko_residual": ko.value, "status": st}
+
+
+def elph_ko_enforce(ctx, T, I, J, F, G):
+    """Kelvin-Onsager enforcement on device responses (I rewritten in place).
+    Returns dict(tensors [6,3,3] numpy, lambda, ko_residual)."""
+    tens = np.zeros(54)
+    lam = ctypes.c_double(0.0)
+    ko = ctypes.c_double(0.0)
+    _check(ctx, load().elph_ko_enforce(ctx.handle, float(T), _ptr(I), _ptr(J), _ptr(F), _ptr(G),
+                                       tens.ctypes.data_as(ctypes.c_void_p), ctypes.byref(lam), ctypes.byref(ko)))
+    names = ("sigma", "sigmaS", "alpha_el", "kappa0_el", "alpha_ph", "kappa_ph")
+    return {"tensors": {n: tens[9 * a:9 * a + 9].reshape(3, 3).copy() for a, n in enumerate(names)},
+            "lambda": lam.value, "ko_residual": ko.value}
 
 
 class Batch:

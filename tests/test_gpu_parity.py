@@ -8,6 +8,7 @@ error over states with W_ref >= 1e-12 max W_ref (smaller ones absolutely).
 import numpy as np
 import pytest
 
+import ko_cases
 import oracle
 import synth
 from synth import materials as sm
@@ -296,6 +297,51 @@ def test_iterate_16_bands_5_atoms(level):
         scale = np.abs(ref[key]).max()
         assert scale > 0, key
         assert np.abs(got[key] - ref[key]).max() <= 1e-8 * scale, key
+    ctx.close()
+
+
+def test_ko_enforce_planted_lambda():
+    # responses for which Eq. 35 holds at lambda = 0.8 (built from the oracle)
+    c = case("metal6")
+    ctx = make_ctx(c.cfg, c.mat)
+    E.elph_sizes(ctx)
+    T = c.T
+    I, J, F, G = ko_cases.planted_ko_case(c.prob, T, 0.8)
+    I_ref, lam_ref, tens_ref = oracle.ko_enforce(c.prob, T, I, J, F, G)
+    dev = [torch.from_numpy(np.ascontiguousarray(a.reshape(-1))).to(DEV) for a in (I, J, F, G)]
+    r = E.elph_ko_enforce(ctx, T, *dev)
+    torch.cuda.synchronize()
+    assert abs(r["lambda"] - 0.8) < 1e-9 and abs(lam_ref - 0.8) < 1e-12
+    assert r["ko_residual"] < 1e-9
+    got = dev[0].cpu().numpy().reshape(I.shape)
+    assert np.abs(got - I_ref).max() <= 1e-10 * np.abs(I_ref).max()
+    for key, val in tens_ref.items():
+        assert np.abs(r["tensors"][key] - val).max() <= 1e-10 * max(np.abs(val).max(), 1e-300), key
+    with pytest.raises(E.ElphError):
+        E.elph_ko_enforce(ctx, T, dev[0], None, dev[2], dev[3])
+    ctx.close()
+
+
+def test_ko_enforce_on_the_coupled_solution():
+    c = case("metal6")
+    T = c.T
+    ctx = make_ctx(c.cfg, c.mat)
+    sz = E.elph_sizes(ctx)
+    M, nm = sz["nstates"], sz["nk"] * sz["nbr"]
+    I, J, F, G = dtensor(3 * M), dtensor(3 * M), dtensor(3 * nm), dtensor(3 * nm)
+    wext = oracle.default_w_ext(c.prob, T, gamma0=1e13)
+    wext_d = torch.from_numpy(np.ascontiguousarray(wext.reshape(-1))).to(DEV)
+    E.elph_iterate(ctx, T, I, J, F, G, W_ph_ext=wext_d, level=3, tol=1e-12, maxit=400)
+    r = E.elph_ko_enforce(ctx, T, I, J, F, G)
+    torch.cuda.synchronize()
+    ref = oracle.iterate(c.prob, T, c.Xp, c.Xm, 3, tol=1e-12, maxit=400, w_ext=wext)
+    I_ref, lam_ref, tens_ref = oracle.ko_enforce(c.prob, T, ref["I"], ref["J"], ref["F"], ref["G"])
+    assert abs(r["lambda"] - lam_ref) <= 1e-6 * abs(lam_ref)
+    got = I.cpu().numpy().reshape(M, 3)
+    assert np.abs(got - I_ref).max() <= 1e-7 * np.abs(I_ref).max()
+    for key, val in tens_ref.items():
+        assert np.abs(r["tensors"][key] - val).max() <= 1e-7 * max(np.abs(val).max(), 1e-300), key
+    assert abs(r["ko_residual"] - oracle.ko_residual(tens_ref, T)) < 1e-6
     ctx.close()
 
 

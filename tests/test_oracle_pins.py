@@ -11,6 +11,7 @@ the coupled BTEs.
 import numpy as np
 import pytest
 
+import ko_cases
 import oracle
 import synth
 from synth import materials as sm
@@ -470,3 +471,58 @@ def test_rta_level_reproduces_eqs_20_24_and_kelvin_onsager():
     # at RTA the phonon Peltier term vanishes and sigma S = alpha_el / T exactly
     assert oracle.ko_residual(tens, T) < 1e-12
     assert np.all(np.linalg.eigvalsh(0.5 * (tens["sigma"] + tens["sigma"].T)) > 0)
+
+
+# ---------------------------------------------------------------------------
+# Kelvin-Onsager enforcement (Eqs. 32-35)
+
+def _ko_problem():
+    cfg = synth.config("metal6")
+    mat = synth.material_for(cfg)
+    return oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"]), 300.0
+
+
+def test_ko_diffusion_part_is_alpha_el_over_T():
+    # Eq. 34: sigma S of I_diff = (eps - mu)/T J equals alpha_el / T
+    prob, T = _ko_problem()
+    rng = np.random.default_rng(3)
+    J = rng.standard_normal((prob.nstates, 3))
+    I_diff = ((prob.eps - prob.mu) / T)[:, None] * J
+    zero = np.zeros_like(prob.v_ph)
+    t = oracle.transport_tensors(prob, T, I_diff, J, zero, zero)
+    assert np.abs(t["sigmaS"] - t["alpha_el"] / T).max() <= 1e-13 * np.abs(t["sigmaS"]).max()
+
+
+@pytest.mark.parametrize("c", [0.8, 1.0, -0.3])
+def test_ko_enforce_recovers_a_planted_lambda(c):
+    prob, T = _ko_problem()
+    I, J, F, G = ko_cases.planted_ko_case(prob, T, c)
+    I_ko, lam, tens = oracle.ko_enforce(prob, T, I, J, F, G)
+    assert abs(lam - c) <= 1e-12 * max(1.0, abs(c))
+    assert oracle.ko_residual(tens, T) < 1e-12
+    I_diff = ((prob.eps - prob.mu) / T)[:, None] * J
+    assert np.abs(I_ko - (I_diff + c * (I - I_diff))).max() <= 1e-12 * np.abs(I).max()
+    if c == 1.0:
+        assert np.abs(I_ko - I).max() <= 1e-12 * np.abs(I).max()
+
+
+def test_ko_enforce_minimises_the_mismatch_on_a_coupled_solution():
+    # the numerator of Eq. 31 after enforcement is the least-squares minimum
+    # over lambda: no other scale of the drag part does better
+    prob, T = _ko_problem()
+    Xp, Xm = prob.transition_probs(T)
+    w_ext = oracle.default_w_ext(prob, T, gamma0=1e13)
+    res = oracle.iterate(prob, T, Xp, Xm, oracle.LEVEL_COUPLED, tol=1e-12, maxit=500, w_ext=w_ext)
+    assert res["converged"]
+    I, J, F, G = res["I"], res["J"], res["F"], res["G"]
+    _, lam, tens = oracle.ko_enforce(prob, T, I, J, F, G)
+
+    def mismatch(t):
+        return np.linalg.norm(t["sigmaS"] - (t["alpha_el"] + t["alpha_ph"]) / T)
+
+    best = mismatch(tens)
+    I_diff = ((prob.eps - prob.mu) / T)[:, None] * J
+    for l2 in (lam * 0.9, lam * 1.1, 1.0, 0.0):
+        t2 = oracle.transport_tensors(prob, T, I_diff + l2 * (I - I_diff), J, F, G)
+        assert best <= mismatch(t2) * (1 + 1e-12)
+    assert best <= mismatch(oracle.transport_tensors(prob, T, I, J, F, G))
