@@ -76,6 +76,12 @@ enum {
                         FP16 numbers (exact inverse scaling in the epilogues) */
 };
 
+/* Energy-conserving delta of Eq. 8 (see elph_set_delta). */
+enum {
+  ELPH_DELTA_GAUSS = 0,  /* Gaussian of standard deviation sigma (elph_create's sigma) */
+  ELPH_DELTA_TETRA = 1   /* analytic tetrahedron weights on the mesh (no smearing parameter) */
+};
+
 /* Solution levels of the coupled BTEs (section "Coupled and decoupled BTEs"). */
 enum {
   ELPH_LEVEL_RTA = 0,       /* Eqs. 20, 24 only */
@@ -181,6 +187,19 @@ elph_status elph_tables(elph_ctx ctx, int32_t* state_k, int32_t* state_m, double
  * sums over degenerate groups do not.  Branches below omega_min give 0. */
 elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
                           const int32_t* qidx, double* g_out);
+
+/* Select the energy-conserving delta of Eq. 8 for this context's later
+ * vertex stores (the paper offers the triangle and the analytic
+ * tetrahedron methods beside smearing; section on the program's workflow).
+ * ELPH_DELTA_TETRA: every mesh cell is split into six tetrahedra along its
+ * main diagonal, E(k'') = eps_n(k'') -+ hbar omega_s(k'' - k) - eps_m(k)
+ * (bands and branches by index) is interpolated linearly in each, and the
+ * delta at the final k' becomes the sum, over the 24 tetrahedra with corner
+ * k', of the integral of delta(E) times the barycentric coordinate of k'
+ * (mesh-cell units, 1/eV).  Marks the vertex store and the cached rates
+ * stale.  EINVAL for an unknown method.  The batch and screened calls
+ * accept only ELPH_DELTA_GAUSS. */
+elph_status elph_set_delta(elph_ctx ctx, int32_t method);
 
 /* Eq. 8 over the window at temperature T: Xp, Xm [nterms] FP64 (term-store
  * layout, absorption + and emission -).  Either may be NULL.  When store_B

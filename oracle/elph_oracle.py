@@ -74,6 +74,7 @@ __all__ = [
     "electron_bands", "electron_velocities", "dynamical_matrix", "dynamical_matrix_grad",
     "phonon_modes", "phonon_velocities", "fermi_pair", "bose_pair", "gaussian_delta",
     "g_wannier_brute", "g_wannier_factorised", "g_bloch", "Problem", "default_w_ext",
+    "tetra_delta_weights", "tetra_neighbourhood",
     "iterate", "transport_tensors", "ko_residual", "ko_enforce", "energy_groups",
 ]
 
@@ -206,6 +207,85 @@ def gaussian_delta(x, sigma):
 
 
 # ----------------------------------------------------------------------------
+# The analytic tetrahedron delta (the alternative to smearing that the paper
+# provides beside the triangle method; section on the program's workflow)
+
+def tetra_delta_weights(e):
+    """e [..., 4]: energies (level 0) at the corners of tetrahedra over which
+    E is linear -> w [..., 4]: the integral over the tetrahedron of
+    delta(E(x)) lambda_c(x), lambda_c the barycentric coordinate of corner c,
+    for a tetrahedron of volume 1/6 (one sixth of a mesh cell in mesh units).
+    By the coarea formula this is the area integral of lambda_c over the
+    section E = 0 divided by |grad E|; lambda_c is linear on each triangle of
+    the section, so a triangle contributes its area times the mean of
+    lambda_c over its corners.  The integral depends only on the corner
+    energies and the volume, so the sorted corners are placed at 0, x, y, z."""
+    e = np.asarray(e, dtype=np.float64)
+    shp = e.shape[:-1]
+    e = e.reshape(-1, 4)
+    order = np.argsort(e, axis=1, kind="stable")
+    es = np.take_along_axis(e, order, axis=1)
+    P = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    grad = np.stack([es[:, 1] - es[:, 0], es[:, 2] - es[:, 0], es[:, 3] - es[:, 0]], axis=1)
+    gn = np.linalg.norm(grad, axis=1)
+    ws = np.zeros_like(es)
+    nneg = (es < 0).sum(axis=1)
+
+    def cross(a, b, rows):
+        # point of edge (a, b) where E = 0: position and barycentric coordinates
+        ea, eb = es[rows, a], es[rows, b]
+        t = ea / (ea - eb)
+        X = P[a][None, :] + t[:, None] * (P[b] - P[a])[None, :]
+        lam = np.zeros((rows.size, 4))
+        lam[:, a] = 1.0 - t
+        lam[:, b] = t
+        return X, lam
+
+    def add_triangle(rows, A, B, C):
+        (Xa, la), (Xb, lb), (Xc, lc) = A, B, C
+        area = 0.5 * np.linalg.norm(np.cross(Xb - Xa, Xc - Xa), axis=1)
+        ws[rows] += (area / gn[rows])[:, None] * (la + lb + lc) / 3.0
+
+    ok = gn > 0
+    r1 = np.nonzero(ok & (nneg == 1))[0]
+    if r1.size:
+        add_triangle(r1, cross(0, 1, r1), cross(0, 2, r1), cross(0, 3, r1))
+    r3 = np.nonzero(ok & (nneg == 3))[0]
+    if r3.size:
+        add_triangle(r3, cross(0, 3, r3), cross(1, 3, r3), cross(2, 3, r3))
+    r2 = np.nonzero(ok & (nneg == 2))[0]
+    if r2.size:
+        q02, q03, q13, q12 = cross(0, 2, r2), cross(0, 3, r2), cross(1, 3, r2), cross(1, 2, r2)
+        add_triangle(r2, q02, q03, q13)   # the section's corners in cyclic order
+        add_triangle(r2, q02, q13, q12)
+    w = np.empty_like(ws)
+    np.put_along_axis(w, order, ws, axis=1)
+    return w.reshape(shp + (4,))
+
+
+def tetra_neighbourhood():
+    """The 24 tetrahedra of the mesh that have a given point as a corner, in
+    the six-tetrahedra split of every mesh cell along its main diagonal (the
+    paths 0 -> e_a -> e_a + e_b -> (1,1,1)).  Points of the 3x3x3
+    neighbourhood are numbered (dx+1)*9 + (dy+1)*3 + (dz+1); returns
+    (corners [24, 4], index of the centre point 13 among them [24])."""
+    import itertools
+    corners, centre = [], []
+    for o in itertools.product((0, 1), repeat=3):
+        for perm in itertools.permutations(range(3)):
+            path = [np.array(o)]
+            for ax in perm:
+                nxt = path[-1].copy()
+                nxt[ax] += 1
+                path.append(nxt)
+            ids = [int(p[0] * 9 + p[1] * 3 + p[2]) for p in path]
+            if 13 in ids:
+                corners.append(ids)
+                centre.append(ids.index(13))
+    return np.array(corners), np.array(centre)
+
+
+# ----------------------------------------------------------------------------
 # Eq. 6: the e-ph vertex
 
 def g_wannier_brute(mat, k, q):
@@ -331,9 +411,34 @@ class Problem:
         return np.abs(g) ** 2, qmesh
 
     # ---- Eq. 8
-    def transition_probs(self, T, rows=None, brute=False):
+    def tetra_delta(self, i):
+        """Delta of Eq. 8 by the analytic tetrahedron method for initial state
+        i and every final state j and branch s -> (Dp, Dm) [nstates, nbr],
+        1/eV: at the final k_j, the sum over the 24 mesh tetrahedra with
+        corner k_j of the corner weight of k_j for
+        E(k'') = eps_n(k'') -+ hw_s(k'' - k_i) - eps_i (n the band of j),
+        linear in each tetrahedron.  Replaces the Gaussian's delta(E(k_j))."""
+        corners, centre = tetra_neighbourhood()
+        off = np.array([[a, b, c] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)])
+        kj = self.ijk[self.state_k]                                   # [M, 3]
+        nbr_mesh = mesh_linear(kj[:, None, :] + off[None, :, :], self.n)  # [M, 27]
+        eps_n = self.eps_all[nbr_mesh, self.state_m[:, None]]       # [M, 27]
+        ki = self.ijk[self.state_k[i]]
+        q_mesh = mesh_linear(kj[:, None, :] + off[None, :, :] - ki, self.n)  # [M, 27]
+        hw = self.hw[q_mesh]                                          # [M, 27, nbr]
+        out = []
+        for sign in (-1.0, 1.0):                                      # absorption, emission
+            E = eps_n[:, :, None] + sign * hw - self.eps[i]           # [M, 27, nbr]
+            Ec = E[:, corners, :]                                     # [M, 24, 4, nbr]
+            w = tetra_delta_weights(np.moveaxis(Ec, 2, -1))           # [M, 24, nbr, 4]
+            out.append(np.take_along_axis(w, centre[None, :, None, None], axis=3)[..., 0].sum(axis=1))
+        return out[0], out[1]
+
+    def transition_probs(self, T, rows=None, brute=False, delta="gauss"):
         """X^+ and X^- of Eq. 8 for initial states ``rows`` (all when None) and
-        every final active state -> (Xp, Xm) of shape [len(rows), nstates, nbr]."""
+        every final active state -> (Xp, Xm) of shape [len(rows), nstates, nbr].
+        delta: "gauss" (Gaussian of width sigma) or "tetra" (analytic
+        tetrahedron weights, see tetra_delta)."""
         rows = np.arange(self.nstates) if rows is None else np.asarray(rows)
         f, omf = fermi_pair(self.eps, self.mu, T)
         pref = 2.0 * np.pi / (HBAR_EVS * self.nk)
@@ -352,9 +457,12 @@ class Problem:
             for r, i in lst:
                 m = self.state_m[i]
                 g2j = g2[jk, :, jm, m]             # [nstates, s]
-                de = (self.eps - self.eps[i])[:, None]          # eps_j - eps_i
-                dp = gaussian_delta(de - hw[jk], self.sigma)
-                dm = gaussian_delta(de + hw[jk], self.sigma)
+                if delta == "tetra":
+                    dp, dm = self.tetra_delta(i)
+                else:
+                    de = (self.eps - self.eps[i])[:, None]      # eps_j - eps_i
+                    dp = gaussian_delta(de - hw[jk], self.sigma)
+                    dm = gaussian_delta(de + hw[jk], self.sigma)
                 occ = f[i] * omf                               # f_i (1 - f_j)
                 with np.errstate(invalid="ignore"):
                     xp = pref * g2j * occ[:, None] * nq[jk] * dp

@@ -417,6 +417,20 @@ __global__ void k_x_inplace(int64_t M, int nbr, int n0, int n1, int n2, const in
   Xm[t] *= occ * (1.0 + n);
 }
 
+extern "C" elph_status elph_set_delta(elph_ctx ctx, int32_t method) {
+  CHECK_CTX(ctx);
+  if (method != ELPH_DELTA_GAUSS && method != ELPH_DELTA_TETRA) {
+    ctx->err = "unknown delta method";
+    return ELPH_EINVAL;
+  }
+  if (method != ctx->delta) {
+    ctx->delta = method;
+    ctx->store_ready = false;
+    ctx->rates_valid = false;
+  }
+  return ELPH_OK;
+}
+
 extern "C" elph_status elph_transition_probs(elph_ctx ctx, double T_K, double* Xp, double* Xm, int32_t store_B) {
   CHECK_CTX(ctx);
   elph_status st = check_T(ctx, T_K);
@@ -561,11 +575,16 @@ extern "C" elph_status elph_batch_create(int32_t n, const elph_ctx* ctxs, elph_b
   }
   *out = nullptr;
   std::vector<elph_ctx> v(ctxs, ctxs + n);
-  for (elph_ctx c : v)
+  for (elph_ctx c : v) {
     if (!c) {
       g_batch_err = "null context";
       return ELPH_EINVAL;
     }
+    if (c->delta != ELPH_DELTA_GAUSS) {
+      g_batch_err = "batches support the Gaussian delta only";
+      return ELPH_EINVAL;
+    }
+  }
   std::string err;
   BatchImpl* impl = batch_new(v, &err);
   if (!impl) {

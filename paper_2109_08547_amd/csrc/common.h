@@ -62,6 +62,7 @@ struct elph_ctx_s {
   int mesh[3] = {0, 0, 0};
   int64_t nk = 0;
   int precision = ELPH_FP64;
+  int delta = ELPH_DELTA_GAUSS;  // energy-conserving delta of Eq. 8
   double mu = 0, window = 0, sigma = 0, omega_min = 1e-4;
   // operand scales of the FP16 split form (powers of two; 1 in the other
   // forms): A_e, A_p, gR, B2

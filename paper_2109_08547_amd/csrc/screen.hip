@@ -216,6 +216,10 @@ extern "C" elph_status elph_scatt_rates_screened(elph_ctx ctx, elph_mlp m, int32
     ctx->err = "unknown screen mode or bad temperature";
     return ELPH_EINVAL;
   }
+  if (ctx->delta != ELPH_DELTA_GAUSS) {
+    ctx->err = "the screened rates support the Gaussian delta only";
+    return ELPH_EINVAL;
+  }
   if (mode == ELPH_SCREEN_MLP && (!m || !(tau > 0.0 && tau < 1.0) || m->hip_dead)) {
     ctx->err = "the MLP screen needs a live network and 0 < tau < 1";
     return ELPH_EINVAL;

@@ -29,6 +29,7 @@
 #include <map>
 #include <string>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 namespace elph {
@@ -492,6 +493,7 @@ struct EpiParams {
   int64_t m_pad;
   const uint8_t* tile_keep;  // [m_pad/32][m_pad/32] computed tiles (null = all)
   double cscale;             // undoes the operand scales of the step-2 contraction (1 but in the FP16 form)
+  int tetra;                 // 1: store pref |g|^2 without the delta (tetrahedron weights follow)
 };
 
 __device__ inline int q_of(int kj, int ki, int n0, int n1, int n2) {
@@ -665,9 +667,13 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
         const double w = hwq[s];
         double bp = 0.0, bm = 0.0;
         if (w >= ep.omega_min) {
-          const double dp = de - w, dm = de + w;
-          bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
-          bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
+          if (ep.tetra) {
+            bp = bm = ep.pref * g2;
+          } else {
+            const double dp = de - w, dm = de + w;
+            bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
+            bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
+          }
         }
         Bp[tb + s] = (ST)bp;
         Bm[tb + s] = (ST)bm;
@@ -1083,9 +1089,13 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
           const double w = hwq[s];
           double bp = 0.0, bm = 0.0;
           if (w >= ep.omega_min) {
-            const double dp = de - w, dm = de + w;
-            bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
-            bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
+            if (ep.tetra) {
+              bp = bm = ep.pref * g2;
+            } else {
+              const double dp = de - w, dm = de + w;
+              bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
+              bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
+            }
           }
           bpv[s] = bp;
           bmv[s] = bm;
@@ -1429,7 +1439,10 @@ static EpiParams epi_params(elph_ctx ctx) {
   ep.n0 = ctx->mesh[0];
   ep.n1 = ctx->mesh[1];
   ep.n2 = ctx->mesh[2];
-  ep.pref = 2.0 * kPi / (kHbarEVs * (double)ctx->nk) / (sqrt(2.0 * kPi) * ctx->sigma);
+  ep.tetra = ctx->delta == ELPH_DELTA_TETRA ? 1 : 0;
+  // with the tetrahedron delta the store first holds 2 pi / (hbar N_k) |g|^2
+  ep.pref = ep.tetra ? 2.0 * kPi / (kHbarEVs * (double)ctx->nk)
+                     : 2.0 * kPi / (kHbarEVs * (double)ctx->nk) / (sqrt(2.0 * kPi) * ctx->sigma);
   ep.inv2s2 = 1.0 / (2.0 * ctx->sigma * ctx->sigma);
   ep.omega_min = ctx->omega_min;
   ep.st_k = ctx->d_state_k;
@@ -1460,6 +1473,199 @@ static elph_status ensure_we_part(elph_ctx ctx) {
   return ELPH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Analytic tetrahedron delta (the alternative to smearing the method offers
+// beside the triangle method): the mesh cells are split into six
+// tetrahedra along their main diagonal, E(k'') = eps_n(k'') -+ hw_s(k'' - k)
+// - eps_m(k) is linear in each, and the delta at the final k' is replaced by
+// the sum over the 24 tetrahedra with corner k' of the integral of
+// delta(E) times the barycentric coordinate of k' (mesh units).
+
+// integral over a tetrahedron of volume 1/6 of delta(E) lambda_c for linear
+// E with corner energies e (coarea: each triangle of the section E = 0
+// contributes its area times the mean of lambda_c over its corners, over
+// |grad E|; the value depends only on the corner energies, so the sorted
+// corners sit at 0, x, y, z)
+__device__ inline double tetra_delta_corner(double e0, double e1, double e2, double e3, int c) {
+  // sort (insertion order: equal energies keep corner order), carrying the
+  // mark of corner c along
+  double s0 = e0, s1 = e1, s2 = e2, s3 = e3;
+  bool m0 = c == 0, m1 = c == 1, m2 = c == 2, m3 = c == 3;
+  auto cs = [](double& a, double& b, bool& ma, bool& mb) {
+    if (b < a) {
+      const double t = a;
+      a = b;
+      b = t;
+      const bool u = ma;
+      ma = mb;
+      mb = u;
+    }
+  };
+  cs(s2, s3, m2, m3);
+  cs(s1, s2, m1, m2);
+  cs(s2, s3, m2, m3);
+  cs(s0, s1, m0, m1);
+  cs(s1, s2, m1, m2);
+  cs(s2, s3, m2, m3);
+  const int pc = m1 ? 1 : m2 ? 2 : m3 ? 3 : 0;
+  const double s[4] = {s0, s1, s2, s3};
+  const double g0 = s1 - s0, g1 = s2 - s0, g2 = s3 - s0;
+  const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+  const int nneg = (s0 < 0.0) + (s1 < 0.0) + (s2 < 0.0) + (s3 < 0.0);
+  if (!(gn > 0.0) || nneg == 0 || nneg == 4) return 0.0;
+  // point of edge (a, b) with E = 0: position (x, y, z) and lambda of pc
+  struct Pt {
+    double x, y, z, l;
+  };
+  auto cross = [&](int a, int b) {
+    const double t = s[a] / (s[a] - s[b]);
+    const double pa[3] = {a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0, a == 3 ? 1.0 : 0.0};
+    const double pb[3] = {b == 1 ? 1.0 : 0.0, b == 2 ? 1.0 : 0.0, b == 3 ? 1.0 : 0.0};
+    Pt p;
+    p.x = pa[0] + t * (pb[0] - pa[0]);
+    p.y = pa[1] + t * (pb[1] - pa[1]);
+    p.z = pa[2] + t * (pb[2] - pa[2]);
+    p.l = (pc == a) ? 1.0 - t : (pc == b) ? t : 0.0;
+    return p;
+  };
+  auto tri = [&](const Pt& A, const Pt& B, const Pt& C) {
+    const double ux = B.x - A.x, uy = B.y - A.y, uz = B.z - A.z;
+    const double vx = C.x - A.x, vy = C.y - A.y, vz = C.z - A.z;
+    const double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+    return 0.5 * sqrt(cx * cx + cy * cy + cz * cz) * (A.l + B.l + C.l) / 3.0;
+  };
+  double w;
+  if (nneg == 1) {
+    w = tri(cross(0, 1), cross(0, 2), cross(0, 3));
+  } else if (nneg == 3) {
+    w = tri(cross(0, 3), cross(1, 3), cross(2, 3));
+  } else {
+    const Pt q02 = cross(0, 2), q03 = cross(0, 3), q13 = cross(1, 3), q12 = cross(1, 2);
+    w = tri(q02, q03, q13) + tri(q02, q13, q12);  // the section's corners in cyclic order
+  }
+  return w / gn;
+}
+
+// The 24 tetrahedra with a given mesh point as corner: the point's 3x3x3
+// neighbourhood is numbered (dx+1)*9 + (dy+1)*3 + (dz+1) (centre 13); each
+// of the 8 cells with the centre as a corner is cut along the paths
+// 0 -> e_a -> e_a + e_b -> (1,1,1) over the 6 axis orders, and a path
+// tetrahedron is kept when it passes through the centre.
+struct TetraTab {
+  unsigned char c[24][4];  // corners (neighbourhood numbers) along the path
+  unsigned char ctr[24];   // which of them is the centre
+};
+
+constexpr TetraTab make_tetra_tab() {
+  TetraTab t{};
+  const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  int n = 0;
+  for (int o = 0; o < 8; ++o)
+    for (int p = 0; p < 6; ++p) {
+      int v[3] = {(o >> 2) & 1, (o >> 1) & 1, o & 1};
+      int ids[4] = {0, 0, 0, 0};
+      int ctr = -1;
+      for (int k = 0; k < 4; ++k) {
+        if (k > 0) v[perms[p][k - 1]] += 1;
+        ids[k] = v[0] * 9 + v[1] * 3 + v[2];
+        if (ids[k] == 13) ctr = k;
+      }
+      if (ctr >= 0) {
+        for (int k = 0; k < 4; ++k) t.c[n][k] = (unsigned char)ids[k];
+        t.ctr[n] = (unsigned char)ctr;
+        ++n;
+      }
+    }
+  return t;
+}
+constexpr TetraTab kTetra = make_tetra_tab();
+
+// one tetrahedron's corner weight of the centre for both signs; the corner
+// numbers are compile-time constants, so the neighbourhood arrays stay in
+// registers
+template <int K>
+__device__ __attribute__((always_inline)) inline void tetra_one(const double (&ej)[27], const double (&w)[27], double ei, double& dp, double& dm) {
+  constexpr int c0 = kTetra.c[K][0], c1 = kTetra.c[K][1], c2 = kTetra.c[K][2], c3 = kTetra.c[K][3];
+  constexpr int ck = kTetra.ctr[K];
+  dp += tetra_delta_corner(ej[c0] - w[c0] - ei, ej[c1] - w[c1] - ei, ej[c2] - w[c2] - ei, ej[c3] - w[c3] - ei, ck);
+  dm += tetra_delta_corner(ej[c0] + w[c0] - ei, ej[c1] + w[c1] - ei, ej[c2] + w[c2] - ei, ej[c3] + w[c3] - ei, ck);
+}
+
+template <int... K>
+__device__ __attribute__((always_inline)) inline void tetra_all(const double (&ej)[27], const double (&w)[27], double ei, double& dp, double& dm,
+                                 std::integer_sequence<int, K...>) {
+  (tetra_one<K>(ej, w, ei, dp, dm), ...);
+}
+
+// B+-[i][j][s] *= tetrahedron delta at k_j for E = eps_n(k'') -+ hw_s(k'' - k_i) - eps_i;
+// one thread per pair (i, j)
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_tetra_scale(int64_t M, int nb, MeshDims md, const int32_t* __restrict__ st_k,
+                                                     const int32_t* __restrict__ st_m,
+                                                     const double* __restrict__ eps,
+                                                     const double* __restrict__ eps_all,
+                                                     const double* __restrict__ hw, ST* __restrict__ Bp,
+                                                     ST* __restrict__ Bm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int64_t i = e / M, j = e - i * M;
+  const int ki = st_k[i], kj = st_k[j], n = st_m[j];
+  const int ic = ki % md.n2, it = ki / md.n2, ib = it % md.n1, ia = it / md.n1;
+  const int jc = kj % md.n2, jt = kj / md.n2, jb = jt % md.n1, ja = jt / md.n1;
+  const double ei = eps[i];
+  double ej[27];
+  int qi[27];
+#pragma unroll
+  for (int p = 0; p < 27; ++p) {
+    int a = ja + p / 9 - 1, b = jb + (p / 3) % 3 - 1, c = jc + p % 3 - 1;
+    a += (a < 0) ? md.n0 : (a >= md.n0 ? -md.n0 : 0);
+    b += (b < 0) ? md.n1 : (b >= md.n1 ? -md.n1 : 0);
+    c += (c < 0) ? md.n2 : (c >= md.n2 ? -md.n2 : 0);
+    ej[p] = eps_all[(int64_t)((a * md.n1 + b) * md.n2 + c) * nb + n];
+    int qa = a - ia, qb = b - ib, qc = c - ic;
+    qa += qa < 0 ? md.n0 : 0;
+    qb += qb < 0 ? md.n1 : 0;
+    qc += qc < 0 ? md.n2 : 0;
+    qi[p] = (qa * md.n1 + qb) * md.n2 + qc;
+  }
+  for (int s = 0; s < NX; ++s) {
+    const int64_t t = e * NX + s;
+    const double bp = (double)Bp[t], bm = (double)Bm[t];
+    if (bp == 0.0 && bm == 0.0) continue;
+    double w[27];
+#pragma unroll
+    for (int p = 0; p < 27; ++p) w[p] = hw[(int64_t)qi[p] * NX + s];
+    double dp = 0.0, dm = 0.0;
+    tetra_all(ej, w, ei, dp, dm, std::make_integer_sequence<int, 24>{});
+    Bp[t] = (ST)(bp * dp);
+    Bm[t] = (ST)(bm * dm);
+  }
+}
+
+static void launch_tetra_scale(elph_ctx ctx, void* Bp, void* Bm, bool store_f64) {
+  const int64_t M = ctx->nstates;
+  const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
+  const dim3 grid(blocks_for(M * M, 256)), blk(256);
+#define TS(STT, NXV)                                                                                            \
+  hipLaunchKernelGGL((k_tetra_scale<STT, NXV>), grid, blk, 0, ctx->stream, M, ctx->nb, md, ctx->d_state_k,      \
+                     ctx->d_state_m, ctx->d_eps, ctx->d_eps_all, ctx->d_hw, (STT*)Bp, (STT*)Bm)
+#define TSN(STT)              \
+  switch (ctx->nbr) {         \
+    case 3: TS(STT, 3); break;   \
+    case 6: TS(STT, 6); break;   \
+    case 9: TS(STT, 9); break;   \
+    case 12: TS(STT, 12); break; \
+    default: TS(STT, 15); break; \
+  }
+  if (store_f64) {
+    TSN(double)
+  } else {
+    TSN(float)
+  }
+#undef TSN
+#undef TS
+}
+
 // Run both contractions and the epilogue.  Bp/Bm receive the term store
 // (double when store_f64, else float).  If th != nullptr the rates at that
 // temperature are accumulated into we_out [nstates] and wph_acc [nk][nbr]
@@ -1477,7 +1683,9 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     ep.fstate = th->f;
     ep.omf = th->omf;
     ep.nocc = th->nocc;
-    ep.we_part = ctx->d_we_part;
+    // with the tetrahedron delta W_e comes from the store rows once the
+    // weights are applied
+    ep.we_part = ep.tetra ? nullptr : ctx->d_we_part;
     ep.wph_acc = wph_acc;
   }
   if (ctx->precision == ELPH_FP64) {
@@ -1525,6 +1733,15 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     if (ep.tile_keep) mark(ctx, 5);
   }
   if (st != ELPH_OK) return st;
+  if (ep.tetra) {
+    launch_tetra_scale(ctx, Bp, Bm, store_f64);
+    if (th) {
+      if (store_f64) launch_we_rows<double>(ctx, (const double*)Bp, (const double*)Bm, th->lomf, th->nocc,
+                                            ctx->d_we_part);
+      else launch_we_rows<float>(ctx, (const float*)Bp, (const float*)Bm, th->lomf, th->nocc, ctx->d_we_part);
+      we_tiles = 1;
+    }
+  }
   if (th && we_out) {
     hipLaunchKernelGGL(k_reduce_we, dim3(blocks_for(ctx->nstates, 256)), dim3(256), 0, ctx->stream,
                        ctx->d_we_part, we_tiles, ctx->m_pad, ctx->nstates, we_out);

@@ -300,6 +300,76 @@ def test_iterate_16_bands_5_atoms(level):
     ctx.close()
 
 
+# analytic tetrahedron delta: the store, X+- and the rates against the oracle
+_tetra_ref = {}
+
+
+def tetra_ref(name):
+    if name not in _tetra_ref:
+        c = case(name)
+        Xp, Xm = c.prob.transition_probs(c.T, delta="tetra")
+        _tetra_ref[name] = (Xp, Xm, c.prob.rates_e(c.T, Xp, Xm), c.prob.rates_ph(c.T, Xp))
+    return _tetra_ref[name]
+
+
+@pytest.mark.parametrize("name", ["tiny4", "metal6"])
+def test_tetra_delta_transition_probs_and_rates(name):
+    c = case(name)
+    Xp_ref, Xm_ref, we_ref, wph_ref = tetra_ref(name)
+    ctx = make_ctx(c.cfg, c.mat)
+    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    sz = E.elph_sizes(ctx)
+    xp, xm = dtensor(sz["nterms"]), dtensor(sz["nterms"])
+    E.elph_transition_probs(ctx, c.T, xp, xm, 1)
+    we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
+    E.elph_scatt_rates(ctx, c.T, we, wph)
+    torch.cuda.synchronize()
+    # the tetrahedron weights divide by energy differences of a tetrahedron's
+    # corners, which magnify the 1e-15 differences of the two sides'
+    # eigenvalues: bars 1e-8 (1e-10 of the largest term absolutely)
+    ok_p, ep = term_ok(xp.cpu().numpy().reshape(Xp_ref.shape), Xp_ref, rtol=1e-8, atol_rel=1e-10)
+    ok_m, em = term_ok(xm.cpu().numpy().reshape(Xm_ref.shape), Xm_ref, rtol=1e-8, atol_rel=1e-10)
+    assert ok_p and ok_m, (ep, em)
+    assert rate_err(we.cpu().numpy(), we_ref) < 1e-8
+    assert rate_err(wph.cpu().numpy(), wph_ref) < 1e-8
+    # switching back gives the Gaussian store again
+    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_GAUSS)
+    E.elph_transition_probs(ctx, c.T, xp, xm, 0)
+    torch.cuda.synchronize()
+    ok, e = term_ok(xp.cpu().numpy().reshape(c.Xp.shape), c.Xp)
+    assert ok, e
+    with pytest.raises(E.ElphError):
+        E.elph_set_delta(ctx, 7)
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16x3"])
+def test_tetra_delta_forms(form):
+    c = case("metal6")
+    _, _, we_ref, wph_ref = tetra_ref("metal6")
+    ctx = make_ctx(c.cfg, c.mat, precision=form)
+    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    sz = E.elph_sizes(ctx)
+    we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
+    E.elph_scatt_rates(ctx, c.T, we, wph)
+    torch.cuda.synchronize()
+    w1, w2 = we.cpu().numpy(), wph.cpu().numpy()
+    e1, e2 = rate_err(w1, we_ref, 1e-6), rate_err(w2, wph_ref, 1e-6)
+    n1 = np.linalg.norm(w1 - we_ref) / np.linalg.norm(we_ref)
+    n2 = np.linalg.norm(w2 - wph_ref.ravel()) / np.linalg.norm(wph_ref)
+    assert e1 < 1e-5 and e2 < 1e-5 and n1 < 1e-6 and n2 < 1e-6, (e1, e2, n1, n2)
+    ctx.close()
+
+
+def test_tetra_delta_is_refused_by_batches():
+    c = case("tiny4")
+    ctx = make_ctx(c.cfg, c.mat, precision="fp32")
+    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    with pytest.raises(Exception):
+        E.Batch([ctx])
+    ctx.close()
+
+
 def test_ko_enforce_planted_lambda():
     # responses for which Eq. 35 holds at lambda = 0.8 (built from the oracle)
     c = case("metal6")

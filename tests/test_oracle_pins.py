@@ -526,3 +526,64 @@ def test_ko_enforce_minimises_the_mismatch_on_a_coupled_solution():
         t2 = oracle.transport_tensors(prob, T, I_diff + l2 * (I - I_diff), J, F, G)
         assert best <= mismatch(t2) * (1 + 1e-12)
     assert best <= mismatch(oracle.transport_tensors(prob, T, I, J, F, G))
+
+
+# ---------------------------------------------------------------------------
+# Analytic tetrahedron delta
+
+def _dos_closed_form(e):
+    """Density of states at 0 of one tetrahedron of volume 1/6 with linear E
+    (the standard piecewise closed forms of the linear tetrahedron method)."""
+    e1, e2, e3, e4 = np.sort(e)
+    V = 1.0 / 6.0
+    if 0 <= e1 or 0 >= e4:
+        return 0.0
+    if e2 >= 0:
+        return V * 3 * e1 ** 2 / ((e2 - e1) * (e3 - e1) * (e4 - e1))
+    if e3 <= 0:
+        return V * 3 * e4 ** 2 / ((e4 - e1) * (e4 - e2) * (e4 - e3))
+    return V / ((e3 - e1) * (e4 - e1)) * (3 * (e2 - e1) - 6 * e2
+                                          - 3 * (e3 - e1 + e4 - e2) * e2 ** 2 / ((e3 - e2) * (e4 - e2)))
+
+
+def test_tetra_weights_sum_to_the_tetrahedron_dos():
+    rng = np.random.default_rng(11)
+    e = rng.standard_normal((4000, 4))
+    w = oracle.tetra_delta_weights(e)
+    ref = np.array([_dos_closed_form(x) for x in e])
+    assert np.all(w >= 0)
+    assert np.abs(w.sum(1) - ref).max() <= 1e-13 * ref.max()
+    assert np.count_nonzero(ref) > 2000          # all three cases occur
+
+
+def test_tetra_corner_weights_against_quadrature():
+    # integral of a narrow Gaussian of E times the barycentric coordinate, on a
+    # fine midpoint grid of the reference tetrahedron (corners 0, x, y, z)
+    n = 240
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h
+    x, y, z = np.meshgrid(c, c, c, indexing="ij")
+    inside = x + y + z < 1.0
+    x, y, z = x[inside], y[inside], z[inside]
+    lam = np.stack([1 - x - y - z, x, y, z])
+    for e in ([-0.9, 0.4, 1.1, 2.0], [-1.3, -0.2, 0.7, 1.5], [-2.0, -1.1, -0.4, 0.8]):
+        e = np.array(e)
+        E = e[0] * lam[0] + e[1] * lam[1] + e[2] * lam[2] + e[3] * lam[3]
+        sig = 0.02
+        d = np.exp(-0.5 * (E / sig) ** 2) / (np.sqrt(2 * np.pi) * sig)
+        quad = (d[None, :] * lam).sum(1) * h ** 3
+        w = oracle.tetra_delta_weights(e)
+        assert np.abs(w - quad).max() <= 0.01 * w.max(), (e, w, quad)
+
+
+@pytest.mark.parametrize("axis,sign,t", [(0, 1, 0.0), (0, 1, 0.3), (1, -1, 0.55), (2, 1, 0.8), (2, -1, 0.1)])
+def test_tetra_neighbourhood_integrates_the_hat_function(axis, sign, t):
+    # for E = sign * x_axis - t (mesh units), the 24 corner weights of the
+    # centre add up to the integral of the centre's hat function over the
+    # plane E = 0, which is 1 - t for a plane at distance t from the centre
+    corners, centre = oracle.tetra_neighbourhood()
+    off = np.array([[a, b, c] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)], dtype=float)
+    E = sign * off[:, axis] - t
+    w = oracle.tetra_delta_weights(E[corners])
+    D = w[np.arange(24), centre].sum()
+    assert abs(D - (1.0 - t)) <= 1e-13
