@@ -1485,8 +1485,11 @@ static elph_status ensure_we_part(elph_ctx ctx) {
 // E with corner energies e (coarea: each triangle of the section E = 0
 // contributes its area times the mean of lambda_c over its corners, over
 // |grad E|; the value depends only on the corner energies, so the sorted
-// corners sit at 0, x, y, z)
+// corners sit at 0, x, y, z; a triangular section has the closed form of
+// the tetrahedron method's density of states)
 __device__ inline double tetra_delta_corner(double e0, double e1, double e2, double e3, int c) {
+  const int nneg = (e0 < 0.0) + (e1 < 0.0) + (e2 < 0.0) + (e3 < 0.0);
+  if (nneg == 0 || nneg == 4) return 0.0;  // the level misses the tetrahedron
   // sort (insertion order: equal energies keep corner order), carrying the
   // mark of corner c along
   double s0 = e0, s1 = e1, s2 = e2, s3 = e3;
@@ -1508,12 +1511,27 @@ __device__ inline double tetra_delta_corner(double e0, double e1, double e2, dou
   cs(s1, s2, m1, m2);
   cs(s2, s3, m2, m3);
   const int pc = m1 ? 1 : m2 ? 2 : m3 ? 3 : 0;
+  if (nneg == 1) {
+    // triangle on the edges from corner 0: the section's measure over |grad E|
+    // is s0^2 / (2 (s1-s0)(s2-s0)(s3-s0)); the crossing on edge (0, k) has
+    // lambda_0 = s_k / (s_k - s0) and lambda_k = -s0 / (s_k - s0)
+    const double d1 = s1 - s0, d2 = s2 - s0, d3 = s3 - s0;
+    const double tot = 0.5 * s0 * s0 / (d1 * d2 * d3);
+    const double l = pc == 0 ? s1 / d1 + s2 / d2 + s3 / d3 : -s0 / (pc == 1 ? d1 : pc == 2 ? d2 : d3);
+    return tot * l / 3.0;
+  }
+  if (nneg == 3) {
+    // triangle on the edges to corner 3, the mirror case
+    const double d0 = s3 - s0, d1 = s3 - s1, d2 = s3 - s2;
+    const double tot = 0.5 * s3 * s3 / (d0 * d1 * d2);
+    const double l = pc == 3 ? -s0 / d0 - s1 / d1 - s2 / d2 : s3 / (pc == 0 ? d0 : pc == 1 ? d1 : d2);
+    return tot * l / 3.0;
+  }
+  // quadrilateral section (two corners on each side): its two triangles'
+  // areas in the tetrahedron with the sorted corners at 0, x, y, z
   const double s[4] = {s0, s1, s2, s3};
   const double g0 = s1 - s0, g1 = s2 - s0, g2 = s3 - s0;
   const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
-  const int nneg = (s0 < 0.0) + (s1 < 0.0) + (s2 < 0.0) + (s3 < 0.0);
-  if (!(gn > 0.0) || nneg == 0 || nneg == 4) return 0.0;
-  // point of edge (a, b) with E = 0: position (x, y, z) and lambda of pc
   struct Pt {
     double x, y, z, l;
   };
@@ -1534,16 +1552,8 @@ __device__ inline double tetra_delta_corner(double e0, double e1, double e2, dou
     const double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
     return 0.5 * sqrt(cx * cx + cy * cy + cz * cz) * (A.l + B.l + C.l) / 3.0;
   };
-  double w;
-  if (nneg == 1) {
-    w = tri(cross(0, 1), cross(0, 2), cross(0, 3));
-  } else if (nneg == 3) {
-    w = tri(cross(0, 3), cross(1, 3), cross(2, 3));
-  } else {
-    const Pt q02 = cross(0, 2), q03 = cross(0, 3), q13 = cross(1, 3), q12 = cross(1, 2);
-    w = tri(q02, q03, q13) + tri(q02, q13, q12);  // the section's corners in cyclic order
-  }
-  return w / gn;
+  const Pt q02 = cross(0, 2), q03 = cross(0, 3), q13 = cross(1, 3), q12 = cross(1, 2);
+  return (tri(q02, q03, q13) + tri(q02, q13, q12)) / gn;  // the section's corners in cyclic order
 }
 
 // The 24 tetrahedra with a given mesh point as corner: the point's 3x3x3
