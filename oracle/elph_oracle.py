@@ -69,7 +69,7 @@ LEVEL_RTA, LEVEL_PARTIAL, LEVEL_DRAGLESS, LEVEL_COUPLED = 0, 1, 2, 3
 
 __all__ = [
     "HBAR_EVS", "KB_EVK", "E_CHARGE", "AMU_KG", "ANG_M", "C_PHONON", "SPIN_DEG",
-    "OMEGA_MIN_DEFAULT", "LEVEL_RTA", "LEVEL_PARTIAL", "LEVEL_DRAGLESS", "LEVEL_COUPLED",
+    "OMEGA_MIN_DEFAULT", "NAC_EV_A", "nac_images", "nac_term", "LEVEL_RTA", "LEVEL_PARTIAL", "LEVEL_DRAGLESS", "LEVEL_COUPLED",
     "mesh_points", "mesh_linear", "phases", "bloch_hamiltonian", "bloch_hamiltonian_grad",
     "electron_bands", "electron_velocities", "dynamical_matrix", "dynamical_matrix_grad",
     "phonon_modes", "phonon_velocities", "fermi_pair", "bose_pair", "gaussian_delta",
@@ -153,15 +153,74 @@ def electron_velocities(mat, kfrac, eps, U):
 # ----------------------------------------------------------------------------
 # phonons: Eq. 3 (D(q), short-range part), Eq. 5 (velocity)
 
+# e^2 / (eps_0 V) in eV / Angstrom^2 for V in Angstrom^3 is NAC_EV_A / V
+EPS0_SI = 8.8541878128e-12        # F / m
+NAC_EV_A = E_CHARGE / EPS0_SI / ANG_M   # e / eps_0 in eV Angstrom
+
+
+def nac_images(mat, qf):
+    """Cartesian images (1/Angstrom, 2 pi included) nearest Gamma of one
+    fractional q: coordinates folded into [-1/2, 1/2), and a coordinate of
+    exactly 1/2 taken at both +1/2 and -1/2 (reading: Eq. 4 is averaged over
+    the equally near images, which keeps it even in q)."""
+    f = np.asarray(qf, dtype=np.float64) - np.floor(np.asarray(qf, dtype=np.float64) + 0.5)
+    B = np.linalg.inv(np.asarray(mat["lat"], dtype=np.float64)).T     # rows b_i, a_i . b_j = delta_ij
+    imgs = [f]
+    for d in range(3):
+        if f[d] == -0.5:
+            imgs = imgs + [g + np.eye(3)[d] for g in imgs]
+    return [2.0 * np.pi * g @ B for g in imgs]
+
+
+def nac_term(mat, qfrac):
+    """Eq. 4, the non-analytic (dipole-dipole) part of D(q) for polar
+    materials, in the units of D (eV / (Angstrom^2 amu)):
+    (e^2 / (eps_0 V)) (q.Z_t)_a (q.Z_t')_b / (q.eps_inf.q) / sqrt(m_t m_t'),
+    with (q.Z_t)_b = sum_a q_a Z_t[a][b], at the image of q nearest Gamma
+    (averaged over equally near images, see nac_images).  Zero at Gamma
+    (reading: the direction-dependent limit is not taken on the mesh).
+    Returns (D_nac [nq, nbr, nbr], dD_nac/dq_cart [nq, 3, nbr, nbr])."""
+    Z = np.asarray(mat["zstar"], dtype=np.float64)               # [na, 3, 3]
+    eps = np.asarray(mat["eps_inf"], dtype=np.float64)
+    m = np.repeat(np.asarray(mat["mass"], dtype=np.float64), 3)    # per x
+    V = abs(np.linalg.det(np.asarray(mat["lat"], dtype=np.float64)))
+    qfrac = np.atleast_2d(np.asarray(qfrac, dtype=np.float64))
+    nq, na = qfrac.shape[0], Z.shape[0]
+    dZ = np.transpose(Z, (1, 0, 2)).reshape(3, 3 * na)             # d(q.Z)_x / dq_c
+    scale = NAC_EV_A / V / np.sqrt(np.outer(m, m))
+    D = np.zeros((nq, 3 * na, 3 * na))
+    G = np.zeros((nq, 3, 3 * na, 3 * na))
+    for k in range(nq):
+        imgs = nac_images(mat, qfrac[k])
+        for q in imgs:
+            Q = q @ eps @ q
+            if Q <= 0.0:
+                continue
+            A = (q @ Z.reshape(na, 3, 3).transpose(1, 0, 2).reshape(3, 3 * na))   # (q.Z_t)_b at x = 3t + b
+            epsq = eps @ q
+            D[k] += scale * np.outer(A, A) / Q / len(imgs)
+            for c in range(3):
+                G[k, c] += scale * ((np.outer(dZ[c], A) + np.outer(A, dZ[c])) / Q
+                                    - 2.0 * epsq[c] * np.outer(A, A) / Q ** 2) / len(imgs)
+    return D, G
+
+
 def dynamical_matrix(mat, qfrac):
-    """Eq. 3 without the non-analytic term: D(q) = sum_Rp w exp(i q.Rp) D(Rp)."""
-    return np.einsum("kr,rab->kab", phases(qfrac, mat["rp"], mat["wrp"]), mat["d_r"])
+    """Eq. 3: D(q) = sum_Rp w exp(i q.Rp) D(Rp), plus the non-analytic term
+    of Eq. 4 when the material carries Born charges ("zstar", "eps_inf")."""
+    D = np.einsum("kr,rab->kab", phases(qfrac, mat["rp"], mat["wrp"]), mat["d_r"])
+    if mat.get("zstar") is not None:
+        D = D + nac_term(mat, qfrac)[0]
+    return D
 
 
 def dynamical_matrix_grad(mat, qfrac):
     ph = phases(qfrac, mat["rp"], mat["wrp"])
     rc = _cart(mat, mat["rp"])
-    return np.einsum("kr,rc,rab->kcab", 1j * ph, rc, mat["d_r"])
+    G = np.einsum("kr,rc,rab->kcab", 1j * ph, rc, mat["d_r"])
+    if mat.get("zstar") is not None:
+        G = G + nac_term(mat, qfrac)[1]
+    return G
 
 
 def phonon_modes(mat, qfrac):

@@ -417,6 +417,66 @@ __global__ void k_x_inplace(int64_t M, int nbr, int n0, int n1, int n2, const in
   Xm[t] *= occ * (1.0 + n);
 }
 
+extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf) {
+  CHECK_CTX(ctx);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!zstar) {
+    if (ctx->d_nac) dev_free(ctx, ctx->d_nac);
+    ctx->d_nac = nullptr;
+    drop_derived(ctx);
+    return ELPH_OK;
+  }
+  if (!eps_inf) {
+    ctx->err = "eps_inf is required with zstar";
+    return ELPH_EINVAL;
+  }
+  const int na = ctx->na;
+  for (int k = 0; k < 9 * na; ++k)
+    if (!std::isfinite(zstar[k])) {
+      ctx->err = "zstar is not finite";
+      return ELPH_EINVAL;
+    }
+  const double* e = eps_inf;
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(e[k])) {
+      ctx->err = "eps_inf is not finite";
+      return ELPH_EINVAL;
+    }
+  const double scale = std::fabs(e[0]) + std::fabs(e[4]) + std::fabs(e[8]);
+  if (std::fabs(e[1] - e[3]) > 1e-12 * scale || std::fabs(e[2] - e[6]) > 1e-12 * scale ||
+      std::fabs(e[5] - e[7]) > 1e-12 * scale) {
+    ctx->err = "eps_inf must be symmetric";
+    return ELPH_EINVAL;
+  }
+  const double m1 = e[0], m2 = e[0] * e[4] - e[1] * e[3];
+  const double m3 = e[0] * (e[4] * e[8] - e[5] * e[7]) - e[1] * (e[3] * e[8] - e[5] * e[6]) +
+                    e[2] * (e[3] * e[7] - e[4] * e[6]);
+  if (!(m1 > 0.0 && m2 > 0.0 && m3 > 0.0)) {
+    ctx->err = "eps_inf must be positive definite";
+    return ELPH_EINVAL;
+  }
+  // reciprocal basis: rows b_i with a_i . b_j = delta_ij, times 2 pi
+  const double* L = ctx->lat;
+  const double det = L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
+                     L[2] * (L[3] * L[7] - L[4] * L[6]);
+  std::vector<double> h(9 * na + 18);
+  std::memcpy(h.data(), zstar, 9 * na * sizeof(double));
+  std::memcpy(h.data() + 9 * na, eps_inf, 9 * sizeof(double));
+  double* B = h.data() + 9 * na + 9;
+  for (int i = 0; i < 3; ++i) {
+    const double* a1 = L + 3 * ((i + 1) % 3);
+    const double* a2 = L + 3 * ((i + 2) % 3);
+    B[3 * i + 0] = 2.0 * kPi * (a1[1] * a2[2] - a1[2] * a2[1]) / det;
+    B[3 * i + 1] = 2.0 * kPi * (a1[2] * a2[0] - a1[0] * a2[2]) / det;
+    B[3 * i + 2] = 2.0 * kPi * (a1[0] * a2[1] - a1[1] * a2[0]) / det;
+  }
+  drop_derived(ctx);
+  if (!ctx->d_nac) ALLOC(ctx->d_nac, h.size() * sizeof(double));
+  HIPCHK(hipMemcpy(ctx->d_nac, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  ctx->nac_coef = kCharge / (kEps0 * ctx->volume_A3) * 1e10;
+  return ELPH_OK;
+}
+
 extern "C" elph_status elph_set_delta(elph_ctx ctx, int32_t method) {
   CHECK_CTX(ctx);
   if (method != ELPH_DELTA_GAUSS && method != ELPH_DELTA_TETRA) {

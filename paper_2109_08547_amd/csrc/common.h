@@ -18,6 +18,7 @@ constexpr double kAmuKg = 1.66053906660e-27;     // kg
 constexpr double kAngM = 1.0e-10;                // m / Angstrom
 constexpr double kSpinDeg = 2.0;
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kEps0 = 8.8541878128e-12;         // F / m
 // (hbar omega)^2 [eV^2] = kPhononC [eV] * lambda [eV/(A^2 amu)]
 constexpr double kHbarJs = kHbarEVs * kCharge;
 constexpr double kPhononC = kHbarJs * kHbarJs / (kAmuKg * kAngM * kAngM) / kCharge;
@@ -81,6 +82,8 @@ struct elph_ctx_s {
   double* d_gr = nullptr;    // [nre][nrp][nbr][nb][nb] complex (as given)
   double* d_mass_x = nullptr;  // [nbr] mass of the atom of each x
   double* d_lat = nullptr;   // [9]
+  double* d_nac = nullptr;   // polar materials: Z* [na][3][3], eps_inf [3][3], 2 pi b_i rows [3][3] (null: none)
+  double nac_coef = 0;       // e^2 / (eps_0 V), eV / Angstrom^2
   double2* d_tab[3] = {nullptr, nullptr, nullptr};  // per-axis exp(2 pi i j / N)
   int32_t* d_qrep = nullptr;                          // mesh points q with q <= -q (one of each +-q pair)
   int64_t nqrep = 0;

@@ -6,7 +6,8 @@
 //  * the transport window and its compaction into kept k and active states,
 //  * band and branch velocities (Eqs. 2 and 5) and the phonon factors of
 //    Eq. 6 (l_{x,s} u_q[x,s], with l = sqrt(C / (2 M hbar omega))), the
-//    phonons diagonalised at one q of each +-q pair (time reversal).
+//    phonons diagonalised at one q of each +-q pair (time reversal), with
+//    the non-analytic term of Eq. 4 for polar materials.
 #include "devutil.h"
 #include "tables.h"
 
@@ -635,6 +636,71 @@ __global__ void k_max_reduce(const double* __restrict__ x, int64_t n, double* __
   if (threadIdx.x == 0) out[blockIdx.x] = s[0];
 }
 
+// Eq. 4, the non-analytic (dipole-dipole) part of D(q) for polar materials,
+// added to the chunk's D and its Cartesian gradient: coef (q.Z_t)_a
+// (q.Z_t')_b / (q.eps.q) / sqrt(m_t m_t') with (q.Z_t)_b = sum_a q_a Z_t[a][b],
+// q the image of the mesh point nearest Gamma (fractional coordinates in
+// [-1/2, 1/2), 2 pi included), averaged over the two images of a coordinate
+// at exactly 1/2 so that the term stays even in q; nothing at Gamma.
+// Thread per (point, x, y).
+__global__ void k_nac_add(int64_t npts, int nbr, MeshDims md, const int32_t* __restrict__ pts,
+                          const double* __restrict__ nac, double coef, const double* __restrict__ mass_x,
+                          cd* __restrict__ D, cd* __restrict__ G) {
+  const int64_t nn = (int64_t)nbr * nbr;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npts * nn) return;
+  const int64_t p = e / nn;
+  const int xy = (int)(e - p * nn), x = xy / nbr, y = xy - x * nbr;
+  const int na = nbr / 3;
+  const int tx = x / 3, ax = x % 3, ty = y / 3, ay = y % 3;
+  const double* Z = nac;
+  const double* eps = nac + 9 * na;
+  const double* B = eps + 9;
+  const int64_t k = pts[p];
+  const int c = (int)(k % md.n2), t = (int)(k / md.n2), b = t % md.n1, a = t / md.n1;
+  const int idx[3] = {a, b, c}, nd[3] = {md.n0, md.n1, md.n2};
+  double f[3];
+  bool half[3];
+  int nimg = 1;
+  for (int d = 0; d < 3; ++d) {
+    half[d] = 2 * idx[d] == nd[d];
+    f[d] = (double)idx[d] / nd[d];
+    if (2 * idx[d] >= nd[d]) f[d] -= 1.0;
+    if (half[d]) nimg *= 2;
+  }
+  const double s = coef / sqrt(mass_x[x] * mass_x[y]) / nimg;
+  double dsum = 0.0, gsum[3] = {0.0, 0.0, 0.0};
+  for (int im = 0; im < 8; ++im) {
+    // image im: bit d set moves a coordinate at -1/2 to +1/2
+    bool skip = false;
+    double g[3];
+    for (int d = 0; d < 3; ++d) {
+      const bool up = (im >> d) & 1;
+      if (up && !half[d]) skip = true;
+      g[d] = f[d] + (up ? 1.0 : 0.0);
+    }
+    if (skip) continue;
+    double q[3];
+    for (int d = 0; d < 3; ++d) q[d] = g[0] * B[d] + g[1] * B[3 + d] + g[2] * B[6 + d];
+    double eq[3], Q = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      eq[d] = eps[3 * d] * q[0] + eps[3 * d + 1] * q[1] + eps[3 * d + 2] * q[2];
+      Q += q[d] * eq[d];
+    }
+    if (!(Q > 0.0)) continue;
+    double A = 0.0, Bv = 0.0;  // (q.Z_tx)_ax, (q.Z_ty)_ay
+    for (int d = 0; d < 3; ++d) {
+      A += q[d] * Z[(tx * 3 + d) * 3 + ax];
+      Bv += q[d] * Z[(ty * 3 + d) * 3 + ay];
+    }
+    dsum += A * Bv / Q;
+    for (int d = 0; d < 3; ++d)
+      gsum[d] += (Z[(tx * 3 + d) * 3 + ax] * Bv + A * Z[(ty * 3 + d) * 3 + ay]) / Q - 2.0 * eq[d] * A * Bv / (Q * Q);
+  }
+  D[p * nn + xy].x += s * dsum;
+  for (int d = 0; d < 3; ++d) G[(p * 3 + d) * nn + xy].x += s * gsum[d];
+}
+
 // ---------------------------------------------------------------------------
 // host drivers
 
@@ -742,6 +808,9 @@ elph_status build_tables(elph_ctx ctx) {
     const int64_t cnt = (ctx->nqrep - r0 < chunk) ? ctx->nqrep - r0 : chunk;
     const int32_t* pts = ctx->d_qrep + r0;  // one q of each +-q pair; -q follows by time reversal
     launch_fourier<true, true>(ctx, pts, 0, cnt, ctx->d_rp, ctx->d_wrp, ctx->nrp, ctx->d_dr, nbr, hbuf, gbuf);
+    if (ctx->d_nac)
+      hipLaunchKernelGGL(k_nac_add, dim3(blocks_for(cnt * nbr * nbr, 256)), dim3(256), 0, s, cnt, nbr, md, pts,
+                         ctx->d_nac, ctx->nac_coef, ctx->d_mass_x, hbuf, gbuf);
     launch_jacobi(hbuf, cnt, nbr, lam, ubuf, s);
     hipLaunchKernelGGL(k_phonon_hw_L, dim3(blocks_for(cnt * nbr * nbr, 256)), dim3(256), 0, s, cnt, nbr, md, pts,
                        lam, ubuf, ctx->d_mass_x, ctx->omega_min, ctx->d_hw, (cd*)ctx->d_Lq);

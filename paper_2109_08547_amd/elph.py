@@ -45,7 +45,7 @@ class ElphSizes(ctypes.Structure):
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
            "elph_batch_tune", "elph_tables",
-           "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta",
+           "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
            "elph_mlp_create", "elph_mlp_destroy", "elph_mlp_last_error", "elph_mlp_nparams",
            "elph_mlp_get_params", "elph_mlp_set_params", "elph_mlp_forward", "elph_mlp_gradients",
            "elph_mlp_train_step", "elph_screen_nin", "elph_screen_samples", "elph_scatt_rates_screened")
@@ -83,6 +83,7 @@ def load():
                                  vp, vp, vp, vp, vp, vp, vp]
     lib.elph_ko_enforce.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp]
     lib.elph_set_delta.argtypes = [vp, ctypes.c_int32]
+    lib.elph_set_polar.argtypes = [vp, vp, vp]
     lib.elph_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.elph_batch_destroy.argtypes = [vp]
     lib.elph_batch_destroy.restype = None
@@ -248,6 +249,17 @@ ELPH_DELTA_GAUSS, ELPH_DELTA_TETRA = 0, 1
 def elph_set_delta(ctx, method):
     """Energy-conserving delta of Eq. 8: ELPH_DELTA_GAUSS or ELPH_DELTA_TETRA."""
     _check(ctx, load().elph_set_delta(ctx.handle, int(method)))
+
+
+def elph_set_polar(ctx, zstar, eps_inf):
+    """Born charges zstar [natom][3][3] and eps_inf [3][3] (host arrays) for
+    the non-analytic term of Eq. 4; zstar=None removes it."""
+    if zstar is None:
+        _check(ctx, load().elph_set_polar(ctx.handle, None, None))
+        return
+    z = np.ascontiguousarray(zstar, dtype=np.float64)
+    e = np.ascontiguousarray(eps_inf, dtype=np.float64)
+    _check(ctx, load().elph_set_polar(ctx.handle, z.ctypes.data_as(ctypes.c_void_p), e.ctypes.data_as(ctypes.c_void_p)))
 
 
 def elph_ko_enforce(ctx, T, I, J, F, G):

@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
 
 This package only draws random numbers and assembles the Wannier-space input
-arrays (Hamiltonian H(R_e), force constants D(R_p), vertex g(R_e, R_p)); it
+arrays (Hamiltonian H(R_e), force constants D(R_p), vertex g(R_e, R_p), and
+for polar materials Born charges and the dielectric tensor); it
 holds none of the method's arithmetic (no Fourier sums, no eigensolves, no
 transition probabilities).  Calibrated scale parameters (band gap offset,
 Hamiltonian scale, force-constant scale, chemical potential) are stored in
@@ -9,6 +10,6 @@ Hamiltonian scale, force-constant scale, chemical potential) are stored in
 """
 from . import mlp  # noqa: F401
 from .materials import (  # noqa: F401
-    rset_cube, rset_sphere, make_material, config, config_names, material_for,
+    rset_cube, rset_sphere, make_material, config, config_names, material_for, polar_params,
     MASS_CYCLE, LATTICE_A,
 )

@@ -237,3 +237,17 @@ def material_for(cfg, **overrides):
     return make_material(nb=c["nb"], na=c["na"], seed=c["seed"], rset_e=_rset(c["rset"]),
                          rset_b=_rset(c["rset_b"]), L=c["L"], s_H=c["s_H"],
                          delta=c["delta"], c_D=c["c_D"], with_g=c.get("with_g", True))
+
+
+def polar_params(na, seed, z0=2.0, eps0=8.0):
+    """Seeded Born effective charges Z*[na][3][3] (random anisotropic parts,
+    sum over atoms zero: charge neutrality) and a symmetric positive definite
+    high-frequency dielectric tensor near eps0 (a polar material's inputs)."""
+    rng = np.random.default_rng(seed)
+    Z = np.zeros((na, 3, 3))
+    for t in range(na):
+        Z[t] = (z0 if t % 2 == 0 else -z0) * np.eye(3) + 0.3 * rng.standard_normal((3, 3))
+    Z -= Z.mean(axis=0, keepdims=True)
+    A = 0.5 * rng.standard_normal((3, 3))
+    eps = eps0 * np.eye(3) + 0.5 * (A + A.T)
+    return Z, eps

@@ -300,6 +300,49 @@ def test_iterate_16_bands_5_atoms(level):
     ctx.close()
 
 
+# polar material: the non-analytic term of Eq. 4 in the phonon tables and
+# everything downstream
+_polar = {}
+
+
+def polar_case():
+    if "metal6" not in _polar:
+        cfg = synth.config("metal6")
+        mat = dict(synth.material_for(cfg))
+        mat["zstar"], mat["eps_inf"] = synth.polar_params(int(mat["natom"]), 7)
+        _polar["metal6"] = Case("metal6", mat=mat, cfg=cfg)
+    return _polar["metal6"]
+
+
+def test_polar_tables_and_rates():
+    c = polar_case()
+    p = c.prob
+    ctx = make_ctx(c.cfg, c.mat)
+    E.elph_set_polar(ctx, c.mat["zstar"], c.mat["eps_inf"])
+    sz = E.elph_sizes(ctx)
+    M, nm = sz["nstates"], sz["nk"] * sz["nbr"]
+    hw, vph = dtensor(nm), dtensor(3 * nm)
+    E.elph_tables(ctx, None, None, None, None, hw, vph)
+    we, wph = dtensor(M), dtensor(nm)
+    E.elph_scatt_rates(ctx, c.T, we, wph)
+    torch.cuda.synchronize()
+    assert np.abs(hw.cpu().numpy().reshape(-1, sz["nbr"]) ** 2 - p.hw ** 2).max() < 1e-12 * p.hw.max() ** 2
+    vp = vph.cpu().numpy().reshape(-1, sz["nbr"], 3)
+    assert np.abs(vp - p.v_ph).max() < 1e-8 * np.abs(p.v_ph).max()
+    assert rate_err(we.cpu().numpy(), c.we) < 1e-10
+    assert rate_err(wph.cpu().numpy(), c.wph) < 1e-10
+    # the term changes the phonons (LO-TO splitting) and is removed again
+    plain = case("metal6")
+    assert np.abs(p.hw - plain.prob.hw).max() > 1e-4
+    E.elph_set_polar(ctx, None, None)
+    E.elph_tables(ctx, None, None, None, None, hw, vph)
+    torch.cuda.synchronize()
+    assert np.abs(hw.cpu().numpy().reshape(-1, sz["nbr"]) ** 2 - plain.prob.hw ** 2).max() < 1e-12 * plain.prob.hw.max() ** 2
+    with pytest.raises(E.ElphError):
+        E.elph_set_polar(ctx, c.mat["zstar"], -np.eye(3))
+    ctx.close()
+
+
 # analytic tetrahedron delta: the store, X+- and the rates against the oracle
 _tetra_ref = {}
 

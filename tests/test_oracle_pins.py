@@ -587,3 +587,69 @@ def test_tetra_neighbourhood_integrates_the_hat_function(axis, sign, t):
     w = oracle.tetra_delta_weights(E[corners])
     D = w[np.arange(24), centre].sum()
     assert abs(D - (1.0 - t)) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Non-analytic (dipole-dipole) term of polar materials (Eq. 4)
+
+def _polar_mat(isotropic=False):
+    cfg = synth.config("metal6")
+    mat = dict(synth.material_for(cfg))
+    Z, eps = synth.polar_params(int(mat["natom"]), 7)
+    if isotropic:
+        Z = np.stack([(2.0 if t % 2 == 0 else -2.0) * np.eye(3) for t in range(int(mat["natom"]))])
+        eps = 6.0 * np.eye(3)
+    mat["zstar"], mat["eps_inf"] = Z, eps
+    return mat
+
+
+def test_nac_lo_to_splitting_of_a_diatomic_ionic_model():
+    # isotropic Z = +-z, eps_inf = e I: the dipole term moves one mode (the
+    # longitudinal optical one, displacements +-q_hat / sqrt(m)) by
+    # (e^2 / (eps_0 V)) z^2 (1/m1 + 1/m2) / e, whatever the direction of q
+    mat = _polar_mat(isotropic=True)
+    assert int(mat["natom"]) == 2
+    m1, m2 = mat["mass"]
+    V = abs(np.linalg.det(np.asarray(mat["lat"])))
+    want = oracle.NAC_EV_A / V * 4.0 * (1 / m1 + 1 / m2) / 6.0
+    rng = np.random.default_rng(2)
+    q = rng.uniform(-0.4, 0.4, (6, 3))
+    D, _ = oracle.nac_term(mat, q)
+    for k in range(q.shape[0]):
+        lam = np.sort(np.linalg.eigvalsh(D[k]))
+        assert abs(lam[-1] - want) <= 1e-12 * want
+        assert np.abs(lam[:-1]).max() <= 1e-12 * want
+    # unchanged by the length of q and by q -> -q; zero at Gamma
+    assert np.allclose(oracle.nac_term(mat, 0.5 * q)[0], D, rtol=1e-12, atol=0)
+    assert np.allclose(oracle.nac_term(mat, -q)[0], D, rtol=1e-12, atol=0)
+    assert not np.any(oracle.nac_term(mat, np.zeros((1, 3)))[0])
+
+
+def test_nac_gradient_against_finite_differences():
+    mat = _polar_mat()
+    lat = np.asarray(mat["lat"])
+    rng = np.random.default_rng(4)
+    q = rng.uniform(-0.3, 0.3, (4, 3))
+    _, G = oracle.nac_term(mat, q)
+    h = 1e-6
+    for c in range(3):
+        dq = np.zeros(3)
+        dq[c] = h
+        # a Cartesian step h is the fractional step h a_c / (2 pi)
+        df = dq @ lat.T / (2.0 * np.pi)
+        Dp, _ = oracle.nac_term(mat, q + df)
+        Dm, _ = oracle.nac_term(mat, q - df)
+        fd = (Dp - Dm) / (2 * h)
+        assert np.abs(G[:, c] - fd).max() <= 1e-6 * np.abs(G).max()
+
+
+def test_polar_phonons_keep_time_reversal_and_the_acoustic_sum():
+    # D(-q) = D(q)^* still holds with the term; at Gamma it adds nothing, so
+    # the three acoustic modes stay at zero
+    mat = _polar_mat()
+    q = np.array([[0.25, -0.125, 0.375], [0.5, 0.25, -0.125], [0.5, 0.5, 0.375], [0.0, 0.0, 0.0]])
+    D = oracle.dynamical_matrix(mat, q)
+    Dm = oracle.dynamical_matrix(mat, -q)
+    assert np.abs(Dm - np.conj(D)).max() <= 1e-12 * np.abs(D).max()
+    hw, _ = oracle.phonon_modes(mat, q[3:])
+    assert np.sort(hw[0])[:3].max() < 1e-5
