@@ -188,18 +188,25 @@ elph_status elph_tables(elph_ctx ctx, int32_t* state_k, int32_t* state_m, double
 elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
                           const int32_t* qidx, double* g_out);
 
-/* Polar materials (Eq. 4): the non-analytic dipole-dipole term
+/* Polar materials.  Eq. 4: the non-analytic dipole-dipole term
  * (e^2 / (eps_0 V)) (q.Z_t)_a (q.Z_t')_b / (q.eps_inf.q) / sqrt(m_t m_t') is
  * added to D(q) (and its gradient to the velocities of Eq. 5), with
  * (q.Z_t)_b = sum_a q_a Z_t[a][b] and q the Cartesian image of the mesh
  * point nearest Gamma (averaged over the two images of a fractional
- * coordinate of exactly 1/2); nothing is added at Gamma.  zstar
- * [natom][3][3] (units of e) and eps_inf [3][3] (symmetric positive
- * definite) are host arrays, copied; zstar = NULL removes the term.  Drops
- * every derived table and the vertex store (as ELPH_RESET_ALL).  The
- * long-range Froehlich part of the vertex (Eq. 7) is not added.  EINVAL for
- * non-finite input or an eps_inf that is not symmetric positive definite. */
-elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf);
+ * coordinate of exactly 1/2); nothing is added at Gamma.  Eq. 7 (when tau
+ * is given): the long-range Froehlich vertex F_s(q) [U_k' U_k^+]_{nm} is
+ * added to g of Eq. 6 (store, rates, iteration and elph_interp_g), with
+ * F_s(q) = i (e^2 / (eps_0 V)) sum_t sum_{G != -q} ((q+G).Z_t.l u_t,s)
+ * / ((q+G).eps_inf.(q+G)) exp(-i (q+G).r_t) exp(-(q+G).eps_inf.(q+G) / (4 alpha)),
+ * alpha = 1 Bohr^-2, summed over every G with (q+G).eps_inf.(q+G)/(4 alpha)
+ * <= 40, and [U_k' U_k^+]_{nm} the overlap of the two states' eigenvectors
+ * in the Wannier basis.  zstar [natom][3][3] (units of e), eps_inf [3][3]
+ * (symmetric positive definite) and tau [natom][3] (Cartesian atom
+ * positions, Angstrom; NULL: Eq. 4 only) are host arrays, copied;
+ * zstar = NULL removes both terms.  Drops every derived table and the
+ * vertex store (as ELPH_RESET_ALL).  EINVAL for non-finite input or an
+ * eps_inf that is not symmetric positive definite. */
+elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf, const double* tau);
 
 /* Select the energy-conserving delta of Eq. 8 for this context's later
  * vertex stores (the paper offers the triangle and the analytic

@@ -69,7 +69,7 @@ LEVEL_RTA, LEVEL_PARTIAL, LEVEL_DRAGLESS, LEVEL_COUPLED = 0, 1, 2, 3
 
 __all__ = [
     "HBAR_EVS", "KB_EVK", "E_CHARGE", "AMU_KG", "ANG_M", "C_PHONON", "SPIN_DEG",
-    "OMEGA_MIN_DEFAULT", "NAC_EV_A", "nac_images", "nac_term", "LEVEL_RTA", "LEVEL_PARTIAL", "LEVEL_DRAGLESS", "LEVEL_COUPLED",
+    "OMEGA_MIN_DEFAULT", "NAC_EV_A", "nac_images", "nac_term", "frohlich_factor", "LEVEL_RTA", "LEVEL_PARTIAL", "LEVEL_DRAGLESS", "LEVEL_COUPLED",
     "mesh_points", "mesh_linear", "phases", "bloch_hamiltonian", "bloch_hamiltonian_grad",
     "electron_bands", "electron_velocities", "dynamical_matrix", "dynamical_matrix_grad",
     "phonon_modes", "phonon_velocities", "fermi_pair", "bose_pair", "gaussian_delta",
@@ -395,6 +395,50 @@ def g_bloch(mat, gW, Uk, Ukq, u_q, hw_q, omega_min=OMEGA_MIN_DEFAULT):
     return np.einsum("...xs,...xnm->...snm", lu, gh)
 
 
+BOHR_A = 0.529177210903           # Angstrom
+EWALD_ALPHA = 1.0 / BOHR_A ** 2    # 1 Bohr^-2 in Angstrom^-2
+EWALD_CUT = 40.0                   # terms with (q+G).eps.(q+G) / (4 alpha) above this are dropped
+
+
+def frohlich_factor(mat, qfrac, lu):
+    """Eq. 7 without its electron overlap: F_s(q) such that
+    g^Fr_{smn}(k, q) = F_s(q) [U_k' U_k^+]_{nm}, for the phonon factors
+    lu[q, x, s] = l_{x,s} u_{x,s}(q) (Angstrom) ->  [nq, nbr] complex, eV:
+    F_s(q) = i (e^2 / (eps_0 V)) sum_t sum_{G != -q} ((q+G).Z_t.lu_t,s)
+    / ((q+G).eps_inf.(q+G)) exp(-i (q+G).r_t) exp(-(q+G).eps_inf.(q+G) / (4 alpha)),
+    alpha = 1 Bohr^-2, over every G with (q+G).eps_inf.(q+G)/(4 alpha) <= 40
+    (reading: the Ewald-damped sum taken to where the damping is below
+    e^-40), q at its fractional coordinates (the sum over G makes it periodic)."""
+    Z = np.asarray(mat["zstar"], dtype=np.float64)
+    eps = np.asarray(mat["eps_inf"], dtype=np.float64)
+    tau = np.asarray(mat["tau"], dtype=np.float64)                # [na, 3] Angstrom
+    lat = np.asarray(mat["lat"], dtype=np.float64)
+    V = abs(np.linalg.det(lat))
+    B = 2.0 * np.pi * np.linalg.inv(lat).T                        # rows 2 pi b_i
+    na = Z.shape[0]
+    qfrac = np.atleast_2d(np.asarray(qfrac, dtype=np.float64))
+    lam_min = np.linalg.eigvalsh(eps).min()
+    gmax = np.sqrt(4.0 * EWALD_ALPHA * EWALD_CUT / lam_min)       # |q+G| bound
+    nmax = [int(np.ceil((gmax + np.linalg.norm(B, axis=1).sum()) * np.linalg.norm(lat[i]) / (2 * np.pi))) + 1
+            for i in range(3)]
+    grid = np.stack(np.meshgrid(*[np.arange(-n, n + 1) for n in nmax], indexing="ij"), -1).reshape(-1, 3)
+    out = np.zeros((qfrac.shape[0], lu.shape[-1]), dtype=np.complex128)
+    for k in range(qfrac.shape[0]):
+        qg = (qfrac[k][None, :] + grid) @ B                        # q + G, Cartesian
+        Q = np.einsum("ga,ab,gb->g", qg, eps, qg)
+        keep = (Q > 0.0) & (Q / (4.0 * EWALD_ALPHA) <= EWALD_CUT)
+        qg, Q = qg[keep], Q[keep]
+        damp = np.exp(-Q / (4.0 * EWALD_ALPHA)) / Q
+        acc = np.zeros(lu.shape[-1], dtype=np.complex128)
+        for t in range(na):
+            qZ = qg @ Z[t]                                         # [nG, 3]: (q+G).Z_t
+            proj = qZ @ lu[k, 3 * t:3 * t + 3, :]                  # [nG, nbr]
+            ph = np.exp(-1j * (qg @ tau[t])) * damp
+            acc += ph @ proj
+        out[k] = 1j * NAC_EV_A / V * acc
+    return out
+
+
 # ----------------------------------------------------------------------------
 # the whole problem on a mesh
 
@@ -467,7 +511,20 @@ class Problem:
             gW = g_wannier_factorised(self.mat, k, qs)
         g = g_bloch(self.mat, gW, self.U_kept[kidx][None], self.U_kept,
                     self.u[qmesh], self.hw[qmesh], self.omega_min)
+        if self.mat.get("zstar") is not None and self.mat.get("tau") is not None:
+            # Eq. 7: the long-range Froehlich part, F_s(q) [U_k' U_k^+]_{nm}
+            g = g + self.frohlich_g(self.U_kept[kidx][None], self.U_kept, qmesh)
         return np.abs(g) ** 2, qmesh
+
+    def frohlich_g(self, Uk, Ukq, qmesh):
+        """Eq. 7 for initial eigenvectors Uk and final Ukq [..., nb, nb] (columns)
+        at mesh q -> [..., nbr, nb(n), nb(m)]: F_s(q) times the overlap
+        sum_w conj(Ukq[w, n]) Uk[w, m] (the [U_k' U_k^+]_{nm} of the paper)."""
+        if not hasattr(self, "_frohlich"):
+            lu = phonon_lengths(self.mat, self.hw, self.omega_min) * self.u   # [nq, x, s]
+            self._frohlich = frohlich_factor(self.mat, self.kfrac, lu)
+        ov = np.einsum("...wn,...wm->...nm", np.conj(Ukq), Uk)
+        return self._frohlich[qmesh][..., :, None, None] * ov[..., None, :, :]
 
     # ---- Eq. 8
     def tetra_delta(self, i):

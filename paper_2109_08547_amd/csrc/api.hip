@@ -307,7 +307,8 @@ static void drop_derived(elph_ctx ctx) {
                    (void**)&ctx->d_gR,      (void**)&ctx->d_B2,        (void**)&ctx->d_Bp,
                    (void**)&ctx->d_Bm,      (void**)&ctx->d_we_part,   (void**)&ctx->d_order,
                    (void**)&ctx->d_goff,    (void**)&ctx->d_we_cache,  (void**)&ctx->d_wph_cache,
-                   (void**)&ctx->d_poff,    (void**)&ctx->d_plist};
+                   (void**)&ctx->d_poff,    (void**)&ctx->d_plist,     (void**)&ctx->d_frohlich,
+                   (void**)&ctx->d_ustate};
   for (void** p : ptrs) {
     dev_free(ctx, *p);
     *p = nullptr;
@@ -417,12 +418,13 @@ __global__ void k_x_inplace(int64_t M, int nbr, int n0, int n1, int n2, const in
   Xm[t] *= occ * (1.0 + n);
 }
 
-extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf) {
+extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf, const double* tau) {
   CHECK_CTX(ctx);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (!zstar) {
     if (ctx->d_nac) dev_free(ctx, ctx->d_nac);
     ctx->d_nac = nullptr;
+    ctx->frohlich = false;
     drop_derived(ctx);
     return ELPH_OK;
   }
@@ -459,7 +461,14 @@ extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const d
   const double* L = ctx->lat;
   const double det = L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
                      L[2] * (L[3] * L[7] - L[4] * L[6]);
-  std::vector<double> h(9 * na + 18);
+  if (tau)
+    for (int k = 0; k < 3 * na; ++k)
+      if (!std::isfinite(tau[k])) {
+        ctx->err = "tau is not finite";
+        return ELPH_EINVAL;
+      }
+  std::vector<double> h(9 * na + 18 + 3 * na, 0.0);
+  if (tau) std::memcpy(h.data() + 9 * na + 18, tau, 3 * na * sizeof(double));
   std::memcpy(h.data(), zstar, 9 * na * sizeof(double));
   std::memcpy(h.data() + 9 * na, eps_inf, 9 * sizeof(double));
   double* B = h.data() + 9 * na + 9;
@@ -471,9 +480,32 @@ extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const d
     B[3 * i + 2] = 2.0 * kPi * (a1[0] * a2[1] - a1[1] * a2[0]) / det;
   }
   drop_derived(ctx);
-  if (!ctx->d_nac) ALLOC(ctx->d_nac, h.size() * sizeof(double));
+  if (ctx->d_nac) dev_free(ctx, ctx->d_nac);
+  ctx->d_nac = nullptr;
+  ALLOC(ctx->d_nac, h.size() * sizeof(double));
   HIPCHK(hipMemcpy(ctx->d_nac, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
   ctx->nac_coef = kCharge / (kEps0 * ctx->volume_A3) * 1e10;
+  ctx->frohlich = tau != nullptr;
+  if (ctx->frohlich) {
+    // G box of the Ewald sum of Eq. 7: every G with (q+G).eps.(q+G) / (4 alpha) <= 40
+    // for any q of the cell has |q+G| <= sqrt(160 alpha / lambda_min(eps)), and
+    // |n_i| <= (|q+G| + sum |2 pi b|) |a_i| / (2 pi) + 1
+    // a positive lower bound of the smallest eigenvalue of eps_inf: the larger
+    // of Gershgorin's and det / trace^2 (the other two eigenvalues are below the trace)
+    double gersh = INFINITY;
+    for (int r = 0; r < 3; ++r)
+      gersh = std::min(gersh, e[4 * r] - std::fabs(e[3 * r + (r + 1) % 3]) - std::fabs(e[3 * r + (r + 2) % 3]));
+    const double tr = e[0] + e[4] + e[8];
+    const double lmin = std::max(gersh, m3 / (tr * tr));
+    const double alpha = 1.0 / (0.529177210903 * 0.529177210903);
+    const double gmax = std::sqrt(4.0 * alpha * 40.0 / lmin);
+    double bsum = 0.0;
+    for (int i = 0; i < 3; ++i) bsum += std::sqrt(B[3 * i] * B[3 * i] + B[3 * i + 1] * B[3 * i + 1] + B[3 * i + 2] * B[3 * i + 2]);
+    for (int i = 0; i < 3; ++i) {
+      const double al = std::sqrt(L[3 * i] * L[3 * i] + L[3 * i + 1] * L[3 * i + 1] + L[3 * i + 2] * L[3 * i + 2]);
+      ctx->fr_box[i] = (int)std::ceil((gmax + bsum) * al / (2.0 * kPi)) + 1;
+    }
+  }
   return ELPH_OK;
 }
 

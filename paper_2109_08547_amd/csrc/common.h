@@ -84,6 +84,10 @@ struct elph_ctx_s {
   double* d_lat = nullptr;   // [9]
   double* d_nac = nullptr;   // polar materials: Z* [na][3][3], eps_inf [3][3], 2 pi b_i rows [3][3] (null: none)
   double nac_coef = 0;       // e^2 / (eps_0 V), eV / Angstrom^2
+  bool frohlich = false;     // polar with atom positions: the Froehlich vertex of Eq. 7 (d_nac then ends with tau [na][3])
+  int fr_box[3] = {0, 0, 0}; // half widths of the G box of its Ewald sum
+  double* d_frohlich = nullptr;  // [nk][nbr] complex F_s(q) of Eq. 7 (eV)
+  double* d_ustate = nullptr;    // [nstates][nb] complex eigenvector of each active state (its column of U)
   double2* d_tab[3] = {nullptr, nullptr, nullptr};  // per-axis exp(2 pi i j / N)
   int32_t* d_qrep = nullptr;                          // mesh points q with q <= -q (one of each +-q pair)
   int64_t nqrep = 0;

@@ -574,7 +574,8 @@ __global__ void k_interp_stage2(int64_t np, int nrp, int64_t inner, const cd* __
 
 // g[p][s][n][m] = sum_x Lq[x][s] sum_{n',m'} conj(Ukq[n'][n]) gW[x][n'][m'] Uk[m'][m]
 __global__ void k_interp_stage3(int64_t np, int nb, int nbr, const cd* __restrict__ gW, const cd* __restrict__ Uk,
-                                const cd* __restrict__ Ukq, const cd* __restrict__ Lq, cd* __restrict__ out) {
+                                const cd* __restrict__ Ukq, const cd* __restrict__ Lq, const cd* __restrict__ Fr,
+                                cd* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)nbr * nb * nb;
   if (e >= np * per) return;
@@ -596,6 +597,12 @@ __global__ void k_interp_stage3(int64_t np, int nb, int nbr, const cd* __restric
       rot = cadd(rot, cmul(cconj(Ukq[p * nn + a * nb + n]), row));
     }
     acc = cadd(acc, cmul(l, rot));
+  }
+  if (Fr) {
+    // Eq. 7: F_s(q) times the overlap sum_w conj(Ukq[w][n]) Uk[w][m]
+    cd ov = cmake(0, 0);
+    for (int w = 0; w < nb; ++w) ov = cadd(ov, cmul(cconj(Ukq[p * nn + w * nb + n]), Uk[p * nn + w * nb + m]));
+    acc = cadd(acc, cmul(Fr[p * nbr + s], ov));
   }
   out[e] = acc;
 }
@@ -630,6 +637,8 @@ elph_status interp_g(elph_ctx ctx, int64_t np, const int32_t* kidx, const int32_
   ALLOC(Ukq, chunk * nn * sizeof(cd));
   ALLOC(u, chunk * mm * sizeof(cd));
   ALLOC(Lq, chunk * mm * sizeof(cd));
+  cd* Fr = nullptr;
+  if (ctx->frohlich) ALLOC(Fr, chunk * nbr * sizeof(cd));
   ALLOC(lam, chunk * nbr * sizeof(double));
   ALLOC(phe, chunk * ctx->nre * sizeof(cd));
   ALLOC(php, chunk * ctx->nrp * sizeof(cd));
@@ -660,8 +669,9 @@ elph_status interp_g(elph_ctx ctx, int64_t np, const int32_t* kidx, const int32_
                        cnt, ctx->nre, ncol, phe, (const cd*)ctx->d_gr, G1);
     hipLaunchKernelGGL(k_interp_stage2, dim3(blocks_for(cnt * inner, 256)), dim3(256), 0, s, cnt, ctx->nrp, inner,
                        php, G1, gW);
+    if (Fr) launch_frohlich(ctx, qp, cnt, Lq, Fr, s);
     hipLaunchKernelGGL(k_interp_stage3, dim3(blocks_for(cnt * inner, 256)), dim3(256), 0, s, cnt, nb, nbr, gW, Uk,
-                       Ukq, Lq, (cd*)g_out + p0 * inner);
+                       Ukq, Lq, (const cd*)Fr, (cd*)g_out + p0 * inner);
     HIPCHK(hipGetLastError());
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -671,6 +681,7 @@ elph_status interp_g(elph_ctx ctx, int64_t np, const int32_t* kidx, const int32_
   dev_free(ctx, Ukq);
   dev_free(ctx, u);
   dev_free(ctx, Lq);
+  if (Fr) dev_free(ctx, Fr);
   dev_free(ctx, lam);
   dev_free(ctx, phe);
   dev_free(ctx, php);

@@ -656,7 +656,7 @@ __global__ void k_nac_add(int64_t npts, int nbr, MeshDims md, const int32_t* __r
   const double* Z = nac;
   const double* eps = nac + 9 * na;
   const double* B = eps + 9;
-  const int64_t k = pts[p];
+  const int64_t k = pts ? (int64_t)pts[p] : p;
   const int c = (int)(k % md.n2), t = (int)(k / md.n2), b = t % md.n1, a = t / md.n1;
   const int idx[3] = {a, b, c}, nd[3] = {md.n0, md.n1, md.n2};
   double f[3];
@@ -698,7 +698,87 @@ __global__ void k_nac_add(int64_t npts, int nbr, MeshDims md, const int32_t* __r
       gsum[d] += (Z[(tx * 3 + d) * 3 + ax] * Bv + A * Z[(ty * 3 + d) * 3 + ay]) / Q - 2.0 * eq[d] * A * Bv / (Q * Q);
   }
   D[p * nn + xy].x += s * dsum;
-  for (int d = 0; d < 3; ++d) G[(p * 3 + d) * nn + xy].x += s * gsum[d];
+  if (G)
+    for (int d = 0; d < 3; ++d) G[(p * 3 + d) * nn + xy].x += s * gsum[d];
+}
+
+// Eq. 7 without its electron overlap: F_s(q) = i (e^2 / (eps_0 V)) sum_t
+// sum_{G != -q} ((q+G).Z_t.lu_t,s) / ((q+G).eps.(q+G)) exp(-i (q+G).r_t)
+// exp(-(q+G).eps.(q+G) / (4 alpha)), alpha = 1 Bohr^-2, over the G of a box
+// with (q+G).eps.(q+G) / (4 alpha) <= 40; lu = l u, the phonon factors of
+// Eq. 6 (Angstrom).  Thread per point; every G term serves all branches.
+constexpr double kBohrA = 0.529177210903;
+constexpr double kEwaldInv4a = kBohrA * kBohrA / 4.0;  // 1 / (4 alpha), Angstrom^2
+constexpr double kEwaldCut = 40.0;
+
+__global__ void __launch_bounds__(256) k_frohlich(int64_t npts, int nbr, MeshDims md, const int32_t* __restrict__ pts,
+                                                  const double* __restrict__ nac, double coef, int g0, int g1, int g2,
+                                                  const cd* __restrict__ Lq, cd* __restrict__ F) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const int na = nbr / 3;
+  const double* Z = nac;
+  const double* eps = nac + 9 * na;
+  const double* B = eps + 9;
+  const double* tau = B + 9;
+  const int64_t k = pts ? (int64_t)pts[p] : p;
+  const int c = (int)(k % md.n2), t = (int)(k / md.n2), b = t % md.n1, a = t / md.n1;
+  const double f[3] = {(double)a / md.n0, (double)b / md.n1, (double)c / md.n2};
+  const cd* lu = Lq + p * nbr * nbr;
+  double ar[15], ai[15];
+#pragma unroll
+  for (int s = 0; s < 15; ++s) ar[s] = ai[s] = 0.0;
+  for (int i = -g0; i <= g0; ++i)
+    for (int j = -g1; j <= g1; ++j)
+      for (int l = -g2; l <= g2; ++l) {
+        const double h0 = f[0] + i, h1 = f[1] + j, h2 = f[2] + l;
+        double qg[3];
+        for (int d = 0; d < 3; ++d) qg[d] = h0 * B[d] + h1 * B[3 + d] + h2 * B[6 + d];
+        double Q = 0.0;
+        for (int d = 0; d < 3; ++d) Q += qg[d] * (eps[3 * d] * qg[0] + eps[3 * d + 1] * qg[1] + eps[3 * d + 2] * qg[2]);
+        if (!(Q > 0.0) || Q * kEwaldInv4a > kEwaldCut) continue;
+        const double damp = exp(-Q * kEwaldInv4a) / Q;
+        for (int at = 0; at < na; ++at) {
+          const double arg = qg[0] * tau[3 * at] + qg[1] * tau[3 * at + 1] + qg[2] * tau[3 * at + 2];
+          double sn, cs;
+          sincos(arg, &sn, &cs);
+          const double pr = cs * damp, pi = -sn * damp;  // exp(-i arg) damp
+          double qZ[3];
+          for (int bb = 0; bb < 3; ++bb)
+            qZ[bb] = qg[0] * Z[(at * 3 + 0) * 3 + bb] + qg[1] * Z[(at * 3 + 1) * 3 + bb] + qg[2] * Z[(at * 3 + 2) * 3 + bb];
+#pragma unroll
+          for (int s = 0; s < 15; ++s) {
+            if (s < nbr) {
+              double xr = 0.0, xi = 0.0;
+              for (int bb = 0; bb < 3; ++bb) {
+                const cd u = lu[(3 * at + bb) * nbr + s];
+                xr += qZ[bb] * u.x;
+                xi += qZ[bb] * u.y;
+              }
+              ar[s] += pr * xr - pi * xi;
+              ai[s] += pr * xi + pi * xr;
+            }
+          }
+        }
+      }
+#pragma unroll
+  for (int s = 0; s < 15; ++s)
+    if (s < nbr) F[p * nbr + s] = cmake(-coef * ai[s], coef * ar[s]);  // i coef acc
+}
+
+__global__ void k_fill_ustate(int64_t M, int nb, const int32_t* __restrict__ st_kidx, const int32_t* __restrict__ st_m,
+                              const cd* __restrict__ U, cd* __restrict__ us) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * nb) return;
+  const int64_t i = e / nb;
+  const int w = (int)(e - i * nb);
+  us[e] = U[((int64_t)st_kidx[i] * nb + w) * nb + st_m[i]];
+}
+
+void launch_frohlich(elph_ctx ctx, const int32_t* pts, int64_t npts, const cd* Lq, cd* F, hipStream_t s) {
+  const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
+  hipLaunchKernelGGL(k_frohlich, dim3(blocks_for(npts, 256)), dim3(256), 0, s, npts, ctx->nbr, md, pts, ctx->d_nac,
+                     ctx->nac_coef, ctx->fr_box[0], ctx->fr_box[1], ctx->fr_box[2], Lq, F);
 }
 
 // ---------------------------------------------------------------------------
@@ -821,6 +901,16 @@ elph_status build_tables(elph_ctx ctx) {
   }
   HIPCHK(hipGetLastError());
 
+  // ---- Eq. 7 for polar materials: F_s(q) and the active states' eigenvectors
+  if (ctx->frohlich) {
+    ALLOC(ctx->d_frohlich, nk * nbr * sizeof(cd));
+    launch_frohlich(ctx, nullptr, nk, (const cd*)ctx->d_Lq, (cd*)ctx->d_frohlich, s);
+    ALLOC(ctx->d_ustate, ctx->nstates * nb * sizeof(cd));
+    hipLaunchKernelGGL(k_fill_ustate, dim3(blocks_for(ctx->nstates * nb, 256)), dim3(256), 0, s, ctx->nstates, nb,
+                       ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_U, (cd*)ctx->d_ustate);
+    HIPCHK(hipGetLastError());
+  }
+
   // ---- hw_max
   double* red = nullptr;
   ALLOC(red, 256 * sizeof(double));
@@ -882,9 +972,15 @@ elph_status make_axis_tables(elph_ctx ctx) {
 
 // H(k) (and optionally eigen-decomposition) for an arbitrary list of mesh points
 elph_status fourier_points(elph_ctx ctx, bool phonon, const int32_t* pts, int64_t npts, cd* out) {
-  if (phonon)
+  if (phonon) {
     launch_fourier<true, false>(ctx, pts, 0, npts, ctx->d_rp, ctx->d_wrp, ctx->nrp, ctx->d_dr, ctx->nbr, out,
                                 nullptr);
+    if (ctx->d_nac) {
+      const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
+      hipLaunchKernelGGL(k_nac_add, dim3(blocks_for(npts * ctx->nbr * ctx->nbr, 256)), dim3(256), 0, ctx->stream,
+                         npts, ctx->nbr, md, pts, ctx->d_nac, ctx->nac_coef, ctx->d_mass_x, out, (cd*)nullptr);
+    }
+  }
   else
     launch_fourier<false, false>(ctx, pts, 0, npts, ctx->d_re, ctx->d_wre, ctx->nre, ctx->d_hr, ctx->nb, out,
                                  nullptr);

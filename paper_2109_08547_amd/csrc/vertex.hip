@@ -494,7 +494,22 @@ struct EpiParams {
   const uint8_t* tile_keep;  // [m_pad/32][m_pad/32] computed tiles (null = all)
   double cscale;             // undoes the operand scales of the step-2 contraction (1 but in the FP16 form)
   int tetra;                 // 1: store pref |g|^2 without the delta (tetrahedron weights follow)
+  const cd* fr;              // [nk][nbr] Froehlich factors F_s(q) of Eq. 7 (null: not polar)
+  const cd* ust;             // [nstates][nb] eigenvector of each active state
+  int nb;
 };
+
+// overlap sum_w conj(U_j[w]) U_i[w] of two active states' eigenvectors (the
+// [U_k' U_k^+]_{nm} of Eq. 7)
+__device__ inline cd state_overlap(const cd* __restrict__ ust, int nb, int64_t i, int64_t j) {
+  double orr = 0.0, oi = 0.0;
+  for (int w = 0; w < nb; ++w) {
+    const cd a = ust[i * nb + w], b = ust[j * nb + w];
+    orr += b.x * a.x + b.y * a.y;
+    oi += b.x * a.y - b.y * a.x;
+  }
+  return cmake(orr, oi);
+}
 
 __device__ inline int q_of(int kj, int ki, int n0, int n1, int n2) {
   const unsigned uj = (unsigned)kj, ui = (unsigned)ki;
@@ -646,6 +661,7 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
       const double* hwq = ep.hw + q * NX;
       const double rij = want_rates ? exp(ep.lomf[j] - lomf_i) : 0.0;
       const int64_t tb = (i * ep.nstates + j) * NX;
+      const cd ov = ep.fr ? state_overlap(ep.ust, ep.nb, i, j) : cmake(0.0, 0.0);
 #pragma unroll
       for (int s = 0; s < NX; ++s) {
         double gr = 0.0, gi = 0.0;
@@ -662,6 +678,11 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
           }
           gr += l.x * ar - l.y * ai;
           gi += l.x * ai + l.y * ar;
+        }
+        if (ep.fr) {  // Eq. 7: F_s(q) times the overlap
+          const cd f = ep.fr[q * NX + s];
+          gr += f.x * ov.x - f.y * ov.y;
+          gi += f.x * ov.y + f.y * ov.x;
         }
         const double g2 = gr * gr + gi * gi;
         const double w = hwq[s];
@@ -1075,6 +1096,7 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
         }
         const double de = ep.eps[j] - ei;
         const int64_t tb = ((int64_t)i * ep.nstates + j) * NX;
+        const cd ov = ep.fr ? state_overlap(ep.ust, ep.nb, i, j) : cmake(0.0, 0.0);
         double bpv[NX], bmv[NX];
 #pragma unroll
         for (int s = 0; s < NX; ++s) {
@@ -1084,6 +1106,11 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
             const cd l = L[x * NX + s];
             gr += l.x * ar[x] - l.y * ai[x];
             gi += l.x * ai[x] + l.y * ar[x];
+          }
+          if (ep.fr) {  // Eq. 7: F_s(q) times the overlap
+            const cd f = ep.fr[q * NX + s];
+            gr += f.x * ov.x - f.y * ov.y;
+            gi += f.x * ov.y + f.y * ov.x;
           }
           const double g2 = gr * gr + gi * gi;
           const double w = hwq[s];
@@ -1440,6 +1467,9 @@ static EpiParams epi_params(elph_ctx ctx) {
   ep.n1 = ctx->mesh[1];
   ep.n2 = ctx->mesh[2];
   ep.tetra = ctx->delta == ELPH_DELTA_TETRA ? 1 : 0;
+  ep.fr = ctx->frohlich ? (const cd*)ctx->d_frohlich : nullptr;
+  ep.ust = (const cd*)ctx->d_ustate;
+  ep.nb = ctx->nb;
   // with the tetrahedron delta the store first holds 2 pi / (hbar N_k) |g|^2
   ep.pref = ep.tetra ? 2.0 * kPi / (kHbarEVs * (double)ctx->nk)
                      : 2.0 * kPi / (kHbarEVs * (double)ctx->nk) / (sqrt(2.0 * kPi) * ctx->sigma);

@@ -83,7 +83,7 @@ def load():
                                  vp, vp, vp, vp, vp, vp, vp]
     lib.elph_ko_enforce.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp]
     lib.elph_set_delta.argtypes = [vp, ctypes.c_int32]
-    lib.elph_set_polar.argtypes = [vp, vp, vp]
+    lib.elph_set_polar.argtypes = [vp, vp, vp, vp]
     lib.elph_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.elph_batch_destroy.argtypes = [vp]
     lib.elph_batch_destroy.restype = None
@@ -251,15 +251,19 @@ def elph_set_delta(ctx, method):
     _check(ctx, load().elph_set_delta(ctx.handle, int(method)))
 
 
-def elph_set_polar(ctx, zstar, eps_inf):
-    """Born charges zstar [natom][3][3] and eps_inf [3][3] (host arrays) for
-    the non-analytic term of Eq. 4; zstar=None removes it."""
+def elph_set_polar(ctx, zstar, eps_inf, tau=None):
+    """Born charges zstar [natom][3][3], eps_inf [3][3] and atom positions tau
+    [natom][3] (Angstrom; None: no Froehlich vertex) for Eqs. 4 and 7;
+    zstar=None removes both."""
     if zstar is None:
-        _check(ctx, load().elph_set_polar(ctx.handle, None, None))
+        _check(ctx, load().elph_set_polar(ctx.handle, None, None, None))
         return
     z = np.ascontiguousarray(zstar, dtype=np.float64)
     e = np.ascontiguousarray(eps_inf, dtype=np.float64)
-    _check(ctx, load().elph_set_polar(ctx.handle, z.ctypes.data_as(ctypes.c_void_p), e.ctypes.data_as(ctypes.c_void_p)))
+    t = None if tau is None else np.ascontiguousarray(tau, dtype=np.float64)
+    _check(ctx, load().elph_set_polar(ctx.handle, z.ctypes.data_as(ctypes.c_void_p),
+                                      e.ctypes.data_as(ctypes.c_void_p),
+                                      None if t is None else t.ctypes.data_as(ctypes.c_void_p)))
 
 
 def elph_ko_enforce(ctx, T, I, J, F, G):

@@ -239,15 +239,23 @@ def material_for(cfg, **overrides):
                          delta=c["delta"], c_D=c["c_D"], with_g=c.get("with_g", True))
 
 
-def polar_params(na, seed, z0=2.0, eps0=8.0):
+def polar_params(na, seed, z0=2.0, eps0=8.0, lat=None):
     """Seeded Born effective charges Z*[na][3][3] (random anisotropic parts,
     sum over atoms zero: charge neutrality) and a symmetric positive definite
-    high-frequency dielectric tensor near eps0 (a polar material's inputs)."""
+    high-frequency dielectric tensor near eps0 (a polar material's inputs);
+    with lat [3][3] (rows a_i, Angstrom) also Cartesian atom positions
+    [na][3] at seeded fractional coordinates."""
     rng = np.random.default_rng(seed)
+    if lat is not None:
+        frac = rng.uniform(0.0, 1.0, (na, 3))
+        frac[0] = 0.0
+        tau = frac @ np.asarray(lat, dtype=np.float64)
     Z = np.zeros((na, 3, 3))
     for t in range(na):
         Z[t] = (z0 if t % 2 == 0 else -z0) * np.eye(3) + 0.3 * rng.standard_normal((3, 3))
     Z -= Z.mean(axis=0, keepdims=True)
     A = 0.5 * rng.standard_normal((3, 3))
     eps = eps0 * np.eye(3) + 0.5 * (A + A.T)
+    if lat is not None:
+        return Z, eps, tau
     return Z, eps

@@ -309,7 +309,7 @@ def polar_case():
     if "metal6" not in _polar:
         cfg = synth.config("metal6")
         mat = dict(synth.material_for(cfg))
-        mat["zstar"], mat["eps_inf"] = synth.polar_params(int(mat["natom"]), 7)
+        mat["zstar"], mat["eps_inf"], mat["tau"] = synth.polar_params(int(mat["natom"]), 7, lat=mat["lat"])
         _polar["metal6"] = Case("metal6", mat=mat, cfg=cfg)
     return _polar["metal6"]
 
@@ -318,7 +318,7 @@ def test_polar_tables_and_rates():
     c = polar_case()
     p = c.prob
     ctx = make_ctx(c.cfg, c.mat)
-    E.elph_set_polar(ctx, c.mat["zstar"], c.mat["eps_inf"])
+    E.elph_set_polar(ctx, c.mat["zstar"], c.mat["eps_inf"], c.mat["tau"])
     sz = E.elph_sizes(ctx)
     M, nm = sz["nstates"], sz["nk"] * sz["nbr"]
     hw, vph = dtensor(nm), dtensor(3 * nm)
@@ -331,7 +331,24 @@ def test_polar_tables_and_rates():
     assert np.abs(vp - p.v_ph).max() < 1e-8 * np.abs(p.v_ph).max()
     assert rate_err(we.cpu().numpy(), c.we) < 1e-10
     assert rate_err(wph.cpu().numpy(), c.wph) < 1e-10
-    # the term changes the phonons (LO-TO splitting) and is removed again
+    # the vertex at arbitrary pairs carries the Froehlich part too
+    rng = np.random.default_rng(9)
+    kk = rng.integers(0, p.nk, 12).astype(np.int32)
+    qq = rng.integers(1, p.nk, 12).astype(np.int32)
+    g = torch.empty((12, p.nbr, p.nb, p.nb, 2), dtype=torch.float64, device=DEV)
+    E.elph_interp_g(ctx, torch.from_numpy(kk).to(DEV), torch.from_numpy(qq).to(DEV), g)
+    torch.cuda.synchronize()
+    g2 = (g.cpu().numpy() ** 2).sum(-1)
+    for t in range(12):
+        k, q = p.kfrac[kk[t]], p.kfrac[qq[t]]
+        gW = oracle.g_wannier_factorised(c.mat, k, q[None])[0]
+        _, Uk = oracle.electron_bands(c.mat, k[None])
+        _, Ukq = oracle.electron_bands(c.mat, (k + q)[None])
+        hwq, u = oracle.phonon_modes(c.mat, q[None])
+        ref = oracle.g_bloch(c.mat, gW, Uk[0], Ukq[0], u[0], hwq[0]) + p.frohlich_g(Uk[0], Ukq[0], qq[t])
+        ref = np.abs(ref) ** 2
+        assert np.abs(g2[t] - ref).max() <= 1e-9 * ref.max(), t
+    # the terms change the phonons (LO-TO splitting) and are removed again
     plain = case("metal6")
     assert np.abs(p.hw - plain.prob.hw).max() > 1e-4
     E.elph_set_polar(ctx, None, None)

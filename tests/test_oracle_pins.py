@@ -653,3 +653,31 @@ def test_polar_phonons_keep_time_reversal_and_the_acoustic_sum():
     assert np.abs(Dm - np.conj(D)).max() <= 1e-12 * np.abs(D).max()
     hw, _ = oracle.phonon_modes(mat, q[3:])
     assert np.sort(hw[0])[:3].max() < 1e-5
+
+
+def test_frohlich_factor_small_q_limit_and_periodicity():
+    # |q| F_s(q) tends to the G = 0 term i (e^2/eps_0 V) sum_t (q^.Z_t.lu_t,s)/(q^.eps.q^)
+    # as q -> 0 along q^ (the other terms stay bounded), and F is periodic
+    mat = _polar_mat()
+    mat["tau"] = np.array([[0.0, 0.0, 0.0], [1.3, 2.1, 0.7]])
+    na = int(mat["natom"])
+    rng = np.random.default_rng(6)
+    lu = rng.standard_normal((1, 3 * na, 3 * na)) + 1j * rng.standard_normal((1, 3 * na, 3 * na))
+    lat = np.asarray(mat["lat"])
+    V = abs(np.linalg.det(lat))
+    B = 2 * np.pi * np.linalg.inv(lat).T
+    d = np.array([0.3, -0.2, 0.5])
+    qhat = d @ B / np.linalg.norm(d @ B)
+    lim = np.zeros(3 * na, dtype=complex)
+    for t in range(na):
+        lim += (qhat @ mat["zstar"][t]) @ lu[0, 3 * t:3 * t + 3, :]
+    lim = 1j * oracle.NAC_EV_A / V * lim / (qhat @ mat["eps_inf"] @ qhat)
+    errs = []
+    for h in (1e-3, 1e-4):
+        F = oracle.frohlich_factor(mat, h * d[None, :], lu)[0]
+        errs.append(np.abs(np.linalg.norm(h * d @ B) * F - lim).max() / np.abs(lim).max())
+    assert errs[1] < 1e-3 and errs[1] < 0.2 * errs[0]
+    q = np.array([[0.25, -0.125, 0.375]])
+    F0 = oracle.frohlich_factor(mat, q, lu)
+    F1 = oracle.frohlich_factor(mat, q + np.array([[1.0, -2.0, 0.0]]), lu)
+    assert np.abs(F1 - F0).max() <= 1e-12 * np.abs(F0).max()
