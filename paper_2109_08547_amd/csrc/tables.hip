@@ -707,6 +707,9 @@ __global__ void k_nac_add(int64_t npts, int nbr, MeshDims md, const int32_t* __r
 // exp(-(q+G).eps.(q+G) / (4 alpha)), alpha = 1 Bohr^-2, over the G of a box
 // with (q+G).eps.(q+G) / (4 alpha) <= 40; lu = l u, the phonon factors of
 // Eq. 6 (Angstrom).  Thread per point; every G term serves all branches.
+// The box is walked in rows along the third reciprocal vector, where Q is
+// a quadratic in the row index (only its range inside the cutoff is
+// visited) and the phases advance by one fixed factor per step.
 constexpr double kBohrA = 0.529177210903;
 constexpr double kEwaldInv4a = kBohrA * kBohrA / 4.0;  // 1 / (4 alpha), Angstrom^2
 constexpr double kEwaldCut = 40.0;
@@ -725,45 +728,84 @@ __global__ void __launch_bounds__(256) k_frohlich(int64_t npts, int nbr, MeshDim
   const int c = (int)(k % md.n2), t = (int)(k / md.n2), b = t % md.n1, a = t / md.n1;
   const double f[3] = {(double)a / md.n0, (double)b / md.n1, (double)c / md.n2};
   const cd* lu = Lq + p * nbr * nbr;
-  double ar[15], ai[15];
+  const double qmax = kEwaldCut / kEwaldInv4a;  // (q+G).eps.(q+G) bound of the kept terms
+  // along a row of the box, q + G = P + l B2: Q(l) = qa l^2 + qb l + qc
+  double eB2[3];
+  for (int d = 0; d < 3; ++d) eB2[d] = eps[3 * d] * B[6] + eps[3 * d + 1] * B[7] + eps[3 * d + 2] * B[8];
+  const double qa = B[6] * eB2[0] + B[7] * eB2[1] + B[8] * eB2[2];
+  // per atom, W_t = sum_G w_G ((q+G).Z_t) with the complex weight
+  // w_G = exp(-i (q+G).r_t) exp(-Q/(4 alpha)) / Q; F_s = i coef sum_t W_t . lu_t,s
+  double wr[5][3], wi[5][3];
 #pragma unroll
-  for (int s = 0; s < 15; ++s) ar[s] = ai[s] = 0.0;
+  for (int at = 0; at < 5; ++at)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) wr[at][bb] = wi[at][bb] = 0.0;
   for (int i = -g0; i <= g0; ++i)
-    for (int j = -g1; j <= g1; ++j)
-      for (int l = -g2; l <= g2; ++l) {
-        const double h0 = f[0] + i, h1 = f[1] + j, h2 = f[2] + l;
-        double qg[3];
-        for (int d = 0; d < 3; ++d) qg[d] = h0 * B[d] + h1 * B[3 + d] + h2 * B[6 + d];
-        double Q = 0.0;
-        for (int d = 0; d < 3; ++d) Q += qg[d] * (eps[3 * d] * qg[0] + eps[3 * d + 1] * qg[1] + eps[3 * d + 2] * qg[2]);
-        if (!(Q > 0.0) || Q * kEwaldInv4a > kEwaldCut) continue;
-        const double damp = exp(-Q * kEwaldInv4a) / Q;
-        for (int at = 0; at < na; ++at) {
-          const double arg = qg[0] * tau[3 * at] + qg[1] * tau[3 * at + 1] + qg[2] * tau[3 * at + 2];
-          double sn, cs;
-          sincos(arg, &sn, &cs);
-          const double pr = cs * damp, pi = -sn * damp;  // exp(-i arg) damp
-          double qZ[3];
-          for (int bb = 0; bb < 3; ++bb)
-            qZ[bb] = qg[0] * Z[(at * 3 + 0) * 3 + bb] + qg[1] * Z[(at * 3 + 1) * 3 + bb] + qg[2] * Z[(at * 3 + 2) * 3 + bb];
+    for (int j = -g1; j <= g1; ++j) {
+      const double h0 = f[0] + i, h1 = f[1] + j;
+      double P[3];
+      for (int d = 0; d < 3; ++d) P[d] = h0 * B[d] + h1 * B[3 + d] + f[2] * B[6 + d];
+      double eP[3];
+      for (int d = 0; d < 3; ++d) eP[d] = eps[3 * d] * P[0] + eps[3 * d + 1] * P[1] + eps[3 * d + 2] * P[2];
+      const double qb = 2.0 * (B[6] * eP[0] + B[7] * eP[1] + B[8] * eP[2]);
+      const double qc = P[0] * eP[0] + P[1] * eP[1] + P[2] * eP[2];
+      // l range of Q(l) <= qmax (widened by one; every term is still tested)
+      const double disc = qb * qb - 4.0 * qa * (qc - qmax);
+      if (disc < 0.0) continue;
+      const double sq = sqrt(disc);
+      int l0 = (int)floor((-qb - sq) / (2.0 * qa)) - 1, l1 = (int)ceil((-qb + sq) / (2.0 * qa)) + 1;
+      l0 = l0 < -g2 ? -g2 : l0;
+      l1 = l1 > g2 ? g2 : l1;
+      if (l0 > l1) continue;
 #pragma unroll
-          for (int s = 0; s < 15; ++s) {
-            if (s < nbr) {
-              double xr = 0.0, xi = 0.0;
-              for (int bb = 0; bb < 3; ++bb) {
-                const cd u = lu[(3 * at + bb) * nbr + s];
-                xr += qZ[bb] * u.x;
-                xi += qZ[bb] * u.y;
-              }
-              ar[s] += pr * xr - pi * xi;
-              ai[s] += pr * xi + pi * xr;
+      for (int at = 0; at < 5; ++at) {
+        if (at >= na) break;
+        // exp(-i (P + l B2).r) from its value at l0 and the per-step factor
+        const double* r = tau + 3 * at;
+        const double br = B[6] * r[0] + B[7] * r[1] + B[8] * r[2];
+        double s0, c0, s1, c1;
+        sincos(P[0] * r[0] + P[1] * r[1] + P[2] * r[2] + l0 * br, &s0, &c0);
+        sincos(br, &s1, &c1);
+        double phr = c0, phi = -s0;
+        const double str = c1, sti = -s1;
+        // (q+G).Z_t = P.Z_t + l B2.Z_t
+        double pz[3], bz[3];
+        for (int bb = 0; bb < 3; ++bb) {
+          pz[bb] = P[0] * Z[(at * 3 + 0) * 3 + bb] + P[1] * Z[(at * 3 + 1) * 3 + bb] + P[2] * Z[(at * 3 + 2) * 3 + bb];
+          bz[bb] = B[6] * Z[(at * 3 + 0) * 3 + bb] + B[7] * Z[(at * 3 + 1) * 3 + bb] + B[8] * Z[(at * 3 + 2) * 3 + bb];
+        }
+        for (int l = l0; l <= l1; ++l) {
+          const double Q = (qa * l + qb) * l + qc;
+          if (Q > 0.0 && Q * kEwaldInv4a <= kEwaldCut) {
+            const double damp = exp(-Q * kEwaldInv4a) / Q;
+            const double pr = phr * damp, pi = phi * damp;
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) {
+              const double z = pz[bb] + l * bz[bb];
+              wr[at][bb] += pr * z;
+              wi[at][bb] += pi * z;
             }
           }
+          const double nr = phr * str - phi * sti;
+          phi = phr * sti + phi * str;
+          phr = nr;
         }
       }
+    }
+  for (int s = 0; s < nbr; ++s) {
+    double xr = 0.0, xi = 0.0;
 #pragma unroll
-  for (int s = 0; s < 15; ++s)
-    if (s < nbr) F[p * nbr + s] = cmake(-coef * ai[s], coef * ar[s]);  // i coef acc
+    for (int at = 0; at < 5; ++at) {
+      if (at >= na) break;
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) {
+        const cd u = lu[(3 * at + bb) * nbr + s];
+        xr += wr[at][bb] * u.x - wi[at][bb] * u.y;
+        xi += wr[at][bb] * u.y + wi[at][bb] * u.x;
+      }
+    }
+    F[p * nbr + s] = cmake(-coef * xi, coef * xr);  // i coef sum
+  }
 }
 
 __global__ void k_fill_ustate(int64_t M, int nb, const int32_t* __restrict__ st_kidx, const int32_t* __restrict__ st_m,
