@@ -421,6 +421,42 @@ def test_tetra_delta_forms(form):
     ctx.close()
 
 
+def _iterate_against_oracle(ctx, c, Xp, Xm, prob):
+    T = c.T
+    sz = E.elph_sizes(ctx)
+    M, nm = sz["nstates"], sz["nk"] * sz["nbr"]
+    I, J, F, G = dtensor(3 * M), dtensor(3 * M), dtensor(3 * nm), dtensor(3 * nm)
+    wext = oracle.default_w_ext(prob, T, gamma0=1e13)
+    wext_d = torch.from_numpy(np.ascontiguousarray(wext.reshape(-1))).to(DEV)
+    E.elph_iterate(ctx, T, I, J, F, G, W_ph_ext=wext_d, level=3, tol=1e-12, maxit=400)
+    torch.cuda.synchronize()
+    ref = oracle.iterate(prob, T, Xp, Xm, 3, tol=1e-12, maxit=400, w_ext=wext)
+    assert ref["converged"]
+    got = dict(I=I.cpu().numpy().reshape(M, 3), J=J.cpu().numpy().reshape(M, 3),
+               F=F.cpu().numpy().reshape(-1, sz["nbr"], 3), G=G.cpu().numpy().reshape(-1, sz["nbr"], 3))
+    for key in ("I", "J", "F", "G"):
+        scale = np.abs(ref[key]).max()
+        assert scale > 0, key
+        assert np.abs(got[key] - ref[key]).max() <= 1e-7 * scale, key
+
+
+def test_tetra_delta_coupled_iteration():
+    c = case("metal6")
+    Xp, Xm, _, _ = tetra_ref("metal6")
+    ctx = make_ctx(c.cfg, c.mat)
+    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    _iterate_against_oracle(ctx, c, Xp, Xm, c.prob)
+    ctx.close()
+
+
+def test_polar_coupled_iteration():
+    c = polar_case()
+    ctx = make_ctx(c.cfg, c.mat)
+    E.elph_set_polar(ctx, c.mat["zstar"], c.mat["eps_inf"], c.mat["tau"])
+    _iterate_against_oracle(ctx, c, c.Xp, c.Xm, c.prob)
+    ctx.close()
+
+
 def test_tetra_delta_is_refused_by_batches():
     c = case("tiny4")
     ctx = make_ctx(c.cfg, c.mat, precision="fp32")
