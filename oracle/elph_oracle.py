@@ -46,9 +46,10 @@ Readings of the paper used here (where it is silent, garbled or ambiguous):
   constrained to sum_{i in group} f_i (1 - f_i) I_i = 0 for every group (no
   change of carrier number), applied after every electron sweep; for
   materials with inversion or time-reversal symmetry this holds by itself.
-* Phonon scattering other than ph-e (ph-ph, ph-isotope) is an external rate
-  per mode (default model gamma0 (hw/hw_max)^2 (T/300 K), gamma0 = 1e12/s);
-  the ph-ph in-scattering term Delta F^S is zero.
+* Phonon scattering other than ph-e enters the iteration as an external rate
+  per mode (default model gamma0 (hw/hw_max)^2 (T/300 K), gamma0 = 1e12/s,
+  or the three-phonon RTA rate of Eq. 26 computed by phph_rates); the ph-ph
+  in-scattering term Delta F^S is zero.
 """
 import numpy as np
 
@@ -76,6 +77,7 @@ __all__ = [
     "g_wannier_brute", "g_wannier_factorised", "g_bloch", "Problem", "default_w_ext",
     "tetra_delta_weights", "tetra_neighbourhood",
     "iterate", "transport_tensors", "ko_residual", "ko_enforce", "energy_groups",
+    "C_PHPH", "eigendisplacements", "ifc3_matrix", "phph_vertex", "phph_rates",
 ]
 
 
@@ -848,3 +850,96 @@ def ko_enforce(prob, T, I, J, F, G, bisect_steps=200):
     lam = 0.5 * (lo + hi)
     I_ko = I_diff + lam * I_drag
     return I_ko, lam, transport_tensors(prob, T, I_ko, J, F, G)
+
+
+# ----------------------------------------------------------------------------
+# Three-phonon processes: the vertex of Eq. 13, the transition rates of
+# Eq. 14 and the ph-ph part of the phonon RTA rate of Eq. 26.
+#
+# Readings: the eigendisplacement e_j(Q) of Eq. 13 is exp(2 pi i Q.R_j) times
+# the mass-weighted eigenvector column u(Q) of D(Q) (the phase convention of
+# Eq. 3; no atom-position phase), and the explicit 1/sqrt(m m m) turns the
+# three columns into u/sqrt(M).  The occupations of Eq. 14 are those of the
+# modes s'q' and s''q'' (the printed branch labels are garbled).  The delta
+# is the Gaussian of standard deviation sigma in hbar*omega, and modes below
+# omega_min take no part (as in the e-ph path).
+
+# hbar^5 e^3 / (amu^3 Angstrom^6): |V|^2 in eV^2 / (A^6 amu^3), energies in eV
+# and the delta in 1/eV give W of Eq. 14 in 1/s
+C_PHPH = HBAR_EVS ** 5 * E_CHARGE ** 3 / (AMU_KG ** 3 * ANG_M ** 6)
+
+
+def eigendisplacements(mat, u):
+    """u_{x,s} / sqrt(M_x) for every column of u (..., nbr, nbr)."""
+    mx = np.repeat(np.asarray(mat["mass"], dtype=np.float64), 3)
+    return u / np.sqrt(mx)[:, None]
+
+
+def ifc3_matrix(ifc3):
+    """Psi entries as [n_entries][x_i][x_j][x_k] with x = 3 * atom + Cartesian."""
+    rj, rk, psi = ifc3
+    n, na = psi.shape[0], psi.shape[1]
+    return psi.transpose(0, 1, 4, 2, 5, 3, 6).reshape(n, 3 * na, 3 * na, 3 * na)
+
+
+def phph_vertex(ifc3, q2, q3, E1, E2, E3):
+    """Eq. 13 for one first leg and many second/third legs:
+    V[n][s1][s2][s3] = sum_{x_i, (R_j, x_j), (R_k, x_k)} Psi
+        E1[x_i, s1] exp(2 pi i q2_n.R_j) E2_n[x_j, s2] exp(2 pi i q3_n.R_k) E3_n[x_k, s3],
+    where the first leg's atom sits in the central cell (its phase is 1),
+    q2, q3 are [n][3] fractional wave vectors of the second and third legs
+    (the three legs' wave vectors sum to a reciprocal lattice vector) and
+    E* are eigendisplacement columns u / sqrt(M)."""
+    rj, rk, _ = ifc3
+    P = ifc3_matrix(ifc3)
+    nent, nbr = P.shape[0], P.shape[1]
+    ph = np.exp(2j * np.pi * (np.atleast_2d(q2) @ rj.T.astype(np.float64)
+                              + np.atleast_2d(q3) @ rk.T.astype(np.float64)))
+    A = (ph @ P.reshape(nent, -1)).reshape(-1, nbr, nbr, nbr)
+    return np.einsum("nabc,as,nbt,ncu->nstu", A, E1, E2, E3, optimize=True)
+
+
+def phph_rates(prob, ifc3, T, sigma, rows=None, parts=False):
+    """Eq. 26's three-phonon part W_sq = sum_{s'q's''} (W+ + W-/2) / (n (1 + n))
+    with W+- of Eq. 14 (absorption q + q' -> q'' = q + q', decay
+    q -> q' + q'' with q'' = q - q'), each vertex from Eq. 13 with the second
+    leg at +-q' and the third at -q''.  Returns W [len(rows)][nbr] in 1/s; with
+    parts=True also the bare sums S+- = sum |V+-|^2 delta / (E E' E'') over
+    the same terms."""
+    n = prob.n
+    nq, nbr = prob.nq, prob.nbr
+    E = eigendisplacements(prob.mat, prob.u)
+    nB, onB = bose_pair(prob.hw, T)
+    on = prob.mode_on
+    pref = np.pi / (4.0 * nq) * C_PHPH
+    rows = np.arange(nq) if rows is None else np.asarray(rows)
+    W = np.zeros((rows.size, nbr))
+    S = {+1: 0.0, -1: 0.0}
+    allq = np.arange(nq)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for r, q in enumerate(rows):
+            for sign in (+1, -1):
+                leg2 = mesh_linear(sign * prob.ijk[allq], n)                 # +-q'
+                qpp = mesh_linear(prob.ijk[q] + sign * prob.ijk[allq], n)    # q''
+                leg3 = mesh_linear(-prob.ijk[qpp], n)                        # -q''
+                V = phph_vertex(ifc3, prob.kfrac[leg2], prob.kfrac[leg3], E[q], E[leg2], E[leg3])
+                e1 = prob.hw[q][None, :, None, None]
+                e2 = prob.hw[allq][:, None, :, None]
+                e3 = prob.hw[qpp][:, None, None, :]
+                mask = (on[q][None, :, None, None] & on[allq][:, None, :, None]
+                        & on[qpp][:, None, None, :])
+                bare = np.abs(V) ** 2 * gaussian_delta(e1 + sign * e2 - e3, sigma) / (e1 * e2 * e3)
+                bare = np.where(mask, bare, 0.0)
+                S[sign] += bare.sum()
+                n1, on1 = nB[q][None, :, None, None], onB[q][None, :, None, None]
+                n2, on2 = nB[allq][:, None, :, None], onB[allq][:, None, :, None]
+                n3 = nB[qpp][:, None, None, :]
+                if sign > 0:
+                    w = pref * bare * on1 * on2 * n3                 # Eq. 14, +
+                else:
+                    w = 0.5 * pref * bare * on1 * n2 * n3            # Eq. 14, - (half in Eq. 26)
+                w = np.where(mask, w, 0.0)
+                W[r] += w.sum(axis=(0, 2, 3)) / np.where(on[q], nB[q] * onB[q], 1.0)
+    if parts:
+        return W, S[+1], S[-1]
+    return W

@@ -2,7 +2,8 @@
 
 This package only draws random numbers and assembles the Wannier-space input
 arrays (Hamiltonian H(R_e), force constants D(R_p), vertex g(R_e, R_p), and
-for polar materials Born charges and the dielectric tensor); it
+for polar materials Born charges and the dielectric tensor, and
+third-order force constants for three-phonon processes); it
 holds none of the method's arithmetic (no Fourier sums, no eigensolves, no
 transition probabilities).  Calibrated scale parameters (band gap offset,
 Hamiltonian scale, force-constant scale, chemical potential) are stored in
@@ -11,5 +12,5 @@ Hamiltonian scale, force-constant scale, chemical potential) are stored in
 from . import mlp  # noqa: F401
 from .materials import (  # noqa: F401
     rset_cube, rset_sphere, make_material, config, config_names, material_for, polar_params,
-    MASS_CYCLE, LATTICE_A,
+    MASS_CYCLE, LATTICE_A, ifc3_params,
 )

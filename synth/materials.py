@@ -259,3 +259,66 @@ def polar_params(na, seed, z0=2.0, eps0=8.0, lat=None):
     if lat is not None:
         return Z, eps, tau
     return Z, eps
+
+
+def ifc3_params(na, seed, cells=None, scale=2.0, L=1.0, sweeps=200):
+    """Seeded third-order force constants Psi (eV/Angstrom^3) on the cell
+    triples {0, Rj, Rk} whose pairwise differences lie in ``cells`` (default
+    the cube {-1, 0, 1}^3).
+
+    Returns (rj [n][3] int32, rk [n][3] int32, psi [n][na][na][na][3][3][3]):
+    entry e holds Psi(0 ti a, rj_e tj b, rk_e tk c) for the atom triple
+    (ti, tj, tk) and Cartesian triple (a, b, c).  The tensor is made
+    symmetric under every permutation of its three legs (with the triple
+    recentred on the first leg's cell) and obeys the acoustic sum rule
+    sum_{Rk, tk} Psi = 0, by alternating the two orthogonal projections from
+    a seeded normal draw damped as exp(-(|Rj| + |Rk| + |Rj - Rk|) / L)."""
+    cells = rset_cube(-1, 1) if cells is None else np.asarray(cells, dtype=np.int32)
+    cset = {tuple(int(x) for x in v) for v in cells}
+    keys = [(a, b) for a in sorted(cset) for b in sorted(cset)
+            if tuple(bb - aa for aa, bb in zip(a, b)) in cset]
+    idx = {k: i for i, k in enumerate(keys)}
+    rng = np.random.default_rng(seed)
+    n = len(keys)
+    rj = np.array([k[0] for k in keys], dtype=np.int32)
+    rk = np.array([k[1] for k in keys], dtype=np.int32)
+    damp = np.exp(-(np.linalg.norm(rj, axis=1) + np.linalg.norm(rk, axis=1)
+                    + np.linalg.norm(rk - rj, axis=1)) / L)
+    psi = rng.standard_normal((n, na, na, na, 3, 3, 3)) * (scale * damp)[:, None, None, None, None, None, None]
+
+    # the six leg orders: entry (Rj, Rk) viewed from leg p[0]; cells of the legs
+    # are (0, Rj, Rk), recentred on the new first leg
+    perms = list(itertools.permutations(range(3)))
+    maps = []
+    for p in perms:
+        tgt = np.empty(n, dtype=np.int64)
+        for e, (a, b) in enumerate(keys):
+            c = ((0, 0, 0), a, b)
+            o = c[p[0]]
+            na_ = tuple(x - y for x, y in zip(c[p[1]], o))
+            nb_ = tuple(x - y for x, y in zip(c[p[2]], o))
+            tgt[e] = idx[(na_, nb_)]
+        axes = (0,) + tuple(1 + q for q in p) + tuple(4 + q for q in p)
+        maps.append((tgt, axes))
+    # groups of entries sharing (Rj) for the sum rule over (Rk, tk)
+    rj_groups = {}
+    for e, (a, b) in enumerate(keys):
+        rj_groups.setdefault(a, []).append(e)
+    rj_groups = [np.array(v) for v in rj_groups.values()]
+
+    def symmetrise(x):
+        out = np.zeros_like(x)
+        for tgt, axes in maps:
+            np.add.at(out, tgt, np.transpose(x, axes))
+        return out / len(maps)
+
+    def sum_rule(x):
+        y = x.copy()
+        for g in rj_groups:
+            m = y[g].sum(axis=(0, 3), keepdims=True) / (g.size * na)
+            y[g] -= m
+        return y
+
+    for _ in range(sweeps):
+        psi = symmetrise(sum_rule(psi))
+    return rj, rk, psi

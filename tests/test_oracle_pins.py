@@ -681,3 +681,131 @@ def test_frohlich_factor_small_q_limit_and_periodicity():
     F0 = oracle.frohlich_factor(mat, q, lu)
     F1 = oracle.frohlich_factor(mat, q + np.array([[1.0, -2.0, 0.0]]), lu)
     assert np.abs(F1 - F0).max() <= 1e-12 * np.abs(F0).max()
+
+
+# ---------------------------------------------------------------------------
+# three-phonon processes (Eqs. 13, 14, 26)
+
+def _phph_problem(name="tiny4", seed=5):
+    cfg, mat = _tiny(name)
+    prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+    return prob, synth.ifc3_params(mat["natom"], seed, scale=0.3)
+
+
+def _leg_vertex(prob, ifc3, q1, q2, q3):
+    """V with legs at the mesh points q1, q2, q3 (first leg in the central cell)."""
+    E = oracle.eigendisplacements(prob.mat, prob.u)
+    return oracle.phph_vertex(ifc3, prob.kfrac[[q2]], prob.kfrac[[q3]], E[q1], E[[q2]], E[[q3]])[0]
+
+
+def test_ifc3_generator_is_symmetric_with_sum_rule():
+    """The synthetic Psi is symmetric under exchange of its legs (recentred on
+    the new first leg's cell) and sums to zero over the third leg's atoms and
+    cells."""
+    rj, rk, psi = synth.ifc3_params(2, 9)
+    key = {(tuple(a), tuple(b)): e for e, (a, b) in enumerate(zip(rj.tolist(), rk.tolist()))}
+    for e, (a, b) in enumerate(zip(rj.tolist(), rk.tolist())):
+        # swap legs j and k
+        f = key[(tuple(b), tuple(a))]
+        assert np.allclose(psi[e], psi[f].transpose(0, 2, 1, 3, 5, 4), atol=1e-14)
+        # swap legs i and j: cells (0, a, b) -> (a, 0, b) recentred on a
+        g = key[(tuple(-x for x in a), tuple(y - x for x, y in zip(a, b)))]
+        assert np.allclose(psi[e], psi[g].transpose(1, 0, 2, 4, 3, 5), atol=1e-14)
+    for a in set(map(tuple, rj.tolist())):
+        sel = [e for e in range(len(rj)) if tuple(rj[e]) == a]
+        assert np.abs(psi[sel].sum(axis=(0, 3))).max() <= 1e-13 * np.abs(psi).max()
+
+
+@pytest.mark.parametrize("leg", [0, 1, 2])
+def test_phph_vertex_vanishes_for_a_uniform_translation(leg):
+    """Eq. 13 with the acoustic sum rule of Psi: a mode that translates the
+    crystal rigidly (acoustic at Gamma) on any one leg gives V = 0.  For the
+    central-cell leg this holds only through translation invariance, so it
+    fixes the signs and cells of the other two legs' phases."""
+    prob, ifc3 = _phph_problem()
+    ac = np.nonzero(prob.hw[0] < prob.omega_min)[0]
+    assert ac.size == 3
+    big = 0.0
+    for q in range(1, prob.nq, 5):
+        mq = prob.neg_q(q)
+        legs = [(0, q, mq), (q, 0, mq), (q, mq, 0)][leg]
+        V = _leg_vertex(prob, ifc3, *legs)
+        big = max(big, np.abs(V).max())
+        zero = np.take(V, ac, axis=leg)
+        assert np.abs(zero).max() <= 1e-12 * np.abs(V).max()
+    assert big > 0
+
+
+def test_phph_vertex_is_symmetric_in_its_legs():
+    """With a leg-symmetric Psi the vertex of Eq. 13 is symmetric under
+    exchange of (wave vector, branch) between legs, although each ordering
+    puts a different leg in the central cell."""
+    prob, ifc3 = _phph_problem()
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        q1, q2 = rng.integers(0, prob.nq, 2)
+        q3 = mesh = oracle.mesh_linear(-(prob.ijk[q1] + prob.ijk[q2]), prob.n)
+        V = _leg_vertex(prob, ifc3, q1, q2, q3)
+        assert np.abs(V).max() > 0
+        assert np.allclose(_leg_vertex(prob, ifc3, q2, q1, q3).transpose(1, 0, 2), V,
+                           rtol=0, atol=1e-12 * np.abs(V).max())
+        assert np.allclose(_leg_vertex(prob, ifc3, q3, q2, q1).transpose(2, 1, 0), V,
+                           rtol=0, atol=1e-12 * np.abs(V).max())
+        assert np.allclose(_leg_vertex(prob, ifc3, q1, q3, q2).transpose(0, 2, 1), V,
+                           rtol=0, atol=1e-12 * np.abs(V).max())
+
+
+def test_phph_vertex_against_explicit_loops():
+    """Eq. 13 summed term by term (cells, atoms, Cartesian directions) on a
+    few pairs equals the vectorised oracle."""
+    prob, ifc3 = _phph_problem("tiny3")
+    rj, rk, psi = ifc3
+    na = psi.shape[1]
+    E = oracle.eigendisplacements(prob.mat, prob.u)
+    for q, qp in [(1, 2), (4, 7), (8, 3)]:
+        qpp = oracle.mesh_linear(prob.ijk[q] - prob.ijk[qp], prob.n)
+        l2, l3 = prob.neg_q(qp), prob.neg_q(qpp)
+        ref = oracle.phph_vertex(ifc3, prob.kfrac[[l2]], prob.kfrac[[l3]], E[q], E[[l2]], E[[l3]])[0]
+        V = np.zeros((3 * na,) * 3, complex)
+        for e in range(len(rj)):
+            p2 = np.exp(2j * np.pi * np.dot(prob.kfrac[l2], rj[e]))
+            p3 = np.exp(2j * np.pi * np.dot(prob.kfrac[l3], rk[e]))
+            for ti in range(na):
+                for tj in range(na):
+                    for tk in range(na):
+                        for a in range(3):
+                            for b in range(3):
+                                for c in range(3):
+                                    w = psi[e, ti, tj, tk, a, b, c] * p2 * p3
+                                    if w == 0:
+                                        continue
+                                    V += w * np.einsum("s,t,u->stu", E[q][3 * ti + a], E[l2][3 * tj + b],
+                                                       E[l3][3 * tk + c])
+        assert np.abs(V - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_phph_absorption_and_decay_sums_agree():
+    """Every three-phonon event a + b -> c appears twice among the absorption
+    terms (first leg a or b) and twice among the decay terms (first leg c,
+    the products in either order); with Eq. 13's leg symmetry and a symmetric
+    delta the bare sums of |V|^2 delta / (E E' E'') over both kinds agree."""
+    prob, ifc3 = _phph_problem()
+    W, Sp, Sm = oracle.phph_rates(prob, ifc3, 300.0, 0.004, parts=True)
+    assert Sp > 0
+    assert abs(Sp - Sm) <= 1e-12 * Sp
+    assert np.all(W >= 0) and np.all(np.isfinite(W))
+    assert np.all(W[0][prob.hw[0] < prob.omega_min] == 0)
+
+
+def test_phph_rate_prefactor_in_si_units():
+    """The prefactor of Eq. 14 evaluated with SI quantities (hbar in J s,
+    omega in rad/s, the vertex in J m^-3 kg^-3/2, the delta in s) equals the
+    eV form the oracle uses."""
+    N, V2, E, d = 512, 3.7, np.array([0.021, 0.013, 0.034]), 11.0   # eV^2/(A^6 amu^3), eV, 1/eV
+    w_ev = np.pi / (4 * N) * oracle.C_PHPH * V2 * d / E.prod()
+    hbar = 1.054571817e-34                                            # J s
+    omega = E * 1.602176634e-19 / hbar
+    v2_si = V2 * (1.602176634e-19 / (1e-30 * 1.66053906660e-27 ** 1.5)) ** 2
+    d_si = d / 1.602176634e-19 * hbar                                 # delta(omega) in s
+    w_si = np.pi * hbar / (4 * N) * v2_si / omega.prod() * d_si
+    assert abs(w_ev - w_si) <= 1e-8 * w_si
