@@ -208,6 +208,37 @@ elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
  * eps_inf that is not symmetric positive definite. */
 elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf, const double* tau);
 
+/* Three-phonon processes (Eqs. 13, 14 and the three-phonon part of Eq. 26).
+ * Third-order force constants: n entries, entry e holding
+ * Psi(0 t_i a, rj_e t_j b, rk_e t_k c) in eV/Angstrom^3 for the atom in the
+ * central cell, the atoms in cells rj_e and rk_e (integer lattice vectors,
+ * host int32 [n][3]) and Cartesian directions (a, b, c); psi is a host array
+ * [n][natom][natom][natom][3][3][3] (t_i, t_j, t_k, a, b, c), copied.  At
+ * most 256 distinct rj and 4 atoms.  n = 0 or psi = NULL removes them.
+ * EINVAL for non-finite input.  Nothing else is changed. */
+elph_status elph_set_ifc3(elph_ctx ctx, int32_t n, const int32_t* rj, const int32_t* rk, const double* psi);
+
+/* |V-(q s, q' s', q'' s'')|^2 of Eq. 13, q'' = q - q', for npairs mesh
+ * pairs (q[p], qp[p]) (device int32 mesh indexes), into V2 (device FP64
+ * [npairs][nbr(s)][nbr(s')][nbr(s'')], eV^2 / (Angstrom^6 amu^3)), with the
+ * second leg at -q', the third at -q'' and the eigendisplacements u / sqrt(M)
+ * of the context's phonon tables; a mode below omega_min contributes a zero
+ * eigendisplacement.  |V+(q, -q', q'')|^2 is the same number.  A pair with
+ * an index outside the mesh gets NaN.  ESTATE without force constants. */
+elph_status elph_phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, const int32_t* qp, double* V2);
+
+/* The three-phonon RTA rate of every mode at T (the ph-ph bracket of Eq. 26
+ * divided by n (1 + n)):
+ *   W_sq = sum_{s'q's''} (W+ + W-/2) / (n_sq (1 + n_sq)),
+ * W+ = (pi hbar / (4 N_q)) |V+|^2 / (w w' w'') (n + 1)(n' + 1) n'' delta(w + w' - w'')
+ * for q + q' -> q'' = q + q', and W- the same with n' in place of n' + 1 and
+ * delta(w - w' - w'') for q -> q' + q'' (Eq. 14), delta the Gaussian of
+ * standard deviation sigma_eV in hbar w; modes below omega_min take no
+ * part.  W_ph: device FP64 [Nq][nbr], 1/s; it can be passed to
+ * elph_iterate as W_ph_ext.  Synchronous.  ESTATE without force constants,
+ * EINVAL for T or sigma not positive. */
+elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W_ph);
+
 /* Select the energy-conserving delta of Eq. 8 for this context's later
  * vertex stores (the paper offers the triangle and the analytic
  * tetrahedron methods beside smearing; section on the program's workflow).

@@ -418,6 +418,25 @@ __global__ void k_x_inplace(int64_t M, int nbr, int n0, int n1, int n2, const in
   Xm[t] *= occ * (1.0 + n);
 }
 
+extern "C" elph_status elph_set_ifc3(elph_ctx ctx, int32_t n, const int32_t* rj, const int32_t* rk,
+                                     const double* psi) {
+  CHECK_CTX(ctx);
+  return elph::phph_set_ifc3(ctx, n, rj, rk, psi);
+}
+
+extern "C" elph_status elph_phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, const int32_t* qp,
+                                        double* V2) {
+  CHECK_CTX(ctx);
+  return elph::phph_vertex(ctx, npairs, q, qp, V2);
+}
+
+extern "C" elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W_ph) {
+  CHECK_CTX(ctx);
+  elph_status st = check_T(ctx, T_K);
+  if (st != ELPH_OK) return st;
+  return elph::phph_rates(ctx, T_K, sigma_eV, W_ph);
+}
+
 extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf, const double* tau) {
   CHECK_CTX(ctx);
   HIPCHK(hipStreamSynchronize(ctx->stream));

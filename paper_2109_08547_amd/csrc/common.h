@@ -88,6 +88,13 @@ struct elph_ctx_s {
   int fr_box[3] = {0, 0, 0}; // half widths of the G box of its Ewald sum
   double* d_frohlich = nullptr;  // [nk][nbr] complex F_s(q) of Eq. 7 (eV)
   double* d_ustate = nullptr;    // [nstates][nb] complex eigenvector of each active state (its column of U)
+  // third-order force constants (three-phonon processes, Eq. 13): entries
+  // grouped by their second cell R_j
+  int n3 = 0, ng3 = 0;
+  int32_t* d_i3_rj = nullptr;   // [ng3][3] distinct R_j
+  int32_t* d_i3_off = nullptr;  // [ng3 + 1] first entry of each R_j
+  int32_t* d_i3_rk = nullptr;   // [n3][3]
+  double* d_i3_psi = nullptr;   // [n3][nbr][nbr][nbr] eV / Angstrom^3, x = 3 atom + Cartesian
   double2* d_tab[3] = {nullptr, nullptr, nullptr};  // per-axis exp(2 pi i j / N)
   int32_t* d_qrep = nullptr;                          // mesh points q with q <= -q (one of each +-q pair)
   int64_t nqrep = 0;

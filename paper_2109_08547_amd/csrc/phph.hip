@@ -1,0 +1,449 @@
+// Three-phonon processes: the vertex V of Eq. 13, the transition rates W+-
+// of Eq. 14 and the three-phonon part of the phonon RTA rate of Eq. 26.
+//
+// V-(q s, q' s', q'' s''), q'' = q - q', is a sum over the third-order force
+// constants Psi(0 x_i, R_j x_j, R_k x_k) (x = 3 atom + Cartesian) of
+//   E_q[x_i][s] exp(-2 pi i q'.R_j) E_{-q'}[x_j][s'] exp(-2 pi i q''.R_k) E_{-q''}[x_k][s'']
+// with E = u / sqrt(M) the eigendisplacement columns (u the eigenvectors of
+// D).  It is computed in two stages:
+//   fold   (per mesh point P, per distinct R_j):
+//     Phi[P][j][x_i][x_j][s''] = sum_{entries with R_j} exp(-2 pi i P.R_k)
+//                                sum_{x_k} Psi[x_i][x_j][x_k] E_{-P}[x_k][s'']
+//   rows   (per q, over every q'):
+//     A[x_i][x_j][s''] = sum_j exp(-2 pi i q'.R_j) Phi[q - q'][j][x_i][x_j][s'']
+//     B[x_i][s'][s'']  = sum_{x_j} E_{-q'}[x_j][s'] A[x_i][x_j][s'']
+//     V[s][s'][s'']    = sum_{x_i} E_q[x_i][s] B[x_i][s'][s'']
+// One V-(q, q') serves both processes of the row: the decay q -> q' + q''
+// and, through |V+(q, -q', q'')| = |V-(q, q', q'')| (the identity the paper
+// states below Eq. 13), the absorption q + (-q') -> q''; omega and n at -q'
+// equal those at q'.
+#include "vertex.h"
+#include "devutil.h"
+#include "tables.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <map>
+#include <vector>
+
+namespace elph {
+
+namespace {
+
+constexpr int kFoldEnt = 64;   // entries of one R_j group staged in LDS per pass
+constexpr int kMaxGroups = 256;  // distinct R_j
+
+// hbar^5 e^3 / (amu^3 Angstrom^6) written through SI quantities:
+// hbar[J s] hbar[eV s]^4 e[C]^2 / (amu[kg]^3 Angstrom[m]^6)
+constexpr double kPhPhC =
+    kHbarJs * kHbarEVs * kHbarEVs * kHbarEVs * kHbarEVs * kCharge * kCharge /
+    (kAmuKg * kAmuKg * kAmuKg * kAngM * kAngM * kAngM * kAngM * kAngM * kAngM);
+
+struct PhaseTab {
+  const double2* t0;
+  const double2* t1;
+  const double2* t2;
+  int n0, n1, n2;
+  // exp(-2 pi i P . R) for the mesh point P (linear index) and integer R
+  __device__ inline cd neg(int P, int r0, int r1, int r2) const {
+    const int c = P % n2, t = P / n2, b = t % n1, a = t / n1;
+    int i0 = (int)(((int64_t)a * r0) % n0); if (i0 < 0) i0 += n0;
+    int i1 = (int)(((int64_t)b * r1) % n1); if (i1 < 0) i1 += n1;
+    int i2 = (int)(((int64_t)c * r2) % n2); if (i2 < 0) i2 += n2;
+    const double2 p0 = t0[i0], p1 = t1[i1], p2 = t2[i2];
+    const cd z = cmul(cmul(cmake(p0.x, p0.y), cmake(p1.x, p1.y)), cmake(p2.x, p2.y));
+    return cconj(z);
+  }
+};
+
+// E[x][s] = u[x][s] / sqrt(M_x) from the table l_{x,s} u[x][s] (zero for
+// modes below omega_min) and hbar omega: l = sqrt(C / (2 M hbar omega)).
+__device__ inline cd edisp(const cd* Lq, const double* hw, int64_t q, int nbr, int x, int s) {
+  const double w = hw[q * nbr + s];
+  const cd L = Lq[(q * nbr + x) * nbr + s];
+  return w > 0.0 ? cscale(L, sqrt(2.0 * w / kPhononC)) : cmake(0.0, 0.0);
+}
+
+// fold: block (P, j), threads over (x_i, x_j, s'')
+template <int NBR>
+__global__ __launch_bounds__(256) void k_ifc3_fold(PhaseTab ph, const int32_t* __restrict__ goff,
+                                                   const int32_t* __restrict__ rk, const double* __restrict__ psi,
+                                                   const cd* __restrict__ Lq, const double* __restrict__ hw,
+                                                   int ng, cd* __restrict__ phi) {
+  constexpr int N2 = NBR * NBR, N3 = N2 * NBR;
+  __shared__ cd em[N2];          // E_{-P}[x_k][s'']
+  __shared__ cd pe[kFoldEnt];    // exp(-2 pi i P.R_k) of the staged entries
+  const int P = blockIdx.x, j = blockIdx.y;
+  const MeshDims md{ph.n0, ph.n1, ph.n2};
+  const int mP = q_neg(P, md.n0, md.n1, md.n2);
+  for (int t = threadIdx.x; t < N2; t += blockDim.x) em[t] = edisp(Lq, hw, mP, NBR, t / NBR, t % NBR);
+  const int e0 = goff[j], e1 = goff[j + 1];
+  cd acc[(N3 + 255) / 256];
+#pragma unroll
+  for (int r = 0; r < (N3 + 255) / 256; ++r) acc[r] = cmake(0.0, 0.0);
+  for (int eb = e0; eb < e1; eb += kFoldEnt) {
+    const int ne = min(kFoldEnt, e1 - eb);
+    __syncthreads();
+    for (int t = threadIdx.x; t < ne; t += blockDim.x)
+      pe[t] = ph.neg(P, rk[3 * (eb + t)], rk[3 * (eb + t) + 1], rk[3 * (eb + t) + 2]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < (N3 + 255) / 256; ++r) {
+      const int o = threadIdx.x + 256 * r;
+      if (o < N3) {
+        const int xij = o / NBR, s3 = o - xij * NBR;
+        for (int e = 0; e < ne; ++e) {
+          const double* row = psi + ((int64_t)(eb + e) * N2 + xij) * NBR;
+          cd t = cmake(0.0, 0.0);
+#pragma unroll
+          for (int xk = 0; xk < NBR; ++xk) {
+            const cd m = em[xk * NBR + s3];
+            t.x += row[xk] * m.x;
+            t.y += row[xk] * m.y;
+          }
+          acc[r] = cadd(acc[r], cmul(pe[e], t));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < (N3 + 255) / 256; ++r) {
+    const int o = threadIdx.x + 256 * r;
+    if (o < N3) phi[((int64_t)P * ng + j) * N3 + o] = acc[r];
+  }
+}
+
+// Shared stages of the row and vertex kernels for one pair (q, q'):
+// V[s][s'][s''] into A (LDS, N3; A is free once B is formed), with
+// eq = E_q and ex = E_{-q'} staged.
+template <int NBR>
+__device__ inline void pair_vertex(const PhaseTab& ph, int qp, int qpp, int ng, const int32_t* gr,
+                                   const cd* __restrict__ phi, const cd* eq, const cd* ex, cd* pg, cd* A, cd* B) {
+  constexpr int N2 = NBR * NBR, N3 = N2 * NBR;
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) pg[g] = ph.neg(qp, gr[3 * g], gr[3 * g + 1], gr[3 * g + 2]);
+  __syncthreads();
+  const cd* src = phi + (int64_t)qpp * ng * N3;
+  for (int o = threadIdx.x; o < N3; o += blockDim.x) {
+    cd a = cmake(0.0, 0.0);
+    for (int g = 0; g < ng; ++g) a = cadd(a, cmul(pg[g], src[(int64_t)g * N3 + o]));
+    A[o] = a;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < N3; o += blockDim.x) {   // o = (x_i, s', s'')
+    const int xi = o / N2, r = o - xi * N2, s2 = r / NBR, s3 = r - s2 * NBR;
+    cd b = cmake(0.0, 0.0);
+#pragma unroll
+    for (int xj = 0; xj < NBR; ++xj) b = cadd(b, cmul(ex[xj * NBR + s2], A[(xi * NBR + xj) * NBR + s3]));
+    B[o] = b;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < N3; o += blockDim.x) {   // o = (s, s', s'')
+    const int s1 = o / N2, r = o - s1 * N2;
+    cd v = cmake(0.0, 0.0);
+#pragma unroll
+    for (int xi = 0; xi < NBR; ++xi) v = cadd(v, cmul(eq[xi * NBR + s1], B[xi * N2 + r]));
+    A[o] = v;
+  }
+  __syncthreads();
+}
+
+template <int NBR>
+struct PairLds {
+  cd eq[NBR * NBR];
+  cd ex[NBR * NBR];
+  cd pg[kMaxGroups];
+  cd A[NBR * NBR * NBR];   // A, then V once B is formed
+  cd B[NBR * NBR * NBR];
+};
+
+// |V-(q s, q' s', q'' s'')|^2 for a list of pairs: block per pair
+template <int NBR>
+__global__ __launch_bounds__(256) void k_phph_vertex(PhaseTab ph, int64_t npairs, const int32_t* __restrict__ qs,
+                                                     const int32_t* __restrict__ qps, const int32_t* __restrict__ gr,
+                                                     int ng, const cd* __restrict__ phi, const cd* __restrict__ Lq,
+                                                     const double* __restrict__ hw, double* __restrict__ V2) {
+  constexpr int N2 = NBR * NBR, N3 = N2 * NBR;
+  __shared__ PairLds<NBR> L;
+  const int64_t p = blockIdx.x;
+  const int q = qs[p], qp = qps[p];
+  const int nq = ph.n0 * ph.n1 * ph.n2;
+  if (q < 0 || q >= nq || qp < 0 || qp >= nq) {   // uniform over the block: no barrier skipped
+    for (int o = threadIdx.x; o < N3; o += blockDim.x) V2[p * N3 + o] = __builtin_nan("");
+    return;
+  }
+  const MeshDims md{ph.n0, ph.n1, ph.n2};
+  const int mqp = q_neg(qp, md.n0, md.n1, md.n2), qpp = q_between(q, qp, md.n0, md.n1, md.n2);
+  for (int t = threadIdx.x; t < N2; t += blockDim.x) {
+    L.eq[t] = edisp(Lq, hw, q, NBR, t / NBR, t % NBR);
+    L.ex[t] = edisp(Lq, hw, mqp, NBR, t / NBR, t % NBR);
+  }
+  pair_vertex<NBR>(ph, qp, qpp, ng, gr, phi, L.eq, L.ex, L.pg, L.A, L.B);
+  for (int o = threadIdx.x; o < N3; o += blockDim.x) V2[p * N3 + o] = cabs2(L.A[o]);
+}
+
+// Rates of one q over a chunk of q': block (q, chunk).  Thread t < NBR^2
+// owns the branch pair (s', s'') = t and sums, per s, over the chunk
+//   |V|^2 n'' [(1 + n') delta(E + E' - E'') + n' delta(E - E' - E'') / 2] / (E' E'')
+// into part[chunk][q][s]; the constant factors follow in k_phph_finish.
+template <int NBR>
+__global__ __launch_bounds__(256) void k_phph_rows(PhaseTab ph, int nq, int chunk, const int32_t* __restrict__ gr,
+                                                   int ng, const cd* __restrict__ phi, const cd* __restrict__ Lq,
+                                                   const double* __restrict__ hw, double kT, double omega_min,
+                                                   double sigma, double* __restrict__ part) {
+  constexpr int N2 = NBR * NBR;
+  __shared__ PairLds<NBR> L;
+  __shared__ double e1[NBR], e2[NBR], n2[NBR], e3[NBR], n3[NBR];
+  const int q = blockIdx.x;
+  const int c0 = blockIdx.y * chunk, c1 = min(nq, c0 + chunk);
+  const MeshDims md{ph.n0, ph.n1, ph.n2};
+  for (int t = threadIdx.x; t < N2; t += blockDim.x) L.eq[t] = edisp(Lq, hw, q, NBR, t / NBR, t % NBR);
+  if (threadIdx.x < NBR) e1[threadIdx.x] = hw[(int64_t)q * NBR + threadIdx.x];
+  const double inv2s2 = 0.5 / (sigma * sigma), dnorm = 1.0 / (sqrt(2.0 * kPi) * sigma);
+  double acc[NBR];
+#pragma unroll
+  for (int s = 0; s < NBR; ++s) acc[s] = 0.0;
+  for (int qp = c0; qp < c1; ++qp) {
+    const int mqp = q_neg(qp, md.n0, md.n1, md.n2), qpp = q_between(q, qp, md.n0, md.n1, md.n2);
+    __syncthreads();  // the previous pair's readers are done with ex, e2, e3
+    for (int t = threadIdx.x; t < N2; t += blockDim.x) L.ex[t] = edisp(Lq, hw, mqp, NBR, t / NBR, t % NBR);
+    if (threadIdx.x < NBR) {
+      const int s = threadIdx.x;
+      const double w2 = hw[(int64_t)qp * NBR + s], w3 = hw[(int64_t)qpp * NBR + s];
+      e2[s] = w2 >= omega_min ? w2 : 0.0;
+      e3[s] = w3 >= omega_min ? w3 : 0.0;
+      n2[s] = w2 >= omega_min ? 1.0 / expm1(w2 / kT) : 0.0;
+      n3[s] = w3 >= omega_min ? 1.0 / expm1(w3 / kT) : 0.0;
+    }
+    pair_vertex<NBR>(ph, qp, qpp, ng, gr, phi, L.eq, L.ex, L.pg, L.A, L.B);
+    const int t = threadIdx.x;
+    if (t < N2) {
+      const int s2 = t / NBR, s3 = t - s2 * NBR;
+      const double E2 = e2[s2], E3 = e3[s3];
+      if (E2 > 0.0 && E3 > 0.0) {
+        const double f = n3[s3] / (E2 * E3), np2 = n2[s2];
+#pragma unroll
+        for (int s1 = 0; s1 < NBR; ++s1) {
+          const double E1 = e1[s1];
+          const double dp = E1 + E2 - E3, dm = E1 - E2 - E3;
+          const double occ = (1.0 + np2) * exp(-dp * dp * inv2s2) + 0.5 * np2 * exp(-dm * dm * inv2s2);
+          acc[s1] += cabs2(L.A[s1 * N2 + t]) * f * occ * dnorm;
+        }
+      }
+    }
+  }
+  // sum over the branch pairs: the N2 <= 144 owners sit in the first waves
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(L.B);   // 4 wave partials per s (2 N3 >= 4 NBR doubles)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < NBR; ++s) {
+    double x = acc[s];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[s * 4 + wave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NBR) {
+    const int s = threadIdx.x;
+    part[((int64_t)blockIdx.y * nq + q) * NBR + s] = (red[s * 4] + red[s * 4 + 1]) + (red[s * 4 + 2] + red[s * 4 + 3]);
+  }
+}
+
+// W[q][s] = pi C / (4 N_q) sum_chunks part / (E n), modes below omega_min 0
+__global__ void k_phph_finish(int64_t nq, int nbr, int nchunk, const double* __restrict__ part,
+                              const double* __restrict__ hw, double kT, double omega_min, double pref,
+                              double* __restrict__ W) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nq * nbr) return;
+  const double w = hw[e];
+  double sum = 0.0;
+  for (int c = 0; c < nchunk; ++c) sum += part[(int64_t)c * nq * nbr + e];
+  W[e] = w >= omega_min ? pref * sum * expm1(w / kT) / w : 0.0;
+}
+
+PhaseTab phase_tab(elph_ctx ctx) {
+  return PhaseTab{ctx->d_tab[0], ctx->d_tab[1], ctx->d_tab[2], ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
+}
+
+template <int NBR>
+void launch_fold(elph_ctx ctx, cd* phi) {
+  hipLaunchKernelGGL(k_ifc3_fold<NBR>, dim3((unsigned)ctx->nk, (unsigned)ctx->ng3), dim3(256), 0, ctx->stream,
+                     phase_tab(ctx), ctx->d_i3_off, ctx->d_i3_rk, ctx->d_i3_psi, (const cd*)ctx->d_Lq, ctx->d_hw,
+                     ctx->ng3, phi);
+}
+
+template <int NBR>
+void launch_rows(elph_ctx ctx, int chunk, int nchunk, const cd* phi, double kT, double sigma, double* part) {
+  hipLaunchKernelGGL(k_phph_rows<NBR>, dim3((unsigned)ctx->nk, (unsigned)nchunk), dim3(256), 0, ctx->stream,
+                     phase_tab(ctx), (int)ctx->nk, chunk, ctx->d_i3_rj, ctx->ng3, phi, (const cd*)ctx->d_Lq, ctx->d_hw,
+                     kT, ctx->omega_min, sigma, part);
+}
+
+template <int NBR>
+void launch_vertex(elph_ctx ctx, int64_t np, const int32_t* q, const int32_t* qp, const cd* phi, double* V2) {
+  hipLaunchKernelGGL(k_phph_vertex<NBR>, dim3((unsigned)np), dim3(256), 0, ctx->stream, phase_tab(ctx), np, q, qp,
+                     ctx->d_i3_rj, ctx->ng3, phi, (const cd*)ctx->d_Lq, ctx->d_hw, V2);
+}
+
+#define NBR_SWITCH(nbr, CALL)          \
+  switch (nbr) {                       \
+    case 3: CALL(3); break;            \
+    case 6: CALL(6); break;            \
+    case 9: CALL(9); break;            \
+    case 12: CALL(12); break;          \
+    default: break;                    \
+  }
+
+elph_status check_phph(elph_ctx ctx) {
+  if (!ctx->d_i3_psi) {
+    ctx->err = "no third-order force constants (elph_set_ifc3)";
+    return ELPH_ESTATE;
+  }
+  if (ctx->nbr > 12) {
+    ctx->err = "three-phonon processes support up to 4 atoms";
+    return ELPH_EINVAL;
+  }
+  return ELPH_OK;
+}
+
+// the fold table for every mesh point, in a pool block the caller frees
+elph_status build_fold(elph_ctx ctx, cd** phi) {
+  const int64_t n3 = (int64_t)ctx->nbr * ctx->nbr * ctx->nbr;
+  ALLOC(*phi, ctx->nk * ctx->ng3 * n3 * sizeof(cd));
+#define FOLD(N) launch_fold<N>(ctx, *phi)
+  NBR_SWITCH(ctx->nbr, FOLD)
+#undef FOLD
+  HIPCHK(hipGetLastError());
+  return ELPH_OK;
+}
+
+}  // namespace
+
+elph_status phph_set_ifc3(elph_ctx ctx, int32_t n, const int32_t* rj, const int32_t* rk, const double* psi) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  void** ptrs[] = {(void**)&ctx->d_i3_rj, (void**)&ctx->d_i3_off, (void**)&ctx->d_i3_rk, (void**)&ctx->d_i3_psi};
+  for (void** p : ptrs) {
+    dev_free(ctx, *p);
+    *p = nullptr;
+  }
+  ctx->n3 = ctx->ng3 = 0;
+  if (n == 0 || !psi) return ELPH_OK;
+  if (n < 0 || !rj || !rk) {
+    ctx->err = "elph_set_ifc3: bad entry count or null cell arrays";
+    return ELPH_EINVAL;
+  }
+  const int na = ctx->na, nbr = ctx->nbr;
+  const int64_t blk = (int64_t)nbr * nbr * nbr;
+  for (int64_t i = 0; i < (int64_t)n * blk; ++i)
+    if (!std::isfinite(psi[i])) {
+      ctx->err = "elph_set_ifc3: psi is not finite";
+      return ELPH_EINVAL;
+    }
+  // entries grouped by R_j (stable), Psi reordered to [x_i][x_j][x_k]
+  std::map<std::array<int32_t, 3>, std::vector<int>> groups;
+  for (int e = 0; e < n; ++e) groups[{rj[3 * e], rj[3 * e + 1], rj[3 * e + 2]}].push_back(e);
+  if ((int)groups.size() > kMaxGroups) {
+    ctx->err = "elph_set_ifc3: more than 256 distinct R_j";
+    return ELPH_EINVAL;
+  }
+  std::vector<int32_t> hg, hoff, hrk;
+  std::vector<double> hpsi((size_t)n * blk);
+  hoff.push_back(0);
+  int pos = 0;
+  for (auto& kv : groups) {
+    hg.insert(hg.end(), kv.first.begin(), kv.first.end());
+    for (int e : kv.second) {
+      hrk.insert(hrk.end(), {rk[3 * e], rk[3 * e + 1], rk[3 * e + 2]});
+      const double* src = psi + (int64_t)e * blk;   // [ti][tj][tk][a][b][c]
+      double* dst = hpsi.data() + (int64_t)pos * blk;
+      for (int ti = 0; ti < na; ++ti)
+        for (int tj = 0; tj < na; ++tj)
+          for (int tk = 0; tk < na; ++tk)
+            for (int a = 0; a < 3; ++a)
+              for (int b = 0; b < 3; ++b)
+                for (int c = 0; c < 3; ++c)
+                  dst[((3 * ti + a) * nbr + 3 * tj + b) * nbr + 3 * tk + c] =
+                      src[((((ti * na + tj) * na + tk) * 3 + a) * 3 + b) * 3 + c];
+      ++pos;
+    }
+    hoff.push_back(pos);
+  }
+  ctx->n3 = n;
+  ctx->ng3 = (int)groups.size();
+  ALLOC(ctx->d_i3_rj, hg.size() * sizeof(int32_t));
+  ALLOC(ctx->d_i3_off, hoff.size() * sizeof(int32_t));
+  ALLOC(ctx->d_i3_rk, hrk.size() * sizeof(int32_t));
+  ALLOC(ctx->d_i3_psi, hpsi.size() * sizeof(double));
+  HIPCHK(hipMemcpy(ctx->d_i3_rj, hg.data(), hg.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->d_i3_off, hoff.data(), hoff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->d_i3_rk, hrk.data(), hrk.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->d_i3_psi, hpsi.data(), hpsi.size() * sizeof(double), hipMemcpyHostToDevice));
+  return ELPH_OK;
+}
+
+elph_status phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, const int32_t* qp, double* V2) {
+  elph_status st = check_phph(ctx);
+  if (st != ELPH_OK) return st;
+  if (npairs < 0 || (npairs > 0 && (!q || !qp || !V2))) {
+    ctx->err = "elph_phph_vertex: bad pair list";
+    return ELPH_EINVAL;
+  }
+  if (npairs == 0) return ELPH_OK;
+  if (npairs > 0x7fffffff) {
+    ctx->err = "elph_phph_vertex: too many pairs for one call";
+    return ELPH_EINVAL;
+  }
+  st = build_tables(ctx);
+  if (st != ELPH_OK) return st;
+  cd* phi = nullptr;
+  st = build_fold(ctx, &phi);
+  if (st != ELPH_OK) return st;
+#define VTX(N) launch_vertex<N>(ctx, npairs, q, qp, phi, V2)
+  NBR_SWITCH(ctx->nbr, VTX)
+#undef VTX
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  dev_free(ctx, phi);
+  return ELPH_OK;
+}
+
+elph_status phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W) {
+  elph_status st = check_phph(ctx);
+  if (st != ELPH_OK) return st;
+  if (!(sigma_eV > 0) || !std::isfinite(sigma_eV) || !W) {
+    ctx->err = "elph_phph_rates: sigma must be positive and W non-null";
+    return ELPH_EINVAL;
+  }
+  if (ctx->nk > 0x7fffffff) {
+    ctx->err = "elph_phph_rates: mesh too large";
+    return ELPH_EINVAL;
+  }
+  st = build_tables(ctx);
+  if (st != ELPH_OK) return st;
+  cd* phi = nullptr;
+  st = build_fold(ctx, &phi);
+  if (st != ELPH_OK) return st;
+  const int64_t nq = ctx->nk;
+  // chunks of q' so that the grid holds at least ~4096 blocks
+  int nchunk = (int)std::min<int64_t>(nq, std::max<int64_t>(1, (4096 + nq - 1) / nq));
+  const int chunk = (int)((nq + nchunk - 1) / nchunk);
+  nchunk = (int)((nq + chunk - 1) / chunk);
+  double* part = nullptr;
+  ALLOC(part, (size_t)nchunk * nq * ctx->nbr * sizeof(double));
+  const double kT = kBoltzEVK * T_K;
+#define ROWS(N) launch_rows<N>(ctx, chunk, nchunk, phi, kT, sigma_eV, part)
+  NBR_SWITCH(ctx->nbr, ROWS)
+#undef ROWS
+  HIPCHK(hipGetLastError());
+  const double pref = kPi / (4.0 * (double)nq) * kPhPhC;
+  hipLaunchKernelGGL(k_phph_finish, dim3(blocks_for(nq * ctx->nbr, 256)), dim3(256), 0, ctx->stream, nq, ctx->nbr,
+                     nchunk, part, ctx->d_hw, kT, ctx->omega_min, pref, W);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  dev_free(ctx, part);
+  dev_free(ctx, phi);
+  return ELPH_OK;
+}
+
+}  // namespace elph

@@ -46,6 +46,7 @@ EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
            "elph_batch_tune", "elph_tables",
            "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
+           "elph_set_ifc3", "elph_phph_vertex", "elph_phph_rates",
            "elph_mlp_create", "elph_mlp_destroy", "elph_mlp_last_error", "elph_mlp_nparams",
            "elph_mlp_get_params", "elph_mlp_set_params", "elph_mlp_forward", "elph_mlp_gradients",
            "elph_mlp_train_step", "elph_screen_nin", "elph_screen_samples", "elph_scatt_rates_screened")
@@ -84,6 +85,9 @@ def load():
     lib.elph_ko_enforce.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp]
     lib.elph_set_delta.argtypes = [vp, ctypes.c_int32]
     lib.elph_set_polar.argtypes = [vp, vp, vp, vp]
+    lib.elph_set_ifc3.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+    lib.elph_phph_vertex.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
+    lib.elph_phph_rates.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
     lib.elph_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.elph_batch_destroy.argtypes = [vp]
     lib.elph_batch_destroy.restype = None
@@ -264,6 +268,30 @@ def elph_set_polar(ctx, zstar, eps_inf, tau=None):
     _check(ctx, load().elph_set_polar(ctx.handle, z.ctypes.data_as(ctypes.c_void_p),
                                       e.ctypes.data_as(ctypes.c_void_p),
                                       None if t is None else t.ctypes.data_as(ctypes.c_void_p)))
+
+
+def elph_set_ifc3(ctx, rj, rk, psi):
+    """Third-order force constants: rj, rk [n][3] cells and psi
+    [n][natom][natom][natom][3][3][3] (eV/A^3) of Eq. 13; psi=None removes them."""
+    if psi is None:
+        _check(ctx, load().elph_set_ifc3(ctx.handle, 0, None, None, None))
+        return
+    a = np.ascontiguousarray(rj, dtype=np.int32)
+    b = np.ascontiguousarray(rk, dtype=np.int32)
+    p = np.ascontiguousarray(psi, dtype=np.float64)
+    _check(ctx, load().elph_set_ifc3(ctx.handle, int(a.shape[0]), a.ctypes.data_as(ctypes.c_void_p),
+                                     b.ctypes.data_as(ctypes.c_void_p), p.ctypes.data_as(ctypes.c_void_p)))
+
+
+def elph_phph_vertex(ctx, q, qp, V2):
+    """|V-(q, q')|^2 of Eq. 13 for device int32 mesh-index lists q, qp into V2
+    [npairs][nbr][nbr][nbr] (device FP64)."""
+    _check(ctx, load().elph_phph_vertex(ctx.handle, int(q.numel()), _ptr(q), _ptr(qp), _ptr(V2)))
+
+
+def elph_phph_rates(ctx, T, sigma, W_ph):
+    """Three-phonon RTA rates (Eq. 26) of every mode into W_ph [Nq][nbr] (device FP64, 1/s)."""
+    _check(ctx, load().elph_phph_rates(ctx.handle, float(T), float(sigma), _ptr(W_ph)))
 
 
 def elph_ko_enforce(ctx, T, I, J, F, G):

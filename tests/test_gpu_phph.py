@@ -1,0 +1,146 @@
+"""GPU parity of the three-phonon path (Eqs. 13, 14, 26) against the oracle.
+
+The C-ABI calls elph_set_ifc3 / elph_phph_vertex / elph_phph_rates run on
+seeded synthetic force constants; the oracle evaluates Eq. 13 from its
+definition (both V+ and V- directly) on the same inputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+E = pytest.importorskip("paper_2109_08547_amd")
+DEV = "cuda:0"
+T, SIGMA = 300.0, 0.004
+
+_cases = {}
+
+
+def _case(name):
+    """(cfg, mat, prob, ifc3) of a small material: tiny3 (1 atom), tiny4 (2
+    atoms), tiny4's settings with 3 and 4 atoms, and the metal metal6."""
+    if name not in _cases:
+        base = {"tiny3": "tiny3", "tiny4": "tiny4", "atoms3": "tiny4", "atoms4": "tiny4", "metal6": "metal6"}[name]
+        cfg = dict(synth.config(base))
+        over = {"atoms3": dict(na=3, mesh=4), "atoms4": dict(na=4, mesh=3)}.get(name, {})
+        cfg.update(over)
+        mat = synth.material_for(cfg, with_g=True)
+        prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+        ifc3 = synth.ifc3_params(mat["natom"], 50 + len(name), scale=0.3)
+        _cases[name] = (cfg, mat, prob, ifc3)
+    return _cases[name]
+
+
+def _ctx(cfg, mat, ifc3):
+    ctx = E.elph_create(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], precision="fp64")
+    E.elph_set_ifc3(ctx, *ifc3)
+    return ctx
+
+
+def _oracle_v2(prob, ifc3, qs, qps):
+    """|V-(q, q')|^2 from the oracle with modes below omega_min zeroed."""
+    Ed = oracle.eigendisplacements(prob.mat, prob.u)
+    on = prob.mode_on
+    out = []
+    for q in np.unique(qs):
+        sel = np.nonzero(qs == q)[0]
+        qp = qps[sel]
+        qpp = oracle.mesh_linear(prob.ijk[q] - prob.ijk[qp], prob.n)
+        l2, l3 = oracle.mesh_linear(-prob.ijk[qp], prob.n), oracle.mesh_linear(-prob.ijk[qpp], prob.n)
+        V = oracle.phph_vertex(ifc3, prob.kfrac[l2], prob.kfrac[l3], Ed[q], Ed[l2], Ed[l3])
+        m = on[q][None, :, None, None] & on[qp][:, None, :, None] & on[qpp][:, None, None, :]
+        out.append((sel, np.where(m, np.abs(V) ** 2, 0.0)))
+    res = np.zeros((qs.size,) + out[0][1].shape[1:])
+    for sel, v in out:
+        res[sel] = v
+    return res
+
+
+@pytest.mark.parametrize("name", ["tiny3", "tiny4", "atoms3", "atoms4"])
+def test_phph_vertex_all_pairs(name):
+    cfg, mat, prob, ifc3 = _case(name)
+    nq, nbr = prob.nq, prob.nbr
+    qs, qps = np.divmod(np.arange(nq * nq), nq)
+    ctx = _ctx(cfg, mat, ifc3)
+    V2 = torch.empty(nq * nq * nbr ** 3, dtype=torch.float64, device=DEV)
+    E.elph_phph_vertex(ctx, torch.from_numpy(qs.astype(np.int32)).to(DEV),
+                       torch.from_numpy(qps.astype(np.int32)).to(DEV), V2)
+    torch.cuda.synchronize()
+    got = V2.cpu().numpy().reshape(nq * nq, nbr, nbr, nbr)
+    ref = _oracle_v2(prob, ifc3, qs, qps)
+    scale = ref.max()
+    assert scale > 0
+    assert np.abs(got - ref).max() <= 1e-11 * scale
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["tiny3", "tiny4", "atoms3", "atoms4"])
+def test_phph_rates(name):
+    cfg, mat, prob, ifc3 = _case(name)
+    ctx = _ctx(cfg, mat, ifc3)
+    W = torch.empty(prob.nq * prob.nbr, dtype=torch.float64, device=DEV)
+    E.elph_phph_rates(ctx, T, SIGMA, W)
+    got = W.cpu().numpy().reshape(prob.nq, prob.nbr)
+    ref = oracle.phph_rates(prob, ifc3, T, SIGMA)
+    assert ref.max() > 0
+    assert np.abs(got - ref).max() <= 1e-10 * ref.max()
+    big = ref > 1e-6 * ref.max()
+    assert np.all(np.abs(got[big] - ref[big]) <= 1e-9 * ref[big])
+    assert np.all(got[~prob.mode_on] == 0)
+    ctx.close()
+
+
+def test_phph_rates_drive_the_coupled_iteration():
+    """The three-phonon RTA rates as the external phonon rate of the coupled
+    iteration (in place of the model rate), GPU against oracle, on the metal
+    (the gapped tiny materials' coupled iteration does not settle to 1e-12)."""
+    cfg, mat, prob, ifc3 = _case("metal6")
+    ctx = _ctx(cfg, mat, ifc3)
+    nq, nbr = prob.nq, prob.nbr
+    W = torch.empty(nq * nbr, dtype=torch.float64, device=DEV)
+    E.elph_phph_rates(ctx, T, SIGMA, W)
+    sz = E.elph_sizes(ctx)
+    M = sz["nstates"]
+    I, J = [torch.empty(3 * M, dtype=torch.float64, device=DEV) for _ in range(2)]
+    F, G = [torch.empty(3 * nq * nbr, dtype=torch.float64, device=DEV) for _ in range(2)]
+    E.elph_iterate(ctx, T, I, J, F, G, W_ph_ext=W, level=3, tol=1e-12, maxit=400)
+    torch.cuda.synchronize()
+    wext = oracle.phph_rates(prob, ifc3, T, SIGMA)
+    Xp, Xm = prob.transition_probs(T)
+    ref = oracle.iterate(prob, T, Xp, Xm, 3, tol=1e-12, maxit=400, w_ext=wext)
+    assert ref["converged"]
+    got = dict(I=I.cpu().numpy().reshape(M, 3), J=J.cpu().numpy().reshape(M, 3),
+               F=F.cpu().numpy().reshape(nq, nbr, 3), G=G.cpu().numpy().reshape(nq, nbr, 3))
+    for key in ("I", "J", "F", "G"):
+        scale = np.abs(ref[key]).max()
+        assert scale > 0, key
+        assert np.abs(got[key] - ref[key]).max() <= 1e-7 * scale, key
+    ctx.close()
+
+
+def test_phph_errors():
+    cfg, mat, prob, ifc3 = _case("tiny4")
+    ctx = E.elph_create(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], precision="fp64")
+    W = torch.empty(prob.nq * prob.nbr, dtype=torch.float64, device=DEV)
+    with pytest.raises(E.ElphError):
+        E.elph_phph_rates(ctx, T, SIGMA, W)          # no force constants yet
+    E.elph_set_ifc3(ctx, *ifc3)
+    with pytest.raises(E.ElphError):
+        E.elph_phph_rates(ctx, T, 0.0, W)            # sigma not positive
+    bad = ifc3[2].copy()
+    bad[0, 0, 0, 0, 0, 0, 0] = np.nan
+    with pytest.raises(E.ElphError):
+        E.elph_set_ifc3(ctx, ifc3[0], ifc3[1], bad)
+    # an index outside the mesh gives NaN for that pair only
+    E.elph_set_ifc3(ctx, *ifc3)
+    q = torch.tensor([1, prob.nq, 2], dtype=torch.int32, device=DEV)
+    qp = torch.tensor([3, 0, 5], dtype=torch.int32, device=DEV)
+    V2 = torch.empty(3 * prob.nbr ** 3, dtype=torch.float64, device=DEV)
+    E.elph_phph_vertex(ctx, q, qp, V2)
+    v = V2.cpu().numpy().reshape(3, -1)
+    assert np.all(np.isnan(v[1])) and np.all(np.isfinite(v[[0, 2]]))
+    ctx.close()
