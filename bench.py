@@ -58,9 +58,13 @@ def stored_traffic(form, workload):
     summary does not cover this form and workload."""
     if workload != "mixed48":
         return None
+    return _stored_value("k_cgemm_mixed48_counters.md", "vertex.hip", "traffic_bytes_per_launch[%s]" % form)
+
+
+def _stored_value(summary, source, key):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_cgemm_mixed48_counters.md")
-    src = os.path.join(ROOT, "paper_2109_08547_amd", "csrc", "vertex.hip")
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_2109_08547_amd", "csrc", source)
     try:
         text = open(path).read()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -68,7 +72,6 @@ def stored_traffic(form, workload):
         return None
     vals = dict(l.split(": ", 1) for l in text.splitlines()
                 if l.startswith(("traffic_bytes_per_launch[", "source_sha256:")))
-    key = "traffic_bytes_per_launch[%s]" % form
     if vals.get("source_sha256", "").strip() != sha or key not in vals:
         return None
     return float(vals[key])
@@ -315,12 +318,107 @@ def run_large(E, torch, form="fp32"):
     }
 
 
+PHPH_WORKLOAD = ("three-phonon RTA rates (Eqs. 13, 14, 26) of every mode on a %d^3 q mesh: the 2-atom material "
+                 "of mixed48 (Si and C masses, 203 R_p vectors), synthetic IFC3 on the cell triples of {-1,0,1}^3 "
+                 "(343 (R_j, R_k) entries, leg-symmetric, acoustic sum rule), Gaussian sigma 2 meV, 300 K, all "
+                 "(q, q') pairs, absorption and decay")
+
+
+def phph_flops(nbr, ng):
+    """Algorithmic flops of one (q, q') pair of the row kernel: the R_j sum
+    (ng complex MACs per element of A), the two eigendisplacement
+    contractions (nbr^4 complex MACs each) at 8 flops per complex MAC, and
+    ~20 flops per branch triple in the rate epilogue."""
+    return 8.0 * (ng * nbr ** 3 + 2 * nbr ** 4) + 20.0 * nbr ** 3
+
+
+def run_phph(E, torch, steps, warmup, n=24, cpu=True, budget_s=20.0):
+    """Three-phonon rates of every mode of an n^3 q mesh: `steps` timed calls
+    of elph_phph_rates (fold table, row kernel, finish) after `warmup`; the
+    oracle on a seeded sample of rows beside it."""
+    import synth
+    dev = torch.device("cuda:0")
+    cfg = dict(synth.config("mixed48"))
+    cfg["mesh"] = n
+    mat = synth.material_for(cfg, with_g=False)
+    nb, na, nr = mat["nwann"], mat["natom"], len(mat["re"])
+    mat["g_r"] = np.zeros((nr, nr, 3 * na, nb, nb), dtype=np.complex128)
+    ifc3 = synth.ifc3_params(na, 2109, scale=0.3)
+    ng = len(set(map(tuple, ifc3[0].tolist())))
+    T, sigma = 300.0, 0.002
+    ctx = E.elph_create(mat, n, cfg["mu"], cfg["window"], cfg["sigma"], precision="fp64")
+    E.elph_set_ifc3(ctx, *ifc3)
+    sz = E.elph_sizes(ctx)
+    nq, nbr = sz["nk"], sz["nbr"]
+    W = torch.empty(nq * nbr, dtype=torch.float64, device=dev)
+    E.elph_timing(ctx, True)
+    for _ in range(warmup):
+        E.elph_phph_rates(ctx, T, sigma, W)
+    torch.cuda.synchronize()
+    times, rows_ms = [], []
+    for i in range(steps):
+        t0 = time.perf_counter()
+        E.elph_phph_rates(ctx, T, sigma, W)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        rows_ms.append(E.elph_timing(ctx, True, read=True)["step2"])
+        print("bench: phph%d step %d: %.1f ms (row kernel %.1f ms)" % (n, i, 1e3 * times[-1], rows_ms[-1]),
+              file=sys.stderr, flush=True)
+    w_gpu = W.cpu().numpy().reshape(nq, nbr)
+    ctx.close()
+    s = float(np.mean(times))
+    rate_terms = 2.0 * nq * nq * nbr ** 3
+    k_ms = float(np.mean(rows_ms))
+    flops = phph_flops(nbr, ng) * nq * nq
+    out = {
+        "metric": "three-phonon transition rates/s (Eq. 14 terms, absorption and decay)", "value": rate_terms / s,
+        "unit": "transition rates/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * s,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "phph%d: " % n + PHPH_WORKLOAD % n, "nq": nq, "nbr": nbr, "ifc3_entries": len(ifc3[0]),
+                   "rj_groups": ng, "pairs": nq * nq},
+        "roofline": {"bound": "alu", "kernel": ("k_phph_tile<%d>" if nbr <= 6 and ng <= 32 else "k_phph_rows<%d>") % nbr, "achieved": flops / (k_ms * 1e-3) / 1e12,
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": flops / (k_ms * 1e-3) / 1e12 / 78.6,
+                     "traffic": _stored_value("phph_kernel_stats.md", "phph.hip",
+                                              "traffic_bytes_per_launch[phph%d]" % n),
+                     "kernel_ms": k_ms, "flops_per_pair": phph_flops(nbr, ng)},
+    }
+    if cpu:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        except Exception:  # pragma: no cover
+            cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        prob = oracle.Problem(mat, n, cfg["mu"], cfg["window"], cfg["sigma"])
+        t_tab = time.perf_counter() - t0
+        rng = np.random.default_rng(7)
+        order = rng.permutation(nq)
+        done, t_rows, err = 0, 0.0, 0.0
+        while done < nq and t_rows < budget_s:
+            rows = order[done:done + 2]
+            t1 = time.perf_counter()
+            w = oracle.phph_rates(prob, ifc3, T, sigma, rows=rows)
+            t_rows += time.perf_counter() - t1
+            err = max(err, float(np.abs(w_gpu[rows] - w).max() / max(np.abs(w).max(), 1e-300)))
+            done += rows.size
+        t_eff = t_rows + t_tab * done / nq
+        out["cpu_baseline"] = {
+            "value": 2.0 * done * nq * nbr ** 3 / t_eff, "unit": "transition rates/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": "oracle phonon tables (%.1f s, amortised by rows) + the rates of %d seeded q rows x all %d q' "
+                      "(%.1f s)" % (t_tab, done, nq, t_rows),
+            "max_rel_err_gpu_vs_oracle_rows": err}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mixed48", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="mixed48",
+                    choices=sorted(WORKLOADS) + ["phph%d" % n for n in (8, 12, 16, 20, 24, 32)])
     ap.add_argument("--forms", default="fp64,fp32,bf16x3,bf16x6,fp16x3")
     ap.add_argument("--no-iterate", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -357,6 +455,11 @@ def main():
         print("bench: copy calibration, 3 x neg over 2^28 float32 (1 GiB read + 1 GiB written each)",
               file=sys.stderr, flush=True)
         del a, b
+    if args.workload.startswith("phph"):
+        n = int(args.workload[4:])
+        print(json.dumps(run_phph(E, torch, args.steps, args.warmup, n=n, cpu=not args.no_cpu,
+                                  budget_s=args.cpu_budget)), flush=True)
+        return
     cfg = synth.config(args.workload)
     mat = synth.material_for(cfg)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]

@@ -235,8 +235,9 @@ elph_status elph_phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, con
  * delta(w - w' - w'') for q -> q' + q'' (Eq. 14), delta the Gaussian of
  * standard deviation sigma_eV in hbar w; modes below omega_min take no
  * part.  W_ph: device FP64 [Nq][nbr], 1/s; it can be passed to
- * elph_iterate as W_ph_ext.  Synchronous.  ESTATE without force constants,
- * EINVAL for T or sigma not positive. */
+ * elph_iterate as W_ph_ext.  Synchronous.  With timing on, the row kernel
+ * (the pair sums) is reported in the step2 slot of elph_timing.  ESTATE
+ * without force constants, EINVAL for T or sigma not positive. */
 elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W_ph);
 
 /* Select the energy-conserving delta of Eq. 8 for this context's later
