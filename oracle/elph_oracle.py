@@ -77,7 +77,7 @@ __all__ = [
     "g_wannier_brute", "g_wannier_factorised", "g_bloch", "Problem", "default_w_ext",
     "tetra_delta_weights", "tetra_neighbourhood",
     "iterate", "transport_tensors", "ko_residual", "ko_enforce", "energy_groups",
-    "C_PHPH", "eigendisplacements", "ifc3_matrix", "phph_vertex", "phph_rates",
+    "C_PHPH", "eigendisplacements", "ifc3_matrix", "phph_vertex", "phph_rates", "phph_inscatter",
 ]
 
 
@@ -943,3 +943,46 @@ def phph_rates(prob, ifc3, T, sigma, rows=None, parts=False):
     if parts:
         return W, S[+1], S[-1]
     return W
+
+
+def phph_inscatter(prob, ifc3, T, sigma, F, rows=None):
+    """The three-phonon in-scattering of a phonon deviation field F [nq][nbr][3]
+    (the self term of Eq. 26 before its division by the RTA rate):
+    S_sq = sum_{s'q's''} [W+ (F_s''q'' - F_s'q') + W-/2 (F_s''q'' + F_s'q')] / (n (1 + n)),
+    W+ for q'' = q + q', W- for q'' = q - q' (Eq. 14), terms as in phph_rates."""
+    n = prob.n
+    nq, nbr = prob.nq, prob.nbr
+    E = eigendisplacements(prob.mat, prob.u)
+    nB, onB = bose_pair(prob.hw, T)
+    on = prob.mode_on
+    pref = np.pi / (4.0 * nq) * C_PHPH
+    rows = np.arange(nq) if rows is None else np.asarray(rows)
+    out = np.zeros((rows.size, nbr, 3))
+    allq = np.arange(nq)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for r, q in enumerate(rows):
+            for sign in (+1, -1):
+                leg2 = mesh_linear(sign * prob.ijk[allq], n)
+                qpp = mesh_linear(prob.ijk[q] + sign * prob.ijk[allq], n)
+                leg3 = mesh_linear(-prob.ijk[qpp], n)
+                V = phph_vertex(ifc3, prob.kfrac[leg2], prob.kfrac[leg3], E[q], E[leg2], E[leg3])
+                e1 = prob.hw[q][None, :, None, None]
+                e2 = prob.hw[allq][:, None, :, None]
+                e3 = prob.hw[qpp][:, None, None, :]
+                mask = (on[q][None, :, None, None] & on[allq][:, None, :, None]
+                        & on[qpp][:, None, None, :])
+                bare = np.abs(V) ** 2 * gaussian_delta(e1 + sign * e2 - e3, sigma) / (e1 * e2 * e3)
+                on1 = onB[q][None, :, None, None]
+                n2, on2 = nB[allq][:, None, :, None], onB[allq][:, None, :, None]
+                n3 = nB[qpp][:, None, None, :]
+                if sign > 0:
+                    w = np.where(mask, pref * bare * on1 * on2 * n3, 0.0)          # W+
+                    # sum_{q', s', s''} W+ (F_{s''q''} - F_{s'q'})
+                    out[r] += (np.einsum("nsab,nbc->sc", w, F[qpp])
+                               - np.einsum("nsab,nac->sc", w, F[allq]))
+                else:
+                    w = np.where(mask, 0.5 * pref * bare * on1 * n2 * n3, 0.0)     # W-/2
+                    out[r] += (np.einsum("nsab,nbc->sc", w, F[qpp])
+                               + np.einsum("nsab,nac->sc", w, F[allq]))
+            out[r] /= np.where(on[q], nB[q] * onB[q], 1.0)[:, None]
+    return out

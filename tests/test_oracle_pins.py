@@ -809,3 +809,20 @@ def test_phph_rate_prefactor_in_si_units():
     d_si = d / 1.602176634e-19 * hbar                                 # delta(omega) in s
     w_si = np.pi * hbar / (4 * N) * v2_si / omega.prod() * d_si
     assert abs(w_ev - w_si) <= 1e-8 * w_si
+
+
+@pytest.mark.parametrize("sigma", [0.004, 0.002])
+def test_phph_inscatter_conserves_energy(sigma):
+    """Each three-phonon event conserves energy up to the width of the delta,
+    so the in-scattering of the field F_sq = hbar omega_sq (Eq. 26) returns
+    hbar omega_sq times the RTA rate of the mode, up to the Gaussian-weighted
+    energy mismatch of its terms (a few sigma): a wrong sign of the W+ term,
+    a missing half on W- or a wrong partner index misses by about hbar omega."""
+    prob, ifc3 = _phph_problem()
+    W = oracle.phph_rates(prob, ifc3, 300.0, sigma)
+    F = np.repeat(prob.hw[:, :, None], 3, axis=2)
+    S = oracle.phph_inscatter(prob, ifc3, 300.0, sigma, F)
+    on = prob.mode_on & (W > 0)
+    assert on.sum() > 100
+    assert np.all(np.abs(S[..., 0] - prob.hw * W)[on] <= 3.0 * sigma * W[on])
+    assert np.allclose(S[..., 1], S[..., 0]) and np.all(S[~prob.mode_on] == 0)
