@@ -240,6 +240,16 @@ elph_status elph_phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, con
  * without force constants, EINVAL for T or sigma not positive. */
 elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W_ph);
 
+/* The three-phonon in-scattering of a phonon deviation field (the self term
+ * of Eq. 26 before its division by the RTA rate):
+ *   S_sq = sum_{s'q's''} [W+ (F_s''q'' - F_s'q') + W-/2 (F_s''q'' + F_s'q')] / (n_sq (1 + n_sq))
+ * with W+- as in elph_phph_rates (q'' = q + q' for W+, q - q' for W-), so
+ * that Delta F^S = S / W^RTA.  F and S: device FP64 [Nq][nbr][3] (S in
+ * units of F times 1/s; zero for modes below omega_min).  For up to 2
+ * atoms and 32 distinct rj.  Synchronous.  ESTATE without force constants,
+ * EINVAL for T or sigma not positive or F null. */
+elph_status elph_phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F, double* S);
+
 /* Select the energy-conserving delta of Eq. 8 for this context's later
  * vertex stores (the paper offers the triangle and the analytic
  * tetrahedron methods beside smearing; section on the program's workflow).

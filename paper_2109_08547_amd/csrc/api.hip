@@ -437,6 +437,14 @@ extern "C" elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV
   return elph::phph_rates(ctx, T_K, sigma_eV, W_ph);
 }
 
+extern "C" elph_status elph_phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F,
+                                           double* S) {
+  CHECK_CTX(ctx);
+  elph_status st = check_T(ctx, T_K);
+  if (st != ELPH_OK) return st;
+  return elph::phph_inscatter(ctx, T_K, sigma_eV, F, S);
+}
+
 extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf, const double* tau) {
   CHECK_CTX(ctx);
   HIPCHK(hipStreamSynchronize(ctx->stream));

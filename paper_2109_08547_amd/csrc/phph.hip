@@ -280,7 +280,7 @@ __global__ void k_phph_bose(int64_t n, const double* __restrict__ hw, double kT,
 // <= 256 (one or two atoms).
 constexpr int kTQ = 16, kQB = 4, kMaxG = 32;
 
-template <int NBR>
+template <int NBR, int NC>
 struct TileLds {
   cd exq[kTQ][NBR * NBR];      // E_q of the tile's rows
   cd exd[kTQ][NBR * NBR];      // E_{-q'} of the rows for the current q''
@@ -291,17 +291,21 @@ struct TileLds {
   double e1[kTQ][NBR];
   double e2[kTQ][NBR], n2[kTQ][NBR];
   double e3[NBR], n3[NBR];
-  double acc[kTQ][NBR];
+  double acc[kTQ][NBR * (NC ? NC : 1)];
+  double f3[NBR * (NC ? NC : 1)];                 // F at q'' (NC > 0)
+  double f2[NC ? kTQ : 1][NBR * (NC ? NC : 1)];   // F at q'
+  double f2m[NC ? kTQ : 1][NBR * (NC ? NC : 1)];  // F at -q'
 };
 
-template <int NBR>
+template <int NBR, int NC>
 __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int prange, const int32_t* __restrict__ gr,
                                                    int ng, const cd* __restrict__ phi, const cd* __restrict__ Lq,
                                                    const double* __restrict__ hw, const double* __restrict__ nbose,
-                                                   double omega_min, double sigma, double* __restrict__ part) {
-  constexpr int N2 = NBR * NBR, N3 = N2 * NBR;
+                                                   double omega_min, double sigma, const double* __restrict__ F,
+                                                   double* __restrict__ part) {
+  constexpr int N2 = NBR * NBR, N3 = N2 * NBR, NV = NC ? NC : 1;
   static_assert(N3 <= 256 && N2 <= 64 && kQB * 64 == 256, "one slab element per thread, one row per wave");
-  __shared__ TileLds<NBR> L;
+  __shared__ TileLds<NBR, NC> L;
   const int q0 = blockIdx.x * kTQ, nt = min(kTQ, nq - q0);
   const int P0 = blockIdx.y * prange, P1 = min(nq, P0 + prange);
   const MeshDims md{ph.n0, ph.n1, ph.n2};
@@ -317,8 +321,8 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
   for (int t = tid; t < kTQ * NBR; t += blockDim.x) {
     const int r = t / NBR, s = t - r * NBR;
     L.e1[r][s] = r < nt ? hw[(int64_t)(q0 + r) * NBR + s] : 0.0;
-    L.acc[r][s] = 0.0;
   }
+  for (int t = tid; t < kTQ * NBR * NV; t += blockDim.x) L.acc[t / (NBR * NV)][t % (NBR * NV)] = 0.0;
   const double inv2s2 = 0.5 / (sigma * sigma), dnorm = 1.0 / (sqrt(2.0 * kPi) * sigma);
   for (int P = P0; P < P1; ++P) {
     cd slab[kMaxG];
@@ -337,6 +341,19 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
       cd v = cmake(0.0, 0.0);
       if (r < nt) v = edisp(Lq, hw, q_between(P, q0 + r, md.n0, md.n1, md.n2), NBR, e / NBR, e % NBR);
       L.exd[r][e] = v;
+    }
+    if constexpr (NC > 0) {
+      for (int t = tid; t < NBR * NC; t += blockDim.x) L.f3[t] = F[(int64_t)P * NBR * NC + t];
+      for (int t = tid; t < kTQ * NBR * NC; t += blockDim.x) {
+        const int r = t / (NBR * NC), e = t - r * (NBR * NC);
+        double a = 0.0, b = 0.0;
+        if (r < nt) {
+          a = F[(int64_t)q_between(q0 + r, P, md.n0, md.n1, md.n2) * NBR * NC + e];
+          b = F[(int64_t)q_between(P, q0 + r, md.n0, md.n1, md.n2) * NBR * NC + e];
+        }
+        L.f2[r][e] = a;
+        L.f2m[r][e] = b;
+      }
     }
     for (int t = tid; t < kTQ * NBR; t += blockDim.x) {
       const int r = t / NBR, s = t - r * NBR;
@@ -386,9 +403,9 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
       __syncthreads();
       {  // wave r: row rb + r, lane = (s', s'')
         const int r = wave;
-        double c[NBR];
+        double c[NBR * NV];
 #pragma unroll
-        for (int s1 = 0; s1 < NBR; ++s1) c[s1] = 0.0;
+        for (int k = 0; k < NBR * NV; ++k) c[k] = 0.0;
         if (lane < N2) {
           const int s2 = lane / NBR, s3 = lane - s2 * NBR;
           const double E2 = L.e2[rb + r][s2], E3 = L.e3[s3];
@@ -398,45 +415,60 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
             for (int s1 = 0; s1 < NBR; ++s1) {
               const double E1 = L.e1[rb + r][s1];
               const double dp = E1 + E2 - E3, dm = E1 - E2 - E3;
-              const double occ = (1.0 + np2) * exp(-dp * dp * inv2s2) + 0.5 * np2 * exp(-dm * dm * inv2s2);
-              c[s1] = cabs2(L.A[r][s1 * N2 + lane]) * f * occ;
+              const double b = cabs2(L.A[r][s1 * N2 + lane]) * f;
+              const double wp = b * (1.0 + np2) * exp(-dp * dp * inv2s2);  // absorption with -q'
+              const double wm = b * 0.5 * np2 * exp(-dm * dm * inv2s2);    // decay into q', half
+              if constexpr (NC == 0) {
+                c[s1] = wp + wm;
+              } else {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                  const double F3 = L.f3[s3 * NC + k];
+                  c[s1 * NC + k] = wp * (F3 - L.f2m[rb + r][s2 * NC + k]) + wm * (F3 + L.f2[rb + r][s2 * NC + k]);
+                }
+              }
             }
           }
         }
 #pragma unroll
-        for (int s1 = 0; s1 < NBR; ++s1) {
-          double x = c[s1];
+        for (int k = 0; k < NBR * NV; ++k) {
+          double x = c[k];
 #pragma unroll
           for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-          c[s1] = x;
+          c[k] = x;
         }
-        if (lane < NBR && rb + r < nt) {
-          double x = c[0];
+        if (rb + r < nt) {
 #pragma unroll
-          for (int s1 = 1; s1 < NBR; ++s1)
-            if (lane == s1) x = c[s1];
-          L.acc[rb + r][lane] += x;
+          for (int k0 = 0; k0 < NBR * NV; k0 += 64) {
+            if (lane + k0 < NBR * NV) {
+              double x = c[k0];
+#pragma unroll
+              for (int k = k0 + 1; k < NBR * NV && k < k0 + 64; ++k)
+                if (lane + k0 == k) x = c[k];
+              L.acc[rb + r][lane + k0] += x;
+            }
+          }
         }
       }
       __syncthreads();   // V (A) is rewritten by the next rows
     }
   }
   __syncthreads();
-  for (int t = tid; t < nt * NBR; t += blockDim.x) {
-    const int r = t / NBR, s = t - r * NBR;
-    part[((int64_t)blockIdx.y * nq + q0 + r) * NBR + s] = L.acc[r][s];
+  for (int t = tid; t < nt * NBR * NV; t += blockDim.x) {
+    const int r = t / (NBR * NV), e = t - r * (NBR * NV);
+    part[((int64_t)blockIdx.y * nq + q0 + r) * NBR * NV + e] = L.acc[r][e];
   }
 }
 
 // W[q][s] = pi C / (4 N_q) sum_chunks part / (E n), modes below omega_min 0
-__global__ void k_phph_finish(int64_t nq, int nbr, int nchunk, const double* __restrict__ part,
+__global__ void k_phph_finish(int64_t nq, int nbr, int nv, int nchunk, const double* __restrict__ part,
                               const double* __restrict__ hw, double kT, double omega_min, double pref,
                               double* __restrict__ W) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nq * nbr) return;
-  const double w = hw[e];
+  if (e >= nq * nbr * nv) return;
+  const double w = hw[e / nv];
   double sum = 0.0;
-  for (int c = 0; c < nchunk; ++c) sum += part[(int64_t)c * nq * nbr + e];
+  for (int c = 0; c < nchunk; ++c) sum += part[(int64_t)c * nq * nbr * nv + e];
   W[e] = w >= omega_min ? pref * sum * expm1(w / kT) / w : 0.0;
 }
 
@@ -458,13 +490,13 @@ void launch_rows(elph_ctx ctx, int chunk, int nchunk, const cd* phi, double kT, 
                      kT, ctx->omega_min, sigma, part);
 }
 
-template <int NBR>
+template <int NBR, int NC>
 void launch_tile(elph_ctx ctx, int prange, int nrange, const cd* phi, const double* nbose, double sigma,
-                 double* part) {
+                 const double* F, double* part) {
   if constexpr (NBR * NBR * NBR <= 256)
-    hipLaunchKernelGGL(k_phph_tile<NBR>, dim3((unsigned)((ctx->nk + kTQ - 1) / kTQ), (unsigned)nrange), dim3(256), 0,
-                       ctx->stream, phase_tab(ctx), (int)ctx->nk, prange, ctx->d_i3_rj, ctx->ng3, phi,
-                       (const cd*)ctx->d_Lq, ctx->d_hw, nbose, ctx->omega_min, sigma, part);
+    hipLaunchKernelGGL((k_phph_tile<NBR, NC>), dim3((unsigned)((ctx->nk + kTQ - 1) / kTQ), (unsigned)nrange),
+                       dim3(256), 0, ctx->stream, phase_tab(ctx), (int)ctx->nk, prange, ctx->d_i3_rj, ctx->ng3, phi,
+                       (const cd*)ctx->d_Lq, ctx->d_hw, nbose, ctx->omega_min, sigma, F, part);
 }
 
 template <int NBR>
@@ -595,15 +627,25 @@ elph_status phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, const in
   return ELPH_OK;
 }
 
-elph_status phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W) {
+// One pass over every (q, q') pair: the rates (F = NULL) or the in-scattering
+// sums of a field F [nq][nbr][3] (Eq. 26), into out [nq][nbr] or [nq][nbr][3].
+static elph_status phph_pass(elph_ctx ctx, const char* name, double T_K, double sigma_eV, const double* F,
+                             double* out) {
   elph_status st = check_phph(ctx);
   if (st != ELPH_OK) return st;
-  if (!(sigma_eV > 0) || !std::isfinite(sigma_eV) || !W) {
-    ctx->err = "elph_phph_rates: sigma must be positive and W non-null";
+  if (!(sigma_eV > 0) || !std::isfinite(sigma_eV) || !out) {
+    ctx->err = std::string(name) + ": sigma must be positive and the output non-null";
     return ELPH_EINVAL;
   }
   if (ctx->nk > 0x7fffffff) {
-    ctx->err = "elph_phph_rates: mesh too large";
+    ctx->err = std::string(name) + ": mesh too large";
+    return ELPH_EINVAL;
+  }
+  const int64_t nq = ctx->nk;
+  const bool tile = ctx->nbr <= 6 && ctx->ng3 <= kMaxG;
+  const int nv = F ? 3 : 1;
+  if (F && !tile) {
+    ctx->err = std::string(name) + ": supported for up to 2 atoms and 32 distinct R_j";
     return ELPH_EINVAL;
   }
   st = build_tables(ctx);
@@ -611,8 +653,6 @@ elph_status phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W) {
   cd* phi = nullptr;
   st = build_fold(ctx, &phi);
   if (st != ELPH_OK) return st;
-  const int64_t nq = ctx->nk;
-  const bool tile = ctx->nbr <= 6 && ctx->ng3 <= kMaxG;
   int nchunk, chunk;
   if (tile) {
     // q'' ranges: about 4096 blocks in all, at least 8 q'' per block
@@ -625,7 +665,7 @@ elph_status phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W) {
   chunk = (int)((nq + nchunk - 1) / nchunk);
   nchunk = (int)((nq + chunk - 1) / chunk);
   double* part = nullptr;
-  ALLOC(part, (size_t)nchunk * nq * ctx->nbr * sizeof(double));
+  ALLOC(part, (size_t)nchunk * nq * ctx->nbr * nv * sizeof(double));
   const double kT = kBoltzEVK * T_K;
   double* nbose = nullptr;
   if (tile) {
@@ -634,8 +674,12 @@ elph_status phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W) {
                        nq * ctx->nbr, ctx->d_hw, kT, ctx->omega_min, nbose);
   }
   mark(ctx, 4);  // the row kernel is reported in the step-2 timing window
-  if (tile) {
-#define TILE(N) launch_tile<N>(ctx, chunk, nchunk, phi, nbose, sigma_eV, part)
+  if (tile && !F) {
+#define TILE(N) launch_tile<N, 0>(ctx, chunk, nchunk, phi, nbose, sigma_eV, nullptr, part)
+    NBR_SWITCH(ctx->nbr, TILE)
+#undef TILE
+  } else if (tile) {
+#define TILE(N) launch_tile<N, 3>(ctx, chunk, nchunk, phi, nbose, sigma_eV, F, part)
     NBR_SWITCH(ctx->nbr, TILE)
 #undef TILE
   } else {
@@ -646,14 +690,26 @@ elph_status phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W) {
   mark(ctx, 5);
   HIPCHK(hipGetLastError());
   const double pref = kPi / (4.0 * (double)nq) * kPhPhC;
-  hipLaunchKernelGGL(k_phph_finish, dim3(blocks_for(nq * ctx->nbr, 256)), dim3(256), 0, ctx->stream, nq, ctx->nbr,
-                     nchunk, part, ctx->d_hw, kT, ctx->omega_min, pref, W);
+  hipLaunchKernelGGL(k_phph_finish, dim3(blocks_for(nq * ctx->nbr * nv, 256)), dim3(256), 0, ctx->stream, nq,
+                     ctx->nbr, nv, nchunk, part, ctx->d_hw, kT, ctx->omega_min, pref, out);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
   dev_free(ctx, part);
   dev_free(ctx, nbose);
   dev_free(ctx, phi);
   return ELPH_OK;
+}
+
+elph_status phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W) {
+  return phph_pass(ctx, "elph_phph_rates", T_K, sigma_eV, nullptr, W);
+}
+
+elph_status phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F, double* S) {
+  if (!F) {
+    ctx->err = "elph_phph_inscatter: F is null";
+    return ELPH_EINVAL;
+  }
+  return phph_pass(ctx, "elph_phph_inscatter", T_K, sigma_eV, F, S);
 }
 
 }  // namespace elph

@@ -38,6 +38,7 @@ elph_status iterate(elph_ctx ctx, double T, const double* wext, int level, doubl
 elph_status phph_set_ifc3(elph_ctx ctx, int32_t n, const int32_t* rj, const int32_t* rk, const double* psi);
 elph_status phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, const int32_t* qp, double* V2);
 elph_status phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W);
+elph_status phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F, double* S);
 elph_status ko_enforce(elph_ctx ctx, double T, double* I, const double* J, const double* F, const double* G,
                        double* tensors, double* lambda, double* ko);
 

@@ -144,3 +144,29 @@ def test_phph_errors():
     v = V2.cpu().numpy().reshape(3, -1)
     assert np.all(np.isnan(v[1])) and np.all(np.isfinite(v[[0, 2]]))
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["tiny3", "tiny4", "metal6"])
+def test_phph_inscatter(name):
+    """The in-scattering of a seeded field and of F = hbar omega against the oracle."""
+    cfg, mat, prob, ifc3 = _case(name)
+    ctx = _ctx(cfg, mat, ifc3)
+    rng = np.random.default_rng(11)
+    for F in (rng.standard_normal((prob.nq, prob.nbr, 3)), np.repeat(prob.hw[:, :, None], 3, axis=2)):
+        Fd = torch.from_numpy(np.ascontiguousarray(F)).to(DEV)
+        S = torch.empty_like(Fd)
+        E.elph_phph_inscatter(ctx, T, SIGMA, Fd, S)
+        got = S.cpu().numpy()
+        ref = oracle.phph_inscatter(prob, ifc3, T, SIGMA, F)
+        assert np.abs(ref).max() > 0
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+    ctx.close()
+
+
+def test_phph_inscatter_refuses_more_than_two_atoms():
+    cfg, mat, prob, ifc3 = _case("atoms3")
+    ctx = _ctx(cfg, mat, ifc3)
+    F = torch.zeros(prob.nq * prob.nbr * 3, dtype=torch.float64, device=DEV)
+    with pytest.raises(E.ElphError):
+        E.elph_phph_inscatter(ctx, T, SIGMA, F, torch.empty_like(F))
+    ctx.close()
