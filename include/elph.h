@@ -250,6 +250,18 @@ elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W
  * EINVAL for T or sigma not positive or F null. */
 elph_status elph_phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F, double* S);
 
+/* Three-phonon processes in elph_iterate (Eq. 26): with sigma_eV > 0 (the
+ * Gaussian width of elph_phph_rates) every later elph_iterate adds the
+ * three-phonon RTA rate to the phonons' W^RTA (W_ph_ext then supplies the
+ * remaining channels; NULL means none instead of the model rate) and
+ * Delta F^S = S[F] / W^RTA (elph_phph_inscatter, for F and G) to every phonon
+ * update of levels PARTIAL and COUPLED; at level DRAGLESS the phonons then
+ * solve their own BTE F = F0 + Delta F^S[F] (G = 0) to tol.  sigma_eV = 0
+ * turns this off (the default).  Needs force constants (elph_set_ifc3) and
+ * at most 2 atoms at iterate time (ESTATE / EINVAL there).  EINVAL for a
+ * negative or non-finite sigma. */
+elph_status elph_set_phph(elph_ctx ctx, double sigma_eV);
+
 /* Select the energy-conserving delta of Eq. 8 for this context's later
  * vertex stores (the paper offers the triangle and the analytic
  * tetrahedron methods beside smearing; section on the program's workflow).

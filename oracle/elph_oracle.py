@@ -77,7 +77,7 @@ __all__ = [
     "g_wannier_brute", "g_wannier_factorised", "g_bloch", "Problem", "default_w_ext",
     "tetra_delta_weights", "tetra_neighbourhood",
     "iterate", "transport_tensors", "ko_residual", "ko_enforce", "energy_groups",
-    "C_PHPH", "eigendisplacements", "ifc3_matrix", "phph_vertex", "phph_rates", "phph_inscatter",
+    "C_PHPH", "eigendisplacements", "ifc3_matrix", "phph_vertex", "phph_rates", "phph_inscatter", "phph_operator",
 ]
 
 
@@ -674,19 +674,27 @@ def _rel_change(new, old):
     return np.linalg.norm(new - old) / max(nn, 1e-300)
 
 
-def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=None):
+def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=None, phph=None):
     """Solve Eq. 19 with the unified scheme: each phonon (outer) iteration
     brings the electrons (inner) to self-consistency with the current phonons.
     ``Xp``/``Xm`` are the full [nstates, nstates, nbr] arrays of Eq. 8.
+    ``phph`` = (ifc3, sigma) adds three-phonon scattering (Eq. 26): its RTA
+    rate joins W^RTA (``w_ext`` then holds the remaining channels, none when
+    None) and Delta F^S = S[F] / W^RTA joins every phonon update; at level
+    DRAGLESS the phonons then solve their own BTE F = F0 + Delta F^S[F].
     Returns dict(I, J, F, G, W_e, W_ph, iters, converged)."""
     M, nbr = prob.nstates, prob.nbr
     f, omf = fermi_pair(prob.eps, prob.mu, T)
     ff = f * omf
     W_e = (Xp + Xm).sum(axis=(1, 2)) / ff
     if w_ext is None:
-        w_ext = default_w_ext(prob, T)
+        w_ext = default_w_ext(prob, T) if phph is None else np.zeros((prob.nq, nbr))
     W_phe = prob.rates_ph(T, Xp)
     W_p = W_phe + w_ext                                     # [nq, nbr]
+    Mph = None
+    if phph is not None:
+        W_p = W_p + phph_rates(prob, phph[0], T, phph[1])
+        Mph = phph_operator(prob, phph[0], T, phph[1])
     n, onp = bose_pair(prob.hw, T)
     on = prob.mode_on
 
@@ -737,6 +745,13 @@ def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=Non
             acc[..., c] = _scatter_q(qij, Xp * diff[:, :, None], prob.nq)
         return phon0 + ph_norm[..., None] * acc
 
+    def ph_self(phon):
+        """Delta F^S of Eq. 26: the three-phonon in-scattering over W^RTA."""
+        if Mph is None:
+            return 0.0
+        S = (Mph @ phon.reshape(-1, 3)).reshape(phon.shape)
+        return S * inv_wp[..., None]
+
     def solve_e(x0, x):
         """Electron BTE (Eqs. 19, 22) to self-consistency for a fixed drive x0."""
         for it in range(1, maxit + 1):
@@ -754,7 +769,17 @@ def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=Non
     if level == LEVEL_DRAGLESS:
         I, itI, cI = solve_e(I0, I0.copy())
         J, itJ, cJ = solve_e(J0, J0.copy())
-        out.update(I=I, J=J, F=F0.copy(), G=G0.copy(), iters=max(itI, itJ), converged=cI and cJ)
+        F, itF, cF = F0.copy(), 0, True
+        if Mph is not None:
+            cF = False
+            for itF in range(1, maxit + 1):
+                Fn = F0 + ph_self(F)
+                r = _rel_change(Fn, F)
+                F = Fn
+                if r < tol:
+                    cF = True
+                    break
+        out.update(I=I, J=J, F=F, G=G0.copy(), iters=max(itI, itJ, itF), converged=cI and cJ and cF)
         return out
 
     I, J, F, G = I0.copy(), J0.copy(), F0.copy(), G0.copy()
@@ -763,8 +788,8 @@ def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=Non
     for it in range(1, maxit + 1):
         In, _, c1 = solve_e(I0 + drag_e(F), I)
         Jn, _, c2 = solve_e(J0 + drag_e(G), J)
-        Fn = ph_drag(In, F0)
-        Gn = ph_drag(Jn, G0)
+        Fn = ph_drag(In, F0) + ph_self(F)
+        Gn = ph_drag(Jn, G0) + ph_self(G)
         r = max(_rel_change(In, I), _rel_change(Jn, J), _rel_change(Fn, F), _rel_change(Gn, G))
         I, J, F, G = In, Jn, Fn, Gn
         if level == LEVEL_PARTIAL:
@@ -943,6 +968,44 @@ def phph_rates(prob, ifc3, T, sigma, rows=None, parts=False):
     if parts:
         return W, S[+1], S[-1]
     return W
+
+
+def phph_operator(prob, ifc3, T, sigma):
+    """The in-scattering of phph_inscatter as a dense matrix M [nq*nbr][nq*nbr]
+    (S = M F for each Cartesian column), assembled from the same W+- terms,
+    for small meshes."""
+    n = prob.n
+    nq, nbr = prob.nq, prob.nbr
+    E = eigendisplacements(prob.mat, prob.u)
+    nB, onB = bose_pair(prob.hw, T)
+    on = prob.mode_on
+    pref = np.pi / (4.0 * nq) * C_PHPH
+    M = np.zeros((nq, nbr, nq, nbr))
+    allq = np.arange(nq)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for q in range(nq):
+            for sign in (+1, -1):
+                leg2 = mesh_linear(sign * prob.ijk[allq], n)
+                qpp = mesh_linear(prob.ijk[q] + sign * prob.ijk[allq], n)
+                leg3 = mesh_linear(-prob.ijk[qpp], n)
+                V = phph_vertex(ifc3, prob.kfrac[leg2], prob.kfrac[leg3], E[q], E[leg2], E[leg3])
+                e1 = prob.hw[q][None, :, None, None]
+                e2 = prob.hw[allq][:, None, :, None]
+                e3 = prob.hw[qpp][:, None, None, :]
+                mask = (on[q][None, :, None, None] & on[allq][:, None, :, None]
+                        & on[qpp][:, None, None, :])
+                bare = np.abs(V) ** 2 * gaussian_delta(e1 + sign * e2 - e3, sigma) / (e1 * e2 * e3)
+                on1 = onB[q][None, :, None, None]
+                n2, on2 = nB[allq][:, None, :, None], onB[allq][:, None, :, None]
+                n3 = nB[qpp][:, None, None, :]
+                if sign > 0:
+                    w = np.where(mask, pref * bare * on1 * on2 * n3, 0.0)          # W+ (F'' - F')
+                else:
+                    w = np.where(mask, 0.5 * pref * bare * on1 * n2 * n3, 0.0)     # W-/2 (F'' + F')
+                M[q][:, qpp, :] += w.sum(axis=2).transpose(1, 0, 2)
+                M[q][:, allq, :] += -sign * w.sum(axis=3).transpose(1, 0, 2)
+            M[q] /= np.where(on[q], nB[q] * onB[q], 1.0)[:, None, None]
+    return M.reshape(nq * nbr, nq * nbr)
 
 
 def phph_inscatter(prob, ifc3, T, sigma, F, rows=None):

@@ -437,6 +437,16 @@ extern "C" elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV
   return elph::phph_rates(ctx, T_K, sigma_eV, W_ph);
 }
 
+extern "C" elph_status elph_set_phph(elph_ctx ctx, double sigma_eV) {
+  CHECK_CTX(ctx);
+  if (!(sigma_eV >= 0.0) || !std::isfinite(sigma_eV)) {
+    ctx->err = "elph_set_phph: sigma must be finite and non-negative";
+    return ELPH_EINVAL;
+  }
+  ctx->phph_sigma = sigma_eV;
+  return ELPH_OK;
+}
+
 extern "C" elph_status elph_phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F,
                                            double* S) {
   CHECK_CTX(ctx);

@@ -889,18 +889,38 @@ __global__ void k_rta_ph(int64_t nm, const double* __restrict__ hw, const double
   }
 }
 
+// W^RTA of the phonons: ph-e + external (or the model rate when neither an
+// external rate nor three-phonon rates are given) + three-phonon (wpp)
 __global__ void k_wp_total(int64_t nm, const double* __restrict__ wphe, const double* __restrict__ wext,
-                           const double* __restrict__ hw, double hw_max, double T, double omega_min,
-                           double* __restrict__ wp) {
+                           const double* __restrict__ wpp, const double* __restrict__ hw, double hw_max, double T,
+                           double omega_min, double* __restrict__ wp) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nm) return;
-  double e;
+  double e = 0.0;
   if (wext) e = wext[p];
-  else {
+  else if (!wpp) {
     const double r = hw[p] / hw_max;
     e = 1.0e12 * r * r * (T / 300.0);
   }
+  if (wpp) e += wpp[p];
   wp[p] = (hw[p] >= omega_min) ? wphe[p] + e : 0.0;
+}
+
+// t3[p][c] = phon[p][3h + c]
+__global__ void k_cols_get(int64_t nm, const double* __restrict__ phon, int h, double* __restrict__ t3) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nm * 3) return;
+  const int64_t p = e / 3;
+  t3[e] = phon[p * 6 + 3 * h + (e - p * 3)];
+}
+
+// phon[p][3h + c] += s3[p][c] / W^RTA_p (Delta F^S of Eq. 26), modes that take part only
+__global__ void k_cols_add_self(int64_t nm, const double* __restrict__ s3, const double* __restrict__ wp,
+                                const double* __restrict__ hw, double omega_min, int h, double* __restrict__ phon) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nm * 3) return;
+  const int64_t p = e / 3;
+  if (hw[p] >= omega_min && wp[p] > 0.0) phon[p * 6 + 3 * h + (e - p * 3)] += s3[e] / wp[p];
 }
 
 // sums of (a - b)^2 and a^2 over column groups [0,3) and [3,6) of [n][6] arrays
@@ -1268,8 +1288,34 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
     st = rates_from_store(ctx, th, we, wphe);
     if (st != ELPH_OK) return st;
   }
-  hipLaunchKernelGGL(k_wp_total, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, wphe, wext, ctx->d_hw, ctx->hw_max,
-                     T, ctx->omega_min, wp);
+  // three-phonon processes (Eq. 26): their RTA rate joins W^RTA, and Delta
+  // F^S = S[phon] / W^RTA joins every phonon update (add_self)
+  const bool phph = ctx->phph_sigma > 0.0;
+  double *wpp = nullptr, *t3 = nullptr, *s3 = nullptr;
+  if (phph) {
+    if (!ctx->d_i3_psi) {
+      ctx->err = "three-phonon processes enabled without force constants (elph_set_ifc3)";
+      return ELPH_ESTATE;
+    }
+    ALLOC(wpp, nm * sizeof(double));
+    ALLOC(t3, nm * 3 * sizeof(double));
+    ALLOC(s3, nm * 3 * sizeof(double));
+    st = phph_rates(ctx, T, ctx->phph_sigma, wpp);
+    if (st != ELPH_OK) return st;
+  }
+  auto add_self = [&](const double* src, double* dst, int halves) -> elph_status {
+    for (int h = 0; h < halves; ++h) {
+      hipLaunchKernelGGL(k_cols_get, dim3(blocks_for(nm * 3, 256)), dim3(256), 0, s, nm, src, h, t3);
+      elph_status e2 = phph_inscatter(ctx, T, ctx->phph_sigma, t3, s3);
+      if (e2 != ELPH_OK) return e2;
+      hipLaunchKernelGGL(k_cols_add_self, dim3(blocks_for(nm * 3, 256)), dim3(256), 0, s, nm, s3, wp, ctx->d_hw,
+                         ctx->omega_min, h, dst);
+      HIPCHK(hipGetLastError());
+    }
+    return ELPH_OK;
+  };
+  hipLaunchKernelGGL(k_wp_total, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, wphe, wext, wpp, ctx->d_hw,
+                     ctx->hw_max, T, ctx->omega_min, wp);
   hipLaunchKernelGGL(k_rta_e, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, ctx->d_eps, ctx->d_vel, ctx->mu, T, we,
                      x0);
   hipLaunchKernelGGL(k_rta_ph, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, ctx->d_hw, ctx->d_vph, T,
@@ -1346,6 +1392,22 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
       if (st != ELPH_OK) return st;
       converged = ok;
       used = 1;
+      if (phph) {
+        // the phonons' own BTE F = F0 + Delta F^S[F] (G stays zero)
+        bool okp = false;
+        for (int it = 1; it <= maxit && !okp; ++it) {
+          HIPCHK(hipMemcpyAsync(phonn, phon0, nm * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+          st = add_self(phon, phonn, 1);
+          if (st != ELPH_OK) return st;
+          Norms np_;
+          st = diff_norms(ctx, nm, phonn, phon, part, hpart, &np_);
+          if (st != ELPH_OK) return st;
+          std::swap(phon, phonn);
+          used = std::max(used, it);
+          okp = rel(np_.dI, np_.nI) < tol;
+        }
+        converged = converged && okp;
+      }
     } else {
       converged = false;
       // Anderson acceleration of the phonon fixed point phon -> Phi(phon)
@@ -1381,6 +1443,10 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
         launch_q_gather<ST, 6>(ctx, Bp, th.f, th.omf, x, acc);
         hipLaunchKernelGGL(k_ph_drag_finalize, dim3(blocks_for(nm, 256)), dim3(256), 0, s, nm, acc, phon0,
                            ctx->d_hw, th.nocc, wp, ctx->omega_min, phonn);
+        if (phph) {
+          st = add_self(phon, phonn, 2);
+          if (st != ELPH_OK) return st;
+        }
         Norms np_;
         st = diff_norms(ctx, nm, phonn, phon, part, hpart, &np_);
         if (st != ELPH_OK) return st;
@@ -1459,7 +1525,8 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   HIPCHK(hipStreamSynchronize(s));
   if (iters) *iters = used;
   for (void* p : {(void*)we, (void*)wphe, (void*)wp, (void*)x0, (void*)x, (void*)De, (void*)phon0, (void*)phon,
-                  (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase})
+                  (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase, (void*)wpp,
+                  (void*)t3, (void*)s3})
     dev_free(ctx, p);
   free_thermal(ctx, &th);
   if (!converged) {

@@ -46,7 +46,7 @@ EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
            "elph_batch_tune", "elph_tables",
            "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
-           "elph_set_ifc3", "elph_phph_vertex", "elph_phph_rates", "elph_phph_inscatter",
+           "elph_set_ifc3", "elph_phph_vertex", "elph_phph_rates", "elph_phph_inscatter", "elph_set_phph",
            "elph_mlp_create", "elph_mlp_destroy", "elph_mlp_last_error", "elph_mlp_nparams",
            "elph_mlp_get_params", "elph_mlp_set_params", "elph_mlp_forward", "elph_mlp_gradients",
            "elph_mlp_train_step", "elph_screen_nin", "elph_screen_samples", "elph_scatt_rates_screened")
@@ -89,6 +89,7 @@ def load():
     lib.elph_phph_vertex.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
     lib.elph_phph_rates.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
     lib.elph_phph_inscatter.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp, vp]
+    lib.elph_set_phph.argtypes = [vp, ctypes.c_double]
     lib.elph_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.elph_batch_destroy.argtypes = [vp]
     lib.elph_batch_destroy.restype = None
@@ -298,6 +299,11 @@ def elph_phph_rates(ctx, T, sigma, W_ph):
 def elph_phph_inscatter(ctx, T, sigma, F, S):
     """Three-phonon in-scattering of F [Nq][nbr][3] into S (device FP64, Eq. 26)."""
     _check(ctx, load().elph_phph_inscatter(ctx.handle, float(T), float(sigma), _ptr(F), _ptr(S)))
+
+
+def elph_set_phph(ctx, sigma):
+    """Three-phonon processes in elph_iterate with Gaussian width sigma (eV); 0 turns them off."""
+    _check(ctx, load().elph_set_phph(ctx.handle, float(sigma)))
 
 
 def elph_ko_enforce(ctx, T, I, J, F, G):

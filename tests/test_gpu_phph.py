@@ -170,3 +170,35 @@ def test_phph_inscatter_refuses_more_than_two_atoms():
     with pytest.raises(E.ElphError):
         E.elph_phph_inscatter(ctx, T, SIGMA, F, torch.empty_like(F))
     ctx.close()
+
+
+@pytest.mark.parametrize("level", [0, 2, 3])
+def test_iterate_with_three_phonon_scattering(level):
+    """elph_iterate with three-phonon processes switched on (their RTA rate in
+    W^RTA, Delta F^S in the phonon updates; at DRAGLESS the phonons' own BTE)
+    against the oracle's iteration with the same terms (metal6)."""
+    cfg, mat, prob, ifc3 = _case("metal6")
+    ctx = _ctx(cfg, mat, ifc3)
+    E.elph_set_phph(ctx, SIGMA)
+    nq, nbr = prob.nq, prob.nbr
+    sz = E.elph_sizes(ctx)
+    M = sz["nstates"]
+    I, J = [torch.empty(3 * M, dtype=torch.float64, device=DEV) for _ in range(2)]
+    F, G = [torch.empty(3 * nq * nbr, dtype=torch.float64, device=DEV) for _ in range(2)]
+    E.elph_iterate(ctx, T, I, J, F, G, W_ph_ext=None, level=level, tol=1e-11, maxit=400)
+    torch.cuda.synchronize()
+    Xp, Xm = prob.transition_probs(T)
+    ref = oracle.iterate(prob, T, Xp, Xm, level, tol=1e-11, maxit=400, phph=(ifc3, SIGMA))
+    assert ref["converged"]
+    got = dict(I=I.cpu().numpy().reshape(M, 3), J=J.cpu().numpy().reshape(M, 3),
+               F=F.cpu().numpy().reshape(nq, nbr, 3), G=G.cpu().numpy().reshape(nq, nbr, 3))
+    keys = ("I", "J", "F", "G") if level == 3 else ("I", "J", "F")
+    for key in keys:
+        scale = np.abs(ref[key]).max()
+        assert scale > 0, key
+        assert np.abs(got[key] - ref[key]).max() <= 1e-7 * scale, key
+    if level == 2:
+        # the phonons' own BTE moved F away from its RTA value
+        assert np.abs(ref["F"] - ref["F0"]).max() > 1e-4 * np.abs(ref["F0"]).max()
+        assert np.all(got["G"] == 0)
+    ctx.close()

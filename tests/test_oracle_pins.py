@@ -826,3 +826,13 @@ def test_phph_inscatter_conserves_energy(sigma):
     assert on.sum() > 100
     assert np.all(np.abs(S[..., 0] - prob.hw * W)[on] <= 3.0 * sigma * W[on])
     assert np.allclose(S[..., 1], S[..., 0]) and np.all(S[~prob.mode_on] == 0)
+
+
+def test_phph_operator_matches_inscatter():
+    """The dense in-scattering matrix the oracle's iteration uses applies the
+    same terms as the row-by-row in-scattering."""
+    prob, ifc3 = _phph_problem()
+    F = np.random.default_rng(4).standard_normal((prob.nq, prob.nbr, 3))
+    S = oracle.phph_inscatter(prob, ifc3, 300.0, 0.004, F)
+    M = oracle.phph_operator(prob, ifc3, 300.0, 0.004)
+    assert np.abs((M @ F.reshape(-1, 3)).reshape(S.shape) - S).max() <= 1e-13 * np.abs(S).max()
