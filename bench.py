@@ -376,7 +376,7 @@ def run_phph(E, torch, steps, warmup, n=24, cpu=True, budget_s=20.0):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "phph%d: " % n + PHPH_WORKLOAD % n, "nq": nq, "nbr": nbr, "ifc3_entries": len(ifc3[0]),
                    "rj_groups": ng, "pairs": nq * nq},
-        "roofline": {"bound": "alu", "kernel": ("k_phph_tile<%d, 0>" if nbr <= 6 and ng <= 32 else "k_phph_rows<%d>") % nbr, "achieved": flops / (k_ms * 1e-3) / 1e12,
+        "roofline": {"bound": "alu", "kernel": ("k_phph_tile<%d, 0, NG>" if nbr <= 6 and ng <= 32 else "k_phph_rows<%d>") % nbr, "achieved": flops / (k_ms * 1e-3) / 1e12,
                      "peak": 78.6, "unit": "TFLOP/s", "frac": flops / (k_ms * 1e-3) / 1e12 / 78.6,
                      "traffic": _stored_value("phph_kernel_stats.md", "phph.hip",
                                               "traffic_bytes_per_launch[phph%d]" % n),

@@ -280,12 +280,12 @@ __global__ void k_phph_bose(int64_t n, const double* __restrict__ hw, double kT,
 // <= 256 (one or two atoms).
 constexpr int kTQ = 16, kQB = 4, kMaxG = 32;
 
-template <int NBR, int NC>
+template <int NBR, int NC, int NGP>
 struct TileLds {
   cd exq[kTQ][NBR * NBR];      // E_q of the tile's rows
   cd exd[kTQ][NBR * NBR];      // E_{-q'} of the rows for the current q''
-  cd tq[kTQ][kMaxG];           // exp(-2 pi i q.R_j) of the tile's rows
-  cd tP[kMaxG];                // exp(+2 pi i P.R_j)
+  cd tq[kTQ][NGP];             // exp(-2 pi i q.R_j) of the tile's rows (zero beyond ng)
+  cd tP[NGP];                  // exp(+2 pi i P.R_j) (zero beyond ng)
   cd A[kQB][NBR * NBR * NBR];  // A, then V
   cd B[kQB][NBR * NBR * NBR];
   double e1[kTQ][NBR];
@@ -297,7 +297,7 @@ struct TileLds {
   double f2m[NC ? kTQ : 1][NBR * (NC ? NC : 1)];  // F at -q'
 };
 
-template <int NBR, int NC>
+template <int NBR, int NC, int NGP>
 __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int prange, const int32_t* __restrict__ gr,
                                                    int ng, const cd* __restrict__ phi, const cd* __restrict__ Lq,
                                                    const double* __restrict__ hw, const double* __restrict__ nbose,
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
                                                    double* __restrict__ part) {
   constexpr int N2 = NBR * NBR, N3 = N2 * NBR, NV = NC ? NC : 1;
   static_assert(N3 <= 256 && N2 <= 64 && kQB * 64 == 256, "one slab element per thread, one row per wave");
-  __shared__ TileLds<NBR, NC> L;
+  __shared__ TileLds<NBR, NC, NGP> L;
   const int q0 = blockIdx.x * kTQ, nt = min(kTQ, nq - q0);
   const int P0 = blockIdx.y * prange, P1 = min(nq, P0 + prange);
   const MeshDims md{ph.n0, ph.n1, ph.n2};
@@ -314,9 +314,9 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
     const int r = t / N2, e = t - r * N2;
     L.exq[r][e] = r < nt ? edisp(Lq, hw, q0 + r, NBR, e / NBR, e % NBR) : cmake(0.0, 0.0);
   }
-  for (int t = tid; t < kTQ * ng; t += blockDim.x) {
-    const int r = t / ng, g = t - r * ng;
-    L.tq[r][g] = r < nt ? ph.neg(q0 + r, gr[3 * g], gr[3 * g + 1], gr[3 * g + 2]) : cmake(0.0, 0.0);
+  for (int t = tid; t < kTQ * NGP; t += blockDim.x) {
+    const int r = t / NGP, g = t - r * NGP;
+    L.tq[r][g] = (r < nt && g < ng) ? ph.neg(q0 + r, gr[3 * g], gr[3 * g + 1], gr[3 * g + 2]) : cmake(0.0, 0.0);
   }
   for (int t = tid; t < kTQ * NBR; t += blockDim.x) {
     const int r = t / NBR, s = t - r * NBR;
@@ -325,17 +325,18 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
   for (int t = tid; t < kTQ * NBR * NV; t += blockDim.x) L.acc[t / (NBR * NV)][t % (NBR * NV)] = 0.0;
   const double inv2s2 = 0.5 / (sigma * sigma), dnorm = 1.0 / (sqrt(2.0 * kPi) * sigma);
   for (int P = P0; P < P1; ++P) {
-    cd slab[kMaxG];
+    cd slab[NGP];
     const cd* src = phi + (int64_t)P * ng * N3 + tid;
 #pragma unroll
-    for (int g = 0; g < kMaxG; ++g) slab[g] = (g < ng && tid < N3) ? src[(int64_t)g * N3] : cmake(0.0, 0.0);
+    for (int g = 0; g < NGP; ++g) slab[g] = (g < ng && tid < N3) ? src[(int64_t)g * N3] : cmake(0.0, 0.0);
     __syncthreads();   // the previous q'' is done with exd, tP, e2, n2, e3, n3
     if (tid < NBR) {
       const double w3 = hw[(int64_t)P * NBR + tid];
       L.e3[tid] = w3 >= omega_min ? w3 : 0.0;
       L.n3[tid] = nbose[(int64_t)P * NBR + tid];
     }
-    if (tid < ng) L.tP[tid] = cconj(ph.neg(P, gr[3 * tid], gr[3 * tid + 1], gr[3 * tid + 2]));
+    if (tid < NGP)
+      L.tP[tid] = tid < ng ? cconj(ph.neg(P, gr[3 * tid], gr[3 * tid + 1], gr[3 * tid + 2])) : cmake(0.0, 0.0);
     for (int t = tid; t < kTQ * N2; t += blockDim.x) {
       const int r = t / N2, e = t - r * N2;
       cd v = cmake(0.0, 0.0);
@@ -368,16 +369,14 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
     }
     __syncthreads();
 #pragma unroll
-    for (int g = 0; g < kMaxG; ++g)
-      if (g < ng) slab[g] = cmul(L.tP[g], slab[g]);
+    for (int g = 0; g < NGP; ++g) slab[g] = cmul(L.tP[g], slab[g]);
     for (int rb = 0; rb < nt; rb += kQB) {
       if (tid < N3) {
 #pragma unroll
         for (int r = 0; r < kQB; ++r) {
           cd a = cmake(0.0, 0.0);
 #pragma unroll
-          for (int g = 0; g < kMaxG; ++g)
-            if (g < ng) a = cfma(a, L.tq[rb + r][g], slab[g]);
+          for (int g = 0; g < NGP; ++g) a = cfma(a, L.tq[rb + r][g], slab[g]);
           L.A[r][tid] = a;
         }
       }
@@ -490,13 +489,28 @@ void launch_rows(elph_ctx ctx, int chunk, int nchunk, const cd* phi, double kT, 
                      kT, ctx->omega_min, sigma, part);
 }
 
+template <int NBR, int NC, int NGP>
+void launch_tile_g(elph_ctx ctx, int prange, int nrange, const cd* phi, const double* nbose, double sigma,
+                   const double* F, double* part) {
+  hipLaunchKernelGGL((k_phph_tile<NBR, NC, NGP>), dim3((unsigned)((ctx->nk + kTQ - 1) / kTQ), (unsigned)nrange),
+                     dim3(256), 0, ctx->stream, phase_tab(ctx), (int)ctx->nk, prange, ctx->d_i3_rj, ctx->ng3, phi,
+                     (const cd*)ctx->d_Lq, ctx->d_hw, nbose, ctx->omega_min, sigma, F, part);
+}
+
+// the R_j count padded to 8, 16, 28 or 32 (zero phases and slab beyond ng)
 template <int NBR, int NC>
 void launch_tile(elph_ctx ctx, int prange, int nrange, const cd* phi, const double* nbose, double sigma,
                  const double* F, double* part) {
-  if constexpr (NBR * NBR * NBR <= 256)
-    hipLaunchKernelGGL((k_phph_tile<NBR, NC>), dim3((unsigned)((ctx->nk + kTQ - 1) / kTQ), (unsigned)nrange),
-                       dim3(256), 0, ctx->stream, phase_tab(ctx), (int)ctx->nk, prange, ctx->d_i3_rj, ctx->ng3, phi,
-                       (const cd*)ctx->d_Lq, ctx->d_hw, nbose, ctx->omega_min, sigma, F, part);
+  if constexpr (NBR * NBR * NBR <= 256) {
+    if (ctx->ng3 <= 8)
+      launch_tile_g<NBR, NC, 8>(ctx, prange, nrange, phi, nbose, sigma, F, part);
+    else if (ctx->ng3 <= 16)
+      launch_tile_g<NBR, NC, 16>(ctx, prange, nrange, phi, nbose, sigma, F, part);
+    else if (ctx->ng3 <= 28)
+      launch_tile_g<NBR, NC, 28>(ctx, prange, nrange, phi, nbose, sigma, F, part);
+    else
+      launch_tile_g<NBR, NC, kMaxG>(ctx, prange, nrange, phi, nbose, sigma, F, part);
+  }
 }
 
 template <int NBR>
