@@ -286,7 +286,7 @@ struct TileLds {
   cd exd[kTQ][NBR * NBR];      // E_{-q'} of the rows for the current q''
   cd tq[kTQ][NGP];             // exp(-2 pi i q.R_j) of the tile's rows (zero beyond ng)
   cd tP[NGP];                  // exp(+2 pi i P.R_j) (zero beyond ng)
-  cd A[kQB][NBR * NBR * NBR];  // A, then V
+  cd A[kQB][NBR * (NBR == 6 ? 38 : NBR * NBR)];  // A, then V; rows of x_i (or s) padded to 38 for bank spread
   cd B[kQB][NBR * NBR * NBR];
   double e1[kTQ][NBR];
   double e2[kTQ][NBR], n2[kTQ][NBR];
@@ -304,8 +304,15 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
                                                    double omega_min, double sigma, const double* __restrict__ F,
                                                    double* __restrict__ part) {
   constexpr int N2 = NBR * NBR, N3 = N2 * NBR, NV = NC ? NC : 1;
+  constexpr int AS = NBR == 6 ? 38 : N2;  // stride of the leading index of A and V in LDS
   static_assert(N3 <= 256 && N2 <= 64 && kQB * 64 == 256, "one slab element per thread, one row per wave");
   __shared__ TileLds<NBR, NC, NGP> L;
+  // rates: per-lane sums over the whole q'' range, one per sub-batch slot and branch
+  double cacc[kTQ / kQB][NBR];
+#pragma unroll
+  for (int k = 0; k < kTQ / kQB; ++k)
+#pragma unroll
+    for (int s1 = 0; s1 < NBR; ++s1) cacc[k][s1] = 0.0;
   const int q0 = blockIdx.x * kTQ, nt = min(kTQ, nq - q0);
   const int P0 = blockIdx.y * prange, P1 = min(nq, P0 + prange);
   const MeshDims md{ph.n0, ph.n1, ph.n2};
@@ -377,7 +384,7 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
           cd a = cmake(0.0, 0.0);
 #pragma unroll
           for (int g = 0; g < NGP; ++g) a = cfma(a, L.tq[rb + r][g], slab[g]);
-          L.A[r][tid] = a;
+          L.A[r][(tid / N2) * AS + tid % N2] = a;
         }
       }
       __syncthreads();
@@ -387,7 +394,7 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
         cd b = cmake(0.0, 0.0);
 #pragma unroll
         for (int xj = 0; xj < NBR; ++xj)
-          b = cfma(b, L.exd[rb + r][xj * NBR + s2], L.A[r][(xi * NBR + xj) * NBR + s3]);
+          b = cfma(b, L.exd[rb + r][xj * NBR + s2], L.A[r][xi * AS + xj * NBR + s3]);
         L.B[r][o] = b;
       }
       __syncthreads();
@@ -397,7 +404,7 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
         cd v = cmake(0.0, 0.0);
 #pragma unroll
         for (int xi = 0; xi < NBR; ++xi) v = cfma(v, L.exq[rb + r][xi * NBR + s1], L.B[r][xi * N2 + rr]);
-        L.A[r][o] = v;
+        L.A[r][s1 * AS + rr] = v;
       }
       __syncthreads();
       {  // wave r: row rb + r, lane = (s', s'')
@@ -414,11 +421,12 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
             for (int s1 = 0; s1 < NBR; ++s1) {
               const double E1 = L.e1[rb + r][s1];
               const double dp = E1 + E2 - E3, dm = E1 - E2 - E3;
-              const double b = cabs2(L.A[r][s1 * N2 + lane]) * f;
+              const double b = cabs2(L.A[r][s1 * AS + lane]) * f;
               const double wp = b * (1.0 + np2) * exp(-dp * dp * inv2s2);  // absorption with -q'
               const double wm = b * 0.5 * np2 * exp(-dm * dm * inv2s2);    // decay into q', half
               if constexpr (NC == 0) {
-                c[s1] = wp + wm;
+#pragma unroll
+                for (int k = 0; k < kTQ / kQB; ++k) cacc[k][s1] += (k * kQB == rb) ? wp + wm : 0.0;
               } else {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
@@ -429,14 +437,16 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
             }
           }
         }
+        if constexpr (NC > 0) {
 #pragma unroll
-        for (int k = 0; k < NBR * NV; ++k) {
-          double x = c[k];
+          for (int k = 0; k < NBR * NV; ++k) {
+            double x = c[k];
 #pragma unroll
-          for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-          c[k] = x;
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+            c[k] = x;
+          }
         }
-        if (rb + r < nt) {
+        if (NC > 0 && rb + r < nt) {
 #pragma unroll
           for (int k0 = 0; k0 < NBR * NV; k0 += 64) {
             if (lane + k0 < NBR * NV) {
@@ -450,6 +460,27 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
         }
       }
       __syncthreads();   // V (A) is rewritten by the next rows
+    }
+  }
+  if constexpr (NC == 0) {
+    // wave w holds row k kQB + w of every sub-batch slot k
+#pragma unroll
+    for (int k = 0; k < kTQ / kQB; ++k) {
+#pragma unroll
+      for (int s1 = 0; s1 < NBR; ++s1) {
+        double x = cacc[k][s1];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        cacc[k][s1] = x;
+      }
+      const int row = k * kQB + wave;
+      if (lane < NBR && row < nt) {
+        double x = cacc[k][0];
+#pragma unroll
+        for (int s1 = 1; s1 < NBR; ++s1)
+          if (lane == s1) x = cacc[k][s1];
+        L.acc[row][lane] += x;
+      }
     }
   }
   __syncthreads();
