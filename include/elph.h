@@ -245,9 +245,9 @@ elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W
  *   S_sq = sum_{s'q's''} [W+ (F_s''q'' - F_s'q') + W-/2 (F_s''q'' + F_s'q')] / (n_sq (1 + n_sq))
  * with W+- as in elph_phph_rates (q'' = q + q' for W+, q - q' for W-), so
  * that Delta F^S = S / W^RTA.  F and S: device FP64 [Nq][nbr][3] (S in
- * units of F times 1/s; zero for modes below omega_min).  For up to 2
- * atoms and 32 distinct rj.  Synchronous.  ESTATE without force constants,
- * EINVAL for T or sigma not positive or F null. */
+ * units of F times 1/s; zero for modes below omega_min).  Synchronous.
+ * ESTATE without force constants, EINVAL for T or sigma not positive or F
+ * null. */
 elph_status elph_phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F, double* S);
 
 /* Three-phonon processes in elph_iterate (Eq. 26): with sigma_eV > 0 (the
@@ -257,9 +257,8 @@ elph_status elph_phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const
  * Delta F^S = S[F] / W^RTA (elph_phph_inscatter, for F and G) to every phonon
  * update of levels PARTIAL and COUPLED; at level DRAGLESS the phonons then
  * solve their own BTE F = F0 + Delta F^S[F] (G = 0) to tol.  sigma_eV = 0
- * turns this off (the default).  Needs force constants (elph_set_ifc3) and
- * at most 2 atoms at iterate time (ESTATE / EINVAL there).  EINVAL for a
- * negative or non-finite sigma. */
+ * turns this off (the default).  Needs force constants (elph_set_ifc3) at
+ * iterate time (ESTATE there).  EINVAL for a negative or non-finite sigma. */
 elph_status elph_set_phph(elph_ctx ctx, double sigma_eV);
 
 /* Select the energy-conserving delta of Eq. 8 for this context's later

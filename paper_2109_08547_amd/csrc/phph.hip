@@ -186,23 +186,27 @@ __global__ __launch_bounds__(256) void k_phph_vertex(PhaseTab ph, int64_t npairs
 // owns the branch pair (s', s'') = t and sums, per s, over the chunk
 //   |V|^2 n'' [(1 + n') delta(E + E' - E'') + n' delta(E - E' - E'') / 2] / (E' E'')
 // into part[chunk][q][s]; the constant factors follow in k_phph_finish.
-template <int NBR>
+// With NC = 3 the same terms weight the field F [nq][NBR][3] as the
+// in-scattering of Eq. 26 does (part[chunk][q][s][c]).
+template <int NBR, int NC>
 __global__ __launch_bounds__(256) void k_phph_rows(PhaseTab ph, int nq, int chunk, const int32_t* __restrict__ gr,
                                                    int ng, const cd* __restrict__ phi, const cd* __restrict__ Lq,
                                                    const double* __restrict__ hw, double kT, double omega_min,
-                                                   double sigma, double* __restrict__ part) {
-  constexpr int N2 = NBR * NBR;
+                                                   double sigma, const double* __restrict__ F,
+                                                   double* __restrict__ part) {
+  constexpr int N2 = NBR * NBR, NV = NC ? NC : 1;
   __shared__ PairLds<NBR> L;
   __shared__ double e1[NBR], e2[NBR], n2[NBR], e3[NBR], n3[NBR];
+  __shared__ double f2[NBR * NV], f2m[NBR * NV], f3[NBR * NV];   // F at q', -q', q'' (NC > 0)
   const int q = blockIdx.x;
   const int c0 = blockIdx.y * chunk, c1 = min(nq, c0 + chunk);
   const MeshDims md{ph.n0, ph.n1, ph.n2};
   for (int t = threadIdx.x; t < N2; t += blockDim.x) L.eq[t] = edisp(Lq, hw, q, NBR, t / NBR, t % NBR);
   if (threadIdx.x < NBR) e1[threadIdx.x] = hw[(int64_t)q * NBR + threadIdx.x];
   const double inv2s2 = 0.5 / (sigma * sigma), dnorm = 1.0 / (sqrt(2.0 * kPi) * sigma);
-  double acc[NBR];
+  double acc[NBR * NV];
 #pragma unroll
-  for (int s = 0; s < NBR; ++s) acc[s] = 0.0;
+  for (int s = 0; s < NBR * NV; ++s) acc[s] = 0.0;
   for (int qp = c0; qp < c1; ++qp) {
     const int mqp = q_neg(qp, md.n0, md.n1, md.n2), qpp = q_between(q, qp, md.n0, md.n1, md.n2);
     __syncthreads();  // the previous pair's readers are done with ex, e2, e3
@@ -215,6 +219,13 @@ __global__ __launch_bounds__(256) void k_phph_rows(PhaseTab ph, int nq, int chun
       n2[s] = w2 >= omega_min ? 1.0 / expm1(w2 / kT) : 0.0;
       n3[s] = w3 >= omega_min ? 1.0 / expm1(w3 / kT) : 0.0;
     }
+    if constexpr (NC > 0) {
+      for (int t = threadIdx.x; t < NBR * NC; t += blockDim.x) {
+        f2[t] = F[(int64_t)qp * NBR * NC + t];
+        f2m[t] = F[(int64_t)mqp * NBR * NC + t];
+        f3[t] = F[(int64_t)qpp * NBR * NC + t];
+      }
+    }
     pair_vertex<NBR>(ph, qp, qpp, ng, gr, phi, L.eq, L.ex, L.pg, L.A, L.B);
     const int t = threadIdx.x;
     if (t < N2) {
@@ -226,27 +237,36 @@ __global__ __launch_bounds__(256) void k_phph_rows(PhaseTab ph, int nq, int chun
         for (int s1 = 0; s1 < NBR; ++s1) {
           const double E1 = e1[s1];
           const double dp = E1 + E2 - E3, dm = E1 - E2 - E3;
-          const double occ = (1.0 + np2) * exp(-dp * dp * inv2s2) + 0.5 * np2 * exp(-dm * dm * inv2s2);
-          acc[s1] += cabs2(L.A[s1 * N2 + t]) * f * occ * dnorm;
+          const double b = cabs2(L.A[s1 * N2 + t]) * f * dnorm;
+          const double wp = b * (1.0 + np2) * exp(-dp * dp * inv2s2);   // absorption with -q'
+          const double wm = b * 0.5 * np2 * exp(-dm * dm * inv2s2);     // decay into q', half
+          if constexpr (NC == 0) {
+            acc[s1] += wp + wm;
+          } else {
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+              acc[s1 * NC + k] += wp * (f3[s3 * NC + k] - f2m[s2 * NC + k]) + wm * (f3[s3 * NC + k] + f2[s2 * NC + k]);
+          }
         }
       }
     }
   }
   // sum over the branch pairs: the N2 <= 144 owners sit in the first waves
   __syncthreads();
-  double* red = reinterpret_cast<double*>(L.B);   // 4 wave partials per s (2 N3 >= 4 NBR doubles)
+  double* red = reinterpret_cast<double*>(L.B);   // 4 wave partials per value (2 N3 >= 4 NBR NV doubles)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int s = 0; s < NBR; ++s) {
+  for (int s = 0; s < NBR * NV; ++s) {
     double x = acc[s];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     if (lane == 0) red[s * 4 + wave] = x;
   }
   __syncthreads();
-  if (threadIdx.x < NBR) {
+  if (threadIdx.x < NBR * NV) {
     const int s = threadIdx.x;
-    part[((int64_t)blockIdx.y * nq + q) * NBR + s] = (red[s * 4] + red[s * 4 + 1]) + (red[s * 4 + 2] + red[s * 4 + 3]);
+    part[((int64_t)blockIdx.y * nq + q) * NBR * NV + s] =
+        (red[s * 4] + red[s * 4 + 1]) + (red[s * 4 + 2] + red[s * 4 + 3]);
   }
 }
 
@@ -513,11 +533,12 @@ void launch_fold(elph_ctx ctx, cd* phi) {
                      ctx->ng3, phi);
 }
 
-template <int NBR>
-void launch_rows(elph_ctx ctx, int chunk, int nchunk, const cd* phi, double kT, double sigma, double* part) {
-  hipLaunchKernelGGL(k_phph_rows<NBR>, dim3((unsigned)ctx->nk, (unsigned)nchunk), dim3(256), 0, ctx->stream,
+template <int NBR, int NC>
+void launch_rows(elph_ctx ctx, int chunk, int nchunk, const cd* phi, double kT, double sigma, const double* F,
+                 double* part) {
+  hipLaunchKernelGGL((k_phph_rows<NBR, NC>), dim3((unsigned)ctx->nk, (unsigned)nchunk), dim3(256), 0, ctx->stream,
                      phase_tab(ctx), (int)ctx->nk, chunk, ctx->d_i3_rj, ctx->ng3, phi, (const cd*)ctx->d_Lq, ctx->d_hw,
-                     kT, ctx->omega_min, sigma, part);
+                     kT, ctx->omega_min, sigma, F, part);
 }
 
 template <int NBR, int NC, int NGP>
@@ -689,10 +710,6 @@ static elph_status phph_pass(elph_ctx ctx, const char* name, double T_K, double 
   const int64_t nq = ctx->nk;
   const bool tile = ctx->nbr <= 6 && ctx->ng3 <= kMaxG;
   const int nv = F ? 3 : 1;
-  if (F && !tile) {
-    ctx->err = std::string(name) + ": supported for up to 2 atoms and 32 distinct R_j";
-    return ELPH_EINVAL;
-  }
   st = build_tables(ctx);
   if (st != ELPH_OK) return st;
   cd* phi = nullptr;
@@ -727,8 +744,12 @@ static elph_status phph_pass(elph_ctx ctx, const char* name, double T_K, double 
 #define TILE(N) launch_tile<N, 3>(ctx, chunk, nchunk, phi, nbose, sigma_eV, F, part)
     NBR_SWITCH(ctx->nbr, TILE)
 #undef TILE
+  } else if (!F) {
+#define ROWS(N) launch_rows<N, 0>(ctx, chunk, nchunk, phi, kT, sigma_eV, nullptr, part)
+    NBR_SWITCH(ctx->nbr, ROWS)
+#undef ROWS
   } else {
-#define ROWS(N) launch_rows<N>(ctx, chunk, nchunk, phi, kT, sigma_eV, part)
+#define ROWS(N) launch_rows<N, 3>(ctx, chunk, nchunk, phi, kT, sigma_eV, F, part)
     NBR_SWITCH(ctx->nbr, ROWS)
 #undef ROWS
   }

@@ -146,7 +146,7 @@ def test_phph_errors():
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["tiny3", "tiny4", "metal6"])
+@pytest.mark.parametrize("name", ["tiny3", "tiny4", "metal6", "atoms3", "atoms4"])
 def test_phph_inscatter(name):
     """The in-scattering of a seeded field and of F = hbar omega against the oracle."""
     cfg, mat, prob, ifc3 = _case(name)
@@ -160,15 +160,6 @@ def test_phph_inscatter(name):
         ref = oracle.phph_inscatter(prob, ifc3, T, SIGMA, F)
         assert np.abs(ref).max() > 0
         assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
-    ctx.close()
-
-
-def test_phph_inscatter_refuses_more_than_two_atoms():
-    cfg, mat, prob, ifc3 = _case("atoms3")
-    ctx = _ctx(cfg, mat, ifc3)
-    F = torch.zeros(prob.nq * prob.nbr * 3, dtype=torch.float64, device=DEV)
-    with pytest.raises(E.ElphError):
-        E.elph_phph_inscatter(ctx, T, SIGMA, F, torch.empty_like(F))
     ctx.close()
 
 
