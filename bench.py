@@ -98,10 +98,12 @@ def contraction_flops(sz, nre, nrp):
     return step1, step2
 
 
-def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit, coupled=True):
+def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit, coupled=True, setup=None):
     dev = torch.device("cuda:0")
     T = cfg["T"]
     ctx = E.elph_create(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], precision=form)
+    if setup is not None:
+        setup(ctx)
     sz = E.elph_sizes(ctx)
     M, nbr, nk = sz["nstates"], sz["nbr"], sz["nk"]
     we = torch.empty(M, dtype=torch.float64, device=dev)
@@ -125,11 +127,12 @@ def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit, 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    kt = {"tables": [], "step1": [], "step2": [], "iterate": []}
+    kt = {"tables": [], "step1": [], "step2": [], "iterate": [], "extra": []}
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
         ms = E.elph_timing(ctx, True, read=True)
+        ms["extra"] = E.elph_timing_extra(ctx) if setup is not None else -1.0
         for key in kt:
             if ms[key] >= 0:
                 kt[key].append(ms[key])
@@ -318,6 +321,95 @@ def run_large(E, torch, form="fp32"):
     }
 
 
+# FP64 operations per transition probability of the tetrahedron scaling: 24
+# tetrahedra around the final point, each with four corner energies (2 ops
+# each), the sign count, a six-exchange sort and the section formula (~15)
+TETRA_OPS = 24 * 35
+VARIANTS = {
+    "tetra48": "mixed48 (8 bands, 2 atoms, 48^3, 3% of k) with the analytic tetrahedron delta instead of the "
+               "Gaussian, FP16x3 contractions; a step = tables + vertices + store + tetrahedron scaling + rates + "
+               "one phonon step of the iteration",
+    "polar48": "mixed48 as a polar material (seeded Born charges, eps_inf near 8, atom positions): the "
+               "non-analytic term of Eq. 4 in D(q) and the Froehlich vertex of Eq. 7 (Ewald table per q) in g, "
+               "FP16x3 contractions; a step = tables (with the Froehlich table) + vertices + store + rates + one "
+               "phonon step of the iteration",
+}
+
+
+def run_variant(E, torch, kind, steps, warmup, cpu=True, budget_s=20.0):
+    """The default step of mixed48 with the tetrahedron delta or as a polar
+    material; the oracle, with the same delta or polar terms, on a sample."""
+    import synth
+    cfg = synth.config("mixed48")
+    mat = synth.material_for(cfg)
+    form = "fp16x3"
+    if kind == "polar48":
+        Z, eps, tau = synth.polar_params(int(mat["natom"]), 7, lat=mat["lat"])
+        omat = dict(mat, zstar=Z, eps_inf=eps, tau=tau)
+
+        def setup(ctx):
+            E.elph_set_polar(ctx, Z, eps, tau)
+    else:
+        omat = mat
+
+        def setup(ctx):
+            E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    print("bench: %s form %s" % (kind, form), file=sys.stderr, flush=True)
+    r = run_form(E, torch, mat, cfg, form, steps, warmup, True, 1e-8, 200, coupled=False, setup=setup)
+    sz = r["sizes"]
+    nterms = 2.0 * sz["nterms"]
+    s = r["ms_per_step"] / 1e3
+    km = r["kernel_ms"]
+    if kind == "tetra48":
+        flops = TETRA_OPS * nterms
+        roof = {"bound": "alu", "kernel": "k_tetra_scale<float, 6>", "achieved": flops / (km["extra"] * 1e-3) / 1e12,
+                "peak": 78.6, "unit": "TFLOP/s", "traffic": None, "kernel_ms": km["extra"],
+                "ops_per_term": TETRA_OPS}
+    else:
+        flops = contraction_flops(sz, len(mat["re"]), len(mat["rp"]))[1]
+        roof = {"bound": "mfma", "kernel": GEMM_KERNEL[form], "achieved": flops / (km["step2"] * 1e-3) / 1e12,
+                "peak": PEAK[form], "unit": "TFLOP/s", "traffic": stored_traffic(form, "mixed48"),
+                "kernel_ms": km["step2"], "frohlich_table_ms": km["extra"]}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {
+        "metric": METRIC, "value": nterms / s, "unit": "transition probabilities/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": 1e3 * s, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[form], "data": "synthetic",
+        "config": {"workload": "%s: %s" % (kind, VARIANTS[kind]), "nstates": sz["nstates"], "terms": nterms,
+                   "form": form},
+        "roofline": roof, "kernel_ms": km,
+    }
+    if cpu:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        except Exception:  # pragma: no cover
+            cores = len(os.sched_getaffinity(0))
+        T = cfg["T"]
+        t0 = time.perf_counter()
+        prob = oracle.Problem(omat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+        t_tab = time.perf_counter() - t0
+        order = np.random.default_rng(2024).permutation(prob.nstates)
+        done, t_rows, errs = 0, 0.0, []
+        while done < order.size and t_rows < budget_s:
+            rows = order[done:done + 4]
+            t1 = time.perf_counter()
+            Xp, Xm = prob.transition_probs(T, rows, delta="tetra" if kind == "tetra48" else "gauss")
+            w = prob.rates_e(T, Xp, Xm, rows)
+            t_rows += time.perf_counter() - t1
+            errs.append(rate_err(r["we"][rows], w))
+            done += rows.size
+        t_eff = t_rows + t_tab * done / prob.nstates
+        out["cpu_baseline"] = {
+            "value": 2.0 * done * prob.nstates * prob.nbr / t_eff, "unit": "transition probabilities/s",
+            "cores": int(cores), "kind": "oracle",
+            "sample": "oracle tables (%.1f s, amortised by rows) + X^{+/-} of %d seeded initial states x all %d "
+                      "final states x %d branches (%.1f s)" % (t_tab, done, prob.nstates, prob.nbr, t_rows),
+            "max_rel_err_W_e_gpu_%s_vs_oracle_sample" % form: float(max(errs))}
+    return out
+
+
 PHPH_WORKLOAD = ("three-phonon RTA rates (Eqs. 13, 14, 26) of every mode on a %d^3 q mesh: the 2-atom material "
                  "of mixed48 (Si and C masses, 203 R_p vectors), synthetic IFC3 on the cell triples of {-1,0,1}^3 "
                  "(343 (R_j, R_k) entries, leg-symmetric, acoustic sum rule), Gaussian sigma 2 meV, 300 K, all "
@@ -418,7 +510,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="mixed48",
-                    choices=sorted(WORKLOADS) + ["phph%d" % n for n in (8, 12, 16, 20, 24, 32)])
+                    choices=sorted(WORKLOADS) + sorted(VARIANTS) + ["phph%d" % n for n in (8, 12, 16, 20, 24, 32)])
     ap.add_argument("--forms", default="fp64,fp32,bf16x3,bf16x6,fp16x3")
     ap.add_argument("--no-iterate", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -455,6 +547,10 @@ def main():
         print("bench: copy calibration, 3 x neg over 2^28 float32 (1 GiB read + 1 GiB written each)",
               file=sys.stderr, flush=True)
         del a, b
+    if args.workload in VARIANTS:
+        print(json.dumps(run_variant(E, torch, args.workload, args.steps, args.warmup, cpu=not args.no_cpu,
+                                     budget_s=args.cpu_budget)), flush=True)
+        return
     if args.workload.startswith("phph"):
         n = int(args.workload[4:])
         print(json.dumps(run_phph(E, torch, args.steps, args.warmup, n=n, cpu=not args.no_cpu,

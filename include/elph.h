@@ -169,6 +169,13 @@ elph_status elph_reset(elph_ctx ctx, int32_t what);
  * synchronises the stream when ms is given. */
 elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms);
 
+/* With timing on (elph_timing): the duration in milliseconds of the most
+ * recent tetrahedron-delta scaling of a vertex store (k_tetra_scale,
+ * elph_set_delta) or Froehlich table (k_frohlich, elph_set_polar), whichever
+ * ran last; -1 when none was recorded.  ms: one host double.  Synchronises
+ * the stream. */
+elph_status elph_timing_extra(elph_ctx ctx, double* ms);
+
 /* Build the electron and phonon tables if needed (Eqs. 1-3, 5 and the
  * window) and report sizes; synchronises the stream. */
 elph_status elph_sizes(elph_ctx ctx, elph_sizes_t* out);

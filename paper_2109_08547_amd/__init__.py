@@ -5,7 +5,7 @@ The compute lives in libelph.so (csrc/, C ABI in include/elph.h); the
 """
 from . import elph  # noqa: F401
 from .elph import (  # noqa: F401
-    elph_create, elph_destroy, elph_reset, elph_timing, elph_sizes, elph_tables, elph_interp_g,
+    elph_create, elph_destroy, elph_reset, elph_timing, elph_timing_extra, elph_sizes, elph_tables, elph_interp_g,
     elph_transition_probs, elph_scatt_rates, elph_iterate, elph_ko_enforce, elph_set_delta, elph_set_polar, elph_set_ifc3,
     elph_phph_vertex, elph_phph_rates, elph_phph_inscatter, elph_set_phph, ElphError,
     elph_batch_create, elph_batch_destroy, elph_batch_scatt_rates, elph_batch_tune,

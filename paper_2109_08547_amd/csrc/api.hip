@@ -261,7 +261,7 @@ extern "C" elph_status elph_create(const elph_wannier* w, const elph_params* p, 
 extern "C" elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms) {
   CHECK_CTX(ctx);
   if (enable && !ctx->ev[0]) {
-    for (int e = 0; e < 8; ++e) HIPCHK(hipEventCreate(&ctx->ev[e]));
+    for (int e = 0; e < 10; ++e) HIPCHK(hipEventCreate(&ctx->ev[e]));
   }
   if (ms) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -278,10 +278,23 @@ extern "C" elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms) {
   return ELPH_OK;
 }
 
+extern "C" elph_status elph_timing_extra(elph_ctx ctx, double* ms) {
+  CHECK_CTX(ctx);
+  if (!ms) return ELPH_EINVAL;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *ms = -1.0;
+  if (ctx->ev_recorded[4]) {
+    float v = 0.f;
+    HIPCHK(hipEventElapsedTime(&v, ctx->ev[8], ctx->ev[9]));
+    *ms = v;
+  }
+  return ELPH_OK;
+}
+
 extern "C" void elph_destroy(elph_ctx ctx) {
   if (!ctx) return;
   if (!ctx->hip_dead) (void)hipStreamSynchronize(ctx->stream);
-  for (int e = 0; e < 8; ++e)
+  for (int e = 0; e < 10; ++e)
     if (ctx->ev[e]) (void)hipEventDestroy(ctx->ev[e]);
   for (auto& b : ctx->allocs) (void)hipFree(b.first);
   for (auto& b : ctx->pool) (void)hipFree(b.first);

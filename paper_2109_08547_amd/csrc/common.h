@@ -143,8 +143,8 @@ struct elph_ctx_s {
 
   // event timing: [0,1] tables, [2,3] step 1, [4,5] step 2, [6,7] iterate
   bool timing = false;
-  hipEvent_t ev[8] = {};
-  bool ev_recorded[4] = {false, false, false, false};
+  hipEvent_t ev[10] = {};
+  bool ev_recorded[5] = {false, false, false, false, false};
 
   // caches reused across calls (dropped with the tables)
   int32_t* d_order = nullptr;     // [nstates] states sorted by energy

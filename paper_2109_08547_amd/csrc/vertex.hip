@@ -1774,7 +1774,9 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
   }
   if (st != ELPH_OK) return st;
   if (ep.tetra) {
+    mark(ctx, 8);
     launch_tetra_scale(ctx, Bp, Bm, store_f64);
+    mark(ctx, 9);
     if (th) {
       if (store_f64) launch_we_rows<double>(ctx, (const double*)Bp, (const double*)Bm, th->lomf, th->nocc,
                                             ctx->d_we_part);

@@ -44,7 +44,7 @@ class ElphSizes(ctypes.Structure):
 
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
-           "elph_batch_tune", "elph_tables",
+           "elph_batch_tune", "elph_tables", "elph_timing_extra",
            "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
            "elph_set_ifc3", "elph_phph_vertex", "elph_phph_rates", "elph_phph_inscatter", "elph_set_phph",
            "elph_mlp_create", "elph_mlp_destroy", "elph_mlp_last_error", "elph_mlp_nparams",
@@ -75,6 +75,7 @@ def load():
     lib.elph_last_error.restype = ctypes.c_char_p
     lib.elph_reset.argtypes = [vp, ctypes.c_int32]
     lib.elph_timing.argtypes = [vp, ctypes.c_int32, vp]
+    lib.elph_timing_extra.argtypes = [vp, vp]
     lib.elph_sizes.argtypes = [vp, ctypes.POINTER(ElphSizes)]
     lib.elph_tables.argtypes = [vp] * 7
     lib.elph_interp_g.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
@@ -207,6 +208,13 @@ def elph_timing(ctx, enable=True, read=False):
     _check(ctx, load().elph_timing(ctx.handle, int(bool(enable)),
                                    ms.ctypes.data_as(ctypes.c_void_p) if read else None))
     return dict(zip(("tables", "step1", "step2", "iterate"), ms)) if read else None
+
+
+def elph_timing_extra(ctx):
+    """Milliseconds of the last tetrahedron-delta scaling or Froehlich table (-1: none)."""
+    ms = ctypes.c_double(-1.0)
+    _check(ctx, load().elph_timing_extra(ctx.handle, ctypes.byref(ms)))
+    return ms.value
 
 
 def elph_sizes(ctx):
