@@ -836,3 +836,52 @@ def test_phph_operator_matches_inscatter():
     S = oracle.phph_inscatter(prob, ifc3, 300.0, 0.004, F)
     M = oracle.phph_operator(prob, ifc3, 300.0, 0.004)
     assert np.abs((M @ F.reshape(-1, 3)).reshape(S.shape) - S).max() <= 1e-13 * np.abs(S).max()
+
+
+def _einstein_triad(mesh=3):
+    """One atom, no dispersion, branches at hbar w_a (twice) and exactly
+    2 hbar w_a: the only three-phonon events are b -> a + a' and its reverse,
+    and they conserve energy exactly."""
+    hwa = 0.020                                           # eV
+    lam = hwa ** 2 / oracle.C_PHONON                      # mass-weighted eV / (A^2 amu)
+    d0 = np.diag([lam, lam, 4.0 * lam])[None]
+    mat = _material(1, 1, [[0, 0, 0]], [[0, 0, 0]], np.zeros((1, 1, 1)), d0, np.zeros((1, 1, 3, 1, 1)), [28.0855])
+    prob = oracle.Problem(mat, mesh, 0.0, np.inf, 0.01)
+    return prob, hwa
+
+
+def test_phph_rates_equal_the_golden_rule_on_exact_resonance():
+    """With every event exactly on shell, the paper's W/(n(1+n)) of Eq. 26
+    must reduce to the golden-rule lifetimes: (n' - n'') for absorption
+    a + a' -> b and (1 + n' + n'')/2 for decay b -> a + a' (the Bose
+    identities (n'+1) n'' = n (n' - n'') and n' n'' = n (1 + n' + n'') at
+    w'' = w + w' and w = w' + w''), with the same vertex and delta.  A wrong
+    occupation factor or a missing half changes the rates at order one."""
+    prob, hwa = _einstein_triad()
+    assert np.allclose(prob.hw, [hwa, hwa, 2 * hwa], rtol=1e-12)
+    ifc3 = synth.ifc3_params(1, 21, scale=0.3)
+    T, sigma = 300.0, hwa / 40.0
+    W = oracle.phph_rates(prob, ifc3, T, sigma)
+    E = oracle.eigendisplacements(prob.mat, prob.u)
+    nB, _ = oracle.bose_pair(prob.hw, T)
+    pref = np.pi / (4.0 * prob.nq) * oracle.C_PHPH
+    d0 = 1.0 / (np.sqrt(2.0 * np.pi) * sigma)            # the delta at zero mismatch
+    ref = np.zeros_like(W)
+    allq = np.arange(prob.nq)
+    for q in range(prob.nq):
+        for sign in (+1, -1):
+            l2 = oracle.mesh_linear(sign * prob.ijk[allq], prob.n)
+            qpp = oracle.mesh_linear(prob.ijk[q] + sign * prob.ijk[allq], prob.n)
+            l3 = oracle.mesh_linear(-prob.ijk[qpp], prob.n)
+            V2 = np.abs(oracle.phph_vertex(ifc3, prob.kfrac[l2], prob.kfrac[l3], E[q], E[l2], E[l3])) ** 2
+            for s1 in range(3):
+                for s2 in range(3):
+                    for s3 in range(3):
+                        w1, w2, w3 = prob.hw[q, s1], prob.hw[allq, s2], prob.hw[qpp, s3]
+                        if not np.allclose(w1 + sign * w2, w3, rtol=0, atol=1e-12):
+                            continue
+                        n2, n3 = nB[allq, s2], nB[qpp, s3]
+                        occ = (n2 - n3) if sign > 0 else 0.5 * (1.0 + n2 + n3)
+                        ref[q, s1] += (pref * d0 * V2[:, s1, s2, s3] * occ / (w1 * w2 * w3)).sum()
+    assert ref.min() > 0
+    assert np.abs(W - ref).max() <= 1e-9 * ref.max()
