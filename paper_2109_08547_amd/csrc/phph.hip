@@ -510,6 +510,203 @@ __global__ __launch_bounds__(256) void k_phph_tile(PhaseTab ph, int nq, int pran
   }
 }
 
+// The tile scheme for more than 32 distinct R_j (up to 256): tiles of kTW
+// rows; the R_j sum runs over chunks of 16 groups, each chunk's slab in
+// registers and the A accumulators of the tile's rows in registers across
+// the chunks; B, V and the epilogue as in k_phph_tile (per-row shuffles).
+constexpr int kTW = 8, kWG = 16;  // rows per tile, R_j groups per chunk
+
+template <int NBR, int NC>
+struct WideLds {
+  cd exq[kTW][NBR * NBR];
+  cd exd[kTW][NBR * NBR];
+  cd tq[kTW][kWG];             // exp(-2 pi i q.R_j) of the current chunk (zero beyond ng)
+  cd tP[kWG];                  // exp(+2 pi i P.R_j) of the current chunk
+  cd A[kTW][NBR * NBR * NBR];  // A of the tile's rows, then V
+  cd B[kQB][NBR * NBR * NBR];
+  double e1[kTW][NBR], e2[kTW][NBR], n2[kTW][NBR];
+  double e3[NBR], n3[NBR];
+  double acc[kTW][NBR * (NC ? NC : 1)];
+  double f3[NBR * (NC ? NC : 1)];
+  double f2[NC ? kTW : 1][NBR * (NC ? NC : 1)];
+  double f2m[NC ? kTW : 1][NBR * (NC ? NC : 1)];
+};
+
+// exp(-2 pi i P.R) with 32-bit index arithmetic (|P_i R_i| stays far below 2^31)
+__device__ inline cd phase_neg32(const PhaseTab& ph, int P, int r0, int r1, int r2) {
+  const int c = P % ph.n2, t = P / ph.n2, b = t % ph.n1, a = t / ph.n1;
+  int i0 = (a * r0) % ph.n0; if (i0 < 0) i0 += ph.n0;
+  int i1 = (b * r1) % ph.n1; if (i1 < 0) i1 += ph.n1;
+  int i2 = (c * r2) % ph.n2; if (i2 < 0) i2 += ph.n2;
+  const double2 p0 = ph.t0[i0], p1 = ph.t1[i1], p2 = ph.t2[i2];
+  return cconj(cmul(cmul(cmake(p0.x, p0.y), cmake(p1.x, p1.y)), cmake(p2.x, p2.y)));
+}
+
+template <int NBR, int NC>
+__global__ __launch_bounds__(256) void k_phph_wide(PhaseTab ph, int nq, int prange, const int32_t* __restrict__ gr,
+                                                   int ng, const cd* __restrict__ phi, const cd* __restrict__ Lq,
+                                                   const double* __restrict__ hw, const double* __restrict__ nbose,
+                                                   double omega_min, double sigma, const double* __restrict__ F,
+                                                   double* __restrict__ part) {
+  constexpr int N2 = NBR * NBR, N3 = N2 * NBR, NV = NC ? NC : 1;
+  static_assert(N3 <= 256 && N2 <= 64 && kQB * 64 == 256 && kTW % kQB == 0, "tile shape");
+  __shared__ WideLds<NBR, NC> L;
+  const int q0 = blockIdx.x * kTW, nt = min(kTW, nq - q0);
+  const int P0 = blockIdx.y * prange, P1 = min(nq, P0 + prange);
+  const MeshDims md{ph.n0, ph.n1, ph.n2};
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int t = tid; t < kTW * N2; t += blockDim.x) {
+    const int r = t / N2, e = t - r * N2;
+    L.exq[r][e] = r < nt ? edisp(Lq, hw, q0 + r, NBR, e / NBR, e % NBR) : cmake(0.0, 0.0);
+  }
+  for (int t = tid; t < kTW * NBR; t += blockDim.x) {
+    const int r = t / NBR, s = t - r * NBR;
+    L.e1[r][s] = r < nt ? hw[(int64_t)(q0 + r) * NBR + s] : 0.0;
+  }
+  for (int t = tid; t < kTW * NBR * NV; t += blockDim.x) L.acc[t / (NBR * NV)][t % (NBR * NV)] = 0.0;
+  const double inv2s2 = 0.5 / (sigma * sigma), dnorm = 1.0 / (sqrt(2.0 * kPi) * sigma);
+  for (int P = P0; P < P1; ++P) {
+    __syncthreads();   // the previous q'' is done with exd, e2, n2, e3, n3, f*, A
+    if (tid < NBR) {
+      const double w3 = hw[(int64_t)P * NBR + tid];
+      L.e3[tid] = w3 >= omega_min ? w3 : 0.0;
+      L.n3[tid] = nbose[(int64_t)P * NBR + tid];
+    }
+    for (int t = tid; t < kTW * N2; t += blockDim.x) {
+      const int r = t / N2, e = t - r * N2;
+      cd v = cmake(0.0, 0.0);
+      if (r < nt) v = edisp(Lq, hw, q_between(P, q0 + r, md.n0, md.n1, md.n2), NBR, e / NBR, e % NBR);
+      L.exd[r][e] = v;
+    }
+    for (int t = tid; t < kTW * NBR; t += blockDim.x) {
+      const int r = t / NBR, s = t - r * NBR;
+      double w2 = 0.0, n2 = 0.0;
+      if (r < nt) {
+        const int64_t m = (int64_t)q_between(q0 + r, P, md.n0, md.n1, md.n2) * NBR + s;
+        w2 = hw[m];
+        n2 = nbose[m];
+      }
+      L.e2[r][s] = w2 >= omega_min ? w2 : 0.0;
+      L.n2[r][s] = n2;
+    }
+    if constexpr (NC > 0) {
+      for (int t = tid; t < NBR * NC; t += blockDim.x) L.f3[t] = F[(int64_t)P * NBR * NC + t];
+      for (int t = tid; t < kTW * NBR * NC; t += blockDim.x) {
+        const int r = t / (NBR * NC), e = t - r * (NBR * NC);
+        double a = 0.0, b = 0.0;
+        if (r < nt) {
+          a = F[(int64_t)q_between(q0 + r, P, md.n0, md.n1, md.n2) * NBR * NC + e];
+          b = F[(int64_t)q_between(P, q0 + r, md.n0, md.n1, md.n2) * NBR * NC + e];
+        }
+        L.f2[r][e] = a;
+        L.f2m[r][e] = b;
+      }
+    }
+    cd a[kTW];
+#pragma unroll
+    for (int r = 0; r < kTW; ++r) a[r] = cmake(0.0, 0.0);
+    for (int c0 = 0; c0 < ng; c0 += kWG) {
+      cd slab[kWG];
+      const cd* src = phi + ((int64_t)P * ng + c0) * N3 + tid;
+#pragma unroll
+      for (int g = 0; g < kWG; ++g)
+        slab[g] = (c0 + g < ng && tid < N3) ? src[(int64_t)g * N3] : cmake(0.0, 0.0);
+      __syncthreads();   // the previous chunk is done with tq and tP
+      for (int t = tid; t < kTW * kWG; t += blockDim.x) {
+        const int r = t / kWG, g = t - r * kWG, G = c0 + g;
+        L.tq[r][g] = (r < nt && G < ng) ? phase_neg32(ph, q0 + r, gr[3 * G], gr[3 * G + 1], gr[3 * G + 2])
+                                        : cmake(0.0, 0.0);
+      }
+      if (tid < kWG) {
+        const int G = c0 + tid;
+        L.tP[tid] = G < ng ? cconj(phase_neg32(ph, P, gr[3 * G], gr[3 * G + 1], gr[3 * G + 2])) : cmake(0.0, 0.0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int g = 0; g < kWG; ++g) slab[g] = cmul(L.tP[g], slab[g]);
+#pragma unroll
+      for (int r = 0; r < kTW; ++r)
+#pragma unroll
+        for (int g = 0; g < kWG; ++g) a[r] = cfma(a[r], L.tq[r][g], slab[g]);
+    }
+    if (tid < N3)
+#pragma unroll
+      for (int r = 0; r < kTW; ++r) L.A[r][tid] = a[r];
+    __syncthreads();
+    for (int rb = 0; rb < nt; rb += kQB) {
+      for (int t = tid; t < kQB * N3; t += blockDim.x) {   // (r, x_i, s', s'')
+        const int r = t / N3, o = t - r * N3;
+        const int xi = o / N2, rr = o - xi * N2, s2 = rr / NBR, s3 = rr - s2 * NBR;
+        cd b = cmake(0.0, 0.0);
+#pragma unroll
+        for (int xj = 0; xj < NBR; ++xj)
+          b = cfma(b, L.exd[rb + r][xj * NBR + s2], L.A[rb + r][(xi * NBR + xj) * NBR + s3]);
+        L.B[r][o] = b;
+      }
+      __syncthreads();
+      for (int t = tid; t < kQB * N3; t += blockDim.x) {   // (r, s, s', s'')
+        const int r = t / N3, o = t - r * N3;
+        const int s1 = o / N2, rr = o - s1 * N2;
+        cd v = cmake(0.0, 0.0);
+#pragma unroll
+        for (int xi = 0; xi < NBR; ++xi) v = cfma(v, L.exq[rb + r][xi * NBR + s1], L.B[r][xi * N2 + rr]);
+        L.A[rb + r][o] = v;
+      }
+      __syncthreads();
+      {  // wave r: row rb + r, lane = (s', s'')
+        const int r = wave;
+        double c[NBR * NV];
+#pragma unroll
+        for (int k = 0; k < NBR * NV; ++k) c[k] = 0.0;
+        if (lane < N2) {
+          const int s2 = lane / NBR, s3 = lane - s2 * NBR;
+          const double E2 = L.e2[rb + r][s2], E3 = L.e3[s3];
+          if (E2 > 0.0 && E3 > 0.0) {
+            const double f = L.n3[s3] / (E2 * E3) * dnorm, np2 = L.n2[rb + r][s2];
+#pragma unroll
+            for (int s1 = 0; s1 < NBR; ++s1) {
+              const double E1 = L.e1[rb + r][s1];
+              const double dp = E1 + E2 - E3, dm = E1 - E2 - E3;
+              const double b = cabs2(L.A[rb + r][s1 * N2 + lane]) * f;
+              const double wp = b * (1.0 + np2) * exp(-dp * dp * inv2s2);  // absorption with -q'
+              const double wm = b * 0.5 * np2 * exp(-dm * dm * inv2s2);    // decay into q', half
+              if constexpr (NC == 0) {
+                c[s1] = wp + wm;
+              } else {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                  const double F3 = L.f3[s3 * NC + k];
+                  c[s1 * NC + k] = wp * (F3 - L.f2m[rb + r][s2 * NC + k]) + wm * (F3 + L.f2[rb + r][s2 * NC + k]);
+                }
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NBR * NV; ++k) {
+          double x = c[k];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+          c[k] = x;
+        }
+        if (rb + r < nt && lane < NBR * NV) {
+          double x = c[0];
+#pragma unroll
+          for (int k = 1; k < NBR * NV; ++k)
+            if (lane == k) x = c[k];
+          L.acc[rb + r][lane] += x;
+        }
+      }
+      __syncthreads();   // B is rewritten by the next rows
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < nt * NBR * NV; t += blockDim.x) {
+    const int r = t / (NBR * NV), e = t - r * (NBR * NV);
+    part[((int64_t)blockIdx.y * nq + q0 + r) * NBR * NV + e] = L.acc[r][e];
+  }
+}
+
 // W[q][s] = pi C / (4 N_q) sum_chunks part / (E n), modes below omega_min 0
 __global__ void k_phph_finish(int64_t nq, int nbr, int nv, int nchunk, const double* __restrict__ part,
                               const double* __restrict__ hw, double kT, double omega_min, double pref,
@@ -563,6 +760,15 @@ void launch_tile(elph_ctx ctx, int prange, int nrange, const cd* phi, const doub
     else
       launch_tile_g<NBR, NC, kMaxG>(ctx, prange, nrange, phi, nbose, sigma, F, part);
   }
+}
+
+template <int NBR, int NC>
+void launch_wide(elph_ctx ctx, int prange, int nrange, const cd* phi, const double* nbose, double sigma,
+                 const double* F, double* part) {
+  if constexpr (NBR * NBR * NBR <= 256)
+    hipLaunchKernelGGL((k_phph_wide<NBR, NC>), dim3((unsigned)((ctx->nk + kTW - 1) / kTW), (unsigned)nrange),
+                       dim3(256), 0, ctx->stream, phase_tab(ctx), (int)ctx->nk, prange, ctx->d_i3_rj, ctx->ng3, phi,
+                       (const cd*)ctx->d_Lq, ctx->d_hw, nbose, ctx->omega_min, sigma, F, part);
 }
 
 template <int NBR>
@@ -709,6 +915,7 @@ static elph_status phph_pass(elph_ctx ctx, const char* name, double T_K, double 
   }
   const int64_t nq = ctx->nk;
   const bool tile = ctx->nbr <= 6 && ctx->ng3 <= kMaxG;
+  const bool wide = ctx->nbr <= 6 && ctx->ng3 > kMaxG;
   const int nv = F ? 3 : 1;
   st = build_tables(ctx);
   if (st != ELPH_OK) return st;
@@ -716,9 +923,9 @@ static elph_status phph_pass(elph_ctx ctx, const char* name, double T_K, double 
   st = build_fold(ctx, &phi);
   if (st != ELPH_OK) return st;
   int nchunk, chunk;
-  if (tile) {
+  if (tile || wide) {
     // q'' ranges: about 4096 blocks in all, at least 8 q'' per block
-    const int64_t ntile = (nq + kTQ - 1) / kTQ;
+    const int64_t ntile = (nq + (wide ? kTW : kTQ) - 1) / (wide ? kTW : kTQ);
     nchunk = (int)std::max<int64_t>(1, std::min<int64_t>((nq + 7) / 8, (4096 + ntile - 1) / ntile));
   } else {
     // chunks of q' so that the grid holds at least ~4096 blocks
@@ -730,13 +937,21 @@ static elph_status phph_pass(elph_ctx ctx, const char* name, double T_K, double 
   ALLOC(part, (size_t)nchunk * nq * ctx->nbr * nv * sizeof(double));
   const double kT = kBoltzEVK * T_K;
   double* nbose = nullptr;
-  if (tile) {
+  if (tile || wide) {
     ALLOC(nbose, (size_t)nq * ctx->nbr * sizeof(double));
     hipLaunchKernelGGL(k_phph_bose, dim3(blocks_for(nq * ctx->nbr, 256)), dim3(256), 0, ctx->stream,
                        nq * ctx->nbr, ctx->d_hw, kT, ctx->omega_min, nbose);
   }
   mark(ctx, 4);  // the row kernel is reported in the step-2 timing window
-  if (tile && !F) {
+  if (wide && !F) {
+#define WIDE(N) launch_wide<N, 0>(ctx, chunk, nchunk, phi, nbose, sigma_eV, nullptr, part)
+    NBR_SWITCH(ctx->nbr, WIDE)
+#undef WIDE
+  } else if (wide) {
+#define WIDE(N) launch_wide<N, 3>(ctx, chunk, nchunk, phi, nbose, sigma_eV, F, part)
+    NBR_SWITCH(ctx->nbr, WIDE)
+#undef WIDE
+  } else if (tile && !F) {
 #define TILE(N) launch_tile<N, 0>(ctx, chunk, nchunk, phi, nbose, sigma_eV, nullptr, part)
     NBR_SWITCH(ctx->nbr, TILE)
 #undef TILE

@@ -193,3 +193,38 @@ def test_iterate_with_three_phonon_scattering(level):
         assert np.abs(ref["F"] - ref["F0"]).max() > 1e-4 * np.abs(ref["F0"]).max()
         assert np.all(got["G"] == 0)
     ctx.close()
+
+
+_wide = {}
+
+
+def _wide_case(name):
+    """A material of _case with force constants on the cell triples of
+    {-2..2}^3 (6859 entries, 125 distinct R_j: the chunked wide kernel)."""
+    if name not in _wide:
+        cfg, mat, prob, _ = _case(name)
+        ifc3 = synth.ifc3_params(mat["natom"], 90 + len(name), cells=synth.rset_cube(-2, 2), scale=0.1, sweeps=20)
+        _wide[name] = (cfg, mat, prob, ifc3)
+    return _wide[name]
+
+
+@pytest.mark.parametrize("name", ["tiny3", "tiny4"])
+def test_phph_wide_rates_and_inscatter(name):
+    """More than 32 distinct R_j (the chunked tile kernel): rates and the
+    in-scattering of a seeded field against the oracle."""
+    cfg, mat, prob, ifc3 = _wide_case(name)
+    assert len(set(map(tuple, ifc3[0].tolist()))) > 32
+    ctx = _ctx(cfg, mat, ifc3)
+    W = torch.empty(prob.nq * prob.nbr, dtype=torch.float64, device=DEV)
+    E.elph_phph_rates(ctx, T, SIGMA, W)
+    got = W.cpu().numpy().reshape(prob.nq, prob.nbr)
+    ref = oracle.phph_rates(prob, ifc3, T, SIGMA)
+    assert ref.max() > 0
+    assert np.abs(got - ref).max() <= 1e-10 * ref.max()
+    F = np.random.default_rng(5).standard_normal((prob.nq, prob.nbr, 3))
+    Fd = torch.from_numpy(F).to(DEV)
+    S = torch.empty_like(Fd)
+    E.elph_phph_inscatter(ctx, T, SIGMA, Fd, S)
+    refS = oracle.phph_inscatter(prob, ifc3, T, SIGMA, F)
+    assert np.abs(S.cpu().numpy() - refS).max() <= 1e-10 * np.abs(refS).max()
+    ctx.close()
