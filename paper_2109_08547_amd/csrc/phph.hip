@@ -17,6 +17,12 @@
 // and, through |V+(q, -q', q'')| = |V-(q, q', q'')| (the identity the paper
 // states below Eq. 13), the absorption q + (-q') -> q''; omega and n at -q'
 // equal those at q'.
+//
+// Three row kernels evaluate the pair sums: k_phph_tile (one or two atoms, at
+// most 32 distinct R_j: the slab of one q'' in registers, reused by a tile of
+// 16 rows), k_phph_wide (one or two atoms, more R_j: the R_j sum in chunks)
+// and k_phph_rows (any atom count: block per (q, q' chunk), the slab read per
+// pair).  Each has a rates mode and a field mode (the in-scattering of Eq. 26).
 #include "vertex.h"
 #include "devutil.h"
 #include "tables.h"
