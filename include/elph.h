@@ -301,7 +301,12 @@ elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, double* W_ph
  * tol/100 at level COUPLED).
  * W_ph_ext [nk][nbr] device: phonon rates from other channels (ph-ph,
  * isotopes), s^-1, added to the ph-e rate (Eq. 25); NULL selects the model
- * 1e12 (hw/hw_max)^2 (T/300).  The ph-ph in-scattering term is zero.
+ * 1e12 (hw/hw_max)^2 (T/300).  Without elph_set_phph the phonon
+ * in-scattering Delta F^S is zero.  After elph_set_phph(sigma > 0) the
+ * three-phonon RTA rate of Eq. 26 is added to W^RTA as well (W_ph_ext then
+ * holds only the channels other than ph-e and three-phonon, and NULL means
+ * none, not the model rate, so no channel is counted twice) and Delta F^S of
+ * Eq. 26 joins every phonon update.
  * Electron responses are constrained to carry no change of carrier number
  * in each energy group (sorted active energies split at gaps wider than
  * hw_max + 12 sigma), which removes the conserved modes of the e-ph

@@ -47,9 +47,12 @@ Readings of the paper used here (where it is silent, garbled or ambiguous):
   change of carrier number), applied after every electron sweep; for
   materials with inversion or time-reversal symmetry this holds by itself.
 * Phonon scattering other than ph-e enters the iteration as an external rate
-  per mode (default model gamma0 (hw/hw_max)^2 (T/300 K), gamma0 = 1e12/s,
-  or the three-phonon RTA rate of Eq. 26 computed by phph_rates); the ph-ph
-  in-scattering term Delta F^S is zero.
+  per mode (default model gamma0 (hw/hw_max)^2 (T/300 K), gamma0 = 1e12/s).
+  Without three-phonon processes the phonon in-scattering Delta F^S is zero;
+  iterate(..., phph=(ifc3, sigma)) adds the three-phonon RTA rate of Eq. 26
+  (phph_rates) to W^RTA, with w_ext then holding only the remaining channels
+  (none when None), and Delta F^S = S[F] / W^RTA (phph_operator) to every
+  phonon update.
 """
 import numpy as np
 
