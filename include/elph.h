@@ -176,6 +176,42 @@ elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms);
  * the stream. */
 elph_status elph_timing_extra(elph_ctx ctx, double* ms);
 
+/* FP64 refinement of ill-conditioned vertices in the GEMM forms (FP32 and
+ * the BF16 / FP16 splits; Eq. 6 evaluated as FP32-accumulated MFMA sums).
+ * A vertex component is a sum of N_Rp * nb products accumulated with an
+ * error of about u times the root-sum-square of those products plus v times
+ * the component's own magnitude (FP32 partial sums; u = 1.2e-7, v = 1e-7 for
+ * FP32, FP16x3 and BF16x6, u = 6e-6, v = 2e-6 for BF16x3); where |g| is far
+ * below that scale (a near-cancellation) |g|^2 is only accurate to a few
+ * digits.  With the refinement on, the vertex store of a GEMM form keeps for
+ * every term a log-coded estimate of the relative error of its |g|^2, and
+ * every rate reduction (elph_scatt_rates, elph_iterate) sums each term's
+ * contribution times its estimate: for a rate (W_e of Eq. 21 or a mode of
+ * Eq. 25) whose estimated relative error exceeds theta, the terms that carry
+ * at least theta/8 of the rate are recomputed in FP64 (the
+ * same contraction with FP64 MFMA step-1 rows of their initial states),
+ * written back to the store as exact, and the affected rates reduced again.
+ * theta: default 2e-6; 0 turns the refinement off (the stored terms keep the
+ * form's plain accuracy).  Applies with the Gaussian delta and without a
+ * screen's tile mask; other evaluations keep the plain form.  Marks the
+ * cached rates stale.  EINVAL for a negative or non-finite theta. */
+elph_status elph_set_refine(elph_ctx ctx, double theta);
+
+/* Counters of the last refinement (host int64[8], may be NULL): rates
+ * flagged (W_e rows, phonon modes), pairs (i, j) recomputed in FP64, their
+ * distinct initial states, their distinct wave vectors, pairs beyond the
+ * per-call capacity of 4194304, rows and modes still above theta after it.
+ * ms (host, may be NULL): duration of the refinement with timing on (-1:
+ * none recorded).  Synchronises the stream. */
+elph_status elph_refine_info(elph_ctx ctx, int64_t* stats, double* ms);
+
+/* The estimates themselves: rel_err [nterms] device FP64, the relative error
+ * estimate of every stored |g|^2 in the term-store layout (0 for terms
+ * recomputed in FP64; estimates are coded to within a factor 2^(1/6)).
+ * ESTATE unless the context holds the store of a GEMM form computed with the
+ * refinement on.  Synchronises the stream. */
+elph_status elph_refine_estimates(elph_ctx ctx, double* rel_err);
+
 /* Build the electron and phonon tables if needed (Eqs. 1-3, 5 and the
  * window) and report sizes; synchronises the stream. */
 elph_status elph_sizes(elph_ctx ctx, elph_sizes_t* out);
@@ -368,7 +404,10 @@ const char* elph_batch_last_error(elph_batch b);
  * may be NULL).  use_graph != 0 captures the sequence in a HIP graph on the
  * first call for a given temperature and set of output pointers and replays
  * it afterwards.  Synchronises the batch stream.  The vertex stores of all
- * contexts are left valid. */
+ * contexts are left valid.  Batches compute the plain form of their
+ * precision: the FP64 refinement of elph_set_refine is not applied (the
+ * results equal those of elph_scatt_rates on each context with the
+ * refinement off). */
 elph_status elph_batch_scatt_rates(elph_batch b, double T_K, double* const* W_e, double* const* W_ph,
                                    int32_t use_graph);
 

@@ -10,6 +10,7 @@
 #include "common.h"
 #include "tables.h"
 #include "vertex.h"
+#include "devutil.h"
 
 using namespace elph;
 
@@ -261,7 +262,7 @@ extern "C" elph_status elph_create(const elph_wannier* w, const elph_params* p, 
 extern "C" elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms) {
   CHECK_CTX(ctx);
   if (enable && !ctx->ev[0]) {
-    for (int e = 0; e < 10; ++e) HIPCHK(hipEventCreate(&ctx->ev[e]));
+    for (int e = 0; e < 12; ++e) HIPCHK(hipEventCreate(&ctx->ev[e]));
   }
   if (ms) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -275,6 +276,60 @@ extern "C" elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms) {
     }
   }
   ctx->timing = enable != 0;
+  return ELPH_OK;
+}
+
+extern "C" elph_status elph_set_refine(elph_ctx ctx, double theta) {
+  CHECK_CTX(ctx);
+  if (!(theta >= 0.0) || !std::isfinite(theta)) {
+    ctx->err = "refinement threshold must be finite and >= 0";
+    return ELPH_EINVAL;
+  }
+  if (theta != ctx->refine_theta) {
+    // the codes stay with the store; only the rates are reduced again
+    ctx->refine_theta = theta;
+    ctx->rates_valid = false;
+  }
+  return ELPH_OK;
+}
+
+extern "C" elph_status elph_refine_info(elph_ctx ctx, int64_t* stats, double* ms) {
+  CHECK_CTX(ctx);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (stats)
+    for (int k = 0; k < 8; ++k) stats[k] = ctx->ref_stats[k];
+  if (ms) {
+    *ms = -1.0;
+    if (ctx->ev_recorded[5]) {
+      float v = 0.f;
+      HIPCHK(hipEventElapsedTime(&v, ctx->ev[10], ctx->ev[11]));
+      *ms = v;
+    }
+  }
+  return ELPH_OK;
+}
+
+__global__ void k_rho_decode(int64_t n, int nbr, int stride, const uint8_t* __restrict__ rho,
+                             double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = rho_decode(rho[(t / nbr) * stride + t % nbr]);
+}
+
+extern "C" elph_status elph_refine_estimates(elph_ctx ctx, double* rel_err) {
+  CHECK_CTX(ctx);
+  if (!rel_err) {
+    ctx->err = "null output";
+    return ELPH_EINVAL;
+  }
+  if (!ctx->store_ready || !ctx->rho_valid) {
+    ctx->err = "no error estimates: the vertex store of a GEMM form with the refinement on is needed";
+    return ELPH_ESTATE;
+  }
+  const int64_t n = ctx->nstates * ctx->nstates * ctx->nbr;
+  hipLaunchKernelGGL(k_rho_decode, dim3(blocks_for(n, 256)), dim3(256), 0, ctx->stream, n, ctx->nbr,
+                     ctx->rho_stride, ctx->d_rho, rel_err);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return ELPH_OK;
 }
 
@@ -294,7 +349,7 @@ extern "C" elph_status elph_timing_extra(elph_ctx ctx, double* ms) {
 extern "C" void elph_destroy(elph_ctx ctx) {
   if (!ctx) return;
   if (!ctx->hip_dead) (void)hipStreamSynchronize(ctx->stream);
-  for (int e = 0; e < 10; ++e)
+  for (int e = 0; e < 12; ++e)
     if (ctx->ev[e]) (void)hipEventDestroy(ctx->ev[e]);
   for (auto& b : ctx->allocs) (void)hipFree(b.first);
   for (auto& b : ctx->pool) (void)hipFree(b.first);
@@ -321,7 +376,7 @@ static void drop_derived(elph_ctx ctx) {
                    (void**)&ctx->d_Bm,      (void**)&ctx->d_we_part,   (void**)&ctx->d_order,
                    (void**)&ctx->d_goff,    (void**)&ctx->d_we_cache,  (void**)&ctx->d_wph_cache,
                    (void**)&ctx->d_poff,    (void**)&ctx->d_plist,     (void**)&ctx->d_frohlich,
-                   (void**)&ctx->d_ustate};
+                   (void**)&ctx->d_ustate,  (void**)&ctx->d_rho,       (void**)&ctx->d_b2n};
   for (void** p : ptrs) {
     dev_free(ctx, *p);
     *p = nullptr;
@@ -329,6 +384,7 @@ static void drop_derived(elph_ctx ctx) {
   ctx->we_part_len = 0;
   ctx->tables_ready = ctx->operands_ready = ctx->store_ready = false;
   ctx->groups_ready = ctx->rates_valid = ctx->pairs_ready = ctx->pairs_failed = false;
+  ctx->rho_valid = false;
   ctx->nkept = ctx->nstates = 0;
   ctx->ngroups = 0;
 }
@@ -347,6 +403,10 @@ extern "C" elph_status elph_reset(elph_ctx ctx, int32_t what) {
     ctx->rates_valid = false;
   } else {
     drop_derived(ctx);
+    // the FP64 vertex operand of the refinement depends on the inputs only
+    // and survives the other resets
+    dev_free(ctx, ctx->d_gR64);
+    ctx->d_gR64 = nullptr;
     pool_trim(ctx);
   }
   return ELPH_OK;
@@ -643,9 +703,17 @@ extern "C" elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, d
       return ELPH_ENOMEM;
     }
     ctx->store_f32 = !f64;
-    st = run_vertex(ctx, ctx->d_Bp, ctx->d_Bm, f64, &th, W_e ? W_e : (double*)we, nullptr);
-    if (st == ELPH_OK) ctx->store_ready = true;
-    if (st == ELPH_OK && W_ph) st = rates_from_store(ctx, th, nullptr, W_ph);
+    if (refine_applicable(ctx)) {
+      // the GEMM forms' rates come from the finished store, after the FP64
+      // refinement of the terms whose error estimate a rate cannot absorb
+      st = run_vertex(ctx, ctx->d_Bp, ctx->d_Bm, f64, nullptr, nullptr, nullptr);
+      if (st == ELPH_OK) ctx->store_ready = true;
+      if (st == ELPH_OK) st = rates_from_store(ctx, th, W_e ? W_e : (double*)we, W_ph);
+    } else {
+      st = run_vertex(ctx, ctx->d_Bp, ctx->d_Bm, f64, &th, W_e ? W_e : (double*)we, nullptr);
+      if (st == ELPH_OK) ctx->store_ready = true;
+      if (st == ELPH_OK && W_ph) st = rates_from_store(ctx, th, nullptr, W_ph);
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     dev_free(ctx, we);
   }

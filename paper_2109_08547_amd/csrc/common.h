@@ -141,10 +141,24 @@ struct elph_ctx_s {
   double* d_we_part = nullptr;    // [n_jtiles][m_pad]
   int64_t we_part_len = 0;
 
-  // event timing: [0,1] tables, [2,3] step 1, [4,5] step 2, [6,7] iterate
+  // FP64 refinement of ill-conditioned vertices in the GEMM forms: every
+  // stored |g|^2 carries an estimate of its relative error; rates whose
+  // estimated relative error exceeds refine_theta have their dominant terms
+  // recomputed in FP64 (0 turns the refinement off)
+  double refine_theta = 2.0e-6;
+  uint8_t* d_rho = nullptr;       // [nstates][nstates][rho_stride] log-coded error estimate of each |g|^2 (0: exact)
+  int rho_stride = 8;             // bytes per pair (i, j): 8 for up to 8 branches, else 16
+  bool rho_valid = false;         // d_rho describes the current vertex store
+  float* d_b2n = nullptr;         // [nstates][nbr] mean over n' of sum_Rp w_p^2 |B2[(i,x)][(Rp,n')]|^2
+  double* d_gR64 = nullptr;       // [nbr*nrp*nb][ke64] FP64 vertex operand of the refinement (built on demand)
+  int64_t ke64 = 0, kp64 = 0;     // FP64 padded contraction lengths
+  int64_t ref_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // last refinement: see elph_refine_info
+
+  // event timing: [0,1] tables, [2,3] step 1, [4,5] step 2, [6,7] iterate,
+  // [8,9] tetrahedron weights / Froehlich table, [10,11] refinement
   bool timing = false;
-  hipEvent_t ev[10] = {};
-  bool ev_recorded[5] = {false, false, false, false, false};
+  hipEvent_t ev[12] = {};
+  bool ev_recorded[6] = {false, false, false, false, false, false};
 
   // caches reused across calls (dropped with the tables)
   int32_t* d_order = nullptr;     // [nstates] states sorted by energy

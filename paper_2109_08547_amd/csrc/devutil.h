@@ -59,6 +59,49 @@ struct MeshDims {
   int n0, n1, n2;
 };
 
+// Log code of the relative error estimate r of a stored |g|^2 in the GEMM
+// forms: code 0 marks an exact (FP64-refined) term, code c >= 1 stands for
+// r = 2^((c - 1)/6 - 42) (rounded up; 1.26 and above saturate at 255).  d2
+// is the squared error scale of g and g2 = |g|^2: r = 2 sqrt(d2/g2) + d2/g2.
+// An estimate needs no more than FP32 and the hardware log2.
+__device__ inline uint32_t rho_encode(float d2, float g2) {
+  if (!(g2 > 0.f)) return d2 > 0.f ? 255u : 1u;
+  const float t = d2 / g2;
+  const float r = 2.f * sqrtf(t) + t;
+  if (!(r > 0.f)) return 1u;
+  const float c = ceilf(6.f * (__log2f(r) + 42.f)) + 1.f;
+  return (uint32_t)fminf(fmaxf(c, 1.f), 255.f);
+}
+
+// bytes per pair (i, j) of the code array for NX branches
+template <int NX>
+struct RhoStride {
+  static constexpr int value = NX <= 8 ? 8 : 16;
+};
+
+// The codes of one pair, read with one 8- or 16-byte load
+template <int NX>
+struct PairCodes {
+  uint32_t w[RhoStride<NX>::value / 4];
+  __device__ inline void load(const uint8_t* p) {
+    if constexpr (RhoStride<NX>::value == 8) {
+      const uint2 v = *reinterpret_cast<const uint2*>(p);
+      w[0] = v.x;
+      w[1] = v.y;
+    } else {
+      const uint4 v = *reinterpret_cast<const uint4*>(p);
+      w[0] = v.x;
+      w[1] = v.y;
+      w[2] = v.z;
+      w[3] = v.w;
+    }
+  }
+  __device__ inline unsigned operator[](int s) const { return (w[s >> 2] >> (8 * (s & 3))) & 255u; }
+};
+
+__device__ inline double rho_decode(unsigned c) { return c ? exp2((double)(c - 1) * (1.0 / 6.0) - 42.0) : 0.0; }
+
+
 // Two adjacent values of T as one 8- or 16-byte access
 template <typename T>
 struct Two;

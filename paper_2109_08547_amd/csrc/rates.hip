@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 namespace elph {
 
@@ -112,31 +113,57 @@ __global__ void k_x_from_store(int64_t M, int nbr, MeshDims md, const ST* __rest
 }
 
 // W_e[i] = sum_{j,s} (B+ n + B- (1+n)) (1 - f_j)/(1 - f_i): Eq. 21 with X/(f(1-f))
+// With error codes (er.rho) the row also sums each term's contribution times
+// its relative error estimate and flags the row when that exceeds er.theta
+// of the rate; er.idx restricts the launch to listed rows.
 template <typename ST, int NX>
 __global__ void __launch_bounds__(256) k_we_rows(int64_t M, MeshDims md, const ST* __restrict__ Bp,
                                                  const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
                                                  const double* __restrict__ lomf, const double* __restrict__ nocc,
-                                                 double* __restrict__ we) {
-  __shared__ double sh[4];
-  const int64_t i = blockIdx.x;
+                                                 double* __restrict__ we, RateErr er) {
+  __shared__ double sh[8];
+  __shared__ double rtab[256];
+  const int64_t i = er.idx ? er.idx[blockIdx.x] : blockIdx.x;
   const int ki = st_k[i];
   const double li = lomf[i];
-  double acc[1] = {0.0};
+  const uint8_t* __restrict__ rho = er.rho;
+  if (rho) {
+    rtab[threadIdx.x] = rho_decode(threadIdx.x);
+    __syncthreads();
+  }
+  double acc[2] = {0.0, 0.0};
   const ST* __restrict__ bp = Bp + i * M * NX;
   const ST* __restrict__ bm = Bm + i * M * NX;
   for (int64_t j = threadIdx.x; j < M; j += 256) {
     const int q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
     const double* nq = nocc + (int64_t)q * NX;
-    double b = 0.0;
+    double b = 0.0, e = 0.0;
+    PairCodes<NX> pc;
+    if (rho) pc.load(rho + (i * M + j) * RhoStride<NX>::value);
 #pragma unroll
     for (int s = 0; s < NX; ++s) {
       const double n = nq[s];
-      b += (double)bp[j * NX + s] * n + (double)bm[j * NX + s] * (1.0 + n);
+      const double t = (double)bp[j * NX + s] * n + (double)bm[j * NX + s] * (1.0 + n);
+      b += t;
+      if (rho) e += t * rtab[pc[s]];
     }
-    if (b != 0.0) acc[0] += b * exp(lomf[j] - li);
+    if (b != 0.0) {
+      const double w = exp(lomf[j] - li);
+      acc[0] += b * w;
+      acc[1] += e * w;
+    }
   }
-  block_sum<1>(acc, sh);
-  if (threadIdx.x == 0) we[i] = acc[0];
+  if (rho) {
+    block_sum<2>(acc, sh);
+  } else {
+    double a1[1] = {acc[0]};
+    block_sum<1>(a1, sh);
+    acc[0] = a1[0];
+  }
+  if (threadIdx.x == 0) {
+    we[i] = acc[0];
+    if (rho && er.cnt && acc[1] > er.theta * acc[0]) er.list[atomicAdd(er.cnt, 1)] = (int32_t)i;
+  }
 }
 
 // Deterministic q-gather over the term store.  One wavefront per phonon
@@ -314,6 +341,8 @@ elph_status ensure_pairs(elph_ctx ctx) {
 
 // acc[q][s][c] over the pair list of q: lanes take every 64th pair, then a
 // fixed-order butterfly over the wavefront
+// (NV = 1: optional error codes as in k_we_rows, per branch; er.idx
+// restricts the launch to er.n listed wave vectors)
 template <typename ST, int NV, int NX>
 __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, MeshDims md,
                                                       const ST* __restrict__ Bp, const int32_t* __restrict__ kept,
@@ -322,10 +351,22 @@ __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, Mes
                                                       const int32_t* __restrict__ poff,
                                                       const int32_t* __restrict__ plist, const double* __restrict__ f,
                                                       const double* __restrict__ omf, const double* __restrict__ x,
-                                                      double* __restrict__ acc) {
+                                                      double* __restrict__ acc, RateErr er) {
   const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= nq) return;  // whole wavefront exits together
+  __shared__ double rtab[NV == 1 ? 256 : 1];
+  const uint8_t* __restrict__ rho = NV == 1 ? er.rho : nullptr;
+  if constexpr (NV == 1) {
+    if (rho) {
+      rtab[threadIdx.x] = rho_decode(threadIdx.x);
+      __syncthreads();
+    }
+  }
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= (er.idx ? er.n : nq)) return;  // whole wavefront exits together
+  const int64_t q = er.idx ? er.idx[w] : w;
+  double ev[NV == 1 ? NX : 1];
+#pragma unroll
+  for (int s = 0; s < (NV == 1 ? NX : 1); ++s) ev[s] = 0.0;
   const int qc = (int)(q % md.n2);
   const int qt = (int)(q / md.n2);
   const int qb = qt % md.n1, qa = qt / md.n1;
@@ -354,11 +395,18 @@ __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, Mes
 #pragma unroll
           for (int c = 0; c < NV; ++c) w[c] = x[(int64_t)j * NV + c] - x[(int64_t)i * NV + c];
         const ST* b = Bp + ((int64_t)i * M + j) * NX;
+        PairCodes<NX> pc;
+        if constexpr (NV == 1) {
+          if (rho) pc.load(rho + ((int64_t)i * M + j) * RhoStride<NX>::value);
+        }
 #pragma unroll
         for (int s = 0; s < NX; ++s) {
           const double v = (double)b[s] * occ;
 #pragma unroll
           for (int c = 0; c < NV; ++c) a[s][c] += v * w[c];
+          if constexpr (NV == 1) {
+            if (rho) ev[s] += v * rtab[pc[s]];
+          }
         }
       }
     }
@@ -371,14 +419,24 @@ __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, Mes
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
       if (lane == 0) acc[(q * NX + s) * NV + c] = v;
+      if constexpr (NV == 1) {
+        if (rho) {
+          double e = ev[s];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+          if (lane == 0 && er.cnt && e > er.theta * v) er.list[atomicAdd(er.cnt, 1)] = (int32_t)(q * NX + s);
+        }
+      }
     }
   }
 }
 
 template <typename ST, int NV>
 void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x,
-                     double* acc) {
-  const dim3 grid(blocks_for(ctx->nk, 4)), blk(256);
+                     double* acc, const RateErr* err) {
+  const RateErr er = err ? *err : RateErr();
+  const dim3 grid(blocks_for(er.idx ? er.n : ctx->nk, 4)), blk(256);
+  if (er.idx && er.n == 0) return;
   const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
   bool csr = ctx->pairs_ready;
   if (!csr && !ctx->pairs_failed && ctx->nkept <= kMaxPairKept) {
@@ -390,7 +448,7 @@ void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* 
   if (csr) {
 #define QG(NXV)                                                                                                \
   hipLaunchKernelGGL((k_q_gather_csr<ST, NV, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, md, Bp,   \
-                     ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist, f, omf, x, acc)
+                     ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist, f, omf, x, acc, er)
     switch (ctx->nbr) {
       case 3: QG(3); break;
       case 6: QG(6); break;
@@ -427,9 +485,9 @@ __global__ void k_wph_finalize(int64_t n, const double* __restrict__ acc, const 
 static MeshDims mdims(elph_ctx ctx) { return MeshDims{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]}; }
 
 template void launch_q_gather<float, 1>(elph_ctx, const float*, const double*, const double*, const double*,
-                                       double*);
+                                       double*, const RateErr*);
 template void launch_q_gather<double, 1>(elph_ctx, const double*, const double*, const double*, const double*,
-                                        double*);
+                                        double*, const RateErr*);
 
 elph_status ensure_store(elph_ctx ctx) {
   if (ctx->store_ready) return ELPH_OK;
@@ -456,12 +514,16 @@ elph_status finalize_wph(elph_ctx ctx, const Thermal& th, double* acc, double* w
 }
 
 template <typename ST>
-void launch_we_rows(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc, double* we) {
+void launch_we_rows(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc, double* we,
+                    const RateErr* err) {
   const int64_t M = ctx->nstates;
   hipStream_t s = ctx->stream;
+  const RateErr er = err ? *err : RateErr();
+  const int64_t nrows = er.idx ? er.n : M;
+  if (nrows == 0) return;
 #define WR(NXV)                                                                                            \
-  hipLaunchKernelGGL((k_we_rows<ST, NXV>), dim3((unsigned)M), dim3(256), 0, s, M, mdims(ctx), Bp, Bm,      \
-                     ctx->d_state_k, lomf, nocc, we)
+  hipLaunchKernelGGL((k_we_rows<ST, NXV>), dim3((unsigned)nrows), dim3(256), 0, s, M, mdims(ctx), Bp, Bm,  \
+                     ctx->d_state_k, lomf, nocc, we, er)
   switch (ctx->nbr) {
     case 3: WR(3); break;
     case 6: WR(6); break;
@@ -471,23 +533,64 @@ void launch_we_rows(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf
   }
 #undef WR
 }
-template void launch_we_rows<float>(elph_ctx, const float*, const float*, const double*, const double*, double*);
-template void launch_we_rows<double>(elph_ctx, const double*, const double*, const double*, const double*, double*);
+template void launch_we_rows<float>(elph_ctx, const float*, const float*, const double*, const double*, double*,
+                                    const RateErr*);
+template void launch_we_rows<double>(elph_ctx, const double*, const double*, const double*, const double*, double*,
+                                     const RateErr*);
 
 template <typename ST>
 static elph_status rates_from_store_t(elph_ctx ctx, const Thermal& th, double* we, double* wph) {
   const int nbr = ctx->nbr;
   hipStream_t s = ctx->stream;
-  if (we) launch_we_rows<ST>(ctx, (const ST*)ctx->d_Bp, (const ST*)ctx->d_Bm, th.lomf, th.nocc, we);
+  const int64_t M = ctx->nstates, nm = ctx->nk * nbr;
+  // GEMM forms with error codes: the reductions flag rates whose estimated
+  // relative error exceeds refine_theta; their dominant terms are then
+  // recomputed in FP64 and the affected rates reduced again
+  const bool refine = std::is_same<ST, float>::value && ctx->rho_valid && ctx->refine_theta > 0.0 &&
+                      refine_applicable(ctx) && (we || wph);
+  RateErr ee, ep;
+  int32_t* cnt = nullptr;
+  double* acc = nullptr;
+  if (wph) ALLOC(acc, nm * sizeof(double));
+  if (refine) {
+    // the phonon side selects terms along the pair lists of q
+    if (wph && !ctx->pairs_ready && !ctx->pairs_failed && ctx->nkept <= kMaxPairKept) {
+      const elph_status st = ensure_pairs(ctx);
+      if (st != ELPH_OK) ctx->pairs_failed = true;
+      if (st == ELPH_ENOMEM) ctx->err.clear();
+      else if (st != ELPH_OK) return st;
+    }
+    ALLOC(cnt, 16 * sizeof(int32_t));
+    HIPCHK(hipMemsetAsync(cnt, 0, 16 * sizeof(int32_t), s));
+    ee.rho = ctx->d_rho;
+    if (ctx->pairs_ready) ep.rho = ctx->d_rho;
+    ee.theta = ep.theta = ctx->refine_theta;
+    ee.cnt = cnt;
+    ep.cnt = cnt + 1;
+    ALLOC(ee.list, M * sizeof(int32_t));
+    ALLOC(ep.list, nm * sizeof(int32_t));
+  }
+  if (we) launch_we_rows<ST>(ctx, (const ST*)ctx->d_Bp, (const ST*)ctx->d_Bm, th.lomf, th.nocc, we,
+                             refine ? &ee : nullptr);
+  if (wph) launch_q_gather<ST, 1>(ctx, (const ST*)ctx->d_Bp, th.f, th.omf, nullptr, acc,
+                                  refine && ep.rho ? &ep : nullptr);
+  if (refine) {
+    mark(ctx, 10);
+    const elph_status st = refine_terms(ctx, th, we, wph ? acc : nullptr, ee, ep, cnt);
+    mark(ctx, 11);
+    if (st != ELPH_OK) return st;
+  }
   if (wph) {
-    const int64_t nm = ctx->nk * nbr;
-    double* acc = nullptr;
-    ALLOC(acc, nm * sizeof(double));
-    launch_q_gather<ST, 1>(ctx, (const ST*)ctx->d_Bp, th.f, th.omf, nullptr, acc);
     elph_status st = finalize_wph(ctx, th, acc, wph);
     HIPCHK(hipStreamSynchronize(s));
-    dev_free(ctx, acc);
     if (st != ELPH_OK) return st;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  dev_free(ctx, acc);
+  if (refine) {
+    dev_free(ctx, cnt);
+    dev_free(ctx, (void*)ee.list);
+    dev_free(ctx, (void*)ep.list);
   }
   HIPCHK(hipGetLastError());
   return ELPH_OK;

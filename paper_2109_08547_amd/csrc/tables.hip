@@ -943,16 +943,18 @@ elph_status build_tables(elph_ctx ctx) {
   }
   HIPCHK(hipGetLastError());
 
-  // ---- Eq. 7 for polar materials: F_s(q) and the active states' eigenvectors
+  // ---- the active states' eigenvectors (state overlaps of Eq. 7, error
+  // estimates and FP64 refinement of the GEMM forms) and, for polar
+  // materials, F_s(q) of Eq. 7
+  ALLOC(ctx->d_ustate, ctx->nstates * nb * sizeof(cd));
+  hipLaunchKernelGGL(k_fill_ustate, dim3(blocks_for(ctx->nstates * nb, 256)), dim3(256), 0, s, ctx->nstates, nb,
+                     ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_U, (cd*)ctx->d_ustate);
+  HIPCHK(hipGetLastError());
   if (ctx->frohlich) {
     ALLOC(ctx->d_frohlich, nk * nbr * sizeof(cd));
     mark(ctx, 8);
     launch_frohlich(ctx, nullptr, nk, (const cd*)ctx->d_Lq, (cd*)ctx->d_frohlich, s);
     mark(ctx, 9);
-    ALLOC(ctx->d_ustate, ctx->nstates * nb * sizeof(cd));
-    hipLaunchKernelGGL(k_fill_ustate, dim3(blocks_for(ctx->nstates * nb, 256)), dim3(256), 0, s, ctx->nstates, nb,
-                       ctx->d_state_kidx, ctx->d_state_m, (const cd*)ctx->d_U, (cd*)ctx->d_ustate);
-    HIPCHK(hipGetLastError());
   }
 
   // ---- hw_max

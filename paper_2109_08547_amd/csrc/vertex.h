@@ -16,11 +16,26 @@ elph_status build_operands(elph_ctx ctx);
 elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const Thermal* th, double* we_out,
                        double* wph_acc);
 
+// Error-estimate options of the rate reductions (null rho: none).  With rho
+// set, a rate whose estimated relative error (sum of term contributions
+// times their codes over the rate) exceeds theta is appended to list (count
+// in *cnt).  idx (optional) restricts the reduction to n listed rows or
+// wave vectors.
+struct RateErr {
+  const uint8_t* rho = nullptr;   // [nstates][nstates][RhoStride<nbr>] codes
+  double theta = 0.0;
+  int32_t* cnt = nullptr;
+  int32_t* list = nullptr;
+  const int32_t* idx = nullptr;
+  int64_t n = 0;
+};
+
 elph_status make_thermal(elph_ctx ctx, double T, Thermal* th);
 elph_status alloc_thermal(elph_ctx ctx, Thermal* th);
 void fill_thermal(elph_ctx ctx, double T, const Thermal& th, hipStream_t s);
 template <typename ST, int NV>
-void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x, double* acc);
+void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x, double* acc,
+                     const RateErr* err = nullptr);
 void free_thermal(elph_ctx ctx, Thermal* th);
 elph_status ensure_store(elph_ctx ctx);
 // pair lists by q used by the q-gathers (built once per table build)
@@ -28,7 +43,29 @@ elph_status ensure_pairs(elph_ctx ctx);
 elph_status rates_from_store(elph_ctx ctx, const Thermal& th, double* we, double* wph);
 // W_e[i] = sum_{j,s} (B+ n + B- (1 + n)) (1 - f_j) / (1 - f_i) from a finished store
 template <typename ST>
-void launch_we_rows(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc, double* we);
+void launch_we_rows(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc, double* we,
+                    const RateErr* err = nullptr);
+
+// FP64 refinement of ill-conditioned vertices in the GEMM forms (refine.hip)
+bool refine_applicable(elph_ctx ctx);
+// error-estimate buffers for the next vertex store (d_rho, d_b2n)
+elph_status refine_prepare(elph_ctx ctx);
+// sum_Rp w_p^2 |B2|^2 of states [i0, i0 + ni) from the step-1 GEMM rows C1
+void refine_b2_norms(elph_ctx ctx, int64_t i0, int64_t ni, const float* C1);
+// contraction error units of the context's form: relative to the
+// root-sum-square of a component's products (coherent = false) or to the
+// component's magnitude (coherent = true)
+double refine_unit(elph_ctx ctx, bool coherent);
+// After the rate reductions at a temperature flagged rows / modes (err_e,
+// err_ph): recompute their dominant terms in FP64, update the store and the
+// codes, recompute the affected W_e rows and phonon accumulators.
+elph_status refine_terms(elph_ctx ctx, const Thermal& th, double* we, double* acc, const RateErr& err_e,
+                         const RateErr& err_ph, int32_t* cnt);
+// FP64 operands of the refinement (vertex.hip): the permuted vertex and
+// step-1 rows B2[(s, x)][(Rp, n')] of listed states
+elph_status ensure_gR64(elph_ctx ctx);
+elph_status step1_fp64_rows(elph_ctx ctx, int64_t ns, const int32_t* st_kidx, const int32_t* st_m, double* Ae64,
+                            double* B2_64);
 elph_status x_from_store(elph_ctx ctx, const Thermal& th, double* Xp, double* Xm);
 elph_status finalize_wph(elph_ctx ctx, const Thermal& th, double* acc, double* wph);
 elph_status interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx, double* g_out);

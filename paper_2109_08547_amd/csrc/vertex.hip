@@ -497,6 +497,15 @@ struct EpiParams {
   const cd* fr;              // [nk][nbr] Froehlich factors F_s(q) of Eq. 7 (null: not polar)
   const cd* ust;             // [nstates][nb] eigenvector of each active state
   int nb;
+  // error estimates of the GEMM forms (null: none): per stored term the
+  // log-coded relative error of |g|^2 from the contraction's error units:
+  // cu times the root-sum-square of its products (b2n: its expected square,
+  // per initial state and branch row x) and cv times the magnitude of the
+  // component itself (rounding of partial sums that grow with it when the
+  // products add coherently, as at q near Gamma)
+  uint8_t* rho;              // [nstates][nstates][RhoStride<nbr>]
+  const float* b2n;          // [nstates][nbr]
+  double cu, cv;
 };
 
 // overlap sum_w conj(U_j[w]) U_i[w] of two active states' eigenvectors (the
@@ -1097,7 +1106,7 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
         const double de = ep.eps[j] - ei;
         const int64_t tb = ((int64_t)i * ep.nstates + j) * NX;
         const cd ov = ep.fr ? state_overlap(ep.ust, ep.nb, i, j) : cmake(0.0, 0.0);
-        double bpv[NX], bmv[NX];
+        double bpv[NX], bmv[NX], g2v[NX];
 #pragma unroll
         for (int s = 0; s < NX; ++s) {
           double gr = 0.0, gi = 0.0;
@@ -1126,9 +1135,38 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
           }
           bpv[s] = bp;
           bmv[s] = bm;
+          g2v[s] = g2;
         }
         store_row<ST, NX>(Bp + tb, bpv);
         store_row<ST, NX>(Bm + tb, bmv);
+        if (ep.rho) {
+          // b2n[i][x]: the expected square root-sum-square of the products
+          // behind gh_x; a vertex component carries an error of about
+          // cu rss[x] + cv |gh_x|, the projection sum_x l u gh_x the
+          // root-sum-square of those weighted by |l u|
+          const float* __restrict__ bn = ep.b2n + (int64_t)i * NX;
+          const float cu2 = (float)(ep.cu * ep.cu), cv2 = (float)(ep.cv * ep.cv);
+          float e2[NX];
+#pragma unroll
+          for (int x = 0; x < NX; ++x) e2[x] = cu2 * bn[x] + cv2 * (float)(ar[x] * ar[x] + ai[x] * ai[x]);
+          constexpr int RS = RhoStride<NX>::value;
+          uint32_t w[RS / 4];
+#pragma unroll
+          for (int t = 0; t < RS / 4; ++t) w[t] = 0u;
+#pragma unroll
+          for (int s = 0; s < NX; ++s) {
+            float d2 = 0.f;
+#pragma unroll
+            for (int x = 0; x < NX; ++x) d2 += (float)cabs2(L[x * NX + s]) * e2[x];
+            w[s >> 2] |= rho_encode(d2, (float)g2v[s]) << (8 * (s & 3));
+          }
+          uint8_t* __restrict__ rp = ep.rho + ((int64_t)i * ep.nstates + j) * RS;
+          if constexpr (RS == 8) {
+            *reinterpret_cast<uint2*>(rp) = make_uint2(w[0], w[1]);
+          } else {
+            *reinterpret_cast<uint4*>(rp) = make_uint4(w[0], w[1], w[2], w[3]);
+          }
+        }
       }
     }
   }
@@ -1339,7 +1377,7 @@ struct UsesGemm {
 };
 
 template <typename T>
-static elph_status launch_step1_t(elph_ctx ctx) {
+static elph_status launch_step1_t(elph_ctx ctx, bool norms = false) {
   const S1Desc<T> d = step1_desc<T>(ctx);
   if constexpr (UsesGemm<T>::value) {
     // GEMM into FP32 rows (chunks <= 2 GiB), then the phase epilogue that
@@ -1358,6 +1396,7 @@ static elph_status launch_step1_t(elph_ctx ctx) {
     for (int64_t i0 = 0; i0 < M; i0 += ci) {
       const int64_t ni = (M - i0 < ci) ? M - i0 : ci;
       launch_cgemm<OP, 1>(ctx->stream, i0, ni, ncol, ctx->ke, 1, ctx->d_Ae, ctx->d_gR, (float*)p, ncol);
+      if (norms) refine_b2_norms(ctx, i0, ni, (const float*)p);
       hipLaunchKernelGGL(k_step1_epi<T>, dim3(blocks_for(ni * ncol, 256)), dim3(256), 0, ctx->stream, i0, ni, ncol,
                          ctx->nrp, ctx->nb, ctx->nbr, ctx->kp, (const float*)p, ctx->d_state_kidx,
                          (const cd*)ctx->d_Ep, ctx->sc_b2 / (ctx->sc_ae * ctx->sc_g),
@@ -1485,6 +1524,9 @@ static EpiParams epi_params(elph_ctx ctx) {
   ep.wph_acc = nullptr;
   ep.tile_keep = ctx->d_tile_keep;
   ep.cscale = 1.0 / (ctx->sc_b2 * ctx->sc_ap);
+  ep.rho = nullptr;
+  ep.b2n = nullptr;
+  ep.cu = ep.cv = 0.0;
   return ep;
 }
 
@@ -1715,6 +1757,17 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
   elph_status st = build_operands(ctx);
   if (st != ELPH_OK) return st;
   EpiParams ep = epi_params(ctx);
+  // GEMM forms writing the context's store keep an error estimate per term
+  if (Bp == ctx->d_Bp) ctx->rho_valid = false;
+  const bool want_rho = !store_f64 && Bp == ctx->d_Bp && refine_applicable(ctx);
+  if (want_rho) {
+    st = refine_prepare(ctx);
+    if (st != ELPH_OK) return st;
+    ep.rho = ctx->d_rho;
+    ep.b2n = ctx->d_b2n;
+    ep.cu = refine_unit(ctx, false);
+    ep.cv = refine_unit(ctx, true);
+  }
   int64_t we_tiles = ctx->m_pad / 32;
   if (th) {
     st = ensure_we_part(ctx);
@@ -1738,7 +1791,7 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     mark(ctx, 5);
   } else if (ctx->precision == ELPH_FP32) {
     mark(ctx, 2);
-    st = launch_step1_t<float>(ctx);
+    st = launch_step1_t<float>(ctx, want_rho);
     if (st != ELPH_OK) return st;
     mark(ctx, 3);
     mark(ctx, 4);
@@ -1746,7 +1799,7 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     if (ep.tile_keep) mark(ctx, 5);  // the GEMM path marks its own window (the contraction)
   } else if (ctx->precision == ELPH_FP16X3) {
     mark(ctx, 2);
-    st = launch_step1_t<F16S<2>>(ctx);
+    st = launch_step1_t<F16S<2>>(ctx, want_rho);
     if (st != ELPH_OK) return st;
     mark(ctx, 3);
     mark(ctx, 4);
@@ -1755,7 +1808,7 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     if (ep.tile_keep) mark(ctx, 5);
   } else if (ctx->precision == ELPH_BF16X3) {
     mark(ctx, 2);
-    st = launch_step1_t<Bf16S<2>>(ctx);
+    st = launch_step1_t<Bf16S<2>>(ctx, want_rho);
     if (st != ELPH_OK) return st;
     mark(ctx, 3);
     mark(ctx, 4);
@@ -1764,7 +1817,7 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     if (ep.tile_keep) mark(ctx, 5);
   } else {
     mark(ctx, 2);
-    st = launch_step1_t<Bf16S<3>>(ctx);
+    st = launch_step1_t<Bf16S<3>>(ctx, want_rho);
     if (st != ELPH_OK) return st;
     mark(ctx, 3);
     mark(ctx, 4);
@@ -1794,6 +1847,54 @@ elph_status run_vertex(elph_ctx ctx, void* Bp, void* Bm, bool store_f64, const T
     ctx->hip_dead = true;
     return ELPH_EHIP;
   }
+  if (want_rho) ctx->rho_valid = true;
+  return ELPH_OK;
+}
+
+// FP64 vertex operand of the refinement, gR[(x, Rp, n')][(Re, m')]
+elph_status ensure_gR64(elph_ctx ctx) {
+  if (ctx->d_gR64) return ELPH_OK;
+  const int nb = ctx->nb, nbr = ctx->nbr;
+  ctx->ke64 = ((int64_t)ctx->nre * nb + 15) / 16 * 16;
+  ctx->kp64 = ((int64_t)ctx->nrp * nb + 15) / 16 * 16;
+  const int64_t ncol = (int64_t)nbr * ctx->nrp * nb;
+  const size_t bytes = (size_t)ncol * ctx->ke64 * 16;
+  ALLOC(ctx->d_gR64, bytes);
+  HIPCHK(hipMemsetAsync(ctx->d_gR64, 0, bytes, ctx->stream));
+  const int64_t gtotal = (int64_t)ctx->nre * ctx->nrp * nbr * nb * nb;
+  hipLaunchKernelGGL(k_permute_g<double>, dim3(blocks_for(gtotal, 256)), dim3(256), 0, ctx->stream, ctx->nre,
+                     ctx->nrp, nbr, nb, ctx->ke64, ctx->d_gr, 1.0, ctx->d_gR64);
+  HIPCHK(hipGetLastError());
+  return ELPH_OK;
+}
+
+// FP64 step-1 rows B2[(s, x)][(Rp, n')] (row stride kp64) of ns listed
+// states, given their kept index and band; Ae64 holds ceil(ns/64)*64 rows of
+// ke64 complex values, B2_64 that many times nbr rows of kp64
+elph_status step1_fp64_rows(elph_ctx ctx, int64_t ns, const int32_t* st_kidx, const int32_t* st_m, double* Ae64,
+                            double* B2_64) {
+  const int nb = ctx->nb;
+  const int64_t ns_pad = (ns + 63) / 64 * 64;
+  HIPCHK(hipMemsetAsync(Ae64, 0, (size_t)ns_pad * ctx->ke64 * 16, ctx->stream));
+  hipLaunchKernelGGL(k_build_Ae<double>, dim3(blocks_for(ns * ctx->nre * nb, 256)), dim3(256), 0, ctx->stream, ns,
+                     nb, ctx->nre, ctx->ke64, st_kidx, st_m, (const cd*)ctx->d_Ee, (const cd*)ctx->d_U, 1.0, Ae64);
+  S1Desc<double> d;
+  d.m_pad = ns_pad;
+  d.ncol = (int64_t)ctx->nbr * ctx->nrp * nb;
+  d.ke = ctx->ke64;
+  d.kp = ctx->kp64;
+  d.nstates = ns;
+  d.Ae = Ae64;
+  d.gR = ctx->d_gR64;
+  d.B2 = B2_64;
+  d.nrp = ctx->nrp;
+  d.nb = nb;
+  d.nbr = ctx->nbr;
+  d.st_kidx = st_kidx;
+  d.Ep = (const cd*)ctx->d_Ep;
+  dim3 grid((unsigned)((d.ncol + 63) / 64), (unsigned)(ns_pad / 64));
+  hipLaunchKernelGGL(k_step1<double>, grid, dim3(256), 0, ctx->stream, d);
+  HIPCHK(hipGetLastError());
   return ELPH_OK;
 }
 
@@ -1915,6 +2016,7 @@ static elph_status batch_prepare_t(BatchImpl* b) {
       }
     }
     c->store_f32 = sizeof(T) == 4;
+    c->rho_valid = false;  // batched launches keep the plain form: no error estimates
     Thermal t;
     st = alloc_thermal(c, &t);
     if (st != ELPH_OK) {

@@ -44,7 +44,8 @@ class ElphSizes(ctypes.Structure):
 
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
-           "elph_batch_tune", "elph_tables", "elph_timing_extra",
+           "elph_batch_tune", "elph_tables", "elph_timing_extra", "elph_set_refine", "elph_refine_info",
+           "elph_refine_estimates",
            "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
            "elph_set_ifc3", "elph_phph_vertex", "elph_phph_rates", "elph_phph_inscatter", "elph_set_phph",
            "elph_mlp_create", "elph_mlp_destroy", "elph_mlp_last_error", "elph_mlp_nparams",
@@ -76,6 +77,9 @@ def load():
     lib.elph_reset.argtypes = [vp, ctypes.c_int32]
     lib.elph_timing.argtypes = [vp, ctypes.c_int32, vp]
     lib.elph_timing_extra.argtypes = [vp, vp]
+    lib.elph_set_refine.argtypes = [vp, ctypes.c_double]
+    lib.elph_refine_info.argtypes = [vp, vp, vp]
+    lib.elph_refine_estimates.argtypes = [vp, vp]
     lib.elph_sizes.argtypes = [vp, ctypes.POINTER(ElphSizes)]
     lib.elph_tables.argtypes = [vp] * 7
     lib.elph_interp_g.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
@@ -215,6 +219,26 @@ def elph_timing_extra(ctx):
     ms = ctypes.c_double(-1.0)
     _check(ctx, load().elph_timing_extra(ctx.handle, ctypes.byref(ms)))
     return ms.value
+
+
+def elph_set_refine(ctx, theta):
+    _check(ctx, load().elph_set_refine(ctx.handle, float(theta)))
+
+
+def elph_refine_info(ctx):
+    """Counters of the last FP64 refinement and its duration (ms, -1: none)."""
+    st = np.zeros(8, dtype=np.int64)
+    ms = ctypes.c_double(-1.0)
+    _check(ctx, load().elph_refine_info(ctx.handle, st.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ms)))
+    keys = ("rows_flagged", "modes_flagged", "pairs", "states", "qs", "overflow", "rows_unresolved",
+            "modes_unresolved")
+    out = dict(zip(keys, (int(v) for v in st)))
+    out["ms"] = ms.value
+    return out
+
+
+def elph_refine_estimates(ctx, rel_err):
+    _check(ctx, load().elph_refine_estimates(ctx.handle, _ptr(rel_err)))
 
 
 def elph_sizes(ctx):
