@@ -231,6 +231,23 @@ elph_status elph_tables(elph_ctx ctx, int32_t* state_k, int32_t* state_m, double
 elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
                           const int32_t* qidx, double* g_out);
 
+/* elph_interp_g for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, layout and result, but no device allocation, no free and
+ * no synchronisation; the work is queued on the context's stream.  Its work
+ * buffers (phases, H(k), eigenvectors of k, k+q and q, the two Wannier
+ * stages of Eq. 6) live in one static device array of 64 MiB per GPU,
+ * resident until the process ends, and pairs are processed in chunks that
+ * fit it (about 50 pairs per chunk for 8 bands, 2 atoms and 203 R_p; 2 for
+ * 16 bands, 5 atoms and 389 R_p).  Every call on a GPU shares that array:
+ * calls that overlap on one GPU (two streams, two threads) race and must be
+ * serialised by the caller; nothing in it needs to start at zero.  The first
+ * call on a device must have that device current (ESTATE otherwise).
+ * EINVAL when one pair needs more work space than the array holds
+ * (nbr * N_Rp * nb^2 * 16 bytes dominate) or for an invalid pair list. */
+elph_status elph_interp_g_noalloc(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
+                                  const int32_t* qidx, double* g_out);
+
 /* Polar materials.  Eq. 4: the non-analytic dipole-dipole term
  * (e^2 / (eps_0 V)) (q.Z_t)_a (q.Z_t')_b / (q.eps_inf.q) / sqrt(m_t m_t') is
  * added to D(q) (and its gradient to the velocities of Eq. 5), with

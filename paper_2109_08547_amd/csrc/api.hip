@@ -459,6 +459,16 @@ extern "C" elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t
   return interp_g(ctx, npairs, kidx, qidx, g_out);
 }
 
+extern "C" elph_status elph_interp_g_noalloc(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
+                                             const int32_t* qidx, double* g_out) {
+  CHECK_CTX(ctx);
+  if (npairs < 0 || (npairs > 0 && (!kidx || !qidx || !g_out))) {
+    ctx->err = "invalid pair list or output";
+    return ELPH_EINVAL;
+  }
+  return interp_g_noalloc(ctx, npairs, kidx, qidx, g_out);
+}
+
 static elph_status check_T(elph_ctx ctx, double T) {
   if (!(T > 0) || !std::isfinite(T)) {
     ctx->err = "temperature must be positive";

@@ -17,6 +17,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 namespace elph {
@@ -722,75 +725,153 @@ __global__ void k_lq_only(int64_t nq, int nbr, const double* __restrict__ lam, c
   Lq[e] = (w >= omega_min) ? cscale(u[e], sqrt(kPhononC / (2.0 * mass_x[x] * w))) : cmake(0, 0);
 }
 
-elph_status interp_g(elph_ctx ctx, int64_t np, const int32_t* kidx, const int32_t* qidx, double* g_out) {
-  if (np <= 0) return ELPH_OK;
+// Work buffers of Eq. 6 at arbitrary pairs, for a chunk of pairs, carved
+// from one block (each region 256-byte aligned).  Every kernel of a chunk
+// writes what it later reads, so nothing needs to start at zero.
+struct InterpScratch {
+  int32_t* kq = nullptr;
+  cd *H = nullptr, *Uk = nullptr, *Ukq = nullptr, *u = nullptr, *Lq = nullptr, *Fr = nullptr;
+  cd *phe = nullptr, *php = nullptr, *G1 = nullptr, *gW = nullptr;
+  double* lam = nullptr;
+};
+
+// bytes of the work buffers for `chunk` pairs (carve = true: also point S
+// into base)
+static size_t interp_scratch(elph_ctx ctx, int64_t chunk, void* base, InterpScratch* S) {
+  const int nb = ctx->nb, nbr = ctx->nbr;
+  const int64_t nn = (int64_t)nb * nb, mm = (int64_t)nbr * nbr;
+  const int64_t ncol = (int64_t)ctx->nrp * nbr * nn, inner = (int64_t)nbr * nn;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)((char*)base + off) : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  InterpScratch T;
+  T.kq = (int32_t*)take(chunk * sizeof(int32_t));
+  T.H = (cd*)take(chunk * std::max(nn, mm) * sizeof(cd));
+  T.Uk = (cd*)take(chunk * nn * sizeof(cd));
+  T.Ukq = (cd*)take(chunk * nn * sizeof(cd));
+  T.u = (cd*)take(chunk * mm * sizeof(cd));
+  T.Lq = (cd*)take(chunk * mm * sizeof(cd));
+  T.Fr = ctx->frohlich ? (cd*)take(chunk * nbr * sizeof(cd)) : nullptr;
+  T.lam = (double*)take(chunk * nbr * sizeof(double));
+  T.phe = (cd*)take(chunk * ctx->nre * sizeof(cd));
+  T.php = (cd*)take(chunk * ctx->nrp * sizeof(cd));
+  T.G1 = (cd*)take(chunk * ncol * sizeof(cd));
+  T.gW = (cd*)take(chunk * inner * sizeof(cd));
+  if (S) *S = T;
+  return off;
+}
+
+// Eq. 6 for np pairs in chunks through the work buffers S (queued on the
+// context stream, no synchronisation)
+static elph_status interp_run(elph_ctx ctx, int64_t np, const int32_t* kidx, const int32_t* qidx, double* g_out,
+                              const InterpScratch& S, int64_t chunk) {
   hipStream_t s = ctx->stream;
   const int nb = ctx->nb, nbr = ctx->nbr;
   const int64_t nn = (int64_t)nb * nb, mm = (int64_t)nbr * nbr;
   const int64_t ncol = (int64_t)ctx->nrp * nbr * nn;  // per Re row of g
   const int64_t inner = (int64_t)nbr * nn;
-  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(np, (int64_t)(512ll << 20) / (ncol * 16)));
-  int32_t* kq = nullptr;
-  cd *H = nullptr, *Uk = nullptr, *Ukq = nullptr, *u = nullptr, *Lq = nullptr, *phe = nullptr, *php = nullptr,
-     *G1 = nullptr, *gW = nullptr;
-  double* lam = nullptr;
-  ALLOC(kq, chunk * sizeof(int32_t));
-  ALLOC(H, chunk * std::max(nn, mm) * sizeof(cd));
-  ALLOC(Uk, chunk * nn * sizeof(cd));
-  ALLOC(Ukq, chunk * nn * sizeof(cd));
-  ALLOC(u, chunk * mm * sizeof(cd));
-  ALLOC(Lq, chunk * mm * sizeof(cd));
-  cd* Fr = nullptr;
-  if (ctx->frohlich) ALLOC(Fr, chunk * nbr * sizeof(cd));
-  ALLOC(lam, chunk * nbr * sizeof(double));
-  ALLOC(phe, chunk * ctx->nre * sizeof(cd));
-  ALLOC(php, chunk * ctx->nrp * sizeof(cd));
-  ALLOC(G1, chunk * ncol * sizeof(cd));
-  ALLOC(gW, chunk * inner * sizeof(cd));
   const MeshDims md = mdims(ctx);
   for (int64_t p0 = 0; p0 < np; p0 += chunk) {
     const int64_t cnt = std::min(chunk, np - p0);
     const int32_t* kp = kidx + p0;
     const int32_t* qp = qidx + p0;
-    hipLaunchKernelGGL(k_pair_points, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, cnt, kp, qp, md, kq);
-    elph_status st = fourier_points(ctx, false, kp, cnt, H);
+    hipLaunchKernelGGL(k_pair_points, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, cnt, kp, qp, md, S.kq);
+    elph_status st = fourier_points(ctx, false, kp, cnt, S.H);
     if (st != ELPH_OK) return st;
-    launch_jacobi(H, cnt, nb, nullptr, Uk, s);
-    st = fourier_points(ctx, false, kq, cnt, H);
+    launch_jacobi(S.H, cnt, nb, nullptr, S.Uk, s);
+    st = fourier_points(ctx, false, S.kq, cnt, S.H);
     if (st != ELPH_OK) return st;
-    launch_jacobi(H, cnt, nb, nullptr, Ukq, s);
-    st = fourier_points(ctx, true, qp, cnt, H);
+    launch_jacobi(S.H, cnt, nb, nullptr, S.Ukq, s);
+    st = fourier_points(ctx, true, qp, cnt, S.H);
     if (st != ELPH_OK) return st;
-    launch_jacobi(H, cnt, nbr, lam, u, s);
-    hipLaunchKernelGGL(k_lq_only, dim3(blocks_for(cnt * mm, 256)), dim3(256), 0, s, cnt, nbr, lam, u,
-                       ctx->d_mass_x, ctx->omega_min, Lq);
+    launch_jacobi(S.H, cnt, nbr, S.lam, S.u, s);
+    hipLaunchKernelGGL(k_lq_only, dim3(blocks_for(cnt * mm, 256)), dim3(256), 0, s, cnt, nbr, S.lam, S.u,
+                       ctx->d_mass_x, ctx->omega_min, S.Lq);
     hipLaunchKernelGGL(k_pair_phases, dim3(blocks_for(cnt * ctx->nre, 256)), dim3(256), 0, s, cnt, kp, md,
-                       ctx->d_tab[0], ctx->d_tab[1], ctx->d_tab[2], ctx->d_re, ctx->d_wre, ctx->nre, phe);
+                       ctx->d_tab[0], ctx->d_tab[1], ctx->d_tab[2], ctx->d_re, ctx->d_wre, ctx->nre, S.phe);
     hipLaunchKernelGGL(k_pair_phases, dim3(blocks_for(cnt * ctx->nrp, 256)), dim3(256), 0, s, cnt, qp, md,
-                       ctx->d_tab[0], ctx->d_tab[1], ctx->d_tab[2], ctx->d_rp, ctx->d_wrp, ctx->nrp, php);
+                       ctx->d_tab[0], ctx->d_tab[1], ctx->d_tab[2], ctx->d_rp, ctx->d_wrp, ctx->nrp, S.php);
     hipLaunchKernelGGL(k_interp_stage1, dim3(blocks_for(ncol, 256), (unsigned)((cnt + 7) / 8)), dim3(256), 0, s,
-                       cnt, ctx->nre, ncol, phe, (const cd*)ctx->d_gr, G1);
+                       cnt, ctx->nre, ncol, S.phe, (const cd*)ctx->d_gr, S.G1);
     hipLaunchKernelGGL(k_interp_stage2, dim3(blocks_for(cnt * inner, 256)), dim3(256), 0, s, cnt, ctx->nrp, inner,
-                       php, G1, gW);
-    if (Fr) launch_frohlich(ctx, qp, cnt, Lq, Fr, s);
-    hipLaunchKernelGGL(k_interp_stage3, dim3(blocks_for(cnt * inner, 256)), dim3(256), 0, s, cnt, nb, nbr, gW, Uk,
-                       Ukq, Lq, (const cd*)Fr, (cd*)g_out + p0 * inner);
+                       S.php, S.G1, S.gW);
+    if (S.Fr) launch_frohlich(ctx, qp, cnt, S.Lq, S.Fr, s);
+    hipLaunchKernelGGL(k_interp_stage3, dim3(blocks_for(cnt * inner, 256)), dim3(256), 0, s, cnt, nb, nbr, S.gW,
+                       S.Uk, S.Ukq, S.Lq, (const cd*)S.Fr, (cd*)g_out + p0 * inner);
     HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipStreamSynchronize(s));
-  dev_free(ctx, kq);
-  dev_free(ctx, H);
-  dev_free(ctx, Uk);
-  dev_free(ctx, Ukq);
-  dev_free(ctx, u);
-  dev_free(ctx, Lq);
-  if (Fr) dev_free(ctx, Fr);
-  dev_free(ctx, lam);
-  dev_free(ctx, phe);
-  dev_free(ctx, php);
-  dev_free(ctx, G1);
-  dev_free(ctx, gW);
   return ELPH_OK;
+}
+
+elph_status interp_g(elph_ctx ctx, int64_t np, const int32_t* kidx, const int32_t* qidx, double* g_out) {
+  if (np <= 0) return ELPH_OK;
+  const int64_t ncol = (int64_t)ctx->nrp * ctx->nbr * ctx->nb * ctx->nb;
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(np, (int64_t)(512ll << 20) / (ncol * 16)));
+  void* base = nullptr;
+  ALLOC(base, interp_scratch(ctx, chunk, nullptr, nullptr));
+  InterpScratch S;
+  interp_scratch(ctx, chunk, base, &S);
+  elph_status st = interp_run(ctx, np, kidx, qidx, g_out, S, chunk);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  dev_free(ctx, base);
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 6 at arbitrary pairs without allocation: the work buffers live in a
+// static device array (each GPU the library runs on holds its own copy until
+// the process ends); host code reaches it only through the address
+// hipGetSymbolAddress returns on that device.
+
+static __device__ __align__(256) unsigned char scratch[kInterpScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;  // device -> address of its copy of the array
+
+static elph_status scratch_address(elph_ctx ctx, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(ctx->device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return ELPH_OK;
+  }
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
+    ctx->err = "the context's device must be current for its first allocation-free call";
+    return ELPH_ESTATE;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    ctx->err = std::string("hipGetSymbolAddress of the static work array failed: ") + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return ELPH_EHIP;
+  }
+  g_scratch_ptr[ctx->device] = p;
+  *out = p;
+  return ELPH_OK;
+}
+
+elph_status interp_g_noalloc(elph_ctx ctx, int64_t np, const int32_t* kidx, const int32_t* qidx, double* g_out) {
+  const size_t per_pair = interp_scratch(ctx, 1, nullptr, nullptr);
+  if (per_pair > kInterpScratchBytes) {
+    ctx->err = "one pair needs " + std::to_string(per_pair) + " bytes of work space, more than the " +
+               std::to_string((size_t)kInterpScratchBytes) + " bytes of the static array";
+    return ELPH_EINVAL;
+  }
+  void* base = nullptr;
+  elph_status st = scratch_address(ctx, &base);
+  if (st != ELPH_OK) return st;
+  if (np <= 0) return ELPH_OK;
+  // largest chunk whose buffers fit the array
+  int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(np, (int64_t)(kInterpScratchBytes / per_pair)));
+  while (chunk > 1 && interp_scratch(ctx, chunk, nullptr, nullptr) > kInterpScratchBytes) --chunk;
+  InterpScratch S;
+  interp_scratch(ctx, chunk, base, &S);
+  return interp_run(ctx, np, kidx, qidx, g_out, S, chunk);
 }
 
 // ---------------------------------------------------------------------------

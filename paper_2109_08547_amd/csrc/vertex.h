@@ -69,6 +69,9 @@ elph_status step1_fp64_rows(elph_ctx ctx, int64_t ns, const int32_t* st_kidx, co
 elph_status x_from_store(elph_ctx ctx, const Thermal& th, double* Xp, double* Xm);
 elph_status finalize_wph(elph_ctx ctx, const Thermal& th, double* acc, double* wph);
 elph_status interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx, double* g_out);
+// the same through the static work array (no device allocation)
+constexpr size_t kInterpScratchBytes = (size_t)64 << 20;
+elph_status interp_g_noalloc(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx, double* g_out);
 elph_status iterate(elph_ctx ctx, double T, const double* wext, int level, double tol, int maxit, double* I,
                     double* J, double* F, double* G, double* tensors, int* iters, double* ko);
 // three-phonon processes (Eqs. 13, 14, 26)

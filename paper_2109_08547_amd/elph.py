@@ -46,7 +46,7 @@ EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
            "elph_batch_tune", "elph_tables", "elph_timing_extra", "elph_set_refine", "elph_refine_info",
            "elph_refine_estimates",
-           "elph_interp_g", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
+           "elph_interp_g", "elph_interp_g_noalloc", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
            "elph_set_ifc3", "elph_phph_vertex", "elph_phph_rates", "elph_phph_inscatter", "elph_set_phph",
            "elph_mlp_create", "elph_mlp_destroy", "elph_mlp_last_error", "elph_mlp_nparams",
            "elph_mlp_get_params", "elph_mlp_set_params", "elph_mlp_forward", "elph_mlp_gradients",
@@ -83,6 +83,7 @@ def load():
     lib.elph_sizes.argtypes = [vp, ctypes.POINTER(ElphSizes)]
     lib.elph_tables.argtypes = [vp] * 7
     lib.elph_interp_g.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
+    lib.elph_interp_g_noalloc.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
     lib.elph_transition_probs.argtypes = [vp, ctypes.c_double, vp, vp, ctypes.c_int32]
     lib.elph_scatt_rates.argtypes = [vp, ctypes.c_double, vp, vp]
     lib.elph_iterate.argtypes = [vp, ctypes.c_double, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
@@ -255,6 +256,11 @@ def elph_tables(ctx, state_k=None, state_m=None, eps=None, vel=None, hw=None, vp
 def elph_interp_g(ctx, kidx, qidx, g_out):
     n = int(kidx.numel())
     _check(ctx, load().elph_interp_g(ctx.handle, n, _ptr(kidx), _ptr(qidx), _ptr(g_out)))
+
+
+def elph_interp_g_noalloc(ctx, kidx, qidx, g_out):
+    n = int(kidx.numel())
+    _check(ctx, load().elph_interp_g_noalloc(ctx.handle, n, _ptr(kidx), _ptr(qidx), _ptr(g_out)))
 
 
 def elph_transition_probs(ctx, T, Xp=None, Xm=None, store_B=False):
