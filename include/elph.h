@@ -176,6 +176,40 @@ elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms);
  * the stream. */
 elph_status elph_timing_extra(elph_ctx ctx, double* ms);
 
+/* Save the context's temperature-independent state to a file: its tables
+ * (active states, energies, velocities, phonon energies and velocities,
+ * eigenvectors of the kept k) and its vertex store B+/- of Eq. 8 with the
+ * error codes of the GEMM forms, so that temperature and carrier sweeps can
+ * resume without recomputing the vertices (the workflow section stores
+ * vertices and rates for reuse).  The file also holds the sizes, parameters
+ * and a hash of the inputs, and a checksum.  ESTATE without a vertex store,
+ * EINVAL when the file cannot be written.  Synchronises the stream. */
+elph_status elph_save(elph_ctx ctx, const char* path);
+
+/* Restore a state saved by elph_save into a context created from the same
+ * inputs and parameters (same sizes, mesh, mu, window, sigma, omega_min,
+ * precision form, delta method and polar terms, checked against the file):
+ * the tables are rebuilt and must equal the saved ones bit for bit, then the
+ * vertex store and its codes are taken from the file and the cached rates
+ * are dropped; later calls give bitwise the results an uninterrupted context
+ * would.  EINVAL for a missing, truncated or corrupt file, another material
+ * or parameters, or tables that differ (another library version or device);
+ * the store is then left invalid.  Synchronises the stream. */
+elph_status elph_load(elph_ctx ctx, const char* path);
+
+/* Device-memory budget of the context in bytes (inputs, tables, operands,
+ * vertex store, work buffers and released blocks kept for reuse; 0 = none,
+ * the default).  Setting a budget first returns the released blocks to the
+ * device.  An allocation beyond it fails like an exhausted device:
+ * the call returns ELPH_ENOMEM, and after every ELPH_ENOMEM the context
+ * releases its derived tables, operands, store and work buffers (the inputs
+ * stay) and remains usable (a batch built over it must be created again).
+ * EINVAL for a negative budget. */
+elph_status elph_set_memory_limit(elph_ctx ctx, int64_t bytes);
+
+/* Bytes of device memory the context holds (live and kept for reuse). */
+elph_status elph_memory_held(elph_ctx ctx, int64_t* bytes);
+
 /* FP64 refinement of ill-conditioned vertices in the GEMM forms (FP32 and
  * the BF16 / FP16 splits; Eq. 6 evaluated as FP32-accumulated MFMA sums).
  * A vertex component is a sum of N_Rp * nb products accumulated with an

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libelph.so")
-SOURCES = ["api.hip", "tables.hip", "vertex.hip", "rates.hip", "solve.hip", "mlp.hip", "screen.hip", "phph.hip", "refine.hip"]
+SOURCES = ["api.hip", "tables.hip", "vertex.hip", "rates.hip", "solve.hip", "mlp.hip", "screen.hip", "phph.hip", "refine.hip", "io.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

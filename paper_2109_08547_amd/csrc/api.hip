@@ -16,6 +16,13 @@ using namespace elph;
 
 namespace elph {
 
+static size_t held_bytes(elph_ctx ctx) {
+  size_t t = 0;
+  for (auto& b : ctx->allocs) t += b.second;
+  for (auto& b : ctx->pool) t += b.second;
+  return t;
+}
+
 hipError_t dev_alloc(elph_ctx ctx, void** p, size_t bytes) {
   *p = nullptr;
   const size_t n = bytes > 0 ? bytes : 1;
@@ -26,6 +33,10 @@ hipError_t dev_alloc(elph_ctx ctx, void** p, size_t bytes) {
       ctx->allocs.push_back({*p, n});
       return hipSuccess;
     }
+  if (ctx->mem_limit > 0 && held_bytes(ctx) + n > ctx->mem_limit) {
+    pool_trim(ctx);
+    if (held_bytes(ctx) + n > ctx->mem_limit) return hipErrorOutOfMemory;  // the context's budget
+  }
   hipError_t e = hipMalloc(p, n);
   if (e != hipSuccess) {
     // give the pool back to the device and try once more
@@ -56,6 +67,35 @@ void pool_trim(elph_ctx ctx) {
 
 }  // namespace elph
 
+static void drop_derived(elph_ctx ctx);
+
+namespace elph {
+
+void recover_after_enomem(elph_ctx ctx) {
+  if (ctx->hip_dead) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  drop_derived(ctx);
+  ctx->d_gR64 = nullptr;
+  // the inputs (and what is built from them alone at create or by the
+  // set_* calls) stay; every other live block, including the work buffers
+  // of the failed call, is freed
+  const void* keep[] = {ctx->d_re,     ctx->d_rp,     ctx->d_wre,    ctx->d_wrp,    ctx->d_hr,     ctx->d_dr,
+                        ctx->d_gr,     ctx->d_mass_x, ctx->d_lat,    ctx->d_nac,    ctx->d_tab[0], ctx->d_tab[1],
+                        ctx->d_tab[2], ctx->d_qrep,   ctx->d_i3_rj,  ctx->d_i3_off, ctx->d_i3_rk,  ctx->d_i3_psi};
+  std::vector<std::pair<void*, size_t>> live;
+  for (auto& b : ctx->allocs) {
+    bool k = false;
+    for (const void* q : keep) k |= (q && q == b.first);
+    if (k) live.push_back(b);
+    else (void)hipFree(b.first);
+  }
+  ctx->allocs.swap(live);
+  pool_trim(ctx);
+  (void)hipGetLastError();
+}
+
+}  // namespace elph
+
 static thread_local std::string g_create_err;
 
 #define CHECK_CTX(ctx)                                          \
@@ -68,6 +108,18 @@ static thread_local std::string g_create_err;
     (ctx)->err.clear();                                         \
   } while (0)
 
+
+// A failed device allocation leaves the context usable: its derived tables,
+// operands, store and work buffers are released (the inputs stay) and the
+// next call starts over.
+static elph_status enomem_guard(elph_ctx ctx, elph_status st) {
+  if (st == ELPH_ENOMEM && ctx) {
+    const std::string e = ctx->err;
+    recover_after_enomem(ctx);
+    ctx->err = e + "; the context released its derived tables and vertex store";
+  }
+  return st;
+}
 
 static bool all_finite(const double* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
@@ -279,6 +331,37 @@ extern "C" elph_status elph_timing(elph_ctx ctx, int32_t enable, double* ms) {
   return ELPH_OK;
 }
 
+extern "C" elph_status elph_save(elph_ctx ctx, const char* path) {
+  CHECK_CTX(ctx);
+  return enomem_guard(ctx, save_state(ctx, path));
+}
+
+extern "C" elph_status elph_load(elph_ctx ctx, const char* path) {
+  CHECK_CTX(ctx);
+  return enomem_guard(ctx, load_state(ctx, path));
+}
+
+extern "C" elph_status elph_set_memory_limit(elph_ctx ctx, int64_t bytes) {
+  CHECK_CTX(ctx);
+  if (bytes < 0) {
+    ctx->err = "memory limit must be >= 0";
+    return ELPH_EINVAL;
+  }
+  ctx->mem_limit = (size_t)bytes;
+  if (ctx->mem_limit > 0) pool_trim(ctx);  // the budget starts from the live blocks
+  return ELPH_OK;
+}
+
+extern "C" elph_status elph_memory_held(elph_ctx ctx, int64_t* bytes) {
+  CHECK_CTX(ctx);
+  if (!bytes) {
+    ctx->err = "null output";
+    return ELPH_EINVAL;
+  }
+  *bytes = (int64_t)held_bytes(ctx);
+  return ELPH_OK;
+}
+
 extern "C" elph_status elph_set_refine(elph_ctx ctx, double theta) {
   CHECK_CTX(ctx);
   if (!(theta >= 0.0) || !std::isfinite(theta)) {
@@ -412,7 +495,7 @@ extern "C" elph_status elph_reset(elph_ctx ctx, int32_t what) {
   return ELPH_OK;
 }
 
-extern "C" elph_status elph_sizes(elph_ctx ctx, elph_sizes_t* out) {
+static elph_status sizes_impl(elph_ctx ctx, elph_sizes_t* out) {
   CHECK_CTX(ctx);
   if (!out) {
     ctx->err = "null output";
@@ -433,8 +516,12 @@ extern "C" elph_status elph_sizes(elph_ctx ctx, elph_sizes_t* out) {
   return ELPH_OK;
 }
 
-extern "C" elph_status elph_tables(elph_ctx ctx, int32_t* state_k, int32_t* state_m, double* eps, double* vel,
-                                   double* hw, double* vph) {
+extern "C" elph_status elph_sizes(elph_ctx ctx, elph_sizes_t* out) {
+  return enomem_guard(ctx, sizes_impl(ctx, out));
+}
+
+static elph_status tables_impl(elph_ctx ctx, int32_t* state_k, int32_t* state_m, double* eps, double* vel,
+                               double* hw, double* vph) {
   CHECK_CTX(ctx);
   elph_status st = build_tables(ctx);
   if (st != ELPH_OK) return st;
@@ -449,14 +536,24 @@ extern "C" elph_status elph_tables(elph_ctx ctx, int32_t* state_k, int32_t* stat
   return ELPH_OK;
 }
 
-extern "C" elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx,
-                                     double* g_out) {
+extern "C" elph_status elph_tables(elph_ctx ctx, int32_t* state_k, int32_t* state_m, double* eps, double* vel,
+                                   double* hw, double* vph) {
+  return enomem_guard(ctx, tables_impl(ctx, state_k, state_m, eps, vel, hw, vph));
+}
+
+static elph_status interp_g_impl(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx,
+                                 double* g_out) {
   CHECK_CTX(ctx);
   if (npairs < 0 || (npairs > 0 && (!kidx || !qidx || !g_out))) {
     ctx->err = "invalid pair list or output";
     return ELPH_EINVAL;
   }
   return interp_g(ctx, npairs, kidx, qidx, g_out);
+}
+
+extern "C" elph_status elph_interp_g(elph_ctx ctx, int64_t npairs, const int32_t* kidx, const int32_t* qidx,
+                                     double* g_out) {
+  return enomem_guard(ctx, interp_g_impl(ctx, npairs, kidx, qidx, g_out));
 }
 
 extern "C" elph_status elph_interp_g_noalloc(elph_ctx ctx, int64_t npairs, const int32_t* kidx,
@@ -507,17 +604,26 @@ extern "C" elph_status elph_set_ifc3(elph_ctx ctx, int32_t n, const int32_t* rj,
   return elph::phph_set_ifc3(ctx, n, rj, rk, psi);
 }
 
-extern "C" elph_status elph_phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, const int32_t* qp,
-                                        double* V2) {
+static elph_status phph_vertex_impl(elph_ctx ctx, int64_t npairs, const int32_t* q, const int32_t* qp,
+                                    double* V2) {
   CHECK_CTX(ctx);
   return elph::phph_vertex(ctx, npairs, q, qp, V2);
 }
 
-extern "C" elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W_ph) {
+extern "C" elph_status elph_phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, const int32_t* qp,
+                                        double* V2) {
+  return enomem_guard(ctx, phph_vertex_impl(ctx, npairs, q, qp, V2));
+}
+
+static elph_status phph_rates_impl(elph_ctx ctx, double T_K, double sigma_eV, double* W_ph) {
   CHECK_CTX(ctx);
   elph_status st = check_T(ctx, T_K);
   if (st != ELPH_OK) return st;
   return elph::phph_rates(ctx, T_K, sigma_eV, W_ph);
+}
+
+extern "C" elph_status elph_phph_rates(elph_ctx ctx, double T_K, double sigma_eV, double* W_ph) {
+  return enomem_guard(ctx, phph_rates_impl(ctx, T_K, sigma_eV, W_ph));
 }
 
 extern "C" elph_status elph_set_phph(elph_ctx ctx, double sigma_eV) {
@@ -530,12 +636,17 @@ extern "C" elph_status elph_set_phph(elph_ctx ctx, double sigma_eV) {
   return ELPH_OK;
 }
 
-extern "C" elph_status elph_phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F,
-                                           double* S) {
+static elph_status phph_inscatter_impl(elph_ctx ctx, double T_K, double sigma_eV, const double* F,
+                                       double* S) {
   CHECK_CTX(ctx);
   elph_status st = check_T(ctx, T_K);
   if (st != ELPH_OK) return st;
   return elph::phph_inscatter(ctx, T_K, sigma_eV, F, S);
+}
+
+extern "C" elph_status elph_phph_inscatter(elph_ctx ctx, double T_K, double sigma_eV, const double* F,
+                                           double* S) {
+  return enomem_guard(ctx, phph_inscatter_impl(ctx, T_K, sigma_eV, F, S));
 }
 
 extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const double* eps_inf, const double* tau) {
@@ -643,7 +754,7 @@ extern "C" elph_status elph_set_delta(elph_ctx ctx, int32_t method) {
   return ELPH_OK;
 }
 
-extern "C" elph_status elph_transition_probs(elph_ctx ctx, double T_K, double* Xp, double* Xm, int32_t store_B) {
+static elph_status transition_probs_impl(elph_ctx ctx, double T_K, double* Xp, double* Xm, int32_t store_B) {
   CHECK_CTX(ctx);
   elph_status st = check_T(ctx, T_K);
   if (st != ELPH_OK) return st;
@@ -687,7 +798,11 @@ extern "C" elph_status elph_transition_probs(elph_ctx ctx, double T_K, double* X
   return st;
 }
 
-extern "C" elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, double* W_ph) {
+extern "C" elph_status elph_transition_probs(elph_ctx ctx, double T_K, double* Xp, double* Xm, int32_t store_B) {
+  return enomem_guard(ctx, transition_probs_impl(ctx, T_K, Xp, Xm, store_B));
+}
+
+static elph_status scatt_rates_impl(elph_ctx ctx, double T_K, double* W_e, double* W_ph) {
   CHECK_CTX(ctx);
   elph_status st = check_T(ctx, T_K);
   if (st != ELPH_OK) return st;
@@ -696,37 +811,31 @@ extern "C" elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, d
   Thermal th;
   st = make_thermal(ctx, T_K, &th);
   if (st != ELPH_OK) return st;
-  if (ctx->store_ready) {
-    st = rates_from_store(ctx, th, W_e, W_ph);
-  } else {
-    // vertices, store and the electron rates in one pass; phonon rates by a
-    // q-gather over the fresh store
+  if (!ctx->store_ready) {
+    // the vertices into the store; every rate is then reduced from the
+    // store (one definition of each rate: a later evaluation from the same
+    // store, or from a saved one, gives the same bits), after the FP64
+    // refinement of the terms whose error estimate a rate cannot absorb in
+    // the GEMM forms
     const bool f64 = ctx->precision == ELPH_FP64;
     const size_t n = (size_t)ctx->nstates * ctx->nstates * ctx->nbr;
-    void* we = nullptr;
-    if ((!ctx->d_Bp && (dev_alloc(ctx, &ctx->d_Bp, n * (f64 ? 8 : 4)) != hipSuccess ||
-                        dev_alloc(ctx, &ctx->d_Bm, n * (f64 ? 8 : 4)) != hipSuccess)) ||
-        dev_alloc(ctx, &we, ctx->nstates * sizeof(double)) != hipSuccess) {
-      (void)hipGetLastError();
-      free_thermal(ctx, &th);
-      ctx->err = "device allocation of the vertex store failed";
-      return ELPH_ENOMEM;
+    if (!ctx->d_Bp) {
+      void *a = nullptr, *b = nullptr;
+      if (dev_alloc(ctx, &a, n * (f64 ? 8 : 4)) != hipSuccess || dev_alloc(ctx, &b, n * (f64 ? 8 : 4)) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_free(ctx, a);
+        free_thermal(ctx, &th);
+        ctx->err = "device allocation of the vertex store failed";
+        return ELPH_ENOMEM;
+      }
+      ctx->d_Bp = a;
+      ctx->d_Bm = b;
     }
     ctx->store_f32 = !f64;
-    if (refine_applicable(ctx)) {
-      // the GEMM forms' rates come from the finished store, after the FP64
-      // refinement of the terms whose error estimate a rate cannot absorb
-      st = run_vertex(ctx, ctx->d_Bp, ctx->d_Bm, f64, nullptr, nullptr, nullptr);
-      if (st == ELPH_OK) ctx->store_ready = true;
-      if (st == ELPH_OK) st = rates_from_store(ctx, th, W_e ? W_e : (double*)we, W_ph);
-    } else {
-      st = run_vertex(ctx, ctx->d_Bp, ctx->d_Bm, f64, &th, W_e ? W_e : (double*)we, nullptr);
-      if (st == ELPH_OK) ctx->store_ready = true;
-      if (st == ELPH_OK && W_ph) st = rates_from_store(ctx, th, nullptr, W_ph);
-    }
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    dev_free(ctx, we);
+    st = run_vertex(ctx, ctx->d_Bp, ctx->d_Bm, f64, nullptr, nullptr, nullptr);
+    if (st == ELPH_OK) ctx->store_ready = true;
   }
+  if (st == ELPH_OK) st = rates_from_store(ctx, th, W_e, W_ph);
   if (st == ELPH_OK && W_e && W_ph) {
     // keep the rates for an iteration at the same temperature
     const int64_t M = ctx->nstates, nm = ctx->nk * ctx->nbr;
@@ -744,9 +853,13 @@ extern "C" elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, d
   return st;
 }
 
-extern "C" elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph_ext, int32_t level, double tol,
-                                    int32_t maxit, double* I, double* J, double* F, double* G, double* tensors,
-                                    int32_t* iters, double* ko_residual) {
+extern "C" elph_status elph_scatt_rates(elph_ctx ctx, double T_K, double* W_e, double* W_ph) {
+  return enomem_guard(ctx, scatt_rates_impl(ctx, T_K, W_e, W_ph));
+}
+
+static elph_status iterate_impl(elph_ctx ctx, double T_K, const double* W_ph_ext, int32_t level, double tol,
+                                int32_t maxit, double* I, double* J, double* F, double* G, double* tensors,
+                                int32_t* iters, double* ko_residual) {
   CHECK_CTX(ctx);
   elph_status st = check_T(ctx, T_K);
   if (st != ELPH_OK) return st;
@@ -764,8 +877,14 @@ extern "C" elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph
   return st;
 }
 
-extern "C" elph_status elph_ko_enforce(elph_ctx ctx, double T_K, double* I, const double* J, const double* F,
-                                       const double* G, double* tensors, double* lambda, double* ko_residual) {
+extern "C" elph_status elph_iterate(elph_ctx ctx, double T_K, const double* W_ph_ext, int32_t level, double tol,
+                                    int32_t maxit, double* I, double* J, double* F, double* G, double* tensors,
+                                    int32_t* iters, double* ko_residual) {
+  return enomem_guard(ctx, iterate_impl(ctx, T_K, W_ph_ext, level, tol, maxit, I, J, F, G, tensors, iters, ko_residual));
+}
+
+static elph_status ko_enforce_impl(elph_ctx ctx, double T_K, double* I, const double* J, const double* F,
+                                   const double* G, double* tensors, double* lambda, double* ko_residual) {
   CHECK_CTX(ctx);
   elph_status st = check_T(ctx, T_K);
   if (st != ELPH_OK) return st;
@@ -776,6 +895,11 @@ extern "C" elph_status elph_ko_enforce(elph_ctx ctx, double T_K, double* I, cons
   st = build_tables(ctx);
   if (st != ELPH_OK) return st;
   return ko_enforce(ctx, T_K, I, J, F, G, tensors, lambda, ko_residual);
+}
+
+extern "C" elph_status elph_ko_enforce(elph_ctx ctx, double T_K, double* I, const double* J, const double* F,
+                                       const double* G, double* tensors, double* lambda, double* ko_residual) {
+  return enomem_guard(ctx, ko_enforce_impl(ctx, T_K, I, J, F, G, tensors, lambda, ko_residual));
 }
 
 // ---------------------------------------------------------------------------

@@ -177,9 +177,10 @@ struct elph_ctx_s {
 
   // device memory: live blocks (pointer, bytes) and released blocks kept for
   // reuse by later allocations of the same size (freed by elph_destroy or
-  // ELPH_RESET_TRIM)
+  // ELPH_RESET_TRIM); mem_limit > 0 caps the bytes of both together
   std::vector<std::pair<void*, size_t>> allocs;
   std::vector<std::pair<void*, size_t>> pool;
+  size_t mem_limit = 0;
 };
 
 namespace elph {
@@ -197,6 +198,9 @@ inline void mark(elph_ctx ctx, int e) {
 hipError_t dev_alloc(elph_ctx ctx, void** p, size_t bytes);
 void dev_free(elph_ctx ctx, void* p);
 void pool_trim(elph_ctx ctx);
+// After a failed allocation: release every derived table, operand, store and
+// work buffer (the inputs stay) so that the context can start over.
+void recover_after_enomem(elph_ctx ctx);
 
 // Host-side error plumbing of functions that take `elph_ctx ctx` and return
 // elph_status.

@@ -46,6 +46,10 @@ template <typename ST>
 void launch_we_rows(elph_ctx ctx, const ST* Bp, const ST* Bm, const double* lomf, const double* nocc, double* we,
                     const RateErr* err = nullptr);
 
+// saved state of a context: tables and vertex store (io.hip)
+elph_status save_state(elph_ctx ctx, const char* path);
+elph_status load_state(elph_ctx ctx, const char* path);
+
 // FP64 refinement of ill-conditioned vertices in the GEMM forms (refine.hip)
 bool refine_applicable(elph_ctx ctx);
 // error-estimate buffers for the next vertex store (d_rho, d_b2n)

@@ -2253,9 +2253,9 @@ static elph_status batch_sequence(BatchImpl* b, double T_K, double* const* we, d
   }
   for (int m = 0; m < n; ++m) {
     elph_ctx c = b->ctx[m];
-    double* wout = (we && we[m]) ? we[m] : b->we_tmp[m];
-    hipLaunchKernelGGL(k_reduce_we, dim3(blocks_for(c->nstates, 256)), dim3(256), 0, b->stream, c->d_we_part,
-                       c->m_pad / 32, c->m_pad, c->nstates, wout);
+    // W_e from the store rows, as elph_scatt_rates reduces it
+    if (we && we[m])
+      launch_we_rows<ST>(c, (const ST*)c->d_Bp, (const ST*)c->d_Bm, b->th[m].lomf, b->th[m].nocc, we[m]);
     if (wph && wph[m]) {
       launch_q_gather<ST, 1>(c, (const ST*)c->d_Bp, b->th[m].f, b->th[m].omf, nullptr, b->acc[m]);
       elph_status st = finalize_wph(c, b->th[m], b->acc[m], wph[m]);

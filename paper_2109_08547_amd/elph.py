@@ -44,7 +44,8 @@ class ElphSizes(ctypes.Structure):
 
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
-           "elph_batch_tune", "elph_tables", "elph_timing_extra", "elph_set_refine", "elph_refine_info",
+           "elph_batch_tune", "elph_tables", "elph_timing_extra", "elph_set_refine", "elph_refine_info", "elph_save", "elph_load", "elph_set_memory_limit",
+           "elph_memory_held",
            "elph_refine_estimates",
            "elph_interp_g", "elph_interp_g_noalloc", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
            "elph_set_ifc3", "elph_phph_vertex", "elph_phph_rates", "elph_phph_inscatter", "elph_set_phph",
@@ -78,6 +79,10 @@ def load():
     lib.elph_timing.argtypes = [vp, ctypes.c_int32, vp]
     lib.elph_timing_extra.argtypes = [vp, vp]
     lib.elph_set_refine.argtypes = [vp, ctypes.c_double]
+    lib.elph_save.argtypes = [vp, ctypes.c_char_p]
+    lib.elph_load.argtypes = [vp, ctypes.c_char_p]
+    lib.elph_set_memory_limit.argtypes = [vp, ctypes.c_int64]
+    lib.elph_memory_held.argtypes = [vp, vp]
     lib.elph_refine_info.argtypes = [vp, vp, vp]
     lib.elph_refine_estimates.argtypes = [vp, vp]
     lib.elph_sizes.argtypes = [vp, ctypes.POINTER(ElphSizes)]
@@ -220,6 +225,24 @@ def elph_timing_extra(ctx):
     ms = ctypes.c_double(-1.0)
     _check(ctx, load().elph_timing_extra(ctx.handle, ctypes.byref(ms)))
     return ms.value
+
+
+def elph_save(ctx, path):
+    _check(ctx, load().elph_save(ctx.handle, os.fsencode(path)))
+
+
+def elph_load(ctx, path):
+    _check(ctx, load().elph_load(ctx.handle, os.fsencode(path)))
+
+
+def elph_set_memory_limit(ctx, nbytes):
+    _check(ctx, load().elph_set_memory_limit(ctx.handle, int(nbytes)))
+
+
+def elph_memory_held(ctx):
+    v = ctypes.c_int64(0)
+    _check(ctx, load().elph_memory_held(ctx.handle, ctypes.byref(v)))
+    return v.value
 
 
 def elph_set_refine(ctx, theta):
