@@ -207,6 +207,14 @@ elph_status elph_load(elph_ctx ctx, const char* path);
  * EINVAL for a negative budget. */
 elph_status elph_set_memory_limit(elph_ctx ctx, int64_t bytes);
 
+/* Largest FP32 output buffer of a GEMM form's contraction in bytes (default
+ * 2 GiB, at least 1 MiB): the step-1 rows and the step-2 output [i][j][x]
+ * are produced in chunks of initial states that fit it (step 2: whole kept k
+ * and at least 16 states per chunk).  Results do not depend on it; a smaller
+ * chunk lowers peak memory at the cost of more launches.  Applies to later
+ * vertex evaluations.  EINVAL below 1 MiB. */
+elph_status elph_set_gemm_chunk(elph_ctx ctx, int64_t bytes);
+
 /* Bytes of device memory the context holds (live and kept for reuse). */
 elph_status elph_memory_held(elph_ctx ctx, int64_t* bytes);
 

@@ -677,9 +677,14 @@ def _rel_change(new, old):
     return np.linalg.norm(new - old) / max(nn, 1e-300)
 
 
-def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=None, phph=None):
+def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=None, phph=None,
+            inner="substitution"):
     """Solve Eq. 19 with the unified scheme: each phonon (outer) iteration
     brings the electrons (inner) to self-consistency with the current phonons.
+    ``inner`` = "substitution" iterates the electron equations to tol/10;
+    "direct" solves them (with the carrier-number constraints) by one dense
+    bordered solve, which reaches the same fixed point where the substitution
+    converges slowly (an in-scattering operator with spectral radius near 1).
     ``Xp``/``Xm`` are the full [nstates, nstates, nbr] arrays of Eq. 8.
     ``phph`` = (ifc3, sigma) adds three-phonon scattering (Eq. 26): its RTA
     rate joins W^RTA (``w_ext`` then holds the remaining channels, none when
@@ -755,8 +760,21 @@ def iterate(prob, T, Xp, Xm, level=LEVEL_COUPLED, tol=1e-8, maxit=200, w_ext=Non
         S = (Mph @ phon.reshape(-1, 3)).reshape(phon.shape)
         return S * inv_wp[..., None]
 
+    if inner == "direct":
+        # x = project(x0 + K x): (1 - K) x + sum_g c_g 1_g = x0 with
+        # sum_{i in g} w_i x_i = 0 for every group g
+        A = np.zeros((M + ngrp, M + ngrp))
+        A[:M, :M] = np.eye(M) - Kself
+        for c in range(ngrp):
+            A[:M, M + c] = (grp == c)
+            A[M + c, :M] = w * (grp == c)
+
     def solve_e(x0, x):
         """Electron BTE (Eqs. 19, 22) to self-consistency for a fixed drive x0."""
+        if inner == "direct":
+            rhs = np.zeros((M + ngrp, x0.shape[1]))
+            rhs[:M] = x0
+            return np.linalg.solve(A, rhs)[:M], 1, True
         for it in range(1, maxit + 1):
             xn = project(x0 + Kself @ x)
             r = _rel_change(xn, x)

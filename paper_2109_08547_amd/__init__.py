@@ -12,5 +12,5 @@ from .elph import (  # noqa: F401
     elph_mlp_create, elph_mlp_nparams, elph_mlp_get_params, elph_mlp_set_params, elph_mlp_forward,
     elph_mlp_gradients, elph_mlp_train_step, elph_screen_nin, elph_screen_samples, elph_scatt_rates_screened,
     elph_set_refine, elph_refine_info, elph_refine_estimates, elph_interp_g_noalloc,
-    elph_save, elph_load, elph_set_memory_limit, elph_memory_held,
+    elph_save, elph_load, elph_set_memory_limit, elph_memory_held, elph_set_gemm_chunk,
 )

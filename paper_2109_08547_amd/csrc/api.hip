@@ -352,6 +352,16 @@ extern "C" elph_status elph_set_memory_limit(elph_ctx ctx, int64_t bytes) {
   return ELPH_OK;
 }
 
+extern "C" elph_status elph_set_gemm_chunk(elph_ctx ctx, int64_t bytes) {
+  CHECK_CTX(ctx);
+  if (bytes < ((int64_t)1 << 20)) {
+    ctx->err = "GEMM output chunk must be at least 1 MiB";
+    return ELPH_EINVAL;
+  }
+  ctx->gemm_chunk = (size_t)bytes;
+  return ELPH_OK;
+}
+
 extern "C" elph_status elph_memory_held(elph_ctx ctx, int64_t* bytes) {
   CHECK_CTX(ctx);
   if (!bytes) {

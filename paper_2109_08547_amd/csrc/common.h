@@ -181,6 +181,8 @@ struct elph_ctx_s {
   std::vector<std::pair<void*, size_t>> allocs;
   std::vector<std::pair<void*, size_t>> pool;
   size_t mem_limit = 0;
+  // largest FP32 output buffer of a GEMM form's contraction (rows in chunks)
+  size_t gemm_chunk = (size_t)1 << 31;
 };
 
 namespace elph {

@@ -1380,11 +1380,12 @@ template <typename T>
 static elph_status launch_step1_t(elph_ctx ctx, bool norms = false) {
   const S1Desc<T> d = step1_desc<T>(ctx);
   if constexpr (UsesGemm<T>::value) {
-    // GEMM into FP32 rows (chunks <= 2 GiB), then the phase epilogue that
-    // writes B2 in the form's operand format
+    // GEMM into FP32 rows (chunks of at most gemm_chunk bytes, 2 GiB by
+    // default), then the phase epilogue that writes B2 in the form's operand
+    // format
     typedef typename GemmOp<T>::type OP;
     const int64_t M = ctx->nstates, ncol = d.ncol;
-    int64_t ci = ((int64_t)1 << 31) / (ncol * 8);
+    int64_t ci = (int64_t)ctx->gemm_chunk / (ncol * 8);
     if (ci < 1) ci = 1;
     if (ci > M) ci = M;
     void* p = nullptr;
@@ -1425,14 +1426,15 @@ static void launch_step2_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* B
 
 // GEMM forms without a tile mask: GEMM into an FP32 buffer [i][j][x], then
 // the per-q epilogue over the kept pairs, in chunks of initial states (whole
-// kept k) so that the buffer stays <= 2 GiB; W_e from the finished store.
+// kept k) so that the buffer stays within gemm_chunk bytes (2 GiB by
+// default; at least 16 states); W_e from the finished store.
 template <typename T, typename ST, int NX>
 static elph_status launch_gemm_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, void* Bm, int64_t* we_tiles) {
   typedef typename GemmOp<T>::type OP;
   const int64_t M = ctx->nstates, ldc = ctx->m_pad;
   elph_status st = ensure_pairs(ctx);
   if (st != ELPH_OK) return st;
-  int64_t cap = ((int64_t)1 << 31) / ((int64_t)NX * ldc * 8);
+  int64_t cap = (int64_t)ctx->gemm_chunk / ((int64_t)NX * ldc * 8);
   if (cap < kMaxBands) cap = kMaxBands;
   std::vector<int32_t> soff(ctx->nkept + 1);
   if (hipMemcpyAsync(soff.data(), ctx->d_soff, (ctx->nkept + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,

@@ -45,7 +45,7 @@ class ElphSizes(ctypes.Structure):
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
            "elph_batch_tune", "elph_tables", "elph_timing_extra", "elph_set_refine", "elph_refine_info", "elph_save", "elph_load", "elph_set_memory_limit",
-           "elph_memory_held",
+           "elph_memory_held", "elph_set_gemm_chunk",
            "elph_refine_estimates",
            "elph_interp_g", "elph_interp_g_noalloc", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
            "elph_set_ifc3", "elph_phph_vertex", "elph_phph_rates", "elph_phph_inscatter", "elph_set_phph",
@@ -83,6 +83,7 @@ def load():
     lib.elph_load.argtypes = [vp, ctypes.c_char_p]
     lib.elph_set_memory_limit.argtypes = [vp, ctypes.c_int64]
     lib.elph_memory_held.argtypes = [vp, vp]
+    lib.elph_set_gemm_chunk.argtypes = [vp, ctypes.c_int64]
     lib.elph_refine_info.argtypes = [vp, vp, vp]
     lib.elph_refine_estimates.argtypes = [vp, vp]
     lib.elph_sizes.argtypes = [vp, ctypes.POINTER(ElphSizes)]
@@ -237,6 +238,10 @@ def elph_load(ctx, path):
 
 def elph_set_memory_limit(ctx, nbytes):
     _check(ctx, load().elph_set_memory_limit(ctx.handle, int(nbytes)))
+
+
+def elph_set_gemm_chunk(ctx, nbytes):
+    _check(ctx, load().elph_set_gemm_chunk(ctx.handle, int(nbytes)))
 
 
 def elph_memory_held(ctx):

@@ -417,3 +417,25 @@ def test_coupled_iteration_with_three_phonon_inscattering_matches_a_dense_solve(
     for got, want in ((res["I"], I), (res["J"], J), (res["F"], F), (res["G"], G)):
         assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
     assert np.abs(G).max() > 1e-6 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("level", [1, 2, 3])
+def test_direct_electron_solve_equals_the_substitution(level):
+    """The dense bordered electron solve (inner="direct") reaches the fixed
+    point the plain substitution reaches (metal6, where it converges), at
+    every level of the scheme."""
+    cfg = synth.config("metal6")
+    mat = synth.material_for(cfg)
+    T = 300.0
+    prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+    Xp, Xm = prob.transition_probs(T)
+    w_ext = oracle.default_w_ext(prob, T, gamma0=1e13)
+    a = oracle.iterate(prob, T, Xp, Xm, level, tol=1e-13, maxit=3000, w_ext=w_ext)
+    b = oracle.iterate(prob, T, Xp, Xm, level, tol=1e-13, maxit=3000, w_ext=w_ext, inner="direct")
+    assert a["converged"] and b["converged"]
+    for k in ("I", "J", "F", "G"):
+        scale = np.abs(a[k]).max()
+        if scale == 0:
+            assert not np.any(b[k])
+            continue
+        assert np.abs(a[k] - b[k]).max() <= 1e-9 * scale, k
