@@ -198,6 +198,14 @@ def run_form(E, torch, mat, cfg, form, steps, warmup, with_iterate, tol, maxit, 
     return out
 
 
+def _cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([d.get("num_threads", 1) for d in threadpool_info()] + [1]))
+    except Exception:  # pragma: no cover
+        return len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(mat, cfg, gpu_we, budget_s=20.0):
     """The oracle on a bounded sample: its tables plus the transition
     probabilities of a seeded subset of initial states (all final states)."""
@@ -232,7 +240,17 @@ def cpu_baseline(mat, cfg, gpu_we, budget_s=20.0):
     }
 
 
-def run_batch(E, torch, steps, warmup, form="fp32"):
+def gen_material(name):
+    """Synthetic material of a configuration (run in a worker process)."""
+    import synth
+    return synth.material_for(synth.config(name))
+
+
+def gen_materials(names):
+    return [gen_material(n) for n in names]
+
+
+def run_batch(E, torch, steps, warmup, form="fp32", mats=None):
     """32 materials: per-context calls one after another versus the batched
     persistent launches (autotuned, replayed from a HIP graph)."""
     import synth
@@ -240,7 +258,7 @@ def run_batch(E, torch, steps, warmup, form="fp32"):
     ctxs, cfgs = [], []
     for j in range(32):
         cfg = synth.config("batch%02d" % j)
-        mat = synth.material_for(cfg)
+        mat = mats[j] if mats is not None else synth.material_for(cfg)
         ctxs.append(E.elph_create(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], precision=form))
         E.elph_set_refine(ctxs[-1], 0.0)   # both legs run the plain form (batches have no FP64 refinement)
         cfgs.append(cfg)
@@ -295,16 +313,20 @@ def run_batch(E, torch, steps, warmup, form="fp32"):
     }
 
 
-def run_large(E, torch, form="fp32"):
+def run_large(E, torch, form="fp32", mat=None, cpu_rows=0):
     """The large configuration: per form, tables, vertices and the
     T-independent store once (timed) with the RTA rates at 300 K, compared
     with the plain FP64 path; then, for the requested form, the coupled
-    iteration to 1e-8 at five temperatures reusing the store."""
+    iteration to 1e-8 at five temperatures reusing the store.  cpu_rows > 0:
+    the oracle's W_e of that many seeded initial states (each against every
+    final state; phonons only at the q they need), timed on the host and
+    compared with both GPU paths."""
     import synth
     dev = torch.device("cuda:0")
     cfg = synth.config("large100")
     t0 = time.perf_counter()
-    mat = synth.material_for(cfg)
+    if mat is None:
+        mat = synth.material_for(cfg)
     t_gen = time.perf_counter() - t0
     print("bench: large100 material generated in %.1f s" % t_gen, file=sys.stderr, flush=True)
     res = {}
@@ -323,6 +345,8 @@ def run_large(E, torch, form="fp32"):
         t_vert = time.perf_counter() - t1
         res[fm] = {"s": t_vert, "kernel_ms": E.elph_timing(ctx, True, read=True), "we": we.cpu().numpy(),
                    "wph": wph.cpu().numpy(), "sizes": sz}
+        if fm != "fp64":
+            res[fm]["refine"] = E.elph_refine_info(ctx)
         print("bench: large100 %s: tables + vertices + rates %.2f s (nstates %d)" % (fm, t_vert, M),
               file=sys.stderr, flush=True)
         if fm == form:
@@ -348,16 +372,32 @@ def run_large(E, torch, form="fp32"):
     errs = {}
     for key in ("we", "wph"):
         w, ref = res[form][key], res["fp64"][key]
-        errs[key] = {"above_1e-6_max": rate_err(w, ref, 1e-6),
+        errs[key] = {"strict": rate_err(w, ref), "above_1e-6_max": rate_err(w, ref, 1e-6),
                      "normwise": float(np.linalg.norm(w - ref) / np.linalg.norm(ref))}
+    cpu = None
+    if cpu_rows > 0:
+        import oracle
+        rows = np.sort(np.random.default_rng(5).choice(sz["nstates"], cpu_rows, replace=False))
+        t1 = time.perf_counter()
+        w_or, M = oracle.rates_e_rows(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], cfg["T"], rows)
+        t_or = time.perf_counter() - t1
+        assert M == sz["nstates"]
+        cpu = {"value": 2.0 * len(rows) * M * sz["nbr"] / t_or, "unit": "transition probabilities/s",
+               "cores": _cores(), "kind": "oracle",
+               "sample": "W_e of %d seeded initial states x all %d final states x %d branches (%.1f s, eigenvalues "
+                         "of the whole mesh for the window included)" % (len(rows), M, sz["nbr"], t_or),
+               "max_rel_err_W_e_gpu_fp64_vs_oracle_rows": rate_err(res["fp64"]["we"][rows], w_or),
+               "max_rel_err_W_e_gpu_%s_vs_oracle_rows" % form: rate_err(res[form]["we"][rows], w_or)}
+        print("bench: large100 oracle rows %s" % json.dumps(cpu), file=sys.stderr, flush=True)
     return {
         "metric": METRIC, "value": nterms / res[form]["s"], "unit": "transition probabilities/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": DTYPE[form], "data": "synthetic",
         "config": {"workload": "large100: " + WORKLOADS["large100"], "nstates": sz["nstates"],
                    "nkept": sz["nkept"], "terms": nterms, "form": form},
         "note": "value counts the whole first evaluation (tables, both contractions, store, rates) at 300 K",
-        "forms": {fm: {"s": r["s"], "value": nterms / r["s"], "kernel_ms": r["kernel_ms"]} for fm, r in res.items()},
-        "rel_err_vs_fp64": errs, "generation_s": t_gen, "sweep": sweep,
+        "forms": {fm: {"s": r["s"], "value": nterms / r["s"], "kernel_ms": r["kernel_ms"], "refine": r.get("refine")}
+                  for fm, r in res.items()},
+        "rel_err_vs_fp64": errs, "generation_s": t_gen, "sweep": sweep, "cpu_baseline": cpu,
     }
 
 
@@ -559,6 +599,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-coupled", action="store_true",
                     help="skip the untimed full coupled solve after the timed steps (shorter profiled runs)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="default workload only: skip the batch32 and large100 records attached to the line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy (neg) of 1 GiB float32 three times, whose HBM "
                          "bytes are known, to scale the byte counters of a profiled run")
@@ -567,6 +609,25 @@ def main():
         print("bench.py: the library runs on one GPU (the path would shard by kept-k rows across GPUs; "
               "see the design notes); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    pool, futs = None, {}
+    if args.workload == "mixed48" and not args.no_configs:
+        # the other configurations' materials are drawn in worker processes
+        # (started before this process touches the GPU) while the default
+        # workload runs
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+        for k in env_keep:
+            os.environ[k] = "2"
+        pool = ProcessPoolExecutor(max_workers=5, mp_context=mp.get_context("spawn"))
+        for k, v in env_keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        futs["large100"] = [pool.submit(gen_material, "large100")]
+        names = ["batch%02d" % j for j in range(32)]
+        futs["batch32"] = [pool.submit(gen_materials, names[a::4]) for a in range(4)]
     import torch
     import synth
     import paper_2109_08547_amd as E
@@ -576,7 +637,7 @@ def main():
         return
     if args.workload == "large100":
         form = args.forms.split(",")[-1] if args.forms != "fp64,fp32,bf16x3,bf16x6,fp16x3" else "fp32"
-        print(json.dumps(run_large(E, torch, form=form)), flush=True)
+        print(json.dumps(run_large(E, torch, form=form, cpu_rows=0 if args.no_cpu else 16)), flush=True)
         return
     if args.copy_calibration:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -652,8 +713,38 @@ def main():
         n = SPLIT_PRODUCTS[best]
         line["roofline"]["split_ceiling"] = {"products_per_flop": n, "peak": PEAK[best] / n,
                                              "frac": achieved / (PEAK[best] / n)}
+    configs_error = None
+    if pool is not None:
+        # wait for the other materials before the host is timed
+        try:
+            large_mat = futs["large100"][0].result()
+            parts = [f.result() for f in futs["batch32"]]
+            batch_mats = [None] * 32
+            for a, lst in enumerate(parts):
+                for t, m in enumerate(lst):
+                    batch_mats[a + 4 * t] = m
+        except Exception as e:  # the default line is still printed
+            configs_error = "material generation failed: %r" % (e,)
+        pool.shutdown()
+        if configs_error:
+            line["configs"] = {"error": configs_error}
+            pool = None
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(mat, cfg, ref_we, args.cpu_budget)
+    if pool is not None:
+        del res
+        print("bench: batch32 record", file=sys.stderr, flush=True)
+        b = run_batch(E, torch, 3, 1, mats=batch_mats)
+        del batch_mats
+        print("bench: large100 record", file=sys.stderr, flush=True)
+        lg = run_large(E, torch, mat=large_mat)
+        del large_mat
+        line["configs"] = {
+            "batch32": {k: b[k] for k in ("value", "unit", "ms_per_step", "dtype", "config", "sequential", "batched",
+                                          "bitwise_equal_to_sequential")},
+            "large100": {k: lg[k] for k in ("value", "unit", "dtype", "config", "note", "forms", "rel_err_vs_fp64",
+                                            "sweep")},
+        }
     print(json.dumps(line), flush=True)
 
 

@@ -74,7 +74,7 @@ LEVEL_RTA, LEVEL_PARTIAL, LEVEL_DRAGLESS, LEVEL_COUPLED = 0, 1, 2, 3
 __all__ = [
     "HBAR_EVS", "KB_EVK", "E_CHARGE", "AMU_KG", "ANG_M", "C_PHONON", "SPIN_DEG",
     "OMEGA_MIN_DEFAULT", "NAC_EV_A", "nac_images", "nac_term", "frohlich_factor", "LEVEL_RTA", "LEVEL_PARTIAL", "LEVEL_DRAGLESS", "LEVEL_COUPLED",
-    "mesh_points", "mesh_linear", "phases", "bloch_hamiltonian", "bloch_hamiltonian_grad",
+    "mesh_points", "mesh_linear", "phases", "rates_e_rows", "bloch_hamiltonian", "bloch_hamiltonian_grad",
     "electron_bands", "electron_velocities", "dynamical_matrix", "dynamical_matrix_grad",
     "phonon_modes", "phonon_velocities", "fermi_pair", "bose_pair", "gaussian_delta",
     "g_wannier_brute", "g_wannier_factorised", "g_bloch", "Problem", "default_w_ext",
@@ -639,6 +639,56 @@ class Problem:
                 w = SPIN_DEG * acc / (n * onp)
             out[t] = np.where(self.mode_on[qm], w, 0.0)
         return out
+
+
+def rates_e_rows(mat, mesh, mu, window, sigma, T, rows, omega_min=OMEGA_MIN_DEFAULT):
+    """W_e of Eq. 21 (e-ph part) for the initial active states ``rows`` (indices
+    in the (kept k, band) order of Problem), each against every final active
+    state, with the Gaussian delta of Eq. 8.  The same definition as
+    Problem.rates_e on Problem.transition_probs, but the phonon modes (Eq. 3)
+    are diagonalised only at the q = k' - k that the rows need, so that it
+    runs on meshes whose whole-mesh phonon tables would not fit (100^3).
+    Returns (W [len(rows)], nstates).  Non-polar materials only."""
+    if mat.get("zstar") is not None:
+        raise ValueError("rates_e_rows: polar materials need Problem")
+    n = int(mesh)
+    kfrac = mesh_points(n)
+    nk = kfrac.shape[0]
+    ijk = np.rint(kfrac * n).astype(np.int64)
+    nb = int(mat["nwann"])
+    eps_all = np.empty((nk, nb))
+    for s in range(0, nk, 32768):
+        eps_all[s:s + 32768] = np.linalg.eigvalsh(bloch_hamiltonian(mat, kfrac[s:s + 32768]))
+    act = np.abs(eps_all - mu) <= window                     # window per state (section on the workflow)
+    kept = np.nonzero(act.any(1))[0]
+    st_k, st_m = np.nonzero(act[kept])
+    state_k = kept[st_k]
+    nstates = st_k.size
+    eps = eps_all[state_k, st_m]
+    _, U_kept = electron_bands(mat, kfrac[kept])
+    f, omf = fermi_pair(eps, mu, T)
+    pref = 2.0 * np.pi / (HBAR_EVS * nk)
+    out = np.empty(len(rows))
+    for r, i in enumerate(np.asarray(rows)):
+        kidx = st_k[i]
+        kmesh = kept[kidx]
+        qmesh = mesh_linear(ijk[kept] - ijk[kmesh], n)       # q of every final kept k'
+        hw, u = phonon_modes(mat, kfrac[qmesh])
+        gW = g_wannier_factorised(mat, kfrac[kmesh], kfrac[qmesh])
+        g = g_bloch(mat, gW, U_kept[kidx][None], U_kept, u, hw, omega_min)
+        g2 = np.abs(g) ** 2                                   # [nK', s, n, m]
+        on = hw >= omega_min
+        nq, onq = bose_pair(hw, T)
+        g2j = g2[st_k, :, st_m, st_m[i]]                     # final states j, all s
+        de = (eps - eps[i])[:, None]
+        dp = gaussian_delta(de - hw[st_k], sigma)
+        dm = gaussian_delta(de + hw[st_k], sigma)
+        occ = (f[i] * omf)[:, None]
+        with np.errstate(invalid="ignore"):
+            x = pref * g2j * occ * (nq[st_k] * dp + onq[st_k] * dm)
+        x = np.where(on[st_k], x, 0.0)
+        out[r] = x.sum() / (f[i] * omf[i])
+    return out, nstates
 
 
 def _scatter_q(qij, vals, nq):

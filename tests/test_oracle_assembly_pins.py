@@ -439,3 +439,18 @@ def test_direct_electron_solve_equals_the_substitution(level):
             assert not np.any(b[k])
             continue
         assert np.abs(a[k] - b[k]).max() <= 1e-9 * scale, k
+
+
+@pytest.mark.parametrize("name", ["tiny4", "plain8"])
+def test_sampled_rows_equal_the_whole_problem(name):
+    """rates_e_rows (phonons only at the q the rows need) equals
+    Problem.rates_e on Problem.transition_probs for the same rows."""
+    cfg = synth.config(name)
+    mat = synth.material_for(cfg)
+    prob = oracle.Problem(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"])
+    rows = np.random.default_rng(3).choice(prob.nstates, 6, replace=False)
+    Xp, Xm = prob.transition_probs(cfg["T"], rows)
+    want = prob.rates_e(cfg["T"], Xp, Xm, rows)
+    got, M = oracle.rates_e_rows(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], cfg["T"], rows)
+    assert M == prob.nstates
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
