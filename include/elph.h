@@ -529,16 +529,24 @@ elph_status elph_screen_samples(elph_ctx ctx, int64_t npairs, const int32_t* kid
                                 const int32_t* qidx, float* x, float* t);
 
 enum { ELPH_SCREEN_NONE = 0, ELPH_SCREEN_ENERGY = 1, ELPH_SCREEN_MLP = 2 };
-/* Screened RTA rates at T (outputs as elph_scatt_rates).  mode ENERGY keeps
- * a term when one of its Gaussian factors exceeds exp(-18) (|dE -/+ hw| <
- * 6 sigma; m may be NULL); mode MLP keeps it when its predicted X is at
- * least tau times the largest predicted X of its initial state.  A step-2
- * tile (32 final x 32 initial states) is computed when any of its terms is
- * kept, otherwise its vertex-store entries are zero.  The vertex store is
- * replaced by the screened one.  stats (host, may be NULL) [4]: tiles,
- * tiles computed, terms evaluated by the screen, screen time (ms). */
-elph_status elph_scatt_rates_screened(elph_ctx ctx, elph_mlp m, int32_t mode, double tau, double T_K,
-                                      double* W_e, double* W_ph, double* stats);
+/* Screened RTA rates at T (outputs as elph_scatt_rates), the skip rule of
+ * the learned screen applied to whole step-2 tiles.  The states are ranked by
+ * energy (ties by state index) and a tile is 32 consecutive ranks of final
+ * states x 32 of initial states.  Mode ENERGY keeps a tile when one of its
+ * terms has a Gaussian factor exp(-(dE -/+ hw)^2 / 2 sigma^2) of at least
+ * gauss_min (0 < gauss_min < 1; m may be NULL; tau unused).  Mode MLP runs
+ * that stage first, then evaluates the network on every term of the kept
+ * tiles and keeps a tile when one of its terms has a predicted X+ + X- of at
+ * least tau (0 < tau < 1) times the largest of its initial state, or a
+ * predicted X+ of at least tau times the largest of its phonon mode (the sums
+ * of Eqs. 21 and 25), maxima over the evaluated terms.  Mode NONE computes every tile.  Tiles not kept have
+ * zero vertex-store entries; the store is not reused as the exact one by
+ * later calls.  stats (host, may be NULL) [5]: tiles, tiles computed, tiles
+ * kept by the energy stage, terms evaluated by the network, screen time (ms,
+ * both stages, before the vertex evaluation).  EINVAL on a bad mode,
+ * threshold, temperature, network size or a non-Gaussian delta. */
+elph_status elph_scatt_rates_screened(elph_ctx ctx, elph_mlp m, int32_t mode, double tau, double gauss_min,
+                                      double T_K, double* W_e, double* W_ph, double* stats);
 
 #ifdef __cplusplus
 }

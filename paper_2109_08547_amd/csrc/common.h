@@ -174,6 +174,7 @@ struct elph_ctx_s {
   bool rates_valid = false;
   double* h_pin = nullptr;        // pinned host words for solver status reads
   const uint8_t* d_tile_keep = nullptr;  // step-2 tile mask of a screened evaluation (else null)
+  const int32_t* d_tile_perm = nullptr;  // state at each tile position of that evaluation (null = identity)
 
   // device memory: live blocks (pointer, bytes) and released blocks kept for
   // reuse by later allocations of the same size (freed by elph_destroy or

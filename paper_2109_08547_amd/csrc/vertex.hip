@@ -492,6 +492,7 @@ struct EpiParams {
   double* wph_acc;           // [nk][nbr]
   int64_t m_pad;
   const uint8_t* tile_keep;  // [m_pad/32][m_pad/32] computed tiles (null = all)
+  const int32_t* perm;       // [m_pad] state at each tile position (null = identity; the padding maps to itself)
   double cscale;             // undoes the operand scales of the step-2 contraction (1 but in the FP16 form)
   int tetra;                 // 1: store pref |g|^2 without the delta (tetrahedron weights follow)
   const cd* fr;              // [nk][nbr] Froehlich factors F_s(q) of Eq. 7 (null: not polar)
@@ -557,19 +558,21 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
   ST* __restrict__ Bp = (ST*)d.Bp;
   ST* __restrict__ Bm = (ST*)d.Bm;
   const EpiParams& ep = d.ep;
+  // tile positions are state indices, or ranks in ep.perm's order
+  auto state_at = [&](int64_t pos) -> int64_t { return ep.perm ? (int64_t)ep.perm[pos] : pos; };
   if (ep.tile_keep && !ep.tile_keep[bx * (ep.m_pad / 32) + by]) {
     // screened out: zero vertex-store entries and W_e partials of the tile
     for (int e = threadIdx.x; e < 32 * 32 * NX; e += 256) {
       const int s = e % NX, jj = (e / NX) % 32, ii = e / (NX * 32);
-      const int64_t i = by * 32 + ii, j = bx * 32 + jj;
-      if (i < ep.nstates && j < ep.nstates) {
-        const int64_t tb = (i * ep.nstates + j) * NX + s;
+      const int64_t pi = by * 32 + ii, pj = bx * 32 + jj;
+      if (pi < ep.nstates && pj < ep.nstates) {
+        const int64_t tb = (state_at(pi) * ep.nstates + state_at(pj)) * NX + s;
         Bp[tb] = (ST)0;
         Bm[tb] = (ST)0;
       }
     }
     if (ep.we_part && threadIdx.x < 32 && by * 32 + threadIdx.x < ep.nstates)
-      ep.we_part[bx * ep.m_pad + by * 32 + threadIdx.x] = 0.0;
+      ep.we_part[bx * ep.m_pad + state_at(by * 32 + threadIdx.x)] = 0.0;
     return;
   }
   const int lane = threadIdx.x & 63;
@@ -577,6 +580,7 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
   const int64_t j0 = bx * 32 + (wave >> 1) * 16;
   const int64_t i0 = by * 32 + (wave & 1) * 16;
   const int lr = lane & 15, lk = lane >> 4;
+  const int64_t jrow = state_at(j0 + lr), irow = state_at(i0 + lr);  // operand rows of this lane
 
   acc_t cr[NX], ci[NX];
   double fr[MM::kFold ? NX : 1][4], fi[MM::kFold ? NX : 1][4];
@@ -593,8 +597,8 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
   }
   if constexpr (IsSplit<T>::value) {
     constexpr int NS = IsSplit<T>::ns;
-    const SE* pa = Ap + (j0 + lr) * kp * 2 * NS + lk * 16 * NS;
-    const SE* pb = B2 + ((i0 + lr) * NX) * kp * 2 * NS + lk * 16 * NS;
+    const SE* pa = Ap + jrow * kp * 2 * NS + lk * 16 * NS;
+    const SE* pb = B2 + (irow * NX) * kp * 2 * NS + lk * 16 * NS;
     for (int64_t k0 = 0; k0 < kp; k0 += 32) {
       const int64_t go = (k0 >> 3) * 16 * NS;
       us8v fa[2 * NS], na[NS];
@@ -618,8 +622,8 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
       }
     }
   } else {
-    const T* pa = Ap + 2 * ((j0 + lr) * kp + lk);
-    const T* pb = B2 + 2 * (((i0 + lr) * NX) * kp + lk);
+    const T* pa = Ap + 2 * (jrow * kp + lk);
+    const T* pb = B2 + 2 * ((irow * NX) * kp + lk);
     auto kstep = [&](int64_t k) {
       const Cplx<T> fa = ldc(pa + 2 * k);
       const T nai = -fa.y;
@@ -652,18 +656,20 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
       }
     }
   }
-  // epilogue: lane owns rows j = j0 + MM::row(lk, r), column i = i0 + lr
-  const int64_t i = i0 + lr;
+  // epilogue: lane owns rows j at positions j0 + MM::row(lk, r), column i at
+  // position i0 + lr
+  const int64_t i = irow;
   const bool want_rates = ep.we_part != nullptr;
   double we = 0.0;
-  if (i < ep.nstates) {
+  if (i0 + lr < ep.nstates) {
     const int64_t ki = ep.st_k[i];
     const double ei = ep.eps[i];
     const double lomf_i = want_rates ? ep.lomf[i] : 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t j = j0 + MM::row(lk, r);
-      if (j >= ep.nstates) continue;
+      const int64_t pj = j0 + MM::row(lk, r);
+      if (pj >= ep.nstates) continue;
+      const int64_t j = state_at(pj);
       const int64_t q = q_of(ep.st_k[j], ki, ep.n0, ep.n1, ep.n2);
       const double de = ep.eps[j] - ei;
       const cd* L = ep.Lq + q * NX * NX;
@@ -722,7 +728,7 @@ __device__ __forceinline__ void step2_tile(const S2Desc<T>& d, int64_t bx, int64
     __syncthreads();
     if (wave < 2 && lk == 0) {
       const double tot = red[wave][lr] + red[wave + 2][lr];
-      if (i < ep.nstates) ep.we_part[bx * ep.m_pad + i] = tot;
+      if (i0 + lr < ep.nstates) ep.we_part[bx * ep.m_pad + i] = tot;
     }
   }
 }
@@ -1221,6 +1227,7 @@ __device__ inline void promote(EpiParams& e) {
   e.we_part = as_global(e.we_part);
   e.wph_acc = as_global(e.wph_acc);
   e.tile_keep = as_global(e.tile_keep);
+  e.perm = as_global(e.perm);
 }
 
 template <typename T>
@@ -1525,6 +1532,7 @@ static EpiParams epi_params(elph_ctx ctx) {
   ep.we_part = nullptr;
   ep.wph_acc = nullptr;
   ep.tile_keep = ctx->d_tile_keep;
+  ep.perm = ctx->d_tile_perm;
   ep.cscale = 1.0 / (ctx->sc_b2 * ctx->sc_ap);
   ep.rho = nullptr;
   ep.b2n = nullptr;

@@ -125,7 +125,8 @@ def load():
     lib.elph_screen_nin.argtypes = [vp]
     lib.elph_screen_nin.restype = ctypes.c_int32
     lib.elph_screen_samples.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
-    lib.elph_scatt_rates_screened.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    lib.elph_scatt_rates_screened.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, vp, vp, vp]
     for name in EXPORTS:
         if name not in _NO_STATUS:
             getattr(lib, name).restype = ctypes.c_int32
@@ -517,10 +518,10 @@ def elph_screen_samples(ctx, kidx, qidx, x, t):
                                            _ptr(t)))
 
 
-def elph_scatt_rates_screened(ctx, mlp, mode, tau, T, W_e=None, W_ph=None):
-    stats = np.zeros(4, dtype=np.float64)
+def elph_scatt_rates_screened(ctx, mlp, mode, tau, T, W_e=None, W_ph=None, gauss_min=1e-30):
+    stats = np.zeros(5, dtype=np.float64)
     _check(ctx, load().elph_scatt_rates_screened(ctx.handle, mlp.handle if mlp is not None else None, int(mode),
-                                                 float(tau), float(T), _ptr(W_e), _ptr(W_ph),
+                                                 float(tau), float(gauss_min), float(T), _ptr(W_e), _ptr(W_ph),
                                                  stats.ctypes.data_as(ctypes.c_void_p)))
-    return {"tiles": int(stats[0]), "tiles_computed": int(stats[1]), "terms_screened": int(stats[2]),
-            "screen_ms": float(stats[3])}
+    return {"tiles": int(stats[0]), "tiles_computed": int(stats[1]), "tiles_energy": int(stats[2]),
+            "terms_queried": int(stats[3]), "screen_ms": float(stats[4])}
