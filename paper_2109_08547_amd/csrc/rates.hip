@@ -957,34 +957,75 @@ __global__ void k_group_bounds(int64_t n, const int32_t* __restrict__ flag, cons
   group[order[t]] = g;
 }
 
-// De[i][c] = sum_{j,s} r_ij / W_i (-P[q][s][c] B+ n + P[-q][s][c] B- (1+n)), c = 0..5
+// The electron drag of the current phonon iterate P (Eq. 22's Delta I^D
+// and its J counterpart):
+//   De[i][c] = sum_{j,s} r_ij / W_i (-n_qs P[q][s][c] B+ + (1 + n_qs) P[-q][s][c] B-),
+// q = k_j - k_i, r_ij = (1 - f_j) / (1 - f_i), c = 0..5.  The two phonon
+// factors depend on (q, s) only and are tabulated first, side by side:
+// uv[q][s][0..5] = -n_qs P[q][s], uv[q][s][6..11] = (1 + n_qs) P[-q][s]
+// (n at -q equals n at q), so a term reads one contiguous row.  The table
+// has the vertex store's number type: in the FP32 store it halves the bytes
+// gathered per term, at the store's own rounding.
+template <typename UT>
+__global__ void k_drag_uv(int64_t nm, int nbr, MeshDims md, const double* __restrict__ nocc,
+                          const double* __restrict__ phon, UT* __restrict__ uv) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nm * 12) return;
+  const int64_t m = t / 12;
+  const int c = (int)(t - m * 12);
+  const double n = nocc[m];
+  if (c < 6) {
+    uv[t] = (UT)(-n * phon[m * 6 + c]);
+  } else {
+    const int q = (int)(m / nbr), s = (int)(m - (int64_t)q * nbr);
+    const int mq = q_neg(q, md.n0, md.n1, md.n2);
+    uv[t] = (UT)((1.0 + n) * phon[((int64_t)mq * nbr + s) * 6 + c - 6]);
+  }
+}
+
+// One block per initial state i.  The j range goes in chunks of 256: the
+// chunk's q indices and occupation ratios are formed once per j into LDS,
+// then the block's threads take the chunk's (j, s) terms in order, reading
+// B+- along the row and the (q, s) row of uv.  Blocks are numbered so that
+// each XCD (blocks b, b + 8, ... dispatched to one) takes a contiguous range
+// of states: neighbouring states sit at neighbouring k, so the q windows
+// their rows visit overlap in that XCD's L2.
 template <typename ST, int NX>
-__global__ void __launch_bounds__(256) k_drag_e(int64_t M, MeshDims md, const ST* __restrict__ Bp,
+__global__ void __launch_bounds__(256) k_drag_e(int64_t M, int64_t per_xcd, MeshDims md, const ST* __restrict__ Bp,
                                                 const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
-                                                const double* __restrict__ lomf, const double* __restrict__ nocc,
-                                                const double* __restrict__ we, const double* __restrict__ phon,
-                                                double* __restrict__ De) {
+                                                const double* __restrict__ lomf, const double* __restrict__ we,
+                                                const ST* __restrict__ uv, double* __restrict__ De) {
+  __shared__ int sq[256];
+  __shared__ double sr[256];
   __shared__ double sh[6 * 4];
-  const int64_t i = blockIdx.x;
+  const int64_t i = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (i >= M) return;  // whole block
   const int ki = st_k[i];
   const double li = lomf[i];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const ST* __restrict__ bp = Bp + i * M * NX;
   const ST* __restrict__ bm = Bm + i * M * NX;
-  const int row = (int)(M * NX);
-  for (int t = threadIdx.x; t < row; t += 256) {
-    const double vp = (double)bp[t], vm = (double)bm[t];
-    if (vp == 0.0 && vm == 0.0) continue;
-    const int j = t / NX, s = t - j * NX;
-    const int q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
-    const int mq = q_neg(q, md.n0, md.n1, md.n2);
-    const double n = nocc[(int64_t)q * NX + s];
-    const double r = exp(lomf[j] - li);
-    const double a = -vp * n * r, b = vm * (1.0 + n) * r;
-    const double* pq = phon + ((int64_t)q * NX + s) * 6;
-    const double* pm = phon + ((int64_t)mq * NX + s) * 6;
+  for (int64_t j0 = 0; j0 < M; j0 += 256) {
+    const int nj = (int)(M - j0 < 256 ? M - j0 : 256);
+    __syncthreads();  // the previous chunk is consumed
+    if ((int)threadIdx.x < nj) {
+      const int64_t j = j0 + threadIdx.x;
+      sq[threadIdx.x] = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
+      sr[threadIdx.x] = exp(lomf[j] - li);
+    }
+    __syncthreads();
+    const ST* __restrict__ cp = bp + j0 * NX;
+    const ST* __restrict__ cm = bm + j0 * NX;
+    for (int t = threadIdx.x; t < nj * NX; t += 256) {
+      const double vp = (double)cp[t], vm = (double)cm[t];
+      if (vp == 0.0 && vm == 0.0) continue;
+      const int jl = t / NX, s = t - jl * NX;
+      const double r = sr[jl];
+      const ST* __restrict__ u = uv + ((int64_t)sq[jl] * NX + s) * 12;
+      const double a = r * vp, b = r * vm;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += a * pq[c] + b * pm[c];
+      for (int c = 0; c < 6; ++c) acc[c] += a * (double)u[c] + b * (double)u[6 + c];
+    }
   }
   block_sum<6>(acc, sh);
   double v = acc[0];
@@ -1449,7 +1490,9 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   double *we = nullptr, *wphe = nullptr, *wp = nullptr, *x0 = nullptr, *x = nullptr, *De = nullptr;
   double *phon0 = nullptr, *phon = nullptr, *phonn = nullptr, *acc = nullptr, *part = nullptr, *wff = nullptr;
   double *xprev = nullptr, *sbase = nullptr;
+  ST* uvt = nullptr;
   ALLOC(we, M * sizeof(double));
+  ALLOC(uvt, nm * 12 * sizeof(ST));
   ALLOC(wphe, nm * sizeof(double));
   ALLOC(wp, nm * sizeof(double));
   ALLOC(x0, M * 6 * sizeof(double));
@@ -1546,9 +1589,12 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
       // fixed point x = P(b + K x) solves L x = b with L = 1 - P K on the
       // range of P, started from the previous solution
       if (drag) {
-#define DE(NXV)                                                                                           \
-  hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)M), dim3(256), 0, s, M, md, Bp, Bm, ctx->d_state_k, \
-                     th.lomf, th.nocc, we, phon, De)
+        hipLaunchKernelGGL(k_drag_uv<ST>, dim3(blocks_for(nm * 12, 256)), dim3(256), 0, s, nm, (int)nbr, md,
+                           th.nocc, phon, uvt);
+        const int64_t per_xcd = (M + 7) / 8;
+#define DE(NXV)                                                                                                 \
+  hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, M, per_xcd, md, Bp, Bm, \
+                     ctx->d_state_k, th.lomf, we, uvt, De)
         switch (nbr) {
           case 3: DE(3); break;
           case 6: DE(6); break;
@@ -1710,7 +1756,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   if (iters) *iters = used;
   for (void* p : {(void*)we, (void*)wphe, (void*)wp, (void*)x0, (void*)x, (void*)De, (void*)phon0, (void*)phon,
                   (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase, (void*)wpp,
-                  (void*)t3, (void*)s3})
+                  (void*)t3, (void*)s3, (void*)uvt})
     dev_free(ctx, p);
   free_thermal(ctx, &th);
   if (!converged) {
