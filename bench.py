@@ -284,7 +284,21 @@ def run_batch(E, torch, steps, warmup, form="fp32", mats=None):
     t_seq = (time.perf_counter() - t0) / steps
     ref = [(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(we, wph)]
     batch = E.elph_batch_create(ctxs)
+
+    def batched_ms():
+        for _ in range(warmup):
+            E.elph_batch_scatt_rates(batch, T, we, wph, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            E.elph_batch_scatt_rates(batch, T, we, wph, use_graph=True)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    E.elph_batch_set_shape(batch, 2, True, 128)          # the untuned default shape
+    t_default = batched_ms()
     tune = E.elph_batch_tune(batch, T)
+    tune["default_shape_ms"] = t_default
     for _ in range(warmup):
         E.elph_batch_scatt_rates(batch, T, we, wph, use_graph=True)
     torch.cuda.synchronize()

@@ -470,12 +470,22 @@ const char* elph_batch_last_error(elph_batch b);
 elph_status elph_batch_scatt_rates(elph_batch b, double T_K, double* const* W_e, double* const* W_ph,
                                    int32_t use_graph);
 
-/* Autotuner: times each persistent-launch variant (blocks per compute unit
- * 1, 2, 4, 8 x work items in cost order or in natural order) on this batch,
- * keeps the fastest, and caches it for batches of the same shape.
- * choice (host, may be NULL) receives [blocks_per_cu, cost_ordered];
- * best_ms (host, may be NULL) the per-evaluation time of the winner. */
+/* Autotuner: times each launch shape of the persistent contractions (blocks
+ * per compute unit 1, 2, 4, 8 x work items in cost order or in natural
+ * order x, in FP32 batches, GEMM tiles of 64 or 128 rows by 64 columns) on
+ * this batch, keeps the fastest, and caches it for batches of the same
+ * signature (precision and each material's states, branches and contraction
+ * lengths).  The vertex epilogues of all materials run as persistent
+ * launches too.  Every shape gives bit-identical results.
+ * choice (host, may be NULL) receives [blocks_per_cu, cost_ordered,
+ * tile_rows]; best_ms (host, may be NULL) the per-evaluation time of the
+ * winner. */
 elph_status elph_batch_tune(elph_batch b, double T_K, int32_t* choice, double* best_ms);
+
+/* Sets a launch shape explicitly (as one of the tuner's candidates):
+ * blocks_per_cu 1, 2, 4 or 8; cost_ordered 0 or 1; tile_rows 64 or 128 (FP32
+ * batches; FP64 batches take 128).  EINVAL otherwise. */
+elph_status elph_batch_set_shape(elph_batch b, int32_t blocks_per_cu, int32_t cost_ordered, int32_t tile_rows);
 
 /* ---------------------------------------------------------------------------
  * Learned screen of negligible terms.  A small MLP predicts log10 |g|^2

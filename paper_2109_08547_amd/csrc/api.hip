@@ -987,12 +987,26 @@ extern "C" elph_status elph_batch_tune(elph_batch b, double T_K, int32_t* choice
     b->err = "temperature must be positive";
     return ELPH_EINVAL;
   }
-  int ch[2] = {0, 0};
+  int ch[3] = {0, 0, 0};
   elph_status st = batch_tune(b->impl, T_K, ch, best_ms);
   if (st != ELPH_OK) b->err = batch_error(b->impl);
   if (choice) {
     choice[0] = ch[0];
     choice[1] = ch[1];
+    choice[2] = ch[2];
   }
+  return st;
+}
+
+extern "C" elph_status elph_batch_set_shape(elph_batch b, int32_t blocks_per_cu, int32_t cost_ordered,
+                                            int32_t tile_rows) {
+  if (!b) return ELPH_EINVAL;
+  b->err.clear();
+  if (tile_rows != 64 && tile_rows != 128) {
+    b->err = "tile rows must be 64 or 128";
+    return ELPH_EINVAL;
+  }
+  elph_status st = batch_set_shape(b->impl, blocks_per_cu, cost_ordered != 0, tile_rows / 32);
+  if (st != ELPH_OK) b->err = batch_error(b->impl);
   return st;
 }

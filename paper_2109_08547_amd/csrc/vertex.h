@@ -115,6 +115,7 @@ BatchImpl* batch_new(const std::vector<elph_ctx>& ctxs, std::string* err);
 void batch_free(BatchImpl* b);
 elph_status batch_rates(BatchImpl* b, double T_K, double* const* we, double* const* wph, bool use_graph);
 elph_status batch_tune(BatchImpl* b, double T_K, int* choice, double* best_ms);
+elph_status batch_set_shape(BatchImpl* b, int bpc, bool sorted, int wr);
 const std::string& batch_error(BatchImpl* b);
 
 }  // namespace elph

@@ -1074,14 +1074,12 @@ struct GemmOp<float> {
 // states) and write g_s = sum_x l u gh_x, |g|^2 and the Gaussians into the
 // store B+/-.
 template <typename ST, int NX>
-__global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t0, int32_t t1, EpiParams ep,
-                                               const int32_t* __restrict__ kept, const int32_t* __restrict__ kidx,
-                                               const int32_t* __restrict__ soff, const int32_t* __restrict__ poff,
-                                               const int32_t* __restrict__ plist, const float* __restrict__ C,
-                                               int64_t ldc, ST* __restrict__ Bp, ST* __restrict__ Bm) {
+__device__ __forceinline__ void epi_q_wave(int64_t q, int64_t i0, int32_t t0, int32_t t1, const EpiParams& ep,
+                                           const int32_t* __restrict__ kept, const int32_t* __restrict__ kidx,
+                                           const int32_t* __restrict__ soff, const int32_t* __restrict__ poff,
+                                           const int32_t* __restrict__ plist, const float* __restrict__ C,
+                                           int64_t ldc, ST* __restrict__ Bp, ST* __restrict__ Bm) {
   const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (q >= nq) return;  // whole wavefront exits together
   const int qc = (int)(q % ep.n2);
   const int qt = (int)(q / ep.n2);
   const int qb = qt % ep.n1, qa = qt / ep.n1;
@@ -1178,14 +1176,24 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
   }
 }
 
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t0, int32_t t1, EpiParams ep,
+                                               const int32_t* __restrict__ kept, const int32_t* __restrict__ kidx,
+                                               const int32_t* __restrict__ soff, const int32_t* __restrict__ poff,
+                                               const int32_t* __restrict__ plist, const float* __restrict__ C,
+                                               int64_t ldc, ST* __restrict__ Bp, ST* __restrict__ Bm) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (q >= nq) return;  // whole wavefront exits together
+  epi_q_wave<ST, NX>(q, i0, t0, t1, ep, kept, kidx, soff, poff, plist, C, ldc, Bp, Bm);
+}
+
 // Step-1 epilogue of the GEMM path: B2[(i, x)][(Rp, n')] = C1[i][col] e^{-2 pi i k_i.Rp}
 // written in the form's operand format; col = (x, Rp, n'), rows [i0, i0 + ni).
 template <typename T>
-__global__ void k_step1_epi(int64_t i0, int64_t ni, int64_t ncol, int nrp, int nb, int nbr, int64_t kp,
-                            const float* __restrict__ C1, const int32_t* __restrict__ st_kidx,
-                            const cd* __restrict__ Ep, double scale, typename Store<T>::type* __restrict__ B2) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ni * ncol) return;
+__device__ __forceinline__ void step1_epi_elem(int64_t e, int64_t i0, int64_t ncol, int nrp, int nb, int nbr,
+                                               int64_t kp, const float* __restrict__ C1,
+                                               const int32_t* __restrict__ st_kidx, const cd* __restrict__ Ep,
+                                               double scale, typename Store<T>::type* __restrict__ B2) {
   const int64_t il = e / ncol, col = e - il * ncol;
   const int64_t i = i0 + il;
   const int64_t per_x = (int64_t)nrp * nb;
@@ -1195,6 +1203,15 @@ __global__ void k_step1_epi(int64_t i0, int64_t ni, int64_t ncol, int nrp, int n
   const float2 v = *reinterpret_cast<const float2*>(C1 + 2 * e);
   const cd z = cmulc(cmake(v.x, v.y), Ep[(int64_t)st_kidx[i] * nrp + rp]);  // * conj(phase)
   PutC<T>::put(B2, i * nbr + x, kp, rem, z.x * scale, z.y * scale);
+}
+
+template <typename T>
+__global__ void k_step1_epi(int64_t i0, int64_t ni, int64_t ncol, int nrp, int nb, int nbr, int64_t kp,
+                            const float* __restrict__ C1, const int32_t* __restrict__ st_kidx,
+                            const cd* __restrict__ Ep, double scale, typename Store<T>::type* __restrict__ B2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ni * ncol) return;
+  step1_epi_elem<T>(e, i0, ncol, nrp, nb, nbr, kp, C1, st_kidx, Ep, scale, B2);
 }
 
 // ---------------------------------------------------------------------------
@@ -1915,6 +1932,71 @@ elph_status step1_fp64_rows(elph_ctx ctx, int64_t ns, const int32_t* st_kidx, co
 // longest contraction first; the whole per-temperature sequence can be
 // captured in a HIP graph and replayed.
 
+// Per-material descriptors of the batched epilogues.
+template <typename ST>
+struct EpiDesc {
+  EpiParams ep;
+  const int32_t* kept;
+  const int32_t* kidx;
+  const int32_t* soff;
+  const int32_t* poff;
+  const int32_t* plist;
+  const float* C;
+  int64_t ldc, nq;
+  int32_t nkept;
+  ST* Bp;
+  ST* Bm;
+};
+
+template <typename T>
+struct S1EpiDesc {
+  int64_t M, ncol, kp;
+  int nrp, nb, nbr;
+  const float* C1;
+  const int32_t* st_kidx;
+  const cd* Ep;
+  double scale;
+  typename Store<T>::type* B2;
+};
+
+// The per-q epilogue of every material of one branch count in one launch:
+// items (slot, q / 4), taken grid-stride; a block's four wavefronts take
+// four q, each exactly as k_epi_q does.
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_epi_q_persist(const EpiDesc<ST>* __restrict__ d,
+                                                       const int2* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    EpiDesc<ST> e = d[w.x];
+    promote(e.ep);
+    const int64_t q = (int64_t)w.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (q < e.nq)
+      epi_q_wave<ST, NX>(q, 0, 0, e.nkept, e.ep, as_global(e.kept), as_global(e.kidx), as_global(e.soff),
+                         as_global(e.poff), as_global(e.plist), as_global(e.C), e.ldc, as_global(e.Bp),
+                         as_global(e.Bm));
+  }
+}
+
+// The step-1 epilogue of every material in one launch: 256-element blocks
+// numbered across the materials (boff), taken grid-stride.
+template <typename T>
+__global__ void __launch_bounds__(256) k_step1_epi_persist(const S1EpiDesc<T>* __restrict__ d,
+                                                           const int32_t* __restrict__ boff, int n, int nblocks) {
+  for (int g = blockIdx.x; g < nblocks; g += gridDim.x) {
+    int lo = 0, hi = n - 1;  // material m with boff[m] <= g < boff[m + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (boff[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const S1EpiDesc<T> e = d[lo];
+    const int64_t el = (int64_t)(g - boff[lo]) * 256 + threadIdx.x;
+    if (el < e.M * e.ncol)
+      step1_epi_elem<T>(el, 0, e.ncol, e.nrp, e.nb, e.nbr, e.kp, as_global(e.C1), as_global(e.st_kidx),
+                        as_global(e.Ep), e.scale, as_global(e.B2));
+  }
+}
+
 struct BatchImpl {
   struct Cls {
     int nx = 0;
@@ -1952,12 +2034,29 @@ struct BatchImpl {
   GemmArgs* d_g2 = nullptr;
   int4* d_g1items = nullptr;
   int4* d_g2items = nullptr;
-  std::vector<int4> g1_natural, g1_sorted, g2_natural, g2_sorted;
+  // item lists per GEMM tile height (index 0: 64 rows, 1: 128 rows)
+  std::vector<int4> g1_natural[2], g1_sorted[2], g2_natural[2], g2_sorted[2];
+  int wr = kGemmWR;                // rows per GEMM tile / 32 (2 or 4)
   std::vector<float*> c1, c2;
+  // persistent epilogues: the step-1 epilogue over every material, the
+  // per-q epilogue over the materials of each branch count
+  void* d_s1epi = nullptr;         // S1EpiDesc<T>[n]
+  int32_t* d_s1boff = nullptr;     // [n + 1] first 256-element block of each material
+  int s1blocks = 0;
+  std::vector<void*> d_epi;        // per class: EpiDesc<ST>[mats]
+  std::vector<int2*> d_epi_items;  // per class: (slot, q / 4)
+  std::vector<int> epi_items;
 };
 
-static std::map<std::string, std::pair<int, bool>>& tune_cache() {
-  static std::map<std::string, std::pair<int, bool>> c;
+// tuned launch shape of a batch: blocks per CU, cost order, GEMM tile rows / 32
+struct BatchShape {
+  int bpc;
+  bool sorted;
+  int wr;
+};
+
+static std::map<std::string, BatchShape>& tune_cache() {
+  static std::map<std::string, BatchShape> c;
   return c;
 }
 
@@ -2076,28 +2175,93 @@ static elph_status batch_prepare_t(BatchImpl* b) {
                        (float*)p1, ncol};
       g2[m] = GemmArgs{0, M * c->nbr, M, c->kp, c->nbr, (const unsigned short*)c->d_B2,
                        (const unsigned short*)c->d_Ap, (float*)p2, c->m_pad};
-      for (const auto& pr : {std::make_pair(&g1[m], &b->g1_natural), std::make_pair(&g2[m], &b->g2_natural)}) {
-        const GemmGrid gg = gemm_grid(pr.first->nc, pr.first->nj, 32 * kGemmWR);
-        for (int ty = 0; ty < gg.ny; ++ty)
-          for (int tx = 0; tx < gg.nx; ++tx) pr.second->push_back(make_int4(m, ty, tx, 0));
-      }
+      for (int h = 0; h < 2; ++h)
+        for (const auto& pr : {std::make_pair(&g1[m], &b->g1_natural[h]), std::make_pair(&g2[m], &b->g2_natural[h])}) {
+          const GemmGrid gg = gemm_grid(pr.first->nc, pr.first->nj, 32 * (2 + 2 * h));
+          for (int ty = 0; ty < gg.ny; ++ty)
+            for (int tx = 0; tx < gg.nx; ++tx) pr.second->push_back(make_int4(m, ty, tx, 0));
+        }
     }
-    b->g1_sorted = b->g1_natural;
-    std::stable_sort(b->g1_sorted.begin(), b->g1_sorted.end(),
-                     [&](const int4& a, const int4& c2) { return g1[a.x].K > g1[c2.x].K; });
-    b->g2_sorted = b->g2_natural;
-    std::stable_sort(b->g2_sorted.begin(), b->g2_sorted.end(),
-                     [&](const int4& a, const int4& c2) { return g2[a.x].K > g2[c2.x].K; });
+    for (int h = 0; h < 2; ++h) {
+      b->g1_sorted[h] = b->g1_natural[h];
+      std::stable_sort(b->g1_sorted[h].begin(), b->g1_sorted[h].end(),
+                       [&](const int4& a, const int4& c2) { return g1[a.x].K > g1[c2.x].K; });
+      b->g2_sorted[h] = b->g2_natural[h];
+      std::stable_sort(b->g2_sorted[h].begin(), b->g2_sorted[h].end(),
+                       [&](const int4& a, const int4& c2) { return g2[a.x].K > g2[c2.x].K; });
+    }
+    // epilogue descriptors (the thermal buffers and results stay in place)
+    std::vector<S1EpiDesc<T>> e1(n);
+    std::vector<int32_t> boff(n + 1, 0);
+    for (int m = 0; m < n; ++m) {
+      elph_ctx c = b->ctx[m];
+      S1EpiDesc<T>& e = e1[m];
+      e.M = c->nstates;
+      e.ncol = (int64_t)c->nbr * c->nrp * c->nb;
+      e.kp = c->kp;
+      e.nrp = c->nrp;
+      e.nb = c->nb;
+      e.nbr = c->nbr;
+      e.C1 = b->c1[m];
+      e.st_kidx = c->d_state_kidx;
+      e.Ep = (const cd*)c->d_Ep;
+      e.scale = c->sc_b2 / (c->sc_ae * c->sc_g);
+      e.B2 = (typename Store<T>::type*)c->d_B2;
+      boff[m + 1] = boff[m] + (int32_t)((e.M * e.ncol + 255) / 256);
+    }
+    b->s1blocks = boff[n];
     if (balloc(b, (void**)&b->d_g1, n * sizeof(GemmArgs)) != hipSuccess ||
         balloc(b, (void**)&b->d_g2, n * sizeof(GemmArgs)) != hipSuccess ||
-        balloc(b, (void**)&b->d_g1items, b->g1_natural.size() * sizeof(int4)) != hipSuccess ||
-        balloc(b, (void**)&b->d_g2items, b->g2_natural.size() * sizeof(int4)) != hipSuccess ||
-        balloc(b, (void**)&b->d_counters, 64 * sizeof(int)) != hipSuccess) {
+        balloc(b, (void**)&b->d_g1items, b->g1_natural[0].size() * sizeof(int4)) != hipSuccess ||
+        balloc(b, (void**)&b->d_g2items, b->g2_natural[0].size() * sizeof(int4)) != hipSuccess ||
+        balloc(b, (void**)&b->d_counters, 64 * sizeof(int)) != hipSuccess ||
+        balloc(b, &b->d_s1epi, n * sizeof(S1EpiDesc<T>)) != hipSuccess ||
+        balloc(b, (void**)&b->d_s1boff, (n + 1) * sizeof(int32_t)) != hipSuccess) {
       b->err = "batch allocation failed";
       return ELPH_ENOMEM;
     }
     BCHK(hipMemcpy(b->d_g1, g1.data(), n * sizeof(GemmArgs), hipMemcpyHostToDevice));
     BCHK(hipMemcpy(b->d_g2, g2.data(), n * sizeof(GemmArgs), hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(b->d_s1epi, e1.data(), n * sizeof(S1EpiDesc<T>), hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(b->d_s1boff, boff.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    for (auto& cl : b->cls) {
+      std::vector<EpiDesc<T>> d(cl.mats.size());
+      std::vector<int2> items;
+      for (size_t slot = 0; slot < cl.mats.size(); ++slot) {
+        const int m = cl.mats[slot];
+        elph_ctx c = b->ctx[m];
+        EpiDesc<T>& e = d[slot];
+        e.ep = epi_params(c);
+        e.ep.lomf = b->th[m].lomf;
+        e.ep.fstate = b->th[m].f;
+        e.ep.omf = b->th[m].omf;
+        e.ep.nocc = b->th[m].nocc;
+        e.ep.we_part = c->d_we_part;
+        e.kept = c->d_kept;
+        e.kidx = c->d_kidx;
+        e.soff = c->d_soff;
+        e.poff = c->d_poff;
+        e.plist = c->d_plist;
+        e.C = b->c2[m];
+        e.ldc = c->m_pad;
+        e.nq = c->nk;
+        e.nkept = (int32_t)c->nkept;
+        e.Bp = (T*)c->d_Bp;
+        e.Bm = (T*)c->d_Bm;
+        for (int64_t qb = 0; qb < (c->nk + 3) / 4; ++qb) items.push_back(make_int2((int)slot, (int)qb));
+      }
+      void *dd = nullptr, *di = nullptr;
+      if (balloc(b, &dd, d.size() * sizeof(EpiDesc<T>)) != hipSuccess ||
+          balloc(b, &di, items.size() * sizeof(int2)) != hipSuccess) {
+        b->err = "batch allocation failed";
+        return ELPH_ENOMEM;
+      }
+      BCHK(hipMemcpy(dd, d.data(), d.size() * sizeof(EpiDesc<T>), hipMemcpyHostToDevice));
+      BCHK(hipMemcpy(di, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
+      b->d_epi.push_back(dd);
+      b->d_epi_items.push_back((int2*)di);
+      b->epi_items.push_back((int)items.size());
+    }
     b->prepared = true;
     return ELPH_OK;
   }
@@ -2149,8 +2313,9 @@ static elph_status batch_prepare_t(BatchImpl* b) {
 
 static elph_status batch_upload_order(BatchImpl* b) {
   if (b->gemm) {
-    const std::vector<int4>& a = b->sorted ? b->g1_sorted : b->g1_natural;
-    const std::vector<int4>& c = b->sorted ? b->g2_sorted : b->g2_natural;
+    const int h = b->wr == 2 ? 0 : 1;
+    const std::vector<int4>& a = b->sorted ? b->g1_sorted[h] : b->g1_natural[h];
+    const std::vector<int4>& c = b->sorted ? b->g2_sorted[h] : b->g2_natural[h];
     BCHK(hipMemcpy(b->d_g1items, a.data(), a.size() * sizeof(int4), hipMemcpyHostToDevice));
     BCHK(hipMemcpy(b->d_g2items, c.data(), c.size() * sizeof(int4), hipMemcpyHostToDevice));
     return ELPH_OK;
@@ -2184,12 +2349,6 @@ static elph_status batch_launch_step2(BatchImpl* b, BatchImpl::Cls& cl, int* cou
   return ELPH_OK;
 }
 
-template <typename ST, int NX>
-static void batch_epi_q(elph_ctx c, const EpiParams& ep, const float* C, hipStream_t s) {
-  hipLaunchKernelGGL((k_epi_q<ST, NX>), dim3((unsigned)((c->nk + 3) / 4)), dim3(256), 0, s, c->nk, (int64_t)0, 0,
-                     (int32_t)c->nkept, ep, c->d_kept, c->d_kidx, c->d_soff, c->d_poff, c->d_plist, C, c->m_pad,
-                     (ST*)c->d_Bp, (ST*)c->d_Bm);
-}
 
 // GEMM forms: two persistent GEMM launches over all materials, each
 // material's step-1 and step-2 epilogues, W_e from the store rows and W_ph.
@@ -2201,37 +2360,42 @@ static elph_status batch_sequence_gemm(BatchImpl* b, double T_K, double* const* 
   StreamSwap sw(b);
   for (int m = 0; m < n; ++m) fill_thermal(b->ctx[m], T_K, b->th[m], b->stream);
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, b->stream, b->d_counters, 64);
-  const int n1 = (int)b->g1_natural.size(), n2 = (int)b->g2_natural.size();
-  hipLaunchKernelGGL((k_cgemm_persist<OP, 1, kGemmWR>), dim3((unsigned)std::min<int64_t>(n1, (int64_t)b->bpc * b->ncu)),
-                     dim3(128 * kGemmWR), 0, b->stream, (const GemmArgs*)b->d_g1, b->d_g1items, n1, b->d_counters);
-  for (int m = 0; m < n; ++m) {
-    elph_ctx c = b->ctx[m];
-    const int64_t M = c->nstates, ncol = (int64_t)c->nbr * c->nrp * c->nb;
-    hipLaunchKernelGGL(k_step1_epi<T>, dim3(blocks_for(M * ncol, 256)), dim3(256), 0, b->stream, (int64_t)0, M, ncol,
-                       c->nrp, c->nb, c->nbr, c->kp, (const float*)b->c1[m], c->d_state_kidx, (const cd*)c->d_Ep,
-                       c->sc_b2 / (c->sc_ae * c->sc_g), (typename Store<T>::type*)c->d_B2);
-  }
-  hipLaunchKernelGGL((k_cgemm_persist<OP, 2, kGemmWR>), dim3((unsigned)std::min<int64_t>(n2, (int64_t)b->bpc * b->ncu)),
-                     dim3(128 * kGemmWR), 0, b->stream, (const GemmArgs*)b->d_g2, b->d_g2items, n2,
-                     b->d_counters + 1);
-  for (int m = 0; m < n; ++m) {
-    elph_ctx c = b->ctx[m];
-    EpiParams ep = epi_params(c);
-    ep.lomf = b->th[m].lomf;
-    ep.fstate = b->th[m].f;
-    ep.omf = b->th[m].omf;
-    ep.nocc = b->th[m].nocc;
-    ep.we_part = c->d_we_part;
-    const float* C = b->c2[m];
-    switch (c->nbr) {
-      case 3: batch_epi_q<ST, 3>(c, ep, C, b->stream); break;
-      case 6: batch_epi_q<ST, 6>(c, ep, C, b->stream); break;
-      case 9: batch_epi_q<ST, 9>(c, ep, C, b->stream); break;
-      case 12: batch_epi_q<ST, 12>(c, ep, C, b->stream); break;
-      case 15: batch_epi_q<ST, 15>(c, ep, C, b->stream); break;
+  const int h = b->wr == 2 ? 0 : 1;
+  const int n1 = (int)b->g1_natural[h].size(), n2 = (int)b->g2_natural[h].size();
+  const unsigned g1b = (unsigned)std::min<int64_t>(n1, (int64_t)b->bpc * b->ncu);
+  const unsigned g2b = (unsigned)std::min<int64_t>(n2, (int64_t)b->bpc * b->ncu);
+  if (b->wr == 2)
+    hipLaunchKernelGGL((k_cgemm_persist<OP, 1, 2>), dim3(g1b), dim3(256), 0, b->stream, (const GemmArgs*)b->d_g1,
+                       b->d_g1items, n1, b->d_counters);
+  else
+    hipLaunchKernelGGL((k_cgemm_persist<OP, 1, 4>), dim3(g1b), dim3(512), 0, b->stream, (const GemmArgs*)b->d_g1,
+                       b->d_g1items, n1, b->d_counters);
+  hipLaunchKernelGGL(k_step1_epi_persist<T>, dim3((unsigned)std::min<int64_t>(b->s1blocks, 8 * (int64_t)b->ncu)),
+                     dim3(256), 0, b->stream, (const S1EpiDesc<T>*)b->d_s1epi, b->d_s1boff, n, b->s1blocks);
+  if (b->wr == 2)
+    hipLaunchKernelGGL((k_cgemm_persist<OP, 2, 2>), dim3(g2b), dim3(256), 0, b->stream, (const GemmArgs*)b->d_g2,
+                       b->d_g2items, n2, b->d_counters + 1);
+  else
+    hipLaunchKernelGGL((k_cgemm_persist<OP, 2, 4>), dim3(g2b), dim3(512), 0, b->stream, (const GemmArgs*)b->d_g2,
+                       b->d_g2items, n2, b->d_counters + 1);
+  for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+    const unsigned eg = (unsigned)std::min<int64_t>(b->epi_items[ci], 8 * (int64_t)b->ncu);
+    const EpiDesc<ST>* d = (const EpiDesc<ST>*)b->d_epi[ci];
+#define EQP(NXV) \
+  hipLaunchKernelGGL((k_epi_q_persist<ST, NXV>), dim3(eg), dim3(256), 0, b->stream, d, b->d_epi_items[ci], b->epi_items[ci])
+    switch (b->cls[ci].nx) {
+      case 3: EQP(3); break;
+      case 6: EQP(6); break;
+      case 9: EQP(9); break;
+      case 12: EQP(12); break;
+      case 15: EQP(15); break;
       default: b->err = "unsupported branch count"; return ELPH_EINVAL;
     }
-    launch_we_rows<ST>(c, (const ST*)c->d_Bp, (const ST*)c->d_Bm, ep.lomf, ep.nocc, c->d_we_part);
+#undef EQP
+  }
+  for (int m = 0; m < n; ++m) {
+    elph_ctx c = b->ctx[m];
+    launch_we_rows<ST>(c, (const ST*)c->d_Bp, (const ST*)c->d_Bm, b->th[m].lomf, b->th[m].nocc, c->d_we_part);
     double* wout = (we && we[m]) ? we[m] : b->we_tmp[m];
     hipLaunchKernelGGL(k_reduce_we, dim3(blocks_for(c->nstates, 256)), dim3(256), 0, b->stream, c->d_we_part,
                        (int64_t)1, c->m_pad, c->nstates, wout);
@@ -2325,8 +2489,9 @@ static elph_status batch_prepare(BatchImpl* b) {
   if (st != ELPH_OK) return st;
   auto it = tune_cache().find(batch_signature(b));
   if (it != tune_cache().end()) {
-    b->bpc = it->second.first;
-    b->sorted = it->second.second;
+    b->bpc = it->second.bpc;
+    b->sorted = it->second.sorted;
+    b->wr = it->second.wr;
     b->tuned = true;
   }
   return batch_upload_order(b);
@@ -2373,8 +2538,46 @@ elph_status batch_rates(BatchImpl* b, double T_K, double* const* we, double* con
   return ELPH_OK;
 }
 
-// Autotuner: time every (blocks per CU, item order) variant of the two
-// persistent contraction launches and keep the fastest for this signature.
+// Autotuner: time every launch shape of the persistent contractions (blocks
+// per CU 1, 2, 4, 8 x item order x, in the GEMM forms, tile height 64 or
+// 128 rows) on this batch and keep the fastest for its signature.  Every
+// shape computes each output exactly as any other (the k order of a sum
+// does not depend on the tile), so the choice changes time only.
+static elph_status batch_time_shape(BatchImpl* b, double T_K, hipEvent_t e0, hipEvent_t e1, double* ms_out) {
+  elph_status st = batch_upload_order(b);
+  if (st != ELPH_OK) return st;
+  st = batch_run(b, T_K, nullptr, nullptr);  // warm
+  if (st != ELPH_OK) return st;
+  BCHK(hipEventRecord(e0, b->stream));
+  for (int rep = 0; rep < 2; ++rep) {
+    st = batch_run(b, T_K, nullptr, nullptr);
+    if (st != ELPH_OK) return st;
+  }
+  BCHK(hipEventRecord(e1, b->stream));
+  BCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  BCHK(hipEventElapsedTime(&ms, e0, e1));
+  *ms_out = ms / 2.0;
+  return ELPH_OK;
+}
+
+elph_status batch_set_shape(BatchImpl* b, int bpc, bool sorted, int wr) {
+  elph_status st = batch_prepare(b);
+  if (st != ELPH_OK) return st;
+  if ((bpc != 1 && bpc != 2 && bpc != 4 && bpc != 8) || (wr != 2 && wr != 4) || (!b->gemm && wr != kGemmWR)) {
+    b->err = "launch shape: blocks per CU 1, 2, 4 or 8; tile rows 64 or 128 (FP32 batches; 128 in FP64)";
+    return ELPH_EINVAL;
+  }
+  b->bpc = bpc;
+  b->sorted = sorted;
+  b->wr = wr;
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  return batch_upload_order(b);
+}
+
 elph_status batch_tune(BatchImpl* b, double T_K, int* choice, double* best_ms) {
   elph_status st = batch_prepare(b);
   if (st != ELPH_OK) return st;
@@ -2382,45 +2585,41 @@ elph_status batch_tune(BatchImpl* b, double T_K, int* choice, double* best_ms) {
   BCHK(hipEventCreate(&e0));
   BCHK(hipEventCreate(&e1));
   double best = 1e300;
-  int best_bpc = b->bpc;
-  bool best_sorted = b->sorted;
-  for (int bpc : {1, 2, 4, 8}) {
-    for (int so = 0; so < 2; ++so) {
-      b->bpc = bpc;
-      b->sorted = so == 1;
-      st = batch_upload_order(b);
-      if (st != ELPH_OK) return st;
-      st = batch_run(b, T_K, nullptr, nullptr);  // warm
-      if (st != ELPH_OK) return st;
-      BCHK(hipEventRecord(e0, b->stream));
-      for (int rep = 0; rep < 2; ++rep) {
-        st = batch_run(b, T_K, nullptr, nullptr);
-        if (st != ELPH_OK) return st;
+  BatchShape win{b->bpc, b->sorted, b->wr};
+  const std::vector<int> heights = b->gemm ? std::vector<int>{2, 4} : std::vector<int>{kGemmWR};
+  for (int wr : heights)
+    for (int bpc : {1, 2, 4, 8})
+      for (int so = 0; so < 2; ++so) {
+        b->bpc = bpc;
+        b->sorted = so == 1;
+        b->wr = wr;
+        double ms = 0.0;
+        st = batch_time_shape(b, T_K, e0, e1, &ms);
+        if (st != ELPH_OK) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return st;
+        }
+        if (ms < best) {
+          best = ms;
+          win = BatchShape{bpc, so == 1, wr};
+        }
       }
-      BCHK(hipEventRecord(e1, b->stream));
-      BCHK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      BCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms / 2.0 < best) {
-        best = ms / 2.0;
-        best_bpc = bpc;
-        best_sorted = so == 1;
-      }
-    }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->bpc = best_bpc;
-  b->sorted = best_sorted;
+  b->bpc = win.bpc;
+  b->sorted = win.sorted;
+  b->wr = win.wr;
   b->tuned = true;
-  tune_cache()[batch_signature(b)] = {best_bpc, best_sorted};
+  tune_cache()[batch_signature(b)] = win;
   if (b->gexec) {
     (void)hipGraphExecDestroy(b->gexec);
     b->gexec = nullptr;
   }
   if (choice) {
-    choice[0] = best_bpc;
-    choice[1] = best_sorted ? 1 : 0;
+    choice[0] = win.bpc;
+    choice[1] = win.sorted ? 1 : 0;
+    choice[2] = 32 * win.wr;
   }
   if (best_ms) *best_ms = best;
   return batch_upload_order(b);

@@ -44,7 +44,7 @@ class ElphSizes(ctypes.Structure):
 
 EXPORTS = ("elph_create", "elph_destroy", "elph_last_error", "elph_reset", "elph_timing", "elph_sizes",
            "elph_batch_create", "elph_batch_destroy", "elph_batch_last_error", "elph_batch_scatt_rates",
-           "elph_batch_tune", "elph_tables", "elph_timing_extra", "elph_set_refine", "elph_refine_info", "elph_save", "elph_load", "elph_set_memory_limit",
+           "elph_batch_tune", "elph_batch_set_shape", "elph_tables", "elph_timing_extra", "elph_set_refine", "elph_refine_info", "elph_save", "elph_load", "elph_set_memory_limit",
            "elph_memory_held", "elph_set_gemm_chunk",
            "elph_refine_estimates",
            "elph_interp_g", "elph_interp_g_noalloc", "elph_transition_probs", "elph_scatt_rates", "elph_iterate", "elph_ko_enforce", "elph_set_delta", "elph_set_polar",
@@ -110,6 +110,7 @@ def load():
     lib.elph_batch_scatt_rates.argtypes = [vp, ctypes.c_double, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                            ctypes.c_int32]
     lib.elph_batch_tune.argtypes = [vp, ctypes.c_double, vp, vp]
+    lib.elph_batch_set_shape.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.elph_mlp_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.POINTER(vp)]
     lib.elph_mlp_destroy.argtypes = [vp]
     lib.elph_mlp_destroy.restype = None
@@ -431,11 +432,17 @@ def elph_batch_scatt_rates(batch, T, W_e=None, W_ph=None, use_graph=True):
 
 
 def elph_batch_tune(batch, T):
-    ch = np.zeros(2, dtype=np.int32)
+    ch = np.zeros(3, dtype=np.int32)
     best = ctypes.c_double(0.0)
     batch._check(load().elph_batch_tune(batch.handle, float(T), ch.ctypes.data_as(ctypes.c_void_p),
                                         ctypes.byref(best)))
-    return {"blocks_per_cu": int(ch[0]), "cost_ordered": bool(ch[1]), "best_ms": best.value}
+    return {"blocks_per_cu": int(ch[0]), "cost_ordered": bool(ch[1]), "tile_rows": int(ch[2]),
+            "best_ms": best.value}
+
+
+def elph_batch_set_shape(batch, blocks_per_cu, cost_ordered, tile_rows):
+    batch._check(load().elph_batch_set_shape(batch.handle, int(blocks_per_cu), int(bool(cost_ordered)),
+                                             int(tile_rows)))
 
 
 # ---------------------------------------------------------------------------

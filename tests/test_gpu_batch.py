@@ -60,15 +60,27 @@ def test_batch_equals_single_contexts(precision):
         c.close()
     ctxs = [_ctx(cfg, mat, precision) for cfg, mat in mats]
     batch = E.elph_batch_create(ctxs)
-    for use_graph in (False, True, True, "tuned"):   # plain, capture, replay, after the tuner
-        if use_graph == "tuned":
-            E.elph_batch_tune(batch, T)                  # other grids and item orders, same blocks
+    # every launch shape the tuner may pick, set explicitly, then the tuner's
+    # own pick, with graph capture and replay
+    heights = (64, 128) if precision == "fp32" else (128,)
+    shapes = [(bpc, so, h) for h in heights for bpc in (1, 2, 4, 8) for so in (0, 1)]
+    runs = [("shape", sh, False) for sh in shapes] + [("plain", None, False), ("plain", None, True),
+                                                      ("plain", None, True), ("tuned", None, True)]
+    for kind, shape, use_graph in runs:
+        if kind == "shape":
+            E.elph_batch_set_shape(batch, *shape)
+        elif kind == "tuned":
+            ch = E.elph_batch_tune(batch, T)             # other grids, item orders and tiles, same blocks
+            assert ch["tile_rows"] in heights and ch["blocks_per_cu"] in (1, 2, 4, 8)
         we, wph = _outputs(ctxs)
         E.elph_batch_scatt_rates(batch, T, we, wph, use_graph=bool(use_graph))
         torch.cuda.synchronize()
         for m in range(len(mats)):
-            assert np.array_equal(we[m].cpu().numpy(), single[m][0]), (use_graph, m)
-            assert np.array_equal(wph[m].cpu().numpy(), single[m][1]), (use_graph, m)
+            assert np.array_equal(we[m].cpu().numpy(), single[m][0]), (kind, shape, use_graph, m)
+            assert np.array_equal(wph[m].cpu().numpy(), single[m][1]), (kind, shape, use_graph, m)
+    with pytest.raises(E.ElphError) as ei:                # not a candidate shape
+        E.elph_batch_set_shape(batch, 3, 1, 128)
+    assert ei.value.status == E.elph.ELPH_EINVAL
     batch.close()
     for c in ctxs:
         c.close()
