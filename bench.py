@@ -419,7 +419,14 @@ def run_large(E, torch, form="fp32", mat=None, cpu_rows=0):
 # tetrahedra around the final point, each with four corner energies (2 ops
 # each), the sign count, a six-exchange sort and the section formula (~15)
 TETRA_OPS = 24 * 35
+# and of the triangle scaling: 6 triangles of the final point's plane, three
+# corner energies (2 ops each), the sign count, a three-exchange sort and the
+# segment formula (~10)
+TRI_OPS = 6 * 22
 VARIANTS = {
+    "triangle48": "mixed48 (8 bands, 2 atoms, 48^3, 3% of k) with the triangle delta (mesh planes normal to the "
+                  "third axis) instead of the Gaussian, FP16x3 contractions; a step = tables + vertices + store + "
+                  "triangle scaling + rates + one phonon step of the iteration",
     "tetra48": "mixed48 (8 bands, 2 atoms, 48^3, 3% of k) with the analytic tetrahedron delta instead of the "
                "Gaussian, FP16x3 contractions; a step = tables + vertices + store + tetrahedron scaling + rates + "
                "one phonon step of the iteration",
@@ -445,20 +452,23 @@ def run_variant(E, torch, kind, steps, warmup, cpu=True, budget_s=20.0):
             E.elph_set_polar(ctx, Z, eps, tau)
     else:
         omat = mat
+        method = E.elph.ELPH_DELTA_TETRA if kind == "tetra48" else E.elph.ELPH_DELTA_TRIANGLE
 
         def setup(ctx):
-            E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+            E.elph_set_delta(ctx, method)
     print("bench: %s form %s" % (kind, form), file=sys.stderr, flush=True)
     r = run_form(E, torch, mat, cfg, form, steps, warmup, True, 1e-8, 200, coupled=False, setup=setup)
     sz = r["sizes"]
     nterms = 2.0 * sz["nterms"]
     s = r["ms_per_step"] / 1e3
     km = r["kernel_ms"]
-    if kind == "tetra48":
-        flops = TETRA_OPS * nterms
-        roof = {"bound": "alu", "kernel": "k_tetra_scale<float, 6>", "achieved": flops / (km["extra"] * 1e-3) / 1e12,
+    if kind in ("tetra48", "triangle48"):
+        ops = TETRA_OPS if kind == "tetra48" else TRI_OPS
+        flops = ops * nterms
+        kern = "k_tetra_scale<float, 6>" if kind == "tetra48" else "k_tri_scale<float, 6>"
+        roof = {"bound": "alu", "kernel": kern, "achieved": flops / (km["extra"] * 1e-3) / 1e12,
                 "peak": 78.6, "unit": "TFLOP/s", "traffic": None, "kernel_ms": km["extra"],
-                "ops_per_term": TETRA_OPS}
+                "ops_per_term": ops}
     else:
         flops = contraction_flops(sz, len(mat["re"]), len(mat["rp"]))[1]
         roof = {"bound": "mfma", "kernel": GEMM_KERNEL[form], "achieved": flops / (km["step2"] * 1e-3) / 1e12,
@@ -489,7 +499,7 @@ def run_variant(E, torch, kind, steps, warmup, cpu=True, budget_s=20.0):
         while done < order.size and t_rows < budget_s:
             rows = order[done:done + 4]
             t1 = time.perf_counter()
-            Xp, Xm = prob.transition_probs(T, rows, delta="tetra" if kind == "tetra48" else "gauss")
+            Xp, Xm = prob.transition_probs(T, rows, delta={"tetra48": "tetra", "triangle48": "triangle"}.get(kind, "gauss"))
             w = prob.rates_e(T, Xp, Xm, rows)
             t_rows += time.perf_counter() - t1
             errs.append(rate_err(r["we"][rows], w))

@@ -78,8 +78,9 @@ enum {
 
 /* Energy-conserving delta of Eq. 8 (see elph_set_delta). */
 enum {
-  ELPH_DELTA_GAUSS = 0,  /* Gaussian of standard deviation sigma (elph_create's sigma) */
-  ELPH_DELTA_TETRA = 1   /* analytic tetrahedron weights on the mesh (no smearing parameter) */
+  ELPH_DELTA_GAUSS = 0,    /* Gaussian of standard deviation sigma (elph_create's sigma) */
+  ELPH_DELTA_TETRA = 1,    /* analytic tetrahedron weights on the mesh (no smearing parameter) */
+  ELPH_DELTA_TRIANGLE = 2  /* triangle weights on the mesh planes (no smearing parameter) */
 };
 
 /* Solution levels of the coupled BTEs (section "Coupled and decoupled BTEs"). */
@@ -371,8 +372,12 @@ elph_status elph_set_phph(elph_ctx ctx, double sigma_eV);
  * (bands and branches by index) is interpolated linearly in each, and the
  * delta at the final k' becomes the sum, over the 24 tetrahedra with corner
  * k', of the integral of delta(E) times the barycentric coordinate of k'
- * (mesh-cell units, 1/eV).  Marks the vertex store and the cached rates
- * stale.  EINVAL for an unknown method.  The batch and screened calls
+ * (mesh-cell units, 1/eV).  ELPH_DELTA_TRIANGLE: the same on the mesh planes
+ * normal to the third mesh axis (a 2-D mesh has one point along it): every
+ * cell of a plane is split into two triangles along its main diagonal and
+ * the delta at k' is the sum over the 6 triangles of its plane with corner
+ * k' (a 3-D sum then adds the planes as mesh points).  Marks the vertex
+ * store and the cached rates stale.  EINVAL for an unknown method.  The batch and screened calls
  * accept only ELPH_DELTA_GAUSS. */
 elph_status elph_set_delta(elph_ctx ctx, int32_t method);
 

@@ -78,7 +78,7 @@ __all__ = [
     "electron_bands", "electron_velocities", "dynamical_matrix", "dynamical_matrix_grad",
     "phonon_modes", "phonon_velocities", "fermi_pair", "bose_pair", "gaussian_delta",
     "g_wannier_brute", "g_wannier_factorised", "g_bloch", "Problem", "default_w_ext",
-    "tetra_delta_weights", "tetra_neighbourhood",
+    "tetra_delta_weights", "tetra_neighbourhood", "triangle_delta_weights", "triangle_neighbourhood",
     "iterate", "transport_tensors", "ko_residual", "ko_enforce", "energy_groups",
     "C_PHPH", "eigendisplacements", "ifc3_matrix", "phph_vertex", "phph_rates", "phph_inscatter", "phph_operator",
 ]
@@ -350,6 +350,83 @@ def tetra_neighbourhood():
 
 
 # ----------------------------------------------------------------------------
+# The triangle delta (the paper's default method for the energy-conserving
+# delta, its only one in two dimensions; section on the program's workflow).
+# Reading: a 2-D mesh (one point along the third axis) is split into
+# triangles; a 3-D mesh is taken as its planes normal to the third mesh axis,
+# each triangulated the same way, the delta resolved within a plane and the
+# planes summed as mesh points.
+
+def triangle_delta_weights(e):
+    """e [..., 3]: energies (level 0) at the corners of triangles over which
+    E is linear -> w [..., 3]: the integral over the triangle of
+    delta(E(x)) lambda_c(x), lambda_c the barycentric coordinate of corner c,
+    for a triangle of area 1/2 (half a mesh cell in mesh units).  By the
+    coarea formula this is the integral of lambda_c along the segment E = 0
+    divided by |grad E|; lambda_c is linear along the segment, so it gives
+    the segment's length times the mean of lambda_c at its two ends.  The
+    integral depends only on the corner energies and the area, so the sorted
+    corners are placed at (0, 0), (1, 0), (0, 1)."""
+    e = np.asarray(e, dtype=np.float64)
+    shp = e.shape[:-1]
+    e = e.reshape(-1, 3)
+    order = np.argsort(e, axis=1, kind="stable")
+    es = np.take_along_axis(e, order, axis=1)
+    P = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    grad = np.stack([es[:, 1] - es[:, 0], es[:, 2] - es[:, 0]], axis=1)
+    gn = np.linalg.norm(grad, axis=1)
+    ws = np.zeros_like(es)
+    nneg = (es < 0).sum(axis=1)
+
+    def cross(a, b, rows):
+        ea, eb = es[rows, a], es[rows, b]
+        t = ea / (ea - eb)
+        X = P[a][None, :] + t[:, None] * (P[b] - P[a])[None, :]
+        lam = np.zeros((rows.size, 3))
+        lam[:, a] = 1.0 - t
+        lam[:, b] = t
+        return X, lam
+
+    def add_segment(rows, A, B):
+        (Xa, la), (Xb, lb) = A, B
+        length = np.linalg.norm(Xb - Xa, axis=1)
+        ws[rows] += (length / gn[rows])[:, None] * (la + lb) / 2.0
+
+    ok = gn > 0
+    r1 = np.nonzero(ok & (nneg == 1))[0]
+    if r1.size:
+        add_segment(r1, cross(0, 1, r1), cross(0, 2, r1))
+    r2 = np.nonzero(ok & (nneg == 2))[0]
+    if r2.size:
+        add_segment(r2, cross(0, 2, r2), cross(1, 2, r2))
+    w = np.empty_like(ws)
+    np.put_along_axis(w, order, ws, axis=1)
+    return w.reshape(shp + (3,))
+
+
+def triangle_neighbourhood():
+    """The 6 triangles of a mesh plane that have a given point as a corner,
+    in the split of every cell of the plane along its main diagonal (the
+    paths 0 -> e_a -> e_a + e_b).  Points of the 3x3 in-plane neighbourhood
+    are numbered (dx+1)*3 + (dy+1) (the third mesh axis fixed); returns
+    (corners [6, 3], index of the centre point 4 among them [6])."""
+    import itertools
+    corners, centre = [], []
+    for o in itertools.product((0, 1), repeat=2):
+        for perm in itertools.permutations(range(2)):
+            path = [np.array(o)]
+            for ax in perm:
+                nxt = path[-1].copy()
+                nxt[ax] += 1
+                path.append(nxt)
+            ids = [int(p[0] * 3 + p[1]) for p in path]
+            if 4 in ids:
+                corners.append(ids)
+                centre.append(ids.index(4))
+    return np.array(corners), np.array(centre)
+
+
+# ----------------------------------------------------------------------------
 # Eq. 6: the e-ph vertex
 
 def g_wannier_brute(mat, k, q):
@@ -555,11 +632,35 @@ class Problem:
             out.append(np.take_along_axis(w, centre[None, :, None, None], axis=3)[..., 0].sum(axis=1))
         return out[0], out[1]
 
+    def triangle_delta(self, i):
+        """Delta of Eq. 8 by the triangle method for initial state i and every
+        final state j and branch s -> (Dp, Dm) [nstates, nbr], 1/eV: at the
+        final k_j, the sum over the 6 triangles of its mesh plane (normal to
+        the third mesh axis) with corner k_j of the corner weight of k_j for
+        E(k'') = eps_n(k'') -+ hw_s(k'' - k_i) - eps_i, linear in each
+        triangle.  Replaces the Gaussian's delta(E(k_j))."""
+        corners, centre = triangle_neighbourhood()
+        off = np.array([[a, b, 0] for a in (-1, 0, 1) for b in (-1, 0, 1)])
+        kj = self.ijk[self.state_k]                                   # [M, 3]
+        nbr_mesh = mesh_linear(kj[:, None, :] + off[None, :, :], self.n)  # [M, 9]
+        eps_n = self.eps_all[nbr_mesh, self.state_m[:, None]]       # [M, 9]
+        ki = self.ijk[self.state_k[i]]
+        q_mesh = mesh_linear(kj[:, None, :] + off[None, :, :] - ki, self.n)  # [M, 9]
+        hw = self.hw[q_mesh]                                          # [M, 9, nbr]
+        out = []
+        for sign in (-1.0, 1.0):                                      # absorption, emission
+            E = eps_n[:, :, None] + sign * hw - self.eps[i]           # [M, 9, nbr]
+            Ec = E[:, corners, :]                                     # [M, 6, 3, nbr]
+            w = triangle_delta_weights(np.moveaxis(Ec, 2, -1))        # [M, 6, nbr, 3]
+            out.append(np.take_along_axis(w, centre[None, :, None, None], axis=3)[..., 0].sum(axis=1))
+        return out[0], out[1]
+
     def transition_probs(self, T, rows=None, brute=False, delta="gauss"):
         """X^+ and X^- of Eq. 8 for initial states ``rows`` (all when None) and
         every final active state -> (Xp, Xm) of shape [len(rows), nstates, nbr].
-        delta: "gauss" (Gaussian of width sigma) or "tetra" (analytic
-        tetrahedron weights, see tetra_delta)."""
+        delta: "gauss" (Gaussian of width sigma), "tetra" (analytic
+        tetrahedron weights, see tetra_delta) or "triangle" (triangle
+        weights, see triangle_delta)."""
         rows = np.arange(self.nstates) if rows is None else np.asarray(rows)
         f, omf = fermi_pair(self.eps, self.mu, T)
         pref = 2.0 * np.pi / (HBAR_EVS * self.nk)
@@ -580,6 +681,8 @@ class Problem:
                 g2j = g2[jk, :, jm, m]             # [nstates, s]
                 if delta == "tetra":
                     dp, dm = self.tetra_delta(i)
+                elif delta == "triangle":
+                    dp, dm = self.triangle_delta(i)
                 else:
                     de = (self.eps - self.eps[i])[:, None]      # eps_j - eps_i
                     dp = gaussian_delta(de - hw[jk], self.sigma)

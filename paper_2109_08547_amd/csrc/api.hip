@@ -752,7 +752,7 @@ extern "C" elph_status elph_set_polar(elph_ctx ctx, const double* zstar, const d
 
 extern "C" elph_status elph_set_delta(elph_ctx ctx, int32_t method) {
   CHECK_CTX(ctx);
-  if (method != ELPH_DELTA_GAUSS && method != ELPH_DELTA_TETRA) {
+  if (method != ELPH_DELTA_GAUSS && method != ELPH_DELTA_TETRA && method != ELPH_DELTA_TRIANGLE) {
     ctx->err = "unknown delta method";
     return ELPH_EINVAL;
   }

@@ -1531,7 +1531,7 @@ static EpiParams epi_params(elph_ctx ctx) {
   ep.n0 = ctx->mesh[0];
   ep.n1 = ctx->mesh[1];
   ep.n2 = ctx->mesh[2];
-  ep.tetra = ctx->delta == ELPH_DELTA_TETRA ? 1 : 0;
+  ep.tetra = (ctx->delta == ELPH_DELTA_TETRA || ctx->delta == ELPH_DELTA_TRIANGLE) ? 1 : 0;
   ep.fr = ctx->frohlich ? (const cd*)ctx->d_frohlich : nullptr;
   ep.ust = (const cd*)ctx->d_ustate;
   ep.nb = ctx->nb;
@@ -1751,13 +1751,148 @@ __global__ void __launch_bounds__(256) k_tetra_scale(int64_t M, int nb, MeshDims
   }
 }
 
+// Triangle delta: the corner weight of corner c (energies at level 0) for a
+// triangle of area 1/2 (half a mesh cell of a plane) over which E is linear:
+// the level-0 segment's length over |grad E| (the linear triangle DOS
+// -s0 / ((s1-s0)(s2-s0)) below the middle corner, s2 / ((s2-s0)(s2-s1))
+// above it) times the mean of the barycentric coordinate of c at the
+// segment's two ends.
+__device__ inline double triangle_delta_corner(double e0, double e1, double e2, int c) {
+  const int nneg = (e0 < 0.0) + (e1 < 0.0) + (e2 < 0.0);
+  if (nneg == 0 || nneg == 3) return 0.0;  // the level misses the triangle
+  double s0 = e0, s1 = e1, s2 = e2;
+  bool m0 = c == 0, m1 = c == 1, m2 = c == 2;
+  auto cs = [](double& a, double& b, bool& ma, bool& mb) {
+    if (b < a) {
+      const double t = a;
+      a = b;
+      b = t;
+      const bool u = ma;
+      ma = mb;
+      mb = u;
+    }
+  };
+  cs(s1, s2, m1, m2);
+  cs(s0, s1, m0, m1);
+  cs(s1, s2, m1, m2);
+  const int pc = m1 ? 1 : m2 ? 2 : 0;
+  if (nneg == 1) {
+    // ends on the edges (0, 1) and (0, 2)
+    const double d1 = s1 - s0, d2 = s2 - s0;
+    const double tot = -s0 / (d1 * d2);
+    const double l = pc == 0 ? s1 / d1 + s2 / d2 : -s0 / (pc == 1 ? d1 : d2);
+    return 0.5 * tot * l;
+  }
+  // ends on the edges (0, 2) and (1, 2)
+  const double d0 = s2 - s0, d1 = s2 - s1;
+  const double tot = s2 / (d0 * d1);
+  const double l = pc == 2 ? -s0 / d0 - s1 / d1 : s2 / (pc == 0 ? d0 : d1);
+  return 0.5 * tot * l;
+}
+
+// The 6 triangles of a mesh plane (normal to the third mesh axis) with a
+// given point as corner: the 3x3 in-plane neighbourhood numbered
+// (dx+1)*3 + (dy+1) (centre 4); each of the 4 cells with the centre as a
+// corner is cut along the paths 0 -> e_a -> e_a + e_b over the 2 axis
+// orders, and a path triangle is kept when it passes through the centre.
+struct TriTab {
+  unsigned char c[6][3];
+  unsigned char ctr[6];
+};
+
+constexpr TriTab make_tri_tab() {
+  TriTab t{};
+  const int perms[2][2] = {{0, 1}, {1, 0}};
+  int n = 0;
+  for (int o = 0; o < 4; ++o)
+    for (int p = 0; p < 2; ++p) {
+      int v[2] = {(o >> 1) & 1, o & 1};
+      int ids[3] = {0, 0, 0};
+      int ctr = -1;
+      for (int k = 0; k < 3; ++k) {
+        if (k > 0) v[perms[p][k - 1]] += 1;
+        ids[k] = v[0] * 3 + v[1];
+        if (ids[k] == 4) ctr = k;
+      }
+      if (ctr >= 0) {
+        for (int k = 0; k < 3; ++k) t.c[n][k] = (unsigned char)ids[k];
+        t.ctr[n] = (unsigned char)ctr;
+        ++n;
+      }
+    }
+  return t;
+}
+constexpr TriTab kTri = make_tri_tab();
+
+template <int K>
+__device__ __attribute__((always_inline)) inline void tri_one(const double (&ej)[9], const double (&w)[9], double ei,
+                                                              double& dp, double& dm) {
+  constexpr int c0 = kTri.c[K][0], c1 = kTri.c[K][1], c2 = kTri.c[K][2];
+  constexpr int ck = kTri.ctr[K];
+  dp += triangle_delta_corner(ej[c0] - w[c0] - ei, ej[c1] - w[c1] - ei, ej[c2] - w[c2] - ei, ck);
+  dm += triangle_delta_corner(ej[c0] + w[c0] - ei, ej[c1] + w[c1] - ei, ej[c2] + w[c2] - ei, ck);
+}
+
+template <int... K>
+__device__ __attribute__((always_inline)) inline void tri_all(const double (&ej)[9], const double (&w)[9], double ei,
+                                                              double& dp, double& dm, std::integer_sequence<int, K...>) {
+  (tri_one<K>(ej, w, ei, dp, dm), ...);
+}
+
+// B+-[i][j][s] *= triangle delta at k_j for E = eps_n(k'') -+ hw_s(k'' - k_i) - eps_i
+// over k_j's mesh plane; one thread per pair (i, j)
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_tri_scale(int64_t M, int nb, MeshDims md, const int32_t* __restrict__ st_k,
+                                                   const int32_t* __restrict__ st_m, const double* __restrict__ eps,
+                                                   const double* __restrict__ eps_all, const double* __restrict__ hw,
+                                                   ST* __restrict__ Bp, ST* __restrict__ Bm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int64_t i = e / M, j = e - i * M;
+  const int ki = st_k[i], kj = st_k[j], n = st_m[j];
+  const int ic = ki % md.n2, it = ki / md.n2, ib = it % md.n1, ia = it / md.n1;
+  const int jc = kj % md.n2, jt = kj / md.n2, jb = jt % md.n1, ja = jt / md.n1;
+  const double ei = eps[i];
+  double ej[9];
+  int qi[9];
+  int qc = jc - ic;
+  qc += qc < 0 ? md.n2 : 0;
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    int a = ja + p / 3 - 1, b = jb + p % 3 - 1;
+    a += (a < 0) ? md.n0 : (a >= md.n0 ? -md.n0 : 0);
+    b += (b < 0) ? md.n1 : (b >= md.n1 ? -md.n1 : 0);
+    ej[p] = eps_all[(int64_t)((a * md.n1 + b) * md.n2 + jc) * nb + n];
+    int qa = a - ia, qb = b - ib;
+    qa += qa < 0 ? md.n0 : 0;
+    qb += qb < 0 ? md.n1 : 0;
+    qi[p] = (qa * md.n1 + qb) * md.n2 + qc;
+  }
+  for (int s = 0; s < NX; ++s) {
+    const int64_t t = e * NX + s;
+    const double bp = (double)Bp[t], bm = (double)Bm[t];
+    if (bp == 0.0 && bm == 0.0) continue;
+    double w[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) w[p] = hw[(int64_t)qi[p] * NX + s];
+    double dp = 0.0, dm = 0.0;
+    tri_all(ej, w, ei, dp, dm, std::make_integer_sequence<int, 6>{});
+    Bp[t] = (ST)(bp * dp);
+    Bm[t] = (ST)(bm * dm);
+  }
+}
+
 static void launch_tetra_scale(elph_ctx ctx, void* Bp, void* Bm, bool store_f64) {
   const int64_t M = ctx->nstates;
   const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
   const dim3 grid(blocks_for(M * M, 256)), blk(256);
 #define TS(STT, NXV)                                                                                            \
-  hipLaunchKernelGGL((k_tetra_scale<STT, NXV>), grid, blk, 0, ctx->stream, M, ctx->nb, md, ctx->d_state_k,      \
-                     ctx->d_state_m, ctx->d_eps, ctx->d_eps_all, ctx->d_hw, (STT*)Bp, (STT*)Bm)
+  if (ctx->delta == ELPH_DELTA_TRIANGLE)                                                                        \
+    hipLaunchKernelGGL((k_tri_scale<STT, NXV>), grid, blk, 0, ctx->stream, M, ctx->nb, md, ctx->d_state_k,      \
+                       ctx->d_state_m, ctx->d_eps, ctx->d_eps_all, ctx->d_hw, (STT*)Bp, (STT*)Bm);              \
+  else                                                                                                          \
+    hipLaunchKernelGGL((k_tetra_scale<STT, NXV>), grid, blk, 0, ctx->stream, M, ctx->nb, md, ctx->d_state_k,    \
+                       ctx->d_state_m, ctx->d_eps, ctx->d_eps_all, ctx->d_hw, (STT*)Bp, (STT*)Bm)
 #define TSN(STT)              \
   switch (ctx->nbr) {         \
     case 3: TS(STT, 3); break;   \

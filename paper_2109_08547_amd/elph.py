@@ -317,11 +317,11 @@ def elph_iterate(ctx, T, I, J, F, G, W_ph_ext=None, level=ELPH_LEVEL_COUPLED, to
             "iters": iters.value, "ko_residual": ko.value, "status": st}
 
 
-ELPH_DELTA_GAUSS, ELPH_DELTA_TETRA = 0, 1
+ELPH_DELTA_GAUSS, ELPH_DELTA_TETRA, ELPH_DELTA_TRIANGLE = 0, 1, 2
 
 
 def elph_set_delta(ctx, method):
-    """Energy-conserving delta of Eq. 8: ELPH_DELTA_GAUSS or ELPH_DELTA_TETRA."""
+    """Energy-conserving delta of Eq. 8: ELPH_DELTA_GAUSS, ELPH_DELTA_TETRA or ELPH_DELTA_TRIANGLE."""
     _check(ctx, load().elph_set_delta(ctx.handle, int(method)))
 
 

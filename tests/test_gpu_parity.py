@@ -453,31 +453,40 @@ def test_polar_tables_and_rates():
 _tetra_ref = {}
 
 
-def tetra_ref(name):
-    if name not in _tetra_ref:
+DELTA = {"tetra": 1, "triangle": 2}
+
+
+def tetra_ref(name, method="tetra"):
+    if (name, method) not in _tetra_ref:
         c = case(name)
-        Xp, Xm = c.prob.transition_probs(c.T, delta="tetra")
-        _tetra_ref[name] = (Xp, Xm, c.prob.rates_e(c.T, Xp, Xm), c.prob.rates_ph(c.T, Xp))
-    return _tetra_ref[name]
+        Xp, Xm = c.prob.transition_probs(c.T, delta=method)
+        _tetra_ref[(name, method)] = (Xp, Xm, c.prob.rates_e(c.T, Xp, Xm), c.prob.rates_ph(c.T, Xp))
+    return _tetra_ref[(name, method)]
 
 
+@pytest.mark.parametrize("method", ["tetra", "triangle"])
 @pytest.mark.parametrize("name", ["tiny4", "metal6"])
-def test_tetra_delta_transition_probs_and_rates(name):
+def test_tetra_delta_transition_probs_and_rates(name, method):
     c = case(name)
-    Xp_ref, Xm_ref, we_ref, wph_ref = tetra_ref(name)
+    Xp_ref, Xm_ref, we_ref, wph_ref = tetra_ref(name, method)
     ctx = make_ctx(c.cfg, c.mat)
-    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    E.elph_set_delta(ctx, DELTA[method])
     sz = E.elph_sizes(ctx)
     xp, xm = dtensor(sz["nterms"]), dtensor(sz["nterms"])
     E.elph_transition_probs(ctx, c.T, xp, xm, 1)
     we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
     E.elph_scatt_rates(ctx, c.T, we, wph)
     torch.cuda.synchronize()
-    # the tetrahedron weights divide by energy differences of a tetrahedron's
+    # the tetrahedron (triangle) weights divide by energy differences of the
     # corners, which magnify the 1e-15 differences of the two sides'
-    # eigenvalues: bars 1e-8 (1e-10 of the largest term absolutely)
-    ok_p, ep = term_ok(xp.cpu().numpy().reshape(Xp_ref.shape), Xp_ref, rtol=1e-8, atol_rel=1e-10)
-    ok_m, em = term_ok(xm.cpu().numpy().reshape(Xm_ref.shape), Xm_ref, rtol=1e-8, atol_rel=1e-10)
+    # eigenvalues: bars 1e-8 (1e-10 of the largest term absolutely).  Where
+    # the level passes within ~1e-10 eV of a triangle's corner (mirror
+    # corners of the symmetric model bands), the two energy differences of a
+    # triangle weight leave those differences at ~1e-7: bar 1e-6 there
+    rtol = 1e-8 if method == "tetra" else 1e-6
+    assert np.count_nonzero(Xp_ref) > 0.01 * Xp_ref.size
+    ok_p, ep = term_ok(xp.cpu().numpy().reshape(Xp_ref.shape), Xp_ref, rtol=rtol, atol_rel=1e-10)
+    ok_m, em = term_ok(xm.cpu().numpy().reshape(Xm_ref.shape), Xm_ref, rtol=rtol, atol_rel=1e-10)
     assert ok_p and ok_m, (ep, em)
     assert rate_err(we.cpu().numpy(), we_ref) < 1e-8
     assert rate_err(wph.cpu().numpy(), wph_ref) < 1e-8
@@ -494,12 +503,13 @@ def test_tetra_delta_transition_probs_and_rates(name):
 
 # the FP64 refinement applies to the Gaussian delta only, so the
 # tetrahedron delta keeps the plain forms' bars
+@pytest.mark.parametrize("method", ["tetra", "triangle"])
 @pytest.mark.parametrize("form", ["fp32", "fp16x3"])
-def test_tetra_delta_forms(form):
+def test_tetra_delta_forms(form, method):
     c = case("metal6")
-    _, _, we_ref, wph_ref = tetra_ref("metal6")
+    _, _, we_ref, wph_ref = tetra_ref("metal6", method)
     ctx = make_ctx(c.cfg, c.mat, precision=form)
-    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    E.elph_set_delta(ctx, DELTA[method])
     sz = E.elph_sizes(ctx)
     we, wph = dtensor(sz["nstates"]), dtensor(sz["nk"] * sz["nbr"])
     E.elph_scatt_rates(ctx, c.T, we, wph)
@@ -531,11 +541,12 @@ def _iterate_against_oracle(ctx, c, Xp, Xm, prob):
         assert np.abs(got[key] - ref[key]).max() <= 1e-7 * scale, key
 
 
-def test_tetra_delta_coupled_iteration():
+@pytest.mark.parametrize("method", ["tetra", "triangle"])
+def test_tetra_delta_coupled_iteration(method):
     c = case("metal6")
-    Xp, Xm, _, _ = tetra_ref("metal6")
+    Xp, Xm, _, _ = tetra_ref("metal6", method)
     ctx = make_ctx(c.cfg, c.mat)
-    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    E.elph_set_delta(ctx, DELTA[method])
     _iterate_against_oracle(ctx, c, Xp, Xm, c.prob)
     ctx.close()
 
@@ -548,10 +559,11 @@ def test_polar_coupled_iteration():
     ctx.close()
 
 
-def test_tetra_delta_is_refused_by_batches():
+@pytest.mark.parametrize("method", ["tetra", "triangle"])
+def test_tetra_delta_is_refused_by_batches(method):
     c = case("tiny4")
     ctx = make_ctx(c.cfg, c.mat, precision="fp32")
-    E.elph_set_delta(ctx, E.elph.ELPH_DELTA_TETRA)
+    E.elph_set_delta(ctx, DELTA[method])
     with pytest.raises(Exception):
         E.Batch([ctx])
     ctx.close()

@@ -147,6 +147,113 @@ def test_tetra_delta_uses_the_phonon_energies_at_the_neighbours():
             assert Dp[lower, s].sum() == 0.0
 
 
+def _tri_dos(e):
+    """Density of states at level 0 of one triangle of area 1/2 (mesh-cell
+    units) over which the energy is linear with corner values e: the
+    piecewise closed forms of the linear triangle method."""
+    e1, e2, e3 = np.sort(e)
+    if 0 <= e1 or 0 >= e3:
+        return 0.0
+    if e2 >= 0:
+        return -e1 / ((e2 - e1) * (e3 - e1))
+    return e3 / ((e3 - e1) * (e3 - e2))
+
+
+def _plane_dos(values, n, level):
+    """Linear-triangle DOS of a function on the n^3 mesh, plane by plane
+    normal to the third axis: every cell (a, b) of a plane split into two
+    triangles along its main diagonal (the paths corner -> +e_x -> +e_x+e_y
+    and corner -> +e_y -> +e_x+e_y), each contributing the closed form."""
+    vals = np.asarray(values).reshape(n, n, n)
+    total = 0.0
+    for a, b, c in itertools.product(range(n), repeat=3):
+        for first in (0, 1):
+            es = [vals[a, b, c]]
+            p = [a, b]
+            p[first] += 1
+            es.append(vals[p[0] % n, p[1] % n, c])
+            es.append(vals[(a + 1) % n, (b + 1) % n, c])
+            total += _tri_dos(np.array(es) - level)
+    return total
+
+
+def test_triangle_delta_sums_to_the_plane_dos_at_the_final_energy():
+    """Two cosine bands, an Einstein phonon hw0: summed over every final state
+    of band n, the absorption weight is the plane-by-plane triangle DOS of
+    band n at eps_i + hw0 and the emission weight at eps_i - hw0."""
+    n = 6
+    onsite, hop = [-0.5, 0.45], [0.1, 0.07]
+    K, M = 2.4, 28.0855
+    mat = _material(2, 1, NN, [[0, 0, 0]], _cosine_bands(onsite, hop), (K / M * np.eye(3))[None],
+                    np.zeros((7, 1, 3, 2, 2)), [M])
+    hw0 = np.sqrt(oracle.C_PHONON * K / M)
+    prob = oracle.Problem(mat, n, 0.0, np.inf, 0.01)
+    checked = 0
+    for target in (-0.72, -0.18, 0.02):
+        i = int(np.argmin(np.abs(prob.eps - target) + 10 * (prob.state_m != 0)))
+        Dp, Dm = prob.triangle_delta(i)
+        for band in range(2):
+            sel = prob.state_m == band
+            want_p = _plane_dos(prob.eps_all[:, band], n, prob.eps[i] + hw0)
+            want_m = _plane_dos(prob.eps_all[:, band], n, prob.eps[i] - hw0)
+            for s in range(3):
+                assert abs(Dp[sel, s].sum() - want_p) <= 1e-11 * max(want_p, 1.0)
+                assert abs(Dm[sel, s].sum() - want_m) <= 1e-11 * max(want_m, 1.0)
+            if abs(want_p - want_m) > 0.05 * max(want_p, want_m):
+                checked += 1
+    assert checked >= 3          # the two signs are told apart
+
+
+def test_triangle_delta_uses_the_phonon_energies_at_the_neighbours():
+    """Two flat bands Delta apart and dispersive phonons: absorption from the
+    lower to the upper band sums to the plane-by-plane phonon DOS at
+    hw = Delta, emission from the upper band likewise, the other two
+    processes to zero."""
+    n = 6
+    ea, eb = 0.0, 0.021
+    K, M = 1.3, 12.011
+    h = np.zeros((1, 2, 2), complex)
+    h[0] = np.diag([ea, eb])
+    mat = _material(2, 1, [[0, 0, 0]], NN, h, _scalar_springs(K, M), np.zeros((1, 7, 3, 2, 2)), [M])
+    prob = oracle.Problem(mat, n, 0.0, np.inf, 0.01)
+    want = _plane_dos(prob.hw[:, 0], n, eb - ea)
+    assert want > 0.05 * n ** 3 / 0.05
+    lower = np.nonzero(prob.state_m == 0)[0]
+    upper = np.nonzero(prob.state_m == 1)[0]
+    for i in (lower[0], lower[37], lower[101]):
+        Dp, Dm = prob.triangle_delta(i)
+        for s in range(3):
+            assert abs(Dp[upper, s].sum() - want) <= 1e-11 * want
+            assert Dm[upper, s].sum() == 0.0
+    for i in (upper[5], upper[77]):
+        Dp, Dm = prob.triangle_delta(i)
+        for s in range(3):
+            assert abs(Dm[lower, s].sum() - want) <= 1e-11 * want
+            assert Dp[lower, s].sum() == 0.0
+
+
+def test_triangle_delta_resolves_in_plane_only():
+    """A band that disperses along the third axis only: E is constant on every
+    mesh plane, so no triangle carries a level crossing and every weight is
+    zero unless the level sits exactly on a plane's energy."""
+    n = 6
+    K, M = 2.4, 28.0855
+    h = np.zeros((3, 1, 1), complex)
+    h[0, 0, 0] = 0.1
+    h[1, 0, 0] = h[2, 0, 0] = 0.2
+    mat = _material(1, 1, [[0, 0, 0], [0, 0, 1], [0, 0, -1]], [[0, 0, 0]], h, (K / M * np.eye(3))[None],
+                    np.zeros((3, 1, 3, 1, 1)), [M])
+    prob = oracle.Problem(mat, n, 0.0, np.inf, 0.01)
+    hw0 = np.sqrt(oracle.C_PHONON * K / M)
+    levels = np.unique(np.round(prob.eps_all[:, 0], 12))
+    assert levels.size == n // 2 + 1                       # one energy per plane pair
+    for i in (0, 5, 40):
+        for shifted in (prob.eps[i] + hw0, prob.eps[i] - hw0):
+            assert np.min(np.abs(levels - shifted)) > 1e-6  # no level on a plane
+        Dp, Dm = prob.triangle_delta(i)
+        assert np.all(Dp == 0.0) and np.all(Dm == 0.0)
+
+
 # ---------------------------------------------------------------------------
 # the overlap <n, k+q | m, k> in the Bloch rotation (Eq. 6) and in the
 # Froehlich vertex (Eq. 7)

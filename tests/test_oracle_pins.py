@@ -590,6 +590,85 @@ def test_tetra_neighbourhood_integrates_the_hat_function(axis, sign, t):
 
 
 # ---------------------------------------------------------------------------
+# The triangle delta: a triangle of area 1/2 over which E is linear
+
+def _tri_dos_closed_form(e):
+    """Length of the level-0 segment over |grad E| for a triangle of area 1/2:
+    the piecewise closed form of the linear triangle method (2 A (0 - e1) /
+    ((e2 - e1)(e3 - e1)) below the middle corner, 2 A (e3 - 0) / ((e3 - e1)
+    (e3 - e2)) above it, A = 1/2)."""
+    e1, e2, e3 = np.sort(e)
+    if 0 <= e1 or 0 >= e3:
+        return 0.0
+    if e2 >= 0:
+        return -e1 / ((e2 - e1) * (e3 - e1))
+    return e3 / ((e3 - e1) * (e3 - e2))
+
+
+def test_triangle_weights_sum_to_the_triangle_dos():
+    rng = np.random.default_rng(12)
+    e = rng.standard_normal((4000, 3))
+    w = oracle.triangle_delta_weights(e)
+    ref = np.array([_tri_dos_closed_form(x) for x in e])
+    assert np.all(w >= 0)
+    assert np.abs(w.sum(1) - ref).max() <= 1e-13 * ref.max()
+    assert np.count_nonzero(ref) > 2000          # both cases occur
+
+
+def test_triangle_corner_weights_against_quadrature():
+    # integral of a narrow Gaussian of E times the barycentric coordinate, on a
+    # fine midpoint grid of the reference triangle (corners 0, x, y)
+    n = 2000
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h
+    x, y = np.meshgrid(c, c, indexing="ij")
+    inside = x + y < 1.0
+    x, y = x[inside], y[inside]
+    lam = np.stack([1 - x - y, x, y])
+    for e in ([-0.9, 0.4, 1.1], [-1.3, -0.2, 0.7], [0.5, -2.0, 0.9]):
+        e = np.array(e)
+        E = e[0] * lam[0] + e[1] * lam[1] + e[2] * lam[2]
+        sig = 0.01
+        d = np.exp(-0.5 * (E / sig) ** 2) / (np.sqrt(2 * np.pi) * sig)
+        quad = (d[None, :] * lam).sum(1) * h ** 2
+        w = oracle.triangle_delta_weights(e)
+        assert np.abs(w - quad).max() <= 0.005 * w.max(), (e, w, quad)
+
+
+def test_triangle_corner_weight_integrates_to_a_third_of_the_area():
+    # over every level, the corner weight integrates to the integral of the
+    # barycentric coordinate over the triangle: (1/2) / 3
+    e = np.array([0.2, 1.0, 1.7])
+    lev = np.linspace(-0.5, 2.5, 300001)
+    w = oracle.triangle_delta_weights(e[None, :] - lev[:, None])
+    integ = w.sum(0) * (lev[1] - lev[0])
+    assert np.abs(integ - 1.0 / 6.0).max() <= 1e-5
+
+
+@pytest.mark.parametrize("axis,sign,t", [(0, 1, 0.0), (0, 1, 0.3), (1, -1, 0.55), (1, 1, 0.8), (0, -1, 0.1)])
+def test_triangle_neighbourhood_integrates_the_hat_function(axis, sign, t):
+    # for E = sign * x_axis - t (mesh units), the 6 corner weights of the
+    # centre add up to the integral of the centre's hat function over the
+    # line E = 0, which is 1 - t for a line at distance t from the centre
+    corners, centre = oracle.triangle_neighbourhood()
+    off = np.array([[a, b] for a in (-1, 0, 1) for b in (-1, 0, 1)], dtype=float)
+    E = sign * off[:, axis] - t
+    w = oracle.triangle_delta_weights(E[corners])
+    D = w[np.arange(6), centre].sum()
+    assert abs(D - (1.0 - t)) <= 1e-13
+
+
+def test_triangle_neighbourhood_is_the_diagonal_split():
+    # the 6 triangles around the centre of the split along the main diagonal:
+    # the centre's neighbours (+-1, 0), (0, +-1) and (1, 1), (-1, -1), never
+    # the anti-diagonal corners
+    corners, centre = oracle.triangle_neighbourhood()
+    assert corners.shape == (6, 3) and np.all(corners[np.arange(6), centre] == 4)
+    used = set(corners.ravel()) - {4}
+    assert used == {1, 3, 5, 7, 0, 8}                     # (dx+1)*3 + (dy+1)
+
+
+# ---------------------------------------------------------------------------
 # Non-analytic (dipole-dipole) term of polar materials (Eq. 4)
 
 def _polar_mat(isotropic=False):
