@@ -95,6 +95,7 @@ struct elph_ctx_s {
   int32_t* d_i3_off = nullptr;  // [ng3 + 1] first entry of each R_j
   int32_t* d_i3_rk = nullptr;   // [n3][3]
   double* d_i3_psi = nullptr;   // [n3][nbr][nbr][nbr] eV / Angstrom^3, x = 3 atom + Cartesian
+  void* d_i3_fold = nullptr;     // fold table of the force constants over the phonon tables (derived; cached)
   double phph_sigma = 0;        // > 0: three-phonon processes in elph_iterate (Gaussian width, eV)
   double2* d_tab[3] = {nullptr, nullptr, nullptr};  // per-axis exp(2 pi i j / N)
   int32_t* d_qrep = nullptr;                          // mesh points q with q <= -q (one of each +-q pair)

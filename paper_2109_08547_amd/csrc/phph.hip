@@ -804,14 +804,21 @@ elph_status check_phph(elph_ctx ctx) {
   return ELPH_OK;
 }
 
-// the fold table for every mesh point, in a pool block the caller frees
+// the fold table for every mesh point: built once and kept on the context
+// (it depends on the force constants and the phonon tables only; setting
+// the force constants or dropping the tables releases it)
 elph_status build_fold(elph_ctx ctx, cd** phi) {
+  if (ctx->d_i3_fold) {
+    *phi = (cd*)ctx->d_i3_fold;
+    return ELPH_OK;
+  }
   const int64_t n3 = (int64_t)ctx->nbr * ctx->nbr * ctx->nbr;
   ALLOC(*phi, ctx->nk * ctx->ng3 * n3 * sizeof(cd));
 #define FOLD(N) launch_fold<N>(ctx, *phi)
   NBR_SWITCH(ctx->nbr, FOLD)
 #undef FOLD
   HIPCHK(hipGetLastError());
+  ctx->d_i3_fold = *phi;
   return ELPH_OK;
 }
 
@@ -819,7 +826,8 @@ elph_status build_fold(elph_ctx ctx, cd** phi) {
 
 elph_status phph_set_ifc3(elph_ctx ctx, int32_t n, const int32_t* rj, const int32_t* rk, const double* psi) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  void** ptrs[] = {(void**)&ctx->d_i3_rj, (void**)&ctx->d_i3_off, (void**)&ctx->d_i3_rk, (void**)&ctx->d_i3_psi};
+  void** ptrs[] = {(void**)&ctx->d_i3_rj, (void**)&ctx->d_i3_off, (void**)&ctx->d_i3_rk, (void**)&ctx->d_i3_psi,
+                   (void**)&ctx->d_i3_fold};
   for (void** p : ptrs) {
     dev_free(ctx, *p);
     *p = nullptr;
@@ -901,7 +909,6 @@ elph_status phph_vertex(elph_ctx ctx, int64_t npairs, const int32_t* q, const in
 #undef VTX
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  dev_free(ctx, phi);
   return ELPH_OK;
 }
 
@@ -983,7 +990,6 @@ static elph_status phph_pass(elph_ctx ctx, const char* name, double T_K, double 
   HIPCHK(hipStreamSynchronize(ctx->stream));
   dev_free(ctx, part);
   dev_free(ctx, nbose);
-  dev_free(ctx, phi);
   return ELPH_OK;
 }
 
