@@ -202,18 +202,61 @@ enum { KMV_PLAIN = 0, KMV_P = 1, KMV_S = 2 };
 // flight; the in vector read from an LDS chunk) and are summed in wave
 // order.  P and S store their in vector (p' or s) from the first row tile,
 // and return at once when every column is done.
+// P with sco != null also takes the rho / beta / convergence step of the
+// previous iteration's x, r update (its dots dxr of nxr blocks): every block
+// reduces them alike from the scalars sco of the previous iteration, and
+// the first block stores the new scalars into sc, a different slot, so no
+// block reads a scalar another one writes during the launch.
 template <typename KS, int MODE>
 __global__ void __launch_bounds__(256) k_kmv(int64_t M, int64_t ldk, int64_t jlen, const KS* __restrict__ KT,
                                              const double* __restrict__ r, const double* __restrict__ a,
                                              const double* __restrict__ b, const double* __restrict__ dpart,
                                              int nblk, double* sc, double* __restrict__ wv,
-                                             double* __restrict__ part) {
+                                             double* __restrict__ part, const double* __restrict__ sco,
+                                             const double* __restrict__ dxr, int nxr, double thr) {
   __shared__ double red[3][2][6][64];
   __shared__ double xs[kKmvChunk * 6];
   __shared__ double d[12];
   __shared__ double s0[6], s1[6];
+  __shared__ int dn[6];
   typedef typename Two<KS>::type K2;
-  if (MODE != KMV_PLAIN && sc[SC_ALL] != 0.0) return;  // the whole grid returns
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+  if (MODE == KMV_P && sco) {
+    if (sco[SC_ALL] != 0.0) {  // converged earlier: carry the scalars over and stop
+      if (first && threadIdx.x < SC_N) sc[threadIdx.x] = sco[threadIdx.x];
+      return;
+    }
+    dots_reduce(nxr, dxr, d);
+    if (threadIdx.x < 6) {
+      const int c = threadIdx.x;
+      const double rn = sqrt(d[6 + c]);
+      bool done = sco[SC_DONE + c] != 0.0;
+      if (!done && rn <= thr * fmax(sco[SC_BNORM + c], 1e-300)) done = true;
+      const double rho_old = sco[SC_RHO + c], om = sco[SC_OMEGA + c], al = sco[SC_ALPHA + c];
+      const double beta = (done || rho_old == 0.0 || om == 0.0) ? 0.0 : (d[c] / rho_old) * (al / om);
+      s0[c] = beta;
+      s1[c] = om;
+      dn[c] = done ? 1 : 0;
+      if (first) {
+        sc[SC_RHO + c] = d[c];
+        sc[SC_ALPHA + c] = al;
+        sc[SC_OMEGA + c] = om;
+        sc[SC_BETA + c] = beta;
+        sc[SC_BNORM + c] = sco[SC_BNORM + c];
+        sc[SC_RNORM + c] = rn;
+        sc[SC_DONE + c] = done ? 1.0 : 0.0;
+      }
+    }
+    __syncthreads();
+    const bool all = dn[0] && dn[1] && dn[2] && dn[3] && dn[4] && dn[5];
+    if (first && threadIdx.x == 0) {
+      sc[SC_ALL] = all ? 1.0 : 0.0;
+      sc[SC_IT] = sco[SC_IT] + 1.0;
+    }
+    if (all) return;  // the whole grid returns
+  } else if (MODE != KMV_PLAIN && sc[SC_ALL] != 0.0) {
+    return;  // the whole grid returns
+  }
   if (MODE == KMV_S) {
     dots_reduce(nblk, dpart, d);
     if (threadIdx.x < 6) {
@@ -222,7 +265,7 @@ __global__ void __launch_bounds__(256) k_kmv(int64_t M, int64_t ldk, int64_t jle
       s0[c] = al;
       if (blockIdx.x == 0 && blockIdx.y == 0) sc[SC_ALPHA + c] = al;
     }
-  } else if (MODE == KMV_P) {
+  } else if (MODE == KMV_P && !sco) {
     if (threadIdx.x < 6) {
       s0[threadIdx.x] = sc[SC_BETA + threadIdx.x];
       s1[threadIdx.x] = sc[SC_OMEGA + threadIdx.x];
@@ -310,9 +353,14 @@ __global__ void __launch_bounds__(kVB) k_kmv_fin(int64_t n6, int S, const double
   if (sc && sc[SC_ALL] != 0.0) return;
   double d0 = 0.0, d1 = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * kVB + threadIdx.x; t < n6; t += (int64_t)gridDim.x * kVB) {
+    // every split's partial is requested before the first is added (S <= 32)
+    double ps[32];
+#pragma unroll
+    for (int s = 0; s < 32; ++s) ps[s] = s < S ? part[(int64_t)s * n6 + t] : 0.0;
     double v = 0.0;
-#pragma unroll 8
-    for (int s = 0; s < S; ++s) v += part[(int64_t)s * n6 + t];
+#pragma unroll
+    for (int s = 0; s < 32; ++s)
+      if (s < S) v += ps[s];
     v = in[t] - v;
     out[t] = v;
     if (a0) d0 += a0[t] * v;
@@ -427,7 +475,8 @@ static size_t kt_doubles(int64_t M, int64_t ldk, bool f32) {
 size_t self_solver_doubles(int64_t M, bool kt_f32) {
   SelfSolver sv;
   self_solver_layout(M, &sv);
-  return kt_doubles(M, sv.ldk, kt_f32) + 9 * (size_t)M * 6 + (size_t)sv.S * M * 6 + 2 * (size_t)sv.nblk * 12 + SC_N;
+  return kt_doubles(M, sv.ldk, kt_f32) + 9 * (size_t)M * 6 + (size_t)sv.S * M * 6 + 2 * (size_t)sv.nblk * 12 +
+         2 * SC_N;
 }
 
 void self_solver_carve(int64_t M, bool kt_f32, double* base, SelfSolver* sv) {
@@ -452,15 +501,18 @@ void self_solver_carve(int64_t M, bool kt_f32, double* base, SelfSolver* sv) {
 
 // split partial products K' in of the in vector of MODE (see k_kmv)
 template <int MODE>
-static void kmv(elph_ctx ctx, const SelfSolver& sv, const double* a, const double* b, double* wv) {
+static void kmv(elph_ctx ctx, const SelfSolver& sv, double* sc, const double* a, const double* b, double* wv,
+                const double* sco = nullptr, double thr = 0.0) {
   const int64_t M = ctx->nstates;
   const dim3 grid((unsigned)sv.nt, (unsigned)sv.S);
   if (sv.kt_f32)
     hipLaunchKernelGGL((k_kmv<float, MODE>), grid, dim3(256), 0, ctx->stream, M, sv.ldk, sv.jlen,
-                       (const float*)sv.KT, sv.r, a, b, sv.dpart, sv.nblk, sv.sc, wv, sv.part);
+                       (const float*)sv.KT, sv.r, a, b, sv.dpart, sv.nblk, sc, wv, sv.part, sco, sv.dxr, sv.nblk,
+                       thr);
   else
     hipLaunchKernelGGL((k_kmv<double, MODE>), grid, dim3(256), 0, ctx->stream, M, sv.ldk, sv.jlen,
-                       (const double*)sv.KT, sv.r, a, b, sv.dpart, sv.nblk, sv.sc, wv, sv.part);
+                       (const double*)sv.KT, sv.r, a, b, sv.dpart, sv.nblk, sc, wv, sv.part, sco, sv.dxr, sv.nblk,
+                       thr);
 }
 
 static void kmv_fin(elph_ctx ctx, const SelfSolver& sv, const double* in, double* out, const double* a0, int sq,
@@ -470,12 +522,15 @@ static void kmv_fin(elph_ctx ctx, const SelfSolver& sv, const double* in, double
 }
 
 // BiCGSTAB with every scalar on the device.  An iteration is five launches:
-// p' and the products of v' = L p'; v' with rh.v'; alpha (in every block)
-// with s and the products of t = L s; t with s.t, t.t; omega (in every
-// block) with the x, r update and rh.r, r.r.  The rho / beta / convergence
-// step of those last dots is one more small launch, before the next
-// iteration or a read of the flags.  p and v alternate between two buffers,
-// since the first launch reads the old pair while it writes the new p'.
+// the rho / beta / convergence step of the previous iteration's dots with p'
+// and the products of v' = L p'; v' with rh.v'; alpha (in every block) with
+// s and the products of t = L s; t with s.t, t.t; omega (in every block)
+// with the x, r update and rh.r, r.r.  The scalars alternate between two
+// slots, since the first launch reads the previous iteration's while its
+// first block writes the new ones.  Before a read of the convergence flags
+// the pending rho step runs on its own (k_bi_scal, in place).  p and v
+// alternate between two buffers, since the first launch reads the old pair
+// while it writes the new p'.
 elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double thr, int maxit, bool* ok,
                        int* iters) {
   hipStream_t s = ctx->stream;
@@ -486,12 +541,14 @@ elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double thr
     *iters = 0;
     return ELPH_OK;
   }
+  double* slot[2] = {sv.sc, sv.sc + SC_N};
+  int cur = 0;
   // r0 = b - L x0 (v holds L x0 until the init kernel clears it)
-  kmv<KMV_PLAIN>(ctx, sv, x, nullptr, nullptr);
+  kmv<KMV_PLAIN>(ctx, sv, slot[cur], x, nullptr, nullptr);
   kmv_fin(ctx, sv, x, sv.v, nullptr, 0, nullptr, nullptr);
   hipLaunchKernelGGL(k_bi_init, dim3((unsigned)sv.nblk), dim3(kVB), 0, s, n6, sv.b, sv.v, sv.r, sv.rh, sv.p, sv.v,
                      sv.dpart);
-  hipLaunchKernelGGL(k_bi_scal, dim3(1), dim3(kVB), 0, s, (int)BI_INIT, sv.nblk, sv.dpart, sv.sc, thr);
+  hipLaunchKernelGGL(k_bi_scal, dim3(1), dim3(kVB), 0, s, (int)BI_INIT, sv.nblk, sv.dpart, slot[cur], thr);
   HIPCHK(hipGetLastError());
   // iterations between reads of the convergence flags; once every column is
   // done the launches of the iterations in between return at once
@@ -503,23 +560,27 @@ elph_status self_solve(elph_ctx ctx, const SelfSolver& sv, double* x, double thr
   for (;;) {
     if (it % kCheck == 0 || it >= maxit) {
       if (pending)
-        hipLaunchKernelGGL(k_bi_scal, dim3(1), dim3(kVB), 0, s, (int)BI_RHO, sv.nblk, sv.dxr, sv.sc, thr);
+        hipLaunchKernelGGL(k_bi_scal, dim3(1), dim3(kVB), 0, s, (int)BI_RHO, sv.nblk, sv.dxr, slot[cur], thr);
       pending = false;
-      HIPCHK(hipMemcpyAsync(ctx->h_pin, sv.sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(ctx->h_pin, slot[cur], SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       all = ctx->h_pin[SC_ALL] != 0.0;
       if (all || it >= maxit) break;
     }
     const int o = it & 1, n = o ^ 1;
     ++it;
-    if (pending)
-      hipLaunchKernelGGL(k_bi_scal, dim3(1), dim3(kVB), 0, s, (int)BI_RHO, sv.nblk, sv.dxr, sv.sc, thr);
-    kmv<KMV_P>(ctx, sv, pv[o], vv[o], pv[n]);                      // p', products of L p'
-    kmv_fin(ctx, sv, pv[n], vv[n], sv.rh, 0, sv.sc, sv.dpart);     // v' = L p'; rh.v'
-    kmv<KMV_S>(ctx, sv, vv[n], nullptr, sv.s);                     // alpha, s, products of L s
-    kmv_fin(ctx, sv, sv.s, sv.t, sv.s, 1, sv.sc, sv.dpart);        // t = L s; s.t, t.t
+    if (pending) {
+      kmv<KMV_P>(ctx, sv, slot[cur ^ 1], pv[o], vv[o], pv[n], slot[cur], thr);  // rho step, p', products of L p'
+      cur ^= 1;
+    } else {
+      kmv<KMV_P>(ctx, sv, slot[cur], pv[o], vv[o], pv[n]);                      // p', products of L p'
+    }
+    double* sc = slot[cur];
+    kmv_fin(ctx, sv, pv[n], vv[n], sv.rh, 0, sc, sv.dpart);     // v' = L p'; rh.v'
+    kmv<KMV_S>(ctx, sv, sc, vv[n], nullptr, sv.s);             // alpha, s, products of L s
+    kmv_fin(ctx, sv, sv.s, sv.t, sv.s, 1, sc, sv.dpart);        // t = L s; s.t, t.t
     hipLaunchKernelGGL(k_bi_xr, dim3((unsigned)sv.nblk), dim3(kVB), 0, s, n6, pv[n], sv.s, sv.t, sv.rh, sv.dpart,
-                       sv.nblk, sv.sc, x, sv.r, sv.dxr);           // omega, x, r; rh.r, r.r
+                       sv.nblk, sc, x, sv.r, sv.dxr);           // omega, x, r; rh.r, r.r
     pending = true;
     HIPCHK(hipGetLastError());
   }
