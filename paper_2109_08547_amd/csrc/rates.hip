@@ -964,22 +964,21 @@ __global__ void k_group_bounds(int64_t n, const int32_t* __restrict__ flag, cons
 // factors depend on (q, s) only and are tabulated first, side by side:
 // uv[q][s][0..5] = -n_qs P[q][s], uv[q][s][6..11] = (1 + n_qs) P[-q][s]
 // (n at -q equals n at q), so a term reads one contiguous row.  The table
-// has the vertex store's number type: in the FP32 store it halves the bytes
-// gathered per term, at the store's own rounding.
-template <typename UT>
+// stays FP64 in every form: an FP32 table puts a rounding floor near 1e-7
+// into the phonon map, which stalls the coupled iteration above 1e-8.
 __global__ void k_drag_uv(int64_t nm, int nbr, MeshDims md, const double* __restrict__ nocc,
-                          const double* __restrict__ phon, UT* __restrict__ uv) {
+                          const double* __restrict__ phon, double* __restrict__ uv) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nm * 12) return;
   const int64_t m = t / 12;
   const int c = (int)(t - m * 12);
   const double n = nocc[m];
   if (c < 6) {
-    uv[t] = (UT)(-n * phon[m * 6 + c]);
+    uv[t] = -n * phon[m * 6 + c];
   } else {
     const int q = (int)(m / nbr), s = (int)(m - (int64_t)q * nbr);
     const int mq = q_neg(q, md.n0, md.n1, md.n2);
-    uv[t] = (UT)((1.0 + n) * phon[((int64_t)mq * nbr + s) * 6 + c - 6]);
+    uv[t] = (1.0 + n) * phon[((int64_t)mq * nbr + s) * 6 + c - 6];
   }
 }
 
@@ -994,7 +993,7 @@ template <typename ST, int NX>
 __global__ void __launch_bounds__(256) k_drag_e(int64_t M, int64_t per_xcd, MeshDims md, const ST* __restrict__ Bp,
                                                 const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
                                                 const double* __restrict__ lomf, const double* __restrict__ we,
-                                                const ST* __restrict__ uv, double* __restrict__ De) {
+                                                const double* __restrict__ uv, double* __restrict__ De) {
   __shared__ int sq[256];
   __shared__ double sr[256];
   __shared__ double sh[6 * 4];
@@ -1021,10 +1020,10 @@ __global__ void __launch_bounds__(256) k_drag_e(int64_t M, int64_t per_xcd, Mesh
       if (vp == 0.0 && vm == 0.0) continue;
       const int jl = t / NX, s = t - jl * NX;
       const double r = sr[jl];
-      const ST* __restrict__ u = uv + ((int64_t)sq[jl] * NX + s) * 12;
+      const double* __restrict__ u = uv + ((int64_t)sq[jl] * NX + s) * 12;
       const double a = r * vp, b = r * vm;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) acc[c] += a * (double)u[c] + b * (double)u[6 + c];
+      for (int c = 0; c < 6; ++c) acc[c] += a * u[c] + b * u[6 + c];
     }
   }
   block_sum<6>(acc, sh);
@@ -1490,9 +1489,9 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   double *we = nullptr, *wphe = nullptr, *wp = nullptr, *x0 = nullptr, *x = nullptr, *De = nullptr;
   double *phon0 = nullptr, *phon = nullptr, *phonn = nullptr, *acc = nullptr, *part = nullptr, *wff = nullptr;
   double *xprev = nullptr, *sbase = nullptr;
-  ST* uvt = nullptr;
+  double* uvt = nullptr;
   ALLOC(we, M * sizeof(double));
-  ALLOC(uvt, nm * 12 * sizeof(ST));
+  ALLOC(uvt, nm * 12 * sizeof(double));
   ALLOC(wphe, nm * sizeof(double));
   ALLOC(wp, nm * sizeof(double));
   ALLOC(x0, M * 6 * sizeof(double));
@@ -1589,8 +1588,8 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
       // fixed point x = P(b + K x) solves L x = b with L = 1 - P K on the
       // range of P, started from the previous solution
       if (drag) {
-        hipLaunchKernelGGL(k_drag_uv<ST>, dim3(blocks_for(nm * 12, 256)), dim3(256), 0, s, nm, (int)nbr, md,
-                           th.nocc, phon, uvt);
+        hipLaunchKernelGGL(k_drag_uv, dim3(blocks_for(nm * 12, 256)), dim3(256), 0, s, nm, (int)nbr, md, th.nocc,
+                           phon, uvt);
         const int64_t per_xcd = (M + 7) / 8;
 #define DE(NXV)                                                                                                 \
   hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, M, per_xcd, md, Bp, Bm, \
