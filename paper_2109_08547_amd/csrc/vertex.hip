@@ -1100,70 +1100,76 @@ __device__ __forceinline__ void epi_q_wave(int64_t q, int64_t i0, int32_t t0, in
       const double ei = ep.eps[i];
       for (int32_t j = soff[u]; j < soff[u + 1]; ++j) {
         const float* cg = C + 2 * (((int64_t)(i - i0) * ldc + j) * NX);
-        double ar[NX], ai[NX];
-#pragma unroll
-        for (int x = 0; x < NX; ++x) {
-          const float2 v = *reinterpret_cast<const float2*>(cg + 2 * x);
-          ar[x] = (double)v.x * ep.cscale;
-          ai[x] = (double)v.y * ep.cscale;
-        }
         const double de = ep.eps[j] - ei;
         const int64_t tb = ((int64_t)i * ep.nstates + j) * NX;
         const cd ov = ep.fr ? state_overlap(ep.ust, ep.nb, i, j) : cmake(0.0, 0.0);
-        double bpv[NX], bmv[NX], g2v[NX];
+        // g_s = sum_x l_xs gh_x with x outermost: one component of the C
+        // row and one row of the q's l.u matrix live at a time (the sums
+        // over x still run in x order), so the branch count does not
+        // multiply the live registers; with error codes the weighted
+        // squares d2_s = sum_x |l_xs|^2 e2_x go along
+        double gr[NX], gi[NX];
+        float d2[NX];
 #pragma unroll
         for (int s = 0; s < NX; ++s) {
-          double gr = 0.0, gi = 0.0;
+          gr[s] = gi[s] = 0.0;
+          d2[s] = 0.f;
+        }
+        const float* __restrict__ bn = ep.rho ? ep.b2n + (int64_t)i * NX : nullptr;
+        const float cu2 = (float)(ep.cu * ep.cu), cv2 = (float)(ep.cv * ep.cv);
+#pragma unroll 1
+        for (int x = 0; x < NX; ++x) {
+          const float2 v = *reinterpret_cast<const float2*>(cg + 2 * x);
+          const double ar = (double)v.x * ep.cscale, ai = (double)v.y * ep.cscale;
+          const cd* __restrict__ Lx = L + x * NX;
 #pragma unroll
-          for (int x = 0; x < NX; ++x) {
-            const cd l = L[x * NX + s];
-            gr += l.x * ar[x] - l.y * ai[x];
-            gi += l.x * ai[x] + l.y * ar[x];
+          for (int s = 0; s < NX; ++s) {
+            const cd l = Lx[s];
+            gr[s] += l.x * ar - l.y * ai;
+            gi[s] += l.x * ai + l.y * ar;
           }
+          if (bn) {
+            // b2n[i][x]: the expected square root-sum-square of the products
+            // behind gh_x; a vertex component carries an error of about
+            // cu rss[x] + cv |gh_x|, the projection sum_x l u gh_x the
+            // root-sum-square of those weighted by |l u|
+            const float e2 = cu2 * bn[x] + cv2 * (float)(ar * ar + ai * ai);
+#pragma unroll
+            for (int s = 0; s < NX; ++s) d2[s] += (float)cabs2(Lx[s]) * e2;
+          }
+        }
+        double bpv[NX], bmv[NX];
+        constexpr int RS = RhoStride<NX>::value;
+        uint32_t w[RS / 4];
+#pragma unroll
+        for (int t = 0; t < RS / 4; ++t) w[t] = 0u;
+#pragma unroll
+        for (int s = 0; s < NX; ++s) {
+          double g_r = gr[s], g_i = gi[s];
           if (ep.fr) {  // Eq. 7: F_s(q) times the overlap
             const cd f = ep.fr[q * NX + s];
-            gr += f.x * ov.x - f.y * ov.y;
-            gi += f.x * ov.y + f.y * ov.x;
+            g_r += f.x * ov.x - f.y * ov.y;
+            g_i += f.x * ov.y + f.y * ov.x;
           }
-          const double g2 = gr * gr + gi * gi;
-          const double w = hwq[s];
+          const double g2 = g_r * g_r + g_i * g_i;
+          const double wq = hwq[s];
           double bp = 0.0, bm = 0.0;
-          if (w >= ep.omega_min) {
+          if (wq >= ep.omega_min) {
             if (ep.tetra) {
               bp = bm = ep.pref * g2;
             } else {
-              const double dp = de - w, dm = de + w;
+              const double dp = de - wq, dm = de + wq;
               bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
               bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
             }
           }
           bpv[s] = bp;
           bmv[s] = bm;
-          g2v[s] = g2;
+          if (bn) w[s >> 2] |= rho_encode(d2[s], (float)g2) << (8 * (s & 3));
         }
         store_row<ST, NX>(Bp + tb, bpv);
         store_row<ST, NX>(Bm + tb, bmv);
-        if (ep.rho) {
-          // b2n[i][x]: the expected square root-sum-square of the products
-          // behind gh_x; a vertex component carries an error of about
-          // cu rss[x] + cv |gh_x|, the projection sum_x l u gh_x the
-          // root-sum-square of those weighted by |l u|
-          const float* __restrict__ bn = ep.b2n + (int64_t)i * NX;
-          const float cu2 = (float)(ep.cu * ep.cu), cv2 = (float)(ep.cv * ep.cv);
-          float e2[NX];
-#pragma unroll
-          for (int x = 0; x < NX; ++x) e2[x] = cu2 * bn[x] + cv2 * (float)(ar[x] * ar[x] + ai[x] * ai[x]);
-          constexpr int RS = RhoStride<NX>::value;
-          uint32_t w[RS / 4];
-#pragma unroll
-          for (int t = 0; t < RS / 4; ++t) w[t] = 0u;
-#pragma unroll
-          for (int s = 0; s < NX; ++s) {
-            float d2 = 0.f;
-#pragma unroll
-            for (int x = 0; x < NX; ++x) d2 += (float)cabs2(L[x * NX + s]) * e2[x];
-            w[s >> 2] |= rho_encode(d2, (float)g2v[s]) << (8 * (s & 3));
-          }
+        if (bn) {
           uint8_t* __restrict__ rp = ep.rho + ((int64_t)i * ep.nstates + j) * RS;
           if constexpr (RS == 8) {
             *reinterpret_cast<uint2*>(rp) = make_uint2(w[0], w[1]);
