@@ -1073,6 +1073,93 @@ struct GemmOp<float> {
 // (k_t, k_t + q) of q's list with t in [t0, t1) (the chunk's initial
 // states) and write g_s = sum_x l u gh_x, |g|^2 and the Gaussians into the
 // store B+/-.
+// One pair (i, j) of the GEMM forms' step-2 epilogue: cg is the pair's C
+// row (NX complex FP32 values), L and hwq the q's l.u matrix and phonon
+// energies; writes the pair's rows of B+ and B- (and its error codes).
+template <typename ST, int NX>
+__device__ __forceinline__ void epi_pair(int64_t i, int64_t j, int64_t q, double ei, const EpiParams& ep,
+                                         const cd* __restrict__ L, const double* __restrict__ hwq,
+                                         const float* __restrict__ cg, ST* __restrict__ Bp,
+                                         ST* __restrict__ Bm) {
+  const double de = ep.eps[j] - ei;
+  const int64_t tb = ((int64_t)i * ep.nstates + j) * NX;
+  const cd ov = ep.fr ? state_overlap(ep.ust, ep.nb, i, j) : cmake(0.0, 0.0);
+  // g_s = sum_x l_xs gh_x with x outermost: one component of the C
+  // row and one row of the q's l.u matrix live at a time (the sums
+  // over x still run in x order), so the branch count does not
+  // multiply the live registers; with error codes the weighted
+  // squares d2_s = sum_x |l_xs|^2 e2_x go along
+  double gr[NX], gi[NX];
+  float d2[NX];
+#pragma unroll
+  for (int s = 0; s < NX; ++s) {
+    gr[s] = gi[s] = 0.0;
+    d2[s] = 0.f;
+  }
+  const float* __restrict__ bn = ep.rho ? ep.b2n + (int64_t)i * NX : nullptr;
+  const float cu2 = (float)(ep.cu * ep.cu), cv2 = (float)(ep.cv * ep.cv);
+#pragma unroll 1
+  for (int x = 0; x < NX; ++x) {
+    const float2 v = *reinterpret_cast<const float2*>(cg + 2 * x);
+    const double ar = (double)v.x * ep.cscale, ai = (double)v.y * ep.cscale;
+    const cd* __restrict__ Lx = L + x * NX;
+#pragma unroll
+    for (int s = 0; s < NX; ++s) {
+      const cd l = Lx[s];
+      gr[s] += l.x * ar - l.y * ai;
+      gi[s] += l.x * ai + l.y * ar;
+    }
+    if (bn) {
+      // b2n[i][x]: the expected square root-sum-square of the products
+      // behind gh_x; a vertex component carries an error of about
+      // cu rss[x] + cv |gh_x|, the projection sum_x l u gh_x the
+      // root-sum-square of those weighted by |l u|
+      const float e2 = cu2 * bn[x] + cv2 * (float)(ar * ar + ai * ai);
+#pragma unroll
+      for (int s = 0; s < NX; ++s) d2[s] += (float)cabs2(Lx[s]) * e2;
+    }
+  }
+  double bpv[NX], bmv[NX];
+  constexpr int RS = RhoStride<NX>::value;
+  uint32_t w[RS / 4];
+#pragma unroll
+  for (int t = 0; t < RS / 4; ++t) w[t] = 0u;
+#pragma unroll
+  for (int s = 0; s < NX; ++s) {
+    double g_r = gr[s], g_i = gi[s];
+    if (ep.fr) {  // Eq. 7: F_s(q) times the overlap
+      const cd f = ep.fr[q * NX + s];
+      g_r += f.x * ov.x - f.y * ov.y;
+      g_i += f.x * ov.y + f.y * ov.x;
+    }
+    const double g2 = g_r * g_r + g_i * g_i;
+    const double wq = hwq[s];
+    double bp = 0.0, bm = 0.0;
+    if (wq >= ep.omega_min) {
+      if (ep.tetra) {
+        bp = bm = ep.pref * g2;
+      } else {
+        const double dp = de - wq, dm = de + wq;
+        bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
+        bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
+      }
+    }
+    bpv[s] = bp;
+    bmv[s] = bm;
+    if (bn) w[s >> 2] |= rho_encode(d2[s], (float)g2) << (8 * (s & 3));
+  }
+  store_row<ST, NX>(Bp + tb, bpv);
+  store_row<ST, NX>(Bm + tb, bmv);
+  if (bn) {
+    uint8_t* __restrict__ rp = ep.rho + ((int64_t)i * ep.nstates + j) * RS;
+    if constexpr (RS == 8) {
+      *reinterpret_cast<uint2*>(rp) = make_uint2(w[0], w[1]);
+    } else {
+      *reinterpret_cast<uint4*>(rp) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+}
+
 template <typename ST, int NX>
 __device__ __forceinline__ void epi_q_wave(int64_t q, int64_t i0, int32_t t0, int32_t t1, const EpiParams& ep,
                                            const int32_t* __restrict__ kept, const int32_t* __restrict__ kidx,
@@ -1099,84 +1186,7 @@ __device__ __forceinline__ void epi_q_wave(int64_t q, int64_t i0, int32_t t0, in
     for (int32_t i = soff[t]; i < soff[t + 1]; ++i) {
       const double ei = ep.eps[i];
       for (int32_t j = soff[u]; j < soff[u + 1]; ++j) {
-        const float* cg = C + 2 * (((int64_t)(i - i0) * ldc + j) * NX);
-        const double de = ep.eps[j] - ei;
-        const int64_t tb = ((int64_t)i * ep.nstates + j) * NX;
-        const cd ov = ep.fr ? state_overlap(ep.ust, ep.nb, i, j) : cmake(0.0, 0.0);
-        // g_s = sum_x l_xs gh_x with x outermost: one component of the C
-        // row and one row of the q's l.u matrix live at a time (the sums
-        // over x still run in x order), so the branch count does not
-        // multiply the live registers; with error codes the weighted
-        // squares d2_s = sum_x |l_xs|^2 e2_x go along
-        double gr[NX], gi[NX];
-        float d2[NX];
-#pragma unroll
-        for (int s = 0; s < NX; ++s) {
-          gr[s] = gi[s] = 0.0;
-          d2[s] = 0.f;
-        }
-        const float* __restrict__ bn = ep.rho ? ep.b2n + (int64_t)i * NX : nullptr;
-        const float cu2 = (float)(ep.cu * ep.cu), cv2 = (float)(ep.cv * ep.cv);
-#pragma unroll 1
-        for (int x = 0; x < NX; ++x) {
-          const float2 v = *reinterpret_cast<const float2*>(cg + 2 * x);
-          const double ar = (double)v.x * ep.cscale, ai = (double)v.y * ep.cscale;
-          const cd* __restrict__ Lx = L + x * NX;
-#pragma unroll
-          for (int s = 0; s < NX; ++s) {
-            const cd l = Lx[s];
-            gr[s] += l.x * ar - l.y * ai;
-            gi[s] += l.x * ai + l.y * ar;
-          }
-          if (bn) {
-            // b2n[i][x]: the expected square root-sum-square of the products
-            // behind gh_x; a vertex component carries an error of about
-            // cu rss[x] + cv |gh_x|, the projection sum_x l u gh_x the
-            // root-sum-square of those weighted by |l u|
-            const float e2 = cu2 * bn[x] + cv2 * (float)(ar * ar + ai * ai);
-#pragma unroll
-            for (int s = 0; s < NX; ++s) d2[s] += (float)cabs2(Lx[s]) * e2;
-          }
-        }
-        double bpv[NX], bmv[NX];
-        constexpr int RS = RhoStride<NX>::value;
-        uint32_t w[RS / 4];
-#pragma unroll
-        for (int t = 0; t < RS / 4; ++t) w[t] = 0u;
-#pragma unroll
-        for (int s = 0; s < NX; ++s) {
-          double g_r = gr[s], g_i = gi[s];
-          if (ep.fr) {  // Eq. 7: F_s(q) times the overlap
-            const cd f = ep.fr[q * NX + s];
-            g_r += f.x * ov.x - f.y * ov.y;
-            g_i += f.x * ov.y + f.y * ov.x;
-          }
-          const double g2 = g_r * g_r + g_i * g_i;
-          const double wq = hwq[s];
-          double bp = 0.0, bm = 0.0;
-          if (wq >= ep.omega_min) {
-            if (ep.tetra) {
-              bp = bm = ep.pref * g2;
-            } else {
-              const double dp = de - wq, dm = de + wq;
-              bp = ep.pref * g2 * exp(-dp * dp * ep.inv2s2);
-              bm = ep.pref * g2 * exp(-dm * dm * ep.inv2s2);
-            }
-          }
-          bpv[s] = bp;
-          bmv[s] = bm;
-          if (bn) w[s >> 2] |= rho_encode(d2[s], (float)g2) << (8 * (s & 3));
-        }
-        store_row<ST, NX>(Bp + tb, bpv);
-        store_row<ST, NX>(Bm + tb, bmv);
-        if (bn) {
-          uint8_t* __restrict__ rp = ep.rho + ((int64_t)i * ep.nstates + j) * RS;
-          if constexpr (RS == 8) {
-            *reinterpret_cast<uint2*>(rp) = make_uint2(w[0], w[1]);
-          } else {
-            *reinterpret_cast<uint4*>(rp) = make_uint4(w[0], w[1], w[2], w[3]);
-          }
-        }
+        epi_pair<ST, NX>(i, j, q, ei, ep, L, hwq, C + 2 * (((int64_t)(i - i0) * ldc + j) * NX), Bp, Bm);
       }
     }
   }
@@ -1191,6 +1201,35 @@ __global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t
   const int64_t q = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (q >= nq) return;  // whole wavefront exits together
   epi_q_wave<ST, NX>(q, i0, t0, t1, ep, kept, kidx, soff, poff, plist, C, ldc, Bp, Bm);
+}
+
+// The same epilogue row by row: one block per initial state i of the chunk
+// [i0, i0 + ni), its threads over final states j (256 at a time, their q
+// indices formed once into LDS), so that the C row, the B+- rows and the
+// error codes are read and written along j; each pair gathers its q's l.u
+// matrix instead.  Blocks are numbered so that each XCD takes a contiguous
+// range of states (neighbouring k: overlapping q, shared in its L2).
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_epi_rows(int64_t i0, int64_t ni, int64_t per_xcd, EpiParams ep,
+                                                  const float* __restrict__ C, int64_t ldc, ST* __restrict__ Bp,
+                                                  ST* __restrict__ Bm) {
+  __shared__ int sq[256];
+  const int64_t il = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (il >= ni) return;  // whole block
+  const int64_t i = i0 + il, M = ep.nstates;
+  const int ki = ep.st_k[i];
+  const double ei = ep.eps[i];
+  for (int64_t j0 = 0; j0 < M; j0 += 256) {
+    const int nj = (int)(M - j0 < 256 ? M - j0 : 256);
+    __syncthreads();  // the previous chunk is consumed
+    if ((int)threadIdx.x < nj) sq[threadIdx.x] = q_of(ep.st_k[j0 + threadIdx.x], ki, ep.n0, ep.n1, ep.n2);
+    __syncthreads();
+    if ((int)threadIdx.x < nj) {
+      const int64_t j = j0 + threadIdx.x, q = sq[threadIdx.x];
+      epi_pair<ST, NX>(i, j, q, ei, ep, ep.Lq + q * NX * NX, ep.hw + q * NX, C + 2 * ((il * ldc + j) * NX), Bp,
+                       Bm);
+    }
+  }
 }
 
 // Step-1 epilogue of the GEMM path: B2[(i, x)][(Rp, n')] = C1[i][col] e^{-2 pi i k_i.Rp}
@@ -1490,9 +1529,9 @@ static elph_status launch_gemm_nx(elph_ctx ctx, const EpiParams& ep, void* Bp, v
     const int64_t c0 = i0 * NX, nc = ni * NX;
     launch_cgemm<OP, 2>(ctx->stream, c0, nc, M, ctx->kp, NX, ctx->d_B2, ctx->d_Ap, C, ldc);
     if (t1 == ctx->nkept) mark(ctx, 5);  // step-2 window: the contraction (and earlier chunks' epilogues)
-    hipLaunchKernelGGL((k_epi_q<ST, NX>), dim3((unsigned)((ctx->nk + 3) / 4)), dim3(256), 0, ctx->stream, ctx->nk,
-                       i0, t0, t1, ep, ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist,
-                       (const float*)C, ldc, (ST*)Bp, (ST*)Bm);
+    const int64_t per_xcd = (ni + 7) / 8;
+    hipLaunchKernelGGL((k_epi_rows<ST, NX>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, ctx->stream, i0, ni,
+                       per_xcd, ep, (const float*)C, ldc, (ST*)Bp, (ST*)Bm);
     t0 = t1;
   }
   dev_free(ctx, C);
