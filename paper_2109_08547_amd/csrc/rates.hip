@@ -434,6 +434,107 @@ __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, Mes
   }
 }
 
+// The six-column gather with the pair terms staged in LDS.  A wavefront
+// per q (the four of a block take neighbouring q, as in k_q_gather_csr)
+// takes its list 64 pairs at a time; each lane stages its pair's terms
+// v_s = B+_ijs f_i (1 - f_j) and w_c = (x_j - x_i)_c, one state pair per
+// round (pairs of several bands take several rounds, lanes already done
+// stage zeros).  Lane (s, g), g < G = 64 / NX, then adds v_s w_c of the
+// staged pairs g, g + G, ... for the six c, and a last pass sums the G
+// partial rows in g order.  A lane holds six accumulators instead of NX x 6,
+// so the gather runs at a higher occupancy; the order of the sum is fixed.
+template <typename ST, int NX>
+__global__ void __launch_bounds__(256) k_q_gather_lds(int64_t nq, int64_t M, MeshDims md,
+                                                      const ST* __restrict__ Bp, const int32_t* __restrict__ kept,
+                                                      const int32_t* __restrict__ kidx,
+                                                      const int32_t* __restrict__ soff,
+                                                      const int32_t* __restrict__ poff,
+                                                      const int32_t* __restrict__ plist, const double* __restrict__ f,
+                                                      const double* __restrict__ omf, const double* __restrict__ x,
+                                                      double* __restrict__ acc) {
+  constexpr int G = 64 / NX, NO = NX * 6;
+  static_assert(G * NO <= 64 * 6, "partial rows fit the staged w block");
+  __shared__ double Ys[4][64][NX];
+  __shared__ double Ws[4][64][6];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+  if (q >= nq) return;  // whole wavefront; only wavefront barriers below
+  const int qc = (int)(q % md.n2);
+  const int qt = (int)(q / md.n2);
+  const int qb = qt % md.n1, qa = qt / md.n1;
+  const int ms = lane % NX, mg = lane / NX;  // lanes with mg >= G idle in the sum
+  double a[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) a[c] = 0.0;
+  double(*__restrict__ ys)[NX] = Ys[wave];
+  double(*__restrict__ ws)[6] = Ws[wave];
+  const int32_t pe = poff[q + 1];
+  for (int32_t p0 = poff[q]; p0 < pe; p0 += 64) {
+    const int32_t p = p0 + lane;
+    int32_t ib = 0, ni = 0, jb = 0, nj = 0;
+    if (p < pe) {
+      const int32_t t = plist[p];
+      const int k = kept[t];
+      const int kc = k % md.n2, kt = k / md.n2;
+      const int kb = kt % md.n1, ka = kt / md.n1;
+      int c2 = kc + qc; if (c2 >= md.n2) c2 -= md.n2;
+      int b2 = kb + qb; if (b2 >= md.n1) b2 -= md.n1;
+      int a2 = ka + qa; if (a2 >= md.n0) a2 -= md.n0;
+      const int32_t u = kidx[(a2 * md.n1 + b2) * md.n2 + c2];
+      ib = soff[t];
+      ni = soff[t + 1] - ib;
+      jb = soff[u];
+      nj = soff[u + 1] - jb;
+    }
+    int nr = ni * nj;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nr = max(nr, __shfl_xor(nr, o, 64));
+    for (int r = 0; r < nr; ++r) {
+      if (r < ni * nj) {
+        const int64_t i = ib + r / nj, j = jb + r % nj;
+        const double occ = f[i] * omf[j];
+        const ST* b = Bp + (i * M + j) * NX;
+#pragma unroll
+        for (int s = 0; s < NX; ++s) ys[lane][s] = (double)b[s] * occ;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ws[lane][c] = x[j * 6 + c] - x[i * 6 + c];
+      } else {
+#pragma unroll
+        for (int s = 0; s < NX; ++s) ys[lane][s] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ws[lane][c] = 0.0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (mg < G) {
+        for (int l = mg; l < 64; l += G) {
+          const double v = ys[l][ms];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) a[c] += v * ws[l][c];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();  // staged values consumed before the next round
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  // partial rows into the w block, then outputs e = s * 6 + c summed over g
+  double* red = &ws[0][0];
+  if (mg < G) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) red[(mg * NX + ms) * 6 + c] = a[c];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int e = lane; e < NO; e += 64) {
+    double v = 0.0;
+    for (int g = 0; g < G; ++g) v += red[g * NO + e];
+    acc[q * NO + e] = v;
+  }
+}
+
 template <typename ST, int NV>
 void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* omf, const double* x,
                      double* acc, const RateErr* err) {
@@ -447,6 +548,20 @@ void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* 
     csr = st == ELPH_OK;
     if (!csr) ctx->pairs_failed = true;
     if (st == ELPH_ENOMEM) ctx->err.clear();  // the walk below needs no extra memory
+  }
+  if (csr && NV == 6 && !er.idx) {
+#define QL(NXV)                                                                                                 \
+  hipLaunchKernelGGL((k_q_gather_lds<ST, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, md, Bp,        \
+                     ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist, f, omf, x, acc)
+    switch (ctx->nbr) {
+      case 3: QL(3); break;
+      case 6: QL(6); break;
+      case 9: QL(9); break;
+      case 12: QL(12); break;
+      default: QL(15); break;
+    }
+#undef QL
+    return;
   }
   if (csr) {
 #define QG(NXV)                                                                                                \
