@@ -1102,18 +1102,21 @@ __global__ void k_drag_uv(int64_t nm, int nbr, MeshDims md, const double* __rest
 // then the block's threads take the chunk's (j, s) terms in order, reading
 // B+- along the row and the (q, s) row of uv.  Blocks are numbered so that
 // each XCD (blocks b, b + 8, ... dispatched to one) takes a contiguous range
-// of states: neighbouring states sit at neighbouring k, so the q windows
-// their rows visit overlap in that XCD's L2.
+// of `rows`, a list of the states in Z order of their k: rows run together
+// on one XCD then sit at nearby k, so the uv rows they visit overlap in that
+// XCD's L2.  Each row is one block's fixed-order sum, whatever the list.
 template <typename ST, int NX>
 __global__ void __launch_bounds__(256) k_drag_e(int64_t M, int64_t per_xcd, MeshDims md, const ST* __restrict__ Bp,
-                                                const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
+                                                const ST* __restrict__ Bm, const int32_t* __restrict__ rows,
+                                                const int32_t* __restrict__ st_k,
                                                 const double* __restrict__ lomf, const double* __restrict__ we,
                                                 const double* __restrict__ uv, double* __restrict__ De) {
   __shared__ int sq[256];
   __shared__ double sr[256];
   __shared__ double sh[6 * 4];
-  const int64_t i = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (i >= M) return;  // whole block
+  const int64_t pos = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (pos >= M) return;  // whole block
+  const int64_t i = rows[pos];
   const int ki = st_k[i];
   const double li = lomf[i];
   double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -1605,8 +1608,10 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   double *phon0 = nullptr, *phon = nullptr, *phonn = nullptr, *acc = nullptr, *part = nullptr, *wff = nullptr;
   double *xprev = nullptr, *sbase = nullptr;
   double* uvt = nullptr;
+  int32_t* drow = nullptr;
   ALLOC(we, M * sizeof(double));
   ALLOC(uvt, nm * 12 * sizeof(double));
+  ALLOC(drow, M * sizeof(int32_t));
   ALLOC(wphe, nm * sizeof(double));
   ALLOC(wp, nm * sizeof(double));
   ALLOC(x0, M * 6 * sizeof(double));
@@ -1620,6 +1625,28 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   ALLOC(wff, M * sizeof(double));
   ALLOC(xprev, M * 6 * sizeof(double));
   std::vector<double> hpart(256 * 64);
+  {
+    // rows of the electron drag in Z order of their k (bit-interleaved
+    // mesh coordinates), so that the rows an XCD runs together have nearby
+    // k and the uv rows they visit overlap in that XCD's L2
+    std::vector<int32_t> hk(M), ord(M);
+    std::vector<uint64_t> key(M);
+    HIPCHK(hipMemcpyAsync(hk.data(), ctx->d_state_k, M * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < M; ++i) {
+      const int k = hk[i];
+      const uint32_t c = (uint32_t)(k % md.n2), b = (uint32_t)((k / md.n2) % md.n1), a = (uint32_t)(k / md.n2 / md.n1);
+      uint64_t z = 0;
+      for (int bit = 0; bit < 21; ++bit)
+        z |= (uint64_t)((a >> bit) & 1) << (3 * bit + 2) | (uint64_t)((b >> bit) & 1) << (3 * bit + 1) |
+             (uint64_t)((c >> bit) & 1) << (3 * bit);
+      key[i] = z;
+      ord[i] = (int32_t)i;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t u, int32_t v) { return key[u] < key[v]; });
+    HIPCHK(hipMemcpyAsync(drow, ord.data(), M * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
 
   if (ctx->rates_valid && ctx->rates_T == T) {
     // rates of the preceding elph_scatt_rates at this temperature
@@ -1708,7 +1735,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
         const int64_t per_xcd = (M + 7) / 8;
 #define DE(NXV)                                                                                                 \
   hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, M, per_xcd, md, Bp, Bm, \
-                     ctx->d_state_k, th.lomf, we, uvt, De)
+                     drow, ctx->d_state_k, th.lomf, we, uvt, De)
         switch (nbr) {
           case 3: DE(3); break;
           case 6: DE(6); break;
@@ -1870,7 +1897,7 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
   if (iters) *iters = used;
   for (void* p : {(void*)we, (void*)wphe, (void*)wp, (void*)x0, (void*)x, (void*)De, (void*)phon0, (void*)phon,
                   (void*)phonn, (void*)acc, (void*)part, (void*)wff, (void*)xprev, (void*)sbase, (void*)wpp,
-                  (void*)t3, (void*)s3, (void*)uvt})
+                  (void*)t3, (void*)s3, (void*)uvt, (void*)drow})
     dev_free(ctx, p);
   free_thermal(ctx, &th);
   if (!converged) {
