@@ -393,7 +393,12 @@ def run_large(E, torch, form="fp32", mat=None, cpu_rows=0):
         import oracle
         rows = np.sort(np.random.default_rng(5).choice(sz["nstates"], cpu_rows, replace=False))
         t1 = time.perf_counter()
-        w_or, M = oracle.rates_e_rows(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], cfg["T"], rows)
+        def said(done, total):
+            print("bench: large100 oracle rows %d / %d (%.1f s)" % (done, total, time.perf_counter() - t1),
+                  file=sys.stderr, flush=True)
+
+        w_or, M = oracle.rates_e_rows(mat, cfg["mesh"], cfg["mu"], cfg["window"], cfg["sigma"], cfg["T"], rows,
+                                      progress=said)
         t_or = time.perf_counter() - t1
         assert M == sz["nstates"]
         cpu = {"value": 2.0 * len(rows) * M * sz["nbr"] / t_or, "unit": "transition probabilities/s",

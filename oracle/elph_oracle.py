@@ -744,14 +744,16 @@ class Problem:
         return out
 
 
-def rates_e_rows(mat, mesh, mu, window, sigma, T, rows, omega_min=OMEGA_MIN_DEFAULT):
+def rates_e_rows(mat, mesh, mu, window, sigma, T, rows, omega_min=OMEGA_MIN_DEFAULT, progress=None):
     """W_e of Eq. 21 (e-ph part) for the initial active states ``rows`` (indices
     in the (kept k, band) order of Problem), each against every final active
     state, with the Gaussian delta of Eq. 8.  The same definition as
     Problem.rates_e on Problem.transition_probs, but the phonon modes (Eq. 3)
     are diagonalised only at the q = k' - k that the rows need, so that it
     runs on meshes whose whole-mesh phonon tables would not fit (100^3).
-    Returns (W [len(rows)], nstates).  Non-polar materials only."""
+    Returns (W [len(rows)], nstates).  Non-polar materials only.  progress,
+    if given, is called as progress(rows done, rows) before the first row and
+    after each row (it only reports)."""
     if mat.get("zstar") is not None:
         raise ValueError("rates_e_rows: polar materials need Problem")
     n = int(mesh)
@@ -772,6 +774,8 @@ def rates_e_rows(mat, mesh, mu, window, sigma, T, rows, omega_min=OMEGA_MIN_DEFA
     f, omf = fermi_pair(eps, mu, T)
     pref = 2.0 * np.pi / (HBAR_EVS * nk)
     out = np.empty(len(rows))
+    if progress is not None:
+        progress(0, len(rows))
     for r, i in enumerate(np.asarray(rows)):
         kidx = st_k[i]
         kmesh = kept[kidx]
@@ -791,6 +795,8 @@ def rates_e_rows(mat, mesh, mu, window, sigma, T, rows, omega_min=OMEGA_MIN_DEFA
             x = pref * g2j * occ * (nq[st_k] * dp + onq[st_k] * dm)
         x = np.where(on[st_k], x, 0.0)
         out[r] = x.sum() / (f[i] * omf[i])
+        if progress is not None:
+            progress(r + 1, len(rows))
     return out, nstates
 
 
