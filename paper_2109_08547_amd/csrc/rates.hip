@@ -124,36 +124,44 @@ __global__ void __launch_bounds__(256) k_we_rows(int64_t M, MeshDims md, const S
                                                  const ST* __restrict__ Bm, const int32_t* __restrict__ st_k,
                                                  const double* __restrict__ lomf, const double* __restrict__ nocc,
                                                  double* __restrict__ we, RateErr er) {
+  // The row goes in chunks of 256 final states: their q indices and
+  // occupation ratios are formed once per j into LDS, then the threads take
+  // the chunk's (j, s) terms in order, so the B+- rows (and the codes) are
+  // read contiguously.
   __shared__ double sh[8];
   __shared__ double rtab[256];
+  __shared__ int sq[256];
+  __shared__ double sw[256];
   const int64_t i = er.idx ? er.idx[blockIdx.x] : blockIdx.x;
   const int ki = st_k[i];
   const double li = lomf[i];
   const uint8_t* __restrict__ rho = er.rho;
-  if (rho) {
-    rtab[threadIdx.x] = rho_decode(threadIdx.x);
-    __syncthreads();
-  }
+  if (rho) rtab[threadIdx.x] = rho_decode(threadIdx.x);  // read after the first chunk's barrier
   double acc[2] = {0.0, 0.0};
   const ST* __restrict__ bp = Bp + i * M * NX;
   const ST* __restrict__ bm = Bm + i * M * NX;
-  for (int64_t j = threadIdx.x; j < M; j += 256) {
-    const int q = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
-    const double* nq = nocc + (int64_t)q * NX;
-    double b = 0.0, e = 0.0;
-    PairCodes<NX> pc;
-    if (rho) pc.load(rho + (i * M + j) * RhoStride<NX>::value);
-#pragma unroll
-    for (int s = 0; s < NX; ++s) {
-      const double n = nq[s];
-      const double t = (double)bp[j * NX + s] * n + (double)bm[j * NX + s] * (1.0 + n);
-      b += t;
-      if (rho) e += t * rtab[pc[s]];
+  constexpr int RS = RhoStride<NX>::value;
+  const uint8_t* __restrict__ rrow = rho ? rho + i * M * RS : nullptr;
+  for (int64_t j0 = 0; j0 < M; j0 += 256) {
+    const int nj = (int)(M - j0 < 256 ? M - j0 : 256);
+    __syncthreads();  // the previous chunk is consumed
+    if ((int)threadIdx.x < nj) {
+      const int64_t j = j0 + threadIdx.x;
+      sq[threadIdx.x] = q_between(st_k[j], ki, md.n0, md.n1, md.n2);
+      sw[threadIdx.x] = exp(lomf[j] - li);
     }
-    if (b != 0.0) {
-      const double w = exp(lomf[j] - li);
-      acc[0] += b * w;
-      acc[1] += e * w;
+    __syncthreads();
+    const ST* __restrict__ cp = bp + j0 * NX;
+    const ST* __restrict__ cm = bm + j0 * NX;
+    for (int t = threadIdx.x; t < nj * NX; t += 256) {
+      const int jl = t / NX, s = t - jl * NX;
+      const double n = nocc[(int64_t)sq[jl] * NX + s];
+      const double b = (double)cp[t] * n + (double)cm[t] * (1.0 + n);
+      if (b != 0.0) {  // a vanished term never meets the ratio (which may overflow far below mu)
+        const double v = b * sw[jl];
+        acc[0] += v;
+        if (rho) acc[1] += v * rtab[rrow[(j0 + jl) * RS + s]];
+      }
     }
   }
   if (rho) {
