@@ -644,6 +644,45 @@ def test_iterate_metal6(level):
     ctx.close()
 
 
+_branch_cases = {}
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("na", [1, 3, 4])
+def test_iterate_coupled_3_9_12_branches(na, form):
+    """The coupled iteration with 3, 9 and 12 phonon branches (metal6's
+    settings with 1, 3 and 4 atoms) against the oracle: the drag kernels and
+    the LDS-staged drag gather at the branch counts the metal6 and 16-band
+    cases leave out, with the FP64 and the FP32 store."""
+    if na not in _branch_cases:
+        cfg = dict(synth.config("metal6"))
+        cfg.update(na=na)
+        _branch_cases[na] = Case("metal6", mat=synth.material_for(cfg), cfg=cfg)
+    c = _branch_cases[na]
+    T = c.T
+    ctx = make_ctx(c.cfg, c.mat, precision=form)
+    sz = E.elph_sizes(ctx)
+    assert sz["nbr"] == 3 * na
+    M, nm = sz["nstates"], sz["nk"] * sz["nbr"]
+    I, J, F, G = dtensor(3 * M), dtensor(3 * M), dtensor(3 * nm), dtensor(3 * nm)
+    wext = oracle.default_w_ext(c.prob, T, gamma0=1e13)
+    wext_d = torch.from_numpy(np.ascontiguousarray(wext.reshape(-1))).to(DEV)
+    E.elph_iterate(ctx, T, I, J, F, G, W_ph_ext=wext_d, level=3, tol=1e-12, maxit=400)
+    torch.cuda.synchronize()
+    ref = oracle.iterate(c.prob, T, c.Xp, c.Xm, 3, tol=1e-12, maxit=400, w_ext=wext)
+    assert ref["converged"]
+    got = dict(I=I.cpu().numpy().reshape(M, 3), J=J.cpu().numpy().reshape(M, 3),
+               F=F.cpu().numpy().reshape(-1, sz["nbr"], 3), G=G.cpu().numpy().reshape(-1, sz["nbr"], 3))
+    # FP32 store: each X carries ~1e-7 of its vertex scale, which the solve
+    # carries into the deviations at the same relative order
+    bar = 1e-8 if form == "fp64" else 1e-5
+    for key in ("I", "J", "F", "G"):
+        scale = np.abs(ref[key]).max()
+        assert scale > 0, key
+        assert np.abs(got[key] - ref[key]).max() <= bar * scale, key
+    ctx.close()
+
+
 def test_window_excluding_everything_is_einval():
     c = case("plain8")
     ctx = make_ctx(c.cfg, c.mat, window=1e-9, mu=50.0)
