@@ -353,7 +353,8 @@ elph_status ensure_pairs(elph_ctx ctx) {
 // acc[q][s][c] over the pair list of q: lanes take every 64th pair, then a
 // fixed-order butterfly over the wavefront
 // (NV = 1: optional error codes as in k_we_rows, per branch; er.idx
-// restricts the launch to er.n listed wave vectors)
+// restricts the launch to er.n listed wave vectors).  The phonon rates use
+// it (NV = 1); the six drag columns go through k_q_gather_lds.
 template <typename ST, int NV, int NX>
 __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, MeshDims md,
                                                       const ST* __restrict__ Bp, const int32_t* __restrict__ kept,
@@ -557,32 +558,33 @@ void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* 
     if (!csr) ctx->pairs_failed = true;
     if (st == ELPH_ENOMEM) ctx->err.clear();  // the walk below needs no extra memory
   }
-  if (csr && NV == 6 && !er.idx) {
+  if (csr) {
+    if constexpr (NV == 6) {
+      // the drag columns (no row list or codes come with them)
 #define QL(NXV)                                                                                                 \
   hipLaunchKernelGGL((k_q_gather_lds<ST, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, md, Bp,        \
                      ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist, f, omf, x, acc)
-    switch (ctx->nbr) {
-      case 3: QL(3); break;
-      case 6: QL(6); break;
-      case 9: QL(9); break;
-      case 12: QL(12); break;
-      default: QL(15); break;
-    }
+      switch (ctx->nbr) {
+        case 3: QL(3); break;
+        case 6: QL(6); break;
+        case 9: QL(9); break;
+        case 12: QL(12); break;
+        default: QL(15); break;
+      }
 #undef QL
-    return;
-  }
-  if (csr) {
+    } else {
 #define QG(NXV)                                                                                                \
   hipLaunchKernelGGL((k_q_gather_csr<ST, NV, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, md, Bp,   \
                      ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist, f, omf, x, acc, er)
-    switch (ctx->nbr) {
-      case 3: QG(3); break;
-      case 6: QG(6); break;
-      case 9: QG(9); break;
-      case 12: QG(12); break;
-      default: QG(15); break;
-    }
+      switch (ctx->nbr) {
+        case 3: QG(3); break;
+        case 6: QG(6); break;
+        case 9: QG(9); break;
+        case 12: QG(12); break;
+        default: QG(15); break;
+      }
 #undef QG
+    }
     return;
   }
   // pair lists beyond 2^31 entries (or not allocatable): walk every kept k per q
