@@ -468,7 +468,7 @@ static void drop_derived(elph_ctx ctx) {
                    (void**)&ctx->d_gR,      (void**)&ctx->d_B2,        (void**)&ctx->d_Bp,
                    (void**)&ctx->d_Bm,      (void**)&ctx->d_we_part,   (void**)&ctx->d_order,
                    (void**)&ctx->d_goff,    (void**)&ctx->d_we_cache,  (void**)&ctx->d_wph_cache,
-                   (void**)&ctx->d_poff,    (void**)&ctx->d_plist,     (void**)&ctx->d_frohlich,
+                   (void**)&ctx->d_poff,    (void**)&ctx->d_plist,     (void**)&ctx->d_frohlich, (void**)&ctx->d_ppk,
                    (void**)&ctx->d_ustate,  (void**)&ctx->d_rho,       (void**)&ctx->d_b2n,
                    (void**)&ctx->d_i3_fold};
   for (void** p : ptrs) {

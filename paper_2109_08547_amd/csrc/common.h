@@ -167,6 +167,7 @@ struct elph_ctx_s {
   bool groups_ready = false;
   int32_t* d_poff = nullptr;      // [nk+1] offsets of the pair lists by q
   int32_t* d_plist = nullptr;     // [nkept^2] kept index t of each pair (k_t, k_t + q)
+  uint64_t* d_ppk = nullptr;      // [nkept^2] the pair's state ranges, packed (pack_pair), list order
   bool pairs_ready = false;
   bool pairs_failed = false;      // lists not allocatable: q-gathers walk the kept set
   double* d_we_cache = nullptr;   // [nstates] W_e of the last full elph_scatt_rates

@@ -255,12 +255,27 @@ __global__ void k_pair_count(int64_t nkept, const int32_t* __restrict__ kept, Me
 }
 
 __global__ void k_pair_fill(int64_t nkept, const int32_t* __restrict__ kept, MeshDims md,
-                            const int32_t* __restrict__ off, int32_t* __restrict__ cur, int32_t* __restrict__ tmp) {
+                            const int32_t* __restrict__ off, int32_t* __restrict__ cur, uint64_t* __restrict__ tmp) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nkept * nkept) return;
   const int64_t t = p / nkept, u = p - t * nkept;
   const int q = q_between(kept[u], kept[t], md.n0, md.n1, md.n2);
-  tmp[off[q] + atomicAdd(&cur[q], 1)] = (int32_t)t;
+  tmp[off[q] + atomicAdd(&cur[q], 1)] = (uint64_t)t | ((uint64_t)u << 32);
+}
+
+// A pair's two state ranges in one word: first state and count of k_t in the
+// low half, of k_u = k_t + q in the high half (26 bits of first state, 6 of
+// count - 1 each; states < 2^26 and at most 64 per k, which the callers check).
+__device__ inline uint64_t pack_pair(int32_t ib, int32_t ni, int32_t jb, int32_t nj) {
+  return (uint64_t)((uint32_t)ib | ((uint32_t)(ni - 1) << 26)) |
+         ((uint64_t)((uint32_t)jb | ((uint32_t)(nj - 1) << 26)) << 32);
+}
+__device__ inline void unpack_pair(uint64_t w, int32_t& ib, int32_t& ni, int32_t& jb, int32_t& nj) {
+  const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+  ib = (int32_t)(lo & 0x3ffffffu);
+  ni = (int32_t)(lo >> 26) + 1;
+  jb = (int32_t)(hi & 0x3ffffffu);
+  nj = (int32_t)(hi >> 26) + 1;
 }
 
 // The entries of one q are distinct kept indices t < nkept, so each lands at
@@ -269,7 +284,8 @@ __global__ void k_pair_fill(int64_t nkept, const int32_t* __restrict__ kept, Mes
 // entry at prefix + popcount of the lower bits of its word.  The block's
 // four wavefronts pass the same barriers whatever their list lengths.
 __global__ void __launch_bounds__(256) k_pair_place(int64_t nq, int nkept, const int32_t* __restrict__ off,
-                                                    const int32_t* __restrict__ tmp, int32_t* __restrict__ list) {
+                                                    const uint64_t* __restrict__ tmp, const int32_t* __restrict__ soff,
+                                                    int32_t* __restrict__ list, uint64_t* __restrict__ ppk) {
   extern __shared__ uint32_t sm[];  // per wavefront: bitmap [W], prefix [W]
   const int W = (nkept + 31) / 32;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -284,7 +300,7 @@ __global__ void __launch_bounds__(256) k_pair_place(int64_t nq, int nkept, const
   for (int w = lane; w < W; w += 64) bits[w] = 0u;
   __syncthreads();
   for (int e = lane; e < len; e += 64) {
-    const int32_t v = tmp[b + e];
+    const int32_t v = (int32_t)(uint32_t)tmp[b + e];
     atomicOr(&bits[v >> 5], 1u << (v & 31));
   }
   __syncthreads();
@@ -311,9 +327,12 @@ __global__ void __launch_bounds__(256) k_pair_place(int64_t nq, int nkept, const
   }
   __syncthreads();
   for (int e = lane; e < len; e += 64) {
-    const int32_t v = tmp[b + e];
+    const uint64_t tu = tmp[b + e];
+    const int32_t v = (int32_t)(uint32_t)tu, u = (int32_t)(tu >> 32);
     const uint32_t word = bits[v >> 5];
-    list[b + (int32_t)pre[v >> 5] + __popc(word & ((1u << (v & 31)) - 1u))] = v;
+    const int32_t at = b + (int32_t)pre[v >> 5] + __popc(word & ((1u << (v & 31)) - 1u));
+    list[at] = v;
+    ppk[at] = pack_pair(soff[v], soff[v + 1] - soff[v], soff[u], soff[u + 1] - soff[u]);
   }
 }
 
@@ -326,11 +345,17 @@ elph_status ensure_pairs(elph_ctx ctx) {
   hipStream_t s = ctx->stream;
   const int64_t nk = ctx->nk, nkept = ctx->nkept, npairs = nkept * nkept;
   const MeshDims md{ctx->mesh[0], ctx->mesh[1], ctx->mesh[2]};
-  int32_t *cnt = nullptr, *tmp = nullptr, *scr = nullptr, *tot = nullptr;
+  if (ctx->nstates >= ((int64_t)1 << 26)) {
+    ctx->err = "too many states for packed pair ranges (2^26)";
+    return ELPH_EINVAL;
+  }
+  int32_t *cnt = nullptr, *scr = nullptr, *tot = nullptr;
+  uint64_t* tmp = nullptr;
   if (!ctx->d_poff) ALLOC(ctx->d_poff, (nk + 1) * sizeof(int32_t));
   if (!ctx->d_plist) ALLOC(ctx->d_plist, npairs * sizeof(int32_t));
+  if (!ctx->d_ppk) ALLOC(ctx->d_ppk, npairs * sizeof(uint64_t));
   ALLOC(cnt, nk * sizeof(int32_t));
-  ALLOC(tmp, npairs * sizeof(int32_t));
+  ALLOC(tmp, npairs * sizeof(uint64_t));
   ALLOC(scr, (4 * ((nk + 1023) / 1024) + 64) * sizeof(int32_t));
   HIPCHK(hipMemsetAsync(cnt, 0, nk * sizeof(int32_t), s));
   hipLaunchKernelGGL(k_pair_count, dim3(blocks_for(npairs, 256)), dim3(256), 0, s, nkept, ctx->d_kept, md, cnt);
@@ -341,7 +366,7 @@ elph_status ensure_pairs(elph_ctx ctx) {
                      ctx->d_poff, cnt, tmp);
   const size_t place_lds = (size_t)4 * 2 * ((nkept + 31) / 32) * sizeof(uint32_t);
   hipLaunchKernelGGL(k_pair_place, dim3((unsigned)((nk + 3) / 4)), dim3(256), place_lds, s, nk, (int)nkept,
-                     ctx->d_poff, tmp, ctx->d_plist);
+                     ctx->d_poff, tmp, ctx->d_soff, ctx->d_plist, ctx->d_ppk);
   HIPCHK(hipGetLastError());
   dev_free(ctx, cnt);
   dev_free(ctx, tmp);
@@ -356,12 +381,9 @@ elph_status ensure_pairs(elph_ctx ctx) {
 // restricts the launch to er.n listed wave vectors).  The phonon rates use
 // it (NV = 1); the six drag columns go through k_q_gather_lds.
 template <typename ST, int NV, int NX>
-__global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, MeshDims md,
-                                                      const ST* __restrict__ Bp, const int32_t* __restrict__ kept,
-                                                      const int32_t* __restrict__ kidx,
-                                                      const int32_t* __restrict__ soff,
+__global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, const ST* __restrict__ Bp,
                                                       const int32_t* __restrict__ poff,
-                                                      const int32_t* __restrict__ plist, const double* __restrict__ f,
+                                                      const uint64_t* __restrict__ ppk, const double* __restrict__ f,
                                                       const double* __restrict__ omf, const double* __restrict__ x,
                                                       double* __restrict__ acc, RateErr er) {
   const int lane = threadIdx.x & 63;
@@ -379,9 +401,6 @@ __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, Mes
   double ev[NV == 1 ? NX : 1];
 #pragma unroll
   for (int s = 0; s < (NV == 1 ? NX : 1); ++s) ev[s] = 0.0;
-  const int qc = (int)(q % md.n2);
-  const int qt = (int)(q / md.n2);
-  const int qb = qt % md.n1, qa = qt / md.n1;
   double a[NX][NV];
 #pragma unroll
   for (int s = 0; s < NX; ++s)
@@ -389,17 +408,11 @@ __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, Mes
     for (int c = 0; c < NV; ++c) a[s][c] = 0.0;
   const int32_t pe = poff[q + 1];
   for (int32_t p = poff[q] + lane; p < pe; p += 64) {
-    const int32_t t = plist[p];
-    const int k = kept[t];
-    const int kc = k % md.n2, kt = k / md.n2;
-    const int kb = kt % md.n1, ka = kt / md.n1;
-    int c2 = kc + qc; if (c2 >= md.n2) c2 -= md.n2;
-    int b2 = kb + qb; if (b2 >= md.n1) b2 -= md.n1;
-    int a2 = ka + qa; if (a2 >= md.n0) a2 -= md.n0;
-    const int32_t u = kidx[(a2 * md.n1 + b2) * md.n2 + c2];
-    for (int32_t i = soff[t]; i < soff[t + 1]; ++i) {
+    int32_t ib, ni, jb, nj;
+    unpack_pair(ppk[p], ib, ni, jb, nj);
+    for (int32_t i = ib; i < ib + ni; ++i) {
       const double fi = f[i];
-      for (int32_t j = soff[u]; j < soff[u + 1]; ++j) {
+      for (int32_t j = jb; j < jb + nj; ++j) {
         const double occ = fi * omf[j];
         double w[NV];
         if (NV == 1) w[0] = 1.0;
@@ -453,12 +466,9 @@ __global__ void __launch_bounds__(256) k_q_gather_csr(int64_t nq, int64_t M, Mes
 // partial rows in g order.  A lane holds six accumulators instead of NX x 6,
 // so the gather runs at a higher occupancy; the order of the sum is fixed.
 template <typename ST, int NX>
-__global__ void __launch_bounds__(256) k_q_gather_lds(int64_t nq, int64_t M, MeshDims md,
-                                                      const ST* __restrict__ Bp, const int32_t* __restrict__ kept,
-                                                      const int32_t* __restrict__ kidx,
-                                                      const int32_t* __restrict__ soff,
+__global__ void __launch_bounds__(256) k_q_gather_lds(int64_t nq, int64_t M, const ST* __restrict__ Bp,
                                                       const int32_t* __restrict__ poff,
-                                                      const int32_t* __restrict__ plist, const double* __restrict__ f,
+                                                      const uint64_t* __restrict__ ppk, const double* __restrict__ f,
                                                       const double* __restrict__ omf, const double* __restrict__ x,
                                                       double* __restrict__ acc) {
   constexpr int G = 64 / NX, NO = NX * 6;
@@ -468,9 +478,6 @@ __global__ void __launch_bounds__(256) k_q_gather_lds(int64_t nq, int64_t M, Mes
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t q = (int64_t)blockIdx.x * 4 + wave;
   if (q >= nq) return;  // whole wavefront; only wavefront barriers below
-  const int qc = (int)(q % md.n2);
-  const int qt = (int)(q / md.n2);
-  const int qb = qt % md.n1, qa = qt / md.n1;
   const int ms = lane % NX, mg = lane / NX;  // lanes with mg >= G idle in the sum
   double a[6];
 #pragma unroll
@@ -481,20 +488,7 @@ __global__ void __launch_bounds__(256) k_q_gather_lds(int64_t nq, int64_t M, Mes
   for (int32_t p0 = poff[q]; p0 < pe; p0 += 64) {
     const int32_t p = p0 + lane;
     int32_t ib = 0, ni = 0, jb = 0, nj = 0;
-    if (p < pe) {
-      const int32_t t = plist[p];
-      const int k = kept[t];
-      const int kc = k % md.n2, kt = k / md.n2;
-      const int kb = kt % md.n1, ka = kt / md.n1;
-      int c2 = kc + qc; if (c2 >= md.n2) c2 -= md.n2;
-      int b2 = kb + qb; if (b2 >= md.n1) b2 -= md.n1;
-      int a2 = ka + qa; if (a2 >= md.n0) a2 -= md.n0;
-      const int32_t u = kidx[(a2 * md.n1 + b2) * md.n2 + c2];
-      ib = soff[t];
-      ni = soff[t + 1] - ib;
-      jb = soff[u];
-      nj = soff[u + 1] - jb;
-    }
+    if (p < pe) unpack_pair(ppk[p], ib, ni, jb, nj);
     int nr = ni * nj;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) nr = max(nr, __shfl_xor(nr, o, 64));
@@ -562,8 +556,8 @@ void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* 
     if constexpr (NV == 6) {
       // the drag columns (no row list or codes come with them)
 #define QL(NXV)                                                                                                 \
-  hipLaunchKernelGGL((k_q_gather_lds<ST, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, md, Bp,        \
-                     ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist, f, omf, x, acc)
+  hipLaunchKernelGGL((k_q_gather_lds<ST, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, Bp,            \
+                     ctx->d_poff, ctx->d_ppk, f, omf, x, acc)
       switch (ctx->nbr) {
         case 3: QL(3); break;
         case 6: QL(6); break;
@@ -574,8 +568,8 @@ void launch_q_gather(elph_ctx ctx, const ST* Bp, const double* f, const double* 
 #undef QL
     } else {
 #define QG(NXV)                                                                                                \
-  hipLaunchKernelGGL((k_q_gather_csr<ST, NV, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, md, Bp,   \
-                     ctx->d_kept, ctx->d_kidx, ctx->d_soff, ctx->d_poff, ctx->d_plist, f, omf, x, acc, er)
+  hipLaunchKernelGGL((k_q_gather_csr<ST, NV, NXV>), grid, blk, 0, ctx->stream, ctx->nk, ctx->nstates, Bp,       \
+                     ctx->d_poff, ctx->d_ppk, f, omf, x, acc, er)
       switch (ctx->nbr) {
         case 3: QG(3); break;
         case 6: QG(6); break;
