@@ -1161,46 +1161,26 @@ __device__ __forceinline__ void epi_pair(int64_t i, int64_t j, int64_t q, double
 }
 
 template <typename ST, int NX>
-__device__ __forceinline__ void epi_q_wave(int64_t q, int64_t i0, int32_t t0, int32_t t1, const EpiParams& ep,
-                                           const int32_t* __restrict__ kept, const int32_t* __restrict__ kidx,
-                                           const int32_t* __restrict__ soff, const int32_t* __restrict__ poff,
-                                           const int32_t* __restrict__ plist, const float* __restrict__ C,
+__device__ __forceinline__ void epi_q_wave(int64_t q, const EpiParams& ep, const int32_t* __restrict__ poff,
+                                           const uint64_t* __restrict__ ppk, const float* __restrict__ C,
                                            int64_t ldc, ST* __restrict__ Bp, ST* __restrict__ Bm) {
   const int lane = threadIdx.x & 63;
-  const int qc = (int)(q % ep.n2);
-  const int qt = (int)(q / ep.n2);
-  const int qb = qt % ep.n1, qa = qt / ep.n1;
   const cd* __restrict__ L = ep.Lq + q * NX * NX;
   const double* __restrict__ hwq = ep.hw + q * NX;
   const int32_t pe = poff[q + 1];
   for (int32_t p = poff[q] + lane; p < pe; p += 64) {
-    const int32_t t = plist[p];
-    if (t < t0 || t >= t1) continue;
-    const int k = kept[t];
-    const int kc = k % ep.n2, kt = k / ep.n2;
-    const int kb = kt % ep.n1, ka = kt / ep.n1;
-    int c2 = kc + qc; if (c2 >= ep.n2) c2 -= ep.n2;
-    int b2 = kb + qb; if (b2 >= ep.n1) b2 -= ep.n1;
-    int a2 = ka + qa; if (a2 >= ep.n0) a2 -= ep.n0;
-    const int32_t u = kidx[(a2 * ep.n1 + b2) * ep.n2 + c2];
-    for (int32_t i = soff[t]; i < soff[t + 1]; ++i) {
+    // the pair's state ranges: first state and count of k and of k + q
+    const uint64_t w = ppk[p];
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    const int32_t ib = (int32_t)(lo & 0x3ffffffu), ie = ib + (int32_t)(lo >> 26) + 1;
+    const int32_t jb = (int32_t)(hi & 0x3ffffffu), je = jb + (int32_t)(hi >> 26) + 1;
+    for (int32_t i = ib; i < ie; ++i) {
       const double ei = ep.eps[i];
-      for (int32_t j = soff[u]; j < soff[u + 1]; ++j) {
-        epi_pair<ST, NX>(i, j, q, ei, ep, L, hwq, C + 2 * (((int64_t)(i - i0) * ldc + j) * NX), Bp, Bm);
+      for (int32_t j = jb; j < je; ++j) {
+        epi_pair<ST, NX>(i, j, q, ei, ep, L, hwq, C + 2 * (((int64_t)i * ldc + j) * NX), Bp, Bm);
       }
     }
   }
-}
-
-template <typename ST, int NX>
-__global__ void __launch_bounds__(256) k_epi_q(int64_t nq, int64_t i0, int32_t t0, int32_t t1, EpiParams ep,
-                                               const int32_t* __restrict__ kept, const int32_t* __restrict__ kidx,
-                                               const int32_t* __restrict__ soff, const int32_t* __restrict__ poff,
-                                               const int32_t* __restrict__ plist, const float* __restrict__ C,
-                                               int64_t ldc, ST* __restrict__ Bp, ST* __restrict__ Bm) {
-  const int64_t q = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (q >= nq) return;  // whole wavefront exits together
-  epi_q_wave<ST, NX>(q, i0, t0, t1, ep, kept, kidx, soff, poff, plist, C, ldc, Bp, Bm);
 }
 
 // The same epilogue row by row: one block per initial state i of the chunk
@@ -2116,11 +2096,8 @@ elph_status step1_fp64_rows(elph_ctx ctx, int64_t ns, const int32_t* st_kidx, co
 template <typename ST>
 struct EpiDesc {
   EpiParams ep;
-  const int32_t* kept;
-  const int32_t* kidx;
-  const int32_t* soff;
   const int32_t* poff;
-  const int32_t* plist;
+  const uint64_t* ppk;
   const float* C;
   int64_t ldc, nq;
   int32_t nkept;
@@ -2141,7 +2118,8 @@ struct S1EpiDesc {
 
 // The per-q epilogue of every material of one branch count in one launch:
 // items (slot, q / 4), taken grid-stride; a block's four wavefronts take
-// four q, each exactly as k_epi_q does.
+// four q, each walking its pair list (packed state ranges) with the pair
+// body of k_epi_rows.
 template <typename ST, int NX>
 __global__ void __launch_bounds__(256) k_epi_q_persist(const EpiDesc<ST>* __restrict__ d,
                                                        const int2* __restrict__ items, int nitems) {
@@ -2151,8 +2129,7 @@ __global__ void __launch_bounds__(256) k_epi_q_persist(const EpiDesc<ST>* __rest
     promote(e.ep);
     const int64_t q = (int64_t)w.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (q < e.nq)
-      epi_q_wave<ST, NX>(q, 0, 0, e.nkept, e.ep, as_global(e.kept), as_global(e.kidx), as_global(e.soff),
-                         as_global(e.poff), as_global(e.plist), as_global(e.C), e.ldc, as_global(e.Bp),
+      epi_q_wave<ST, NX>(q, e.ep, as_global(e.poff), as_global(e.ppk), as_global(e.C), e.ldc, as_global(e.Bp),
                          as_global(e.Bm));
   }
 }
@@ -2417,11 +2394,8 @@ static elph_status batch_prepare_t(BatchImpl* b) {
         e.ep.omf = b->th[m].omf;
         e.ep.nocc = b->th[m].nocc;
         e.ep.we_part = c->d_we_part;
-        e.kept = c->d_kept;
-        e.kidx = c->d_kidx;
-        e.soff = c->d_soff;
         e.poff = c->d_poff;
-        e.plist = c->d_plist;
+        e.ppk = c->d_ppk;
         e.C = b->c2[m];
         e.ldc = c->m_pad;
         e.nq = c->nk;
