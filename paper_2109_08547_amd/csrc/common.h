@@ -44,6 +44,24 @@ __host__ __device__ inline cd cscale(cd a, double s) { return cd{a.x * s, a.y * 
 __host__ __device__ inline double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
 
 // ---------------------------------------------------------------- launch helpers
+// Dynamic LDS that a kernel leaves unused, sized so that at most `per_cu`
+// of its blocks (each also holding own_lds bytes of static LDS) are resident
+// on a CU: for row kernels whose rows each sweep their own window of a
+// table, so that the windows of the rows running together stay in L2.
+inline size_t lds_pad_for(int per_cu, int own_lds) {
+  int dev = 0, cu = 0, blk = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const int64_t margin = 1024;  // allocation granularity
+  int64_t pad = (int64_t)cu / per_cu - own_lds - margin;
+  if (pad > (int64_t)blk - own_lds - margin) pad = (int64_t)blk - own_lds - margin;
+  return pad > 0 ? (size_t)(pad / 1024 * 1024) : 0;
+}
+
 inline unsigned blocks_for(int64_t n, int threads) {
   return (unsigned)((n + threads - 1) / threads);
 }

@@ -1085,6 +1085,13 @@ __global__ void k_group_bounds(int64_t n, const int32_t* __restrict__ flag, cons
 // (n at -q equals n at q), so a term reads one contiguous row.  The table
 // stays FP64 in every form: an FP32 table puts a rounding floor near 1e-7
 // into the phonon map, which stalls the coupled iteration above 1e-8.
+// Rows of the electron drag resident per CU.  Each row sweeps its own
+// window of the (q, s) table; with more than three rows per CU at once their
+// windows crowd each other out of the L2, and the gathers slow down (six
+// rows: 0.58 ms at mixed48, three: 0.54; at 15 branches 13.7 and 11.4 ms).
+constexpr int kDragRowsPerCU = 3;
+constexpr int kDragOwnLds = 256 * 4 + 256 * 8 + 24 * 8;  // sq, sr, sh of k_drag_e
+
 __global__ void k_drag_uv(int64_t nm, int nbr, MeshDims md, const double* __restrict__ nocc,
                           const double* __restrict__ phon, double* __restrict__ uv) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1737,8 +1744,9 @@ static elph_status iterate_t(elph_ctx ctx, double T, const double* wext, int lev
         hipLaunchKernelGGL(k_drag_uv, dim3(blocks_for(nm * 12, 256)), dim3(256), 0, s, nm, (int)nbr, md, th.nocc,
                            phon, uvt);
         const int64_t per_xcd = (M + 7) / 8;
+        const size_t dpad = lds_pad_for(kDragRowsPerCU, kDragOwnLds);
 #define DE(NXV)                                                                                                 \
-  hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, M, per_xcd, md, Bp, Bm, \
+  hipLaunchKernelGGL((k_drag_e<ST, NXV>), dim3((unsigned)(8 * per_xcd)), dim3(256), dpad, s, M, per_xcd, md, Bp, Bm, \
                      drow, ctx->d_state_k, th.lomf, we, uvt, De)
         switch (nbr) {
           case 3: DE(3); break;
