@@ -635,8 +635,8 @@ def main():
                          "bytes are known, to scale the byte counters of a profiled run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: the library runs on one GPU (the path would shard by kept-k rows across GPUs; "
-              "see the design notes); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU (the path would shard by kept-k rows across GPUs, "
+              "which it does not implement); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     pool, futs = None, {}
     if args.workload == "mixed48" and not args.no_configs:
