@@ -1088,7 +1088,8 @@ __global__ void k_group_bounds(int64_t n, const int32_t* __restrict__ flag, cons
 // Rows of the electron drag resident per CU.  Each row sweeps its own
 // window of the (q, s) table; with more than three rows per CU at once their
 // windows crowd each other out of the L2, and the gathers slow down (six
-// rows: 0.58 ms at mixed48, three: 0.54; at 15 branches 13.7 and 11.4 ms).
+// rows: 0.58 ms for 3318 states and 6 branches, three: 0.54; for 9581
+// states and 15 branches 13.7 and 11.4 ms).
 constexpr int kDragRowsPerCU = 3;
 constexpr int kDragOwnLds = 256 * 4 + 256 * 8 + 24 * 8;  // sq, sr, sh of k_drag_e
 
